@@ -1,0 +1,165 @@
+"""SpAMM reference oracle -- test infrastructure only.
+
+A plain FP64 CPU implementation of the sparse approximate matrix multiply,
+written from the paper (quadtree depth/padding, Sec. II.A; node norms, product
+recursion and SpAMM condition, Sec. II.B; linear index, Sec. III.B).  Only the
+tests, the smoke check and the benchmark's CPU-baseline leg may import it; the
+GPU library never does, and the two share no code.
+
+The arithmetic lives in ``spamm_oracle.c`` (plain C, -O2, no fast-math,
+no FP contraction); this module only marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "spamm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OR_OK, OR_EINVAL, OR_ERANGE, OR_ENOMEM = 0, -1, -2, -3
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+             "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        i32, i64, u64, dbl, vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                                  ctypes.c_double, ctypes.c_void_p)
+        lib.oracle_depth.argtypes = [i64, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        lib.oracle_depth.restype = ctypes.c_int
+        lib.oracle_linear_index.argtypes = [u64, u64]
+        lib.oracle_linear_index.restype = u64
+        lib.oracle_norms_len.argtypes = [i32]
+        lib.oracle_norms_len.restype = i64
+        lib.oracle_norms.argtypes = [vp, i64, i32, vp]
+        lib.oracle_norms.restype = ctypes.c_int
+        lib.oracle_spamm.argtypes = [vp, vp, i64, i32, dbl, vp, vp, i64, vp, vp]
+        lib.oracle_spamm.restype = ctypes.c_int
+        lib.oracle_spamm_tiles.argtypes = [vp, vp, i64, i32, dbl, vp, i64, vp, vp, vp,
+                                           ctypes.c_int]
+        lib.oracle_spamm_tiles.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _f32(A: np.ndarray) -> np.ndarray:
+    A = np.ascontiguousarray(A)
+    if A.dtype != np.float32 or A.ndim != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("expected a square float32 matrix")
+    return A
+
+
+def depth(n: int, b: int):
+    """(d, n_p): quadtree depth and padded size."""
+    d = ctypes.c_int32()
+    np_ = ctypes.c_int64()
+    rc = _load().oracle_depth(n, b, ctypes.byref(d), ctypes.byref(np_))
+    if rc:
+        raise ValueError(f"oracle_depth({n}, {b}) -> {rc}")
+    return d.value, np_.value
+
+
+def linear_index(i: int, j: int) -> int:
+    return int(_load().oracle_linear_index(i, j))
+
+
+def norms(A: np.ndarray, b: int):
+    """Squared Frobenius norms of all tiers: list, tier 0 (root) first, tier t
+    as a 2^t x 2^t row-major float64 array."""
+    A = _f32(A)
+    n = A.shape[0]
+    d, _ = depth(n, b)
+    out = np.empty(int(_load().oracle_norms_len(d)), dtype=np.float64)
+    rc = _load().oracle_norms(A.ctypes.data, n, b, out.ctypes.data)
+    if rc:
+        raise RuntimeError(f"oracle_norms -> {rc}")
+    tiers, off = [], 0
+    for t in range(d + 1):
+        m = 1 << t
+        tiers.append(out[off:off + m * m].reshape(m, m))
+        off += m * m
+    return tiers
+
+
+class Result:
+    def __init__(self, C, keys, Kt):
+        self.C = C          # float64 n x n (or None)
+        self.keys = keys    # sorted uint64 (linear_index(I,J) << 32) | K
+        self.Kt = Kt        # kept node triples per tier
+
+    @property
+    def K(self) -> int:
+        return int(self.Kt[-1])
+
+
+def spamm(A: np.ndarray, B: np.ndarray, b: int, tau: float, want_C: bool = True,
+          want_keys: bool = True, cap: int | None = None) -> Result:
+    """Full recursive SpAMM product in FP64."""
+    A, B = _f32(A), _f32(B)
+    n = A.shape[0]
+    if B.shape[0] != n:
+        raise ValueError("shape mismatch")
+    d, _ = depth(n, b)
+    C = np.empty((n, n), dtype=np.float64) if want_C else None
+    Kt = np.zeros(d + 1, dtype=np.int64)
+    nk = np.zeros(1, dtype=np.int64)
+    keys = None
+    if want_keys:
+        if cap is None:
+            # count first so the key buffer is exactly sized
+            rc = _load().oracle_spamm(A.ctypes.data, B.ctypes.data, n, b, float(tau),
+                                      None, None, 0, nk.ctypes.data, Kt.ctypes.data)
+            if rc:
+                raise RuntimeError(f"oracle_spamm -> {rc}")
+            cap = int(nk[0])
+        keys = np.empty(max(cap, 1), dtype=np.uint64)
+    rc = _load().oracle_spamm(A.ctypes.data, B.ctypes.data, n, b, float(tau),
+                              None if C is None else C.ctypes.data,
+                              None if keys is None else keys.ctypes.data,
+                              0 if keys is None else cap, nk.ctypes.data, Kt.ctypes.data)
+    if rc:
+        raise RuntimeError(f"oracle_spamm -> {rc}")
+    if keys is not None:
+        keys = keys[:int(nk[0])]
+    return Result(C, keys, Kt)
+
+
+def spamm_tiles(A: np.ndarray, B: np.ndarray, b: int, tau: float, tiles,
+                threads: int = 1, want_klists: bool = False):
+    """Per-tile recursion for the output tiles ``tiles`` ((I, J) pairs).
+
+    Returns (Ctiles [ntiles, b, b] float64, counts [ntiles], klists or None);
+    klists[s, :counts[s]] are the kept K values of tile s in ascending order.
+    """
+    A, B = _f32(A), _f32(B)
+    n = A.shape[0]
+    d, _ = depth(n, b)
+    t = np.ascontiguousarray(np.asarray(tiles, dtype=np.int64).reshape(-1, 2))
+    m = t.shape[0]
+    Ct = np.empty((m, b, b), dtype=np.float64)
+    counts = np.zeros(m, dtype=np.int64)
+    kl = np.empty((m, 1 << d), dtype=np.int32) if want_klists else None
+    rc = _load().oracle_spamm_tiles(A.ctypes.data, B.ctypes.data, n, b, float(tau),
+                                    t.ctypes.data, m, Ct.ctypes.data, counts.ctypes.data,
+                                    None if kl is None else kl.ctypes.data, int(threads))
+    if rc:
+        raise RuntimeError(f"oracle_spamm_tiles -> {rc}")
+    return Ct, counts, kl
