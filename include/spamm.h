@@ -1,0 +1,157 @@
+/*
+ * spamm.h -- C ABI of the MI355X SpAMM library (libspamm.so).
+ *
+ * Sparse Approximate Matrix Multiply (Bock & Challacombe, "An Optimized Sparse
+ * Approximate Matrix Multiply for Matrices with Decay"): C ~= A B for matrices
+ * whose entries decay away from the diagonal.  Each operand is held as a
+ * quadtree of n_b x n_b dense leaves with a Frobenius norm per node (Sec. II.A
+ * and II.B); a sub-product A_ik B_kj is skipped whenever
+ * ||A_ik||_F ||B_kj||_F < tau (Eq. norm condition), at every tier.
+ *
+ * Conventions
+ *  - Every call returns an int status: SPAMM_OK (0) or a negative SPAMM_E_*
+ *    code; spamm_strerror() names it and spamm_last_error() gives the detail
+ *    of the calling thread's last failure.  Nothing is thrown across the ABI.
+ *  - Matrix pointers are DEVICE pointers (FP32, row-major, leading dimension
+ *    n, square n x n).  `stream` is a hipStream_t (NULL = the null stream).
+ *    Work is enqueued on that stream; pointers must stay valid until the
+ *    stream has passed the work.
+ *  - Host pointers are named `host` and are written synchronously.
+ *  - Sizes are element counts unless stated otherwise.
+ *  - Limits: leaf n_b in {16, 32, 64}; tiles per dimension N = n_p / n_b at
+ *    most 1024 (so n <= 1024 n_b); tau finite, tau = 0 or tau >= 1e-150.
+ */
+#ifndef SPAMM_H
+#define SPAMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define SPAMM_OK            0
+#define SPAMM_E_INVAL      -1   /* bad argument (null pointer, size, leaf, tau) */
+#define SPAMM_E_NONFINITE  -2   /* NaN or Inf in the input matrix             */
+#define SPAMM_E_NOMEM      -3   /* device allocation failed                   */
+#define SPAMM_E_HIP        -4   /* a HIP runtime call failed (see last_error) */
+#define SPAMM_E_RANGE      -5   /* host buffer too small / size over a limit  */
+#define SPAMM_E_MISMATCH   -6   /* operands of different n or leaf size       */
+
+typedef struct spamm_tree spamm_tree;   /* one operand: packed leaves + norms  */
+typedef struct spamm_plan spamm_plan;   /* one product's kept task list        */
+
+/* Statistics of one product (filled by spamm_plan_stats / spamm_multiply_ex). */
+typedef struct spamm_stats {
+    int32_t depth;            /* d: tiers 0..d                                  */
+    int32_t leaf;             /* n_b                                            */
+    int64_t kept[32];         /* kept node triples per tier t = 0..d            */
+    int64_t tasks;            /* K = kept[d]: leaf products performed           */
+    int64_t block_entries;    /* (k, mask) entries scheduled for the leaf GEMM  */
+    double  flops;            /* 2 n_b^3 K                                      */
+    double  symbolic_ms;      /* cull time (events), or -1 when not timed        */
+    double  numeric_ms;       /* leaf-GEMM time (events), or -1 when not timed   */
+} spamm_stats;
+
+/* ---- operands -------------------------------------------------------------- */
+
+/*
+ * Build the quadtree of A (Sec. II.A, II.B).
+ *   A      device pointer, n x n FP32 row-major (lda = n); read only by work
+ *          enqueued here; the caller keeps it alive until `stream` passes it.
+ *   n      matrix order, n >= 1.
+ *   leaf   n_b in {16, 32, 64}.  Depth d = smallest d >= 0 with n_b 2^d >= n;
+ *          A is zero-padded to n_p = n_b 2^d (padding is never read from A).
+ *   out    receives the handle.  The tree owns copies: the packed leaves
+ *          (FP32, row-major inside each leaf, leaves in linear-index order of
+ *          Eq. linear index) and the squared Frobenius norms of all tiers in
+ *          FP64 (leaf: pairwise sum of squares over the leaf's row-major
+ *          flattened index; parent: (s11 + s12) + (s21 + s22)).
+ * Synchronizes `stream` once, to read the root norm; a non-finite root means
+ * NaN/Inf in A -> SPAMM_E_NONFINITE (no tree is returned).
+ * Errors: SPAMM_E_INVAL (n < 1, bad leaf, null A/out), SPAMM_E_RANGE (N > 1024),
+ *         SPAMM_E_NONFINITE, SPAMM_E_NOMEM, SPAMM_E_HIP.
+ */
+int spamm_build_tree(const float *A, int64_t n, int32_t leaf, void *stream,
+                     spamm_tree **out);
+
+/* Release a tree (stream-ordered on the stream it was built on; work on other
+ * streams that uses the tree must be complete).  NULL is a no-op. */
+int spamm_tree_free(spamm_tree *tree);
+
+/* Shape of a tree; any output pointer may be NULL.  norm2 = ||A||_F^2 (FP64
+ * root of the norm pyramid). */
+int spamm_tree_info(const spamm_tree *tree, int64_t *n, int32_t *leaf,
+                    int32_t *depth, double *norm2);
+
+/* Copy tier `tier` (0..d) of the squared-norm pyramid to host memory as a
+ * 2^tier x 2^tier row-major FP64 array (len >= 4^tier, else SPAMM_E_RANGE).
+ * Synchronizes the tree's stream. */
+int spamm_tree_norms(const spamm_tree *tree, int32_t tier, double *host, size_t len);
+
+/* Copy the zero-padded matrix held by the tree to host memory as an
+ * n_p x n_p row-major FP32 array (len >= n_p^2).  Synchronizes. */
+int spamm_tree_matrix(const spamm_tree *tree, float *host, size_t len);
+
+/* ---- symbolic / numeric multiply (Alg. 1: collect products, then multiply) -- */
+
+/*
+ * Symbolic multiply: the tier-by-tier (i,k,j) cull of Eq. product under
+ * Eq. norm condition.  A triple is kept iff s_A > 0, s_B > 0 and
+ * fl64(s_A * s_B) >= fl64(tau * tau) on the stored squared norms (equality
+ * keeps; zero-norm nodes are never kept, at any tau).  The plan holds the
+ * kept leaf triples sorted by output tile, then k.  Asynchronous on `stream`
+ * (no host synchronization).  A and B may be the same tree.
+ * Errors: SPAMM_E_INVAL (null, tau < 0, tau NaN/Inf, 0 < tau < 1e-150),
+ *         SPAMM_E_MISMATCH (n or leaf differ), SPAMM_E_NOMEM, SPAMM_E_HIP.
+ */
+int spamm_symbolic(const spamm_tree *A, const spamm_tree *B, double tau,
+                   void *stream, spamm_plan **out);
+
+/*
+ * Numeric multiply: C = sum over kept k (ascending) of A_ik B_kj for every
+ * output leaf, FP32 MFMA with FP32 accumulation (Eq. product, Alg. 1 steps
+ * 7-9).  C: device pointer, n x n FP32 row-major, fully overwritten (zeros
+ * where no product lands; alpha = 1, beta = 0).  C must not overlap the
+ * trees' storage; it may alias the matrix a tree was built from.  Enqueue on
+ * the plan's stream or order streams yourself.
+ */
+int spamm_numeric(const spamm_plan *plan, float *C, void *stream);
+
+/*
+ * Copy the kept leaf triples to host memory as sorted uint64 keys
+ * (linear_index(i, j) << 32) | k, linear_index from Eq. linear index (row
+ * bits on odd positions).  *count receives K.  cap < K -> SPAMM_E_RANGE
+ * (nothing copied).  Synchronizes the plan's stream.
+ */
+int spamm_plan_tasks(const spamm_plan *plan, uint64_t *host, size_t cap, size_t *count);
+
+/* Kept counts per tier and work totals.  Synchronizes the plan's stream. */
+int spamm_plan_stats(const spamm_plan *plan, spamm_stats *out);
+
+/* Release a plan (stream-ordered).  NULL is a no-op. */
+int spamm_plan_free(spamm_plan *plan);
+
+/* ---- one-call multiply --------------------------------------------------- */
+
+/* C = A B under the SpAMM condition with tolerance tau: symbolic + numeric on
+ * `stream`, with a temporary plan.  Asynchronous (no host synchronization). */
+int spamm_multiply(const spamm_tree *A, const spamm_tree *B, double tau, float *C,
+                   void *stream);
+
+/* As spamm_multiply; when `stats` is not NULL the call also times the cull
+ * and the leaf GEMM with HIP events on `stream`, synchronizes, and fills it. */
+int spamm_multiply_ex(const spamm_tree *A, const spamm_tree *B, double tau, float *C,
+                      void *stream, spamm_stats *stats);
+
+/* ---- errors --------------------------------------------------------------- */
+const char *spamm_strerror(int code);
+const char *spamm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPAMM_H */

@@ -1,0 +1,466 @@
+// C ABI of libspamm: argument checks, device memory (stream-ordered HIP
+// memory pool), launches and host-side exports.  No computation of the
+// multiply happens here; every step runs in the kernels of norms.hip,
+// cull.hip and gemm.hip.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "common.hpp"
+
+namespace spamm {
+hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *tiles,
+                        double *norms, hipStream_t s);
+hipError_t launch_cull(spamm_plan *p, hipStream_t s);
+hipError_t launch_gemm(const spamm_plan *p, float *C, hipStream_t s);
+size_t scan_partials_len(uint32_t m);
+}  // namespace spamm
+
+using namespace spamm;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    if (e == hipErrorOutOfMemory)
+        return fail(SPAMM_E_NOMEM, "%s: out of device memory", what);
+    return fail(SPAMM_E_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+#define HIP_TRY(expr, what)                       \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess)                     \
+            return hip_fail(e_, what);            \
+    } while (0)
+
+// Keep freed pool memory cached on every device we touch (the default pool
+// would otherwise hand it back to the driver at each synchronization).
+int prepare_device(int *dev)
+{
+    static std::mutex mu;
+    static bool done[64] = {};
+    HIP_TRY(hipGetDevice(dev), "hipGetDevice");
+    if (*dev < 0 || *dev >= 64)
+        return fail(SPAMM_E_HIP, "device ordinal %d out of range", *dev);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!done[*dev]) {
+        hipMemPool_t pool;
+        HIP_TRY(hipDeviceGetDefaultMemPool(&pool, *dev), "hipDeviceGetDefaultMemPool");
+        uint64_t thr = UINT64_MAX;
+        HIP_TRY(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr),
+                "hipMemPoolSetAttribute");
+        done[*dev] = true;
+    }
+    return SPAMM_OK;
+}
+
+int depth_of(int64_t n, int32_t leaf, int32_t *d, int64_t *np)
+{
+    int32_t t = 0;
+    int64_t p = leaf;
+    while (p < n) {
+        p *= 2;
+        t += 1;
+        if (t > kMaxDepth)
+            return fail(SPAMM_E_RANGE, "n = %lld needs more than %d tiers at leaf %d",
+                        (long long)n, kMaxDepth, leaf);
+    }
+    *d = t;
+    *np = p;
+    return SPAMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *spamm_strerror(int code)
+{
+    switch (code) {
+    case SPAMM_OK: return "success";
+    case SPAMM_E_INVAL: return "invalid argument";
+    case SPAMM_E_NONFINITE: return "non-finite value in input matrix";
+    case SPAMM_E_NOMEM: return "out of device memory";
+    case SPAMM_E_HIP: return "HIP runtime error";
+    case SPAMM_E_RANGE: return "size out of range";
+    case SPAMM_E_MISMATCH: return "operand shapes differ";
+    default: return "unknown status";
+    }
+}
+
+const char *spamm_last_error(void) { return g_err; }
+
+int spamm_build_tree(const float *A, int64_t n, int32_t leaf, void *stream, spamm_tree **out)
+{
+    if (out == nullptr)
+        return fail(SPAMM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (A == nullptr)
+        return fail(SPAMM_E_INVAL, "A is NULL");
+    if (n < 1)
+        return fail(SPAMM_E_INVAL, "n = %lld < 1", (long long)n);
+    if (leaf != 16 && leaf != 32 && leaf != 64)
+        return fail(SPAMM_E_INVAL, "leaf = %d not in {16, 32, 64}", leaf);
+    int32_t d;
+    int64_t np;
+    int rc = depth_of(n, leaf, &d, &np);
+    if (rc)
+        return rc;
+    int dev;
+    if ((rc = prepare_device(&dev)))
+        return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t N = int64_t(1) << d;
+    const size_t tile_bytes = sizeof(float) * (size_t)(N * N) * (size_t)leaf * (size_t)leaf;
+    const size_t norm_bytes = sizeof(double) * (size_t)tier_offset(d + 1);
+
+    spamm_tree *t = new (std::nothrow) spamm_tree();
+    if (!t)
+        return fail(SPAMM_E_NOMEM, "host allocation failed");
+    t->device = dev;
+    t->stream = s;
+    t->n = n;
+    t->np = np;
+    t->leaf = leaf;
+    t->depth = d;
+    hipError_t e = hipMallocAsync((void **)&t->tiles, tile_bytes, s);
+    if (e == hipSuccess)
+        e = hipMallocAsync((void **)&t->norms, norm_bytes, s);
+    if (e == hipSuccess)
+        e = launch_build(A, n, leaf, d, t->tiles, t->norms, s);
+    double root = 0.0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&root, t->norms, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "spamm_build_tree");
+        spamm_tree_free(t);
+        return rc;
+    }
+    if (!isfinite(root)) {
+        spamm_tree_free(t);
+        return fail(SPAMM_E_NONFINITE, "input matrix holds NaN or Inf (||A||_F^2 = %g)", root);
+    }
+    t->root = root;
+    *out = t;
+    return SPAMM_OK;
+}
+
+int spamm_tree_free(spamm_tree *t)
+{
+    if (t == nullptr)
+        return SPAMM_OK;
+    int dev0 = -1;
+    hipGetDevice(&dev0);
+    if (dev0 != t->device)
+        hipSetDevice(t->device);
+    hipError_t e = hipSuccess;
+    if (t->tiles)
+        e = hipFreeAsync(t->tiles, t->stream);
+    if (t->norms && e == hipSuccess)
+        e = hipFreeAsync(t->norms, t->stream);
+    if (dev0 >= 0 && dev0 != t->device)
+        hipSetDevice(dev0);
+    delete t;
+    return e == hipSuccess ? SPAMM_OK : hip_fail(e, "spamm_tree_free");
+}
+
+int spamm_tree_info(const spamm_tree *t, int64_t *n, int32_t *leaf, int32_t *depth, double *norm2)
+{
+    if (t == nullptr)
+        return fail(SPAMM_E_INVAL, "tree is NULL");
+    if (n) *n = t->n;
+    if (leaf) *leaf = t->leaf;
+    if (depth) *depth = t->depth;
+    if (norm2) *norm2 = t->root;
+    return SPAMM_OK;
+}
+
+int spamm_tree_norms(const spamm_tree *t, int32_t tier, double *host, size_t len)
+{
+    if (t == nullptr || host == nullptr)
+        return fail(SPAMM_E_INVAL, "NULL argument");
+    if (tier < 0 || tier > t->depth)
+        return fail(SPAMM_E_INVAL, "tier %d outside 0..%d", tier, t->depth);
+    const int64_t Nt = int64_t(1) << tier;
+    if (len < (size_t)(Nt * Nt))
+        return fail(SPAMM_E_RANGE, "host buffer holds %zu < %lld values", len, (long long)(Nt * Nt));
+    std::vector<double> lin((size_t)(Nt * Nt));
+    HIP_TRY(hipMemcpyAsync(lin.data(), t->norms + tier_offset(tier), sizeof(double) * lin.size(),
+                           hipMemcpyDeviceToHost, t->stream),
+            "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(t->stream), "hipStreamSynchronize");
+    for (int64_t l = 0; l < Nt * Nt; ++l)
+        host[(int64_t)lin_row((uint32_t)l) * Nt + lin_col((uint32_t)l)] = lin[(size_t)l];
+    return SPAMM_OK;
+}
+
+int spamm_tree_matrix(const spamm_tree *t, float *host, size_t len)
+{
+    if (t == nullptr || host == nullptr)
+        return fail(SPAMM_E_INVAL, "NULL argument");
+    const int64_t np = t->np, b = t->leaf, N = int64_t(1) << t->depth;
+    if (len < (size_t)(np * np))
+        return fail(SPAMM_E_RANGE, "host buffer holds %zu < %lld values", len, (long long)(np * np));
+    std::vector<float> tiles((size_t)(np * np));
+    HIP_TRY(hipMemcpyAsync(tiles.data(), t->tiles, sizeof(float) * tiles.size(),
+                           hipMemcpyDeviceToHost, t->stream),
+            "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(t->stream), "hipStreamSynchronize");
+    for (int64_t l = 0; l < N * N; ++l) {
+        const int64_t I = lin_row((uint32_t)l), J = lin_col((uint32_t)l);
+        const float *src = tiles.data() + l * b * b;
+        for (int64_t r = 0; r < b; ++r)
+            memcpy(host + (I * b + r) * np + J * b, src + r * b, sizeof(float) * (size_t)b);
+    }
+    return SPAMM_OK;
+}
+
+int spamm_plan_free(spamm_plan *p)
+{
+    if (p == nullptr)
+        return SPAMM_OK;
+    int dev0 = -1;
+    hipGetDevice(&dev0);
+    if (dev0 != p->device)
+        hipSetDevice(p->device);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < p->npool; ++i) {
+        hipError_t f = hipFreeAsync(p->pool[i], p->stream);
+        if (e == hipSuccess)
+            e = f;
+    }
+    if (dev0 >= 0 && dev0 != p->device)
+        hipSetDevice(dev0);
+    delete p;
+    return e == hipSuccess ? SPAMM_OK : hip_fail(e, "spamm_plan_free");
+}
+
+int spamm_symbolic(const spamm_tree *A, const spamm_tree *B, double tau, void *stream,
+                   spamm_plan **out)
+{
+    if (out == nullptr)
+        return fail(SPAMM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (A == nullptr || B == nullptr)
+        return fail(SPAMM_E_INVAL, "tree is NULL");
+    if (!(tau >= 0.0) || isinf(tau))
+        return fail(SPAMM_E_INVAL, "tau = %g must be finite and >= 0", tau);
+    if (tau > 0.0 && tau < 1e-150)
+        return fail(SPAMM_E_INVAL, "tau = %g below 1e-150 (tau^2 would underflow)", tau);
+    if (A->n != B->n || A->leaf != B->leaf)
+        return fail(SPAMM_E_MISMATCH, "A is %lld/%d, B is %lld/%d (n/leaf)", (long long)A->n,
+                    A->leaf, (long long)B->n, B->leaf);
+    int dev;
+    int rc = prepare_device(&dev);
+    if (rc)
+        return rc;
+    if (A->device != dev || B->device != dev)
+        return fail(SPAMM_E_INVAL, "trees live on device %d/%d, current device is %d", A->device,
+                    B->device, dev);
+    spamm_plan *p = new (std::nothrow) spamm_plan();
+    if (!p)
+        return fail(SPAMM_E_NOMEM, "host allocation failed");
+    hipStream_t s = (hipStream_t)stream;
+    p->device = dev;
+    p->stream = s;
+    p->A = A;
+    p->B = B;
+    p->depth = A->depth;
+    p->leaf = A->leaf;
+    p->n = A->n;
+    p->tau = tau;
+    p->T2 = tau * tau;
+    const int d = p->depth;
+    p->nblocks = d == 0 ? 1 : (int64_t(1) << (2 * (d - 1)));
+
+    // capacities (worst case: every candidate kept)
+    int64_t rp = 0;
+    for (int t = 0; t < d; ++t) {
+        p->rp_off[t] = rp;
+        rp += (int64_t(1) << (2 * t)) + 1;
+    }
+    p->rp_off[d] = rp;
+    int64_t cap_list[2] = {1, 1};
+    for (int t = 0; t < d; ++t)
+        cap_list[t & 1] = std::max(cap_list[t & 1], int64_t(1) << (3 * t));
+    const int64_t ncounts = d == 0 ? 1 : (int64_t(1) << (2 * (d - 1)));
+    const int64_t cap_bent = d == 0 ? 1 : p->nblocks * (int64_t(1) << d);
+    const size_t npart = scan_partials_len((uint32_t)std::max<int64_t>(ncounts, 1));
+
+    struct Req { void **dst; size_t bytes; } reqs[] = {
+        {(void **)&p->rowptr, sizeof(uint32_t) * (size_t)std::max<int64_t>(rp, 2)},
+        {(void **)&p->list[0], sizeof(uint32_t) * (size_t)cap_list[0]},
+        {(void **)&p->list[1], sizeof(uint32_t) * (size_t)cap_list[1]},
+        {(void **)&p->counts, sizeof(uint32_t) * (size_t)ncounts},
+        {(void **)&p->partials, sizeof(uint32_t) * npart},
+        {(void **)&p->browptr, sizeof(uint32_t) * (size_t)(p->nblocks + 1)},
+        {(void **)&p->bent, sizeof(uint32_t) * (size_t)cap_bent},
+        {(void **)&p->leafK, sizeof(uint64_t)},
+    };
+    for (auto &r : reqs) {
+        hipError_t e = hipMallocAsync(r.dst, r.bytes, s);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "hipMallocAsync (plan)");
+            spamm_plan_free(p);
+            return rc;
+        }
+        p->pool[p->npool++] = *r.dst;
+    }
+    hipError_t e = launch_cull(p, s);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "cull launch");
+        spamm_plan_free(p);
+        return rc;
+    }
+    *out = p;
+    return SPAMM_OK;
+}
+
+int spamm_numeric(const spamm_plan *p, float *C, void *stream)
+{
+    if (p == nullptr || C == nullptr)
+        return fail(SPAMM_E_INVAL, "NULL argument");
+    HIP_TRY(launch_gemm(p, C, (hipStream_t)stream), "leaf GEMM launch");
+    return SPAMM_OK;
+}
+
+int spamm_plan_stats(const spamm_plan *p, spamm_stats *out)
+{
+    if (p == nullptr || out == nullptr)
+        return fail(SPAMM_E_INVAL, "NULL argument");
+    memset(out, 0, sizeof *out);
+    const int d = p->depth;
+    out->depth = d;
+    out->leaf = p->leaf;
+    out->symbolic_ms = -1.0;
+    out->numeric_ms = -1.0;
+    std::vector<uint32_t> tot((size_t)d + 1, 0);
+    for (int t = 0; t < d; ++t)
+        HIP_TRY(hipMemcpyAsync(&tot[(size_t)t], p->rowptr + p->rp_off[t] + (int64_t(1) << (2 * t)),
+                               sizeof(uint32_t), hipMemcpyDeviceToHost, p->stream),
+                "hipMemcpyAsync");
+    uint64_t K = 0;
+    uint32_t entries = 0;
+    HIP_TRY(hipMemcpyAsync(&K, p->leafK, sizeof K, hipMemcpyDeviceToHost, p->stream), "hipMemcpyAsync");
+    HIP_TRY(hipMemcpyAsync(&entries, p->browptr + p->nblocks, sizeof entries, hipMemcpyDeviceToHost,
+                           p->stream),
+            "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+    for (int t = 0; t < d; ++t)
+        out->kept[t] = tot[(size_t)t];
+    out->kept[d] = (int64_t)K;
+    out->tasks = (int64_t)K;
+    out->block_entries = entries;
+    out->flops = 2.0 * (double)p->leaf * p->leaf * p->leaf * (double)K;
+    return SPAMM_OK;
+}
+
+int spamm_plan_tasks(const spamm_plan *p, uint64_t *host, size_t cap, size_t *count)
+{
+    if (p == nullptr || count == nullptr)
+        return fail(SPAMM_E_INVAL, "NULL argument");
+    const size_t nb = (size_t)p->nblocks;
+    std::vector<uint32_t> rp(nb + 1);
+    HIP_TRY(hipMemcpyAsync(rp.data(), p->browptr, sizeof(uint32_t) * (nb + 1), hipMemcpyDeviceToHost,
+                           p->stream),
+            "hipMemcpyAsync");
+    uint64_t K = 0;
+    HIP_TRY(hipMemcpyAsync(&K, p->leafK, sizeof K, hipMemcpyDeviceToHost, p->stream), "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+    *count = (size_t)K;
+    if (host == nullptr || cap < K)
+        return host == nullptr && cap == 0 ? SPAMM_OK
+                                           : fail(SPAMM_E_RANGE, "cap %zu < K = %llu", cap,
+                                                  (unsigned long long)K);
+    std::vector<uint32_t> ent(rp[nb]);
+    if (!ent.empty()) {
+        HIP_TRY(hipMemcpyAsync(ent.data(), p->bent, sizeof(uint32_t) * ent.size(),
+                               hipMemcpyDeviceToHost, p->stream),
+                "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+    }
+    // Expand block entries to leaf keys in (output leaf, k) order: leaf
+    // 4 P + q of block P takes the entries whose mask has bit q.
+    size_t o = 0;
+    for (size_t P = 0; P < nb; ++P)
+        for (uint32_t q = 0; q < 4; ++q) {
+            const uint64_t lc = p->depth == 0 ? 0 : 4 * (uint64_t)P + q;
+            for (uint32_t e = rp[P]; e < rp[P + 1]; ++e)
+                if ((ent[e] >> (16 + q)) & 1u) {
+                    if (o >= cap)
+                        return fail(SPAMM_E_RANGE, "inconsistent task count");
+                    host[o++] = (lc << 32) | (ent[e] & 0xFFFFu);
+                }
+        }
+    if (o != K)
+        return fail(SPAMM_E_HIP, "task count mismatch: %zu expanded vs %llu counted", o,
+                    (unsigned long long)K);
+    return SPAMM_OK;
+}
+
+int spamm_multiply_ex(const spamm_tree *A, const spamm_tree *B, double tau, float *C, void *stream,
+                      spamm_stats *stats)
+{
+    if (C == nullptr)
+        return fail(SPAMM_E_INVAL, "C is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (stats) {
+        for (auto &x : ev)
+            HIP_TRY(hipEventCreate(&x), "hipEventCreate");
+        HIP_TRY(hipEventRecord(ev[0], s), "hipEventRecord");
+    }
+    spamm_plan *p = nullptr;
+    int rc = spamm_symbolic(A, B, tau, stream, &p);
+    if (rc == SPAMM_OK && stats) {
+        hipError_t e = hipEventRecord(ev[1], s);
+        if (e != hipSuccess)
+            rc = hip_fail(e, "hipEventRecord");
+    }
+    if (rc == SPAMM_OK)
+        rc = spamm_numeric(p, C, stream);
+    if (rc == SPAMM_OK && stats) {
+        hipError_t e = hipEventRecord(ev[2], s);
+        if (e != hipSuccess)
+            rc = hip_fail(e, "hipEventRecord");
+        if (rc == SPAMM_OK)
+            rc = spamm_plan_stats(p, stats);   // synchronizes
+        float ms = 0.f;
+        if (rc == SPAMM_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess)
+            stats->symbolic_ms = ms;
+        if (rc == SPAMM_OK && hipEventElapsedTime(&ms, ev[1], ev[2]) == hipSuccess)
+            stats->numeric_ms = ms;
+    }
+    int rc2 = spamm_plan_free(p);
+    for (auto &x : ev)
+        if (x)
+            hipEventDestroy(x);
+    return rc != SPAMM_OK ? rc : rc2;
+}
+
+int spamm_multiply(const spamm_tree *A, const spamm_tree *B, double tau, float *C, void *stream)
+{
+    return spamm_multiply_ex(A, B, tau, C, stream, nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Shared device helpers and internal structures of libspamm (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spamm.h"
+
+namespace spamm {
+
+constexpr int kWave = 64;
+constexpr int kMaxDepth = 10;        // N = 2^d <= 1024 tiles per dimension
+
+// ---- linear (Morton) index, Eq. linear index: row bits on odd positions ----
+__host__ __device__ inline uint32_t spread_bits(uint32_t x)
+{
+    x &= 0xFFFFu;
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+
+__host__ __device__ inline uint32_t compact_bits(uint32_t x)
+{
+    x &= 0x55555555u;
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+    x = (x | (x >> 4)) & 0x00FF00FFu;
+    x = (x | (x >> 8)) & 0x0000FFFFu;
+    return x;
+}
+
+__host__ __device__ inline uint32_t lin_index(uint32_t i, uint32_t j)
+{
+    return (spread_bits(i) << 1) | spread_bits(j);
+}
+
+__host__ __device__ inline uint32_t lin_row(uint32_t l) { return compact_bits(l >> 1); }
+__host__ __device__ inline uint32_t lin_col(uint32_t l) { return compact_bits(l); }
+
+// Offset of tier t inside the norm pyramid: tiers 0..d stored back to back,
+// tier t holds 4^t values in linear-index order.
+__host__ __device__ inline int64_t tier_offset(int t) { return ((int64_t(1) << (2 * t)) - 1) / 3; }
+
+// The SpAMM keep decision on stored squared norms (both FP64):
+// zero norm -> NULL link, never kept; otherwise kept unless s_A s_B < tau^2.
+__device__ inline bool keep_pair(double sa, double sb, double T2)
+{
+    return (sa > 0.0) & (sb > 0.0) & !(sa * sb < T2);
+}
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+__device__ inline uint64_t lanes_below() { return (uint64_t(1) << lane_id()) - 1; }
+
+}  // namespace spamm
+
+// ---- internal handles ------------------------------------------------------
+struct spamm_tree {
+    int device;
+    hipStream_t stream;     // stream the tree was built on (frees are ordered there)
+    int64_t n, np;
+    int32_t leaf, depth;
+    float *tiles;           // N^2 leaves, linear-index order, row-major inside
+    double *norms;          // tiers 0..d, tier_offset layout
+    double root;            // ||A||_F^2
+};
+
+struct spamm_plan {
+    int device;
+    hipStream_t stream;
+    const spamm_tree *A, *B;
+    int32_t depth, leaf;
+    int64_t n;
+    double tau, T2;
+    // tier lists for t < d: CSR over the 4^t tier-t output tiles (linear
+    // index), entries = kept k at that tier, ascending
+    uint32_t *rowptr;       // all tiers t = 0..d-1, offset rp_off[t], 4^t + 1 each
+    int64_t rp_off[spamm::kMaxDepth + 1];
+    uint32_t *list[2];      // ping-pong tier lists
+    uint32_t *counts;       // per-child-tile counts of the tier being built
+    uint32_t *partials;     // scan block sums
+    // leaf-tier schedule: CSR over the GEMM blocks (tier d-1 tiles, or the
+    // single leaf when d = 0); entry = k | (quadrant mask << 16)
+    uint32_t *browptr;
+    uint32_t *bent;
+    uint64_t *leafK;        // number of kept leaf triples
+    int64_t nblocks;
+    void *pool[8];          // allocations owned by the plan
+    int npool;
+};

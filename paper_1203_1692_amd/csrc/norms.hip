@@ -1,0 +1,146 @@
+// Quadtree construction (Sec. II.A, II.B): pack the zero-padded leaves and
+// build the FP64 squared-Frobenius-norm pyramid bottom-up (Eq. norm).
+//
+// Canonical order (the cull decisions depend on every bit of these values):
+//   leaf   s = pairwise (recursive-halving) sum of x_e^2 over the leaf's
+//          row-major flattened index e in [0, b^2);
+//   parent s = (s_11 + s_12) + (s_21 + s_22).
+// A wave owns one leaf.  Load m of lane L covers e = 256 m + 4 L + x
+// (x = 0..3, one float4): the tree over e is then the in-lane pair sums
+// (bits 0-1 of e), a six-step xor butterfly over lanes (bits 2-7) and an
+// in-register tree over m (bits 8 and up).  Squares of FP32 values are exact
+// in FP64, so only the additions round and their order is fixed.
+#include "common.hpp"
+
+namespace spamm {
+
+template <int VEC>
+__device__ inline float4 load_row4(const float *__restrict__ A, int64_t n, int64_t row,
+                                   int64_t col)
+{
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (row >= n || col >= n)
+        return v;
+    const float *p = A + row * n + col;
+    if (col + 3 < n) {
+        if constexpr (VEC == 4) {
+            v = *reinterpret_cast<const float4 *>(p);
+        } else if constexpr (VEC == 2) {
+            const float2 a = reinterpret_cast<const float2 *>(p)[0];
+            const float2 b = reinterpret_cast<const float2 *>(p)[1];
+            v = make_float4(a.x, a.y, b.x, b.y);
+        } else {
+            v = make_float4(p[0], p[1], p[2], p[3]);
+        }
+    } else {
+        v.x = p[0];
+        if (col + 1 < n) v.y = p[1];
+        if (col + 2 < n) v.z = p[2];
+    }
+    return v;
+}
+
+// Block of 4 waves = the 4 children of one tier-(d-1) node (linear indices
+// 4p .. 4p+3); the block also writes that parent's norm when `parent` != null.
+template <int B, int VEC>
+__global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ A, int64_t n,
+                                                      float *__restrict__ tiles,
+                                                      double *__restrict__ leaf_norm,
+                                                      double *__restrict__ parent,
+                                                      uint32_t ntiles)
+{
+    constexpr int M = (B * B) / 256;   // float4 loads per lane
+    static_assert(M >= 1 && (M & (M - 1)) == 0, "leaf must be 16, 32 or 64");
+    __shared__ double part[4];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const uint32_t l = blockIdx.x * 4u + (uint32_t)w;
+    double s = 0.0;
+    if (l < ntiles) {
+        const int64_t I = lin_row(l), J = lin_col(l);
+        float4 v[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int e = 256 * m + 4 * lane;
+            v[m] = load_row4<VEC>(A, n, I * B + e / B, J * B + e % B);
+        }
+        float *dst = tiles + (int64_t)l * (B * B);
+        double sm[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int e = 256 * m + 4 * lane;
+            *reinterpret_cast<float4 *>(dst + e) = v[m];
+            const double x0 = v[m].x, x1 = v[m].y, x2 = v[m].z, x3 = v[m].w;
+            double t = (x0 * x0 + x1 * x1) + (x2 * x2 + x3 * x3);
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1)
+                t += __shfl_xor(t, o);
+            sm[m] = t;
+        }
+#pragma unroll
+        for (int st = 1; st < M; st <<= 1)
+#pragma unroll
+            for (int i = 0; i < M; i += 2 * st)
+                sm[i] += sm[i + st];
+        s = sm[0];
+        if (lane == 0)
+            leaf_norm[l] = s;
+    }
+    if (parent != nullptr) {
+        if (lane == 0)
+            part[w] = s;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            parent[blockIdx.x] = (part[0] + part[1]) + (part[2] + part[3]);
+    }
+}
+
+// Tiers top-1 .. 0 from tier `top` (already built), one workgroup.
+__global__ __launch_bounds__(1024) void norm_pyramid(double *__restrict__ norms, int top)
+{
+    for (int t = top - 1; t >= 0; --t) {
+        const double *ch = norms + tier_offset(t + 1);
+        double *pa = norms + tier_offset(t);
+        const int64_t cnt = int64_t(1) << (2 * t);
+        for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x)
+            pa[i] = (ch[4 * i] + ch[4 * i + 1]) + (ch[4 * i + 2] + ch[4 * i + 3]);
+        __syncthreads();
+    }
+}
+
+template <int B>
+static hipError_t launch_leaf(const float *A, int64_t n, int vec, float *tiles, double *leaf,
+                              double *parent, uint32_t ntiles, hipStream_t s)
+{
+    const dim3 grid((ntiles + 3) / 4), block(256);
+    if (vec == 4)
+        hipLaunchKernelGGL((leaf_norm_pack<B, 4>), grid, block, 0, s, A, n, tiles, leaf, parent, ntiles);
+    else if (vec == 2)
+        hipLaunchKernelGGL((leaf_norm_pack<B, 2>), grid, block, 0, s, A, n, tiles, leaf, parent, ntiles);
+    else
+        hipLaunchKernelGGL((leaf_norm_pack<B, 1>), grid, block, 0, s, A, n, tiles, leaf, parent, ntiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *tiles,
+                        double *norms, hipStream_t s)
+{
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(A);
+    const int vec = (n % 4 == 0 && addr % 16 == 0) ? 4 : (n % 2 == 0 && addr % 8 == 0) ? 2 : 1;
+    const uint32_t ntiles = 1u << (2 * depth);
+    double *leafn = norms + tier_offset(depth);
+    double *parent = depth >= 1 ? norms + tier_offset(depth - 1) : nullptr;
+    hipError_t e;
+    switch (leaf) {
+    case 16: e = launch_leaf<16>(A, n, vec, tiles, leafn, parent, ntiles, s); break;
+    case 32: e = launch_leaf<32>(A, n, vec, tiles, leafn, parent, ntiles, s); break;
+    case 64: e = launch_leaf<64>(A, n, vec, tiles, leafn, parent, ntiles, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess || depth < 2)
+        return e;
+    hipLaunchKernelGGL(norm_pyramid, dim3(1), dim3(1024), 0, s, norms, depth - 1);
+    return hipGetLastError();
+}
+
+}  // namespace spamm

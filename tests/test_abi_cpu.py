@@ -1,0 +1,60 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/spamm.h declares, and rejects bad arguments before touching HIP."""
+import ctypes
+import re
+
+import pytest
+
+import paper_1203_1692_amd as sp
+
+
+def test_library_exports_every_declared_symbol():
+    lib = sp.load()
+    names = sp.header_functions()
+    assert "spamm_build_tree" in names and "spamm_multiply" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_header_status_codes_match_binding():
+    text = open(sp.HEADER).read()
+    codes = dict((m[0], int(m[1])) for m in re.findall(r"#define (SPAMM_[A-Z_]+)\s+(-?\d+)", text))
+    assert codes["SPAMM_OK"] == sp.SPAMM_OK
+    assert codes["SPAMM_E_INVAL"] == sp.SPAMM_E_INVAL
+    assert codes["SPAMM_E_NONFINITE"] == sp.SPAMM_E_NONFINITE
+    assert codes["SPAMM_E_NOMEM"] == sp.SPAMM_E_NOMEM
+    assert codes["SPAMM_E_HIP"] == sp.SPAMM_E_HIP
+    assert codes["SPAMM_E_RANGE"] == sp.SPAMM_E_RANGE
+    assert codes["SPAMM_E_MISMATCH"] == sp.SPAMM_E_MISMATCH
+
+
+def test_strerror_names_every_code():
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert sp.strerror(code) != "unknown status"
+    assert sp.strerror(-99) == "unknown status"
+
+
+def test_argument_checks_before_any_device_call():
+    lib = sp.load()
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(4096)
+    assert lib.spamm_build_tree(None, 64, 32, None, ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_build_tree(fake, 0, 32, None, ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_build_tree(fake, 64, 48, None, ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_build_tree(fake, 64, 128, None, ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_build_tree(fake, 64, 32, None, None) == sp.SPAMM_E_INVAL
+    # more than 1024 leaves per dimension
+    assert lib.spamm_build_tree(fake, 16 * 1024 + 1, 16, None, ctypes.byref(h)) == sp.SPAMM_E_RANGE
+    assert b"tiers" in lib.spamm_last_error()
+    assert lib.spamm_symbolic(None, None, 0.0, None, ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_numeric(None, None, None) == sp.SPAMM_E_INVAL
+    assert lib.spamm_multiply(None, None, 1e-6, fake, None) == sp.SPAMM_E_INVAL
+    assert lib.spamm_tree_info(None, None, None, None, None) == sp.SPAMM_E_INVAL
+    assert lib.spamm_tree_free(None) == sp.SPAMM_OK
+    assert lib.spamm_plan_free(None) == sp.SPAMM_OK
+
+
+def test_python_binding_rejects_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError):
+        sp.build_tree(torch.zeros(8, 8), 16)
