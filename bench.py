@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""SpAMM benchmark on one MI355X.
+
+One step = the whole hot path over one input matrix already resident in HBM:
+build the quadtree (leaf norms + pack + norm pyramid), then the product
+C = A A under the SpAMM condition (tier-by-tier cull + MFMA leaf GEMM).
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME]
+
+Prints one JSON line.  `value` is kept-leaf TFLOP/s over the whole step
+(2 n_b^3 K / step time).  `roofline` rates the leaf GEMM kernel (the dominant
+kernel) against the FP32 MFMA peak, with its duration from HIP events recorded
+around its launch on the stream it runs on.  `cpu_baseline` times the FP64
+oracle on a seeded sample of output leaves of the same matrix.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MFMA_FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "leaf_gemm_cluster1310-n32750_traffic.json")
+
+
+def kernel_source_digest() -> str:
+    with open(os.path.join(ROOT, "paper_1203_1692_amd", "csrc", "gemm.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per leaf-GEMM launch from the committed rocprofv3 counter runs,
+    or None when absent, for another workload, or taken on other kernel code."""
+    try:
+        with open(PROFILE_TRAFFIC) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("workload") != workload or rec.get("gemm_hip_sha256") != kernel_source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def sample_tiles(N: int, count: int, seed: int = 0):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    flat = rng.choice(N * N, size=min(count, N * N), replace=False)
+    return [(int(f) // N, int(f) % N) for f in np.sort(flat)]
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cluster1310-n32750")
+    ap.add_argument("--tau", type=float, default=None)
+    ap.add_argument("--sample-tiles", type=int, default=96,
+                    help="output leaves checked against the dense FP64 product")
+    ap.add_argument("--oracle-tiles", type=int, default=2048,
+                    help="output leaves computed by the FP64 oracle (CPU baseline)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (for scaling HBM counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the SpAMM path here is single-device "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1203_1692_amd as sp
+    import workloads
+
+    wl = workloads.WORKLOADS[args.workload]
+    tau = wl.tau if args.tau is None else args.tau
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    sp.load()
+
+    t_gen = time.perf_counter()
+    A = wl.matrix()
+    t_gen = time.perf_counter() - t_gen
+    n, leaf = wl.n, wl.leaf
+    dA = torch.from_numpy(A).to(dev)
+    C = torch.empty_like(dA)
+    torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    def step():
+        tree = sp.build_tree(dA, leaf)          # synchronizes once (root norm)
+        st = sp.multiply_ex(tree, tree, tau, C)  # events around cull and GEMM
+        tree.free()
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    st = stats[-1]
+    flops = st["flops"]
+    K = st["tasks"]
+    gemm_ms = sum(s["numeric_ms"] for s in stats) / len(stats)
+    cull_ms = sum(s["symbolic_ms"] for s in stats) / len(stats)
+    value = flops / (ms_step * 1e-3) / 1e12
+    gemm_tflops = flops / (gemm_ms * 1e-3) / 1e12
+
+    # ---- error on sampled output leaves -------------------------------------
+    d = st["depth"]
+    N = 1 << d
+    tiles = sample_tiles(N, args.sample_tiles)
+    Ch = C.cpu().numpy()
+    err_exact = 0.0
+    for (I, J) in tiles:
+        r0, r1 = I * leaf, min((I + 1) * leaf, n)
+        c0, c1 = J * leaf, min((J + 1) * leaf, n)
+        if r0 >= n or c0 >= n:
+            continue
+        exact = A[r0:r1].astype(np.float64) @ A[:, c0:c1].astype(np.float64)
+        err_exact = max(err_exact, float(np.abs(Ch[r0:r1, c0:c1] - exact).max()))
+
+    out = {
+        "metric": "kept-tile TFLOP/s (2 n_b^3 K per step / step time)",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name, "n": n, "n_padded": leaf << d, "leaf": leaf, "tau": tau,
+            "depth": d, "kept_tasks": K, "kept_per_tier": st["kept"],
+            "kept_fraction": K / float(N) ** 3, "block_entries": st["block_entries"],
+            "ms_multiply": round(cull_ms + gemm_ms, 3), "ms_cull": round(cull_ms, 3),
+            "ms_leaf_gemm": round(gemm_ms, 3),
+            "ms_build": round(ms_step - cull_ms - gemm_ms, 3),
+            "max_norm_err_vs_fp64_dense_sampled": err_exact,
+            "error_sample_tiles": len(tiles),
+            "effective_tflops_2n3": round(2.0 * n ** 3 / (ms_step * 1e-3) / 1e12, 3),
+        },
+        "roofline": {
+            "bound": "mfma",
+            "achieved": round(gemm_tflops, 3),
+            "peak": MFMA_FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(gemm_tflops / MFMA_FP32_PEAK_TFLOPS, 4),
+            "traffic": measured_traffic(wl.name),
+        },
+    }
+
+    # ---- CPU baseline: the FP64 oracle on the sampled output leaves ----------
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = min(16, os.cpu_count() or 1)
+        otiles = sample_tiles(N, args.oracle_tiles, seed=1)
+        t = time.perf_counter()
+        Ct, counts, _ = oracle.spamm_tiles(A, A, leaf, tau, otiles, threads=threads)
+        t = time.perf_counter() - t
+        cflops = 2.0 * leaf ** 3 * float(counts.sum())
+        err_oracle = 0.0
+        for s, (I, J) in enumerate(otiles):
+            r0, r1 = I * leaf, min((I + 1) * leaf, n)
+            c0, c1 = J * leaf, min((J + 1) * leaf, n)
+            if r0 >= n or c0 >= n:
+                continue
+            err_oracle = max(err_oracle, float(np.abs(
+                Ch[r0:r1, c0:c1] - Ct[s, :r1 - r0, :c1 - c0]).max()))
+        out["config"]["max_norm_err_vs_oracle_sampled"] = err_oracle
+        out["config"]["oracle_sample_tiles"] = len(otiles)
+        out["cpu_baseline"] = {
+            "value": cflops / t / 1e12,
+            "unit": "TFLOP/s",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": (f"{len(otiles)} seeded output leaves of {wl.name} (tau={tau:g}), "
+                       f"{int(counts.sum())} kept leaf products, recursive FP64 oracle incl. its "
+                       f"full-matrix norm pass, {t:.1f} s wall"),
+        }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -311,7 +311,7 @@ int spamm_symbolic(const spamm_tree *A, const spamm_tree *B, double tau, void *s
         {(void **)&p->rowptr, sizeof(uint32_t) * (size_t)std::max<int64_t>(rp, 2)},
         {(void **)&p->list[0], sizeof(uint32_t) * (size_t)cap_list[0]},
         {(void **)&p->list[1], sizeof(uint32_t) * (size_t)cap_list[1]},
-        {(void **)&p->counts, sizeof(uint32_t) * (size_t)ncounts},
+        {(void **)&p->counts, sizeof(uint32_t) * 2 * (size_t)ncounts},
         {(void **)&p->partials, sizeof(uint32_t) * npart},
         {(void **)&p->browptr, sizeof(uint32_t) * (size_t)(p->nblocks + 1)},
         {(void **)&p->bent, sizeof(uint32_t) * (size_t)cap_bent},

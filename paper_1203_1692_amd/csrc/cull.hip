@@ -82,8 +82,7 @@ __global__ __launch_bounds__(256) void cull_count(const double *__restrict__ nA,
                                                   const double *__restrict__ nB, double T2,
                                                   const uint32_t *__restrict__ prow,
                                                   const uint32_t *__restrict__ plist,
-                                                  uint32_t nparents, uint32_t *__restrict__ counts,
-                                                  unsigned long long *__restrict__ leafK)
+                                                  uint32_t nparents, uint32_t *__restrict__ counts)
 {
     const uint32_t P = blockIdx.x * 4u + (threadIdx.x >> 6);
     if (P >= nparents)
@@ -110,13 +109,13 @@ __global__ __launch_bounds__(256) void cull_count(const double *__restrict__ nA,
         }
     }
     if constexpr (LAST) {
-        // lane-local task counts -> one atomic per wave (integer, order-free)
+        // entries per block for the GEMM schedule; leaf products per block
+        // (counts[nparents + P]) are summed by reduce_tasks
         for (int o = 32; o > 0; o >>= 1)
             tasks += __shfl_xor(tasks, o);
         if (lane == 0) {
             counts[P] = entries;
-            if (tasks)
-                atomicAdd(leafK, (unsigned long long)tasks);
+            counts[nparents + P] = tasks;
         }
     } else {
         if (lane == 0) {
@@ -180,6 +179,27 @@ __global__ __launch_bounds__(256) void cull_emit(const double *__restrict__ nA,
                 run[q] += __popcll(b0) + __popcll(b1);
             }
         }
+    }
+}
+
+// Sum of m uint32 values into one uint64 (single workgroup).
+__global__ __launch_bounds__(1024) void reduce_tasks(const uint32_t *__restrict__ in, uint32_t m,
+                                                     uint64_t *__restrict__ out)
+{
+    __shared__ uint64_t part[1024 / kWave];
+    uint64_t s = 0;
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x)
+        s += in[i];
+    for (int o = 32; o > 0; o >>= 1)
+        s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i)
+            t += part[i];
+        *out = t;
     }
 }
 
@@ -314,7 +334,7 @@ hipError_t launch_cull(spamm_plan *p, hipStream_t s)
         if (t < d) {
             uint32_t *crow = p->rowptr + p->rp_off[t];
             hipLaunchKernelGGL(cull_count<false>, grid, block, 0, s, tA, tB, p->T2, prow, plist, np,
-                               p->counts, (unsigned long long *)p->leafK);
+                               p->counts);
             if ((e = hipGetLastError()) != hipSuccess)
                 return e;
             if ((e = launch_scan(p->counts, 4 * np, crow, p->partials, s)) != hipSuccess)
@@ -323,7 +343,8 @@ hipError_t launch_cull(spamm_plan *p, hipStream_t s)
                                (const uint32_t *)crow, p->list[t & 1]);
         } else {
             hipLaunchKernelGGL(cull_count<true>, grid, block, 0, s, tA, tB, p->T2, prow, plist, np,
-                               p->counts, (unsigned long long *)p->leafK);
+                               p->counts);
+            hipLaunchKernelGGL(reduce_tasks, dim3(1), dim3(1024), 0, s, p->counts + np, np, p->leafK);
             if ((e = hipGetLastError()) != hipSuccess)
                 return e;
             if ((e = launch_scan(p->counts, np, p->browptr, p->partials, s)) != hipSuccess)

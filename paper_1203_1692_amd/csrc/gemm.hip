@@ -38,26 +38,80 @@ __device__ inline uint32_t xcd_block(uint32_t bid, uint32_t nblocks)
     return (bid % 8u) * (nblocks / 8u) + bid / 8u;
 }
 
+// One entry's operand leaves in registers: A_(2I, k), A_(2I+1, k),
+// B_(k, 2J), B_(k, 2J+1); thread t holds float4 number t + 256 i of each leaf.
 template <int B>
-__device__ inline void stage_A(float *__restrict__ dst, const float *__restrict__ src)
+struct Stage {
+    static constexpr int kVec = B * B / 4;                   // float4 per leaf
+    static constexpr int kPer = kVec >= 256 ? kVec / 256 : 1;
+    float4 v[4][kPer];
+};
+
+template <int B>
+__device__ inline void stage_load(Stage<B> &st, uint32_t ent, const float *__restrict__ tA,
+                                  const float *__restrict__ tB, uint32_t I0, uint32_t J0)
 {
-    constexpr int P = B + 1;
-    for (int f = threadIdx.x; f < B * B / 4; f += 256) {
-        const float4 v = reinterpret_cast<const float4 *>(src)[f];
-        const int r = (4 * f) / B, c = (4 * f) % B;
-        float *o = dst + r * P + c;
-        o[0] = v.x;
-        o[1] = v.y;
-        o[2] = v.z;
-        o[3] = v.w;
+    using S = Stage<B>;
+    const uint32_t k = ent & 0xFFFFu, mask = ent >> 16;
+    const bool need[4] = {(mask & 0x3u) != 0, (mask & 0xCu) != 0, (mask & 0x5u) != 0,
+                          (mask & 0xAu) != 0};
+    const float4 *src[4] = {
+        reinterpret_cast<const float4 *>(tA + (int64_t)lin_index(I0, k) * (B * B)),
+        reinterpret_cast<const float4 *>(tA + (int64_t)lin_index(I0 + 1, k) * (B * B)),
+        reinterpret_cast<const float4 *>(tB + (int64_t)lin_index(k, J0) * (B * B)),
+        reinterpret_cast<const float4 *>(tB + (int64_t)lin_index(k, J0 + 1) * (B * B))};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (!need[t])
+            continue;
+#pragma unroll
+        for (int i = 0; i < S::kPer; ++i) {
+            const int f = threadIdx.x + 256 * i;
+            if (S::kVec >= 256 || f < S::kVec)
+                st.v[t][i] = src[t][f];
+        }
     }
 }
 
 template <int B>
-__device__ inline void stage_B(float *__restrict__ dst, const float *__restrict__ src)
+__device__ inline void stage_store(const Stage<B> &st, uint32_t ent, float *__restrict__ As,
+                                   float *__restrict__ Bs)
 {
-    for (int f = threadIdx.x; f < B * B / 4; f += 256)
-        reinterpret_cast<float4 *>(dst)[f] = reinterpret_cast<const float4 *>(src)[f];
+    using S = Stage<B>;
+    using G = GemmShape<B>;
+    const uint32_t mask = ent >> 16;
+    const bool need[4] = {(mask & 0x3u) != 0, (mask & 0xCu) != 0, (mask & 0x5u) != 0,
+                          (mask & 0xAu) != 0};
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        if (!need[t])
+            continue;
+        float *dst = As + t * G::kTileA;
+#pragma unroll
+        for (int i = 0; i < S::kPer; ++i) {
+            const int f = threadIdx.x + 256 * i;
+            if (S::kVec >= 256 || f < S::kVec) {
+                const int r = (4 * f) / B, c = (4 * f) % B;
+                float *o = dst + r * G::kPitchA + c;
+                o[0] = st.v[t][i].x;
+                o[1] = st.v[t][i].y;
+                o[2] = st.v[t][i].z;
+                o[3] = st.v[t][i].w;
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        if (!need[2 + t])
+            continue;
+        float4 *dst = reinterpret_cast<float4 *>(Bs + t * G::kTileB);
+#pragma unroll
+        for (int i = 0; i < S::kPer; ++i) {
+            const int f = threadIdx.x + 256 * i;
+            if (S::kVec >= 256 || f < S::kVec)
+                dst[f] = st.v[2 + t][i];
+        }
+    }
 }
 
 template <int B>
@@ -96,16 +150,24 @@ __global__ __launch_bounds__(256) void leaf_gemm(const float *__restrict__ tA,
         acc16 = floatx4{0};
     }
 
+    // Register double buffering: the leaves of entry e+1 are in flight from
+    // memory while entry e is multiplied out of LDS.
     const uint32_t e0 = browptr[blk], e1 = browptr[blk + 1];
+    Stage<B> st;
+    uint32_t ent = 0;
+    if (e0 < e1) {
+        ent = bent[e0];
+        stage_load<B>(st, ent, tA, tB, I0, J0);
+    }
     for (uint32_t e = e0; e < e1; ++e) {
-        const uint32_t ent = bent[e];
-        const uint32_t k = ent & 0xFFFFu, mask = ent >> 16;
+        __syncthreads();                 // every wave is done with the previous entry
+        stage_store<B>(st, ent, As, Bs);
         __syncthreads();
-        if (mask & 0x3u) stage_A<B>(As, tA + (int64_t)lin_index(I0, k) * (B * B));
-        if (mask & 0xCu) stage_A<B>(As + S::kTileA, tA + (int64_t)lin_index(I0 + 1, k) * (B * B));
-        if (mask & 0x5u) stage_B<B>(Bs, tB + (int64_t)lin_index(k, J0) * (B * B));
-        if (mask & 0xAu) stage_B<B>(Bs + S::kTileB, tB + (int64_t)lin_index(k, J0 + 1) * (B * B));
-        __syncthreads();
+        const uint32_t mask = ent >> 16;
+        if (e + 1 < e1) {
+            ent = bent[e + 1];
+            stage_load<B>(st, ent, tA, tB, I0, J0);
+        }
         if ((mask >> w) & 1u) {
             if constexpr (B >= 32) {
                 const int r = lane & 31, h = lane >> 5;
