@@ -2,7 +2,7 @@
 
 A plain FP64 CPU implementation of the sparse approximate matrix multiply,
 written from the paper (quadtree depth/padding, Sec. II.A; node norms, product
-recursion and SpAMM condition, Sec. II.B; linear index, Sec. III.B).  Only the
+recursion and SpAMM condition, Sec. II.B; linear index, Sec. III.D.1).  Only the
 tests, the smoke check and the benchmark's CPU-baseline leg may import it; the
 GPU library never does, and the two share no code.
 

@@ -24,7 +24,7 @@
  *                         form, s_A * s_B >= tau^2 keeps (equality keeps).  A
  *                         node whose norm is zero is a NULL link (Sec. II.A)
  *                         and is never multiplied, at any tau.
- *   linear index       -- Sec. III.B.2, Eq. linear index: row bits on the odd
+ *   linear index       -- Sec. III.D.1, Eq. linear index: row bits on the odd
  *                         positions, column bits on the even positions.
  *
  * Leaf products accumulate in FP64, k ascending within each output tile, and
