@@ -1,0 +1,159 @@
+"""GPU path against the oracle at the full sizes of the named workloads, in the
+launch configuration bench.py times (one build + one multiply per matrix).
+
+Where the oracle can afford the whole computation (every norm tier, the kept
+task set and its count per tier) the comparison is complete and bit-exact; the
+product C is compared on seeded samples of output leaves that the oracle
+computes one by one (per-leaf recursion), including diagonal leaves where the
+entries are largest, the last (partly padded) row and column of leaves, and
+leaves with no kept product.  Bound per element: Higham's
+|C_gpu - C_oracle| <= gamma_m sum_kept |A_ik||B_kj| + m 2^-126,
+gamma_m = m u/(1 - m u), u = 2^-24, m = n_b K_ij + 1.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def leaf_block(M, I, J, leaf, n):
+    out = np.zeros((leaf, leaf), dtype=np.float64)
+    r0, c0 = I * leaf, J * leaf
+    r1, c1 = min(r0 + leaf, n), min(c0 + leaf, n)
+    if r0 < n and c0 < n:
+        out[:r1 - r0, :c1 - c0] = M[r0:r1, c0:c1]
+    return out
+
+
+def tile_bound(A, leaf, I, J, klist):
+    n = A.shape[0]
+    M = np.zeros((leaf, leaf))
+    for k in klist:
+        M += np.abs(leaf_block(A, I, k, leaf, n)) @ np.abs(leaf_block(A, k, J, leaf, n))
+    m = leaf * len(klist) + 1
+    gamma = m * U32 / (1 - m * U32)
+    return gamma * M + m * 2.0 ** -126
+
+
+def choose_tiles(N, seed, count=48):
+    rng = np.random.default_rng(seed)
+    tiles = {(int(i), int(j)) for i, j in rng.integers(0, N, size=(count, 2))}
+    tiles |= {(int(i), int(i)) for i in rng.integers(0, N, size=count // 4)}
+    tiles |= {(N - 1, N - 1), (N - 1, 0), (0, N - 1), (0, 0), (N // 2, N // 2 + 1)}
+    return sorted(tiles)
+
+
+class FullRun:
+    def __init__(self, sp, name, tau):
+        import torch
+        wl = workloads.WORKLOADS[name]
+        self.wl, self.tau, self.leaf, self.n = wl, tau, wl.leaf, wl.n
+        print(f"\n[fullsize] {name} tau={tau:g}: generating", flush=True)
+        self.A = wl.matrix()
+        dA = torch.from_numpy(self.A).cuda()
+        self.tree = sp.build_tree(dA, wl.leaf)
+        self.plan = sp.symbolic(self.tree, self.tree, tau)
+        C = torch.full_like(dA, float("nan"))
+        self.plan.numeric(C)
+        torch.cuda.synchronize()
+        del dA
+        self.C = C.cpu().numpy()
+        del C
+        self.keys = self.plan.tasks()
+        self.stats = self.plan.stats()
+        print(f"[fullsize] {name}: K={self.stats['tasks']}", flush=True)
+
+
+def check_norms(run):
+    tiers = oracle.norms(run.A, run.leaf)
+    for t, want in enumerate(tiers):
+        got = run.tree.norms(t)
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), f"tier {t}"
+
+
+def check_sampled_product(run, seed):
+    d = run.tree.depth
+    N = 1 << d
+    tiles = choose_tiles(N, seed)
+    Ct, counts, kl = oracle.spamm_tiles(run.A, run.A, run.leaf, run.tau, tiles, threads=16,
+                                        want_klists=True)
+    hi = run.keys >> np.uint64(32)
+    worst = -np.inf
+    for s, (I, J) in enumerate(tiles):
+        ks = kl[s, :counts[s]]
+        lc = np.uint64(oracle.linear_index(I, J))
+        lo, up = np.searchsorted(hi, lc, "left"), np.searchsorted(hi, lc, "right")
+        gpu_k = (run.keys[lo:up] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+        assert np.array_equal(gpu_k, ks.astype(np.int64)), (I, J)
+        got = leaf_block(run.C, I, J, run.leaf, run.n)
+        want = Ct[s]
+        assert np.all(np.isfinite(got))
+        err = np.abs(got - want)
+        worst = max(worst, float(np.max(err - tile_bound(run.A, run.leaf, I, J, ks))))
+        if counts[s] == 0:
+            assert not np.any(got)
+    assert worst <= 0.0, f"rounding bound exceeded by {worst}"
+    nrm2 = run.tree.norm2
+    err = max(float(np.abs(leaf_block(run.C, I, J, run.leaf, run.n) - Ct[s]).max())
+              for s, (I, J) in enumerate(tiles))
+    assert err <= 1e-5 * nrm2   # 1e-5 ||A||_F ||B||_F with B = A
+
+
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def cluster300(gpu):
+    return FullRun(gpu, "cluster300-n7500", 1e-8)
+
+
+def test_cluster300_norms(cluster300):
+    check_norms(cluster300)
+
+
+def test_cluster300_task_set(cluster300):
+    r = cluster300
+    ref = oracle.spamm(r.A, r.A, r.leaf, r.tau, want_C=False)
+    assert r.stats["kept"] == [int(v) for v in ref.Kt]
+    assert np.array_equal(r.keys, ref.keys)
+
+
+def test_cluster300_sampled_product(cluster300):
+    check_sampled_product(cluster300, seed=11)
+
+
+@pytest.mark.parametrize("tau", [1e-4, 1e-6, 1e-8, 1e-10])
+def test_algdecay_tau_sweep(gpu, tau):
+    r = FullRun(gpu, "algdecay-n16384", tau)
+    ref = oracle.spamm(r.A, r.A, r.leaf, tau, want_C=False)
+    assert r.stats["kept"] == [int(v) for v in ref.Kt]
+    assert np.array_equal(r.keys, ref.keys)
+    check_sampled_product(r, seed=int(-math.log10(tau)))
+    if tau == 1e-4:
+        check_norms(r)
+
+
+@pytest.fixture(scope="module")
+def cluster1310(gpu):
+    return FullRun(gpu, "cluster1310-n32750", 1e-8)
+
+
+def test_cluster1310_norms(cluster1310):
+    check_norms(cluster1310)
+
+
+def test_cluster1310_task_set(cluster1310):
+    r = cluster1310
+    ref = oracle.spamm(r.A, r.A, r.leaf, r.tau, want_C=False)
+    assert r.stats["kept"] == [int(v) for v in ref.Kt]
+    assert len(r.keys) == ref.K
+    assert np.array_equal(r.keys, ref.keys)
+
+
+def test_cluster1310_sampled_product(cluster1310):
+    check_sampled_product(cluster1310, seed=5)
