@@ -29,9 +29,17 @@ MFMA_FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "leaf_gemm_cluster1310-n32750_traffic.json")
 
 
+GEMM_SOURCES = ("paper_1203_1692_amd/csrc/gemm.hip", "paper_1203_1692_amd/csrc/common.hpp",
+                "paper_1203_1692_amd/_build.py")
+
+
 def kernel_source_digest() -> str:
-    with open(os.path.join(ROOT, "paper_1203_1692_amd", "csrc", "gemm.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """SHA-256 over the leaf GEMM's source, its layout header and build flags."""
+    h = hashlib.sha256()
+    for rel in GEMM_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(workload: str):
@@ -42,7 +50,7 @@ def measured_traffic(workload: str):
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("workload") != workload or rec.get("gemm_hip_sha256") != kernel_source_digest():
+    if rec.get("workload") != workload or rec.get("gemm_sources_sha256") != kernel_source_digest():
         return None
     return rec.get("bytes_per_launch")
 

@@ -65,8 +65,9 @@ typedef struct spamm_stats {
  *   leaf   n_b in {16, 32, 64}.  Depth d = smallest d >= 0 with n_b 2^d >= n;
  *          A is zero-padded to n_p = n_b 2^d (padding is never read from A).
  *   out    receives the handle.  The tree owns copies: the packed leaves
- *          (FP32, row-major inside each leaf, leaves in linear-index order of
- *          Eq. linear index) and the squared Frobenius norms of all tiers in
+ *          (FP32, leaves in linear-index order of Eq. linear index, each
+ *          stored twice: as is for the left operand and transposed for the
+ *          right operand) and the squared Frobenius norms of all tiers in
  *          FP64 (leaf: pairwise sum of squares over the leaf's row-major
  *          flattened index; parent: (s11 + s12) + (s21 + s22)).
  * Synchronizes `stream` once, to read the root norm; a non-finite root means
@@ -92,8 +93,11 @@ int spamm_tree_info(const spamm_tree *tree, int64_t *n, int32_t *leaf,
 int spamm_tree_norms(const spamm_tree *tree, int32_t tier, double *host, size_t len);
 
 /* Copy the zero-padded matrix held by the tree to host memory as an
- * n_p x n_p row-major FP32 array (len >= n_p^2).  Synchronizes. */
-int spamm_tree_matrix(const spamm_tree *tree, float *host, size_t len);
+ * n_p x n_p row-major FP32 array (len >= n_p^2).  The tree keeps two copies
+ * of every leaf: copy 0 is read when the tree is the left operand, copy 1
+ * (stored transposed) when it is the right operand; both must reproduce the
+ * same matrix.  Synchronizes. */
+int spamm_tree_matrix(const spamm_tree *tree, int32_t copy, float *host, size_t len);
 
 /* ---- symbolic / numeric multiply (Alg. 1: collect products, then multiply) -- */
 

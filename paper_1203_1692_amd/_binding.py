@@ -83,7 +83,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "spamm_tree_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
                             ctypes.POINTER(dbl)],
         "spamm_tree_norms": [vp, i32, vp, sz],
-        "spamm_tree_matrix": [vp, vp, sz],
+        "spamm_tree_matrix": [vp, i32, vp, sz],
         "spamm_symbolic": [vp, vp, dbl, vp, pp],
         "spamm_numeric": [vp, vp, vp],
         "spamm_plan_tasks": [vp, vp, sz, ctypes.POINTER(sz)],
@@ -160,9 +160,12 @@ class Tree:
                "spamm_tree_norms")
         return out
 
-    def matrix(self) -> np.ndarray:
+    def matrix(self, copy: int = 0) -> np.ndarray:
+        """The padded matrix as held by the tree: copy 0 = left-operand
+        leaves, copy 1 = right-operand (transposed) leaves."""
         out = np.empty((self.np, self.np), dtype=np.float32)
-        _check(load().spamm_tree_matrix(self.handle, out.ctypes.data, out.size), "spamm_tree_matrix")
+        _check(load().spamm_tree_matrix(self.handle, copy, out.ctypes.data, out.size),
+               "spamm_tree_matrix")
         return out
 
     def free(self):

@@ -25,6 +25,10 @@ COMMON_FLAGS = [
     "-fno-gpu-flush-denormals-to-zero",
     # no packed-FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: the leaf GEMM's loop-carried
+    # accumulators would otherwise be copied between AGPRs and VGPRs on
+    # every pass through its conditional MFMA block
+    "-mllvm", "--amdgpu-mfma-vgpr-form",
     "-Wall",
     "-I", INCLUDE,
     "-I", CSRC,

@@ -16,7 +16,7 @@
 
 namespace spamm {
 hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *tiles,
-                        double *norms, hipStream_t s);
+                        float *tilesT, double *norms, hipStream_t s);
 hipError_t launch_cull(spamm_plan *p, hipStream_t s);
 hipError_t launch_gemm(const spamm_plan *p, float *C, hipStream_t s);
 size_t scan_partials_len(uint32_t m);
@@ -143,9 +143,11 @@ int spamm_build_tree(const float *A, int64_t n, int32_t leaf, void *stream, spam
     t->depth = d;
     hipError_t e = hipMallocAsync((void **)&t->tiles, tile_bytes, s);
     if (e == hipSuccess)
+        e = hipMallocAsync((void **)&t->tilesT, tile_bytes, s);
+    if (e == hipSuccess)
         e = hipMallocAsync((void **)&t->norms, norm_bytes, s);
     if (e == hipSuccess)
-        e = launch_build(A, n, leaf, d, t->tiles, t->norms, s);
+        e = launch_build(A, n, leaf, d, t->tiles, t->tilesT, t->norms, s);
     double root = 0.0;
     if (e == hipSuccess)
         e = hipMemcpyAsync(&root, t->norms, sizeof(double), hipMemcpyDeviceToHost, s);
@@ -174,10 +176,13 @@ int spamm_tree_free(spamm_tree *t)
     if (dev0 != t->device)
         hipSetDevice(t->device);
     hipError_t e = hipSuccess;
-    if (t->tiles)
-        e = hipFreeAsync(t->tiles, t->stream);
-    if (t->norms && e == hipSuccess)
-        e = hipFreeAsync(t->norms, t->stream);
+    for (void *ptr : {(void *)t->tiles, (void *)t->tilesT, (void *)t->norms}) {
+        if (ptr == nullptr)
+            continue;
+        hipError_t f = hipFreeAsync(ptr, t->stream);
+        if (e == hipSuccess)
+            e = f;
+    }
     if (dev0 >= 0 && dev0 != t->device)
         hipSetDevice(dev0);
     delete t;
@@ -214,23 +219,31 @@ int spamm_tree_norms(const spamm_tree *t, int32_t tier, double *host, size_t len
     return SPAMM_OK;
 }
 
-int spamm_tree_matrix(const spamm_tree *t, float *host, size_t len)
+int spamm_tree_matrix(const spamm_tree *t, int32_t copy, float *host, size_t len)
 {
     if (t == nullptr || host == nullptr)
         return fail(SPAMM_E_INVAL, "NULL argument");
+    if (copy != 0 && copy != 1)
+        return fail(SPAMM_E_INVAL, "copy = %d not in {0, 1}", copy);
     const int64_t np = t->np, b = t->leaf, N = int64_t(1) << t->depth;
     if (len < (size_t)(np * np))
         return fail(SPAMM_E_RANGE, "host buffer holds %zu < %lld values", len, (long long)(np * np));
     std::vector<float> tiles((size_t)(np * np));
-    HIP_TRY(hipMemcpyAsync(tiles.data(), t->tiles, sizeof(float) * tiles.size(),
-                           hipMemcpyDeviceToHost, t->stream),
+    HIP_TRY(hipMemcpyAsync(tiles.data(), copy == 0 ? t->tiles : t->tilesT,
+                           sizeof(float) * tiles.size(), hipMemcpyDeviceToHost, t->stream),
             "hipMemcpyAsync");
     HIP_TRY(hipStreamSynchronize(t->stream), "hipStreamSynchronize");
     for (int64_t l = 0; l < N * N; ++l) {
         const int64_t I = lin_row((uint32_t)l), J = lin_col((uint32_t)l);
         const float *src = tiles.data() + l * b * b;
-        for (int64_t r = 0; r < b; ++r)
-            memcpy(host + (I * b + r) * np + J * b, src + r * b, sizeof(float) * (size_t)b);
+        for (int r = 0; r < (int)b; ++r)
+            for (int c = 0; c < (int)b; ++c) {
+                const float v = src[leaf_index((int)b, r, c)];
+                if (copy == 0)
+                    host[(I * b + r) * np + J * b + c] = v;
+                else
+                    host[(I * b + c) * np + J * b + r] = v;
+            }
     }
     return SPAMM_OK;
 }

@@ -44,6 +44,42 @@ __host__ __device__ inline uint32_t lin_col(uint32_t l) { return compact_bits(l)
 // tier t holds 4^t values in linear-index order.
 __host__ __device__ inline int64_t tier_offset(int t) { return ((int64_t(1) << (2 * t)) - 1) / 3; }
 
+// Storage of one packed n_b x n_b leaf, designed for the leaf GEMM: the
+// columns (the k of a left operand) are cut into panels of kKS = min(n_b, 32)
+// columns stored one after the other, each panel row-major with rows of kKS
+// floats.  Inside a panel row the 16-byte granules (4 floats) are permuted by
+// an XOR with a function of the row, so that the 16 rows read at one logical
+// column by a ds_read_b128 hit 16 distinct groups of LDS banks.  A panel is
+// the unit the GEMM copies to LDS (verbatim, with direct-to-LDS loads).
+// Element (r, c) of the leaf lives at index(r, c).
+template <int B>
+struct LeafLayout {
+    static constexpr int kKS = B < 32 ? B : 32;                  // panel width
+    static constexpr int kPanels = B / kKS;
+    static constexpr int kPanel = B * kKS;                       // floats per panel
+    static constexpr int kGran = kKS / 4;                        // granules per panel row
+    // 16 consecutive rows cover 16 / kGran bank offsets; the XOR separates
+    // the rows that share one
+    static constexpr int kShift = kGran == 8 ? 1 : (kGran == 4 ? 2 : 3);
+    __host__ __device__ static constexpr int pindex(int r, int cc)   // inside a panel
+    {
+        return r * kKS + 4 * ((cc >> 2) ^ ((r >> kShift) & (kGran - 1))) + (cc & 3);
+    }
+    __host__ __device__ static constexpr int index(int r, int c)
+    {
+        return (c / kKS) * kPanel + pindex(r, c % kKS);
+    }
+};
+
+__host__ __device__ inline int leaf_index(int B, int r, int c)
+{
+    switch (B) {
+    case 16: return LeafLayout<16>::index(r, c);
+    case 32: return LeafLayout<32>::index(r, c);
+    default: return LeafLayout<64>::index(r, c);
+    }
+}
+
 // The SpAMM keep decision on stored squared norms (both FP64):
 // zero norm -> NULL link, never kept; otherwise kept unless s_A s_B < tau^2.
 __device__ inline bool keep_pair(double sa, double sb, double T2)
@@ -63,7 +99,8 @@ struct spamm_tree {
     hipStream_t stream;     // stream the tree was built on (frees are ordered there)
     int64_t n, np;
     int32_t leaf, depth;
-    float *tiles;           // N^2 leaves, linear-index order, row-major inside
+    float *tiles;           // N^2 leaves (left-operand copy), linear-index order, LeafLayout
+    float *tilesT;          // the same leaves transposed (right-operand copy), LeafLayout
     double *norms;          // tiers 0..d, tier_offset layout
     double root;            // ||A||_F^2
 };

@@ -1,32 +1,45 @@
 // Numeric multiply: C_ij = sum over kept k (ascending) of A_ik B_kj
 // (Eq. product, Alg. 1 steps 7-9) on FP32 MFMA with FP32 accumulation.
 //
-// A workgroup of 4 waves owns one block of 2 x 2 output leaves (the children
-// of one tier-(d-1) tile); wave q = 2a + b owns leaf (2I+a, 2J+b) and is the
-// only writer of it, so no atomics touch C.  The block walks the union of its
-// leaves' kept k (entries k | mask << 16 from the cull): it stages the needed
-// A_(2I+a, k) and B_(k, 2J+b) leaves in LDS once and every wave whose mask
-// bit is set runs its leaf product from there.  Every output leaf is written
-// once, with zeros where nothing was kept, cropped to n.
+// Ownership.  A workgroup of 4 waves owns one block of 2 x 2 output leaves
+// (the children of one tier-(d-1) tile); wave q = 2a + b owns leaf
+// (2I+a, 2J+b) and is its only writer, so no atomics touch C.  The block walks
+// the union of its leaves' kept k (entries k | mask << 16 from the cull); for
+// each entry the needed A_(2I+a, k) (left-operand copy) and B_(k, 2J+b)
+// (right-operand copy, stored transposed) go to LDS once and every wave whose
+// mask bit is set multiplies from there.  Every output leaf is written once,
+// with zeros where nothing was kept, cropped to n.
 //
-// MFMA layouts (v_mfma_f32_32x32x2_f32): A operand lane l = A[l%32][l/32],
-// B operand lane l = B[l/32][l%32]; result register v of lane l is
-// D[8(v/4) + 4(l/32) + v%4][l%32].  16x16x4: A[l%16][l/16], B[l/16][l%16],
-// D[4(l/16) + v][l%16].  The A leaves sit in LDS with a row pitch of n_b + 1
-// floats so that the 32 rows read by one MFMA operand fall in distinct banks.
+// Pipeline.  The unit of staging is one k-panel of the four operand leaves
+// (LeafLayout: n_b x 32 floats each, 32 KB for all four at n_b = 64).  Wave w
+// copies operand leaf w's panel with direct-to-LDS loads (global_load_lds,
+// 1 KB per instruction, no registers), into one of two LDS buffers: the copy
+// of stage t+1 is in flight while stage t is multiplied.  One barrier per
+// stage.  Two workgroups per CU (64 KB LDS each at n_b = 64).
+//
+// Operand feed.  In a panel, lane l reads 4 consecutive k of its row with one
+// conflict-free ds_read_b128.  v_mfma_f32_32x32x2_f32: A operand of lane l is
+// A[l%32][k0 + l/32], B operand B[k0 + l/32][l%32]; MFMA step s of a 32-wide
+// panel pairs the inner indices {s, 16 + s} (lane half h = l/32 supplies
+// k = 16 h + s), so one 16-byte read feeds 4 steps.  16x16x4 (n_b = 16,
+// one 16-wide panel): lane l supplies k = 4 (l/16) + s, s < 4.  The sum over k
+// inside a leaf is the same; only the FP32 summation order inside it differs
+// from a plain loop.  Result register v of lane l: D[8(v/4) + 4(l/32) + v%4]
+// [l%32] (32x32), D[4(l/16) + v][l%16] (16x16).
 #include "common.hpp"
 
 namespace spamm {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void global_void_t;
 
 template <int B>
 struct GemmShape {
-    static constexpr int kPitchA = B + 1;
-    static constexpr int kTileA = B * kPitchA;
-    static constexpr int kTileB = B * B;
-    static constexpr size_t kLds = sizeof(float) * 2 * (kTileA + kTileB);
+    using L = LeafLayout<B>;
+    static constexpr int kStage = 4 * L::kPanel;                     // floats per stage
+    static constexpr size_t kLds = sizeof(float) * 2 * kStage;       // double buffered
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
@@ -38,94 +51,90 @@ __device__ inline uint32_t xcd_block(uint32_t bid, uint32_t nblocks)
     return (bid % 8u) * (nblocks / 8u) + bid / 8u;
 }
 
-// One entry's operand leaves in registers: A_(2I, k), A_(2I+1, k),
-// B_(k, 2J), B_(k, 2J+1); thread t holds float4 number t + 256 i of each leaf.
+// Wave w copies panel p of operand leaf w (0: A_2I, 1: A_2I+1, 2: B_2J,
+// 3: B_2J+1) of entry `ent` into LDS at dst, if the entry's mask needs it.
 template <int B>
-struct Stage {
-    static constexpr int kVec = B * B / 4;                   // float4 per leaf
-    static constexpr int kPer = kVec >= 256 ? kVec / 256 : 1;
-    float4 v[4][kPer];
-};
-
-template <int B>
-__device__ inline void stage_load(Stage<B> &st, uint32_t ent, const float *__restrict__ tA,
-                                  const float *__restrict__ tB, uint32_t I0, uint32_t J0)
+__device__ inline void stage_issue(uint32_t ent, int p, const float *__restrict__ tA,
+                                   const float *__restrict__ tBT, uint32_t I0, uint32_t J0,
+                                   float *dst, int w, int lane)
 {
-    using S = Stage<B>;
+    using L = LeafLayout<B>;
+    // leaves that use operand w: A_2I -> q 0,1; A_2I+1 -> q 2,3; B_2J -> q 0,2;
+    // B_2J+1 -> q 1,3
+    const uint32_t users = w < 2 ? (0x3u << (2 * w)) : (0x5u << (w - 2));
     const uint32_t k = ent & 0xFFFFu, mask = ent >> 16;
-    const bool need[4] = {(mask & 0x3u) != 0, (mask & 0xCu) != 0, (mask & 0x5u) != 0,
-                          (mask & 0xAu) != 0};
-    const float4 *src[4] = {
-        reinterpret_cast<const float4 *>(tA + (int64_t)lin_index(I0, k) * (B * B)),
-        reinterpret_cast<const float4 *>(tA + (int64_t)lin_index(I0 + 1, k) * (B * B)),
-        reinterpret_cast<const float4 *>(tB + (int64_t)lin_index(k, J0) * (B * B)),
-        reinterpret_cast<const float4 *>(tB + (int64_t)lin_index(k, J0 + 1) * (B * B))};
+    if ((mask & users) == 0)
+        return;
+    const float *leaf = w < 2 ? tA + (int64_t)lin_index(I0 + w, k) * (B * B)
+                              : tBT + (int64_t)lin_index(k, J0 + (w - 2)) * (B * B);
+    const float *src = leaf + p * L::kPanel + 4 * lane;
+    float *d = dst + w * L::kPanel;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        if (!need[t])
-            continue;
+    for (int i = 0; i < L::kPanel / 256; ++i)
+        __builtin_amdgcn_global_load_lds((global_void_t *)(src + 256 * i), (lds_void_t *)(d + 256 * i),
+                                         16, 0, 0);
+}
+
+// acc += A_panel * B_panel for a 64- or 32-row leaf (MB = B/32 blocks of
+// 32x32 per dimension).  Ap: rows i, 32 columns k; Bp: rows j, 32 columns k.
+template <int B>
+__device__ inline void panel_mfma32(const float *__restrict__ Ap, const float *__restrict__ Bp,
+                                    floatx16 (&acc)[B / 32][B / 32], int lane)
+{
+    using L = LeafLayout<B>;
+    constexpr int MB = B / 32;
+    constexpr int NG = L::kKS / 8;     // groups of 4 MFMA steps per lane half
+    const int r = lane & 31, h = lane >> 5;
+    floatx4 av[2][MB], bv[2][MB];
+    auto load = [&](int buf, int g) {
+        const int c = (L::kKS / 2) * h + 4 * g;
 #pragma unroll
-        for (int i = 0; i < S::kPer; ++i) {
-            const int f = threadIdx.x + 256 * i;
-            if (S::kVec >= 256 || f < S::kVec)
-                st.v[t][i] = src[t][f];
-        }
+        for (int i = 0; i < MB; ++i)
+            av[buf][i] = *reinterpret_cast<const floatx4 *>(Ap + L::pindex(i * 32 + r, c));
+#pragma unroll
+        for (int j = 0; j < MB; ++j)
+            bv[buf][j] = *reinterpret_cast<const floatx4 *>(Bp + L::pindex(j * 32 + r, c));
+    };
+    load(0, 0);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        if (g + 1 < NG)
+            load((g + 1) & 1, g + 1);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+#pragma unroll
+                for (int j = 0; j < MB; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[g & 1][i][s], bv[g & 1][j][s],
+                                                                     acc[i][j], 0, 0, 0);
     }
 }
 
-template <int B>
-__device__ inline void stage_store(const Stage<B> &st, uint32_t ent, float *__restrict__ As,
-                                   float *__restrict__ Bs)
+__device__ inline void panel_mfma16(const float *__restrict__ Ap, const float *__restrict__ Bp,
+                                    floatx4 &acc, int lane)
 {
-    using S = Stage<B>;
-    using G = GemmShape<B>;
-    const uint32_t mask = ent >> 16;
-    const bool need[4] = {(mask & 0x3u) != 0, (mask & 0xCu) != 0, (mask & 0x5u) != 0,
-                          (mask & 0xAu) != 0};
+    using L = LeafLayout<16>;
+    const int r = lane & 15, h = lane >> 4;
+    const floatx4 av = *reinterpret_cast<const floatx4 *>(Ap + L::pindex(r, 4 * h));
+    const floatx4 bv = *reinterpret_cast<const floatx4 *>(Bp + L::pindex(r, 4 * h));
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        if (!need[t])
-            continue;
-        float *dst = As + t * G::kTileA;
-#pragma unroll
-        for (int i = 0; i < S::kPer; ++i) {
-            const int f = threadIdx.x + 256 * i;
-            if (S::kVec >= 256 || f < S::kVec) {
-                const int r = (4 * f) / B, c = (4 * f) % B;
-                float *o = dst + r * G::kPitchA + c;
-                o[0] = st.v[t][i].x;
-                o[1] = st.v[t][i].y;
-                o[2] = st.v[t][i].z;
-                o[3] = st.v[t][i].w;
-            }
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        if (!need[2 + t])
-            continue;
-        float4 *dst = reinterpret_cast<float4 *>(Bs + t * G::kTileB);
-#pragma unroll
-        for (int i = 0; i < S::kPer; ++i) {
-            const int f = threadIdx.x + 256 * i;
-            if (S::kVec >= 256 || f < S::kVec)
-                dst[f] = st.v[2 + t][i];
-        }
-    }
+    for (int s = 0; s < 4; ++s)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[s], acc, 0, 0, 0);
 }
 
 template <int B>
 __global__ __launch_bounds__(256) void leaf_gemm(const float *__restrict__ tA,
-                                                 const float *__restrict__ tB,
+                                                 const float *__restrict__ tBT,
                                                  const uint32_t *__restrict__ browptr,
                                                  const uint32_t *__restrict__ bent,
                                                  uint32_t nblocks, int single, int64_t n,
                                                  float *__restrict__ C)
 {
+    using L = LeafLayout<B>;
     using S = GemmShape<B>;
-    extern __shared__ float smem[];
-    float *As = smem;                    // 2 leaves, pitch B+1
-    float *Bs = smem + 2 * S::kTileA;    // 2 leaves, pitch B
+    constexpr int NP = L::kPanels;
+    extern __shared__ float smem[];       // 2 stages x {A_2I, A_2I+1, B_2J, B_2J+1} panels
     const uint32_t blk = xcd_block(blockIdx.x, nblocks);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int qa = w >> 1, qb = w & 1;
@@ -134,8 +143,6 @@ __global__ __launch_bounds__(256) void leaf_gemm(const float *__restrict__ tA,
         I0 = 2 * lin_row(blk);
         J0 = 2 * lin_col(blk);
     }
-    const float *Am = As + qa * S::kTileA;
-    const float *Bm = Bs + qb * S::kTileB;
 
     constexpr int MB = B >= 32 ? B / 32 : 1;
     floatx16 acc[MB][MB];
@@ -150,52 +157,27 @@ __global__ __launch_bounds__(256) void leaf_gemm(const float *__restrict__ tA,
         acc16 = floatx4{0};
     }
 
-    // Register double buffering: the leaves of entry e+1 are in flight from
-    // memory while entry e is multiplied out of LDS.
     const uint32_t e0 = browptr[blk], e1 = browptr[blk + 1];
-    Stage<B> st;
-    uint32_t ent = 0;
-    if (e0 < e1) {
-        ent = bent[e0];
-        stage_load<B>(st, ent, tA, tB, I0, J0);
-    }
-    for (uint32_t e = e0; e < e1; ++e) {
-        __syncthreads();                 // every wave is done with the previous entry
-        stage_store<B>(st, ent, As, Bs);
+    const uint32_t T = (e1 - e0) * NP;                  // stages of this block
+    if (T > 0)
+        stage_issue<B>(bent[e0], 0, tA, tBT, I0, J0, smem, w, lane);
+    for (uint32_t t = 0; t < T; ++t) {
+        const uint32_t ent = bent[e0 + t / NP];
+        // this wave's copies of stage t have landed; after the barrier every
+        // wave's have, and every wave is done reading the other buffer
+        __builtin_amdgcn_s_waitcnt(0x0F70);             // vmcnt(0)
         __syncthreads();
-        const uint32_t mask = ent >> 16;
-        if (e + 1 < e1) {
-            ent = bent[e + 1];
-            stage_load<B>(st, ent, tA, tB, I0, J0);
-        }
-        if ((mask >> w) & 1u) {
-            if constexpr (B >= 32) {
-                const int r = lane & 31, h = lane >> 5;
-#pragma unroll 4
-                for (int kk = 0; kk < B; kk += 2) {
-                    float av[MB], bv[MB];
-#pragma unroll
-                    for (int i = 0; i < MB; ++i)
-                        av[i] = Am[(i * 32 + r) * S::kPitchA + kk + h];
-#pragma unroll
-                    for (int j = 0; j < MB; ++j)
-                        bv[j] = Bm[(kk + h) * B + j * 32 + r];
-#pragma unroll
-                    for (int i = 0; i < MB; ++i)
-#pragma unroll
-                        for (int j = 0; j < MB; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j],
-                                                                             0, 0, 0);
-                }
-            } else {
-                const int r = lane & 15, h = lane >> 4;
-#pragma unroll
-                for (int kk = 0; kk < B; kk += 4) {
-                    const float av = Am[r * S::kPitchA + kk + h];
-                    const float bv = Bm[(kk + h) * B + r];
-                    acc16 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc16, 0, 0, 0);
-                }
-            }
+        if (t + 1 < T)
+            stage_issue<B>(bent[e0 + (t + 1) / NP], (int)((t + 1) % NP), tA, tBT, I0, J0,
+                           smem + ((t + 1) & 1) * S::kStage, w, lane);
+        if ((ent >> (16 + w)) & 1u) {
+            const float *buf = smem + (t & 1) * S::kStage;
+            const float *Ap = buf + qa * L::kPanel;
+            const float *Bp = buf + (2 + qb) * L::kPanel;
+            if constexpr (B >= 32)
+                panel_mfma32<B>(Ap, Bp, acc, lane);
+            else
+                panel_mfma16(Ap, Bp, acc16, lane);
         }
     }
 
@@ -238,7 +220,7 @@ static hipError_t launch_gemm_b(const spamm_plan *p, float *C, hipStream_t s)
         attr_set = true;
     }
     hipLaunchKernelGGL(leaf_gemm<B>, dim3((uint32_t)p->nblocks), dim3(256), S::kLds, s,
-                       p->A->tiles, p->B->tiles, p->browptr, p->bent, (uint32_t)p->nblocks,
+                       p->A->tiles, p->B->tilesT, p->browptr, p->bent, (uint32_t)p->nblocks,
                        p->depth == 0 ? 1 : 0, p->n, C);
     return hipGetLastError();
 }

@@ -42,21 +42,30 @@ __device__ inline float4 load_row4(const float *__restrict__ A, int64_t n, int64
 
 // Block of 4 waves = the 4 children of one tier-(d-1) node (linear indices
 // 4p .. 4p+3); the block also writes that parent's norm when `parent` != null.
+// Each leaf is stored twice in LeafLayout: as is (left-operand copy) and
+// transposed through LDS (right-operand copy), so that the GEMM reads both of
+// its operands along k with contiguous 16-byte loads.
 template <int B, int VEC>
 __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ A, int64_t n,
                                                       float *__restrict__ tiles,
+                                                      float *__restrict__ tilesT,
                                                       double *__restrict__ leaf_norm,
                                                       double *__restrict__ parent,
                                                       uint32_t ntiles)
 {
+    using L = LeafLayout<B>;
     constexpr int M = (B * B) / 256;   // float4 loads per lane
+    constexpr int P = B + 1;           // LDS pitch of the transpose buffer
     static_assert(M >= 1 && (M & (M - 1)) == 0, "leaf must be 16, 32 or 64");
+    extern __shared__ float tr_smem[];
     __shared__ double part[4];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const uint32_t l = blockIdx.x * 4u + (uint32_t)w;
+    const bool valid = l < ntiles;
+    float *tr = tr_smem + w * (B * P);
     double s = 0.0;
-    if (l < ntiles) {
+    if (valid) {
         const int64_t I = lin_row(l), J = lin_col(l);
         float4 v[M];
 #pragma unroll
@@ -69,12 +78,18 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int e = 256 * m + 4 * lane;
-            *reinterpret_cast<float4 *>(dst + e) = v[m];
+            const int r = e / B, c = e % B;
+            *reinterpret_cast<float4 *>(dst + L::index(r, c)) = v[m];
+            float *o = tr + r * P + c;
+            o[0] = v[m].x;
+            o[1] = v[m].y;
+            o[2] = v[m].z;
+            o[3] = v[m].w;
             const double x0 = v[m].x, x1 = v[m].y, x2 = v[m].z, x3 = v[m].w;
             double t = (x0 * x0 + x1 * x1) + (x2 * x2 + x3 * x3);
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1)
-                t += __shfl_xor(t, o);
+            for (int o2 = 1; o2 < 64; o2 <<= 1)
+                t += __shfl_xor(t, o2);
             sm[m] = t;
         }
 #pragma unroll
@@ -85,6 +100,18 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
         s = sm[0];
         if (lane == 0)
             leaf_norm[l] = s;
+    }
+    __syncthreads();
+    if (valid) {
+        float *dstT = tilesT + (int64_t)l * (B * B);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int e = 256 * m + 4 * lane;
+            const int rt = e / B, ct = e % B;   // element (rt, ct..ct+3) of the transpose
+            const float4 t = make_float4(tr[(ct + 0) * P + rt], tr[(ct + 1) * P + rt],
+                                         tr[(ct + 2) * P + rt], tr[(ct + 3) * P + rt]);
+            *reinterpret_cast<float4 *>(dstT + L::index(rt, ct)) = t;
+        }
     }
     if (parent != nullptr) {
         if (lane == 0)
@@ -108,22 +135,37 @@ __global__ __launch_bounds__(1024) void norm_pyramid(double *__restrict__ norms,
     }
 }
 
-template <int B>
-static hipError_t launch_leaf(const float *A, int64_t n, int vec, float *tiles, double *leaf,
-                              double *parent, uint32_t ntiles, hipStream_t s)
+template <int B, int VEC>
+static hipError_t launch_leaf_v(const float *A, int64_t n, float *tiles, float *tilesT, double *leaf,
+                                double *parent, uint32_t ntiles, hipStream_t s)
 {
-    const dim3 grid((ntiles + 3) / 4), block(256);
-    if (vec == 4)
-        hipLaunchKernelGGL((leaf_norm_pack<B, 4>), grid, block, 0, s, A, n, tiles, leaf, parent, ntiles);
-    else if (vec == 2)
-        hipLaunchKernelGGL((leaf_norm_pack<B, 2>), grid, block, 0, s, A, n, tiles, leaf, parent, ntiles);
-    else
-        hipLaunchKernelGGL((leaf_norm_pack<B, 1>), grid, block, 0, s, A, n, tiles, leaf, parent, ntiles);
+    constexpr size_t lds = sizeof(float) * 4 * B * (B + 1);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)leaf_norm_pack<B, VEC>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((leaf_norm_pack<B, VEC>), dim3((ntiles + 3) / 4), dim3(256), lds, s, A, n,
+                       tiles, tilesT, leaf, parent, ntiles);
     return hipGetLastError();
 }
 
+template <int B>
+static hipError_t launch_leaf(const float *A, int64_t n, int vec, float *tiles, float *tilesT,
+                              double *leaf, double *parent, uint32_t ntiles, hipStream_t s)
+{
+    if (vec == 4)
+        return launch_leaf_v<B, 4>(A, n, tiles, tilesT, leaf, parent, ntiles, s);
+    if (vec == 2)
+        return launch_leaf_v<B, 2>(A, n, tiles, tilesT, leaf, parent, ntiles, s);
+    return launch_leaf_v<B, 1>(A, n, tiles, tilesT, leaf, parent, ntiles, s);
+}
+
 hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *tiles,
-                        double *norms, hipStream_t s)
+                        float *tilesT, double *norms, hipStream_t s)
 {
     const uintptr_t addr = reinterpret_cast<uintptr_t>(A);
     const int vec = (n % 4 == 0 && addr % 16 == 0) ? 4 : (n % 2 == 0 && addr % 8 == 0) ? 2 : 1;
@@ -132,9 +174,9 @@ hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *t
     double *parent = depth >= 1 ? norms + tier_offset(depth - 1) : nullptr;
     hipError_t e;
     switch (leaf) {
-    case 16: e = launch_leaf<16>(A, n, vec, tiles, leafn, parent, ntiles, s); break;
-    case 32: e = launch_leaf<32>(A, n, vec, tiles, leafn, parent, ntiles, s); break;
-    case 64: e = launch_leaf<64>(A, n, vec, tiles, leafn, parent, ntiles, s); break;
+    case 16: e = launch_leaf<16>(A, n, vec, tiles, tilesT, leafn, parent, ntiles, s); break;
+    case 32: e = launch_leaf<32>(A, n, vec, tiles, tilesT, leafn, parent, ntiles, s); break;
+    case 64: e = launch_leaf<64>(A, n, vec, tiles, tilesT, leafn, parent, ntiles, s); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess || depth < 2)

@@ -149,7 +149,8 @@ def test_norms_bit_exact(runs, name):
 def test_packed_leaves_are_padded_copy(runs, name):
     A, B, leaf, tau, ref, g = runs(name)
     P, _ = padded(A, leaf)
-    assert np.array_equal(g.tA.matrix().view(np.uint32), P.view(np.uint32))
+    assert np.array_equal(g.tA.matrix(0).view(np.uint32), P.view(np.uint32))
+    assert np.array_equal(g.tA.matrix(1).view(np.uint32), P.view(np.uint32))
 
 
 @pytest.mark.parametrize("name", CASES)
