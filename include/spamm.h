@@ -40,6 +40,13 @@ extern "C" {
 #define SPAMM_E_RANGE      -5   /* host buffer too small / size over a limit  */
 #define SPAMM_E_MISMATCH   -6   /* operands of different n or leaf size       */
 
+/* ---- precision of the leaf products (split precision) -------------------- */
+#define SPAMM_PREC_FP32        0   /* every kept product in FP32 (MFMA, FP32 accumulation) */
+#define SPAMM_PREC_SPLIT_BF16  1   /* LOW products on BF16 operands, HIGH ones in FP32      */
+
+/* Tree build flags. */
+#define SPAMM_TREE_BF16        1u  /* also keep BF16 copies of the leaves (split precision) */
+
 typedef struct spamm_tree spamm_tree;   /* one operand: packed leaves + norms  */
 typedef struct spamm_plan spamm_plan;   /* one product's kept task list        */
 
@@ -49,7 +56,9 @@ typedef struct spamm_stats {
     int32_t leaf;             /* n_b                                            */
     int64_t kept[32];         /* kept node triples per tier t = 0..d            */
     int64_t tasks;            /* K = kept[d]: leaf products performed           */
-    int64_t block_entries;    /* (k, mask) entries scheduled for the leaf GEMM  */
+    int64_t tasks_low;        /* of which LOW (BF16 operands; split precision)   */
+    int64_t block_entries;    /* (k, mask) entries scheduled, HIGH list         */
+    int64_t block_entries_low;/* (k, mask) entries scheduled, LOW list          */
     double  flops;            /* 2 n_b^3 K                                      */
     double  symbolic_ms;      /* cull time (events), or -1 when not timed        */
     double  numeric_ms;       /* leaf-GEMM time (events), or -1 when not timed   */
@@ -77,6 +86,29 @@ typedef struct spamm_stats {
  */
 int spamm_build_tree(const float *A, int64_t n, int32_t leaf, void *stream,
                      spamm_tree **out);
+
+/*
+ * Options of a product.
+ *   tau        SpAMM tolerance (absolute), as for spamm_symbolic.
+ *   precision  SPAMM_PREC_FP32 or SPAMM_PREC_SPLIT_BF16.
+ *   low_tol    split only: a kept product A_ik B_kj is LOW iff
+ *              fl64(s_A s_B) < fl64(low_tol^2) on the stored squared norms,
+ *              i.e. ||A_ik||_F ||B_kj||_F < low_tol; LOW products use BF16
+ *              operands (each FP32 entry rounded to nearest even) with FP32
+ *              accumulation, HIGH products stay FP32.  0 = nothing is LOW.
+ *              A relative threshold theta ||A||_F ||B||_F is low_tol =
+ *              theta * sqrt(norm2_A) * sqrt(norm2_B) (spamm_tree_info).
+ */
+typedef struct spamm_opts {
+    double  tau;
+    int32_t precision;
+    double  low_tol;
+} spamm_opts;
+
+/* As spamm_build_tree, with flags (SPAMM_TREE_BF16: also store BF16 copies of
+ * every leaf, needed by split-precision products; leaf must be 32 or 64). */
+int spamm_build_tree_ex(const float *A, int64_t n, int32_t leaf, uint32_t flags, void *stream,
+                        spamm_tree **out);
 
 /* Release a tree (stream-ordered on the stream it was built on; work on other
  * streams that uses the tree must be complete).  NULL is a no-op. */
@@ -115,6 +147,16 @@ int spamm_symbolic(const spamm_tree *A, const spamm_tree *B, double tau,
                    void *stream, spamm_plan **out);
 
 /*
+ * Symbolic multiply with options (split precision).  With
+ * SPAMM_PREC_SPLIT_BF16 each kept leaf product is also classed LOW or HIGH
+ * (see spamm_opts); both trees must have been built with SPAMM_TREE_BF16.
+ * Errors as spamm_symbolic, plus SPAMM_E_INVAL for an unknown precision, a
+ * bad low_tol (negative, NaN/Inf, 0 < low_tol < 1e-150) or missing BF16 copies.
+ */
+int spamm_symbolic_ex(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
+                      void *stream, spamm_plan **out);
+
+/*
  * Numeric multiply: C = sum over kept k (ascending) of A_ik B_kj for every
  * output leaf, FP32 MFMA with FP32 accumulation (Eq. product, Alg. 1 steps
  * 7-9).  C: device pointer, n x n FP32 row-major, fully overwritten (zeros
@@ -127,8 +169,9 @@ int spamm_numeric(const spamm_plan *plan, float *C, void *stream);
 /*
  * Copy the kept leaf triples to host memory as sorted uint64 keys
  * (linear_index(i, j) << 32) | k, linear_index from Eq. linear index (row
- * bits on odd positions).  *count receives K.  cap < K -> SPAMM_E_RANGE
- * (nothing copied).  Synchronizes the plan's stream.
+ * bits on odd positions); with split precision bit 63 is set on LOW products.
+ * *count receives K.  cap < K -> SPAMM_E_RANGE (nothing copied).
+ * Synchronizes the plan's stream.
  */
 int spamm_plan_tasks(const spamm_plan *plan, uint64_t *host, size_t cap, size_t *count);
 
@@ -149,6 +192,11 @@ int spamm_multiply(const spamm_tree *A, const spamm_tree *B, double tau, float *
  * and the leaf GEMM with HIP events on `stream`, synchronizes, and fills it. */
 int spamm_multiply_ex(const spamm_tree *A, const spamm_tree *B, double tau, float *C,
                       void *stream, spamm_stats *stats);
+
+/* Product with options: symbolic + numeric on `stream` with a temporary plan;
+ * `stats` as for spamm_multiply_ex (NULL: no timing, no synchronization). */
+int spamm_multiply_opts(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
+                        float *C, void *stream, spamm_stats *stats);
 
 /* ---- errors --------------------------------------------------------------- */
 const char *spamm_strerror(int code);

@@ -56,6 +56,13 @@ def _load():
         lib.oracle_spamm_tiles.argtypes = [vp, vp, i64, i32, dbl, vp, i64, vp, vp, vp,
                                            ctypes.c_int]
         lib.oracle_spamm_tiles.restype = ctypes.c_int
+        lib.oracle_spamm_split.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, vp, i64, vp, vp, vp]
+        lib.oracle_spamm_split.restype = ctypes.c_int
+        lib.oracle_spamm_tiles_split.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, i64, vp, vp, vp,
+                                                 ctypes.c_int]
+        lib.oracle_spamm_tiles_split.restype = ctypes.c_int
+        lib.oracle_bf16.argtypes = [ctypes.c_float]
+        lib.oracle_bf16.restype = dbl
         _lib = lib
     return _lib
 
@@ -99,11 +106,20 @@ def norms(A: np.ndarray, b: int):
     return tiers
 
 
+LOW_BIT = np.uint64(1) << np.uint64(63)
+
+
+def bf16(x: float) -> float:
+    """x (a float32) rounded to the nearest bfloat16, ties to even."""
+    return float(_load().oracle_bf16(x))
+
+
 class Result:
-    def __init__(self, C, keys, Kt):
+    def __init__(self, C, keys, Kt, Klow=0):
         self.C = C          # float64 n x n (or None)
-        self.keys = keys    # sorted uint64 (linear_index(I,J) << 32) | K
+        self.keys = keys    # sorted uint64 (linear_index(I,J) << 32) | K, bit 63 = LOW
         self.Kt = Kt        # kept node triples per tier
+        self.Klow = Klow    # kept leaf products classed LOW (split precision)
 
     @property
     def K(self) -> int:
@@ -111,8 +127,9 @@ class Result:
 
 
 def spamm(A: np.ndarray, B: np.ndarray, b: int, tau: float, want_C: bool = True,
-          want_keys: bool = True, cap: int | None = None) -> Result:
-    """Full recursive SpAMM product in FP64."""
+          want_keys: bool = True, cap: int | None = None, low_tol: float = 0.0) -> Result:
+    """Full recursive SpAMM product in FP64; low_tol > 0 selects split
+    precision (LOW products on bfloat16-rounded operands)."""
     A, B = _f32(A), _f32(B)
     n = A.shape[0]
     if B.shape[0] != n:
@@ -121,33 +138,37 @@ def spamm(A: np.ndarray, B: np.ndarray, b: int, tau: float, want_C: bool = True,
     C = np.empty((n, n), dtype=np.float64) if want_C else None
     Kt = np.zeros(d + 1, dtype=np.int64)
     nk = np.zeros(1, dtype=np.int64)
+    kl = np.zeros(1, dtype=np.int64)
     keys = None
     if want_keys:
         if cap is None:
             # count first so the key buffer is exactly sized
-            rc = _load().oracle_spamm(A.ctypes.data, B.ctypes.data, n, b, float(tau),
-                                      None, None, 0, nk.ctypes.data, Kt.ctypes.data)
+            rc = _load().oracle_spamm_split(A.ctypes.data, B.ctypes.data, n, b, float(tau),
+                                            float(low_tol), None, None, 0, nk.ctypes.data,
+                                            Kt.ctypes.data, kl.ctypes.data)
             if rc:
                 raise RuntimeError(f"oracle_spamm -> {rc}")
             cap = int(nk[0])
         keys = np.empty(max(cap, 1), dtype=np.uint64)
-    rc = _load().oracle_spamm(A.ctypes.data, B.ctypes.data, n, b, float(tau),
-                              None if C is None else C.ctypes.data,
-                              None if keys is None else keys.ctypes.data,
-                              0 if keys is None else cap, nk.ctypes.data, Kt.ctypes.data)
+    rc = _load().oracle_spamm_split(A.ctypes.data, B.ctypes.data, n, b, float(tau), float(low_tol),
+                                    None if C is None else C.ctypes.data,
+                                    None if keys is None else keys.ctypes.data,
+                                    0 if keys is None else cap, nk.ctypes.data, Kt.ctypes.data,
+                                    kl.ctypes.data)
     if rc:
         raise RuntimeError(f"oracle_spamm -> {rc}")
     if keys is not None:
         keys = keys[:int(nk[0])]
-    return Result(C, keys, Kt)
+    return Result(C, keys, Kt, int(kl[0]))
 
 
 def spamm_tiles(A: np.ndarray, B: np.ndarray, b: int, tau: float, tiles,
-                threads: int = 1, want_klists: bool = False):
+                threads: int = 1, want_klists: bool = False, low_tol: float = 0.0):
     """Per-tile recursion for the output tiles ``tiles`` ((I, J) pairs).
 
     Returns (Ctiles [ntiles, b, b] float64, counts [ntiles], klists or None);
-    klists[s, :counts[s]] are the kept K values of tile s in ascending order.
+    klists[s, :counts[s]] are the kept K values of tile s in ascending order,
+    with 1 << 30 added for a LOW product (split precision, low_tol > 0).
     """
     A, B = _f32(A), _f32(B)
     n = A.shape[0]
@@ -157,9 +178,10 @@ def spamm_tiles(A: np.ndarray, B: np.ndarray, b: int, tau: float, tiles,
     Ct = np.empty((m, b, b), dtype=np.float64)
     counts = np.zeros(m, dtype=np.int64)
     kl = np.empty((m, 1 << d), dtype=np.int32) if want_klists else None
-    rc = _load().oracle_spamm_tiles(A.ctypes.data, B.ctypes.data, n, b, float(tau),
-                                    t.ctypes.data, m, Ct.ctypes.data, counts.ctypes.data,
-                                    None if kl is None else kl.ctypes.data, int(threads))
+    rc = _load().oracle_spamm_tiles_split(A.ctypes.data, B.ctypes.data, n, b, float(tau),
+                                          float(low_tol), t.ctypes.data, m, Ct.ctypes.data,
+                                          counts.ctypes.data,
+                                          None if kl is None else kl.ctypes.data, int(threads))
     if rc:
         raise RuntimeError(f"oracle_spamm_tiles -> {rc}")
     return Ct, counts, kl

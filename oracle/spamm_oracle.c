@@ -29,6 +29,12 @@
  *
  * Leaf products accumulate in FP64, k ascending within each output tile, and
  * the product of two FP32 values is exact in FP64.
+ *
+ * Split precision (the precision extension the paper's conclusions point
+ * to): a kept leaf product is LOW iff s_A * s_B < low_tol^2; its operands
+ * are rounded elementwise to bfloat16 (8 significant bits, round to nearest,
+ * ties to even) before the (exact, FP64) products; other products are
+ * unchanged.  The class is part of the task key (bit 63).
  */
 #include <math.h>
 #include <stdint.h>
@@ -148,11 +154,13 @@ typedef struct {
     int64_t n;
     int32_t b, d;
     double T2;             /* tau * tau */
+    double L2;             /* low_tol * low_tol (0: nothing is LOW) */
     const double *sA, *sB; /* all tiers, oracle_norms layout */
     double *C;             /* n x n, may be NULL */
     uint64_t *keys;        /* may be NULL */
     int64_t cap, nkeys;
     int64_t *Kt;           /* kept count per tier, d+1 entries */
+    int64_t Klow;          /* kept leaf products classed LOW */
 } mul_ctx;
 
 static int kept(const mul_ctx *x, int t, int64_t I, int64_t K, int64_t J)
@@ -167,9 +175,44 @@ static int kept(const mul_ctx *x, int t, int64_t I, int64_t K, int64_t J)
     return 1;
 }
 
-/* C_IJ += A_IK * B_KJ over the n x n (unpadded) part, l ascending. */
+/* x rounded to the nearest bfloat16 (ties to even), returned as a double.
+ * bfloat16 keeps the sign, the 8 exponent bits and the top 7 fraction bits of
+ * an IEEE single; the 16 dropped bits decide the rounding. */
+static double to_bf16(float x)
+{
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    uint32_t hi = u >> 16, rem = u & 0xFFFFu;
+    if (rem > 0x8000u || (rem == 0x8000u && (hi & 1u)))
+        hi += 1u;
+    uint32_t r = hi << 16;
+    float y;
+    memcpy(&y, &r, 4);
+    return (double)y;
+}
+
+double oracle_bf16(float x) { return to_bf16(x); }
+
+static int is_low(const mul_ctx *x, int t, int64_t I, int64_t K, int64_t J)
+{
+    int64_t Nt = (int64_t)1 << t;
+    double sa = x->sA[tier_offset(t) + I * Nt + K];
+    double sb = x->sB[tier_offset(t) + K * Nt + J];
+    return sa * sb < x->L2;
+}
+
+/* Element (r, c) of the padded matrix, rounded to bfloat16 when low. */
+static double elem_p(const float *A, int64_t n, int64_t r, int64_t c, int low)
+{
+    if (r >= n || c >= n)
+        return 0.0;
+    return low ? to_bf16(A[r * n + c]) : (double)A[r * n + c];
+}
+
+/* C_IJ += A_IK * B_KJ over the n x n (unpadded) part, l ascending; operands
+ * rounded to bfloat16 for a LOW product. */
 static void leaf_product(mul_ctx *x, int64_t I, int64_t K, int64_t J, double *Ct,
-                         int64_t ldc, int64_t r0, int64_t c0)
+                         int64_t ldc, int64_t r0, int64_t c0, int low)
 {
     int64_t b = x->b, n = x->n;
     for (int64_t p = 0; p < b; ++p) {
@@ -182,16 +225,17 @@ static void leaf_product(mul_ctx *x, int64_t I, int64_t K, int64_t J, double *Ct
                 break;
             double acc = 0.0;
             for (int64_t l = 0; l < b; ++l)
-                acc += elem(x->A, n, row, K * b + l) * elem(x->B, n, K * b + l, col);
+                acc += elem_p(x->A, n, row, K * b + l, low) * elem_p(x->B, n, K * b + l, col, low);
             Ct[(row - r0) * ldc + (col - c0)] += acc;
         }
     }
 }
 
-static void emit(mul_ctx *x, int64_t I, int64_t K, int64_t J)
+static void emit(mul_ctx *x, int64_t I, int64_t K, int64_t J, int low)
 {
     if (x->keys && x->nkeys < x->cap)
-        x->keys[x->nkeys] = (oracle_linear_index((uint64_t)I, (uint64_t)J) << 32) | (uint64_t)K;
+        x->keys[x->nkeys] = (oracle_linear_index((uint64_t)I, (uint64_t)J) << 32) | (uint64_t)K |
+                            ((uint64_t)low << 63);
     x->nkeys += 1;
 }
 
@@ -202,9 +246,11 @@ static void spamm(mul_ctx *x, int t, int64_t I, int64_t K, int64_t J)
         return;
     x->Kt[t] += 1;
     if (t == x->d) {
-        emit(x, I, K, J);
+        int low = is_low(x, t, I, K, J);
+        x->Klow += low;
+        emit(x, I, K, J, low);
         if (x->C)
-            leaf_product(x, I, K, J, x->C, x->n, 0, 0);
+            leaf_product(x, I, K, J, x->C, x->n, 0, 0, low);
         return;
     }
     for (int a = 0; a < 2; ++a)          /* child row    (quadrants 11,12,21,22) */
@@ -213,9 +259,11 @@ static void spamm(mul_ctx *x, int t, int64_t I, int64_t K, int64_t J)
                 spamm(x, t + 1, 2 * I + a, 2 * K + c, 2 * J + bq);
 }
 
+/* Keys compare on (leaf, k); bit 63 only carries the class. */
 static int cmp_u64(const void *a, const void *b)
 {
-    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    uint64_t m = ~((uint64_t)1 << 63);
+    uint64_t x = *(const uint64_t *)a & m, y = *(const uint64_t *)b & m;
     return x < y ? -1 : (x > y ? 1 : 0);
 }
 
@@ -234,12 +282,27 @@ static int check_inputs(int64_t n, int32_t b, double tau)
  * (linear_index(I,J) << 32) | K; *nkeys gets the total (keys beyond cap are
  * counted, not stored; OR_ERANGE then).  Kt[t] = kept triples at tier t.
  */
+int oracle_spamm_split(const float *A, const float *B, int64_t n, int32_t b, double tau,
+                       double low_tol, double *C, uint64_t *keys, int64_t cap, int64_t *nkeys,
+                       int64_t *Kt, int64_t *Klow);
+
 int oracle_spamm(const float *A, const float *B, int64_t n, int32_t b, double tau,
                  double *C, uint64_t *keys, int64_t cap, int64_t *nkeys, int64_t *Kt)
+{
+    int64_t Klow;
+    return oracle_spamm_split(A, B, n, b, tau, 0.0, C, keys, cap, nkeys, Kt, &Klow);
+}
+
+/* As oracle_spamm with split precision: LOW iff s_A s_B < low_tol^2. */
+int oracle_spamm_split(const float *A, const float *B, int64_t n, int32_t b, double tau,
+                       double low_tol, double *C, uint64_t *keys, int64_t cap, int64_t *nkeys,
+                       int64_t *Kt, int64_t *Klow)
 {
     int rc = check_inputs(n, b, tau);
     if (rc)
         return rc;
+    if (!(low_tol >= 0.0) || isinf(low_tol))
+        return OR_EINVAL;
     mul_ctx x;
     memset(&x, 0, sizeof x);
     int64_t np;
@@ -259,6 +322,7 @@ int oracle_spamm(const float *A, const float *B, int64_t n, int32_t b, double ta
     x.n = n;
     x.b = b;
     x.T2 = tau * tau;
+    x.L2 = low_tol * low_tol;
     x.sA = sA;
     x.sB = sB;
     x.C = C;
@@ -271,6 +335,7 @@ int oracle_spamm(const float *A, const float *B, int64_t n, int32_t b, double ta
         memset(C, 0, sizeof(double) * (size_t)n * (size_t)n);
     spamm(&x, 0, 0, 0, 0);
     *nkeys = x.nkeys;
+    *Klow = x.Klow;
     if (keys)
         qsort(keys, (size_t)(x.nkeys < cap ? x.nkeys : cap), sizeof(uint64_t), cmp_u64);
     free(sA);
@@ -301,23 +366,39 @@ static void spamm_tile(tile_ctx *y, int t, int64_t K)
     if (!kept(x, t, I, K, J))
         return;
     if (t == x->d) {
+        int low = is_low(x, t, I, K, J);
         if (y->kl)
-            y->kl[y->count] = (int32_t)K;
+            y->kl[y->count] = (int32_t)K | (low << 30);
         y->count += 1;
-        leaf_product(x, I, K, J, y->Ct, x->b, I * x->b, J * x->b);
+        leaf_product(x, I, K, J, y->Ct, x->b, I * x->b, J * x->b, low);
         return;
     }
     for (int c = 0; c < 2; ++c)
         spamm_tile(y, t + 1, 2 * K + c);
 }
 
+int oracle_spamm_tiles_split(const float *A, const float *B, int64_t n, int32_t b, double tau,
+                             double low_tol, const int64_t *tiles, int64_t ntiles, double *Ctiles,
+                             int64_t *counts, int32_t *klists, int nthreads);
+
 int oracle_spamm_tiles(const float *A, const float *B, int64_t n, int32_t b, double tau,
                        const int64_t *tiles, int64_t ntiles, double *Ctiles,
                        int64_t *counts, int32_t *klists, int nthreads)
 {
+    return oracle_spamm_tiles_split(A, B, n, b, tau, 0.0, tiles, ntiles, Ctiles, counts, klists,
+                                    nthreads);
+}
+
+/* klists entries: K | (1 << 30) for a LOW product. */
+int oracle_spamm_tiles_split(const float *A, const float *B, int64_t n, int32_t b, double tau,
+                             double low_tol, const int64_t *tiles, int64_t ntiles, double *Ctiles,
+                             int64_t *counts, int32_t *klists, int nthreads)
+{
     int rc = check_inputs(n, b, tau);
     if (rc)
         return rc;
+    if (!(low_tol >= 0.0) || isinf(low_tol))
+        return OR_EINVAL;
     mul_ctx x;
     memset(&x, 0, sizeof x);
     int64_t np;
@@ -341,6 +422,7 @@ int oracle_spamm_tiles(const float *A, const float *B, int64_t n, int32_t b, dou
     x.n = n;
     x.b = b;
     x.T2 = tau * tau;
+    x.L2 = low_tol * low_tol;
     x.sA = sA;
     x.sB = sB;
     int64_t bb = (int64_t)b * b;

@@ -25,6 +25,10 @@ SPAMM_E_HIP = -4
 SPAMM_E_RANGE = -5
 SPAMM_E_MISMATCH = -6
 
+PREC_FP32 = 0
+PREC_SPLIT_BF16 = 1
+TREE_BF16 = 1
+
 _lib = None
 
 
@@ -34,13 +38,20 @@ class SpammError(RuntimeError):
         self.code = code
 
 
+class Opts(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("low_tol", ctypes.c_double)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [
         ("depth", ctypes.c_int32),
         ("leaf", ctypes.c_int32),
         ("kept", ctypes.c_int64 * 32),
         ("tasks", ctypes.c_int64),
+        ("tasks_low", ctypes.c_int64),
         ("block_entries", ctypes.c_int64),
+        ("block_entries_low", ctypes.c_int64),
         ("flops", ctypes.c_double),
         ("symbolic_ms", ctypes.c_double),
         ("numeric_ms", ctypes.c_double),
@@ -50,7 +61,9 @@ class Stats(ctypes.Structure):
         return {
             "depth": self.depth, "leaf": self.leaf,
             "kept": [int(self.kept[t]) for t in range(self.depth + 1)],
-            "tasks": int(self.tasks), "block_entries": int(self.block_entries),
+            "tasks": int(self.tasks), "tasks_low": int(self.tasks_low),
+            "block_entries": int(self.block_entries),
+            "block_entries_low": int(self.block_entries_low),
             "flops": float(self.flops), "symbolic_ms": float(self.symbolic_ms),
             "numeric_ms": float(self.numeric_ms),
         }
@@ -79,6 +92,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     pp = ctypes.POINTER(ctypes.c_void_p)
     sig = {
         "spamm_build_tree": [vp, i64, i32, vp, pp],
+        "spamm_build_tree_ex": [vp, i64, i32, ctypes.c_uint32, vp, pp],
+        "spamm_symbolic_ex": [vp, vp, ctypes.POINTER(Opts), vp, pp],
+        "spamm_multiply_opts": [vp, vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Stats)],
         "spamm_tree_free": [vp],
         "spamm_tree_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
                             ctypes.POINTER(dbl)],
@@ -224,18 +240,34 @@ class Plan:
             pass
 
 
-def build_tree(A, leaf: int, stream=None) -> Tree:
+def build_tree(A, leaf: int, stream=None, bf16: bool = False) -> Tree:
+    """Quadtree of A; bf16=True also keeps BF16 leaf copies (split precision)."""
     A = _device_matrix(A, "A")
     h = ctypes.c_void_p()
-    _check(load().spamm_build_tree(ctypes.c_void_p(A.data_ptr()), A.shape[0], leaf,
-                                   _stream(stream), ctypes.byref(h)), "spamm_build_tree")
-    return Tree(h)
+    _check(load().spamm_build_tree_ex(ctypes.c_void_p(A.data_ptr()), A.shape[0], leaf,
+                                      TREE_BF16 if bf16 else 0, _stream(stream), ctypes.byref(h)),
+           "spamm_build_tree")
+    t = Tree(h)
+    t.bf16 = bool(bf16)
+    return t
 
 
-def symbolic(A: Tree, B: Tree, tau: float, stream=None) -> Plan:
+def _opts(tau, precision, low_tol) -> Opts:
+    return Opts(float(tau), int(precision), float(low_tol))
+
+
+def relative_low_tol(A: Tree, B: Tree, theta: float) -> float:
+    """low_tol for the split class 'norm product < theta ||A||_F ||B||_F'."""
+    import math
+    return float(theta) * math.sqrt(A.norm2) * math.sqrt(B.norm2)
+
+
+def symbolic(A: Tree, B: Tree, tau: float, stream=None, precision: int = PREC_FP32,
+             low_tol: float = 0.0) -> Plan:
     h = ctypes.c_void_p()
-    _check(load().spamm_symbolic(A.handle, B.handle, float(tau), _stream(stream), ctypes.byref(h)),
-           "spamm_symbolic")
+    o = _opts(tau, precision, low_tol)
+    _check(load().spamm_symbolic_ex(A.handle, B.handle, ctypes.byref(o), _stream(stream),
+                                    ctypes.byref(h)), "spamm_symbolic")
     return Plan(h, A, B)
 
 
@@ -248,11 +280,15 @@ def multiply(A: Tree, B: Tree, tau: float, C, stream=None):
     return C
 
 
-def multiply_ex(A: Tree, B: Tree, tau: float, C, stream=None) -> dict:
+def multiply_ex(A: Tree, B: Tree, tau: float, C, stream=None, precision: int = PREC_FP32,
+                low_tol: float = 0.0) -> dict:
+    """C = A B under the SpAMM condition, timed (synchronizes); returns stats."""
     _device_matrix(C, "C")
     if C.shape[0] != A.n:
         raise ValueError("C has the wrong shape")
     st = Stats()
-    _check(load().spamm_multiply_ex(A.handle, B.handle, float(tau), ctypes.c_void_p(C.data_ptr()),
-                                    _stream(stream), ctypes.byref(st)), "spamm_multiply_ex")
+    o = _opts(tau, precision, low_tol)
+    _check(load().spamm_multiply_opts(A.handle, B.handle, ctypes.byref(o),
+                                      ctypes.c_void_p(C.data_ptr()), _stream(stream),
+                                      ctypes.byref(st)), "spamm_multiply_opts")
     return st.as_dict()

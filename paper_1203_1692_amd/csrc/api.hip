@@ -16,7 +16,8 @@
 
 namespace spamm {
 hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *tiles,
-                        float *tilesT, double *norms, hipStream_t s);
+                        float *tilesT, uint16_t *t16, uint16_t *tT16, double *norms,
+                        hipStream_t s);
 hipError_t launch_cull(spamm_plan *p, hipStream_t s);
 hipError_t launch_gemm(const spamm_plan *p, float *C, hipStream_t s);
 size_t scan_partials_len(uint32_t m);
@@ -110,6 +111,12 @@ const char *spamm_last_error(void) { return g_err; }
 
 int spamm_build_tree(const float *A, int64_t n, int32_t leaf, void *stream, spamm_tree **out)
 {
+    return spamm_build_tree_ex(A, n, leaf, 0u, stream, out);
+}
+
+int spamm_build_tree_ex(const float *A, int64_t n, int32_t leaf, uint32_t flags, void *stream,
+                        spamm_tree **out)
+{
     if (out == nullptr)
         return fail(SPAMM_E_INVAL, "out is NULL");
     *out = nullptr;
@@ -119,6 +126,11 @@ int spamm_build_tree(const float *A, int64_t n, int32_t leaf, void *stream, spam
         return fail(SPAMM_E_INVAL, "n = %lld < 1", (long long)n);
     if (leaf != 16 && leaf != 32 && leaf != 64)
         return fail(SPAMM_E_INVAL, "leaf = %d not in {16, 32, 64}", leaf);
+    if ((flags & ~SPAMM_TREE_BF16) != 0)
+        return fail(SPAMM_E_INVAL, "unknown tree flags 0x%x", flags);
+    const bool bf16 = (flags & SPAMM_TREE_BF16) != 0;
+    if (bf16 && leaf == 16)
+        return fail(SPAMM_E_INVAL, "BF16 leaf copies need leaf 32 or 64");
     int32_t d;
     int64_t np;
     int rc = depth_of(n, leaf, &d, &np);
@@ -144,10 +156,14 @@ int spamm_build_tree(const float *A, int64_t n, int32_t leaf, void *stream, spam
     hipError_t e = hipMallocAsync((void **)&t->tiles, tile_bytes, s);
     if (e == hipSuccess)
         e = hipMallocAsync((void **)&t->tilesT, tile_bytes, s);
+    if (e == hipSuccess && bf16)
+        e = hipMallocAsync((void **)&t->tiles16, tile_bytes / 2, s);
+    if (e == hipSuccess && bf16)
+        e = hipMallocAsync((void **)&t->tilesT16, tile_bytes / 2, s);
     if (e == hipSuccess)
         e = hipMallocAsync((void **)&t->norms, norm_bytes, s);
     if (e == hipSuccess)
-        e = launch_build(A, n, leaf, d, t->tiles, t->tilesT, t->norms, s);
+        e = launch_build(A, n, leaf, d, t->tiles, t->tilesT, t->tiles16, t->tilesT16, t->norms, s);
     double root = 0.0;
     if (e == hipSuccess)
         e = hipMemcpyAsync(&root, t->norms, sizeof(double), hipMemcpyDeviceToHost, s);
@@ -176,7 +192,8 @@ int spamm_tree_free(spamm_tree *t)
     if (dev0 != t->device)
         hipSetDevice(t->device);
     hipError_t e = hipSuccess;
-    for (void *ptr : {(void *)t->tiles, (void *)t->tilesT, (void *)t->norms}) {
+    for (void *ptr : {(void *)t->tiles, (void *)t->tilesT, (void *)t->tiles16, (void *)t->tilesT16,
+                      (void *)t->norms}) {
         if (ptr == nullptr)
             continue;
         hipError_t f = hipFreeAsync(ptr, t->stream);
@@ -268,24 +285,48 @@ int spamm_plan_free(spamm_plan *p)
     return e == hipSuccess ? SPAMM_OK : hip_fail(e, "spamm_plan_free");
 }
 
+static int check_tol(double v, const char *name)
+{
+    if (!(v >= 0.0) || isinf(v))
+        return fail(SPAMM_E_INVAL, "%s = %g must be finite and >= 0", name, v);
+    if (v > 0.0 && v < 1e-150)
+        return fail(SPAMM_E_INVAL, "%s = %g below 1e-150 (its square would underflow)", name, v);
+    return SPAMM_OK;
+}
+
 int spamm_symbolic(const spamm_tree *A, const spamm_tree *B, double tau, void *stream,
                    spamm_plan **out)
+{
+    spamm_opts o;
+    o.tau = tau;
+    o.precision = SPAMM_PREC_FP32;
+    o.low_tol = 0.0;
+    return spamm_symbolic_ex(A, B, &o, stream, out);
+}
+
+int spamm_symbolic_ex(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
+                      void *stream, spamm_plan **out)
 {
     if (out == nullptr)
         return fail(SPAMM_E_INVAL, "out is NULL");
     *out = nullptr;
-    if (A == nullptr || B == nullptr)
-        return fail(SPAMM_E_INVAL, "tree is NULL");
-    if (!(tau >= 0.0) || isinf(tau))
-        return fail(SPAMM_E_INVAL, "tau = %g must be finite and >= 0", tau);
-    if (tau > 0.0 && tau < 1e-150)
-        return fail(SPAMM_E_INVAL, "tau = %g below 1e-150 (tau^2 would underflow)", tau);
+    if (A == nullptr || B == nullptr || opts == nullptr)
+        return fail(SPAMM_E_INVAL, "tree or options NULL");
+    int rc;
+    if ((rc = check_tol(opts->tau, "tau")))
+        return rc;
+    if (opts->precision != SPAMM_PREC_FP32 && opts->precision != SPAMM_PREC_SPLIT_BF16)
+        return fail(SPAMM_E_INVAL, "unknown precision %d", opts->precision);
+    const bool split = opts->precision == SPAMM_PREC_SPLIT_BF16;
+    if (split && (rc = check_tol(opts->low_tol, "low_tol")))
+        return rc;
     if (A->n != B->n || A->leaf != B->leaf)
         return fail(SPAMM_E_MISMATCH, "A is %lld/%d, B is %lld/%d (n/leaf)", (long long)A->n,
                     A->leaf, (long long)B->n, B->leaf);
+    if (split && (A->tiles16 == nullptr || B->tilesT16 == nullptr))
+        return fail(SPAMM_E_INVAL, "split precision needs trees built with SPAMM_TREE_BF16");
     int dev;
-    int rc = prepare_device(&dev);
-    if (rc)
+    if ((rc = prepare_device(&dev)))
         return rc;
     if (A->device != dev || B->device != dev)
         return fail(SPAMM_E_INVAL, "trees live on device %d/%d, current device is %d", A->device,
@@ -301,8 +342,11 @@ int spamm_symbolic(const spamm_tree *A, const spamm_tree *B, double tau, void *s
     p->depth = A->depth;
     p->leaf = A->leaf;
     p->n = A->n;
-    p->tau = tau;
-    p->T2 = tau * tau;
+    p->tau = opts->tau;
+    p->T2 = opts->tau * opts->tau;
+    p->precision = opts->precision;
+    p->low_tol = split ? opts->low_tol : 0.0;
+    p->L2 = p->low_tol * p->low_tol;
     const int d = p->depth;
     p->nblocks = d == 0 ? 1 : (int64_t(1) << (2 * (d - 1)));
 
@@ -324,13 +368,17 @@ int spamm_symbolic(const spamm_tree *A, const spamm_tree *B, double tau, void *s
         {(void **)&p->rowptr, sizeof(uint32_t) * (size_t)std::max<int64_t>(rp, 2)},
         {(void **)&p->list[0], sizeof(uint32_t) * (size_t)cap_list[0]},
         {(void **)&p->list[1], sizeof(uint32_t) * (size_t)cap_list[1]},
-        {(void **)&p->counts, sizeof(uint32_t) * 2 * (size_t)ncounts},
+        {(void **)&p->counts, sizeof(uint32_t) * 4 * (size_t)ncounts},
         {(void **)&p->partials, sizeof(uint32_t) * npart},
         {(void **)&p->browptr, sizeof(uint32_t) * (size_t)(p->nblocks + 1)},
         {(void **)&p->bent, sizeof(uint32_t) * (size_t)cap_bent},
-        {(void **)&p->leafK, sizeof(uint64_t)},
+        {(void **)&p->leafK, 2 * sizeof(uint64_t)},
+        {(void **)&p->browptr_lo, split ? sizeof(uint32_t) * (size_t)(p->nblocks + 1) : 0},
+        {(void **)&p->bent_lo, split ? sizeof(uint32_t) * (size_t)cap_bent : 0},
     };
     for (auto &r : reqs) {
+        if (r.bytes == 0)
+            continue;
         hipError_t e = hipMallocAsync(r.dst, r.bytes, s);
         if (e != hipSuccess) {
             rc = hip_fail(e, "hipMallocAsync (plan)");
@@ -372,19 +420,49 @@ int spamm_plan_stats(const spamm_plan *p, spamm_stats *out)
         HIP_TRY(hipMemcpyAsync(&tot[(size_t)t], p->rowptr + p->rp_off[t] + (int64_t(1) << (2 * t)),
                                sizeof(uint32_t), hipMemcpyDeviceToHost, p->stream),
                 "hipMemcpyAsync");
-    uint64_t K = 0;
-    uint32_t entries = 0;
-    HIP_TRY(hipMemcpyAsync(&K, p->leafK, sizeof K, hipMemcpyDeviceToHost, p->stream), "hipMemcpyAsync");
-    HIP_TRY(hipMemcpyAsync(&entries, p->browptr + p->nblocks, sizeof entries, hipMemcpyDeviceToHost,
+    const bool split = p->precision != SPAMM_PREC_FP32;
+    uint64_t K[2] = {0, 0};
+    uint32_t entries[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(K, p->leafK, (split ? 2 : 1) * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                           p->stream),
+            "hipMemcpyAsync");
+    HIP_TRY(hipMemcpyAsync(&entries[0], p->browptr + p->nblocks, sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, p->stream),
+            "hipMemcpyAsync");
+    if (split)
+        HIP_TRY(hipMemcpyAsync(&entries[1], p->browptr_lo + p->nblocks, sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, p->stream),
+                "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+    const int64_t all = (int64_t)(K[0] + K[1]);
+    for (int t = 0; t < d; ++t)
+        out->kept[t] = tot[(size_t)t];
+    out->kept[d] = all;
+    out->tasks = all;
+    out->tasks_low = (int64_t)K[1];
+    out->block_entries = entries[0];
+    out->block_entries_low = entries[1];
+    out->flops = 2.0 * (double)p->leaf * p->leaf * p->leaf * (double)all;
+    return SPAMM_OK;
+}
+
+// Copies one class's block schedule (row pointers + entries) to the host.
+static int fetch_schedule(const spamm_plan *p, const uint32_t *drp, const uint32_t *dent,
+                          std::vector<uint32_t> &rp, std::vector<uint32_t> &ent)
+{
+    const size_t nb = (size_t)p->nblocks;
+    rp.assign(nb + 1, 0);
+    HIP_TRY(hipMemcpyAsync(rp.data(), drp, sizeof(uint32_t) * (nb + 1), hipMemcpyDeviceToHost,
                            p->stream),
             "hipMemcpyAsync");
     HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
-    for (int t = 0; t < d; ++t)
-        out->kept[t] = tot[(size_t)t];
-    out->kept[d] = (int64_t)K;
-    out->tasks = (int64_t)K;
-    out->block_entries = entries;
-    out->flops = 2.0 * (double)p->leaf * p->leaf * p->leaf * (double)K;
+    ent.assign(rp[nb], 0);
+    if (!ent.empty()) {
+        HIP_TRY(hipMemcpyAsync(ent.data(), dent, sizeof(uint32_t) * ent.size(),
+                               hipMemcpyDeviceToHost, p->stream),
+                "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+    }
     return SPAMM_OK;
 }
 
@@ -392,47 +470,57 @@ int spamm_plan_tasks(const spamm_plan *p, uint64_t *host, size_t cap, size_t *co
 {
     if (p == nullptr || count == nullptr)
         return fail(SPAMM_E_INVAL, "NULL argument");
-    const size_t nb = (size_t)p->nblocks;
-    std::vector<uint32_t> rp(nb + 1);
-    HIP_TRY(hipMemcpyAsync(rp.data(), p->browptr, sizeof(uint32_t) * (nb + 1), hipMemcpyDeviceToHost,
+    const bool split = p->precision != SPAMM_PREC_FP32;
+    uint64_t K[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(K, p->leafK, (split ? 2 : 1) * sizeof(uint64_t), hipMemcpyDeviceToHost,
                            p->stream),
             "hipMemcpyAsync");
-    uint64_t K = 0;
-    HIP_TRY(hipMemcpyAsync(&K, p->leafK, sizeof K, hipMemcpyDeviceToHost, p->stream), "hipMemcpyAsync");
     HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
-    *count = (size_t)K;
-    if (host == nullptr || cap < K)
+    const uint64_t total = K[0] + K[1];
+    *count = (size_t)total;
+    if (host == nullptr || cap < total)
         return host == nullptr && cap == 0 ? SPAMM_OK
                                            : fail(SPAMM_E_RANGE, "cap %zu < K = %llu", cap,
-                                                  (unsigned long long)K);
-    std::vector<uint32_t> ent(rp[nb]);
-    if (!ent.empty()) {
-        HIP_TRY(hipMemcpyAsync(ent.data(), p->bent, sizeof(uint32_t) * ent.size(),
-                               hipMemcpyDeviceToHost, p->stream),
-                "hipMemcpyAsync");
-        HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
-    }
+                                                  (unsigned long long)total);
+    std::vector<uint32_t> rp[2], ent[2];
+    int rc = fetch_schedule(p, p->browptr, p->bent, rp[0], ent[0]);
+    if (rc == SPAMM_OK && split)
+        rc = fetch_schedule(p, p->browptr_lo, p->bent_lo, rp[1], ent[1]);
+    if (rc != SPAMM_OK)
+        return rc;
     // Expand block entries to leaf keys in (output leaf, k) order: leaf
-    // 4 P + q of block P takes the entries whose mask has bit q.
+    // 4 P + q of block P takes the entries whose mask has bit q; within a
+    // leaf the two classes are merged by k (each list is ascending).
+    const size_t nb = (size_t)p->nblocks;
     size_t o = 0;
     for (size_t P = 0; P < nb; ++P)
         for (uint32_t q = 0; q < 4; ++q) {
             const uint64_t lc = p->depth == 0 ? 0 : 4 * (uint64_t)P + q;
-            for (uint32_t e = rp[P]; e < rp[P + 1]; ++e)
-                if ((ent[e] >> (16 + q)) & 1u) {
-                    if (o >= cap)
-                        return fail(SPAMM_E_RANGE, "inconsistent task count");
-                    host[o++] = (lc << 32) | (ent[e] & 0xFFFFu);
-                }
+            uint32_t e[2] = {rp[0][P], split ? rp[1][P] : 0u};
+            const uint32_t end[2] = {rp[0][P + 1], split ? rp[1][P + 1] : 0u};
+            for (;;) {
+                for (int c = 0; c < 2; ++c)
+                    while (e[c] < end[c] && !((ent[c][e[c]] >> (16 + q)) & 1u))
+                        ++e[c];
+                const bool has0 = e[0] < end[0], has1 = e[1] < end[1];
+                if (!has0 && !has1)
+                    break;
+                const int c = !has1 ? 0 : !has0 ? 1
+                                     : ((ent[0][e[0]] & 0xFFFFu) < (ent[1][e[1]] & 0xFFFFu) ? 0 : 1);
+                if (o >= cap)
+                    return fail(SPAMM_E_RANGE, "inconsistent task count");
+                host[o++] = (lc << 32) | (ent[c][e[c]] & 0xFFFFu) | ((uint64_t)c << 63);
+                ++e[c];
+            }
         }
-    if (o != K)
+    if (o != total)
         return fail(SPAMM_E_HIP, "task count mismatch: %zu expanded vs %llu counted", o,
-                    (unsigned long long)K);
+                    (unsigned long long)total);
     return SPAMM_OK;
 }
 
-int spamm_multiply_ex(const spamm_tree *A, const spamm_tree *B, double tau, float *C, void *stream,
-                      spamm_stats *stats)
+int spamm_multiply_opts(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
+                        float *C, void *stream, spamm_stats *stats)
 {
     if (C == nullptr)
         return fail(SPAMM_E_INVAL, "C is NULL");
@@ -444,7 +532,7 @@ int spamm_multiply_ex(const spamm_tree *A, const spamm_tree *B, double tau, floa
         HIP_TRY(hipEventRecord(ev[0], s), "hipEventRecord");
     }
     spamm_plan *p = nullptr;
-    int rc = spamm_symbolic(A, B, tau, stream, &p);
+    int rc = spamm_symbolic_ex(A, B, opts, stream, &p);
     if (rc == SPAMM_OK && stats) {
         hipError_t e = hipEventRecord(ev[1], s);
         if (e != hipSuccess)
@@ -469,6 +557,16 @@ int spamm_multiply_ex(const spamm_tree *A, const spamm_tree *B, double tau, floa
         if (x)
             hipEventDestroy(x);
     return rc != SPAMM_OK ? rc : rc2;
+}
+
+int spamm_multiply_ex(const spamm_tree *A, const spamm_tree *B, double tau, float *C, void *stream,
+                      spamm_stats *stats)
+{
+    spamm_opts o;
+    o.tau = tau;
+    o.precision = SPAMM_PREC_FP32;
+    o.low_tol = 0.0;
+    return spamm_multiply_opts(A, B, &o, C, stream, stats);
 }
 
 int spamm_multiply(const spamm_tree *A, const spamm_tree *B, double tau, float *C, void *stream)

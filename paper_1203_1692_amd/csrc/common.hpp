@@ -80,12 +80,44 @@ __host__ __device__ inline int leaf_index(int B, int r, int c)
     }
 }
 
+// BF16 copy of a leaf (split precision): rows of n_b bf16 (n_b in {32, 64}),
+// the 16-byte granules (8 bf16) of each row XOR-permuted so that 16 rows read
+// at one logical column by a ds_read_b128 hit 16 distinct groups of banks.
+template <int B>
+struct Leaf16Layout {
+    static constexpr int kGran = B / 8;                          // granules per row
+    static constexpr int kShift = kGran == 8 ? 1 : 2;
+    __host__ __device__ static constexpr int index(int r, int c)
+    {
+        return r * B + 8 * ((c >> 3) ^ ((r >> kShift) & (kGran - 1))) + (c & 7);
+    }
+};
+
+__host__ __device__ inline int leaf16_index(int B, int r, int c)
+{
+    return B == 32 ? Leaf16Layout<32>::index(r, c) : Leaf16Layout<64>::index(r, c);
+}
+
+// FP32 -> BF16 with round-to-nearest-even on the bit pattern (inputs are
+// finite: non-finite matrices are rejected when the tree is built).
+__host__ __device__ inline uint16_t to_bf16(float x)
+{
+    uint32_t u;
+    __builtin_memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 // The SpAMM keep decision on stored squared norms (both FP64):
 // zero norm -> NULL link, never kept; otherwise kept unless s_A s_B < tau^2.
 __device__ inline bool keep_pair(double sa, double sb, double T2)
 {
     return (sa > 0.0) & (sb > 0.0) & !(sa * sb < T2);
 }
+
+// Split precision: a kept product is LOW (BF16 operands) iff s_A s_B < L2,
+// L2 = fl64(low_tol^2); L2 = 0 makes every product HIGH (FP32).
+__device__ inline bool low_pair(double sa, double sb, double L2) { return sa * sb < L2; }
 
 __device__ inline int lane_id() { return __lane_id(); }
 
@@ -101,6 +133,8 @@ struct spamm_tree {
     int32_t leaf, depth;
     float *tiles;           // N^2 leaves (left-operand copy), linear-index order, LeafLayout
     float *tilesT;          // the same leaves transposed (right-operand copy), LeafLayout
+    uint16_t *tiles16;      // BF16 left-operand copy (Leaf16Layout), or null
+    uint16_t *tilesT16;     // BF16 right-operand (transposed) copy, or null
     double *norms;          // tiers 0..d, tier_offset layout
     double root;            // ||A||_F^2
 };
@@ -112,6 +146,8 @@ struct spamm_plan {
     int32_t depth, leaf;
     int64_t n;
     double tau, T2;
+    int32_t precision;      // SPAMM_PREC_*
+    double low_tol, L2;     // split: LOW iff s_A s_B < L2 = low_tol^2
     // tier lists for t < d: CSR over the 4^t tier-t output tiles (linear
     // index), entries = kept k at that tier, ascending
     uint32_t *rowptr;       // all tiers t = 0..d-1, offset rp_off[t], 4^t + 1 each
@@ -121,10 +157,12 @@ struct spamm_plan {
     uint32_t *partials;     // scan block sums
     // leaf-tier schedule: CSR over the GEMM blocks (tier d-1 tiles, or the
     // single leaf when d = 0); entry = k | (quadrant mask << 16)
-    uint32_t *browptr;
+    uint32_t *browptr;      // HIGH (FP32) products
     uint32_t *bent;
-    uint64_t *leafK;        // number of kept leaf triples
+    uint32_t *browptr_lo;   // LOW (BF16) products, split precision only
+    uint32_t *bent_lo;
+    uint64_t *leafK;        // [0] kept leaf triples, [1] of which LOW
     int64_t nblocks;
-    void *pool[8];          // allocations owned by the plan
+    void *pool[12];         // allocations owned by the plan
     int npool;
 };

@@ -19,26 +19,38 @@
 //
 // Leaf tier: the GEMM works on blocks of 2 x 2 output leaves (the children of
 // one tier-(d-1) tile), so the last tier emits per block the union of kept k
-// with a 4-bit mask of the leaves (q) that take the product.
+// with a 4-bit mask of the leaves (q) that take the product.  With split
+// precision each kept leaf product is also classed LOW (s_A s_B < low_tol^2,
+// BF16 operands) or HIGH (FP32), and the two classes get separate lists.
 #include "common.hpp"
 
 namespace spamm {
 
 // Root triple (0,0,0) at tier 0.
 __global__ void cull_root(const double *__restrict__ nA, const double *__restrict__ nB, double T2,
-                          uint32_t *__restrict__ rowptr0, uint32_t *__restrict__ list0,
+                          double L2, uint32_t *__restrict__ rowptr0, uint32_t *__restrict__ list0,
                           uint32_t *__restrict__ browptr, uint32_t *__restrict__ bent,
+                          uint32_t *__restrict__ browptr_lo, uint32_t *__restrict__ bent_lo,
                           uint64_t *__restrict__ leafK, int last)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0)
         return;
     const uint32_t kept = keep_pair(nA[0], nB[0], T2) ? 1u : 0u;
     if (last) {
+        // d = 0: the root is the only leaf
+        const uint32_t low = (kept && low_pair(nA[0], nB[0], L2)) ? 1u : 0u;
         browptr[0] = 0;
-        browptr[1] = kept;
-        if (kept)
+        browptr[1] = kept & ~low;
+        if (kept & ~low)
             bent[0] = 0u | (1u << 16);
-        *leafK = kept;
+        leafK[0] = kept & ~low;
+        if (browptr_lo != nullptr) {
+            browptr_lo[0] = 0;
+            browptr_lo[1] = low;
+            if (low)
+                bent_lo[0] = 0u | (1u << 16);
+            leafK[1] = low;
+        }
     } else {
         rowptr0[0] = 0;
         rowptr0[1] = kept;
@@ -70,6 +82,27 @@ __device__ inline uint32_t child_flags(const double *__restrict__ nA, const doub
     return f;
 }
 
+// The 8 LOW flags (split precision) of the same children, among kept ones.
+__device__ inline uint32_t child_low(const double *__restrict__ nA, const double *__restrict__ nB,
+                                     double L2, uint32_t I, uint32_t kp, uint32_t J, uint32_t kept)
+{
+    const double2 *pa = reinterpret_cast<const double2 *>(nA + 4 * (int64_t)lin_index(I, kp));
+    const double2 *pb = reinterpret_cast<const double2 *>(nB + 4 * (int64_t)lin_index(kp, J));
+    const double2 a01 = pa[0], a23 = pa[1];
+    const double2 b01 = pb[0], b23 = pb[1];
+    const double a[4] = {a01.x, a01.y, a23.x, a23.y};
+    const double b[4] = {b01.x, b01.y, b23.x, b23.y};
+    uint32_t f = 0;
+#pragma unroll
+    for (int qa = 0; qa < 2; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                f |= (low_pair(a[2 * qa + c], b[2 * c + qb], L2) ? 1u : 0u) << (2 * (2 * qa + qb) + c);
+    return f & kept;
+}
+
 // Leaf-tier quadrant mask of inner child c from the 8 flags.
 __device__ inline uint32_t mask_of(uint32_t f, int c)
 {
@@ -77,7 +110,8 @@ __device__ inline uint32_t mask_of(uint32_t f, int c)
            (((f >> (6 + c)) & 1u) << 3);
 }
 
-template <bool LAST>
+// Tiers below the leaves: per parent output tile P, the number of kept
+// children in each child tile 4P + q.
 __global__ __launch_bounds__(256) void cull_count(const double *__restrict__ nA,
                                                   const double *__restrict__ nB, double T2,
                                                   const uint32_t *__restrict__ prow,
@@ -91,42 +125,75 @@ __global__ __launch_bounds__(256) void cull_count(const double *__restrict__ nA,
     const uint32_t I = lin_row(P), J = lin_col(P);
     const uint32_t beg = prow[P], end = prow[P + 1];
     uint32_t tot[4] = {0, 0, 0, 0};
-    uint32_t entries = 0, tasks = 0;
     for (uint32_t base = beg; base < end; base += kWave) {
         const uint32_t idx = base + lane;
         uint32_t f = 0;
         if (idx < end)
             f = child_flags(nA, nB, T2, I, plist[idx], J);
-        if constexpr (LAST) {
-            const uint32_t m0 = mask_of(f, 0), m1 = mask_of(f, 1);
-            entries += __popcll(__ballot(m0 != 0)) + __popcll(__ballot(m1 != 0));
-            tasks += __popc(f);
-        } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                tot[q] += __popcll(__ballot((f >> (2 * q)) & 1u)) +
-                          __popcll(__ballot((f >> (2 * q + 1)) & 1u));
+        for (int q = 0; q < 4; ++q)
+            tot[q] += __popcll(__ballot((f >> (2 * q)) & 1u)) +
+                      __popcll(__ballot((f >> (2 * q + 1)) & 1u));
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            counts[4 * P + q] = tot[q];
+    }
+}
+
+// Leaf tier: per GEMM block P (a tier-(d-1) tile), the number of schedule
+// entries (distinct k with at least one product) and of leaf products, for the
+// HIGH list and, when SPLIT, the LOW list.  counts layout (np = nparents):
+// [0,np) HIGH entries, [np,2np) HIGH products, [2np,3np) LOW entries,
+// [3np,4np) LOW products.
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void cull_count_leaf(const double *__restrict__ nA,
+                                                       const double *__restrict__ nB, double T2,
+                                                       double L2, const uint32_t *__restrict__ prow,
+                                                       const uint32_t *__restrict__ plist,
+                                                       uint32_t nparents,
+                                                       uint32_t *__restrict__ counts)
+{
+    const uint32_t P = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (P >= nparents)
+        return;
+    const int lane = threadIdx.x & 63;
+    const uint32_t I = lin_row(P), J = lin_col(P);
+    const uint32_t beg = prow[P], end = prow[P + 1];
+    uint32_t ent_hi = 0, ent_lo = 0, tasks_hi = 0, tasks_lo = 0;
+    for (uint32_t base = beg; base < end; base += kWave) {
+        const uint32_t idx = base + lane;
+        uint32_t f = 0, lo = 0;
+        if (idx < end) {
+            const uint32_t kp = plist[idx];
+            f = child_flags(nA, nB, T2, I, kp, J);
+            if constexpr (SPLIT)
+                lo = child_low(nA, nB, L2, I, kp, J, f);
+        }
+        const uint32_t hi = f & ~lo;
+        ent_hi += __popcll(__ballot(mask_of(hi, 0) != 0)) + __popcll(__ballot(mask_of(hi, 1) != 0));
+        tasks_hi += __popc(hi);
+        if constexpr (SPLIT) {
+            ent_lo += __popcll(__ballot(mask_of(lo, 0) != 0)) + __popcll(__ballot(mask_of(lo, 1) != 0));
+            tasks_lo += __popc(lo);
         }
     }
-    if constexpr (LAST) {
-        // entries per block for the GEMM schedule; leaf products per block
-        // (counts[nparents + P]) are summed by reduce_tasks
-        for (int o = 32; o > 0; o >>= 1)
-            tasks += __shfl_xor(tasks, o);
-        if (lane == 0) {
-            counts[P] = entries;
-            counts[nparents + P] = tasks;
-        }
-    } else {
-        if (lane == 0) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                counts[4 * P + q] = tot[q];
+    for (int o = 32; o > 0; o >>= 1) {
+        tasks_hi += __shfl_xor(tasks_hi, o);
+        if constexpr (SPLIT)
+            tasks_lo += __shfl_xor(tasks_lo, o);
+    }
+    if (lane == 0) {
+        counts[P] = ent_hi;
+        counts[nparents + P] = tasks_hi;
+        if constexpr (SPLIT) {
+            counts[2 * nparents + P] = ent_lo;
+            counts[3 * nparents + P] = tasks_lo;
         }
     }
 }
 
-template <bool LAST>
 __global__ __launch_bounds__(256) void cull_emit(const double *__restrict__ nA,
                                                  const double *__restrict__ nB, double T2,
                                                  const uint32_t *__restrict__ prow,
@@ -143,13 +210,9 @@ __global__ __launch_bounds__(256) void cull_emit(const double *__restrict__ nA,
     const uint32_t I = lin_row(P), J = lin_col(P);
     const uint32_t beg = prow[P], end = prow[P + 1];
     uint32_t run[4];
-    if constexpr (LAST) {
-        run[0] = crow[P];
-    } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            run[q] = crow[4 * P + q];
-    }
+    for (int q = 0; q < 4; ++q)
+        run[q] = crow[4 * P + q];
     for (uint32_t base = beg; base < end; base += kWave) {
         const uint32_t idx = base + lane;
         uint32_t f = 0, kp = 0;
@@ -157,28 +220,67 @@ __global__ __launch_bounds__(256) void cull_emit(const double *__restrict__ nA,
             kp = plist[idx];
             f = child_flags(nA, nB, T2, I, kp, J);
         }
-        if constexpr (LAST) {
-            const uint32_t m0 = mask_of(f, 0), m1 = mask_of(f, 1);
-            const uint64_t b0 = __ballot(m0 != 0), b1 = __ballot(m1 != 0);
-            const uint32_t pos = run[0] + __popcll(b0 & below) + __popcll(b1 & below);
-            if (m0)
-                clist[pos] = (2 * kp) | (m0 << 16);
-            if (m1)
-                clist[pos + (m0 ? 1 : 0)] = (2 * kp + 1) | (m1 << 16);
-            run[0] += __popcll(b0) + __popcll(b1);
-        } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t f0 = (f >> (2 * q)) & 1u, f1 = (f >> (2 * q + 1)) & 1u;
-                const uint64_t b0 = __ballot(f0), b1 = __ballot(f1);
-                const uint32_t pos = run[q] + __popcll(b0 & below) + __popcll(b1 & below);
-                if (f0)
-                    clist[pos] = 2 * kp;
-                if (f1)
-                    clist[pos + f0] = 2 * kp + 1;
-                run[q] += __popcll(b0) + __popcll(b1);
-            }
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t f0 = (f >> (2 * q)) & 1u, f1 = (f >> (2 * q + 1)) & 1u;
+            const uint64_t b0 = __ballot(f0), b1 = __ballot(f1);
+            const uint32_t pos = run[q] + __popcll(b0 & below) + __popcll(b1 & below);
+            if (f0)
+                clist[pos] = 2 * kp;
+            if (f1)
+                clist[pos + f0] = 2 * kp + 1;
+            run[q] += __popcll(b0) + __popcll(b1);
         }
+    }
+}
+
+// Writes the (k | mask << 16) entries of the flags `fl` of one chunk.
+__device__ inline void emit_entries(uint32_t fl, uint32_t kp, uint64_t below, uint32_t &run,
+                                    uint32_t *__restrict__ clist)
+{
+    const uint32_t m0 = mask_of(fl, 0), m1 = mask_of(fl, 1);
+    const uint64_t b0 = __ballot(m0 != 0), b1 = __ballot(m1 != 0);
+    const uint32_t pos = run + __popcll(b0 & below) + __popcll(b1 & below);
+    if (m0)
+        clist[pos] = (2 * kp) | (m0 << 16);
+    if (m1)
+        clist[pos + (m0 ? 1 : 0)] = (2 * kp + 1) | (m1 << 16);
+    run += __popcll(b0) + __popcll(b1);
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void cull_emit_leaf(const double *__restrict__ nA,
+                                                      const double *__restrict__ nB, double T2,
+                                                      double L2, const uint32_t *__restrict__ prow,
+                                                      const uint32_t *__restrict__ plist,
+                                                      uint32_t nparents,
+                                                      const uint32_t *__restrict__ rp_hi,
+                                                      uint32_t *__restrict__ ent_hi,
+                                                      const uint32_t *__restrict__ rp_lo,
+                                                      uint32_t *__restrict__ ent_lo)
+{
+    const uint32_t P = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (P >= nparents)
+        return;
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = lanes_below();
+    const uint32_t I = lin_row(P), J = lin_col(P);
+    const uint32_t beg = prow[P], end = prow[P + 1];
+    uint32_t run_hi = rp_hi[P], run_lo = 0;
+    if constexpr (SPLIT)
+        run_lo = rp_lo[P];
+    for (uint32_t base = beg; base < end; base += kWave) {
+        const uint32_t idx = base + lane;
+        uint32_t f = 0, lo = 0, kp = 0;
+        if (idx < end) {
+            kp = plist[idx];
+            f = child_flags(nA, nB, T2, I, kp, J);
+            if constexpr (SPLIT)
+                lo = child_low(nA, nB, L2, I, kp, J, f);
+        }
+        emit_entries(f & ~lo, kp, below, run_hi, ent_hi);
+        if constexpr (SPLIT)
+            emit_entries(lo, kp, below, run_lo, ent_lo);
     }
 }
 
@@ -319,9 +421,11 @@ size_t scan_partials_len(uint32_t m) { return (m + kScanChunk - 1) / kScanChunk 
 hipError_t launch_cull(spamm_plan *p, hipStream_t s)
 {
     const int d = p->depth;
+    const bool split = p->precision != SPAMM_PREC_FP32;
     const double *nA = p->A->norms, *nB = p->B->norms;
-    hipLaunchKernelGGL(cull_root, dim3(1), dim3(64), 0, s, nA, nB, p->T2, p->rowptr + p->rp_off[0],
-                       p->list[0], p->browptr, p->bent, p->leafK, d == 0 ? 1 : 0);
+    hipLaunchKernelGGL(cull_root, dim3(1), dim3(64), 0, s, nA, nB, p->T2, split ? p->L2 : 0.0,
+                       p->rowptr + p->rp_off[0], p->list[0], p->browptr, p->bent, p->browptr_lo,
+                       p->bent_lo, p->leafK, d == 0 ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || d == 0)
         return e;
@@ -333,29 +437,44 @@ hipError_t launch_cull(spamm_plan *p, hipStream_t s)
         const dim3 grid((np + 3) / 4), block(256);
         if (t < d) {
             uint32_t *crow = p->rowptr + p->rp_off[t];
-            hipLaunchKernelGGL(cull_count<false>, grid, block, 0, s, tA, tB, p->T2, prow, plist, np,
-                               p->counts);
+            hipLaunchKernelGGL(cull_count, grid, block, 0, s, tA, tB, p->T2, prow, plist, np, p->counts);
             if ((e = hipGetLastError()) != hipSuccess)
                 return e;
             if ((e = launch_scan(p->counts, 4 * np, crow, p->partials, s)) != hipSuccess)
                 return e;
-            hipLaunchKernelGGL(cull_emit<false>, grid, block, 0, s, tA, tB, p->T2, prow, plist, np,
+            hipLaunchKernelGGL(cull_emit, grid, block, 0, s, tA, tB, p->T2, prow, plist, np,
                                (const uint32_t *)crow, p->list[t & 1]);
-        } else {
-            hipLaunchKernelGGL(cull_count<true>, grid, block, 0, s, tA, tB, p->T2, prow, plist, np,
-                               p->counts);
+        } else if (!split) {
+            hipLaunchKernelGGL(cull_count_leaf<false>, grid, block, 0, s, tA, tB, p->T2, 0.0, prow,
+                               plist, np, p->counts);
             hipLaunchKernelGGL(reduce_tasks, dim3(1), dim3(1024), 0, s, p->counts + np, np, p->leafK);
             if ((e = hipGetLastError()) != hipSuccess)
                 return e;
             if ((e = launch_scan(p->counts, np, p->browptr, p->partials, s)) != hipSuccess)
                 return e;
-            hipLaunchKernelGGL(cull_emit<true>, grid, block, 0, s, tA, tB, p->T2, prow, plist, np,
-                               (const uint32_t *)p->browptr, p->bent);
+            hipLaunchKernelGGL(cull_emit_leaf<false>, grid, block, 0, s, tA, tB, p->T2, 0.0, prow,
+                               plist, np, (const uint32_t *)p->browptr, p->bent,
+                               (const uint32_t *)nullptr, (uint32_t *)nullptr);
+        } else {
+            hipLaunchKernelGGL(cull_count_leaf<true>, grid, block, 0, s, tA, tB, p->T2, p->L2, prow,
+                               plist, np, p->counts);
+            hipLaunchKernelGGL(reduce_tasks, dim3(1), dim3(1024), 0, s, p->counts + np, np, p->leafK);
+            hipLaunchKernelGGL(reduce_tasks, dim3(1), dim3(1024), 0, s, p->counts + 3 * np, np,
+                               p->leafK + 1);
+            if ((e = hipGetLastError()) != hipSuccess)
+                return e;
+            if ((e = launch_scan(p->counts, np, p->browptr, p->partials, s)) != hipSuccess)
+                return e;
+            if ((e = launch_scan(p->counts + 2 * np, np, p->browptr_lo, p->partials, s)) != hipSuccess)
+                return e;
+            hipLaunchKernelGGL(cull_emit_leaf<true>, grid, block, 0, s, tA, tB, p->T2, p->L2, prow,
+                               plist, np, (const uint32_t *)p->browptr, p->bent,
+                               (const uint32_t *)p->browptr_lo, p->bent_lo);
         }
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
-    return hipSuccess;
+    return hipSuccess;   // leafK[0] = HIGH leaf products, leafK[1] = LOW ones (split)
 }
 
 }  // namespace spamm

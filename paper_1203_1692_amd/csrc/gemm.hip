@@ -32,6 +32,7 @@ namespace spamm {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void global_void_t;
 
@@ -123,13 +124,51 @@ __device__ inline void panel_mfma16(const float *__restrict__ Ap, const float *_
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[s], acc, 0, 0, 0);
 }
 
+// Store (or add to) one output leaf held in MFMA result layout, cropped to n.
+template <int B>
+__device__ inline void write_leaf32(const floatx16 (&acc)[B / 32][B / 32], int64_t row0,
+                                    int64_t col0, int64_t n, float *__restrict__ C, int accumulate,
+                                    int lane)
+{
+#pragma unroll
+    for (int i = 0; i < B / 32; ++i)
+#pragma unroll
+        for (int j = 0; j < B / 32; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int64_t row = row0 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int64_t col = col0 + j * 32 + (lane & 31);
+                if (row < n && col < n) {
+                    float *c = C + row * n + col;
+                    *c = accumulate ? *c + acc[i][j][v] : acc[i][j][v];
+                }
+            }
+}
+
+__device__ inline void write_leaf16(const floatx4 &acc, int64_t row0, int64_t col0, int64_t n,
+                                    float *__restrict__ C, int accumulate, int lane)
+{
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t row = row0 + 4 * (lane >> 4) + v;
+        const int64_t col = col0 + (lane & 15);
+        if (row < n && col < n) {
+            float *c = C + row * n + col;
+            *c = accumulate ? *c + acc[v] : acc[v];
+        }
+    }
+}
+
+// accumulate = 0: every output leaf of the block is written (zeros where
+// nothing lands).  accumulate = 1: blocks without entries are left alone and
+// the others add their products to C (second pass of a split product).
 template <int B>
 __global__ __launch_bounds__(256) void leaf_gemm(const float *__restrict__ tA,
                                                  const float *__restrict__ tBT,
                                                  const uint32_t *__restrict__ browptr,
                                                  const uint32_t *__restrict__ bent,
                                                  uint32_t nblocks, int single, int64_t n,
-                                                 float *__restrict__ C)
+                                                 float *__restrict__ C, int accumulate)
 {
     using L = LeafLayout<B>;
     using S = GemmShape<B>;
@@ -158,6 +197,8 @@ __global__ __launch_bounds__(256) void leaf_gemm(const float *__restrict__ tA,
     }
 
     const uint32_t e0 = browptr[blk], e1 = browptr[blk + 1];
+    if (accumulate && e0 == e1)
+        return;
     const uint32_t T = (e1 - e0) * NP;                  // stages of this block
     if (T > 0)
         stage_issue<B>(bent[e0], 0, tA, tBT, I0, J0, smem, w, lane);
@@ -184,31 +225,105 @@ __global__ __launch_bounds__(256) void leaf_gemm(const float *__restrict__ tA,
     if (single && w != 0)
         return;
     const int64_t row0 = (int64_t)(I0 + qa) * B, col0 = (int64_t)(J0 + qb) * B;
-    if constexpr (B >= 32) {
+    if constexpr (B >= 32)
+        write_leaf32<B>(acc, row0, col0, n, C, accumulate, lane);
+    else
+        write_leaf16(acc16, row0, col0, n, C, accumulate, lane);
+}
+
+// ---------------------------------------------------------------------------
+// LOW products (split precision): BF16 operands, FP32 accumulation, on
+// v_mfma_f32_32x32x16_bf16 (A operand of lane l: A[l%32][k0 + 8(l/32) + i],
+// i < 8; B operand B[k0 + 8(l/32) + i][l%32]).  Same ownership and
+// double-buffered direct-to-LDS staging as the FP32 kernel; a stage is the
+// four whole BF16 leaves of one entry (Leaf16Layout, 8 KB each at n_b = 64).
+// This kernel writes every output leaf (zeros where no LOW product lands);
+// the FP32 kernel then adds the HIGH products of the blocks that have any.
+template <int B>
+__global__ __launch_bounds__(256) void leaf_gemm_bf16(const uint16_t *__restrict__ tA16,
+                                                      const uint16_t *__restrict__ tBT16,
+                                                      const uint32_t *__restrict__ browptr,
+                                                      const uint32_t *__restrict__ bent,
+                                                      uint32_t nblocks, int single, int64_t n,
+                                                      float *__restrict__ C)
+{
+    using L = Leaf16Layout<B>;
+    constexpr int LEAF = B * B;            // bf16 per leaf
+    constexpr int MB = B / 32;
+    extern __shared__ uint16_t smem16[];   // 2 stages x {A_2I, A_2I+1, B_2J, B_2J+1}
+    const uint32_t blk = xcd_block(blockIdx.x, nblocks);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int qa = w >> 1, qb = w & 1;
+    uint32_t I0 = 0, J0 = 0;
+    if (!single) {
+        I0 = 2 * lin_row(blk);
+        J0 = 2 * lin_col(blk);
+    }
+    floatx16 acc[MB][MB];
 #pragma unroll
-        for (int i = 0; i < MB; ++i)
+    for (int i = 0; i < MB; ++i)
 #pragma unroll
-            for (int j = 0; j < MB; ++j)
+        for (int j = 0; j < MB; ++j)
+            acc[i][j] = floatx16{0};
+
+    auto issue = [&](uint32_t ent, uint16_t *dst) {
+        const uint32_t users = w < 2 ? (0x3u << (2 * w)) : (0x5u << (w - 2));
+        const uint32_t k = ent & 0xFFFFu, mask = ent >> 16;
+        if ((mask & users) == 0)
+            return;
+        const uint16_t *leaf = w < 2 ? tA16 + (int64_t)lin_index(I0 + w, k) * LEAF
+                                     : tBT16 + (int64_t)lin_index(k, J0 + (w - 2)) * LEAF;
+        const uint16_t *src = leaf + 8 * lane;
+        uint16_t *d = dst + w * LEAF;
 #pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    const int64_t row = row0 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                    const int64_t col = col0 + j * 32 + (lane & 31);
-                    if (row < n && col < n)
-                        C[row * n + col] = acc[i][j][v];
-                }
-    } else {
+        for (int i = 0; i < LEAF / 512; ++i)
+            __builtin_amdgcn_global_load_lds((global_void_t *)(src + 512 * i), (lds_void_t *)(d + 512 * i),
+                                             16, 0, 0);
+    };
+
+    const uint32_t e0 = browptr[blk], e1 = browptr[blk + 1];
+    const uint32_t T = e1 - e0;
+    if (T > 0)
+        issue(bent[e0], smem16);
+    const int r = lane & 31, h = lane >> 5;
+    for (uint32_t t = 0; t < T; ++t) {
+        const uint32_t ent = bent[e0 + t];
+        __builtin_amdgcn_s_waitcnt(0x0F70);             // vmcnt(0)
+        __syncthreads();
+        if (t + 1 < T)
+            issue(bent[e0 + t + 1], smem16 + ((t + 1) & 1) * (4 * LEAF));
+        if ((ent >> (16 + w)) & 1u) {
+            const uint16_t *buf = smem16 + (t & 1) * (4 * LEAF);
+            const uint16_t *Ap = buf + qa * LEAF;
+            const uint16_t *Bp = buf + (2 + qb) * LEAF;
+            bf16x8 av[B / 16][MB], bv[B / 16][MB];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t row = row0 + 4 * (lane >> 4) + v;
-            const int64_t col = col0 + (lane & 15);
-            if (row < n && col < n)
-                C[row * n + col] = acc16[v];
+            for (int st = 0; st < B / 16; ++st) {
+                const int c = 16 * st + 8 * h;
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+                    av[st][i] = *reinterpret_cast<const bf16x8 *>(Ap + L::index(i * 32 + r, c));
+#pragma unroll
+                for (int j = 0; j < MB; ++j)
+                    bv[st][j] = *reinterpret_cast<const bf16x8 *>(Bp + L::index(j * 32 + r, c));
+            }
+#pragma unroll
+            for (int st = 0; st < B / 16; ++st)
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < MB; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[st][i], bv[st][j],
+                                                                            acc[i][j], 0, 0, 0);
         }
     }
+    if (single && w != 0)
+        return;
+    write_leaf32<B>(acc, (int64_t)(I0 + qa) * B, (int64_t)(J0 + qb) * B, n, C, 0, lane);
 }
 
 template <int B>
-static hipError_t launch_gemm_b(const spamm_plan *p, float *C, hipStream_t s)
+static hipError_t launch_gemm_b(const spamm_plan *p, float *C, hipStream_t s, int accumulate)
 {
     using S = GemmShape<B>;
     static bool attr_set = false;
@@ -221,16 +336,50 @@ static hipError_t launch_gemm_b(const spamm_plan *p, float *C, hipStream_t s)
     }
     hipLaunchKernelGGL(leaf_gemm<B>, dim3((uint32_t)p->nblocks), dim3(256), S::kLds, s,
                        p->A->tiles, p->B->tilesT, p->browptr, p->bent, (uint32_t)p->nblocks,
+                       p->depth == 0 ? 1 : 0, p->n, C, accumulate);
+    return hipGetLastError();
+}
+
+template <int B>
+static hipError_t launch_gemm_bf16_b(const spamm_plan *p, float *C, hipStream_t s)
+{
+    constexpr size_t lds = sizeof(uint16_t) * 2 * 4 * B * B;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)leaf_gemm_bf16<B>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(leaf_gemm_bf16<B>, dim3((uint32_t)p->nblocks), dim3(256), lds, s,
+                       p->A->tiles16, p->B->tilesT16, p->browptr_lo, p->bent_lo, (uint32_t)p->nblocks,
                        p->depth == 0 ? 1 : 0, p->n, C);
     return hipGetLastError();
 }
 
+// FP32: one pass.  Split: the BF16 pass writes C, then the FP32 pass adds the
+// HIGH products (k ascending inside each class).
 hipError_t launch_gemm(const spamm_plan *p, float *C, hipStream_t s)
 {
+    if (p->precision == SPAMM_PREC_FP32) {
+        switch (p->leaf) {
+        case 16: return launch_gemm_b<16>(p, C, s, 0);
+        case 32: return launch_gemm_b<32>(p, C, s, 0);
+        case 64: return launch_gemm_b<64>(p, C, s, 0);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    hipError_t e;
     switch (p->leaf) {
-    case 16: return launch_gemm_b<16>(p, C, s);
-    case 32: return launch_gemm_b<32>(p, C, s);
-    case 64: return launch_gemm_b<64>(p, C, s);
+    case 32:
+        if ((e = launch_gemm_bf16_b<32>(p, C, s)) != hipSuccess)
+            return e;
+        return launch_gemm_b<32>(p, C, s, 1);
+    case 64:
+        if ((e = launch_gemm_bf16_b<64>(p, C, s)) != hipSuccess)
+            return e;
+        return launch_gemm_b<64>(p, C, s, 1);
     default: return hipErrorInvalidValue;
     }
 }

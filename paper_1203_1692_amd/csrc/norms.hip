@@ -40,6 +40,14 @@ __device__ inline float4 load_row4(const float *__restrict__ A, int64_t n, int64
     return v;
 }
 
+// Four consecutive elements of a row, rounded to BF16 (8 bytes, aligned).
+__device__ inline void store_bf16x4(uint16_t *dst, float4 v)
+{
+    const uint32_t lo = (uint32_t)to_bf16(v.x) | ((uint32_t)to_bf16(v.y) << 16);
+    const uint32_t hi = (uint32_t)to_bf16(v.z) | ((uint32_t)to_bf16(v.w) << 16);
+    *reinterpret_cast<uint2 *>(dst) = make_uint2(lo, hi);
+}
+
 // Block of 4 waves = the 4 children of one tier-(d-1) node (linear indices
 // 4p .. 4p+3); the block also writes that parent's norm when `parent` != null.
 // Each leaf is stored twice in LeafLayout: as is (left-operand copy) and
@@ -49,6 +57,8 @@ template <int B, int VEC>
 __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ A, int64_t n,
                                                       float *__restrict__ tiles,
                                                       float *__restrict__ tilesT,
+                                                      uint16_t *__restrict__ tiles16,
+                                                      uint16_t *__restrict__ tilesT16,
                                                       double *__restrict__ leaf_norm,
                                                       double *__restrict__ parent,
                                                       uint32_t ntiles)
@@ -80,6 +90,10 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
             const int e = 256 * m + 4 * lane;
             const int r = e / B, c = e % B;
             *reinterpret_cast<float4 *>(dst + L::index(r, c)) = v[m];
+            if constexpr (B >= 32) {
+                if (tiles16 != nullptr)
+                    store_bf16x4(tiles16 + (int64_t)l * (B * B) + Leaf16Layout<B>::index(r, c), v[m]);
+            }
             float *o = tr + r * P + c;
             o[0] = v[m].x;
             o[1] = v[m].y;
@@ -111,6 +125,10 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
             const float4 t = make_float4(tr[(ct + 0) * P + rt], tr[(ct + 1) * P + rt],
                                          tr[(ct + 2) * P + rt], tr[(ct + 3) * P + rt]);
             *reinterpret_cast<float4 *>(dstT + L::index(rt, ct)) = t;
+            if constexpr (B >= 32) {
+                if (tilesT16 != nullptr)
+                    store_bf16x4(tilesT16 + (int64_t)l * (B * B) + Leaf16Layout<B>::index(rt, ct), t);
+            }
         }
     }
     if (parent != nullptr) {
@@ -136,8 +154,9 @@ __global__ __launch_bounds__(1024) void norm_pyramid(double *__restrict__ norms,
 }
 
 template <int B, int VEC>
-static hipError_t launch_leaf_v(const float *A, int64_t n, float *tiles, float *tilesT, double *leaf,
-                                double *parent, uint32_t ntiles, hipStream_t s)
+static hipError_t launch_leaf_v(const float *A, int64_t n, float *tiles, float *tilesT,
+                                uint16_t *t16, uint16_t *tT16, double *leaf, double *parent,
+                                uint32_t ntiles, hipStream_t s)
 {
     constexpr size_t lds = sizeof(float) * 4 * B * (B + 1);
     static bool attr_set = false;
@@ -149,23 +168,25 @@ static hipError_t launch_leaf_v(const float *A, int64_t n, float *tiles, float *
         attr_set = true;
     }
     hipLaunchKernelGGL((leaf_norm_pack<B, VEC>), dim3((ntiles + 3) / 4), dim3(256), lds, s, A, n,
-                       tiles, tilesT, leaf, parent, ntiles);
+                       tiles, tilesT, t16, tT16, leaf, parent, ntiles);
     return hipGetLastError();
 }
 
 template <int B>
 static hipError_t launch_leaf(const float *A, int64_t n, int vec, float *tiles, float *tilesT,
-                              double *leaf, double *parent, uint32_t ntiles, hipStream_t s)
+                              uint16_t *t16, uint16_t *tT16, double *leaf, double *parent,
+                              uint32_t ntiles, hipStream_t s)
 {
     if (vec == 4)
-        return launch_leaf_v<B, 4>(A, n, tiles, tilesT, leaf, parent, ntiles, s);
+        return launch_leaf_v<B, 4>(A, n, tiles, tilesT, t16, tT16, leaf, parent, ntiles, s);
     if (vec == 2)
-        return launch_leaf_v<B, 2>(A, n, tiles, tilesT, leaf, parent, ntiles, s);
-    return launch_leaf_v<B, 1>(A, n, tiles, tilesT, leaf, parent, ntiles, s);
+        return launch_leaf_v<B, 2>(A, n, tiles, tilesT, t16, tT16, leaf, parent, ntiles, s);
+    return launch_leaf_v<B, 1>(A, n, tiles, tilesT, t16, tT16, leaf, parent, ntiles, s);
 }
 
 hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *tiles,
-                        float *tilesT, double *norms, hipStream_t s)
+                        float *tilesT, uint16_t *t16, uint16_t *tT16, double *norms,
+                        hipStream_t s)
 {
     const uintptr_t addr = reinterpret_cast<uintptr_t>(A);
     const int vec = (n % 4 == 0 && addr % 16 == 0) ? 4 : (n % 2 == 0 && addr % 8 == 0) ? 2 : 1;
@@ -174,9 +195,9 @@ hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *t
     double *parent = depth >= 1 ? norms + tier_offset(depth - 1) : nullptr;
     hipError_t e;
     switch (leaf) {
-    case 16: e = launch_leaf<16>(A, n, vec, tiles, tilesT, leafn, parent, ntiles, s); break;
-    case 32: e = launch_leaf<32>(A, n, vec, tiles, tilesT, leafn, parent, ntiles, s); break;
-    case 64: e = launch_leaf<64>(A, n, vec, tiles, tilesT, leafn, parent, ntiles, s); break;
+    case 16: e = launch_leaf<16>(A, n, vec, tiles, tilesT, nullptr, nullptr, leafn, parent, ntiles, s); break;
+    case 32: e = launch_leaf<32>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent, ntiles, s); break;
+    case 64: e = launch_leaf<64>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent, ntiles, s); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess || depth < 2)
