@@ -39,6 +39,8 @@ extern "C" {
 #define SPAMM_E_HIP        -4   /* a HIP runtime call failed (see last_error) */
 #define SPAMM_E_RANGE      -5   /* host buffer too small / size over a limit  */
 #define SPAMM_E_MISMATCH   -6   /* operands of different n or leaf size       */
+#define SPAMM_E_BUSY       -7   /* server queue full; submit again later      */
+#define SPAMM_PENDING       1   /* server request queued or running (poll)    */
 
 /* ---- precision of the leaf products (split precision) -------------------- */
 #define SPAMM_PREC_FP32        0   /* every kept product in FP32 (MFMA, FP32 accumulation) */
@@ -197,6 +199,95 @@ int spamm_multiply_ex(const spamm_tree *A, const spamm_tree *B, double tau, floa
  * `stats` as for spamm_multiply_ex (NULL: no timing, no synchronization). */
 int spamm_multiply_opts(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
                         float *C, void *stream, spamm_stats *stats);
+
+/* ---- serving: continuous batching of products and squaring chains -------- */
+
+/*
+ * A server owns one scheduler thread, `max_slots` streams and a device-memory
+ * budget on the device current at spamm_server_create.  Requests wait in a
+ * FIFO queue; the scheduler admits the head whenever a slot is free and the
+ * request's footprint (trees + task arena, spamm_request_footprint) fits in
+ * what the admitted requests leave of the budget.  An admitted request's
+ * trees and cull run on its slot's stream, overlapping other requests' work;
+ * the leaf products of every request whose cull has been enqueued are
+ * gathered into one batched leaf-GEMM launch (up to 16 requests of one leaf
+ * size per launch, uneven n, tau and precision allowed) on the server's
+ * GEMM stream, so small products share the chip.  A squaring chain (the
+ * matrix square is the central step of density-matrix purification,
+ * Sec. IV.B) stays on the device: each step's product is rebuilt into a tree
+ * and squared again without a host round trip.
+ *
+ * Determinism: every output leaf is computed by one workgroup with a fixed k
+ * order, so a request's C is bit-identical whether it runs alone or in a mix.
+ */
+typedef struct spamm_server spamm_server;
+
+typedef struct spamm_request {
+    const float *A;      /* device, n x n FP32 row-major (lda = n)                    */
+    const float *B;      /* device n x n, or NULL for B = A; must be NULL or A when    */
+                         /* chain_len > 0                                             */
+    float *C;            /* device, n x n FP32 row-major output; may alias A          */
+    int64_t n;           /* order, >= 1                                                */
+    int32_t leaf;        /* n_b in {16, 32, 64} (32 or 64 for split precision)         */
+    int32_t precision;   /* SPAMM_PREC_FP32 or SPAMM_PREC_SPLIT_BF16                   */
+    double tau;          /* SpAMM tolerance of every product (as spamm_symbolic)      */
+    double low_tol;      /* split precision: LOW threshold (as spamm_opts)            */
+    int32_t chain_len;   /* 0: C = A B.  L in 1..64: X_0 = A, X_{s+1} = X_s X_s under  */
+                         /* tau (each X_s rebuilt into a tree), C = X_L               */
+} spamm_request;
+
+typedef struct spamm_result {
+    int32_t status;      /* SPAMM_OK, or the request's error (e.g. SPAMM_E_NONFINITE    */
+                         /* when an input or an intermediate square holds NaN/Inf)   */
+    int32_t steps;       /* products performed (1, or chain_len)                      */
+    int64_t tasks;       /* leaf products over all steps                              */
+    int64_t tasks_low;   /* of which LOW                                              */
+    double  flops;       /* 2 n_b^3 tasks                                             */
+    double  queue_ms;    /* submit -> admission (host clock)                          */
+    double  latency_ms;  /* submit -> completion seen by the scheduler (host clock)   */
+} spamm_result;
+
+/*
+ * Create a server on the current device.  hbm_budget: bytes of device memory
+ * the admitted requests may hold at once (> 0).  max_slots: requests admitted
+ * at once, 1..64.  Errors: SPAMM_E_INVAL, SPAMM_E_NOMEM, SPAMM_E_HIP.
+ */
+int spamm_server_create(size_t hbm_budget, int32_t max_slots, spamm_server **out);
+
+/*
+ * Device bytes the server reserves for a request while it is admitted; also
+ * validates it (host only, no device call).  Errors: SPAMM_E_INVAL (null
+ * pointers, n < 1, bad leaf, precision, tau, low_tol, chain_len outside 0..64,
+ * a chain with B not NULL and not A, split precision with leaf 16),
+ * SPAMM_E_RANGE (more than 1024 leaves per dimension).
+ */
+int spamm_request_footprint(const spamm_request *req, size_t *bytes);
+
+/*
+ * Queue a request (thread-safe, non-blocking).  The caller keeps A, B and C
+ * alive and unwritten-by-others until the request is done; A and B must
+ * already hold their values (the server's streams do not wait on the
+ * caller's).  *ticket receives a positive id.  Errors: as
+ * spamm_request_footprint; SPAMM_E_NOMEM when the footprint exceeds the
+ * whole budget (it could never be admitted); SPAMM_E_BUSY when 65536
+ * requests are already queued; SPAMM_E_INVAL after destroy began.
+ */
+int spamm_submit(spamm_server *server, const spamm_request *req, uint64_t *ticket);
+
+/*
+ * Non-blocking, thread-safe.  Returns SPAMM_PENDING while the request is
+ * queued or running; otherwise fills *out (may be NULL), forgets the ticket
+ * and returns SPAMM_OK (the request's own status is out->status).
+ * SPAMM_E_INVAL for an unknown or already collected ticket.
+ */
+int spamm_poll(spamm_server *server, uint64_t ticket, spamm_result *out);
+
+/*
+ * Stop the server: queued requests that were not admitted are dropped
+ * (their C is not written), admitted ones run to completion, then the
+ * scheduler thread, streams and memory are released.  NULL is a no-op.
+ */
+int spamm_server_destroy(spamm_server *server);
 
 /* ---- errors --------------------------------------------------------------- */
 const char *spamm_strerror(int code);

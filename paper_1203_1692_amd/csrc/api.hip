@@ -8,11 +8,12 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <new>
 #include <vector>
 
-#include "common.hpp"
+#include "runtime.hpp"
 
 namespace spamm {
 hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *tiles,
@@ -26,8 +27,10 @@ size_t scan_partials_len(uint32_t m);
 using namespace spamm;
 
 namespace {
-
 thread_local char g_err[512] = "";
+}  // namespace
+
+namespace spamm {
 
 int fail(int code, const char *fmt, ...)
 {
@@ -73,7 +76,13 @@ int prepare_device(int *dev)
     return SPAMM_OK;
 }
 
-int depth_of(int64_t n, int32_t leaf, int32_t *d, int64_t *np)
+double now_us()
+{
+    using namespace std::chrono;
+    return (double)duration_cast<nanoseconds>(steady_clock::now().time_since_epoch()).count() * 1e-3;
+}
+
+static int depth_of(int64_t n, int32_t leaf, int32_t *d, int64_t *np)
 {
     int32_t t = 0;
     int64_t p = leaf;
@@ -89,33 +98,61 @@ int depth_of(int64_t n, int32_t leaf, int32_t *d, int64_t *np)
     return SPAMM_OK;
 }
 
-}  // namespace
+// Device buffers of a plan of depth d (worst case: every candidate kept).
+struct PlanSizes {
+    int64_t rp_off[kMaxDepth + 1];
+    size_t rowptr, list[2], counts, partials, browptr, bent;
+};
 
-extern "C" {
-
-const char *spamm_strerror(int code)
+static PlanSizes plan_sizes(int d)
 {
-    switch (code) {
-    case SPAMM_OK: return "success";
-    case SPAMM_E_INVAL: return "invalid argument";
-    case SPAMM_E_NONFINITE: return "non-finite value in input matrix";
-    case SPAMM_E_NOMEM: return "out of device memory";
-    case SPAMM_E_HIP: return "HIP runtime error";
-    case SPAMM_E_RANGE: return "size out of range";
-    case SPAMM_E_MISMATCH: return "operand shapes differ";
-    default: return "unknown status";
+    PlanSizes z{};
+    int64_t rp = 0;
+    for (int t = 0; t < d; ++t) {
+        z.rp_off[t] = rp;
+        rp += (int64_t(1) << (2 * t)) + 1;
     }
+    z.rp_off[d] = rp;
+    int64_t cap_list[2] = {1, 1};
+    for (int t = 0; t < d; ++t)
+        cap_list[t & 1] = std::max(cap_list[t & 1], int64_t(1) << (3 * t));
+    const int64_t nblocks = d == 0 ? 1 : (int64_t(1) << (2 * (d - 1)));
+    const int64_t ncounts = nblocks;
+    const int64_t cap_bent = d == 0 ? 1 : nblocks * (int64_t(1) << d);
+    z.rowptr = sizeof(uint32_t) * (size_t)std::max<int64_t>(rp, 2);
+    z.list[0] = sizeof(uint32_t) * (size_t)cap_list[0];
+    z.list[1] = sizeof(uint32_t) * (size_t)cap_list[1];
+    z.counts = sizeof(uint32_t) * 4 * (size_t)ncounts;
+    z.partials = sizeof(uint32_t) * scan_partials_len((uint32_t)std::max<int64_t>(ncounts, 1));
+    z.browptr = sizeof(uint32_t) * (size_t)(nblocks + 1);
+    z.bent = sizeof(uint32_t) * (size_t)cap_bent;
+    return z;
 }
 
-const char *spamm_last_error(void) { return g_err; }
-
-int spamm_build_tree(const float *A, int64_t n, int32_t leaf, void *stream, spamm_tree **out)
+size_t plan_device_bytes(int depth, bool split)
 {
-    return spamm_build_tree_ex(A, n, leaf, 0u, stream, out);
+    const PlanSizes z = plan_sizes(depth);
+    size_t b = z.rowptr + z.list[0] + z.list[1] + z.counts + z.partials + z.browptr + z.bent +
+               2 * sizeof(uint64_t);
+    if (split)
+        b += z.browptr + z.bent;
+    return b;
 }
 
-int spamm_build_tree_ex(const float *A, int64_t n, int32_t leaf, uint32_t flags, void *stream,
-                        spamm_tree **out)
+size_t tree_device_bytes(int64_t n, int32_t leaf, bool bf16)
+{
+    int32_t d = 0;
+    int64_t p = leaf;
+    while (p < n) {
+        p *= 2;
+        d += 1;
+    }
+    const size_t tile = sizeof(float) * (size_t)p * (size_t)p;
+    return 2 * tile + (bf16 ? tile : 0) + sizeof(double) * (size_t)tier_offset(d + 1);
+}
+
+int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hipStream_t s,
+                     double *root_dst, spamm_tree **out)
 {
     if (out == nullptr)
         return fail(SPAMM_E_INVAL, "out is NULL");
@@ -139,7 +176,6 @@ int spamm_build_tree_ex(const float *A, int64_t n, int32_t leaf, uint32_t flags,
     int dev;
     if ((rc = prepare_device(&dev)))
         return rc;
-    hipStream_t s = (hipStream_t)stream;
     const int64_t N = int64_t(1) << d;
     const size_t tile_bytes = sizeof(float) * (size_t)(N * N) * (size_t)leaf * (size_t)leaf;
     const size_t norm_bytes = sizeof(double) * (size_t)tier_offset(d + 1);
@@ -164,11 +200,57 @@ int spamm_build_tree_ex(const float *A, int64_t n, int32_t leaf, uint32_t flags,
         e = hipMallocAsync((void **)&t->norms, norm_bytes, s);
     if (e == hipSuccess)
         e = launch_build(A, n, leaf, d, t->tiles, t->tilesT, t->tiles16, t->tilesT16, t->norms, s);
+    if (e == hipSuccess && root_dst != nullptr)
+        e = hipMemcpyAsync(root_dst, t->norms, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "tree build");
+        spamm_tree_free(t);
+        return rc;
+    }
+    *out = t;
+    return SPAMM_OK;
+}
+
+}  // namespace spamm
+
+extern "C" {
+
+const char *spamm_strerror(int code)
+{
+    switch (code) {
+    case SPAMM_OK: return "success";
+    case SPAMM_E_INVAL: return "invalid argument";
+    case SPAMM_E_NONFINITE: return "non-finite value in input matrix";
+    case SPAMM_E_NOMEM: return "out of device memory";
+    case SPAMM_E_HIP: return "HIP runtime error";
+    case SPAMM_E_RANGE: return "size out of range";
+    case SPAMM_E_MISMATCH: return "operand shapes differ";
+    case SPAMM_E_BUSY: return "server queue full";
+    case SPAMM_PENDING: return "request pending";
+    default: return "unknown status";
+    }
+}
+
+const char *spamm_last_error(void) { return g_err; }
+
+int spamm_build_tree(const float *A, int64_t n, int32_t leaf, void *stream, spamm_tree **out)
+{
+    return spamm_build_tree_ex(A, n, leaf, 0u, stream, out);
+}
+
+int spamm_build_tree_ex(const float *A, int64_t n, int32_t leaf, uint32_t flags, void *stream,
+                        spamm_tree **out)
+{
+    if (out == nullptr)
+        return fail(SPAMM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
     double root = 0.0;
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(&root, t->norms, sizeof(double), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(s);
+    spamm_tree *t = nullptr;
+    int rc = tree_build_async(A, n, leaf, flags, s, &root, &t);
+    if (rc)
+        return rc;
+    hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         rc = hip_fail(e, "spamm_build_tree");
         spamm_tree_free(t);
@@ -350,31 +432,20 @@ int spamm_symbolic_ex(const spamm_tree *A, const spamm_tree *B, const spamm_opts
     const int d = p->depth;
     p->nblocks = d == 0 ? 1 : (int64_t(1) << (2 * (d - 1)));
 
-    // capacities (worst case: every candidate kept)
-    int64_t rp = 0;
-    for (int t = 0; t < d; ++t) {
-        p->rp_off[t] = rp;
-        rp += (int64_t(1) << (2 * t)) + 1;
-    }
-    p->rp_off[d] = rp;
-    int64_t cap_list[2] = {1, 1};
-    for (int t = 0; t < d; ++t)
-        cap_list[t & 1] = std::max(cap_list[t & 1], int64_t(1) << (3 * t));
-    const int64_t ncounts = d == 0 ? 1 : (int64_t(1) << (2 * (d - 1)));
-    const int64_t cap_bent = d == 0 ? 1 : p->nblocks * (int64_t(1) << d);
-    const size_t npart = scan_partials_len((uint32_t)std::max<int64_t>(ncounts, 1));
-
+    const PlanSizes z = plan_sizes(d);
+    for (int t = 0; t <= d; ++t)
+        p->rp_off[t] = z.rp_off[t];
     struct Req { void **dst; size_t bytes; } reqs[] = {
-        {(void **)&p->rowptr, sizeof(uint32_t) * (size_t)std::max<int64_t>(rp, 2)},
-        {(void **)&p->list[0], sizeof(uint32_t) * (size_t)cap_list[0]},
-        {(void **)&p->list[1], sizeof(uint32_t) * (size_t)cap_list[1]},
-        {(void **)&p->counts, sizeof(uint32_t) * 4 * (size_t)ncounts},
-        {(void **)&p->partials, sizeof(uint32_t) * npart},
-        {(void **)&p->browptr, sizeof(uint32_t) * (size_t)(p->nblocks + 1)},
-        {(void **)&p->bent, sizeof(uint32_t) * (size_t)cap_bent},
+        {(void **)&p->rowptr, z.rowptr},
+        {(void **)&p->list[0], z.list[0]},
+        {(void **)&p->list[1], z.list[1]},
+        {(void **)&p->counts, z.counts},
+        {(void **)&p->partials, z.partials},
+        {(void **)&p->browptr, z.browptr},
+        {(void **)&p->bent, z.bent},
         {(void **)&p->leafK, 2 * sizeof(uint64_t)},
-        {(void **)&p->browptr_lo, split ? sizeof(uint32_t) * (size_t)(p->nblocks + 1) : 0},
-        {(void **)&p->bent_lo, split ? sizeof(uint32_t) * (size_t)cap_bent : 0},
+        {(void **)&p->browptr_lo, split ? z.browptr : 0},
+        {(void **)&p->bent_lo, split ? z.bent : 0},
     };
     for (auto &r : reqs) {
         if (r.bytes == 0)

@@ -123,6 +123,30 @@ __device__ inline int lane_id() { return __lane_id(); }
 
 __device__ inline uint64_t lanes_below() { return (uint64_t(1) << lane_id()) - 1; }
 
+// One product in a (possibly batched) leaf-GEMM launch: grid blocks
+// [block0, block0 + nblocks) work on this job.  tA / tBT point to FP32
+// leaves (LeafLayout) for the FP32 kernel and to BF16 leaves
+// (Leaf16Layout) for the BF16 kernel.
+struct GemmJob {
+    const void *tA;
+    const void *tBT;
+    const uint32_t *browptr;
+    const uint32_t *bent;
+    float *C;
+    int64_t n;
+    uint32_t nblocks, block0;
+    int32_t single;        // depth 0: one leaf
+    int32_t accumulate;    // add to C (second pass of a split product)
+};
+
+constexpr int kMaxJobs = 16;
+
+struct GemmJobs {          // passed by value as a kernel argument
+    int32_t njobs;
+    uint32_t nblocks;      // total grid
+    GemmJob job[kMaxJobs];
+};
+
 }  // namespace spamm
 
 // ---- internal handles ------------------------------------------------------

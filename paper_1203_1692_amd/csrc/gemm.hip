@@ -162,19 +162,32 @@ __device__ inline void write_leaf16(const floatx4 &acc, int64_t row0, int64_t co
 // accumulate = 0: every output leaf of the block is written (zeros where
 // nothing lands).  accumulate = 1: blocks without entries are left alone and
 // the others add their products to C (second pass of a split product).
+// The job of grid block `bid` (jobs sorted by block0; at most kMaxJobs).
+__device__ inline int job_of(const GemmJobs &jobs, uint32_t bid)
+{
+    int j = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxJobs; ++i)
+        j += (i < jobs.njobs && bid >= jobs.job[i].block0) ? 1 : 0;
+    return j;
+}
+
 template <int B>
-__global__ __launch_bounds__(256) void leaf_gemm(const float *__restrict__ tA,
-                                                 const float *__restrict__ tBT,
-                                                 const uint32_t *__restrict__ browptr,
-                                                 const uint32_t *__restrict__ bent,
-                                                 uint32_t nblocks, int single, int64_t n,
-                                                 float *__restrict__ C, int accumulate)
+__global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
 {
     using L = LeafLayout<B>;
     using S = GemmShape<B>;
     constexpr int NP = L::kPanels;
     extern __shared__ float smem[];       // 2 stages x {A_2I, A_2I+1, B_2J, B_2J+1} panels
-    const uint32_t blk = xcd_block(blockIdx.x, nblocks);
+    const GemmJob &job = jobs.job[job_of(jobs, blockIdx.x)];
+    const float *__restrict__ tA = (const float *)job.tA;
+    const float *__restrict__ tBT = (const float *)job.tBT;
+    const uint32_t *__restrict__ browptr = job.browptr;
+    const uint32_t *__restrict__ bent = job.bent;
+    float *__restrict__ C = job.C;
+    const int64_t n = job.n;
+    const int single = job.single, accumulate = job.accumulate;
+    const uint32_t blk = xcd_block(blockIdx.x - job.block0, job.nblocks);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int qa = w >> 1, qb = w & 1;
     uint32_t I0 = 0, J0 = 0;
@@ -240,18 +253,21 @@ __global__ __launch_bounds__(256) void leaf_gemm(const float *__restrict__ tA,
 // This kernel writes every output leaf (zeros where no LOW product lands);
 // the FP32 kernel then adds the HIGH products of the blocks that have any.
 template <int B>
-__global__ __launch_bounds__(256) void leaf_gemm_bf16(const uint16_t *__restrict__ tA16,
-                                                      const uint16_t *__restrict__ tBT16,
-                                                      const uint32_t *__restrict__ browptr,
-                                                      const uint32_t *__restrict__ bent,
-                                                      uint32_t nblocks, int single, int64_t n,
-                                                      float *__restrict__ C)
+__global__ __launch_bounds__(256) void leaf_gemm_bf16(const GemmJobs jobs)
 {
     using L = Leaf16Layout<B>;
     constexpr int LEAF = B * B;            // bf16 per leaf
     constexpr int MB = B / 32;
     extern __shared__ uint16_t smem16[];   // 2 stages x {A_2I, A_2I+1, B_2J, B_2J+1}
-    const uint32_t blk = xcd_block(blockIdx.x, nblocks);
+    const GemmJob &job = jobs.job[job_of(jobs, blockIdx.x)];
+    const uint16_t *__restrict__ tA16 = (const uint16_t *)job.tA;
+    const uint16_t *__restrict__ tBT16 = (const uint16_t *)job.tBT;
+    const uint32_t *__restrict__ browptr = job.browptr;
+    const uint32_t *__restrict__ bent = job.bent;
+    float *__restrict__ C = job.C;
+    const int64_t n = job.n;
+    const int single = job.single;
+    const uint32_t blk = xcd_block(blockIdx.x - job.block0, job.nblocks);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int qa = w >> 1, qb = w & 1;
     uint32_t I0 = 0, J0 = 0;
@@ -323,7 +339,7 @@ __global__ __launch_bounds__(256) void leaf_gemm_bf16(const uint16_t *__restrict
 }
 
 template <int B>
-static hipError_t launch_gemm_b(const spamm_plan *p, float *C, hipStream_t s, int accumulate)
+static hipError_t launch_fp32(const GemmJobs &jobs, hipStream_t s)
 {
     using S = GemmShape<B>;
     static bool attr_set = false;
@@ -334,14 +350,12 @@ static hipError_t launch_gemm_b(const spamm_plan *p, float *C, hipStream_t s, in
             return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(leaf_gemm<B>, dim3((uint32_t)p->nblocks), dim3(256), S::kLds, s,
-                       p->A->tiles, p->B->tilesT, p->browptr, p->bent, (uint32_t)p->nblocks,
-                       p->depth == 0 ? 1 : 0, p->n, C, accumulate);
+    hipLaunchKernelGGL(leaf_gemm<B>, dim3(jobs.nblocks), dim3(256), S::kLds, s, jobs);
     return hipGetLastError();
 }
 
 template <int B>
-static hipError_t launch_gemm_bf16_b(const spamm_plan *p, float *C, hipStream_t s)
+static hipError_t launch_bf16(const GemmJobs &jobs, hipStream_t s)
 {
     constexpr size_t lds = sizeof(uint16_t) * 2 * 4 * B * B;
     static bool attr_set = false;
@@ -352,36 +366,61 @@ static hipError_t launch_gemm_bf16_b(const spamm_plan *p, float *C, hipStream_t 
             return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(leaf_gemm_bf16<B>, dim3((uint32_t)p->nblocks), dim3(256), lds, s,
-                       p->A->tiles16, p->B->tilesT16, p->browptr_lo, p->bent_lo, (uint32_t)p->nblocks,
-                       p->depth == 0 ? 1 : 0, p->n, C);
+    hipLaunchKernelGGL(leaf_gemm_bf16<B>, dim3(jobs.nblocks), dim3(256), lds, s, jobs);
     return hipGetLastError();
+}
+
+// One batched launch of the FP32 (bf16 = false) or BF16 leaf GEMM over the
+// jobs' blocks; all jobs share the leaf size.
+hipError_t launch_gemm_jobs(int leaf, bool bf16, const GemmJobs &jobs, hipStream_t s)
+{
+    if (jobs.njobs <= 0 || jobs.nblocks == 0)
+        return hipSuccess;
+    if (bf16) {
+        switch (leaf) {
+        case 32: return launch_bf16<32>(jobs, s);
+        case 64: return launch_bf16<64>(jobs, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (leaf) {
+    case 16: return launch_fp32<16>(jobs, s);
+    case 32: return launch_fp32<32>(jobs, s);
+    case 64: return launch_fp32<64>(jobs, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// The plan's jobs: FP32 pass (write, or accumulate after the BF16 pass).
+void plan_jobs(const spamm_plan *p, float *C, bool bf16, GemmJob &j)
+{
+    j.tA = bf16 ? (const void *)p->A->tiles16 : (const void *)p->A->tiles;
+    j.tBT = bf16 ? (const void *)p->B->tilesT16 : (const void *)p->B->tilesT;
+    j.browptr = bf16 ? p->browptr_lo : p->browptr;
+    j.bent = bf16 ? p->bent_lo : p->bent;
+    j.C = C;
+    j.n = p->n;
+    j.nblocks = (uint32_t)p->nblocks;
+    j.block0 = 0;
+    j.single = p->depth == 0 ? 1 : 0;
+    j.accumulate = (!bf16 && p->precision != SPAMM_PREC_FP32) ? 1 : 0;
 }
 
 // FP32: one pass.  Split: the BF16 pass writes C, then the FP32 pass adds the
 // HIGH products (k ascending inside each class).
 hipError_t launch_gemm(const spamm_plan *p, float *C, hipStream_t s)
 {
-    if (p->precision == SPAMM_PREC_FP32) {
-        switch (p->leaf) {
-        case 16: return launch_gemm_b<16>(p, C, s, 0);
-        case 32: return launch_gemm_b<32>(p, C, s, 0);
-        case 64: return launch_gemm_b<64>(p, C, s, 0);
-        default: return hipErrorInvalidValue;
-        }
-    }
+    GemmJobs jobs{};
+    jobs.njobs = 1;
+    jobs.nblocks = (uint32_t)p->nblocks;
     hipError_t e;
-    switch (p->leaf) {
-    case 32:
-        if ((e = launch_gemm_bf16_b<32>(p, C, s)) != hipSuccess)
+    if (p->precision != SPAMM_PREC_FP32) {
+        plan_jobs(p, C, true, jobs.job[0]);
+        if ((e = launch_gemm_jobs(p->leaf, true, jobs, s)) != hipSuccess)
             return e;
-        return launch_gemm_b<32>(p, C, s, 1);
-    case 64:
-        if ((e = launch_gemm_bf16_b<64>(p, C, s)) != hipSuccess)
-            return e;
-        return launch_gemm_b<64>(p, C, s, 1);
-    default: return hipErrorInvalidValue;
     }
+    plan_jobs(p, C, false, jobs.job[0]);
+    return launch_gemm_jobs(p->leaf, false, jobs, s);
 }
 
 }  // namespace spamm

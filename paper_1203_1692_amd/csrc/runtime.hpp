@@ -1,0 +1,35 @@
+// Internal runtime pieces shared by the one-call API (api.hip) and the
+// serving loop (server.hip).  Not part of the C ABI.
+#pragma once
+
+#include <stddef.h>
+
+#include "common.hpp"
+
+namespace spamm {
+
+// Error plumbing: set the calling thread's message, return code.
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+
+// Current device, with the stream-ordered memory pool prepared.
+int prepare_device(int *dev);
+
+// Validates and enqueues a tree build on `s` without synchronizing; the
+// root squared norm is copied to *root_dst (pinned host memory, may be null)
+// asynchronously.  On error nothing stays allocated.
+int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hipStream_t s,
+                     double *root_dst, spamm_tree **out);
+
+// Device bytes one tree / one plan of depth d needs (admission control).
+size_t tree_device_bytes(int64_t n, int32_t leaf, bool bf16);
+size_t plan_device_bytes(int depth, bool split);
+
+// Leaf GEMM launches (gemm.hip).
+void plan_jobs(const spamm_plan *p, float *C, bool bf16, GemmJob &j);
+hipError_t launch_gemm_jobs(int leaf, bool bf16, const GemmJobs &jobs, hipStream_t s);
+
+// Steady clock in microseconds (request timestamps).
+double now_us();
+
+}  // namespace spamm
