@@ -247,6 +247,20 @@ typedef struct spamm_result {
     double  latency_ms;  /* submit -> completion seen by the scheduler (host clock)   */
 } spamm_result;
 
+/* Counters of a server since its creation (spamm_server_info). */
+typedef struct spamm_server_stats {
+    int64_t  admitted;           /* requests admitted                                */
+    int64_t  completed;          /* requests finished (any status)                   */
+    int64_t  queued;             /* requests waiting for admission now               */
+    int64_t  launches;           /* batched leaf-GEMM launch groups (BF16 + FP32)     */
+    int64_t  launched_products;  /* products over all launch groups                  */
+    int64_t  max_batch;          /* most products in one launch group                */
+    int64_t  peak_active;        /* most requests admitted at once                   */
+    uint64_t used;               /* footprint bytes held by admitted requests now    */
+    uint64_t peak_used;          /* most footprint bytes held at once                */
+    uint64_t budget;             /* hbm_budget                                       */
+} spamm_server_stats;
+
 /*
  * Create a server on the current device.  hbm_budget: bytes of device memory
  * the admitted requests may hold at once (> 0).  max_slots: requests admitted
@@ -281,6 +295,9 @@ int spamm_submit(spamm_server *server, const spamm_request *req, uint64_t *ticke
  * SPAMM_E_INVAL for an unknown or already collected ticket.
  */
 int spamm_poll(spamm_server *server, uint64_t ticket, spamm_result *out);
+
+/* Copy the server's counters (thread-safe). */
+int spamm_server_info(spamm_server *server, spamm_server_stats *out);
 
 /*
  * Stop the server: queued requests that were not admitted are dropped

@@ -1,7 +1,10 @@
 """MI355X-native SpAMM: quadtree norm build, tier-by-tier cull and a
-persistent FP32-MFMA leaf GEMM behind the C ABI of include/spamm.h."""
+persistent FP32-MFMA leaf GEMM behind the C ABI of include/spamm.h, plus a
+continuous-batching server for products and squaring chains."""
 from ._binding import (  # noqa: F401
-    HEADER, LIB_PATH, PREC_FP32, PREC_SPLIT_BF16, SPAMM_E_HIP, SPAMM_E_INVAL, SPAMM_E_MISMATCH, SPAMM_E_NOMEM,
-    SPAMM_E_NONFINITE, SPAMM_E_RANGE, SPAMM_OK, Plan, SpammError, Stats, Tree, build_tree,
-    Opts, header_functions, load, multiply, multiply_ex, relative_low_tol, strerror, symbolic,
+    HEADER, LIB_PATH, PREC_FP32, PREC_SPLIT_BF16, SPAMM_E_BUSY, SPAMM_E_HIP, SPAMM_E_INVAL,
+    SPAMM_E_MISMATCH, SPAMM_E_NOMEM, SPAMM_E_NONFINITE, SPAMM_E_RANGE, SPAMM_OK, SPAMM_PENDING,
+    Opts, Plan, Request, Result, Server, ServerStats, SpammError, Stats, Tree, build_tree,
+    header_functions, load, multiply, multiply_ex, relative_low_tol, request_footprint, strerror,
+    symbolic,
 )

@@ -24,6 +24,8 @@ SPAMM_E_NOMEM = -3
 SPAMM_E_HIP = -4
 SPAMM_E_RANGE = -5
 SPAMM_E_MISMATCH = -6
+SPAMM_E_BUSY = -7
+SPAMM_PENDING = 1
 
 PREC_FP32 = 0
 PREC_SPLIT_BF16 = 1
@@ -69,6 +71,32 @@ class Stats(ctypes.Structure):
         }
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("leaf", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("low_tol", ctypes.c_double),
+                ("chain_len", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("tasks", ctypes.c_int64), ("tasks_low", ctypes.c_int64),
+                ("flops", ctypes.c_double), ("queue_ms", ctypes.c_double),
+                ("latency_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("admitted", "completed", "queued", "launches",
+                                              "launched_products", "max_batch", "peak_active")] + \
+               [(k, ctypes.c_uint64) for k in ("used", "peak_used", "budget")]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 def header_functions() -> list:
     """Names of the functions declared in include/spamm.h."""
     text = open(HEADER).read()
@@ -107,6 +135,12 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "spamm_plan_free": [vp],
         "spamm_multiply": [vp, vp, dbl, vp, vp],
         "spamm_multiply_ex": [vp, vp, dbl, vp, vp, ctypes.POINTER(Stats)],
+        "spamm_server_create": [sz, i32, pp],
+        "spamm_request_footprint": [ctypes.POINTER(Request), ctypes.POINTER(sz)],
+        "spamm_submit": [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)],
+        "spamm_poll": [vp, ctypes.c_uint64, ctypes.POINTER(Result)],
+        "spamm_server_info": [vp, ctypes.POINTER(ServerStats)],
+        "spamm_server_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -292,3 +326,102 @@ def multiply_ex(A: Tree, B: Tree, tau: float, C, stream=None, precision: int = P
                                       ctypes.c_void_p(C.data_ptr()), _stream(stream),
                                       ctypes.byref(st)), "spamm_multiply_opts")
     return st.as_dict()
+
+
+# ---- serving -----------------------------------------------------------------
+
+def _request(A_ptr, B_ptr, C_ptr, n, leaf, tau, precision, low_tol, chain_len) -> Request:
+    return Request(A_ptr, B_ptr, C_ptr, int(n), int(leaf), int(precision), float(tau),
+                   float(low_tol), int(chain_len))
+
+
+def request_footprint(n: int, leaf: int, tau: float = 0.0, precision: int = PREC_FP32,
+                      low_tol: float = 0.0, chain_len: int = 0, distinct_b: bool = False) -> int:
+    """Device bytes a server reserves for such a request (host-only check;
+    the placeholder pointers are never dereferenced)."""
+    r = _request(1, 2 if distinct_b else None, 3, n, leaf, tau, precision, low_tol, chain_len)
+    out = ctypes.c_size_t()
+    _check(load().spamm_request_footprint(ctypes.byref(r), ctypes.byref(out)),
+           "spamm_request_footprint")
+    return out.value
+
+
+class Server:
+    """Continuous-batching SpAMM server on the current device.
+
+    submit() queues C = A B (or a chain of `chain_len` squarings of A) and
+    returns a ticket; poll() returns None while it runs, else the result
+    dict.  The tensors of a request are kept referenced until its result has
+    been collected.
+    """
+
+    def __init__(self, hbm_budget: int, max_slots: int = 8):
+        h = ctypes.c_void_p()
+        _check(load().spamm_server_create(int(hbm_budget), int(max_slots), ctypes.byref(h)),
+               "spamm_server_create")
+        self._h = h
+        self._keep = {}
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("server has been destroyed")
+        return self._h
+
+    def submit(self, A, C, tau: float, leaf: int, B=None, precision: int = PREC_FP32,
+               low_tol: float = 0.0, chain_len: int = 0, sync: bool = True) -> int:
+        """Queue a request; `sync` first waits for the current stream so that
+        A and B hold their values when the server's streams read them."""
+        import torch
+        _device_matrix(A, "A")
+        _device_matrix(C, "C")
+        if B is not None:
+            _device_matrix(B, "B")
+        for t in (C, B):
+            if t is not None and t.shape != A.shape:
+                raise ValueError("A, B and C must have the same shape")
+        if sync:
+            torch.cuda.current_stream().synchronize()
+        r = _request(A.data_ptr(), None if B is None else B.data_ptr(), C.data_ptr(), A.shape[0],
+                     leaf, tau, precision, low_tol, chain_len)
+        t = ctypes.c_uint64()
+        _check(load().spamm_submit(self.handle, ctypes.byref(r), ctypes.byref(t)), "spamm_submit")
+        self._keep[t.value] = (A, B, C)
+        return t.value
+
+    def poll(self, ticket: int):
+        res = Result()
+        rc = load().spamm_poll(self.handle, int(ticket), ctypes.byref(res))
+        if rc == SPAMM_PENDING:
+            return None
+        _check(rc, "spamm_poll")
+        self._keep.pop(int(ticket), None)
+        return res.as_dict()
+
+    def wait(self, ticket: int, timeout: float = 60.0) -> dict:
+        import time
+        t0 = time.monotonic()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.monotonic() - t0 > timeout:
+                raise TimeoutError(f"request {ticket} still pending after {timeout} s")
+            time.sleep(50e-6)
+
+    def info(self) -> dict:
+        st = ServerStats()
+        _check(load().spamm_server_info(self.handle, ctypes.byref(st)), "spamm_server_info")
+        return st.as_dict()
+
+    def destroy(self):
+        if self._h is not None:
+            _check(load().spamm_server_destroy(self._h), "spamm_server_destroy")
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

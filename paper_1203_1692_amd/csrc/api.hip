@@ -82,7 +82,7 @@ double now_us()
     return (double)duration_cast<nanoseconds>(steady_clock::now().time_since_epoch()).count() * 1e-3;
 }
 
-static int depth_of(int64_t n, int32_t leaf, int32_t *d, int64_t *np)
+int tree_depth(int64_t n, int32_t leaf, int32_t *d, int64_t *np)
 {
     int32_t t = 0;
     int64_t p = leaf;
@@ -170,7 +170,7 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
         return fail(SPAMM_E_INVAL, "BF16 leaf copies need leaf 32 or 64");
     int32_t d;
     int64_t np;
-    int rc = depth_of(n, leaf, &d, &np);
+    int rc = tree_depth(n, leaf, &d, &np);
     if (rc)
         return rc;
     int dev;

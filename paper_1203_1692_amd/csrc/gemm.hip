@@ -342,14 +342,11 @@ template <int B>
 static hipError_t launch_fp32(const GemmJobs &jobs, hipStream_t s)
 {
     using S = GemmShape<B>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)leaf_gemm<B>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::kLds);
-        if (e != hipSuccess)
-            return e;
-        attr_set = true;
-    }
+    // once per process (thread-safe static initialization)
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)leaf_gemm<B>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::kLds);
+    if (attr != hipSuccess)
+        return attr;
     hipLaunchKernelGGL(leaf_gemm<B>, dim3(jobs.nblocks), dim3(256), S::kLds, s, jobs);
     return hipGetLastError();
 }
@@ -358,14 +355,10 @@ template <int B>
 static hipError_t launch_bf16(const GemmJobs &jobs, hipStream_t s)
 {
     constexpr size_t lds = sizeof(uint16_t) * 2 * 4 * B * B;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)leaf_gemm_bf16<B>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess)
-            return e;
-        attr_set = true;
-    }
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)leaf_gemm_bf16<B>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess)
+        return attr;
     hipLaunchKernelGGL(leaf_gemm_bf16<B>, dim3(jobs.nblocks), dim3(256), lds, s, jobs);
     return hipGetLastError();
 }

@@ -159,14 +159,11 @@ static hipError_t launch_leaf_v(const float *A, int64_t n, float *tiles, float *
                                 uint32_t ntiles, hipStream_t s)
 {
     constexpr size_t lds = sizeof(float) * 4 * B * (B + 1);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)leaf_norm_pack<B, VEC>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess)
-            return e;
-        attr_set = true;
-    }
+    // once per process (thread-safe static initialization)
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)leaf_norm_pack<B, VEC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess)
+        return attr;
     hipLaunchKernelGGL((leaf_norm_pack<B, VEC>), dim3((ntiles + 3) / 4), dim3(256), lds, s, A, n,
                        tiles, tilesT, t16, tT16, leaf, parent, ntiles);
     return hipGetLastError();

@@ -12,6 +12,10 @@ namespace spamm {
 int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 
+// Depth d and padded order n_p = n_b 2^d of an n x n operand (SPAMM_E_RANGE
+// past kMaxDepth tiers).
+int tree_depth(int64_t n, int32_t leaf, int32_t *d, int64_t *np);
+
 // Current device, with the stream-ordered memory pool prepared.
 int prepare_device(int *dev);
 

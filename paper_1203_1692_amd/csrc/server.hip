@@ -1,0 +1,560 @@
+// Serving loop: FIFO admission by device-memory footprint and free slots,
+// one stream per slot for tree builds and culls, batched leaf-GEMM launches
+// across requests on one GEMM stream, squaring chains kept on the device.
+//
+// Stream protocol of one admitted request (slot stream ss, GEMM stream gs):
+//   ss: build tree(s) -> root norm to pinned host -> cull -> task counts to
+//       pinned host -> record ev_cull
+//   gs: wait ev_cull (of every request in the batch) -> [BF16 pass] -> FP32
+//       pass -> record ev_done
+//   chain step s -> s+1, enqueued at once after the GEMM:
+//   ss: wait ev_done -> free plan and tree of X_s -> build the tree of
+//       X_{s+1} from C -> cull -> ... (no host round trip)
+// The host only watches ev_done of a request's last product.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "runtime.hpp"
+
+using namespace spamm;
+
+namespace {
+
+constexpr int kMaxSlots = 64;
+constexpr int kMaxChain = 64;
+constexpr size_t kMaxQueue = 65536;
+// GEMM batches allowed on the GEMM stream at once; requests culled while
+// the stream is full wait and join the next batch.
+constexpr int kInflightBatches = 2;
+
+struct Pinned {                    // per-slot readbacks (host-visible)
+    double root[kMaxChain][2];     // ||X_s||_F^2 of each step's tree(s)
+    uint64_t K[kMaxChain][2];      // HIGH / LOW leaf products of each step
+};
+
+struct Job {
+    uint64_t ticket;
+    spamm_request rq;
+    size_t bytes;
+    double t_submit;
+};
+
+struct Active {
+    Job job;
+    int slot = -1;
+    int steps = 1, step = 0;
+    bool split = false, distinctB = false;
+    spamm_tree *tA = nullptr, *tB = nullptr;
+    spamm_plan *plan = nullptr;
+    bool culled = false;           // this step's cull enqueued, its GEMM not yet
+    bool final = false;            // nothing more to enqueue; done once ev_done passes
+    int status = SPAMM_OK;
+    double t_admit = 0.0;
+};
+
+bool bad_tol(double v) { return !(v >= 0.0) || isinf(v) || (v > 0.0 && v < 1e-150); }
+
+int check_request(const spamm_request *r, size_t *bytes)
+{
+    if (r == nullptr)
+        return fail(SPAMM_E_INVAL, "request is NULL");
+    if (r->A == nullptr || r->C == nullptr)
+        return fail(SPAMM_E_INVAL, "A and C must be device pointers");
+    if (r->n < 1)
+        return fail(SPAMM_E_INVAL, "n = %lld < 1", (long long)r->n);
+    if (r->leaf != 16 && r->leaf != 32 && r->leaf != 64)
+        return fail(SPAMM_E_INVAL, "leaf = %d not in {16, 32, 64}", r->leaf);
+    if (r->precision != SPAMM_PREC_FP32 && r->precision != SPAMM_PREC_SPLIT_BF16)
+        return fail(SPAMM_E_INVAL, "unknown precision %d", r->precision);
+    const bool split = r->precision == SPAMM_PREC_SPLIT_BF16;
+    if (split && r->leaf == 16)
+        return fail(SPAMM_E_INVAL, "split precision needs leaf 32 or 64");
+    if (bad_tol(r->tau))
+        return fail(SPAMM_E_INVAL, "tau = %g must be 0 or in [1e-150, inf)", r->tau);
+    if (split && bad_tol(r->low_tol))
+        return fail(SPAMM_E_INVAL, "low_tol = %g must be 0 or in [1e-150, inf)", r->low_tol);
+    if (r->chain_len < 0 || r->chain_len > kMaxChain)
+        return fail(SPAMM_E_INVAL, "chain_len = %d outside 0..%d", r->chain_len, kMaxChain);
+    if (r->chain_len > 0 && r->B != nullptr && r->B != r->A)
+        return fail(SPAMM_E_INVAL, "a squaring chain takes B = NULL (or B = A)");
+    int32_t d;
+    int64_t np;
+    int rc = tree_depth(r->n, r->leaf, &d, &np);
+    if (rc)
+        return rc;
+    const bool distinctB = r->B != nullptr && r->B != r->A;
+    *bytes = tree_device_bytes(r->n, r->leaf, split) * (distinctB ? 2 : 1) +
+             plan_device_bytes(d, split);
+    return SPAMM_OK;
+}
+
+}  // namespace
+
+struct spamm_server {
+    int device = -1;
+    size_t budget = 0;
+    int nslots = 0;
+    hipStream_t gemm = nullptr;
+    hipStream_t ss[kMaxSlots] = {};
+    hipEvent_t ev_cull[kMaxSlots] = {}, ev_done[kMaxSlots] = {};
+    Pinned *pin = nullptr;
+    std::deque<hipEvent_t> inflight;     // batch events on the GEMM stream
+    std::vector<hipEvent_t> spare;       // idle batch events
+
+    // shared with submit / poll (guarded by mu)
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Job> queue;
+    std::unordered_set<uint64_t> live;   // queued or admitted
+    std::unordered_map<uint64_t, spamm_result> done;
+    size_t used = 0;
+    spamm_server_stats st{};
+    bool busy[kMaxSlots] = {};
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+
+    // scheduler thread only
+    std::vector<Active> active;
+    std::thread worker;
+};
+
+namespace {
+
+// Enqueue the trees and the cull of the request's current step on its slot
+// stream.  Step 0 reads A (and B); step s > 0 reads X_s from C.
+int start_step(spamm_server *S, Active &a)
+{
+    hipStream_t ss = S->ss[a.slot];
+    Pinned &P = S->pin[a.slot];
+    const spamm_request &r = a.job.rq;
+    const uint32_t flags = a.split ? SPAMM_TREE_BF16 : 0u;
+    P.root[a.step][1] = 0.0;
+    P.K[a.step][1] = 0;
+    int rc = tree_build_async(a.step == 0 ? r.A : r.C, r.n, r.leaf, flags, ss,
+                              &P.root[a.step][0], &a.tA);
+    if (rc)
+        return rc;
+    if (a.step == 0 && a.distinctB) {
+        if ((rc = tree_build_async(r.B, r.n, r.leaf, flags, ss, &P.root[0][1], &a.tB)))
+            return rc;
+    } else {
+        a.tB = a.tA;
+    }
+    spamm_opts o;
+    o.tau = r.tau;
+    o.precision = r.precision;
+    o.low_tol = a.split ? r.low_tol : 0.0;
+    if ((rc = spamm_symbolic_ex(a.tA, a.tB, &o, ss, &a.plan)))
+        return rc;
+    hipError_t e = hipMemcpyAsync(P.K[a.step], a.plan->leafK, (a.split ? 2 : 1) * sizeof(uint64_t),
+                                  hipMemcpyDeviceToHost, ss);
+    if (e == hipSuccess)
+        e = hipEventRecord(S->ev_cull[a.slot], ss);
+    if (e != hipSuccess)
+        return hip_fail(e, "server step");
+    a.culled = true;
+    return SPAMM_OK;
+}
+
+// Release the step's plan and trees, stream-ordered after its GEMM.
+void release_step(spamm_server *S, Active &a)
+{
+    hipStream_t ss = S->ss[a.slot];
+    hipStreamWaitEvent(ss, S->ev_done[a.slot], 0);
+    spamm_plan_free(a.plan);
+    if (a.tB != nullptr && a.tB != a.tA)
+        spamm_tree_free(a.tB);
+    spamm_tree_free(a.tA);
+    a.plan = nullptr;
+    a.tA = a.tB = nullptr;
+}
+
+// After the GEMM of step s was enqueued: queue step s+1 or mark final.
+void advance(spamm_server *S, Active &a)
+{
+    a.culled = false;
+    if (a.step + 1 >= a.steps) {
+        a.final = true;
+        return;
+    }
+    release_step(S, a);
+    a.step += 1;
+    int rc = start_step(S, a);
+    if (rc) {
+        a.status = rc;
+        a.final = true;
+    }
+}
+
+// Gather every culled request into batched launches on the GEMM stream.
+// Returns true if anything was launched.
+bool launch_batches(spamm_server *S)
+{
+    while (!S->inflight.empty() && hipEventQuery(S->inflight.front()) == hipSuccess) {
+        S->spare.push_back(S->inflight.front());
+        S->inflight.pop_front();
+    }
+    bool any = false;
+    std::vector<size_t> ready;
+    for (size_t i = 0; i < S->active.size(); ++i)
+        if (S->active[i].culled)
+            ready.push_back(i);
+    while (!ready.empty() && (int)S->inflight.size() < kInflightBatches) {
+        // one batch: up to kMaxJobs requests of the first ready request's leaf size
+        const int leaf = S->active[ready[0]].job.rq.leaf;
+        std::vector<size_t> batch, rest;
+        for (size_t i : ready)
+            (S->active[i].job.rq.leaf == leaf && (int)batch.size() < kMaxJobs ? batch : rest)
+                .push_back(i);
+        ready.swap(rest);
+        GemmJobs lo{}, hi{};
+        hipError_t e = hipSuccess;
+        for (size_t i : batch) {
+            Active &a = S->active[i];
+            if (e == hipSuccess)
+                e = hipStreamWaitEvent(S->gemm, S->ev_cull[a.slot], 0);
+            if (a.split) {
+                GemmJob &j = lo.job[lo.njobs++];
+                plan_jobs(a.plan, a.job.rq.C, true, j);
+                j.block0 = lo.nblocks;
+                lo.nblocks += j.nblocks;
+            }
+            GemmJob &j = hi.job[hi.njobs++];
+            plan_jobs(a.plan, a.job.rq.C, false, j);
+            j.block0 = hi.nblocks;
+            hi.nblocks += j.nblocks;
+        }
+        if (e == hipSuccess && lo.njobs > 0)
+            e = launch_gemm_jobs(leaf, true, lo, S->gemm);
+        if (e == hipSuccess)
+            e = launch_gemm_jobs(leaf, false, hi, S->gemm);
+        hipEvent_t bev = S->spare.back();
+        if (e == hipSuccess)
+            e = hipEventRecord(bev, S->gemm);
+        if (e == hipSuccess) {
+            S->spare.pop_back();
+            S->inflight.push_back(bev);
+            std::lock_guard<std::mutex> lock(S->mu);
+            S->st.launches += 1;
+            S->st.launched_products += (int64_t)batch.size();
+            S->st.max_batch = std::max<int64_t>(S->st.max_batch, (int64_t)batch.size());
+        }
+        for (size_t i : batch) {
+            Active &a = S->active[i];
+            hipError_t f = e == hipSuccess ? hipEventRecord(S->ev_done[a.slot], S->gemm) : e;
+            if (f != hipSuccess) {
+                // nothing further is enqueued for this request; its resources
+                // are released once the GEMM stream has drained
+                a.status = hip_fail(f, "batched leaf GEMM");
+                a.culled = false;
+                a.final = true;
+                hipStreamSynchronize(S->gemm);
+                continue;
+            }
+            advance(S, a);
+        }
+        any = true;
+    }
+    return any;
+}
+
+// Post the result of a request whose last GEMM has passed (or that failed).
+void finish(spamm_server *S, Active &a)
+{
+    release_step(S, a);
+    const Pinned &P = S->pin[a.slot];
+    spamm_result res;
+    memset(&res, 0, sizeof res);
+    res.status = a.status;
+    res.steps = a.step + 1;
+    if (res.status == SPAMM_OK) {
+        for (int s = 0; s <= a.step; ++s) {
+            const bool finite = isfinite(P.root[s][0]) && isfinite(P.root[s][1]);
+            if (!finite) {
+                res.status = SPAMM_E_NONFINITE;
+                break;
+            }
+            res.tasks += (int64_t)(P.K[s][0] + P.K[s][1]);
+            res.tasks_low += (int64_t)P.K[s][1];
+        }
+    }
+    const double b = a.job.rq.leaf;
+    res.flops = 2.0 * b * b * b * (double)res.tasks;
+    const double t = now_us();
+    res.queue_ms = (a.t_admit - a.job.t_submit) * 1e-3;
+    res.latency_ms = (t - a.job.t_submit) * 1e-3;
+    std::lock_guard<std::mutex> lock(S->mu);
+    S->done[a.job.ticket] = res;
+    S->st.completed += 1;
+    S->live.erase(a.job.ticket);
+    S->used -= a.job.bytes;
+    S->busy[a.slot] = false;
+}
+
+void scheduler(spamm_server *S)
+{
+    hipSetDevice(S->device);
+    int idle = 0;
+    for (;;) {
+        std::vector<Job> admitted;
+        std::vector<int> slots;
+        {
+            std::unique_lock<std::mutex> lock(S->mu);
+            if (S->active.empty() && S->queue.empty()) {
+                if (S->stopping)
+                    break;
+                S->cv.wait(lock, [S] { return S->stopping || !S->queue.empty(); });
+                continue;
+            }
+            while (!S->queue.empty() && S->used + S->queue.front().bytes <= S->budget) {
+                int slot = -1;
+                for (int i = 0; i < S->nslots && slot < 0; ++i)
+                    if (!S->busy[i])
+                        slot = i;
+                if (slot < 0)
+                    break;
+                S->busy[slot] = true;
+                S->used += S->queue.front().bytes;
+                S->st.admitted += 1;
+                S->st.peak_used = std::max<uint64_t>(S->st.peak_used, S->used);
+                int64_t nb = 0;
+                for (int k = 0; k < S->nslots; ++k)
+                    nb += S->busy[k] ? 1 : 0;
+                S->st.peak_active = std::max<int64_t>(S->st.peak_active, nb);
+                admitted.push_back(S->queue.front());
+                slots.push_back(slot);
+                S->queue.pop_front();
+            }
+        }
+        bool progress = !admitted.empty();
+        for (size_t i = 0; i < admitted.size(); ++i) {
+            Active a;
+            a.job = admitted[i];
+            a.slot = slots[i];
+            a.steps = std::max(1, a.job.rq.chain_len);
+            a.split = a.job.rq.precision == SPAMM_PREC_SPLIT_BF16;
+            a.distinctB = a.job.rq.B != nullptr && a.job.rq.B != a.job.rq.A;
+            a.t_admit = now_us();
+            int rc = start_step(S, a);
+            if (rc) {
+                a.status = rc;
+                a.culled = false;
+                a.final = true;
+            }
+            S->active.push_back(a);
+        }
+        progress |= launch_batches(S);
+        for (size_t i = 0; i < S->active.size();) {
+            Active &a = S->active[i];
+            bool over = false;
+            if (a.final) {
+                hipError_t q = hipEventQuery(S->ev_done[a.slot]);
+                if (q == hipSuccess) {
+                    over = true;
+                } else if (q != hipErrorNotReady) {
+                    a.status = hip_fail(q, "request completion");
+                    hipStreamSynchronize(S->gemm);
+                    over = true;
+                }
+            }
+            if (over) {
+                finish(S, a);
+                S->active.erase(S->active.begin() + (std::ptrdiff_t)i);
+                progress = true;
+            } else {
+                ++i;
+            }
+        }
+        if (progress) {
+            idle = 0;
+        } else if (++idle < 256) {
+            std::this_thread::yield();
+        } else {
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
+    }
+}
+
+void release_server(spamm_server *S)
+{
+    if (S->gemm)
+        hipStreamSynchronize(S->gemm);
+    for (int i = 0; i < S->nslots; ++i)
+        if (S->ss[i])
+            hipStreamSynchronize(S->ss[i]);
+    for (hipEvent_t e : S->inflight)
+        hipEventDestroy(e);
+    for (hipEvent_t e : S->spare)
+        hipEventDestroy(e);
+    for (int i = 0; i < kMaxSlots; ++i) {
+        if (S->ev_cull[i])
+            hipEventDestroy(S->ev_cull[i]);
+        if (S->ev_done[i])
+            hipEventDestroy(S->ev_done[i]);
+        if (S->ss[i])
+            hipStreamDestroy(S->ss[i]);
+    }
+    if (S->gemm)
+        hipStreamDestroy(S->gemm);
+    if (S->pin)
+        hipHostFree(S->pin);
+    delete S;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spamm_request_footprint(const spamm_request *req, size_t *bytes)
+{
+    if (bytes == nullptr)
+        return fail(SPAMM_E_INVAL, "bytes is NULL");
+    return check_request(req, bytes);
+}
+
+int spamm_server_create(size_t hbm_budget, int32_t max_slots, spamm_server **out)
+{
+    if (out == nullptr)
+        return fail(SPAMM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (hbm_budget == 0)
+        return fail(SPAMM_E_INVAL, "hbm_budget = 0");
+    if (max_slots < 1 || max_slots > kMaxSlots)
+        return fail(SPAMM_E_INVAL, "max_slots = %d outside 1..%d", max_slots, kMaxSlots);
+    int dev, rc;
+    if ((rc = prepare_device(&dev)))
+        return rc;
+    spamm_server *S = new (std::nothrow) spamm_server();
+    if (S == nullptr)
+        return fail(SPAMM_E_NOMEM, "host allocation failed");
+    S->device = dev;
+    S->budget = hbm_budget;
+    S->nslots = max_slots;
+    hipError_t e = hipStreamCreateWithFlags(&S->gemm, hipStreamNonBlocking);
+    for (int i = 0; i < max_slots && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&S->ss[i], hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&S->ev_cull[i], hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&S->ev_done[i], hipEventDisableTiming);
+    }
+    for (int i = 0; i < kInflightBatches && e == hipSuccess; ++i) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            S->spare.push_back(ev);
+    }
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&S->pin, sizeof(Pinned) * (size_t)max_slots, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "spamm_server_create");
+        release_server(S);
+        return rc;
+    }
+    memset(S->pin, 0, sizeof(Pinned) * (size_t)max_slots);
+    try {
+        S->worker = std::thread(scheduler, S);
+    } catch (...) {
+        release_server(S);
+        return fail(SPAMM_E_HIP, "could not start the scheduler thread");
+    }
+    *out = S;
+    return SPAMM_OK;
+}
+
+int spamm_submit(spamm_server *S, const spamm_request *req, uint64_t *ticket)
+{
+    if (S == nullptr || ticket == nullptr)
+        return fail(SPAMM_E_INVAL, "NULL argument");
+    size_t bytes = 0;
+    int rc = check_request(req, &bytes);
+    if (rc)
+        return rc;
+    if (bytes > S->budget)
+        return fail(SPAMM_E_NOMEM, "request needs %zu bytes, the server's budget is %zu", bytes,
+                    S->budget);
+    Job j;
+    j.rq = *req;
+    j.bytes = bytes;
+    j.t_submit = now_us();
+    {
+        std::lock_guard<std::mutex> lock(S->mu);
+        if (S->stopping)
+            return fail(SPAMM_E_INVAL, "server is shutting down");
+        if (S->queue.size() >= kMaxQueue)
+            return fail(SPAMM_E_BUSY, "%zu requests queued", S->queue.size());
+        j.ticket = S->next_ticket++;
+        S->queue.push_back(j);
+        S->live.insert(j.ticket);
+        *ticket = j.ticket;
+    }
+    S->cv.notify_one();
+    return SPAMM_OK;
+}
+
+int spamm_poll(spamm_server *S, uint64_t ticket, spamm_result *out)
+{
+    if (S == nullptr)
+        return fail(SPAMM_E_INVAL, "server is NULL");
+    std::lock_guard<std::mutex> lock(S->mu);
+    auto it = S->done.find(ticket);
+    if (it != S->done.end()) {
+        if (out)
+            *out = it->second;
+        S->done.erase(it);
+        return SPAMM_OK;
+    }
+    if (S->live.count(ticket))
+        return SPAMM_PENDING;
+    return fail(SPAMM_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
+}
+
+int spamm_server_info(spamm_server *S, spamm_server_stats *out)
+{
+    if (S == nullptr || out == nullptr)
+        return fail(SPAMM_E_INVAL, "NULL argument");
+    std::lock_guard<std::mutex> lock(S->mu);
+    *out = S->st;
+    out->queued = (int64_t)S->queue.size();
+    out->used = S->used;
+    out->budget = S->budget;
+    return SPAMM_OK;
+}
+
+int spamm_server_destroy(spamm_server *S)
+{
+    if (S == nullptr)
+        return SPAMM_OK;
+    {
+        std::lock_guard<std::mutex> lock(S->mu);
+        S->stopping = true;
+        for (const Job &j : S->queue)
+            S->live.erase(j.ticket);
+        S->queue.clear();
+    }
+    S->cv.notify_all();
+    if (S->worker.joinable())
+        S->worker.join();
+    const int dev = S->device;
+    int dev0 = -1;
+    hipGetDevice(&dev0);
+    if (dev0 != dev)
+        hipSetDevice(dev);
+    release_server(S);
+    if (dev0 >= 0 && dev0 != dev)
+        hipSetDevice(dev0);
+    return SPAMM_OK;
+}
+
+}  // extern "C"

@@ -26,10 +26,12 @@ def test_header_status_codes_match_binding():
     assert codes["SPAMM_E_HIP"] == sp.SPAMM_E_HIP
     assert codes["SPAMM_E_RANGE"] == sp.SPAMM_E_RANGE
     assert codes["SPAMM_E_MISMATCH"] == sp.SPAMM_E_MISMATCH
+    assert codes["SPAMM_E_BUSY"] == sp.SPAMM_E_BUSY
+    assert codes["SPAMM_PENDING"] == sp.SPAMM_PENDING
 
 
 def test_strerror_names_every_code():
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, 1):
         assert sp.strerror(code) != "unknown status"
     assert sp.strerror(-99) == "unknown status"
 

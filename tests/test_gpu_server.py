@@ -1,0 +1,316 @@
+"""The serving loop on the GPU.
+
+* every request's C is bit-identical whether it runs alone or in a mix of
+  uneven n, tau, leaf, precision and chain length (fixed owner and k order
+  per output leaf), and equal to the one-call API's result;
+* plain requests agree with the oracle (task counts exact, C within
+  1e-5 ||A||_F ||B||_F); a chain's last step agrees with the oracle run on
+  the previous step's matrix;
+* admission under a budget that holds one request at a time, rejection of a
+  request larger than the budget, destroy with requests pending, NaN input
+  and an overflowing chain reported as non-finite, poll semantics, several
+  submitting threads, and C aliasing A in a chain.
+"""
+import math
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+GiB = 1 << 30
+
+
+def decay(n, rate, seed, scale=1.0, sym=True):
+    rng = np.random.default_rng(seed)
+    i = np.arange(n)
+    A = rng.uniform(-1, 1, (n, n)) * np.exp(-rate * np.abs(i[:, None] - i[None, :]))
+    if sym:
+        A = np.triu(A) + np.triu(A, 1).T
+    return (scale * A).astype(np.float32)
+
+
+def gershgorin_scaled(A):
+    """X_0 = A / max_i sum_j |a_ij|: every power of X_0 stays bounded."""
+    return (A / np.abs(A.astype(np.float64)).sum(axis=1).max()).astype(np.float32)
+
+
+# (n, leaf, tau, precision, theta (relative LOW threshold), chain_len, distinct B, rate, seed)
+MIX = [
+    (100, 16, 1e-6, 0, 0.0, 0, False, 0.1, 1),
+    (257, 32, 1e-6, 1, 1e-3, 0, False, 0.1, 2),
+    (512, 32, 1e-8, 0, 0.0, 0, True, 0.05, 3),
+    (700, 64, 1e-6, 1, 1e-4, 0, False, 0.02, 4),
+    (1024, 32, 1e-6, 0, 0.0, 3, False, 0.1, 5),
+    (1024, 32, 1e-8, 1, 1e-4, 3, False, 0.2, 6),
+    (333, 32, 0.0, 0, 0.0, 0, True, 0.3, 7),
+    (1500, 64, 1e-4, 0, 0.0, 0, False, 0.05, 8),
+    (64, 64, 1e-6, 1, 1e-2, 2, False, 0.1, 9),
+    (2048, 32, 1e-6, 1, 1e-4, 0, False, 0.1, 10),
+    (900, 16, 1e-8, 0, 0.0, 2, False, 0.15, 11),
+    (512, 32, 1e-6, 0, 0.0, 0, False, 0.5, 12),
+    (1, 32, 0.0, 0, 0.0, 0, False, 0.1, 13),
+    (1200, 32, 1e-6, 1, 1e-3, 0, True, 0.08, 14),
+]
+
+
+def make_inputs(spec):
+    import torch
+    n, leaf, tau, prec, theta, chain, distinct, rate, seed = spec
+    A = decay(n, rate, seed)
+    if chain:
+        A = gershgorin_scaled(A)
+    B = decay(n, rate * 1.3, seed + 100, sym=False) if distinct else None
+    dA = torch.from_numpy(A).cuda()
+    dB = None if B is None else torch.from_numpy(B).cuda()
+    return A, B, dA, dB
+
+
+def low_tol_of(gpu, spec, dA, dB):
+    """Absolute LOW threshold theta ||A||_F ||B||_F from the trees' roots."""
+    n, leaf, tau, prec, theta, *_ = spec
+    if prec == 0:
+        return 0.0
+    tA = gpu.build_tree(dA, leaf)
+    tB = tA if dB is None else gpu.build_tree(dB, leaf)
+    return gpu.relative_low_tol(tA, tB, theta)
+
+
+def reference(gpu, spec, dA, dB, low):
+    """The same request through the one-call API, step by step."""
+    import torch
+    n, leaf, tau, prec, theta, chain, *_ = spec
+    bf = prec == gpu.PREC_SPLIT_BF16
+    X = dA
+    prev = None
+    tasks = 0
+    for _ in range(max(1, chain)):
+        tA = gpu.build_tree(X, leaf, bf16=bf)
+        tB = tA if (dB is None or chain) else gpu.build_tree(dB, leaf, bf16=bf)
+        C = torch.empty_like(dA)
+        st = gpu.multiply_ex(tA, tB, tau, C, precision=prec, low_tol=low)
+        tasks += st["tasks"]
+        prev, X = X, C
+    return X, prev, tasks
+
+
+@pytest.fixture(scope="module")
+def mix(gpu):
+    import torch
+    inputs = [make_inputs(s) for s in MIX]
+    lows = [low_tol_of(gpu, s, a[2], a[3]) for s, a in zip(MIX, inputs)]
+    refs = [reference(gpu, s, a[2], a[3], lo) for s, a, lo in zip(MIX, inputs, lows)]
+    torch.cuda.synchronize()
+
+    def submit(srv, i, C):
+        n, leaf, tau, prec, theta, chain, *_ = MIX[i]
+        return srv.submit(inputs[i][2], C, tau, leaf, B=inputs[i][3], precision=prec,
+                          low_tol=lows[i], chain_len=chain)
+
+    alone = []
+    srv = gpu.Server(8 * GiB, max_slots=8)
+    for i in range(len(MIX)):
+        C = torch.full_like(inputs[i][2], float("nan"))
+        res = srv.wait(submit(srv, i, C))
+        alone.append((C, res))
+    srv.destroy()
+
+    srv = gpu.Server(8 * GiB, max_slots=16)
+    outs = [torch.full_like(a[2], float("nan")) for a in inputs]
+    tickets = [submit(srv, i, outs[i]) for i in range(len(MIX))]
+    results = [srv.wait(t) for t in tickets]
+    info = srv.info()
+    srv.destroy()
+    return dict(inputs=inputs, lows=lows, refs=refs, alone=alone, outs=outs, results=results,
+                info=info)
+
+
+@pytest.mark.parametrize("i", range(len(MIX)))
+def test_same_alone_and_in_mix(mix, i):
+    import torch
+    C_alone, r_alone = mix["alone"][i]
+    C_mix, r_mix = mix["outs"][i], mix["results"][i]
+    assert r_alone["status"] == 0 and r_mix["status"] == 0
+    assert torch.equal(C_alone, C_mix)
+    assert r_alone["tasks"] == r_mix["tasks"] and r_alone["tasks_low"] == r_mix["tasks_low"]
+    assert r_mix["steps"] == max(1, MIX[i][5])
+    # and the one-call API gives the same bits
+    X, _, tasks = mix["refs"][i]
+    assert torch.equal(C_mix, X)
+    assert r_mix["tasks"] == tasks
+    assert r_mix["flops"] == 2.0 * MIX[i][1] ** 3 * r_mix["tasks"]
+    assert 0.0 <= r_mix["queue_ms"] <= r_mix["latency_ms"]
+
+
+def test_mix_was_batched(mix):
+    info = mix["info"]
+    assert info["admitted"] == info["completed"] == len(MIX)
+    assert info["max_batch"] > 1, info
+    assert info["launched_products"] == sum(max(1, s[5]) for s in MIX)
+    assert info["launches"] < info["launched_products"]
+    assert info["peak_active"] > 1
+    assert info["used"] == 0 and info["queued"] == 0
+
+
+@pytest.mark.parametrize("i", [i for i, s in enumerate(MIX) if s[0] <= 1200])
+def test_matches_oracle(mix, i):
+    n, leaf, tau, prec, theta, chain, *_ = MIX[i]
+    A, B = mix["inputs"][i][0], mix["inputs"][i][1]
+    low = mix["lows"][i]
+    if chain:
+        # the last squaring, on the previous step's matrix as the GPU holds it
+        prev = mix["refs"][i][1].cpu().numpy()
+        ref = oracle.spamm(prev, prev, leaf, tau, low_tol=low)
+        nrm = float(np.sqrt(oracle.norms(prev, leaf)[0][0, 0]))
+        bound = 1e-5 * nrm * nrm
+    else:
+        Bm = A if B is None else B
+        ref = oracle.spamm(A, Bm, leaf, tau, low_tol=low)
+        nA = math.sqrt(oracle.norms(A, leaf)[0][0, 0])
+        nB = math.sqrt(oracle.norms(Bm, leaf)[0][0, 0])
+        bound = 1e-5 * nA * nB
+        assert mix["results"][i]["tasks"] == ref.K
+        assert mix["results"][i]["tasks_low"] == ref.Klow
+    C = mix["outs"][i].cpu().numpy().astype(np.float64)
+    assert float(np.abs(C - ref.C).max()) <= bound
+
+
+def test_tiny_budget_one_at_a_time(gpu):
+    import torch
+    specs = [MIX[2], MIX[3], MIX[9], MIX[7]]
+    need = [gpu.request_footprint(s[0], s[1], s[2], s[3], 1e-3, s[5], s[6]) for s in specs]
+    srv = gpu.Server(max(need), max_slots=4)
+    try:
+        ins = [make_inputs(s) for s in specs]
+        refs = [reference(gpu, s, a[2], a[3], 1e-3 if s[3] else 0.0) for s, a in zip(specs, ins)]
+        outs = [torch.empty_like(a[2]) for a in ins]
+        tickets = [srv.submit(a[2], C, s[2], s[1], B=a[3], precision=s[3],
+                              low_tol=1e-3 if s[3] else 0.0, chain_len=s[5])
+                   for s, a, C in zip(specs, ins, outs)]
+        res = [srv.wait(t) for t in tickets]
+        info = srv.info()
+        assert all(r["status"] == 0 for r in res)
+        for C, ref in zip(outs, refs):
+            assert torch.equal(C, ref[0])
+        assert info["peak_used"] <= max(need)
+        assert info["peak_active"] < len(specs)
+        # a request larger than the whole budget is refused at submit
+        big = torch.zeros(4096, 4096, device="cuda")
+        with pytest.raises(gpu.SpammError) as ei:
+            srv.submit(big, torch.empty_like(big), 1e-6, 32)
+        assert ei.value.code == gpu.SPAMM_E_NOMEM
+    finally:
+        srv.destroy()
+
+
+def test_destroy_with_requests_pending(gpu):
+    import torch
+    A = torch.from_numpy(decay(1024, 0.1, 0)).cuda()
+    outs = [torch.empty_like(A) for _ in range(24)]
+    srv = gpu.Server(4 * GiB, max_slots=2)
+    for C in outs:
+        srv.submit(A, C, 1e-6, 32, chain_len=2)
+    srv.destroy()        # drops the queued ones, drains the admitted ones
+    srv = gpu.Server(4 * GiB, max_slots=2)
+    C = torch.empty_like(A)
+    r = srv.wait(srv.submit(A, C, 1e-6, 32))
+    srv.destroy()
+    t = gpu.build_tree(A, 32)
+    ref = torch.empty_like(A)
+    gpu.multiply_ex(t, t, 1e-6, ref)
+    assert r["status"] == 0 and torch.equal(C, ref)
+
+
+def test_nonfinite_input_and_overflowing_chain(gpu):
+    import torch
+    A = decay(300, 0.1, 3)
+    bad = A.copy()
+    bad[17, 200] = np.nan
+    big = decay(300, 0.1, 4, scale=1e20)
+    good = gershgorin_scaled(decay(300, 0.1, 5))
+    srv = gpu.Server(2 * GiB, max_slots=4)
+    try:
+        dbad, dbig, dgood = (torch.from_numpy(x).cuda() for x in (bad, big, good))
+        outs = [torch.empty_like(dbad) for _ in range(3)]
+        t1 = srv.submit(dbad, outs[0], 1e-6, 32)
+        t2 = srv.submit(dbig, outs[1], 1e-6, 32, chain_len=3)
+        t3 = srv.submit(dgood, outs[2], 1e-6, 32, chain_len=3)
+        r1, r2, r3 = srv.wait(t1), srv.wait(t2), srv.wait(t3)
+        assert r1["status"] == gpu.SPAMM_E_NONFINITE
+        assert r2["status"] == gpu.SPAMM_E_NONFINITE     # X_1 = A^2 overflows FP32
+        assert r3["status"] == 0
+        ref = reference(gpu, (300, 32, 1e-6, 0, 0.0, 3, False, 0, 0), dgood, None, 0.0)[0]
+        assert torch.equal(outs[2], ref)
+    finally:
+        srv.destroy()
+
+
+def test_poll_semantics(gpu):
+    import torch
+    A = torch.from_numpy(decay(256, 0.1, 1)).cuda()
+    srv = gpu.Server(GiB, max_slots=1)
+    try:
+        with pytest.raises(gpu.SpammError) as ei:
+            srv.poll(12345)
+        assert ei.value.code == gpu.SPAMM_E_INVAL
+        C = torch.empty_like(A)
+        t = srv.submit(A, C, 1e-6, 32)
+        assert t > 0
+        r = srv.wait(t)
+        assert r["status"] == 0
+        with pytest.raises(gpu.SpammError):
+            srv.poll(t)                   # already collected
+        t2 = srv.submit(A, C, 1e-6, 32)
+        assert t2 > t
+        srv.wait(t2)
+    finally:
+        srv.destroy()
+
+
+def test_submitters_on_several_threads(gpu):
+    import torch
+    specs = [(n, 32, 1e-6, 0, 0.0, c, False, 0.1, 50 + k)
+             for k, (n, c) in enumerate([(256, 0), (512, 2), (384, 0), (640, 1)] * 2)]
+    ins = [make_inputs(s) for s in specs]
+    refs = [reference(gpu, s, a[2], None, 0.0)[0] for s, a in zip(specs, ins)]
+    torch.cuda.synchronize()
+    outs = [torch.empty_like(a[2]) for a in ins]
+    srv = gpu.Server(4 * GiB, max_slots=8)
+    errors = []
+
+    def worker(idx):
+        try:
+            for i in idx:
+                s = specs[i]
+                t = srv.submit(ins[i][2], outs[i], s[2], s[1], chain_len=s[5], sync=False)
+                assert srv.wait(t)["status"] == 0
+        except Exception as e:      # surfaced below
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(range(k, len(specs), 4),)) for k in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    srv.destroy()
+    assert not errors, errors
+    for C, ref in zip(outs, refs):
+        assert torch.equal(C, ref)
+
+
+def test_chain_in_place(gpu):
+    import torch
+    A = gershgorin_scaled(decay(700, 0.1, 21))
+    X = torch.from_numpy(A).cuda()
+    ref = reference(gpu, (700, 32, 1e-7, 1, 0.0, 4, False, 0, 0), X.clone(), None, 1e-4)[0]
+    srv = gpu.Server(2 * GiB, max_slots=2)
+    try:
+        r = srv.wait(srv.submit(X, X, 1e-7, 32, precision=gpu.PREC_SPLIT_BF16, low_tol=1e-4,
+                                chain_len=4))
+    finally:
+        srv.destroy()
+    assert r["status"] == 0 and r["steps"] == 4
+    assert torch.equal(X, ref)

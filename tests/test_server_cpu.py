@@ -1,0 +1,97 @@
+"""Serving ABI without a GPU: request validation and footprints (host-only),
+server argument checks, NULL handling."""
+import ctypes
+
+import pytest
+
+import paper_1203_1692_amd as sp
+
+
+def fp(**kw):
+    args = dict(n=1000, leaf=32, tau=1e-6)
+    args.update(kw)
+    return sp.request_footprint(**args)
+
+
+def tree_bytes(n, leaf, bf16):
+    """Packed leaves (two FP32 copies, two BF16 copies when bf16) plus the
+    FP64 norm pyramid of tiers 0..d."""
+    d = 0
+    while leaf << d < n:
+        d += 1
+    np_ = leaf << d
+    return 8 * np_ * np_ + (4 * np_ * np_ if bf16 else 0) + 8 * (4 ** (d + 1) - 1) // 3
+
+
+@pytest.mark.parametrize("n,leaf,prec", [(1, 16, sp.PREC_FP32), (1000, 32, sp.PREC_FP32),
+                                         (4096, 32, sp.PREC_SPLIT_BF16),
+                                         (8192, 64, sp.PREC_SPLIT_BF16)])
+def test_footprint_tree_part(n, leaf, prec):
+    one = fp(n=n, leaf=leaf, precision=prec, low_tol=1e-3)
+    two = fp(n=n, leaf=leaf, precision=prec, low_tol=1e-3, distinct_b=True)
+    assert two - one == tree_bytes(n, leaf, prec == sp.PREC_SPLIT_BF16)
+    # the task arena is a modest share of the operand at these sizes
+    assert 0 < one - tree_bytes(n, leaf, prec == sp.PREC_SPLIT_BF16) <= tree_bytes(n, leaf, False)
+
+
+def test_footprint_grows_with_n_and_chain_does_not_change_it():
+    sizes = [fp(n=n) for n in (512, 1024, 2048, 4096, 8192)]
+    assert sizes == sorted(sizes) and len(set(sizes)) == 5
+    assert fp(n=2048, chain_len=10) == fp(n=2048)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=0), sp.SPAMM_E_INVAL),
+    (dict(leaf=48), sp.SPAMM_E_INVAL),
+    (dict(leaf=16, precision=sp.PREC_SPLIT_BF16), sp.SPAMM_E_INVAL),
+    (dict(precision=5), sp.SPAMM_E_INVAL),
+    (dict(tau=-1.0), sp.SPAMM_E_INVAL),
+    (dict(tau=float("nan")), sp.SPAMM_E_INVAL),
+    (dict(tau=float("inf")), sp.SPAMM_E_INVAL),
+    (dict(tau=1e-200), sp.SPAMM_E_INVAL),
+    (dict(precision=sp.PREC_SPLIT_BF16, low_tol=-1.0), sp.SPAMM_E_INVAL),
+    (dict(chain_len=-1), sp.SPAMM_E_INVAL),
+    (dict(chain_len=65), sp.SPAMM_E_INVAL),
+    (dict(chain_len=3, distinct_b=True), sp.SPAMM_E_INVAL),
+    (dict(n=16 * 1024 + 1, leaf=16), sp.SPAMM_E_RANGE),
+])
+def test_request_validation(kw, code):
+    with pytest.raises(sp.SpammError) as ei:
+        fp(**kw)
+    assert ei.value.code == code
+
+
+def test_low_tol_ignored_for_fp32():
+    assert fp(low_tol=-1.0) == fp()
+
+
+def test_null_pointers_and_handles():
+    lib = sp.load()
+    r = sp.Request(None, None, 3, 100, 32, 0, 0.0, 0.0, 0)
+    out = ctypes.c_size_t()
+    assert lib.spamm_request_footprint(ctypes.byref(r), ctypes.byref(out)) == sp.SPAMM_E_INVAL
+    r.A, r.C = 1, None
+    assert lib.spamm_request_footprint(ctypes.byref(r), ctypes.byref(out)) == sp.SPAMM_E_INVAL
+    r.C = 3
+    assert lib.spamm_request_footprint(ctypes.byref(r), None) == sp.SPAMM_E_INVAL
+    assert lib.spamm_request_footprint(None, ctypes.byref(out)) == sp.SPAMM_E_INVAL
+    t = ctypes.c_uint64()
+    assert lib.spamm_submit(None, ctypes.byref(r), ctypes.byref(t)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_poll(None, 1, None) == sp.SPAMM_E_INVAL
+    assert lib.spamm_server_info(None, None) == sp.SPAMM_E_INVAL
+    assert lib.spamm_server_destroy(None) == sp.SPAMM_OK
+
+
+def test_server_create_argument_checks():
+    lib = sp.load()
+    h = ctypes.c_void_p()
+    assert lib.spamm_server_create(0, 4, ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_server_create(1 << 30, 0, ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_server_create(1 << 30, 65, ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_server_create(1 << 30, 4, None) == sp.SPAMM_E_INVAL
+    assert h.value is None
+
+
+def test_new_status_codes():
+    assert sp.strerror(sp.SPAMM_E_BUSY) != "unknown status"
+    assert sp.strerror(sp.SPAMM_PENDING) != "unknown status"
