@@ -11,7 +11,11 @@ Prints one JSON line.  `value` is kept-leaf TFLOP/s over the whole step
 (2 n_b^3 K / step time).  `roofline` rates the leaf GEMM kernel (the dominant
 kernel) against the FP32 MFMA peak, with its duration from HIP events recorded
 around its launch on the stream it runs on.  `cpu_baseline` times the FP64
-oracle on a seeded sample of output leaves of the same matrix.
+oracle on a seeded sample of output leaves of the same matrix.  `serving`
+then drives a stream of 2000 products and squaring chains of uneven size
+through the continuous-batching server: saturation throughput, and p50/p99
+latency under Poisson arrivals at 0.5x and 0.8x of it (`--serve` runs only
+that, `--no-serve` skips it).
 """
 from __future__ import annotations
 
@@ -113,6 +117,234 @@ def matched_error(sp, wl, A, dA, C, tau, leaf, n, N, reps=2):
     }
 
 
+# ---------------------------------------------------------------------------
+# Serving: continuous batching of a stream of products and squaring chains
+# ---------------------------------------------------------------------------
+def serve_matrix(torch, req, dev):
+    """Request r's input on the device: symmetric u ~ U(-1, 1) from a torch
+    generator seeded 1000 + r, times exp(-rate |i - j|); a chain starts from
+    X_0 = A / max_i sum_j |a_ij| (Gershgorin), so no power overflows."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(req.seed)
+    n = req.n
+    u = torch.rand((n, n), generator=g, device=dev, dtype=torch.float32).mul_(2.0).sub_(1.0)
+    A = torch.triu(u)
+    A += torch.triu(u, 1).T
+    del u
+    i = torch.arange(n, device=dev, dtype=torch.float32)
+    A *= torch.exp((i[:, None] - i[None, :]).abs_().mul_(-req.rate))
+    if req.chain_len:
+        A /= A.abs().sum(dim=1).max()
+    return A
+
+
+def percentile(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
+
+
+def serve_inputs(torch, reqs, dev):
+    """Every request's input and absolute LOW threshold, generated on the
+    device before any timed run (so the runs measure the server, not the
+    generator).  low_tol = theta ||A||_F^2 for split requests (A = B)."""
+    from workloads import SERVE_THETA
+    inputs = {}
+    for req in reqs:
+        A = serve_matrix(torch, req, dev)
+        low = 0.0
+        if req.split:
+            low = SERVE_THETA * float(torch.linalg.vector_norm(A, dtype=torch.float64)) ** 2
+        inputs[req.index] = (A, low)
+    torch.cuda.synchronize()
+    return inputs
+
+
+def serve_run(sp, torch, srv, reqs, inputs, qps=None, window=16, keep=()):
+    """Drive `reqs` through the server: open loop with Poisson arrivals at
+    `qps`, or closed loop with `window` requests outstanding (qps None).
+    Returns per-request results, timing and the C of the requests in `keep`."""
+    import numpy as np
+    from workloads import SERVE_LEAF
+    out, kept = {}, {}
+    pending = {}
+    arrivals = None
+    t0 = time.perf_counter()
+    if qps is not None:
+        arrivals = t0 + np.cumsum([r.gap for r in reqs]) / qps
+
+    def sweep():
+        got = False
+        for t in list(pending):
+            res = srv.poll(t)
+            if res is not None:
+                req, C = pending.pop(t)
+                res["n"], res["chain"], res["split"] = req.n, req.chain_len, req.split
+                out[req.index] = res
+                if req.index in keep:
+                    kept[req.index] = C
+                got = True
+        return got
+
+    t_first = t_last = None
+    for k, req in enumerate(reqs):
+        if arrivals is None:
+            while len(pending) >= window:
+                if not sweep():
+                    time.sleep(50e-6)
+        else:
+            while time.perf_counter() < arrivals[k]:
+                if not sweep():
+                    time.sleep(50e-6)
+        A, low = inputs[req.index]
+        C = torch.empty_like(A)
+        t_sub = time.perf_counter()
+        t_first = t_first or t_sub
+        t_last = t_sub
+        tk = srv.submit(A, C, req.tau, SERVE_LEAF,
+                        precision=sp.PREC_SPLIT_BF16 if req.split else sp.PREC_FP32,
+                        low_tol=low, chain_len=req.chain_len, sync=False)
+        pending[tk] = (req, C)
+    while pending:
+        if not sweep():
+            time.sleep(50e-6)
+    t_end = time.perf_counter()
+    return out, kept, dict(t0=t0, t_first=t_first, t_last=t_last, t_end=t_end)
+
+
+def serve_summary(reqs, res, tm, qps):
+    lat = [res[r.index]["latency_ms"] for r in reqs]
+    bad = sum(res[r.index]["status"] != 0 for r in reqs)
+    span = tm["t_end"] - tm["t_first"]
+    flops = sum(res[r.index]["flops"] for r in reqs)
+
+    def pq(sel):
+        v = [res[r.index]["latency_ms"] for r in reqs if sel(r)]
+        return {"count": len(v), "p50_ms": percentile(v, 50), "p99_ms": percentile(v, 99)}
+
+    d = {
+        "offered_qps": qps,
+        "arrival_qps": (len(reqs) - 1) / (tm["t_last"] - tm["t_first"]) if len(reqs) > 1 else None,
+        "throughput_rps": len(reqs) / span,
+        "kept_tile_tflops": flops / span / 1e12,
+        "p50_ms": percentile(lat, 50),
+        "p99_ms": percentile(lat, 99),
+        "queue_p50_ms": percentile([res[r.index]["queue_ms"] for r in reqs], 50),
+        "queue_p99_ms": percentile([res[r.index]["queue_ms"] for r in reqs], 99),
+        "failed": bad,
+        "plain": pq(lambda r: r.chain_len == 0),
+        "chains": pq(lambda r: r.chain_len > 0),
+        "fp32": pq(lambda r: not r.split),
+        "split_bf16": pq(lambda r: r.split),
+        "by_n": {str(n): pq(lambda r, n=n: r.n == n) for n in sorted({r.n for r in reqs})},
+    }
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+
+
+def serve_verify(sp, torch, reqs, kept, inputs):
+    """Requests kept from the mix, recomputed alone through the one-call API
+    (tree build + multiply per step): the bits must agree."""
+    from workloads import SERVE_LEAF
+    ok = 0
+    for req in reqs:
+        if req.index not in kept:
+            continue
+        X, low = inputs[req.index]
+        prec = sp.PREC_SPLIT_BF16 if req.split else sp.PREC_FP32
+        for _ in range(max(1, req.chain_len)):
+            t = sp.build_tree(X, SERVE_LEAF, bf16=req.split)
+            C = torch.empty_like(X)
+            sp.multiply_ex(t, t, req.tau, C, precision=prec, low_tol=low)
+            t.free()
+            X = C
+        ok += int(torch.equal(X, kept[req.index]))
+    return ok
+
+
+def serve_bench(sp, torch, dev, count, slots, budget_gib):
+    """Saturation (closed loop, 2 x slots outstanding), then Poisson arrivals
+    at 0.5x and 0.8x of it; returns the summary dict."""
+    import workloads
+    reqs = workloads.serving_mix(count)
+    t = time.perf_counter()
+    inputs = serve_inputs(torch, reqs, dev)
+    t_gen = time.perf_counter() - t
+    print(f"serving inputs: {len(reqs)} matrices in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    srv = sp.Server(int(budget_gib * (1 << 30)), max_slots=slots)
+    try:
+        warm = workloads.serving_mix(24, seed=99)
+        serve_run(sp, torch, srv, warm, serve_inputs(torch, warm, dev), window=slots)
+        res, _, tm = serve_run(sp, torch, srv, reqs, inputs, window=2 * slots)
+        sat = serve_summary(reqs, res, tm, None)
+        print(f"saturation: {sat['throughput_rps']:.2f} req/s, p50 {sat['p50_ms']} ms, "
+              f"p99 {sat['p99_ms']} ms", file=sys.stderr, flush=True)
+        loads = {}
+        keep_idx = set()
+        for want in (lambda r: r.chain_len > 0 and r.split, lambda r: r.chain_len > 0,
+                     lambda r: r.split and r.n == 8192, lambda r: r.n == 512):
+            keep_idx |= {next(r.index for r in reqs if want(r))}
+        verified = None
+        for frac in (0.5, 0.8):
+            qps = frac * sat["throughput_rps"]
+            i0 = srv.info()
+            res, kept, tm = serve_run(sp, torch, srv, reqs, inputs, qps=qps,
+                                      keep=keep_idx if frac == 0.8 else ())
+            i1 = srv.info()
+            s = serve_summary(reqs, res, tm, round(qps, 3))
+            s["launches"] = i1["launches"] - i0["launches"]
+            s["mean_products_per_launch"] = round(
+                (i1["launched_products"] - i0["launched_products"]) / max(1, s["launches"]), 3)
+            loads[f"{frac}x"] = s
+            print(f"{frac}x load: {s['arrival_qps']} req/s offered, p50 {s['p50_ms']} ms, "
+                  f"p99 {s['p99_ms']} ms", file=sys.stderr, flush=True)
+            if frac == 0.8:
+                verified = serve_verify(sp, torch, reqs, kept, inputs)
+        info = srv.info()
+    finally:
+        srv.destroy()
+    del inputs
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"serve-mix{len(reqs)}",
+        "requests": len(reqs), "sizes": list(workloads.SERVE_SIZES),
+        "leaf": workloads.SERVE_LEAF, "taus": [1e-6, 1e-8], "chain_share": 0.3,
+        "chain_len": 10, "split_share": 0.5, "split_theta": workloads.SERVE_THETA,
+        "slots": slots, "budget_gib": budget_gib,
+        "input": "device-generated per request (torch generator, seed 1000+r), resident "
+                 "before the timed runs",
+        "saturation": sat,
+        "loads": loads,
+        "verified_bitwise_vs_alone": f"{verified}/{len(keep_idx)}",
+        "server": {k: info[k] for k in ("max_batch", "peak_active", "peak_used", "budget")},
+    }
+
+
+def serve_main(args) -> int:
+    import torch
+
+    import paper_1203_1692_amd as sp
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    sp.load()
+    sv = serve_bench(sp, torch, dev, args.serve_requests, args.serve_slots, args.serve_budget_gib)
+    out = {
+        "metric": "serving: saturation throughput; p50/p99 latency at 0.5x and 0.8x of it",
+        "value": round(sv["saturation"]["throughput_rps"], 3),
+        "unit": "requests/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+bf16",
+        "data": "synthetic",
+        "config": {k: v for k, v in sv.items() if k not in ("saturation", "loads")},
+        "saturation": sv["saturation"],
+        "loads": sv["loads"],
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,12 +361,22 @@ def main() -> int:
                     help="also run a 1 GiB device copy (for scaling HBM counters)")
     ap.add_argument("--no-matched-error", action="store_true",
                     help="skip the FP32-vs-split comparison at a fixed max-norm error")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark instead: saturation, then Poisson arrivals")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving run that follows the main workload")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-budget-gib", type=float, default=96.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the SpAMM path here is single-device "
               "(run with --gpus 1)", file=sys.stderr)
         return 2
+
+    if args.serve:
+        return serve_main(args)
 
     import numpy as np
     import torch
@@ -274,6 +516,15 @@ def main() -> int:
                        f"{int(counts.sum())} kept leaf products, recursive FP64 oracle incl. its "
                        f"full-matrix norm pass, {t:.1f} s wall"),
         }
+    # ---- serving: a stream of products and squaring chains --------------------
+    if not args.no_serve:
+        del dA, C
+        torch.cuda.empty_cache()
+        sv = serve_bench(sp, torch, dev, args.serve_requests, args.serve_slots,
+                         args.serve_budget_gib)
+        for part in [sv["saturation"], *sv["loads"].values()]:
+            part.pop("by_n", None)
+        out["serving"] = sv
     print(json.dumps(out), flush=True)
     return 0
 

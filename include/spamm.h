@@ -204,10 +204,12 @@ int spamm_multiply_opts(const spamm_tree *A, const spamm_tree *B, const spamm_op
 
 /*
  * A server owns one scheduler thread, `max_slots` streams and a device-memory
- * budget on the device current at spamm_server_create.  Requests wait in a
- * FIFO queue; the scheduler admits the head whenever a slot is free and the
- * request's footprint (trees + task arena, spamm_request_footprint) fits in
- * what the admitted requests leave of the budget.  An admitted request's
+ * budget on the device current at spamm_server_create.  Each slot keeps one
+ * device arena for the trees and the task arena of the request it runs
+ * (spamm_request_footprint bytes; C is the caller's), reused across requests
+ * and grown when needed.  Requests wait in a FIFO queue; the scheduler admits
+ * the head when a slot is free and its arena fits: idle arenas are released
+ * to make room, and the arenas together never exceed the budget.  An admitted request's
  * trees and cull run on its slot's stream, overlapping other requests' work;
  * the leaf products of every request whose cull has been enqueued are
  * gathered into one batched leaf-GEMM launch (up to 16 requests of one leaf
@@ -256,21 +258,21 @@ typedef struct spamm_server_stats {
     int64_t  launched_products;  /* products over all launch groups                  */
     int64_t  max_batch;          /* most products in one launch group                */
     int64_t  peak_active;        /* most requests admitted at once                   */
-    uint64_t used;               /* footprint bytes held by admitted requests now    */
-    uint64_t peak_used;          /* most footprint bytes held at once                */
+    uint64_t used;               /* bytes held by the slot arenas now                */
+    uint64_t peak_used;          /* most bytes held by the slot arenas at once       */
     uint64_t budget;             /* hbm_budget                                       */
 } spamm_server_stats;
 
 /*
  * Create a server on the current device.  hbm_budget: bytes of device memory
- * the admitted requests may hold at once (> 0).  max_slots: requests admitted
+ * the slot arenas may hold at once (> 0).  max_slots: requests admitted
  * at once, 1..64.  Errors: SPAMM_E_INVAL, SPAMM_E_NOMEM, SPAMM_E_HIP.
  */
 int spamm_server_create(size_t hbm_budget, int32_t max_slots, spamm_server **out);
 
 /*
- * Device bytes the server reserves for a request while it is admitted; also
- * validates it (host only, no device call).  Errors: SPAMM_E_INVAL (null
+ * Device bytes of a request's slot arena (its trees and task arena, buffers
+ * at 256-byte aligned offsets); also validates the request (host only, no device call).  Errors: SPAMM_E_INVAL (null
  * pointers, n < 1, bad leaf, precision, tau, low_tol, chain_len outside 0..64,
  * a chain with B not NULL and not A, split precision with leaf 16),
  * SPAMM_E_RANGE (more than 1024 leaves per dimension).

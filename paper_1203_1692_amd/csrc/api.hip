@@ -98,7 +98,10 @@ int tree_depth(int64_t n, int32_t leaf, int32_t *d, int64_t *np)
     return SPAMM_OK;
 }
 
-// Device buffers of a plan of depth d (worst case: every candidate kept).
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Device buffers of a plan of depth d (worst case: every candidate kept),
+// each at a 256-byte aligned offset of one block.
 struct PlanSizes {
     int64_t rp_off[kMaxDepth + 1];
     size_t rowptr, list[2], counts, partials, browptr, bent;
@@ -129,14 +132,62 @@ static PlanSizes plan_sizes(int d)
     return z;
 }
 
+// The plan's buffers in allocation order (split adds the LOW schedule).
+struct PlanBuf { void **dst; size_t bytes; };
+
+static int plan_bufs(spamm_plan *p, const PlanSizes &z, bool split, PlanBuf *out)
+{
+    int k = 0;
+    out[k++] = {(void **)&p->rowptr, z.rowptr};
+    out[k++] = {(void **)&p->list[0], z.list[0]};
+    out[k++] = {(void **)&p->list[1], z.list[1]};
+    out[k++] = {(void **)&p->counts, z.counts};
+    out[k++] = {(void **)&p->partials, z.partials};
+    out[k++] = {(void **)&p->browptr, z.browptr};
+    out[k++] = {(void **)&p->bent, z.bent};
+    out[k++] = {(void **)&p->leafK, 2 * sizeof(uint64_t)};
+    if (split) {
+        out[k++] = {(void **)&p->browptr_lo, z.browptr};
+        out[k++] = {(void **)&p->bent_lo, z.bent};
+    }
+    return k;
+}
+
 size_t plan_device_bytes(int depth, bool split)
 {
-    const PlanSizes z = plan_sizes(depth);
-    size_t b = z.rowptr + z.list[0] + z.list[1] + z.counts + z.partials + z.browptr + z.bent +
-               2 * sizeof(uint64_t);
-    if (split)
-        b += z.browptr + z.bent;
-    return b;
+    spamm_plan dummy{};
+    PlanBuf b[12];
+    const int k = plan_bufs(&dummy, plan_sizes(depth), split, b);
+    size_t total = 0;
+    for (int i = 0; i < k; ++i)
+        total += align256(b[i].bytes);
+    return total;
+}
+
+// Tree buffers: left and right FP32 leaf copies, optional BF16 copies, the
+// norm pyramid; 256-byte aligned offsets of one block.
+struct TreeLayout {
+    size_t tiles, tilesT, t16, tT16, norms, total;
+};
+
+static TreeLayout tree_layout(int64_t np, int32_t d, bool bf16)
+{
+    TreeLayout L{};
+    const size_t tile = sizeof(float) * (size_t)np * (size_t)np;
+    const size_t norm = sizeof(double) * (size_t)tier_offset(d + 1);
+    size_t o = 0;
+    L.tiles = o;
+    o += align256(tile);
+    L.tilesT = o;
+    o += align256(tile);
+    L.t16 = o;
+    o += bf16 ? align256(tile / 2) : 0;
+    L.tT16 = o;
+    o += bf16 ? align256(tile / 2) : 0;
+    L.norms = o;
+    o += align256(norm);
+    L.total = o;
+    return L;
 }
 
 size_t tree_device_bytes(int64_t n, int32_t leaf, bool bf16)
@@ -147,12 +198,11 @@ size_t tree_device_bytes(int64_t n, int32_t leaf, bool bf16)
         p *= 2;
         d += 1;
     }
-    const size_t tile = sizeof(float) * (size_t)p * (size_t)p;
-    return 2 * tile + (bf16 ? tile : 0) + sizeof(double) * (size_t)tier_offset(d + 1);
+    return tree_layout(p, d, bf16).total;
 }
 
 int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hipStream_t s,
-                     double *root_dst, spamm_tree **out)
+                     double *root_dst, spamm_tree **out, void *arena)
 {
     if (out == nullptr)
         return fail(SPAMM_E_INVAL, "out is NULL");
@@ -176,9 +226,7 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
     int dev;
     if ((rc = prepare_device(&dev)))
         return rc;
-    const int64_t N = int64_t(1) << d;
-    const size_t tile_bytes = sizeof(float) * (size_t)(N * N) * (size_t)leaf * (size_t)leaf;
-    const size_t norm_bytes = sizeof(double) * (size_t)tier_offset(d + 1);
+    const TreeLayout L = tree_layout(np, d, bf16);
 
     spamm_tree *t = new (std::nothrow) spamm_tree();
     if (!t)
@@ -189,15 +237,27 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
     t->np = np;
     t->leaf = leaf;
     t->depth = d;
-    hipError_t e = hipMallocAsync((void **)&t->tiles, tile_bytes, s);
-    if (e == hipSuccess)
-        e = hipMallocAsync((void **)&t->tilesT, tile_bytes, s);
-    if (e == hipSuccess && bf16)
-        e = hipMallocAsync((void **)&t->tiles16, tile_bytes / 2, s);
-    if (e == hipSuccess && bf16)
-        e = hipMallocAsync((void **)&t->tilesT16, tile_bytes / 2, s);
-    if (e == hipSuccess)
-        e = hipMallocAsync((void **)&t->norms, norm_bytes, s);
+    hipError_t e = hipSuccess;
+    if (arena != nullptr) {
+        char *base = (char *)arena;
+        t->borrowed = true;
+        t->tiles = (float *)(base + L.tiles);
+        t->tilesT = (float *)(base + L.tilesT);
+        t->tiles16 = bf16 ? (uint16_t *)(base + L.t16) : nullptr;
+        t->tilesT16 = bf16 ? (uint16_t *)(base + L.tT16) : nullptr;
+        t->norms = (double *)(base + L.norms);
+    } else {
+        const size_t tile_bytes = L.tilesT - L.tiles, half = L.tT16 - L.t16;
+        e = hipMallocAsync((void **)&t->tiles, tile_bytes, s);
+        if (e == hipSuccess)
+            e = hipMallocAsync((void **)&t->tilesT, tile_bytes, s);
+        if (e == hipSuccess && bf16)
+            e = hipMallocAsync((void **)&t->tiles16, half, s);
+        if (e == hipSuccess && bf16)
+            e = hipMallocAsync((void **)&t->tilesT16, half, s);
+        if (e == hipSuccess)
+            e = hipMallocAsync((void **)&t->norms, L.total - L.norms, s);
+    }
     if (e == hipSuccess)
         e = launch_build(A, n, leaf, d, t->tiles, t->tilesT, t->tiles16, t->tilesT16, t->norms, s);
     if (e == hipSuccess && root_dst != nullptr)
@@ -208,6 +268,90 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
         return rc;
     }
     *out = t;
+    return SPAMM_OK;
+}
+
+static int check_tol(double v, const char *name)
+{
+    if (!(v >= 0.0) || isinf(v))
+        return fail(SPAMM_E_INVAL, "%s = %g must be finite and >= 0", name, v);
+    if (v > 0.0 && v < 1e-150)
+        return fail(SPAMM_E_INVAL, "%s = %g below 1e-150 (its square would underflow)", name, v);
+    return SPAMM_OK;
+}
+
+int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
+                   hipStream_t s, void *arena, spamm_plan **out)
+{
+    if (out == nullptr)
+        return fail(SPAMM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (A == nullptr || B == nullptr || opts == nullptr)
+        return fail(SPAMM_E_INVAL, "tree or options NULL");
+    int rc;
+    if ((rc = check_tol(opts->tau, "tau")))
+        return rc;
+    if (opts->precision != SPAMM_PREC_FP32 && opts->precision != SPAMM_PREC_SPLIT_BF16)
+        return fail(SPAMM_E_INVAL, "unknown precision %d", opts->precision);
+    const bool split = opts->precision == SPAMM_PREC_SPLIT_BF16;
+    if (split && (rc = check_tol(opts->low_tol, "low_tol")))
+        return rc;
+    if (A->n != B->n || A->leaf != B->leaf)
+        return fail(SPAMM_E_MISMATCH, "A is %lld/%d, B is %lld/%d (n/leaf)", (long long)A->n,
+                    A->leaf, (long long)B->n, B->leaf);
+    if (split && (A->tiles16 == nullptr || B->tilesT16 == nullptr))
+        return fail(SPAMM_E_INVAL, "split precision needs trees built with SPAMM_TREE_BF16");
+    int dev;
+    if ((rc = prepare_device(&dev)))
+        return rc;
+    if (A->device != dev || B->device != dev)
+        return fail(SPAMM_E_INVAL, "trees live on device %d/%d, current device is %d", A->device,
+                    B->device, dev);
+    spamm_plan *p = new (std::nothrow) spamm_plan();
+    if (!p)
+        return fail(SPAMM_E_NOMEM, "host allocation failed");
+    p->device = dev;
+    p->stream = s;
+    p->A = A;
+    p->B = B;
+    p->depth = A->depth;
+    p->leaf = A->leaf;
+    p->n = A->n;
+    p->tau = opts->tau;
+    p->T2 = opts->tau * opts->tau;
+    p->precision = opts->precision;
+    p->low_tol = split ? opts->low_tol : 0.0;
+    p->L2 = p->low_tol * p->low_tol;
+    const int d = p->depth;
+    p->nblocks = d == 0 ? 1 : (int64_t(1) << (2 * (d - 1)));
+
+    const PlanSizes z = plan_sizes(d);
+    for (int t = 0; t <= d; ++t)
+        p->rp_off[t] = z.rp_off[t];
+    PlanBuf bufs[12];
+    const int nb = plan_bufs(p, z, split, bufs);
+    size_t off = 0;
+    for (int i = 0; i < nb; ++i) {
+        if (arena != nullptr) {
+            *bufs[i].dst = (char *)arena + off;
+            off += align256(bufs[i].bytes);
+            continue;
+        }
+        hipError_t e = hipMallocAsync(bufs[i].dst, bufs[i].bytes, s);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "hipMallocAsync (plan)");
+            spamm_plan_free(p);
+            return rc;
+        }
+        p->pool[p->npool++] = *bufs[i].dst;
+    }
+    hipError_t e = launch_cull(p, s);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "cull launch");
+        spamm_plan_free(p);
+        return rc;
+    }
+    *out = p;
     return SPAMM_OK;
 }
 
@@ -276,7 +420,7 @@ int spamm_tree_free(spamm_tree *t)
     hipError_t e = hipSuccess;
     for (void *ptr : {(void *)t->tiles, (void *)t->tilesT, (void *)t->tiles16, (void *)t->tilesT16,
                       (void *)t->norms}) {
-        if (ptr == nullptr)
+        if (ptr == nullptr || t->borrowed)
             continue;
         hipError_t f = hipFreeAsync(ptr, t->stream);
         if (e == hipSuccess)
@@ -367,15 +511,6 @@ int spamm_plan_free(spamm_plan *p)
     return e == hipSuccess ? SPAMM_OK : hip_fail(e, "spamm_plan_free");
 }
 
-static int check_tol(double v, const char *name)
-{
-    if (!(v >= 0.0) || isinf(v))
-        return fail(SPAMM_E_INVAL, "%s = %g must be finite and >= 0", name, v);
-    if (v > 0.0 && v < 1e-150)
-        return fail(SPAMM_E_INVAL, "%s = %g below 1e-150 (its square would underflow)", name, v);
-    return SPAMM_OK;
-}
-
 int spamm_symbolic(const spamm_tree *A, const spamm_tree *B, double tau, void *stream,
                    spamm_plan **out)
 {
@@ -389,83 +524,7 @@ int spamm_symbolic(const spamm_tree *A, const spamm_tree *B, double tau, void *s
 int spamm_symbolic_ex(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
                       void *stream, spamm_plan **out)
 {
-    if (out == nullptr)
-        return fail(SPAMM_E_INVAL, "out is NULL");
-    *out = nullptr;
-    if (A == nullptr || B == nullptr || opts == nullptr)
-        return fail(SPAMM_E_INVAL, "tree or options NULL");
-    int rc;
-    if ((rc = check_tol(opts->tau, "tau")))
-        return rc;
-    if (opts->precision != SPAMM_PREC_FP32 && opts->precision != SPAMM_PREC_SPLIT_BF16)
-        return fail(SPAMM_E_INVAL, "unknown precision %d", opts->precision);
-    const bool split = opts->precision == SPAMM_PREC_SPLIT_BF16;
-    if (split && (rc = check_tol(opts->low_tol, "low_tol")))
-        return rc;
-    if (A->n != B->n || A->leaf != B->leaf)
-        return fail(SPAMM_E_MISMATCH, "A is %lld/%d, B is %lld/%d (n/leaf)", (long long)A->n,
-                    A->leaf, (long long)B->n, B->leaf);
-    if (split && (A->tiles16 == nullptr || B->tilesT16 == nullptr))
-        return fail(SPAMM_E_INVAL, "split precision needs trees built with SPAMM_TREE_BF16");
-    int dev;
-    if ((rc = prepare_device(&dev)))
-        return rc;
-    if (A->device != dev || B->device != dev)
-        return fail(SPAMM_E_INVAL, "trees live on device %d/%d, current device is %d", A->device,
-                    B->device, dev);
-    spamm_plan *p = new (std::nothrow) spamm_plan();
-    if (!p)
-        return fail(SPAMM_E_NOMEM, "host allocation failed");
-    hipStream_t s = (hipStream_t)stream;
-    p->device = dev;
-    p->stream = s;
-    p->A = A;
-    p->B = B;
-    p->depth = A->depth;
-    p->leaf = A->leaf;
-    p->n = A->n;
-    p->tau = opts->tau;
-    p->T2 = opts->tau * opts->tau;
-    p->precision = opts->precision;
-    p->low_tol = split ? opts->low_tol : 0.0;
-    p->L2 = p->low_tol * p->low_tol;
-    const int d = p->depth;
-    p->nblocks = d == 0 ? 1 : (int64_t(1) << (2 * (d - 1)));
-
-    const PlanSizes z = plan_sizes(d);
-    for (int t = 0; t <= d; ++t)
-        p->rp_off[t] = z.rp_off[t];
-    struct Req { void **dst; size_t bytes; } reqs[] = {
-        {(void **)&p->rowptr, z.rowptr},
-        {(void **)&p->list[0], z.list[0]},
-        {(void **)&p->list[1], z.list[1]},
-        {(void **)&p->counts, z.counts},
-        {(void **)&p->partials, z.partials},
-        {(void **)&p->browptr, z.browptr},
-        {(void **)&p->bent, z.bent},
-        {(void **)&p->leafK, 2 * sizeof(uint64_t)},
-        {(void **)&p->browptr_lo, split ? z.browptr : 0},
-        {(void **)&p->bent_lo, split ? z.bent : 0},
-    };
-    for (auto &r : reqs) {
-        if (r.bytes == 0)
-            continue;
-        hipError_t e = hipMallocAsync(r.dst, r.bytes, s);
-        if (e != hipSuccess) {
-            rc = hip_fail(e, "hipMallocAsync (plan)");
-            spamm_plan_free(p);
-            return rc;
-        }
-        p->pool[p->npool++] = *r.dst;
-    }
-    hipError_t e = launch_cull(p, s);
-    if (e != hipSuccess) {
-        rc = hip_fail(e, "cull launch");
-        spamm_plan_free(p);
-        return rc;
-    }
-    *out = p;
-    return SPAMM_OK;
+    return symbolic_async(A, B, opts, (hipStream_t)stream, nullptr, out);
 }
 
 int spamm_numeric(const spamm_plan *p, float *C, void *stream)

@@ -161,6 +161,7 @@ struct spamm_tree {
     uint16_t *tilesT16;     // BF16 right-operand (transposed) copy, or null
     double *norms;          // tiers 0..d, tier_offset layout
     double root;            // ||A||_F^2
+    bool borrowed;          // buffers carved from a caller's arena (not freed here)
 };
 
 struct spamm_plan {

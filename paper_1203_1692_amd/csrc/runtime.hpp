@@ -21,11 +21,20 @@ int prepare_device(int *dev);
 
 // Validates and enqueues a tree build on `s` without synchronizing; the
 // root squared norm is copied to *root_dst (pinned host memory, may be null)
-// asynchronously.  On error nothing stays allocated.
+// asynchronously.  With `arena` (device memory of tree_device_bytes bytes,
+// 256-byte aligned) the tree's buffers are carved from it and never freed by
+// the tree; otherwise they come from the stream-ordered pool.  On error
+// nothing stays allocated.
 int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hipStream_t s,
-                     double *root_dst, spamm_tree **out);
+                     double *root_dst, spamm_tree **out, void *arena = nullptr);
 
-// Device bytes one tree / one plan of depth d needs (admission control).
+// spamm_symbolic_ex on stream `s`, optionally with the plan's buffers carved
+// from `arena` (plan_device_bytes bytes, 256-byte aligned).
+int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
+                   hipStream_t s, void *arena, spamm_plan **out);
+
+// Device bytes of one tree / one plan of depth d, buffers at 256-byte
+// aligned offsets (the arena sizes; also admission control).
 size_t tree_device_bytes(int64_t n, int32_t leaf, bool bf16);
 size_t plan_device_bytes(int depth, bool split);
 

@@ -8,9 +8,14 @@
 //   gs: wait ev_cull (of every request in the batch) -> [BF16 pass] -> FP32
 //       pass -> record ev_done
 //   chain step s -> s+1, enqueued at once after the GEMM:
-//   ss: wait ev_done -> free plan and tree of X_s -> build the tree of
-//       X_{s+1} from C -> cull -> ... (no host round trip)
+//   ss: wait ev_done -> build the tree of X_{s+1} from C over the arena
+//       space of X_s's tree -> cull -> ... (no host round trip)
 // The host only watches ev_done of a request's last product.
+//
+// Memory: each slot owns one device arena (trees + task arena of its current
+// request, carved at fixed offsets), kept across requests and grown when a
+// larger request lands on the slot, so the steady state allocates nothing.
+// The arenas together never exceed the server's budget.
 #include <math.h>
 #include <string.h>
 
@@ -118,7 +123,9 @@ struct spamm_server {
     std::deque<Job> queue;
     std::unordered_set<uint64_t> live;   // queued or admitted
     std::unordered_map<uint64_t, spamm_result> done;
-    size_t used = 0;
+    size_t used = 0;                     // bytes held by the slot arenas
+    void *arena[kMaxSlots] = {};
+    size_t cap[kMaxSlots] = {};
     spamm_server_stats st{};
     bool busy[kMaxSlots] = {};
     uint64_t next_ticket = 1;
@@ -141,12 +148,15 @@ int start_step(spamm_server *S, Active &a)
     const uint32_t flags = a.split ? SPAMM_TREE_BF16 : 0u;
     P.root[a.step][1] = 0.0;
     P.K[a.step][1] = 0;
+    // arena: [tree of A or X_s][tree of B, step 0 only][plan]
+    char *base = (char *)S->arena[a.slot];
+    const size_t tb = tree_device_bytes(r.n, r.leaf, a.split);
     int rc = tree_build_async(a.step == 0 ? r.A : r.C, r.n, r.leaf, flags, ss,
-                              &P.root[a.step][0], &a.tA);
+                              &P.root[a.step][0], &a.tA, base);
     if (rc)
         return rc;
     if (a.step == 0 && a.distinctB) {
-        if ((rc = tree_build_async(r.B, r.n, r.leaf, flags, ss, &P.root[0][1], &a.tB)))
+        if ((rc = tree_build_async(r.B, r.n, r.leaf, flags, ss, &P.root[0][1], &a.tB, base + tb)))
             return rc;
     } else {
         a.tB = a.tA;
@@ -155,7 +165,7 @@ int start_step(spamm_server *S, Active &a)
     o.tau = r.tau;
     o.precision = r.precision;
     o.low_tol = a.split ? r.low_tol : 0.0;
-    if ((rc = spamm_symbolic_ex(a.tA, a.tB, &o, ss, &a.plan)))
+    if ((rc = symbolic_async(a.tA, a.tB, &o, ss, base + (a.distinctB ? 2 : 1) * tb, &a.plan)))
         return rc;
     hipError_t e = hipMemcpyAsync(P.K[a.step], a.plan->leafK, (a.split ? 2 : 1) * sizeof(uint64_t),
                                   hipMemcpyDeviceToHost, ss);
@@ -167,7 +177,9 @@ int start_step(spamm_server *S, Active &a)
     return SPAMM_OK;
 }
 
-// Release the step's plan and trees, stream-ordered after its GEMM.
+// Order the slot stream after the step's GEMM (the next step overwrites the
+// arena and reads C) and drop the step's handles; their buffers live in the
+// slot arena.
 void release_step(spamm_server *S, Active &a)
 {
     hipStream_t ss = S->ss[a.slot];
@@ -298,8 +310,55 @@ void finish(spamm_server *S, Active &a)
     S->done[a.job.ticket] = res;
     S->st.completed += 1;
     S->live.erase(a.job.ticket);
-    S->used -= a.job.bytes;
     S->busy[a.slot] = false;
+}
+
+// Pick a free slot whose arena can hold `need` bytes, growing one (and
+// releasing idle arenas) within the budget.  Called with S->mu held; -1 when
+// the request has to wait.  Returns a HIP error through *err.
+int claim_slot(spamm_server *S, size_t need, hipError_t *err)
+{
+    int fit = -1, big = -1;
+    for (int i = 0; i < S->nslots; ++i) {
+        if (S->busy[i])
+            continue;
+        if (S->cap[i] >= need && (fit < 0 || S->cap[i] < S->cap[fit]))
+            fit = i;
+        if (big < 0 || S->cap[i] > S->cap[big])
+            big = i;
+    }
+    if (fit >= 0)
+        return fit;
+    if (big < 0)
+        return -1;
+    // release idle arenas (smallest first) until the grown arena fits
+    while (S->used - S->cap[big] + need > S->budget) {
+        int v = -1;
+        for (int i = 0; i < S->nslots; ++i)
+            if (!S->busy[i] && i != big && S->cap[i] > 0 && (v < 0 || S->cap[i] < S->cap[v]))
+                v = i;
+        if (v < 0)
+            return -1;
+        hipFreeAsync(S->arena[v], S->ss[v]);
+        S->used -= S->cap[v];
+        S->arena[v] = nullptr;
+        S->cap[v] = 0;
+    }
+    if (S->arena[big] != nullptr) {
+        hipFreeAsync(S->arena[big], S->ss[big]);
+        S->used -= S->cap[big];
+        S->arena[big] = nullptr;
+        S->cap[big] = 0;
+    }
+    hipError_t e = hipMallocAsync(&S->arena[big], need, S->ss[big]);
+    if (e != hipSuccess) {
+        S->arena[big] = nullptr;
+        *err = e;
+        return -1;
+    }
+    S->cap[big] = need;
+    S->used += need;
+    return big;
 }
 
 void scheduler(spamm_server *S)
@@ -317,15 +376,25 @@ void scheduler(spamm_server *S)
                 S->cv.wait(lock, [S] { return S->stopping || !S->queue.empty(); });
                 continue;
             }
-            while (!S->queue.empty() && S->used + S->queue.front().bytes <= S->budget) {
-                int slot = -1;
-                for (int i = 0; i < S->nslots && slot < 0; ++i)
-                    if (!S->busy[i])
-                        slot = i;
-                if (slot < 0)
-                    break;
+            while (!S->queue.empty()) {
+                hipError_t err = hipSuccess;
+                const int slot = claim_slot(S, S->queue.front().bytes, &err);
+                if (slot < 0) {
+                    if (err == hipSuccess)
+                        break;
+                    // the arena could not be allocated: fail this request
+                    Job j = S->queue.front();
+                    S->queue.pop_front();
+                    spamm_result res;
+                    memset(&res, 0, sizeof res);
+                    res.status = hip_fail(err, "slot arena");
+                    res.latency_ms = (now_us() - j.t_submit) * 1e-3;
+                    S->done[j.ticket] = res;
+                    S->live.erase(j.ticket);
+                    S->st.completed += 1;
+                    continue;
+                }
                 S->busy[slot] = true;
-                S->used += S->queue.front().bytes;
                 S->st.admitted += 1;
                 S->st.peak_used = std::max<uint64_t>(S->st.peak_used, S->used);
                 int64_t nb = 0;
@@ -398,6 +467,8 @@ void release_server(spamm_server *S)
     for (hipEvent_t e : S->spare)
         hipEventDestroy(e);
     for (int i = 0; i < kMaxSlots; ++i) {
+        if (S->arena[i])
+            hipFree(S->arena[i]);
         if (S->ev_cull[i])
             hipEventDestroy(S->ev_cull[i]);
         if (S->ev_done[i])

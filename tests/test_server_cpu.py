@@ -15,12 +15,14 @@ def fp(**kw):
 
 def tree_bytes(n, leaf, bf16):
     """Packed leaves (two FP32 copies, two BF16 copies when bf16) plus the
-    FP64 norm pyramid of tiers 0..d."""
+    FP64 norm pyramid of tiers 0..d, each buffer rounded up to 256 bytes
+    (leaf copies are multiples of 256 already)."""
     d = 0
     while leaf << d < n:
         d += 1
     np_ = leaf << d
-    return 8 * np_ * np_ + (4 * np_ * np_ if bf16 else 0) + 8 * (4 ** (d + 1) - 1) // 3
+    norms = 8 * (4 ** (d + 1) - 1) // 3
+    return 8 * np_ * np_ + (4 * np_ * np_ if bf16 else 0) + -(-norms // 256) * 256
 
 
 @pytest.mark.parametrize("n,leaf,prec", [(1, 16, sp.PREC_FP32), (1000, 32, sp.PREC_FP32),
@@ -38,6 +40,7 @@ def test_footprint_grows_with_n_and_chain_does_not_change_it():
     sizes = [fp(n=n) for n in (512, 1024, 2048, 4096, 8192)]
     assert sizes == sorted(sizes) and len(set(sizes)) == 5
     assert fp(n=2048, chain_len=10) == fp(n=2048)
+    assert all(s % 256 == 0 for s in sizes)
 
 
 @pytest.mark.parametrize("kw,code", [

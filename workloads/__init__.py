@@ -204,3 +204,40 @@ WORKLOADS = {
                                    {"n_mol": 1310, "density": 0.0334, "rate": 0.6,
                                     "funcs": 25, "seed": 0}),
 }
+
+
+# ---------------------------------------------------------------------------
+# Serving mix: a stream of products and squaring chains of uneven size.
+# ---------------------------------------------------------------------------
+@dataclass
+class ServeRequest:
+    index: int
+    n: int            # order, uniform over SERVE_SIZES
+    rate: float       # exponential decay rate, U(0.05, 0.5)
+    tau: float        # 1e-6 or 1e-8
+    chain_len: int    # 0 (one product C = A A) or 10 squarings X <- X X
+    split: bool       # split-BF16 precision (else FP32)
+    seed: int         # matrix seed, 1000 + index
+    gap: float        # unit-rate exponential inter-arrival gap (scaled by 1 / QPS)
+
+
+SERVE_SIZES = (512, 1024, 2048, 4096, 8192)
+SERVE_LEAF = 32
+SERVE_THETA = 1e-4    # split: LOW iff norm product < theta ||A||_F ||B||_F
+
+
+def serving_mix(count: int = 2000, seed: int = 0, chain_share: float = 0.3,
+                split_share: float = 0.5) -> list:
+    """Request parameters drawn from one master seed: n uniform over
+    SERVE_SIZES, decay rate U(0.05, 0.5), tau in {1e-6, 1e-8}, a share of
+    10-step squaring chains, a share in split precision, Poisson arrivals
+    (unit-rate exponential gaps).  Request r's matrix uses seed 1000 + r."""
+    rng = np.random.default_rng(seed)
+    n = rng.choice(np.array(SERVE_SIZES), size=count)
+    rate = rng.uniform(0.05, 0.5, size=count)
+    tau = rng.choice(np.array([1e-6, 1e-8]), size=count)
+    chain = rng.random(count) < chain_share
+    split = rng.random(count) < split_share
+    gap = rng.exponential(1.0, size=count)
+    return [ServeRequest(r, int(n[r]), float(rate[r]), float(tau[r]), 10 if chain[r] else 0,
+                         bool(split[r]), 1000 + r, float(gap[r])) for r in range(count)]
