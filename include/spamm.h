@@ -48,6 +48,9 @@ extern "C" {
 
 /* Tree build flags. */
 #define SPAMM_TREE_BF16        1u  /* also keep BF16 copies of the leaves (split precision) */
+#define SPAMM_TREE_SUBNORMS    2u  /* n_b = 64: also keep the norms of the 32 x 32 sub-blocks */
+                                   /* (sub-leaf culling); the whole pyramid is then that of  */
+                                   /* a tree with 32 x 32 leaves                            */
 
 typedef struct spamm_tree spamm_tree;   /* one operand: packed leaves + norms  */
 typedef struct spamm_plan spamm_plan;   /* one product's kept task list        */
@@ -61,9 +64,11 @@ typedef struct spamm_stats {
     int64_t tasks_low;        /* of which LOW (BF16 operands; split precision)   */
     int64_t block_entries;    /* (k, mask) entries scheduled, HIGH list         */
     int64_t block_entries_low;/* (k, mask) entries scheduled, LOW list          */
-    double  flops;            /* 2 n_b^3 K                                      */
+    double  flops;            /* 2 n_b^3 K; sub-leaf culling: 2 (n_b/2)^3 subtasks */
     double  symbolic_ms;      /* cull time (events), or -1 when not timed        */
     double  numeric_ms;       /* leaf-GEMM time (events), or -1 when not timed   */
+    int64_t subtasks;         /* sub-leaf culling: 32 x 32 sub-products performed */
+                              /* by the last spamm_numeric of the plan, else 0     */
 } spamm_stats;
 
 /* ---- operands -------------------------------------------------------------- */
@@ -105,10 +110,20 @@ typedef struct spamm_opts {
     double  tau;
     int32_t precision;
     double  low_tol;
+    int32_t sub_cull;   /* 1: sub-leaf culling (FP32, n_b = 64, trees built with     */
+                        /* SPAMM_TREE_SUBNORMS): inside every kept 64 x 64 leaf product */
+                        /* the 8 products of 32 x 32 sub-blocks are tested against tau */
+                        /* with their own norms and only the kept ones are multiplied  */
+                        /* (the paper's conditional products inside a leaf, Alg. 2);   */
+                        /* the performed set equals the cull of a tree with 32 x 32    */
+                        /* leaves.  0: whole leaf products.                             */
 } spamm_opts;
 
 /* As spamm_build_tree, with flags (SPAMM_TREE_BF16: also store BF16 copies of
- * every leaf, needed by split-precision products; leaf must be 32 or 64). */
+ * every leaf, needed by split-precision products; leaf must be 32 or 64.
+ * SPAMM_TREE_SUBNORMS: leaf must be 64; tiers 0..d+1 of norms, tier d+1 being
+ * the 32 x 32 sub-blocks, each a pairwise sum over its own row-major index,
+ * and every coarser tier the (s11 + s12) + (s21 + s22) of its children). */
 int spamm_build_tree_ex(const float *A, int64_t n, int32_t leaf, uint32_t flags, void *stream,
                         spamm_tree **out);
 
@@ -121,9 +136,9 @@ int spamm_tree_free(spamm_tree *tree);
 int spamm_tree_info(const spamm_tree *tree, int64_t *n, int32_t *leaf,
                     int32_t *depth, double *norm2);
 
-/* Copy tier `tier` (0..d) of the squared-norm pyramid to host memory as a
- * 2^tier x 2^tier row-major FP64 array (len >= 4^tier, else SPAMM_E_RANGE).
- * Synchronizes the tree's stream. */
+/* Copy tier `tier` (0..d, or 0..d+1 with SPAMM_TREE_SUBNORMS) of the
+ * squared-norm pyramid to host memory as a 2^tier x 2^tier row-major FP64
+ * array (len >= 4^tier, else SPAMM_E_RANGE).  Synchronizes the tree's stream. */
 int spamm_tree_norms(const spamm_tree *tree, int32_t tier, double *host, size_t len);
 
 /* Copy the zero-padded matrix held by the tree to host memory as an
@@ -153,7 +168,8 @@ int spamm_symbolic(const spamm_tree *A, const spamm_tree *B, double tau,
  * SPAMM_PREC_SPLIT_BF16 each kept leaf product is also classed LOW or HIGH
  * (see spamm_opts); both trees must have been built with SPAMM_TREE_BF16.
  * Errors as spamm_symbolic, plus SPAMM_E_INVAL for an unknown precision, a
- * bad low_tol (negative, NaN/Inf, 0 < low_tol < 1e-150) or missing BF16 copies.
+ * bad low_tol (negative, NaN/Inf, 0 < low_tol < 1e-150), missing BF16 copies,
+ * or sub_cull with split precision, n_b != 64 or trees without sub-norms.
  */
 int spamm_symbolic_ex(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
                       void *stream, spamm_plan **out);
@@ -176,6 +192,16 @@ int spamm_numeric(const spamm_plan *plan, float *C, void *stream);
  * Synchronizes the plan's stream.
  */
 int spamm_plan_tasks(const spamm_plan *plan, uint64_t *host, size_t cap, size_t *count);
+
+/*
+ * Sub-leaf culling: copy the 32 x 32 sub-products performed by the last
+ * spamm_numeric of the plan as sorted uint64 keys (linear_index(i, j) << 32) | k
+ * over the grid of 32 x 32 sub-blocks (i, j, k < 2N), i.e. the task keys of
+ * the same product on a tree with 32 x 32 leaves.  *count receives their
+ * number; cap too small -> SPAMM_E_RANGE.  SPAMM_E_INVAL when the plan does
+ * not cull sub-leaves.  Synchronizes the plan's stream.
+ */
+int spamm_plan_subtasks(const spamm_plan *plan, uint64_t *host, size_t cap, size_t *count);
 
 /* Kept counts per tier and work totals.  Synchronizes the plan's stream. */
 int spamm_plan_stats(const spamm_plan *plan, spamm_stats *out);

@@ -30,6 +30,7 @@ SPAMM_PENDING = 1
 PREC_FP32 = 0
 PREC_SPLIT_BF16 = 1
 TREE_BF16 = 1
+TREE_SUBNORMS = 2
 
 _lib = None
 
@@ -42,7 +43,7 @@ class SpammError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("low_tol", ctypes.c_double)]
+                ("low_tol", ctypes.c_double), ("sub_cull", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -57,6 +58,7 @@ class Stats(ctypes.Structure):
         ("flops", ctypes.c_double),
         ("symbolic_ms", ctypes.c_double),
         ("numeric_ms", ctypes.c_double),
+        ("subtasks", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -68,6 +70,7 @@ class Stats(ctypes.Structure):
             "block_entries_low": int(self.block_entries_low),
             "flops": float(self.flops), "symbolic_ms": float(self.symbolic_ms),
             "numeric_ms": float(self.numeric_ms),
+            "subtasks": int(self.subtasks),
         }
 
 
@@ -131,6 +134,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "spamm_symbolic": [vp, vp, dbl, vp, pp],
         "spamm_numeric": [vp, vp, vp],
         "spamm_plan_tasks": [vp, vp, sz, ctypes.POINTER(sz)],
+        "spamm_plan_subtasks": [vp, vp, sz, ctypes.POINTER(sz)],
         "spamm_plan_stats": [vp, ctypes.POINTER(Stats)],
         "spamm_plan_free": [vp],
         "spamm_multiply": [vp, vp, dbl, vp, vp],
@@ -256,6 +260,17 @@ class Plan:
                "spamm_plan_tasks")
         return out[:cnt.value]
 
+    def subtasks(self) -> np.ndarray:
+        """Sub-leaf culling: the 32 x 32 sub-products the last numeric pass
+        performed, as sorted keys on the 32 x 32 grid."""
+        cnt = ctypes.c_size_t()
+        _check(load().spamm_plan_subtasks(self.handle, None, 0, ctypes.byref(cnt)),
+               "spamm_plan_subtasks")
+        out = np.empty(max(cnt.value, 1), dtype=np.uint64)
+        _check(load().spamm_plan_subtasks(self.handle, out.ctypes.data, out.size,
+                                          ctypes.byref(cnt)), "spamm_plan_subtasks")
+        return out[:cnt.value]
+
     def numeric(self, C, stream=None):
         _device_matrix(C, "C")
         _check(load().spamm_numeric(self.handle, ctypes.c_void_p(C.data_ptr()), _stream(stream)),
@@ -274,20 +289,24 @@ class Plan:
             pass
 
 
-def build_tree(A, leaf: int, stream=None, bf16: bool = False) -> Tree:
-    """Quadtree of A; bf16=True also keeps BF16 leaf copies (split precision)."""
+def build_tree(A, leaf: int, stream=None, bf16: bool = False, subnorms: bool = False) -> Tree:
+    """Quadtree of A; bf16=True also keeps BF16 leaf copies (split precision);
+    subnorms=True (leaf 64) also keeps 32 x 32 sub-block norms (sub-leaf
+    culling)."""
     A = _device_matrix(A, "A")
     h = ctypes.c_void_p()
-    _check(load().spamm_build_tree_ex(ctypes.c_void_p(A.data_ptr()), A.shape[0], leaf,
-                                      TREE_BF16 if bf16 else 0, _stream(stream), ctypes.byref(h)),
+    flags = (TREE_BF16 if bf16 else 0) | (TREE_SUBNORMS if subnorms else 0)
+    _check(load().spamm_build_tree_ex(ctypes.c_void_p(A.data_ptr()), A.shape[0], leaf, flags,
+                                      _stream(stream), ctypes.byref(h)),
            "spamm_build_tree")
     t = Tree(h)
     t.bf16 = bool(bf16)
+    t.subnorms = bool(subnorms)
     return t
 
 
-def _opts(tau, precision, low_tol) -> Opts:
-    return Opts(float(tau), int(precision), float(low_tol))
+def _opts(tau, precision, low_tol, sub_cull=False) -> Opts:
+    return Opts(float(tau), int(precision), float(low_tol), 1 if sub_cull else 0)
 
 
 def relative_low_tol(A: Tree, B: Tree, theta: float) -> float:
@@ -297,9 +316,9 @@ def relative_low_tol(A: Tree, B: Tree, theta: float) -> float:
 
 
 def symbolic(A: Tree, B: Tree, tau: float, stream=None, precision: int = PREC_FP32,
-             low_tol: float = 0.0) -> Plan:
+             low_tol: float = 0.0, sub_cull: bool = False) -> Plan:
     h = ctypes.c_void_p()
-    o = _opts(tau, precision, low_tol)
+    o = _opts(tau, precision, low_tol, sub_cull)
     _check(load().spamm_symbolic_ex(A.handle, B.handle, ctypes.byref(o), _stream(stream),
                                     ctypes.byref(h)), "spamm_symbolic")
     return Plan(h, A, B)
@@ -315,13 +334,13 @@ def multiply(A: Tree, B: Tree, tau: float, C, stream=None):
 
 
 def multiply_ex(A: Tree, B: Tree, tau: float, C, stream=None, precision: int = PREC_FP32,
-                low_tol: float = 0.0) -> dict:
+                low_tol: float = 0.0, sub_cull: bool = False) -> dict:
     """C = A B under the SpAMM condition, timed (synchronizes); returns stats."""
     _device_matrix(C, "C")
     if C.shape[0] != A.n:
         raise ValueError("C has the wrong shape")
     st = Stats()
-    o = _opts(tau, precision, low_tol)
+    o = _opts(tau, precision, low_tol, sub_cull)
     _check(load().spamm_multiply_opts(A.handle, B.handle, ctypes.byref(o),
                                       ctypes.c_void_p(C.data_ptr()), _stream(stream),
                                       ctypes.byref(st)), "spamm_multiply_opts")

@@ -17,7 +17,7 @@
 
 namespace spamm {
 hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *tiles,
-                        float *tilesT, uint16_t *t16, uint16_t *tT16, double *norms,
+                        float *tilesT, uint16_t *t16, uint16_t *tT16, double *norms, bool sub,
                         hipStream_t s);
 hipError_t launch_cull(spamm_plan *p, hipStream_t s);
 hipError_t launch_gemm(const spamm_plan *p, float *C, hipStream_t s);
@@ -135,7 +135,7 @@ static PlanSizes plan_sizes(int d)
 // The plan's buffers in allocation order (split adds the LOW schedule).
 struct PlanBuf { void **dst; size_t bytes; };
 
-static int plan_bufs(spamm_plan *p, const PlanSizes &z, bool split, PlanBuf *out)
+static int plan_bufs(spamm_plan *p, const PlanSizes &z, bool split, bool sub, PlanBuf *out)
 {
     int k = 0;
     out[k++] = {(void **)&p->rowptr, z.rowptr};
@@ -145,11 +145,13 @@ static int plan_bufs(spamm_plan *p, const PlanSizes &z, bool split, PlanBuf *out
     out[k++] = {(void **)&p->partials, z.partials};
     out[k++] = {(void **)&p->browptr, z.browptr};
     out[k++] = {(void **)&p->bent, z.bent};
-    out[k++] = {(void **)&p->leafK, 2 * sizeof(uint64_t)};
+    out[k++] = {(void **)&p->leafK, 4 * sizeof(uint64_t)};
     if (split) {
         out[k++] = {(void **)&p->browptr_lo, z.browptr};
         out[k++] = {(void **)&p->bent_lo, z.bent};
     }
+    if (sub)
+        out[k++] = {(void **)&p->submask, z.bent};   // 4 bytes per leaf-tier entry
     return k;
 }
 
@@ -157,7 +159,7 @@ size_t plan_device_bytes(int depth, bool split)
 {
     spamm_plan dummy{};
     PlanBuf b[12];
-    const int k = plan_bufs(&dummy, plan_sizes(depth), split, b);
+    const int k = plan_bufs(&dummy, plan_sizes(depth), split, false, b);
     size_t total = 0;
     for (int i = 0; i < k; ++i)
         total += align256(b[i].bytes);
@@ -170,11 +172,11 @@ struct TreeLayout {
     size_t tiles, tilesT, t16, tT16, norms, total;
 };
 
-static TreeLayout tree_layout(int64_t np, int32_t d, bool bf16)
+static TreeLayout tree_layout(int64_t np, int32_t d, bool bf16, bool sub)
 {
     TreeLayout L{};
     const size_t tile = sizeof(float) * (size_t)np * (size_t)np;
-    const size_t norm = sizeof(double) * (size_t)tier_offset(d + 1);
+    const size_t norm = sizeof(double) * (size_t)tier_offset(d + (sub ? 2 : 1));
     size_t o = 0;
     L.tiles = o;
     o += align256(tile);
@@ -190,7 +192,7 @@ static TreeLayout tree_layout(int64_t np, int32_t d, bool bf16)
     return L;
 }
 
-size_t tree_device_bytes(int64_t n, int32_t leaf, bool bf16)
+size_t tree_device_bytes(int64_t n, int32_t leaf, bool bf16, bool sub)
 {
     int32_t d = 0;
     int64_t p = leaf;
@@ -198,7 +200,7 @@ size_t tree_device_bytes(int64_t n, int32_t leaf, bool bf16)
         p *= 2;
         d += 1;
     }
-    return tree_layout(p, d, bf16).total;
+    return tree_layout(p, d, bf16, sub).total;
 }
 
 int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hipStream_t s,
@@ -213,11 +215,14 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
         return fail(SPAMM_E_INVAL, "n = %lld < 1", (long long)n);
     if (leaf != 16 && leaf != 32 && leaf != 64)
         return fail(SPAMM_E_INVAL, "leaf = %d not in {16, 32, 64}", leaf);
-    if ((flags & ~SPAMM_TREE_BF16) != 0)
+    if ((flags & ~(SPAMM_TREE_BF16 | SPAMM_TREE_SUBNORMS)) != 0)
         return fail(SPAMM_E_INVAL, "unknown tree flags 0x%x", flags);
     const bool bf16 = (flags & SPAMM_TREE_BF16) != 0;
+    const bool sub = (flags & SPAMM_TREE_SUBNORMS) != 0;
     if (bf16 && leaf == 16)
         return fail(SPAMM_E_INVAL, "BF16 leaf copies need leaf 32 or 64");
+    if (sub && leaf != 64)
+        return fail(SPAMM_E_INVAL, "sub-block norms need leaf 64");
     int32_t d;
     int64_t np;
     int rc = tree_depth(n, leaf, &d, &np);
@@ -226,7 +231,7 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
     int dev;
     if ((rc = prepare_device(&dev)))
         return rc;
-    const TreeLayout L = tree_layout(np, d, bf16);
+    const TreeLayout L = tree_layout(np, d, bf16, sub);
 
     spamm_tree *t = new (std::nothrow) spamm_tree();
     if (!t)
@@ -237,6 +242,7 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
     t->np = np;
     t->leaf = leaf;
     t->depth = d;
+    t->sub = sub;
     hipError_t e = hipSuccess;
     if (arena != nullptr) {
         char *base = (char *)arena;
@@ -259,7 +265,8 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
             e = hipMallocAsync((void **)&t->norms, L.total - L.norms, s);
     }
     if (e == hipSuccess)
-        e = launch_build(A, n, leaf, d, t->tiles, t->tilesT, t->tiles16, t->tilesT16, t->norms, s);
+        e = launch_build(A, n, leaf, d, t->tiles, t->tilesT, t->tiles16, t->tilesT16, t->norms, sub,
+                         s);
     if (e == hipSuccess && root_dst != nullptr)
         e = hipMemcpyAsync(root_dst, t->norms, sizeof(double), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) {
@@ -301,6 +308,13 @@ int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *o
                     A->leaf, (long long)B->n, B->leaf);
     if (split && (A->tiles16 == nullptr || B->tilesT16 == nullptr))
         return fail(SPAMM_E_INVAL, "split precision needs trees built with SPAMM_TREE_BF16");
+    if (opts->sub_cull != 0 && opts->sub_cull != 1)
+        return fail(SPAMM_E_INVAL, "sub_cull = %d not in {0, 1}", opts->sub_cull);
+    const bool sub = opts->sub_cull == 1;
+    if (sub && (split || A->leaf != 64 || !A->sub || !B->sub))
+        return fail(SPAMM_E_INVAL,
+                    "sub-leaf culling needs FP32 precision and leaf-64 trees built with "
+                    "SPAMM_TREE_SUBNORMS");
     int dev;
     if ((rc = prepare_device(&dev)))
         return rc;
@@ -322,6 +336,7 @@ int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *o
     p->precision = opts->precision;
     p->low_tol = split ? opts->low_tol : 0.0;
     p->L2 = p->low_tol * p->low_tol;
+    p->sub = sub ? 1 : 0;
     const int d = p->depth;
     p->nblocks = d == 0 ? 1 : (int64_t(1) << (2 * (d - 1)));
 
@@ -329,7 +344,7 @@ int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *o
     for (int t = 0; t <= d; ++t)
         p->rp_off[t] = z.rp_off[t];
     PlanBuf bufs[12];
-    const int nb = plan_bufs(p, z, split, bufs);
+    const int nb = plan_bufs(p, z, split, sub, bufs);
     size_t off = 0;
     for (int i = 0; i < nb; ++i) {
         if (arena != nullptr) {
@@ -447,8 +462,9 @@ int spamm_tree_norms(const spamm_tree *t, int32_t tier, double *host, size_t len
 {
     if (t == nullptr || host == nullptr)
         return fail(SPAMM_E_INVAL, "NULL argument");
-    if (tier < 0 || tier > t->depth)
-        return fail(SPAMM_E_INVAL, "tier %d outside 0..%d", tier, t->depth);
+    const int top = t->depth + (t->sub ? 1 : 0);
+    if (tier < 0 || tier > top)
+        return fail(SPAMM_E_INVAL, "tier %d outside 0..%d", tier, top);
     const int64_t Nt = int64_t(1) << tier;
     if (len < (size_t)(Nt * Nt))
         return fail(SPAMM_E_RANGE, "host buffer holds %zu < %lld values", len, (long long)(Nt * Nt));
@@ -514,7 +530,7 @@ int spamm_plan_free(spamm_plan *p)
 int spamm_symbolic(const spamm_tree *A, const spamm_tree *B, double tau, void *stream,
                    spamm_plan **out)
 {
-    spamm_opts o;
+    spamm_opts o{};
     o.tau = tau;
     o.precision = SPAMM_PREC_FP32;
     o.low_tol = 0.0;
@@ -551,11 +567,12 @@ int spamm_plan_stats(const spamm_plan *p, spamm_stats *out)
                                sizeof(uint32_t), hipMemcpyDeviceToHost, p->stream),
                 "hipMemcpyAsync");
     const bool split = p->precision != SPAMM_PREC_FP32;
-    uint64_t K[2] = {0, 0};
+    uint64_t K[3] = {0, 0, 0};
     uint32_t entries[2] = {0, 0};
-    HIP_TRY(hipMemcpyAsync(K, p->leafK, (split ? 2 : 1) * sizeof(uint64_t), hipMemcpyDeviceToHost,
-                           p->stream),
+    HIP_TRY(hipMemcpyAsync(K, p->leafK, (p->sub ? 3 : split ? 2 : 1) * sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, p->stream),
             "hipMemcpyAsync");
+    // the FP32 cull writes only the HIGH count; the LOW slot is not initialized
     HIP_TRY(hipMemcpyAsync(&entries[0], p->browptr + p->nblocks, sizeof(uint32_t),
                            hipMemcpyDeviceToHost, p->stream),
             "hipMemcpyAsync");
@@ -564,6 +581,8 @@ int spamm_plan_stats(const spamm_plan *p, spamm_stats *out)
                                hipMemcpyDeviceToHost, p->stream),
                 "hipMemcpyAsync");
     HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+    if (!split)
+        K[1] = 0;
     const int64_t all = (int64_t)(K[0] + K[1]);
     for (int t = 0; t < d; ++t)
         out->kept[t] = tot[(size_t)t];
@@ -573,6 +592,11 @@ int spamm_plan_stats(const spamm_plan *p, spamm_stats *out)
     out->block_entries = entries[0];
     out->block_entries_low = entries[1];
     out->flops = 2.0 * (double)p->leaf * p->leaf * p->leaf * (double)all;
+    if (p->sub) {
+        const double h = p->leaf / 2;
+        out->subtasks = (int64_t)K[2];
+        out->flops = 2.0 * h * h * h * (double)K[2];
+    }
     return SPAMM_OK;
 }
 
@@ -649,6 +673,60 @@ int spamm_plan_tasks(const spamm_plan *p, uint64_t *host, size_t cap, size_t *co
     return SPAMM_OK;
 }
 
+int spamm_plan_subtasks(const spamm_plan *p, uint64_t *host, size_t cap, size_t *count)
+{
+    if (p == nullptr || count == nullptr)
+        return fail(SPAMM_E_INVAL, "NULL argument");
+    if (!p->sub)
+        return fail(SPAMM_E_INVAL, "the plan does not cull sub-leaves");
+    uint64_t K[3] = {0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(K, p->leafK, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, p->stream),
+            "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+    *count = (size_t)K[2];
+    if (host == nullptr || cap < K[2])
+        return host == nullptr && cap == 0 ? SPAMM_OK
+                                           : fail(SPAMM_E_RANGE, "cap %zu < %llu sub-products", cap,
+                                                  (unsigned long long)K[2]);
+    std::vector<uint32_t> rp, ent;
+    int rc = fetch_schedule(p, p->browptr, p->bent, rp, ent);
+    if (rc != SPAMM_OK)
+        return rc;
+    std::vector<uint8_t> mask(4 * ent.size());
+    if (!mask.empty()) {
+        HIP_TRY(hipMemcpyAsync(mask.data(), p->submask, mask.size(), hipMemcpyDeviceToHost,
+                               p->stream),
+                "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+    }
+    // leaf (I, J) = child q of block P; its sub-leaf (a, b) has linear index
+    // 4 lin(I, J) + 2a + b on the 32 x 32 grid and takes sub-product (k, c) as
+    // k32 = 2k + c: leaves, then sub-leaves, then k, then c ascending is the
+    // sorted order.
+    const size_t nb = (size_t)p->nblocks;
+    size_t o = 0;
+    for (size_t P = 0; P < nb; ++P)
+        for (uint32_t q = 0; q < 4; ++q) {
+            const uint64_t lc = p->depth == 0 ? 0 : 4 * (uint64_t)P + q;
+            for (uint32_t ab = 0; ab < 4; ++ab)
+                for (uint32_t e = rp[P]; e < rp[P + 1]; ++e) {
+                    const uint32_t m = mask[4 * (size_t)e + q];
+                    const uint64_t k = ent[e] & 0xFFFFu;
+                    for (uint32_t c = 0; c < 2; ++c) {
+                        if (!((m >> (2 * ab + c)) & 1u))
+                            continue;
+                        if (o >= cap)
+                            return fail(SPAMM_E_RANGE, "inconsistent sub-product count");
+                        host[o++] = ((4 * lc + ab) << 32) | (2 * k + c);
+                    }
+                }
+        }
+    if (o != K[2])
+        return fail(SPAMM_E_HIP, "sub-product count mismatch: %zu expanded vs %llu counted", o,
+                    (unsigned long long)K[2]);
+    return SPAMM_OK;
+}
+
 int spamm_multiply_opts(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
                         float *C, void *stream, spamm_stats *stats)
 {
@@ -692,7 +770,7 @@ int spamm_multiply_opts(const spamm_tree *A, const spamm_tree *B, const spamm_op
 int spamm_multiply_ex(const spamm_tree *A, const spamm_tree *B, double tau, float *C, void *stream,
                       spamm_stats *stats)
 {
-    spamm_opts o;
+    spamm_opts o{};
     o.tau = tau;
     o.precision = SPAMM_PREC_FP32;
     o.low_tol = 0.0;

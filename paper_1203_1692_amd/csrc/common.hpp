@@ -137,6 +137,12 @@ struct GemmJob {
     uint32_t nblocks, block0;
     int32_t single;        // depth 0: one leaf
     int32_t accumulate;    // add to C (second pass of a split product)
+    // sub-leaf culling (n_b = 64, 32 x 32 sub-blocks), else null
+    const double *subA;    // tier d+1 norms of A: 4 per leaf, child 2a + c
+    const double *subB;    // tier d+1 norms of B
+    double T2;             // tau^2
+    uint8_t *submask;      // per (entry, wave): performed sub-products, bit 2(2a+b)+c
+    unsigned long long *subK;  // count of performed sub-products
 };
 
 constexpr int kMaxJobs = 16;
@@ -159,9 +165,10 @@ struct spamm_tree {
     float *tilesT;          // the same leaves transposed (right-operand copy), LeafLayout
     uint16_t *tiles16;      // BF16 left-operand copy (Leaf16Layout), or null
     uint16_t *tilesT16;     // BF16 right-operand (transposed) copy, or null
-    double *norms;          // tiers 0..d, tier_offset layout
+    double *norms;          // tiers 0..d (0..d+1 with sub-norms), tier_offset layout
     double root;            // ||A||_F^2
     bool borrowed;          // buffers carved from a caller's arena (not freed here)
+    bool sub;               // tier d+1 holds the norms of the 32 x 32 sub-blocks (n_b = 64)
 };
 
 struct spamm_plan {
@@ -186,7 +193,9 @@ struct spamm_plan {
     uint32_t *bent;
     uint32_t *browptr_lo;   // LOW (BF16) products, split precision only
     uint32_t *bent_lo;
-    uint64_t *leafK;        // [0] kept leaf triples, [1] of which LOW
+    uint64_t *leafK;        // [0] kept leaf triples, [1] of which LOW, [2] sub-products done
+    uint8_t *submask;       // sub-leaf culling: 4 bytes per leaf-tier entry, else null
+    int32_t sub;            // sub-leaf culling in the numeric multiply
     int64_t nblocks;
     void *pool[12];         // allocations owned by the plan
     int npool;

@@ -112,6 +112,44 @@ __device__ inline void panel_mfma32(const float *__restrict__ Ap, const float *_
     }
 }
 
+// As panel_mfma32, with the sub-leaf culling mask of this panel: accumulator
+// (i, j) takes the panel only if bit 2 i + j of `pm` is set (wave-uniform).
+template <int B>
+__device__ inline void panel_mfma32_sub(const float *__restrict__ Ap, const float *__restrict__ Bp,
+                                        floatx16 (&acc)[B / 32][B / 32], int lane, uint32_t pm)
+{
+    using L = LeafLayout<B>;
+    constexpr int MB = B / 32;
+    constexpr int NG = L::kKS / 8;
+    const int r = lane & 31, h = lane >> 5;
+    floatx4 av[2][MB], bv[2][MB];
+    auto load = [&](int buf, int g) {
+        const int c = (L::kKS / 2) * h + 4 * g;
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+            av[buf][i] = *reinterpret_cast<const floatx4 *>(Ap + L::pindex(i * 32 + r, c));
+#pragma unroll
+        for (int j = 0; j < MB; ++j)
+            bv[buf][j] = *reinterpret_cast<const floatx4 *>(Bp + L::pindex(j * 32 + r, c));
+    };
+    load(0, 0);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        if (g + 1 < NG)
+            load((g + 1) & 1, g + 1);
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < MB; ++j)
+                if ((pm >> (i * MB + j)) & 1u) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                            av[g & 1][i][s], bv[g & 1][j][s], acc[i][j], 0, 0, 0);
+                }
+    }
+}
+
 __device__ inline void panel_mfma16(const float *__restrict__ Ap, const float *__restrict__ Bp,
                                     floatx4 &acc, int lane)
 {
@@ -172,7 +210,12 @@ __device__ inline int job_of(const GemmJobs &jobs, uint32_t bid)
     return j;
 }
 
-template <int B>
+// SUB (n_b = 64): sub-leaf culling.  For its leaf product A_(2I+a', k) B_(k, 2J+b')
+// a wave tests the 8 products of 32 x 32 sub-blocks A_(a, c) B_(c, b) against
+// tau with the stored sub-block norms (tier d+1) and runs the MFMAs of
+// accumulator (a, b) on k-panel c only for the kept ones.  The performed set
+// is written per (entry, wave) to submask and counted in subK.
+template <int B, bool SUB>
 __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
 {
     using L = LeafLayout<B>;
@@ -213,6 +256,7 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
     if (accumulate && e0 == e1)
         return;
     const uint32_t T = (e1 - e0) * NP;                  // stages of this block
+    uint32_t smask = 0, sub_count = 0;                  // SUB: this entry's kept sub-products
     if (T > 0)
         stage_issue<B>(bent[e0], 0, tA, tBT, I0, J0, smem, w, lane);
     for (uint32_t t = 0; t < T; ++t) {
@@ -224,15 +268,49 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
         if (t + 1 < T)
             stage_issue<B>(bent[e0 + (t + 1) / NP], (int)((t + 1) % NP), tA, tBT, I0, J0,
                            smem + ((t + 1) & 1) * S::kStage, w, lane);
-        if ((ent >> (16 + w)) & 1u) {
+        const bool mine = (ent >> (16 + w)) & 1u;
+        if constexpr (SUB) {
+            if (t % NP == 0) {
+                smask = 0;
+                if (mine) {
+                    const uint32_t k = ent & 0xFFFFu;
+                    const double *sa = job.subA + 4 * (int64_t)lin_index(I0 + qa, k);
+                    const double *sb = job.subB + 4 * (int64_t)lin_index(k, J0 + qb);
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b)
+#pragma unroll
+                            for (int c = 0; c < 2; ++c)
+                                smask |= keep_pair(sa[2 * a + c], sb[2 * c + b], job.T2)
+                                             ? 1u << (2 * (2 * a + b) + c) : 0u;
+                    sub_count += __builtin_popcount(smask);
+                }
+                if (lane == 0)
+                    job.submask[4 * (int64_t)(e0 + t / NP) + w] = (uint8_t)smask;
+            }
+        }
+        if (mine) {
             const float *buf = smem + (t & 1) * S::kStage;
             const float *Ap = buf + qa * L::kPanel;
             const float *Bp = buf + (2 + qb) * L::kPanel;
-            if constexpr (B >= 32)
+            if constexpr (SUB) {
+                // accumulator (a, b) on panel c = t % NP
+                const uint32_t c = t % NP;
+                const uint32_t pm = ((smask >> c) & 1u) | ((smask >> (1 + c)) & 2u) |
+                                    ((smask >> (2 + c)) & 4u) | ((smask >> (3 + c)) & 8u);
+                if (pm != 0u)
+                    panel_mfma32_sub<B>(Ap, Bp, acc, lane, pm);
+            } else if constexpr (B >= 32) {
                 panel_mfma32<B>(Ap, Bp, acc, lane);
-            else
+            } else {
                 panel_mfma16(Ap, Bp, acc16, lane);
+            }
         }
+    }
+    if constexpr (SUB) {
+        if (lane == 0 && sub_count != 0)
+            atomicAdd(job.subK, (unsigned long long)sub_count);
     }
 
     if (single && w != 0)
@@ -338,16 +416,17 @@ __global__ __launch_bounds__(256) void leaf_gemm_bf16(const GemmJobs jobs)
     write_leaf32<B>(acc, (int64_t)(I0 + qa) * B, (int64_t)(J0 + qb) * B, n, C, 0, lane);
 }
 
-template <int B>
+template <int B, bool SUB>
 static hipError_t launch_fp32(const GemmJobs &jobs, hipStream_t s)
 {
     using S = GemmShape<B>;
     // once per process (thread-safe static initialization)
-    static const hipError_t attr = hipFuncSetAttribute(
-        (const void *)leaf_gemm<B>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::kLds);
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void *)leaf_gemm<B, SUB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::kLds);
     if (attr != hipSuccess)
         return attr;
-    hipLaunchKernelGGL(leaf_gemm<B>, dim3(jobs.nblocks), dim3(256), S::kLds, s, jobs);
+    hipLaunchKernelGGL((leaf_gemm<B, SUB>), dim3(jobs.nblocks), dim3(256), S::kLds, s, jobs);
     return hipGetLastError();
 }
 
@@ -364,11 +443,13 @@ static hipError_t launch_bf16(const GemmJobs &jobs, hipStream_t s)
 }
 
 // One batched launch of the FP32 (bf16 = false) or BF16 leaf GEMM over the
-// jobs' blocks; all jobs share the leaf size.
-hipError_t launch_gemm_jobs(int leaf, bool bf16, const GemmJobs &jobs, hipStream_t s)
+// jobs' blocks; all jobs share the leaf size (and sub-leaf culling, n_b = 64).
+hipError_t launch_gemm_jobs(int leaf, bool bf16, const GemmJobs &jobs, hipStream_t s, bool sub)
 {
     if (jobs.njobs <= 0 || jobs.nblocks == 0)
         return hipSuccess;
+    if (sub)
+        return leaf == 64 && !bf16 ? launch_fp32<64, true>(jobs, s) : hipErrorInvalidValue;
     if (bf16) {
         switch (leaf) {
         case 32: return launch_bf16<32>(jobs, s);
@@ -377,9 +458,9 @@ hipError_t launch_gemm_jobs(int leaf, bool bf16, const GemmJobs &jobs, hipStream
         }
     }
     switch (leaf) {
-    case 16: return launch_fp32<16>(jobs, s);
-    case 32: return launch_fp32<32>(jobs, s);
-    case 64: return launch_fp32<64>(jobs, s);
+    case 16: return launch_fp32<16, false>(jobs, s);
+    case 32: return launch_fp32<32, false>(jobs, s);
+    case 64: return launch_fp32<64, false>(jobs, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -397,6 +478,16 @@ void plan_jobs(const spamm_plan *p, float *C, bool bf16, GemmJob &j)
     j.block0 = 0;
     j.single = p->depth == 0 ? 1 : 0;
     j.accumulate = (!bf16 && p->precision != SPAMM_PREC_FP32) ? 1 : 0;
+    j.subA = j.subB = nullptr;
+    j.submask = nullptr;
+    j.subK = nullptr;
+    j.T2 = p->T2;
+    if (p->sub) {
+        j.subA = p->A->norms + tier_offset(p->depth + 1);
+        j.subB = p->B->norms + tier_offset(p->depth + 1);
+        j.submask = p->submask;
+        j.subK = (unsigned long long *)(p->leafK + 2);
+    }
 }
 
 // FP32: one pass.  Split: the BF16 pass writes C, then the FP32 pass adds the
@@ -409,11 +500,13 @@ hipError_t launch_gemm(const spamm_plan *p, float *C, hipStream_t s)
     hipError_t e;
     if (p->precision != SPAMM_PREC_FP32) {
         plan_jobs(p, C, true, jobs.job[0]);
-        if ((e = launch_gemm_jobs(p->leaf, true, jobs, s)) != hipSuccess)
+        if ((e = launch_gemm_jobs(p->leaf, true, jobs, s, false)) != hipSuccess)
             return e;
     }
+    if (p->sub && (e = hipMemsetAsync(p->leafK + 2, 0, sizeof(uint64_t), s)) != hipSuccess)
+        return e;
     plan_jobs(p, C, false, jobs.job[0]);
-    return launch_gemm_jobs(p->leaf, false, jobs, s);
+    return launch_gemm_jobs(p->leaf, false, jobs, s, p->sub != 0);
 }
 
 }  // namespace spamm

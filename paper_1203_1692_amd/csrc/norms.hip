@@ -53,7 +53,16 @@ __device__ inline void store_bf16x4(uint16_t *dst, float4 v)
 // Each leaf is stored twice in LeafLayout: as is (left-operand copy) and
 // transposed through LDS (right-operand copy), so that the GEMM reads both of
 // its operands along k with contiguous 16-byte loads.
-template <int B, int VEC>
+//
+// SUB (n_b = 64, sub-leaf culling): the norms are those of a tree with 32 x 32
+// leaves one tier deeper.  Sub-block (a, b) (rows 32a.., columns 32b..) is
+// summed pairwise over its own row-major flattened index f = 32 r' + c'; in
+// the load pattern above its bits are f0-1 = in-lane, f2-4 = lane bits 0-2,
+// f5-6 = lane bits 4-5, f7-9 = m bits 0-2, while lane bit 3 is b and m bit 3
+// is a.  So the butterfly skips lane bit 3, the register tree stops below m
+// bit 3, and the leaf norm is the parent of its four sub-blocks:
+// (s_00 + s_01) + (s_10 + s_11), written to sub_norm[4 l + 2a + b].
+template <int B, int VEC, bool SUB>
 __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ A, int64_t n,
                                                       float *__restrict__ tiles,
                                                       float *__restrict__ tilesT,
@@ -61,8 +70,10 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
                                                       uint16_t *__restrict__ tilesT16,
                                                       double *__restrict__ leaf_norm,
                                                       double *__restrict__ parent,
+                                                      double *__restrict__ sub_norm,
                                                       uint32_t ntiles)
 {
+    static_assert(!SUB || B == 64, "sub-block norms are built for 64 x 64 leaves");
     using L = LeafLayout<B>;
     constexpr int M = (B * B) / 256;   // float4 loads per lane
     constexpr int P = B + 1;           // LDS pitch of the transpose buffer
@@ -103,17 +114,40 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
             double t = (x0 * x0 + x1 * x1) + (x2 * x2 + x3 * x3);
 #pragma unroll
             for (int o2 = 1; o2 < 64; o2 <<= 1)
-                t += __shfl_xor(t, o2);
+                if (!SUB || o2 != 8)
+                    t += __shfl_xor(t, o2);
             sm[m] = t;
         }
+        if constexpr (SUB) {
 #pragma unroll
-        for (int st = 1; st < M; st <<= 1)
+            for (int st = 1; st < M / 2; st <<= 1)
 #pragma unroll
-            for (int i = 0; i < M; i += 2 * st)
-                sm[i] += sm[i + st];
-        s = sm[0];
-        if (lane == 0)
-            leaf_norm[l] = s;
+                for (int i = 0; i < M; i += 2 * st)
+                    sm[i] += sm[i + st];
+            // sm[0]: sub-row a = 0, sm[M/2]: a = 1, for this lane's sub-column
+            const double o0 = __shfl_xor(sm[0], 8), o1 = __shfl_xor(sm[M / 2], 8);
+            const bool right = (lane >> 3) & 1;
+            const double s00 = right ? o0 : sm[0], s01 = right ? sm[0] : o0;
+            const double s10 = right ? o1 : sm[M / 2], s11 = right ? sm[M / 2] : o1;
+            s = (s00 + s01) + (s10 + s11);
+            if (lane == 0) {
+                double *sn = sub_norm + 4 * (int64_t)l;
+                sn[0] = s00;
+                sn[1] = s01;
+                sn[2] = s10;
+                sn[3] = s11;
+                leaf_norm[l] = s;
+            }
+        } else {
+#pragma unroll
+            for (int st = 1; st < M; st <<= 1)
+#pragma unroll
+                for (int i = 0; i < M; i += 2 * st)
+                    sm[i] += sm[i + st];
+            s = sm[0];
+            if (lane == 0)
+                leaf_norm[l] = s;
+        }
     }
     __syncthreads();
     if (valid) {
@@ -153,36 +187,39 @@ __global__ __launch_bounds__(1024) void norm_pyramid(double *__restrict__ norms,
     }
 }
 
-template <int B, int VEC>
+template <int B, int VEC, bool SUB>
 static hipError_t launch_leaf_v(const float *A, int64_t n, float *tiles, float *tilesT,
                                 uint16_t *t16, uint16_t *tT16, double *leaf, double *parent,
-                                uint32_t ntiles, hipStream_t s)
+                                double *sub, uint32_t ntiles, hipStream_t s)
 {
     constexpr size_t lds = sizeof(float) * 4 * B * (B + 1);
     // once per process (thread-safe static initialization)
-    static const hipError_t attr = hipFuncSetAttribute(
-        (const void *)leaf_norm_pack<B, VEC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void *)leaf_norm_pack<B, VEC, SUB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (attr != hipSuccess)
         return attr;
-    hipLaunchKernelGGL((leaf_norm_pack<B, VEC>), dim3((ntiles + 3) / 4), dim3(256), lds, s, A, n,
-                       tiles, tilesT, t16, tT16, leaf, parent, ntiles);
+    hipLaunchKernelGGL((leaf_norm_pack<B, VEC, SUB>), dim3((ntiles + 3) / 4), dim3(256), lds, s, A,
+                       n, tiles, tilesT, t16, tT16, leaf, parent, sub, ntiles);
     return hipGetLastError();
 }
 
-template <int B>
+template <int B, bool SUB>
 static hipError_t launch_leaf(const float *A, int64_t n, int vec, float *tiles, float *tilesT,
                               uint16_t *t16, uint16_t *tT16, double *leaf, double *parent,
-                              uint32_t ntiles, hipStream_t s)
+                              double *sub, uint32_t ntiles, hipStream_t s)
 {
     if (vec == 4)
-        return launch_leaf_v<B, 4>(A, n, tiles, tilesT, t16, tT16, leaf, parent, ntiles, s);
+        return launch_leaf_v<B, 4, SUB>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, ntiles, s);
     if (vec == 2)
-        return launch_leaf_v<B, 2>(A, n, tiles, tilesT, t16, tT16, leaf, parent, ntiles, s);
-    return launch_leaf_v<B, 1>(A, n, tiles, tilesT, t16, tT16, leaf, parent, ntiles, s);
+        return launch_leaf_v<B, 2, SUB>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, ntiles, s);
+    return launch_leaf_v<B, 1, SUB>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, ntiles, s);
 }
 
+// sub (n_b = 64 only): norms hold tiers 0..depth+1, tier depth+1 being the
+// 32 x 32 sub-blocks; otherwise tiers 0..depth.
 hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *tiles,
-                        float *tilesT, uint16_t *t16, uint16_t *tT16, double *norms,
+                        float *tilesT, uint16_t *t16, uint16_t *tT16, double *norms, bool sub,
                         hipStream_t s)
 {
     const uintptr_t addr = reinterpret_cast<uintptr_t>(A);
@@ -190,11 +227,25 @@ hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *t
     const uint32_t ntiles = 1u << (2 * depth);
     double *leafn = norms + tier_offset(depth);
     double *parent = depth >= 1 ? norms + tier_offset(depth - 1) : nullptr;
+    double *subn = sub ? norms + tier_offset(depth + 1) : nullptr;
+    if (sub && leaf != 64)
+        return hipErrorInvalidValue;
     hipError_t e;
     switch (leaf) {
-    case 16: e = launch_leaf<16>(A, n, vec, tiles, tilesT, nullptr, nullptr, leafn, parent, ntiles, s); break;
-    case 32: e = launch_leaf<32>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent, ntiles, s); break;
-    case 64: e = launch_leaf<64>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent, ntiles, s); break;
+    case 16:
+        e = launch_leaf<16, false>(A, n, vec, tiles, tilesT, nullptr, nullptr, leafn, parent,
+                                   nullptr, ntiles, s);
+        break;
+    case 32:
+        e = launch_leaf<32, false>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent, nullptr,
+                                   ntiles, s);
+        break;
+    case 64:
+        e = sub ? launch_leaf<64, true>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent, subn,
+                                        ntiles, s)
+                : launch_leaf<64, false>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent,
+                                         nullptr, ntiles, s);
+        break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess || depth < 2)

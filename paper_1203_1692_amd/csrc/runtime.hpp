@@ -35,12 +35,13 @@ int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *o
 
 // Device bytes of one tree / one plan of depth d, buffers at 256-byte
 // aligned offsets (the arena sizes; also admission control).
-size_t tree_device_bytes(int64_t n, int32_t leaf, bool bf16);
+size_t tree_device_bytes(int64_t n, int32_t leaf, bool bf16, bool sub = false);
 size_t plan_device_bytes(int depth, bool split);
 
 // Leaf GEMM launches (gemm.hip).
 void plan_jobs(const spamm_plan *p, float *C, bool bf16, GemmJob &j);
-hipError_t launch_gemm_jobs(int leaf, bool bf16, const GemmJobs &jobs, hipStream_t s);
+hipError_t launch_gemm_jobs(int leaf, bool bf16, const GemmJobs &jobs, hipStream_t s,
+                            bool sub = false);
 
 // Steady clock in microseconds (request timestamps).
 double now_us();

@@ -161,7 +161,7 @@ int start_step(spamm_server *S, Active &a)
     } else {
         a.tB = a.tA;
     }
-    spamm_opts o;
+    spamm_opts o{};
     o.tau = r.tau;
     o.precision = r.precision;
     o.low_tol = a.split ? r.low_tol : 0.0;
