@@ -185,3 +185,24 @@ def spamm_tiles(A: np.ndarray, B: np.ndarray, b: int, tau: float, tiles,
     if rc:
         raise RuntimeError(f"oracle_spamm_tiles -> {rc}")
     return Ct, counts, kl
+
+
+def sparsify(A: np.ndarray, b: int, tau: float, norm2_other: float = 0.0):
+    """Epsilon-sparsification of Sec. II.C (Eq. epsilon), at leaf granularity.
+
+    epsilon = tau / max(||A||_F, ||B||_F): a leaf is dropped (zeroed) when its
+    squared norm s is 0 or when s * m < tau^2 with m = max(||A||_F^2,
+    norm2_other), all in FP64 on the stored squared norms (the root is that
+    of A's full pyramid).  Returns (A with the dropped leaves zeroed, FP32,
+    same shape; boolean N x N mask of kept leaves).
+    """
+    A = _f32(A)
+    s = norms(A, b)
+    leaf = s[-1]
+    m = max(float(s[0][0, 0]), float(norm2_other))
+    keep = (leaf > 0.0) & ~(leaf * m < tau * tau)
+    n = A.shape[0]
+    out = A.copy()
+    for I, J in zip(*np.nonzero(~keep)):
+        out[I * b:min((I + 1) * b, n), J * b:min((J + 1) * b, n)] = 0.0
+    return out, keep
