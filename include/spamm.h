@@ -127,6 +127,34 @@ typedef struct spamm_opts {
 int spamm_build_tree_ex(const float *A, int64_t n, int32_t leaf, uint32_t flags, void *stream,
                         spamm_tree **out);
 
+/*
+ * Build the epsilon-sparsified quadtree of A (Sec. II.C, Eq. epsilon):
+ * epsilon = tau / max(||A||_F, ||B||_F); a leaf is dropped (a NULL node: not
+ * stored, norm 0) when its squared norm s is 0 or fl64(s * m) < fl64(tau^2),
+ * with m = max(||A||_F^2, norm2_other) and ||A||_F^2 the root of A's full
+ * pyramid.  Coarser tiers are rebuilt over the kept leaves ((s11 + s12) +
+ * (s21 + s22)), so the tree is that of A with its dropped leaves zeroed.
+ * Only the kept leaves are packed (same layout as spamm_build_tree, addressed
+ * through a per-leaf slot map), so storage follows the kept leaves instead of
+ * N^2.  A dropped leaf can never pass the product's test against any leaf of
+ * an operand whose squared norm is at most m, so a product of sparsified
+ * trees keeps the same leaf products as the dense trees and gives the same C.
+ *   tau          the tolerance of the products the tree will take part in.
+ *   norm2_other  ||B||_F^2 of the other operand (0 for a square A A).
+ *   flags        0 or SPAMM_TREE_BF16.
+ * Synchronizes `stream` once (kept-leaf count and roots).  spamm_tree_info's
+ * norm2 is ||A_sparsified||_F^2.  NaN/Inf anywhere in A -> SPAMM_E_NONFINITE.
+ * Errors as spamm_build_tree_ex, plus SPAMM_E_INVAL for a bad tau or
+ * norm2_other (negative, NaN/Inf) or SPAMM_TREE_SUBNORMS.
+ */
+int spamm_build_tree_sparse(const float *A, int64_t n, int32_t leaf, uint32_t flags, double tau,
+                            double norm2_other, void *stream, spamm_tree **out);
+
+/* Storage of a tree: leaves stored (N^2 for a dense tree), N^2, and the device
+ * bytes it holds (leaf copies, norm pyramid, slot map).  Outputs may be NULL. */
+int spamm_tree_storage(const spamm_tree *tree, int64_t *leaves_stored, int64_t *leaves_total,
+                       size_t *device_bytes);
+
 /* Release a tree (stream-ordered on the stream it was built on; work on other
  * streams that uses the tree must be complete).  NULL is a no-op. */
 int spamm_tree_free(spamm_tree *tree);

@@ -127,6 +127,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "spamm_symbolic_ex": [vp, vp, ctypes.POINTER(Opts), vp, pp],
         "spamm_multiply_opts": [vp, vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Stats)],
         "spamm_tree_free": [vp],
+        "spamm_build_tree_sparse": [vp, i64, i32, ctypes.c_uint32, dbl, dbl, vp, pp],
+        "spamm_tree_storage": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(sz)],
         "spamm_tree_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
                             ctypes.POINTER(dbl)],
         "spamm_tree_norms": [vp, i32, vp, sz],
@@ -222,6 +224,13 @@ class Tree:
                "spamm_tree_matrix")
         return out
 
+    def storage(self) -> dict:
+        """Leaves stored, leaves in the grid, device bytes held."""
+        st, tot, by = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+        _check(load().spamm_tree_storage(self.handle, ctypes.byref(st), ctypes.byref(tot),
+                                         ctypes.byref(by)), "spamm_tree_storage")
+        return {"stored": st.value, "total": tot.value, "bytes": by.value}
+
     def free(self):
         if self._h is not None:
             _check(load().spamm_tree_free(self._h), "spamm_tree_free")
@@ -302,6 +311,22 @@ def build_tree(A, leaf: int, stream=None, bf16: bool = False, subnorms: bool = F
     t = Tree(h)
     t.bf16 = bool(bf16)
     t.subnorms = bool(subnorms)
+    return t
+
+
+def build_tree_sparse(A, leaf: int, tau: float, norm2_other: float = 0.0, stream=None,
+                      bf16: bool = False) -> Tree:
+    """Epsilon-sparsified quadtree of A: leaves with norm below
+    tau / max(||A||_F, sqrt(norm2_other)) are dropped and not stored."""
+    A = _device_matrix(A, "A")
+    h = ctypes.c_void_p()
+    _check(load().spamm_build_tree_sparse(ctypes.c_void_p(A.data_ptr()), A.shape[0], leaf,
+                                          TREE_BF16 if bf16 else 0, float(tau), float(norm2_other),
+                                          _stream(stream), ctypes.byref(h)),
+           "spamm_build_tree_sparse")
+    t = Tree(h)
+    t.bf16 = bool(bf16)
+    t.subnorms = False
     return t
 
 

@@ -21,7 +21,6 @@ hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *t
                         hipStream_t s);
 hipError_t launch_cull(spamm_plan *p, hipStream_t s);
 hipError_t launch_gemm(const spamm_plan *p, float *C, hipStream_t s);
-size_t scan_partials_len(uint32_t m);
 }  // namespace spamm
 
 using namespace spamm;
@@ -243,6 +242,7 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
     t->leaf = leaf;
     t->depth = d;
     t->sub = sub;
+    t->stored = int64_t(1) << (2 * d);
     hipError_t e = hipSuccess;
     if (arena != nullptr) {
         char *base = (char *)arena;
@@ -420,7 +420,125 @@ int spamm_build_tree_ex(const float *A, int64_t n, int32_t leaf, uint32_t flags,
         return fail(SPAMM_E_NONFINITE, "input matrix holds NaN or Inf (||A||_F^2 = %g)", root);
     }
     t->root = root;
+    t->root_dense = root;
     *out = t;
+    return SPAMM_OK;
+}
+
+int spamm_build_tree_sparse(const float *A, int64_t n, int32_t leaf, uint32_t flags, double tau,
+                            double norm2_other, void *stream, spamm_tree **out)
+{
+    if (out == nullptr)
+        return fail(SPAMM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (A == nullptr)
+        return fail(SPAMM_E_INVAL, "A is NULL");
+    if (n < 1)
+        return fail(SPAMM_E_INVAL, "n = %lld < 1", (long long)n);
+    if (leaf != 16 && leaf != 32 && leaf != 64)
+        return fail(SPAMM_E_INVAL, "leaf = %d not in {16, 32, 64}", leaf);
+    if ((flags & ~SPAMM_TREE_BF16) != 0)
+        return fail(SPAMM_E_INVAL, "flags 0x%x: a sparsified tree takes SPAMM_TREE_BF16 only",
+                    flags);
+    const bool bf16 = (flags & SPAMM_TREE_BF16) != 0;
+    if (bf16 && leaf == 16)
+        return fail(SPAMM_E_INVAL, "BF16 leaf copies need leaf 32 or 64");
+    int rc;
+    if ((rc = check_tol(tau, "tau")))
+        return rc;
+    if (!(norm2_other >= 0.0) || isinf(norm2_other))
+        return fail(SPAMM_E_INVAL, "norm2_other = %g must be finite and >= 0", norm2_other);
+    int32_t d;
+    int64_t np;
+    if ((rc = tree_depth(n, leaf, &d, &np)))
+        return rc;
+    int dev;
+    if ((rc = prepare_device(&dev)))
+        return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t N2 = 1u << (2 * d);
+    spamm_tree *t = new (std::nothrow) spamm_tree();
+    if (!t)
+        return fail(SPAMM_E_NOMEM, "host allocation failed");
+    t->device = dev;
+    t->stream = s;
+    t->n = n;
+    t->np = np;
+    t->leaf = leaf;
+    t->depth = d;
+    // scratch: scan partials, then the dense root (8-byte aligned)
+    const size_t np_bytes = align256(sizeof(uint32_t) * scan_partials_len(N2));
+    void *scratch = nullptr;
+    hipError_t e = hipMallocAsync((void **)&t->norms, sizeof(double) * (size_t)tier_offset(d + 1), s);
+    if (e == hipSuccess)
+        e = hipMallocAsync((void **)&t->keep, sizeof(uint32_t) * N2, s);
+    if (e == hipSuccess)
+        e = hipMallocAsync((void **)&t->slot, sizeof(uint32_t) * ((size_t)N2 + 1), s);
+    if (e == hipSuccess)
+        e = hipMallocAsync(&scratch, np_bytes + sizeof(double), s);
+    double *root_dense_dev = (double *)((char *)scratch + np_bytes);
+    if (e == hipSuccess)
+        e = launch_sparse_norms(A, n, leaf, d, t->norms, tau, norm2_other, t->keep, t->slot,
+                                (uint32_t *)scratch, root_dense_dev, s);
+    uint32_t kept = 0;
+    double roots[2] = {0.0, 0.0};
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&kept, t->slot + N2, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&roots[0], t->norms, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&roots[1], root_dense_dev, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (scratch != nullptr)
+        hipFreeAsync(scratch, s);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "spamm_build_tree_sparse");
+        spamm_tree_free(t);
+        return rc;
+    }
+    if (!isfinite(roots[1])) {
+        spamm_tree_free(t);
+        return fail(SPAMM_E_NONFINITE, "input matrix holds NaN or Inf (||A||_F^2 = %g)", roots[1]);
+    }
+    const size_t leaf_bytes = sizeof(float) * (size_t)leaf * (size_t)leaf;
+    const size_t cnt = std::max<size_t>(kept, 1);     // keep the pointers valid when empty
+    e = hipMallocAsync((void **)&t->tiles, cnt * leaf_bytes, s);
+    if (e == hipSuccess)
+        e = hipMallocAsync((void **)&t->tilesT, cnt * leaf_bytes, s);
+    if (e == hipSuccess && bf16)
+        e = hipMallocAsync((void **)&t->tiles16, cnt * leaf_bytes / 2, s);
+    if (e == hipSuccess && bf16)
+        e = hipMallocAsync((void **)&t->tilesT16, cnt * leaf_bytes / 2, s);
+    if (e == hipSuccess && kept > 0)
+        e = launch_sparse_pack(A, n, leaf, d, t->tiles, t->tilesT, t->tiles16, t->tilesT16, t->keep,
+                               t->slot, s);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "spamm_build_tree_sparse (pack)");
+        spamm_tree_free(t);
+        return rc;
+    }
+    t->stored = kept;
+    t->root = roots[0];
+    t->root_dense = roots[1];
+    *out = t;
+    return SPAMM_OK;
+}
+
+int spamm_tree_storage(const spamm_tree *t, int64_t *stored, int64_t *total, size_t *device_bytes)
+{
+    if (t == nullptr)
+        return fail(SPAMM_E_INVAL, "tree is NULL");
+    const int64_t N2 = int64_t(1) << (2 * t->depth);
+    const size_t leaf_bytes = sizeof(float) * (size_t)t->leaf * (size_t)t->leaf;
+    const size_t copies = (t->tiles16 != nullptr) ? 3 : 2;   // two FP32 + two half-size BF16
+    size_t b = copies * leaf_bytes * (size_t)std::max<int64_t>(t->stored, t->slot ? 1 : 0) +
+               sizeof(double) * (size_t)tier_offset(t->depth + (t->sub ? 2 : 1));
+    if (t->slot != nullptr)
+        b += sizeof(uint32_t) * (2 * (size_t)N2 + 1);
+    if (stored) *stored = t->stored;
+    if (total) *total = N2;
+    if (device_bytes) *device_bytes = b;
     return SPAMM_OK;
 }
 
@@ -434,7 +552,7 @@ int spamm_tree_free(spamm_tree *t)
         hipSetDevice(t->device);
     hipError_t e = hipSuccess;
     for (void *ptr : {(void *)t->tiles, (void *)t->tilesT, (void *)t->tiles16, (void *)t->tilesT16,
-                      (void *)t->norms}) {
+                      (void *)t->norms, (void *)t->slot, (void *)t->keep}) {
         if (ptr == nullptr || t->borrowed)
             continue;
         hipError_t f = hipFreeAsync(ptr, t->stream);
@@ -487,14 +605,29 @@ int spamm_tree_matrix(const spamm_tree *t, int32_t copy, float *host, size_t len
     const int64_t np = t->np, b = t->leaf, N = int64_t(1) << t->depth;
     if (len < (size_t)(np * np))
         return fail(SPAMM_E_RANGE, "host buffer holds %zu < %lld values", len, (long long)(np * np));
-    std::vector<float> tiles((size_t)(np * np));
-    HIP_TRY(hipMemcpyAsync(tiles.data(), copy == 0 ? t->tiles : t->tilesT,
-                           sizeof(float) * tiles.size(), hipMemcpyDeviceToHost, t->stream),
-            "hipMemcpyAsync");
+    // a sparsified tree holds only its kept leaves (leaf l at slot[l])
+    const bool sparse = t->slot != nullptr;
+    std::vector<float> tiles((size_t)(t->stored * b * b));
+    std::vector<uint32_t> slot(sparse ? (size_t)(N * N) : 0), keep(sparse ? (size_t)(N * N) : 0);
+    if (!tiles.empty())
+        HIP_TRY(hipMemcpyAsync(tiles.data(), copy == 0 ? t->tiles : t->tilesT,
+                               sizeof(float) * tiles.size(), hipMemcpyDeviceToHost, t->stream),
+                "hipMemcpyAsync");
+    if (sparse) {
+        HIP_TRY(hipMemcpyAsync(slot.data(), t->slot, sizeof(uint32_t) * slot.size(),
+                               hipMemcpyDeviceToHost, t->stream),
+                "hipMemcpyAsync");
+        HIP_TRY(hipMemcpyAsync(keep.data(), t->keep, sizeof(uint32_t) * keep.size(),
+                               hipMemcpyDeviceToHost, t->stream),
+                "hipMemcpyAsync");
+    }
     HIP_TRY(hipStreamSynchronize(t->stream), "hipStreamSynchronize");
+    const std::vector<float> zero((size_t)(b * b), 0.0f);
     for (int64_t l = 0; l < N * N; ++l) {
         const int64_t I = lin_row((uint32_t)l), J = lin_col((uint32_t)l);
-        const float *src = tiles.data() + l * b * b;
+        const float *src = !sparse ? tiles.data() + l * b * b
+                           : keep[(size_t)l] ? tiles.data() + (int64_t)slot[(size_t)l] * b * b
+                                             : zero.data();
         for (int r = 0; r < (int)b; ++r)
             for (int c = 0; c < (int)b; ++c) {
                 const float v = src[leaf_index((int)b, r, c)];

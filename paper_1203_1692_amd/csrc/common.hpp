@@ -143,7 +143,17 @@ struct GemmJob {
     double T2;             // tau^2
     uint8_t *submask;      // per (entry, wave): performed sub-products, bit 2(2a+b)+c
     unsigned long long *subK;  // count of performed sub-products
+    // sparsified trees: storage slot of each leaf (linear index), else null
+    const uint32_t *slotA;
+    const uint32_t *slotB;
 };
+
+// Storage position of leaf `l` of a tree: its slot when the tree is
+// sparsified (only kept leaves stored), else l itself.
+__device__ inline int64_t leaf_slot(const uint32_t *slot, uint32_t l)
+{
+    return slot != nullptr ? (int64_t)slot[l] : (int64_t)l;
+}
 
 constexpr int kMaxJobs = 16;
 
@@ -169,6 +179,12 @@ struct spamm_tree {
     double root;            // ||A||_F^2
     bool borrowed;          // buffers carved from a caller's arena (not freed here)
     bool sub;               // tier d+1 holds the norms of the 32 x 32 sub-blocks (n_b = 64)
+    // epsilon-sparsified tree: only the kept leaves are stored, leaf l at
+    // slot[l] (dropped leaves have norm 0 and are never read); else null
+    uint32_t *slot;
+    uint32_t *keep;         // 1 per stored leaf (linear index), sparsified trees
+    int64_t stored;         // leaves held in tiles (N^2 for a dense tree)
+    double root_dense;      // ||A||_F^2 before dropping (== root for a dense tree)
 };
 
 struct spamm_plan {

@@ -401,8 +401,8 @@ __global__ __launch_bounds__(kScanThreads) void scan_chunks(const uint32_t *__re
 }
 
 // partials needs ceil(m / kScanChunk) + 1 entries.
-static hipError_t launch_scan(const uint32_t *in, uint32_t m, uint32_t *out, uint32_t *partials,
-                              hipStream_t s)
+hipError_t launch_scan_u32(const uint32_t *in, uint32_t m, uint32_t *out, uint32_t *partials,
+                           hipStream_t s)
 {
     if (m <= (uint32_t)kScanChunk * 4) {
         hipLaunchKernelGGL(scan_single, dim3(1), dim3(kScanThreads), 0, s, in, m, out);
@@ -440,7 +440,7 @@ hipError_t launch_cull(spamm_plan *p, hipStream_t s)
             hipLaunchKernelGGL(cull_count, grid, block, 0, s, tA, tB, p->T2, prow, plist, np, p->counts);
             if ((e = hipGetLastError()) != hipSuccess)
                 return e;
-            if ((e = launch_scan(p->counts, 4 * np, crow, p->partials, s)) != hipSuccess)
+            if ((e = launch_scan_u32(p->counts, 4 * np, crow, p->partials, s)) != hipSuccess)
                 return e;
             hipLaunchKernelGGL(cull_emit, grid, block, 0, s, tA, tB, p->T2, prow, plist, np,
                                (const uint32_t *)crow, p->list[t & 1]);
@@ -450,7 +450,7 @@ hipError_t launch_cull(spamm_plan *p, hipStream_t s)
             hipLaunchKernelGGL(reduce_tasks, dim3(1), dim3(1024), 0, s, p->counts + np, np, p->leafK);
             if ((e = hipGetLastError()) != hipSuccess)
                 return e;
-            if ((e = launch_scan(p->counts, np, p->browptr, p->partials, s)) != hipSuccess)
+            if ((e = launch_scan_u32(p->counts, np, p->browptr, p->partials, s)) != hipSuccess)
                 return e;
             hipLaunchKernelGGL(cull_emit_leaf<false>, grid, block, 0, s, tA, tB, p->T2, 0.0, prow,
                                plist, np, (const uint32_t *)p->browptr, p->bent,
@@ -463,9 +463,9 @@ hipError_t launch_cull(spamm_plan *p, hipStream_t s)
                                p->leafK + 1);
             if ((e = hipGetLastError()) != hipSuccess)
                 return e;
-            if ((e = launch_scan(p->counts, np, p->browptr, p->partials, s)) != hipSuccess)
+            if ((e = launch_scan_u32(p->counts, np, p->browptr, p->partials, s)) != hipSuccess)
                 return e;
-            if ((e = launch_scan(p->counts + 2 * np, np, p->browptr_lo, p->partials, s)) != hipSuccess)
+            if ((e = launch_scan_u32(p->counts + 2 * np, np, p->browptr_lo, p->partials, s)) != hipSuccess)
                 return e;
             hipLaunchKernelGGL(cull_emit_leaf<true>, grid, block, 0, s, tA, tB, p->T2, p->L2, prow,
                                plist, np, (const uint32_t *)p->browptr, p->bent,

@@ -56,8 +56,9 @@ __device__ inline uint32_t xcd_block(uint32_t bid, uint32_t nblocks)
 // 3: B_2J+1) of entry `ent` into LDS at dst, if the entry's mask needs it.
 template <int B>
 __device__ inline void stage_issue(uint32_t ent, int p, const float *__restrict__ tA,
-                                   const float *__restrict__ tBT, uint32_t I0, uint32_t J0,
-                                   float *dst, int w, int lane)
+                                   const float *__restrict__ tBT, const uint32_t *slotA,
+                                   const uint32_t *slotB, uint32_t I0, uint32_t J0, float *dst,
+                                   int w, int lane)
 {
     using L = LeafLayout<B>;
     // leaves that use operand w: A_2I -> q 0,1; A_2I+1 -> q 2,3; B_2J -> q 0,2;
@@ -66,8 +67,8 @@ __device__ inline void stage_issue(uint32_t ent, int p, const float *__restrict_
     const uint32_t k = ent & 0xFFFFu, mask = ent >> 16;
     if ((mask & users) == 0)
         return;
-    const float *leaf = w < 2 ? tA + (int64_t)lin_index(I0 + w, k) * (B * B)
-                              : tBT + (int64_t)lin_index(k, J0 + (w - 2)) * (B * B);
+    const float *leaf = w < 2 ? tA + leaf_slot(slotA, lin_index(I0 + w, k)) * (B * B)
+                              : tBT + leaf_slot(slotB, lin_index(k, J0 + (w - 2))) * (B * B);
     const float *src = leaf + p * L::kPanel + 4 * lane;
     float *d = dst + w * L::kPanel;
 #pragma unroll
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
     const uint32_t T = (e1 - e0) * NP;                  // stages of this block
     uint32_t smask = 0, sub_count = 0;                  // SUB: this entry's kept sub-products
     if (T > 0)
-        stage_issue<B>(bent[e0], 0, tA, tBT, I0, J0, smem, w, lane);
+        stage_issue<B>(bent[e0], 0, tA, tBT, job.slotA, job.slotB, I0, J0, smem, w, lane);
     for (uint32_t t = 0; t < T; ++t) {
         const uint32_t ent = bent[e0 + t / NP];
         // this wave's copies of stage t have landed; after the barrier every
@@ -266,8 +267,8 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
         __builtin_amdgcn_s_waitcnt(0x0F70);             // vmcnt(0)
         __syncthreads();
         if (t + 1 < T)
-            stage_issue<B>(bent[e0 + (t + 1) / NP], (int)((t + 1) % NP), tA, tBT, I0, J0,
-                           smem + ((t + 1) & 1) * S::kStage, w, lane);
+            stage_issue<B>(bent[e0 + (t + 1) / NP], (int)((t + 1) % NP), tA, tBT, job.slotA,
+                           job.slotB, I0, J0, smem + ((t + 1) & 1) * S::kStage, w, lane);
         const bool mine = (ent >> (16 + w)) & 1u;
         if constexpr (SUB) {
             if (t % NP == 0) {
@@ -365,8 +366,8 @@ __global__ __launch_bounds__(256) void leaf_gemm_bf16(const GemmJobs jobs)
         const uint32_t k = ent & 0xFFFFu, mask = ent >> 16;
         if ((mask & users) == 0)
             return;
-        const uint16_t *leaf = w < 2 ? tA16 + (int64_t)lin_index(I0 + w, k) * LEAF
-                                     : tBT16 + (int64_t)lin_index(k, J0 + (w - 2)) * LEAF;
+        const uint16_t *leaf = w < 2 ? tA16 + leaf_slot(job.slotA, lin_index(I0 + w, k)) * LEAF
+                                     : tBT16 + leaf_slot(job.slotB, lin_index(k, J0 + (w - 2))) * LEAF;
         const uint16_t *src = leaf + 8 * lane;
         uint16_t *d = dst + w * LEAF;
 #pragma unroll
@@ -482,6 +483,8 @@ void plan_jobs(const spamm_plan *p, float *C, bool bf16, GemmJob &j)
     j.submask = nullptr;
     j.subK = nullptr;
     j.T2 = p->T2;
+    j.slotA = p->A->slot;
+    j.slotB = p->B->slot;
     if (p->sub) {
         j.subA = p->A->norms + tier_offset(p->depth + 1);
         j.subB = p->B->norms + tier_offset(p->depth + 1);

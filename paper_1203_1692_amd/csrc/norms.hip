@@ -10,7 +10,7 @@
 // (bits 0-1 of e), a six-step xor butterfly over lanes (bits 2-7) and an
 // in-register tree over m (bits 8 and up).  Squares of FP32 values are exact
 // in FP64, so only the additions round and their order is fixed.
-#include "common.hpp"
+#include "runtime.hpp"
 
 namespace spamm {
 
@@ -71,6 +71,8 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
                                                       double *__restrict__ leaf_norm,
                                                       double *__restrict__ parent,
                                                       double *__restrict__ sub_norm,
+                                                      const uint32_t *__restrict__ keep,
+                                                      const uint32_t *__restrict__ slot,
                                                       uint32_t ntiles)
 {
     static_assert(!SUB || B == 64, "sub-block norms are built for 64 x 64 leaves");
@@ -86,6 +88,10 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
     const bool valid = l < ntiles;
     float *tr = tr_smem + w * (B * P);
     double s = 0.0;
+    // pack this leaf?  (tiles null: norms only; keep/slot: a sparsified tree
+    // stores only its kept leaves, leaf l at slot[l])
+    const bool pack = valid && tiles != nullptr && (keep == nullptr || keep[l] != 0u);
+    const int64_t dl = pack && slot != nullptr ? (int64_t)slot[l] : (int64_t)l;
     if (valid) {
         const int64_t I = lin_row(l), J = lin_col(l);
         float4 v[M];
@@ -94,16 +100,17 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
             const int e = 256 * m + 4 * lane;
             v[m] = load_row4<VEC>(A, n, I * B + e / B, J * B + e % B);
         }
-        float *dst = tiles + (int64_t)l * (B * B);
         double sm[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int e = 256 * m + 4 * lane;
             const int r = e / B, c = e % B;
-            *reinterpret_cast<float4 *>(dst + L::index(r, c)) = v[m];
-            if constexpr (B >= 32) {
-                if (tiles16 != nullptr)
-                    store_bf16x4(tiles16 + (int64_t)l * (B * B) + Leaf16Layout<B>::index(r, c), v[m]);
+            if (pack) {
+                *reinterpret_cast<float4 *>(tiles + dl * (B * B) + L::index(r, c)) = v[m];
+                if constexpr (B >= 32) {
+                    if (tiles16 != nullptr)
+                        store_bf16x4(tiles16 + dl * (B * B) + Leaf16Layout<B>::index(r, c), v[m]);
+                }
             }
             float *o = tr + r * P + c;
             o[0] = v[m].x;
@@ -130,7 +137,7 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
             const double s00 = right ? o0 : sm[0], s01 = right ? sm[0] : o0;
             const double s10 = right ? o1 : sm[M / 2], s11 = right ? sm[M / 2] : o1;
             s = (s00 + s01) + (s10 + s11);
-            if (lane == 0) {
+            if (lane == 0 && leaf_norm != nullptr) {
                 double *sn = sub_norm + 4 * (int64_t)l;
                 sn[0] = s00;
                 sn[1] = s01;
@@ -145,13 +152,13 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
                 for (int i = 0; i < M; i += 2 * st)
                     sm[i] += sm[i + st];
             s = sm[0];
-            if (lane == 0)
+            if (lane == 0 && leaf_norm != nullptr)
                 leaf_norm[l] = s;
         }
     }
     __syncthreads();
-    if (valid) {
-        float *dstT = tilesT + (int64_t)l * (B * B);
+    if (pack) {
+        float *dstT = tilesT + dl * (B * B);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int e = 256 * m + 4 * lane;
@@ -161,7 +168,7 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
             *reinterpret_cast<float4 *>(dstT + L::index(rt, ct)) = t;
             if constexpr (B >= 32) {
                 if (tilesT16 != nullptr)
-                    store_bf16x4(tilesT16 + (int64_t)l * (B * B) + Leaf16Layout<B>::index(rt, ct), t);
+                    store_bf16x4(tilesT16 + dl * (B * B) + Leaf16Layout<B>::index(rt, ct), t);
             }
         }
     }
@@ -190,7 +197,8 @@ __global__ __launch_bounds__(1024) void norm_pyramid(double *__restrict__ norms,
 template <int B, int VEC, bool SUB>
 static hipError_t launch_leaf_v(const float *A, int64_t n, float *tiles, float *tilesT,
                                 uint16_t *t16, uint16_t *tT16, double *leaf, double *parent,
-                                double *sub, uint32_t ntiles, hipStream_t s)
+                                double *sub, const uint32_t *keep, const uint32_t *slot,
+                                uint32_t ntiles, hipStream_t s)
 {
     constexpr size_t lds = sizeof(float) * 4 * B * (B + 1);
     // once per process (thread-safe static initialization)
@@ -200,58 +208,126 @@ static hipError_t launch_leaf_v(const float *A, int64_t n, float *tiles, float *
     if (attr != hipSuccess)
         return attr;
     hipLaunchKernelGGL((leaf_norm_pack<B, VEC, SUB>), dim3((ntiles + 3) / 4), dim3(256), lds, s, A,
-                       n, tiles, tilesT, t16, tT16, leaf, parent, sub, ntiles);
+                       n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep, slot, ntiles);
     return hipGetLastError();
 }
 
 template <int B, bool SUB>
 static hipError_t launch_leaf(const float *A, int64_t n, int vec, float *tiles, float *tilesT,
                               uint16_t *t16, uint16_t *tT16, double *leaf, double *parent,
-                              double *sub, uint32_t ntiles, hipStream_t s)
+                              double *sub, const uint32_t *keep, const uint32_t *slot,
+                              uint32_t ntiles, hipStream_t s)
 {
     if (vec == 4)
-        return launch_leaf_v<B, 4, SUB>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, ntiles, s);
+        return launch_leaf_v<B, 4, SUB>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep,
+                                        slot, ntiles, s);
     if (vec == 2)
-        return launch_leaf_v<B, 2, SUB>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, ntiles, s);
-    return launch_leaf_v<B, 1, SUB>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, ntiles, s);
+        return launch_leaf_v<B, 2, SUB>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep,
+                                        slot, ntiles, s);
+    return launch_leaf_v<B, 1, SUB>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep, slot,
+                                    ntiles, s);
+}
+
+static hipError_t launch_leaf_any(const float *A, int64_t n, int leaf, float *tiles,
+                                  float *tilesT, uint16_t *t16, uint16_t *tT16, double *leafn,
+                                  double *parent, double *subn, const uint32_t *keep,
+                                  const uint32_t *slot, uint32_t ntiles, hipStream_t s)
+{
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(A);
+    const int vec = (n % 4 == 0 && addr % 16 == 0) ? 4 : (n % 2 == 0 && addr % 8 == 0) ? 2 : 1;
+    switch (leaf) {
+    case 16:
+        return launch_leaf<16, false>(A, n, vec, tiles, tilesT, nullptr, nullptr, leafn, parent,
+                                      nullptr, keep, slot, ntiles, s);
+    case 32:
+        return launch_leaf<32, false>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent, nullptr,
+                                      keep, slot, ntiles, s);
+    case 64:
+        return subn != nullptr
+                   ? launch_leaf<64, true>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent,
+                                           subn, keep, slot, ntiles, s)
+                   : launch_leaf<64, false>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent,
+                                            nullptr, keep, slot, ntiles, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 // sub (n_b = 64 only): norms hold tiers 0..depth+1, tier depth+1 being the
-// 32 x 32 sub-blocks; otherwise tiers 0..depth.
+// 32 x 32 sub-blocks; otherwise tiers 0..depth.  tiles == null: norms only.
 hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *tiles,
                         float *tilesT, uint16_t *t16, uint16_t *tT16, double *norms, bool sub,
                         hipStream_t s)
 {
-    const uintptr_t addr = reinterpret_cast<uintptr_t>(A);
-    const int vec = (n % 4 == 0 && addr % 16 == 0) ? 4 : (n % 2 == 0 && addr % 8 == 0) ? 2 : 1;
     const uint32_t ntiles = 1u << (2 * depth);
     double *leafn = norms + tier_offset(depth);
     double *parent = depth >= 1 ? norms + tier_offset(depth - 1) : nullptr;
     double *subn = sub ? norms + tier_offset(depth + 1) : nullptr;
     if (sub && leaf != 64)
         return hipErrorInvalidValue;
-    hipError_t e;
-    switch (leaf) {
-    case 16:
-        e = launch_leaf<16, false>(A, n, vec, tiles, tilesT, nullptr, nullptr, leafn, parent,
-                                   nullptr, ntiles, s);
-        break;
-    case 32:
-        e = launch_leaf<32, false>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent, nullptr,
-                                   ntiles, s);
-        break;
-    case 64:
-        e = sub ? launch_leaf<64, true>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent, subn,
-                                        ntiles, s)
-                : launch_leaf<64, false>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent,
-                                         nullptr, ntiles, s);
-        break;
-    default: return hipErrorInvalidValue;
-    }
+    hipError_t e = launch_leaf_any(A, n, leaf, tiles, tilesT, t16, tT16, leafn, parent, subn,
+                                   nullptr, nullptr, ntiles, s);
     if (e != hipSuccess || depth < 2)
         return e;
     hipLaunchKernelGGL(norm_pyramid, dim3(1), dim3(1024), 0, s, norms, depth - 1);
     return hipGetLastError();
+}
+
+// ---- epsilon-sparsified trees (Sec. II.C) ------------------------------------
+// Leaf l is kept iff s_l > 0 and fl64(s_l * m) >= fl64(tau^2), with
+// m = max(||A||_F^2, other2) read from the dense root; a dropped leaf's norm
+// becomes 0.  The dense root is copied to root_dense first.
+__global__ __launch_bounds__(256) void drop_leaves(double *__restrict__ leafn, uint32_t count,
+                                                   const double *__restrict__ root, double other2,
+                                                   double T2, uint32_t *__restrict__ keep,
+                                                   double *__restrict__ root_dense)
+{
+    const double r = root[0];
+    const double m = r > other2 ? r : other2;
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l == 0)
+        root_dense[0] = r;
+    if (l >= count)
+        return;
+    const double v = leafn[l];
+    const bool k = (v > 0.0) & !(v * m < T2);
+    keep[l] = k ? 1u : 0u;
+    if (!k)
+        leafn[l] = 0.0;
+}
+
+// Pass 1 of a sparsified build: dense norms (no pack), drop, the exclusive
+// scan of the keep flags into slots (slot[N^2] = leaves kept), and the norm
+// pyramid rebuilt over the kept leaves.
+hipError_t launch_sparse_norms(const float *A, int64_t n, int leaf, int depth, double *norms,
+                               double tau, double other2, uint32_t *keep, uint32_t *slot,
+                               uint32_t *partials, double *root_dense, hipStream_t s)
+{
+    const uint32_t ntiles = 1u << (2 * depth);
+    hipError_t e = launch_build(A, n, leaf, depth, nullptr, nullptr, nullptr, nullptr, norms,
+                                false, s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(drop_leaves, dim3((ntiles + 255) / 256), dim3(256), 0, s,
+                       norms + tier_offset(depth), ntiles, (const double *)norms, other2,
+                       tau * tau, keep, root_dense);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    if ((e = launch_scan_u32(keep, ntiles, slot, partials, s)) != hipSuccess)
+        return e;
+    if (depth >= 1) {
+        hipLaunchKernelGGL(norm_pyramid, dim3(1), dim3(1024), 0, s, norms, depth);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+// Pass 2: pack the kept leaves (A is read again only where a leaf is kept).
+hipError_t launch_sparse_pack(const float *A, int64_t n, int leaf, int depth, float *tiles,
+                              float *tilesT, uint16_t *t16, uint16_t *tT16, const uint32_t *keep,
+                              const uint32_t *slot, hipStream_t s)
+{
+    return launch_leaf_any(A, n, leaf, tiles, tilesT, t16, tT16, nullptr, nullptr, nullptr, keep,
+                           slot, 1u << (2 * depth), s);
 }
 
 }  // namespace spamm

@@ -43,6 +43,20 @@ void plan_jobs(const spamm_plan *p, float *C, bool bf16, GemmJob &j);
 hipError_t launch_gemm_jobs(int leaf, bool bf16, const GemmJobs &jobs, hipStream_t s,
                             bool sub = false);
 
+// Exclusive scan of m uint32 (out[m] = total); partials: scan_partials_len(m).
+hipError_t launch_scan_u32(const uint32_t *in, uint32_t m, uint32_t *out, uint32_t *partials,
+                           hipStream_t s);
+size_t scan_partials_len(uint32_t m);
+
+// Epsilon-sparsified build (norms.hip): dense norms, drop, slots, pyramid;
+// then the pack of the kept leaves.
+hipError_t launch_sparse_norms(const float *A, int64_t n, int leaf, int depth, double *norms,
+                               double tau, double other2, uint32_t *keep, uint32_t *slot,
+                               uint32_t *partials, double *root_dense, hipStream_t s);
+hipError_t launch_sparse_pack(const float *A, int64_t n, int leaf, int depth, float *tiles,
+                              float *tilesT, uint16_t *t16, uint16_t *tT16, const uint32_t *keep,
+                              const uint32_t *slot, hipStream_t s);
+
 // Steady clock in microseconds (request timestamps).
 double now_us();
 
