@@ -102,18 +102,45 @@ def matched_error(sp, wl, A, dA, C, tau, leaf, n, N, reps=2):
                            "tasks": st["tasks"], "low_frac": round(st["tasks_low"] / max(1, st["tasks"]), 4)})
     tree.free()
     target = next(p["err"] for p in points if p["precision"] == "fp32" and p["tau"] == tau)
+    subleaf = None
+    if leaf == 64:
+        # sub-leaf culling: 32 x 32 sub-products tested inside each 64 x 64 one
+        sub_tree = sp.build_tree(dA, leaf, subnorms=True)
+        for tmul in (0.1, 0.3, 1.0, 3.0, 10.0, 30.0, 100.0, 300.0, 1e3, 3e3, 1e4):
+            t_ = tau * tmul
+            best = None
+            for _ in range(reps):
+                st = sp.multiply_ex(sub_tree, sub_tree, t_, C, sub_cull=True)
+                ms = st["symbolic_ms"] + st["numeric_ms"]
+                if best is None or ms < best[0]:
+                    best = (ms, st["numeric_ms"])
+            points.append({"precision": "fp32-subleaf", "tau": t_, "low_tol": 0.0,
+                           "ms": round(best[0], 3), "ms_leaf_gemm": round(best[1], 3),
+                           "err": max_err(), "tasks": st["tasks"],
+                           "sub_products": st["subtasks"],
+                           "sub_fraction": round(st["subtasks"] / max(1, 8 * st["tasks"]), 4)})
+        sub_tree.free()
+        at_tau = next(p for p in points if p["precision"] == "fp32-subleaf" and p["tau"] == tau)
+        plain = next(p for p in points if p["precision"] == "fp32" and p["tau"] == tau)
+        subleaf = {"tau": tau, "leaf_products": plain["tasks"],
+                   "sub_products": at_tau["sub_products"], "sub_fraction": at_tau["sub_fraction"],
+                   "ms_plain": plain["ms"], "ms_subleaf": at_tau["ms"],
+                   "err_plain": plain["err"], "err_subleaf": at_tau["err"]}
 
     def fastest(kind):
         ok = [p for p in points if p["precision"] == kind and p["err"] <= target]
         return min(ok, key=lambda p: p["ms"]) if ok else None
 
-    f32, spl = fastest("fp32"), fastest("split-bf16")
+    f32, spl, sub = fastest("fp32"), fastest("split-bf16"), fastest("fp32-subleaf")
     return {
         "target_err": target,
         "err_sample": f"{len(tiles)} seeded output leaves (incl. diagonal), dense FP64 reference",
-        "fp32_at_target": f32, "split_at_target": spl,
+        "fp32_at_target": f32, "split_at_target": spl, "subleaf_at_target": sub,
         "speedup_split_vs_fp32": round(f32["ms"] / spl["ms"], 3) if f32 and spl else None,
-        "grid": "tau x {1,10,...,1e5}, low_tol = tau x {0 (fp32), 256, 1024, 4096, 16384}",
+        "speedup_subleaf_vs_fp32": round(f32["ms"] / sub["ms"], 3) if f32 and sub else None,
+        "subleaf_same_tau": subleaf,
+        "grid": "tau x {1,10,...,1e5}, low_tol = tau x {0 (fp32), 256, 1024, 4096, 16384}; "
+                "sub-leaf culling: tau x {0.1, 0.3, ..., 1e4}",
     }
 
 
@@ -363,6 +390,8 @@ def main() -> int:
                     help="skip the FP32-vs-split comparison at a fixed max-norm error")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark instead: saturation, then Poisson arrivals")
+    ap.add_argument("--no-sparse", action="store_true",
+                    help="skip the epsilon-sparsified tree comparison")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving run that follows the main workload")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -478,6 +507,30 @@ def main() -> int:
             "traffic": measured_traffic(wl.name),
         },
     }
+
+    # ---- epsilon-sparsified tree of the same matrix ----------------------------
+    # leaves below tau / ||A||_F dropped at build; the product keeps the same
+    # leaf products, so C must equal the dense step's bit for bit
+    if not args.no_sparse:
+        C2 = torch.empty_like(C)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sparse = sp.build_tree_sparse(dA, leaf, tau)
+        torch.cuda.synchronize()
+        t_build = (time.perf_counter() - t) * 1e3
+        sst = sp.multiply_ex(sparse, sparse, tau, C2)
+        sto = sparse.storage()
+        dense_bytes = sp.build_tree(dA, leaf).storage()["bytes"]
+        out["sparse_tree"] = {
+            "tau": tau, "leaves_stored": sto["stored"], "leaves_total": sto["total"],
+            "stored_fraction": round(sto["stored"] / sto["total"], 4),
+            "device_bytes": sto["bytes"], "dense_device_bytes": dense_bytes,
+            "ms_build": round(t_build, 3),
+            "ms_multiply": round(sst["symbolic_ms"] + sst["numeric_ms"], 3),
+            "tasks": sst["tasks"], "C_bitwise_equal_dense": bool(torch.equal(C, C2)),
+        }
+        sparse.free()
+        del C2
 
     # ---- FP32 vs split precision at the same max-norm error -------------------
     # The paper compares variants with tau adjusted so that their max-norm
