@@ -157,3 +157,44 @@ def test_cluster1310_task_set(cluster1310):
 
 def test_cluster1310_sampled_product(cluster1310):
     check_sampled_product(cluster1310, seed=5)
+
+
+class MatrixRun(FullRun):
+    """FullRun on a given matrix (not a named workload)."""
+
+    def __init__(self, sp, A, leaf, tau, label):
+        import torch
+        self.A, self.leaf, self.tau, self.n = A, leaf, tau, A.shape[0]
+        print(f"\n[fullsize] {label} tau={tau:g}", flush=True)
+        dA = torch.from_numpy(A).cuda()
+        self.tree = sp.build_tree(dA, leaf)
+        self.plan = sp.symbolic(self.tree, self.tree, tau)
+        C = torch.full_like(dA, float("nan"))
+        self.plan.numeric(C)
+        torch.cuda.synchronize()
+        del dA
+        self.C = C.cpu().numpy()
+        del C
+        self.keys = self.plan.tasks()
+        self.stats = self.plan.stats()
+        print(f"[fullsize] {label}: K={self.stats['tasks']}", flush=True)
+
+
+def test_largest_grid_n16384_leaf16(gpu):
+    """The largest grid the library takes: N = 1024 leaves per dimension
+    (n = 16384 at n_b = 16, 10 tiers below the root, worst-case task arena
+    capacities); every norm tier and the whole task set bit-exact, C on
+    sampled leaves; one more row or column is out of range."""
+    import torch
+    A = workloads.exp_decay(16384, 0.5, 3)
+    r = MatrixRun(gpu, A, 16, 1e-6, "expdecay0.5-n16384-leaf16")
+    assert r.tree.depth == 10
+    check_norms(r)
+    ref = oracle.spamm(r.A, r.A, 16, r.tau, want_C=False)
+    assert r.stats["kept"] == [int(v) for v in ref.Kt]
+    assert np.array_equal(r.keys, ref.keys)
+    check_sampled_product(r, seed=3)
+    big = torch.zeros(16385, 16385, device="cuda")
+    with pytest.raises(gpu.SpammError) as ei:
+        gpu.build_tree(big, 16)
+    assert ei.value.code == gpu.SPAMM_E_RANGE
