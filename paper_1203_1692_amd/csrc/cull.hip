@@ -110,18 +110,13 @@ __device__ inline uint32_t mask_of(uint32_t f, int c)
            (((f >> (6 + c)) & 1u) << 3);
 }
 
-// Tiers below the leaves: per parent output tile P, the number of kept
-// children in each child tile 4P + q.
-__global__ __launch_bounds__(256) void cull_count(const double *__restrict__ nA,
-                                                  const double *__restrict__ nB, double T2,
-                                                  const uint32_t *__restrict__ prow,
-                                                  const uint32_t *__restrict__ plist,
-                                                  uint32_t nparents, uint32_t *__restrict__ counts)
+// Tiers below the leaves: per parent output tile P (one wave), the number of
+// kept children in each child tile 4P + q.
+__device__ inline void count_tile(const double *__restrict__ nA, const double *__restrict__ nB,
+                                  double T2, const uint32_t *__restrict__ prow,
+                                  const uint32_t *__restrict__ plist, uint32_t P,
+                                  uint32_t *__restrict__ counts, int lane)
 {
-    const uint32_t P = blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (P >= nparents)
-        return;
-    const int lane = threadIdx.x & 63;
     const uint32_t I = lin_row(P), J = lin_col(P);
     const uint32_t beg = prow[P], end = prow[P + 1];
     uint32_t tot[4] = {0, 0, 0, 0};
@@ -140,6 +135,17 @@ __global__ __launch_bounds__(256) void cull_count(const double *__restrict__ nA,
         for (int q = 0; q < 4; ++q)
             counts[4 * P + q] = tot[q];
     }
+}
+
+__global__ __launch_bounds__(256) void cull_count(const double *__restrict__ nA,
+                                                  const double *__restrict__ nB, double T2,
+                                                  const uint32_t *__restrict__ prow,
+                                                  const uint32_t *__restrict__ plist,
+                                                  uint32_t nparents, uint32_t *__restrict__ counts)
+{
+    const uint32_t P = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (P < nparents)
+        count_tile(nA, nB, T2, prow, plist, P, counts, threadIdx.x & 63);
 }
 
 // Leaf tier: per GEMM block P (a tier-(d-1) tile), the number of schedule
@@ -194,18 +200,14 @@ __global__ __launch_bounds__(256) void cull_count_leaf(const double *__restrict_
     }
 }
 
-__global__ __launch_bounds__(256) void cull_emit(const double *__restrict__ nA,
-                                                 const double *__restrict__ nB, double T2,
-                                                 const uint32_t *__restrict__ prow,
-                                                 const uint32_t *__restrict__ plist,
-                                                 uint32_t nparents,
-                                                 const uint32_t *__restrict__ crow,
-                                                 uint32_t *__restrict__ clist)
+// Writes the kept children of parent output tile P (one wave) into the
+// child lists at the positions given by the scanned counts.
+__device__ inline void emit_tile(const double *__restrict__ nA, const double *__restrict__ nB,
+                                 double T2, const uint32_t *__restrict__ prow,
+                                 const uint32_t *__restrict__ plist, uint32_t P,
+                                 const uint32_t *__restrict__ crow, uint32_t *__restrict__ clist,
+                                 int lane)
 {
-    const uint32_t P = blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (P >= nparents)
-        return;
-    const int lane = threadIdx.x & 63;
     const uint64_t below = lanes_below();
     const uint32_t I = lin_row(P), J = lin_col(P);
     const uint32_t beg = prow[P], end = prow[P + 1];
@@ -232,6 +234,19 @@ __global__ __launch_bounds__(256) void cull_emit(const double *__restrict__ nA,
             run[q] += __popcll(b0) + __popcll(b1);
         }
     }
+}
+
+__global__ __launch_bounds__(256) void cull_emit(const double *__restrict__ nA,
+                                                 const double *__restrict__ nB, double T2,
+                                                 const uint32_t *__restrict__ prow,
+                                                 const uint32_t *__restrict__ plist,
+                                                 uint32_t nparents,
+                                                 const uint32_t *__restrict__ crow,
+                                                 uint32_t *__restrict__ clist)
+{
+    const uint32_t P = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (P < nparents)
+        emit_tile(nA, nB, T2, prow, plist, P, crow, clist, threadIdx.x & 63);
 }
 
 // Writes the (k | mask << 16) entries of the flags `fl` of one chunk.
@@ -400,6 +415,70 @@ __global__ __launch_bounds__(kScanThreads) void scan_chunks(const uint32_t *__re
         out[m] = offs[gridDim.x];   // grand total
 }
 
+// Row pointers of tier t start at tier_offset(t) + t (tier u holds 4^u + 1).
+__device__ inline int64_t rowptr_offset(int t) { return tier_offset(t) + t; }
+
+// The root and tiers 1..top in one workgroup (top <= kTopTiers): the small
+// upper tiers cost one launch instead of three each.  Same count -> scan ->
+// emit per tier as the per-tier kernels (same per-wave code), so the lists
+// are identical; barriers separate the phases.
+constexpr int kTopTiers = 5;
+
+__global__ __launch_bounds__(kScanThreads) void cull_top(const double *__restrict__ nA,
+                                                         const double *__restrict__ nB, double T2,
+                                                         uint32_t *__restrict__ rowptr,
+                                                         uint32_t *__restrict__ list0,
+                                                         uint32_t *__restrict__ list1,
+                                                         uint32_t *__restrict__ counts,
+                                                         uint64_t *__restrict__ leafK, int top)
+{
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int NW = kScanThreads / kWave;
+    if (threadIdx.x == 0) {
+        rowptr[0] = 0;
+        rowptr[1] = keep_pair(nA[0], nB[0], T2) ? 1u : 0u;
+        list0[0] = 0;
+        *leafK = 0;
+    }
+    __syncthreads();
+    for (int t = 1; t <= top; ++t) {
+        const uint32_t np = 1u << (2 * (t - 1));
+        const double *tA = nA + tier_offset(t), *tB = nB + tier_offset(t);
+        const uint32_t *prow = rowptr + rowptr_offset(t - 1);
+        uint32_t *crow = rowptr + rowptr_offset(t);
+        const uint32_t *plist = (t - 1) & 1 ? list1 : list0;
+        uint32_t *clist = t & 1 ? list1 : list0;
+        for (uint32_t P = w; P < np; P += NW)
+            count_tile(tA, tB, T2, prow, plist, P, counts, lane);
+        __syncthreads();
+        // exclusive scan of counts[0 .. 4 np) into crow, crow[4 np] = total
+        const uint32_t m = 4 * np;
+        uint32_t carry = 0;
+        for (uint32_t c0 = 0; c0 < m; c0 += kScanChunk) {
+            const uint32_t base = c0 + threadIdx.x * kScanItems;
+            uint32_t v[kScanItems];
+#pragma unroll
+            for (int i = 0; i < kScanItems; ++i)
+                v[i] = (base + i < m) ? counts[base + i] : 0u;
+            uint32_t total;
+            uint32_t pfx = block_scan4(v, &total) + carry;
+#pragma unroll
+            for (int i = 0; i < kScanItems; ++i) {
+                if (base + i < m)
+                    crow[base + i] = pfx;
+                pfx += v[i];
+            }
+            carry += total;
+        }
+        if (threadIdx.x == 0)
+            crow[m] = carry;
+        __syncthreads();
+        for (uint32_t P = w; P < np; P += NW)
+            emit_tile(tA, tB, T2, prow, plist, P, crow, clist, lane);
+        __syncthreads();
+    }
+}
+
 // partials needs ceil(m / kScanChunk) + 1 entries.
 hipError_t launch_scan_u32(const uint32_t *in, uint32_t m, uint32_t *out, uint32_t *partials,
                            hipStream_t s)
@@ -423,13 +502,20 @@ hipError_t launch_cull(spamm_plan *p, hipStream_t s)
     const int d = p->depth;
     const bool split = p->precision != SPAMM_PREC_FP32;
     const double *nA = p->A->norms, *nB = p->B->norms;
-    hipLaunchKernelGGL(cull_root, dim3(1), dim3(64), 0, s, nA, nB, p->T2, split ? p->L2 : 0.0,
-                       p->rowptr + p->rp_off[0], p->list[0], p->browptr, p->bent, p->browptr_lo,
-                       p->bent_lo, p->leafK, d == 0 ? 1 : 0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || d == 0)
+    hipError_t e;
+    if (d == 0) {
+        hipLaunchKernelGGL(cull_root, dim3(1), dim3(64), 0, s, nA, nB, p->T2, split ? p->L2 : 0.0,
+                           p->rowptr + p->rp_off[0], p->list[0], p->browptr, p->bent,
+                           p->browptr_lo, p->bent_lo, p->leafK, 1);
+        return hipGetLastError();
+    }
+    // root and the upper tiers in one workgroup, the rest tier by tier
+    const int top = d - 1 < kTopTiers ? d - 1 : kTopTiers;
+    hipLaunchKernelGGL(cull_top, dim3(1), dim3(kScanThreads), 0, s, nA, nB, p->T2, p->rowptr,
+                       p->list[0], p->list[1], p->counts, p->leafK, top);
+    if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    for (int t = 1; t <= d; ++t) {
+    for (int t = top + 1; t <= d; ++t) {
         const uint32_t np = 1u << (2 * (t - 1));
         const double *tA = nA + tier_offset(t), *tB = nB + tier_offset(t);
         const uint32_t *prow = p->rowptr + p->rp_off[t - 1];
