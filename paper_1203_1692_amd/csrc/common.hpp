@@ -124,9 +124,8 @@ __device__ inline int lane_id() { return __lane_id(); }
 __device__ inline uint64_t lanes_below() { return (uint64_t(1) << lane_id()) - 1; }
 
 // One product in a (possibly batched) leaf-GEMM launch: grid blocks
-// [block0, block0 + nblocks) work on this job.  tA / tBT point to FP32
-// leaves (LeafLayout) for the FP32 kernel and to BF16 leaves
-// (Leaf16Layout) for the BF16 kernel.
+// [block0, block0 + nblocks) work on this job.  tA / tBT point to the FP32
+// leaves (LeafLayout), tA16 / tBT16 to the BF16 ones (Leaf16Layout).
 struct GemmJob {
     const void *tA;
     const void *tBT;
@@ -136,7 +135,12 @@ struct GemmJob {
     int64_t n;
     uint32_t nblocks, block0;
     int32_t single;        // depth 0: one leaf
-    int32_t accumulate;    // add to C (second pass of a split product)
+    // split precision: BF16 leaf copies and the LOW schedule (tA/tBT,
+    // browptr/bent then hold the FP32 copies and the HIGH schedule), else null
+    const void *tA16;
+    const void *tBT16;
+    const uint32_t *browptr_lo;
+    const uint32_t *bent_lo;
     // sub-leaf culling (n_b = 64, 32 x 32 sub-blocks), else null
     const double *subA;    // tier d+1 norms of A: 4 per leaf, child 2a + c
     const double *subB;    // tier d+1 norms of B
@@ -156,6 +160,10 @@ __device__ inline int64_t leaf_slot(const uint32_t *slot, uint32_t l)
 }
 
 constexpr int kMaxJobs = 16;
+
+// Leaf-GEMM kernels of a launch: whole FP32 leaf products, split precision
+// (LOW on BF16, HIGH on FP32, one kernel), FP32 with sub-leaf culling.
+enum class GemmKind { Fp32, Split, Sub };
 
 struct GemmJobs {          // passed by value as a kernel argument
     int32_t njobs;

@@ -1,5 +1,6 @@
 // Numeric multiply: C_ij = sum over kept k (ascending) of A_ik B_kj
-// (Eq. product, Alg. 1 steps 7-9) on FP32 MFMA with FP32 accumulation.
+// (Eq. product, Alg. 1 steps 7-9) on FP32 MFMA with FP32 accumulation; with
+// split precision the LOW products run on BF16 MFMA in the same kernel.
 //
 // Ownership.  A workgroup of 4 waves owns one block of 2 x 2 output leaves
 // (the children of one tier-(d-1) tile); wave q = 2a + b owns leaf
@@ -166,8 +167,7 @@ __device__ inline void panel_mfma16(const float *__restrict__ Ap, const float *_
 // Store (or add to) one output leaf held in MFMA result layout, cropped to n.
 template <int B>
 __device__ inline void write_leaf32(const floatx16 (&acc)[B / 32][B / 32], int64_t row0,
-                                    int64_t col0, int64_t n, float *__restrict__ C, int accumulate,
-                                    int lane)
+                                    int64_t col0, int64_t n, float *__restrict__ C, int lane)
 {
 #pragma unroll
     for (int i = 0; i < B / 32; ++i)
@@ -177,30 +177,55 @@ __device__ inline void write_leaf32(const floatx16 (&acc)[B / 32][B / 32], int64
             for (int v = 0; v < 16; ++v) {
                 const int64_t row = row0 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const int64_t col = col0 + j * 32 + (lane & 31);
-                if (row < n && col < n) {
-                    float *c = C + row * n + col;
-                    *c = accumulate ? *c + acc[i][j][v] : acc[i][j][v];
-                }
+                if (row < n && col < n)
+                    C[row * n + col] = acc[i][j][v];
             }
 }
 
 __device__ inline void write_leaf16(const floatx4 &acc, int64_t row0, int64_t col0, int64_t n,
-                                    float *__restrict__ C, int accumulate, int lane)
+                                    float *__restrict__ C, int lane)
 {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int64_t row = row0 + 4 * (lane >> 4) + v;
         const int64_t col = col0 + (lane & 15);
-        if (row < n && col < n) {
-            float *c = C + row * n + col;
-            *c = accumulate ? *c + acc[v] : acc[v];
+        if (row < n && col < n)
+            C[row * n + col] = acc[v];
+    }
+}
+
+// FP32 products of one block, n_b >= 32: its entries [e0, e1) of `bent`,
+// staged by k-panels (see the pipeline note above), into acc.
+template <int B>
+__device__ inline void fp32_products(const float *__restrict__ tA, const float *__restrict__ tBT,
+                                     const uint32_t *slotA, const uint32_t *slotB,
+                                     const uint32_t *__restrict__ bent, uint32_t e0, uint32_t e1,
+                                     uint32_t I0, uint32_t J0, float *smem, int w, int lane,
+                                     floatx16 (&acc)[B / 32][B / 32])
+{
+    using L = LeafLayout<B>;
+    using S = GemmShape<B>;
+    constexpr int NP = L::kPanels;
+    const int qa = w >> 1, qb = w & 1;
+    const uint32_t T = (e1 - e0) * NP;                  // stages of this block
+    if (T > 0)
+        stage_issue<B>(bent[e0], 0, tA, tBT, slotA, slotB, I0, J0, smem, w, lane);
+    for (uint32_t t = 0; t < T; ++t) {
+        const uint32_t ent = bent[e0 + t / NP];
+        // this wave's copies of stage t have landed; after the barrier every
+        // wave's have, and every wave is done reading the other buffer
+        __builtin_amdgcn_s_waitcnt(0x0F70);             // vmcnt(0)
+        __syncthreads();
+        if (t + 1 < T)
+            stage_issue<B>(bent[e0 + (t + 1) / NP], (int)((t + 1) % NP), tA, tBT, slotA, slotB,
+                           I0, J0, smem + ((t + 1) & 1) * S::kStage, w, lane);
+        if ((ent >> (16 + w)) & 1u) {
+            const float *buf = smem + (t & 1) * S::kStage;
+            panel_mfma32<B>(buf + qa * L::kPanel, buf + (2 + qb) * L::kPanel, acc, lane);
         }
     }
 }
 
-// accumulate = 0: every output leaf of the block is written (zeros where
-// nothing lands).  accumulate = 1: blocks without entries are left alone and
-// the others add their products to C (second pass of a split product).
 // The job of grid block `bid` (jobs sorted by block0; at most kMaxJobs).
 __device__ inline int job_of(const GemmJobs &jobs, uint32_t bid)
 {
@@ -230,7 +255,7 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
     const uint32_t *__restrict__ bent = job.bent;
     float *__restrict__ C = job.C;
     const int64_t n = job.n;
-    const int single = job.single, accumulate = job.accumulate;
+    const int single = job.single;
     const uint32_t blk = xcd_block(blockIdx.x - job.block0, job.nblocks);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int qa = w >> 1, qb = w & 1;
@@ -254,8 +279,13 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
     }
 
     const uint32_t e0 = browptr[blk], e1 = browptr[blk + 1];
-    if (accumulate && e0 == e1)
+    if constexpr (!SUB && B >= 32) {
+        fp32_products<B>(tA, tBT, job.slotA, job.slotB, bent, e0, e1, I0, J0, smem, w, lane, acc);
+        if (single && w != 0)
+            return;
+        write_leaf32<B>(acc, (int64_t)(I0 + qa) * B, (int64_t)(J0 + qb) * B, n, C, lane);
         return;
+    }
     const uint32_t T = (e1 - e0) * NP;                  // stages of this block
     uint32_t smask = 0, sub_count = 0;                  // SUB: this entry's kept sub-products
     if (T > 0)
@@ -302,8 +332,6 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
                                     ((smask >> (2 + c)) & 4u) | ((smask >> (3 + c)) & 8u);
                 if (pm != 0u)
                     panel_mfma32_sub<B>(Ap, Bp, acc, lane, pm);
-            } else if constexpr (B >= 32) {
-                panel_mfma32<B>(Ap, Bp, acc, lane);
             } else {
                 panel_mfma16(Ap, Bp, acc16, lane);
             }
@@ -318,56 +346,36 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
         return;
     const int64_t row0 = (int64_t)(I0 + qa) * B, col0 = (int64_t)(J0 + qb) * B;
     if constexpr (B >= 32)
-        write_leaf32<B>(acc, row0, col0, n, C, accumulate, lane);
+        write_leaf32<B>(acc, row0, col0, n, C, lane);
     else
-        write_leaf16(acc16, row0, col0, n, C, accumulate, lane);
+        write_leaf16(acc16, row0, col0, n, C, lane);
 }
 
 // ---------------------------------------------------------------------------
 // LOW products (split precision): BF16 operands, FP32 accumulation, on
 // v_mfma_f32_32x32x16_bf16 (A operand of lane l: A[l%32][k0 + 8(l/32) + i],
 // i < 8; B operand B[k0 + 8(l/32) + i][l%32]).  Same ownership and
-// double-buffered direct-to-LDS staging as the FP32 kernel; a stage is the
-// four whole BF16 leaves of one entry (Leaf16Layout, 8 KB each at n_b = 64).
-// This kernel writes every output leaf (zeros where no LOW product lands);
-// the FP32 kernel then adds the HIGH products of the blocks that have any.
+// double-buffered direct-to-LDS staging as the FP32 loop; a stage is the four
+// whole BF16 leaves of one entry (Leaf16Layout, 8 KB each at n_b = 64).
 template <int B>
-__global__ __launch_bounds__(256) void leaf_gemm_bf16(const GemmJobs jobs)
+__device__ inline void bf16_products(const uint16_t *__restrict__ tA16,
+                                     const uint16_t *__restrict__ tBT16, const uint32_t *slotA,
+                                     const uint32_t *slotB, const uint32_t *__restrict__ bent,
+                                     uint32_t e0, uint32_t e1, uint32_t I0, uint32_t J0,
+                                     uint16_t *smem16, int w, int lane,
+                                     floatx16 (&acc)[B / 32][B / 32])
 {
     using L = Leaf16Layout<B>;
     constexpr int LEAF = B * B;            // bf16 per leaf
     constexpr int MB = B / 32;
-    extern __shared__ uint16_t smem16[];   // 2 stages x {A_2I, A_2I+1, B_2J, B_2J+1}
-    const GemmJob &job = jobs.job[job_of(jobs, blockIdx.x)];
-    const uint16_t *__restrict__ tA16 = (const uint16_t *)job.tA;
-    const uint16_t *__restrict__ tBT16 = (const uint16_t *)job.tBT;
-    const uint32_t *__restrict__ browptr = job.browptr;
-    const uint32_t *__restrict__ bent = job.bent;
-    float *__restrict__ C = job.C;
-    const int64_t n = job.n;
-    const int single = job.single;
-    const uint32_t blk = xcd_block(blockIdx.x - job.block0, job.nblocks);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int qa = w >> 1, qb = w & 1;
-    uint32_t I0 = 0, J0 = 0;
-    if (!single) {
-        I0 = 2 * lin_row(blk);
-        J0 = 2 * lin_col(blk);
-    }
-    floatx16 acc[MB][MB];
-#pragma unroll
-    for (int i = 0; i < MB; ++i)
-#pragma unroll
-        for (int j = 0; j < MB; ++j)
-            acc[i][j] = floatx16{0};
-
     auto issue = [&](uint32_t ent, uint16_t *dst) {
         const uint32_t users = w < 2 ? (0x3u << (2 * w)) : (0x5u << (w - 2));
         const uint32_t k = ent & 0xFFFFu, mask = ent >> 16;
         if ((mask & users) == 0)
             return;
-        const uint16_t *leaf = w < 2 ? tA16 + leaf_slot(job.slotA, lin_index(I0 + w, k)) * LEAF
-                                     : tBT16 + leaf_slot(job.slotB, lin_index(k, J0 + (w - 2))) * LEAF;
+        const uint16_t *leaf = w < 2 ? tA16 + leaf_slot(slotA, lin_index(I0 + w, k)) * LEAF
+                                     : tBT16 + leaf_slot(slotB, lin_index(k, J0 + (w - 2))) * LEAF;
         const uint16_t *src = leaf + 8 * lane;
         uint16_t *d = dst + w * LEAF;
 #pragma unroll
@@ -375,8 +383,6 @@ __global__ __launch_bounds__(256) void leaf_gemm_bf16(const GemmJobs jobs)
             __builtin_amdgcn_global_load_lds((global_void_t *)(src + 512 * i), (lds_void_t *)(d + 512 * i),
                                              16, 0, 0);
     };
-
-    const uint32_t e0 = browptr[blk], e1 = browptr[blk + 1];
     const uint32_t T = e1 - e0;
     if (T > 0)
         issue(bent[e0], smem16);
@@ -412,9 +418,56 @@ __global__ __launch_bounds__(256) void leaf_gemm_bf16(const GemmJobs jobs)
                                                                             acc[i][j], 0, 0, 0);
         }
     }
+}
+
+// Split precision in one launch: every block runs its LOW list (BF16) and
+// then its HIGH list (FP32), so the few blocks with many HIGH products (the
+// large leaves near the diagonal) overlap the LOW work of the others instead
+// of forming a second launch of their own.  The classes keep separate
+// accumulators (the MFMA result layouts are the same): a leaf is written as
+// its LOW sum, plus its HIGH sum in one FP32 addition when the block has HIGH
+// entries -- the sums of the paper's product split by class, each over k
+// ascending.
+template <int B>
+__global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
+{
+    constexpr int MB = B / 32;
+    extern __shared__ float smem[];        // the BF16 stages, then the FP32 stages
+    const GemmJob &job = jobs.job[job_of(jobs, blockIdx.x)];
+    const int single = job.single;
+    const uint32_t blk = xcd_block(blockIdx.x - job.block0, job.nblocks);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int qa = w >> 1, qb = w & 1;
+    uint32_t I0 = 0, J0 = 0;
+    if (!single) {
+        I0 = 2 * lin_row(blk);
+        J0 = 2 * lin_col(blk);
+    }
+    floatx16 lo[MB][MB], hi[MB][MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+            lo[i][j] = floatx16{0};
+            hi[i][j] = floatx16{0};
+        }
+    bf16_products<B>((const uint16_t *)job.tA16, (const uint16_t *)job.tBT16, job.slotA, job.slotB,
+                     job.bent_lo, job.browptr_lo[blk], job.browptr_lo[blk + 1], I0, J0,
+                     (uint16_t *)smem, w, lane, lo);
+    __syncthreads();                       // every wave is done with the BF16 stages
+    const uint32_t h0 = job.browptr[blk], h1 = job.browptr[blk + 1];
+    fp32_products<B>((const float *)job.tA, (const float *)job.tBT, job.slotA, job.slotB, job.bent,
+                     h0, h1, I0, J0, smem, w, lane, hi);
     if (single && w != 0)
         return;
-    write_leaf32<B>(acc, (int64_t)(I0 + qa) * B, (int64_t)(J0 + qb) * B, n, C, 0, lane);
+    if (h0 != h1) {
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < MB; ++j)
+                lo[i][j] += hi[i][j];
+    }
+    write_leaf32<B>(lo, (int64_t)(I0 + qa) * B, (int64_t)(J0 + qb) * B, job.n, job.C, lane);
 }
 
 template <int B, bool SUB>
@@ -432,53 +485,68 @@ static hipError_t launch_fp32(const GemmJobs &jobs, hipStream_t s)
 }
 
 template <int B>
-static hipError_t launch_bf16(const GemmJobs &jobs, hipStream_t s)
+static hipError_t launch_split(const GemmJobs &jobs, hipStream_t s)
 {
-    constexpr size_t lds = sizeof(uint16_t) * 2 * 4 * B * B;
+    constexpr size_t lds_bf16 = sizeof(uint16_t) * 2 * 4 * B * B;
+    constexpr size_t lds = lds_bf16 > GemmShape<B>::kLds ? lds_bf16 : GemmShape<B>::kLds;
     static const hipError_t attr = hipFuncSetAttribute(
-        (const void *)leaf_gemm_bf16<B>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (const void *)leaf_gemm_split<B>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (attr != hipSuccess)
         return attr;
-    hipLaunchKernelGGL(leaf_gemm_bf16<B>, dim3(jobs.nblocks), dim3(256), lds, s, jobs);
+    hipLaunchKernelGGL(leaf_gemm_split<B>, dim3(jobs.nblocks), dim3(256), lds, s, jobs);
     return hipGetLastError();
 }
 
-// One batched launch of the FP32 (bf16 = false) or BF16 leaf GEMM over the
-// jobs' blocks; all jobs share the leaf size (and sub-leaf culling, n_b = 64).
-hipError_t launch_gemm_jobs(int leaf, bool bf16, const GemmJobs &jobs, hipStream_t s, bool sub)
+// One batched launch over the jobs' blocks; all jobs share the leaf size and
+// the kind.
+hipError_t launch_gemm_jobs(int leaf, GemmKind kind, const GemmJobs &jobs, hipStream_t s)
 {
     if (jobs.njobs <= 0 || jobs.nblocks == 0)
         return hipSuccess;
-    if (sub)
-        return leaf == 64 && !bf16 ? launch_fp32<64, true>(jobs, s) : hipErrorInvalidValue;
-    if (bf16) {
+    switch (kind) {
+    case GemmKind::Sub:
+        return leaf == 64 ? launch_fp32<64, true>(jobs, s) : hipErrorInvalidValue;
+    case GemmKind::Split:
         switch (leaf) {
-        case 32: return launch_bf16<32>(jobs, s);
-        case 64: return launch_bf16<64>(jobs, s);
+        case 32: return launch_split<32>(jobs, s);
+        case 64: return launch_split<64>(jobs, s);
+        default: return hipErrorInvalidValue;
+        }
+    case GemmKind::Fp32:
+        switch (leaf) {
+        case 16: return launch_fp32<16, false>(jobs, s);
+        case 32: return launch_fp32<32, false>(jobs, s);
+        case 64: return launch_fp32<64, false>(jobs, s);
         default: return hipErrorInvalidValue;
         }
     }
-    switch (leaf) {
-    case 16: return launch_fp32<16, false>(jobs, s);
-    case 32: return launch_fp32<32, false>(jobs, s);
-    case 64: return launch_fp32<64, false>(jobs, s);
-    default: return hipErrorInvalidValue;
-    }
+    return hipErrorInvalidValue;
 }
 
-// The plan's jobs: FP32 pass (write, or accumulate after the BF16 pass).
-void plan_jobs(const spamm_plan *p, float *C, bool bf16, GemmJob &j)
+GemmKind plan_kind(const spamm_plan *p)
 {
-    j.tA = bf16 ? (const void *)p->A->tiles16 : (const void *)p->A->tiles;
-    j.tBT = bf16 ? (const void *)p->B->tilesT16 : (const void *)p->B->tilesT;
-    j.browptr = bf16 ? p->browptr_lo : p->browptr;
-    j.bent = bf16 ? p->bent_lo : p->bent;
+    return p->sub ? GemmKind::Sub : p->precision != SPAMM_PREC_FP32 ? GemmKind::Split
+                                                                    : GemmKind::Fp32;
+}
+
+// The plan's job: FP32 copies and HIGH (or only) schedule; with split
+// precision also the BF16 copies and the LOW schedule.
+void plan_jobs(const spamm_plan *p, float *C, GemmJob &j)
+{
+    const bool split = p->precision != SPAMM_PREC_FP32;
+    j.tA = p->A->tiles;
+    j.tBT = p->B->tilesT;
+    j.browptr = p->browptr;
+    j.bent = p->bent;
     j.C = C;
     j.n = p->n;
     j.nblocks = (uint32_t)p->nblocks;
     j.block0 = 0;
     j.single = p->depth == 0 ? 1 : 0;
-    j.accumulate = (!bf16 && p->precision != SPAMM_PREC_FP32) ? 1 : 0;
+    j.tA16 = split ? (const void *)p->A->tiles16 : nullptr;
+    j.tBT16 = split ? (const void *)p->B->tilesT16 : nullptr;
+    j.browptr_lo = split ? p->browptr_lo : nullptr;
+    j.bent_lo = split ? p->bent_lo : nullptr;
     j.subA = j.subB = nullptr;
     j.submask = nullptr;
     j.subK = nullptr;
@@ -493,23 +561,16 @@ void plan_jobs(const spamm_plan *p, float *C, bool bf16, GemmJob &j)
     }
 }
 
-// FP32: one pass.  Split: the BF16 pass writes C, then the FP32 pass adds the
-// HIGH products (k ascending inside each class).
 hipError_t launch_gemm(const spamm_plan *p, float *C, hipStream_t s)
 {
     GemmJobs jobs{};
     jobs.njobs = 1;
     jobs.nblocks = (uint32_t)p->nblocks;
     hipError_t e;
-    if (p->precision != SPAMM_PREC_FP32) {
-        plan_jobs(p, C, true, jobs.job[0]);
-        if ((e = launch_gemm_jobs(p->leaf, true, jobs, s, false)) != hipSuccess)
-            return e;
-    }
     if (p->sub && (e = hipMemsetAsync(p->leafK + 2, 0, sizeof(uint64_t), s)) != hipSuccess)
         return e;
-    plan_jobs(p, C, false, jobs.job[0]);
-    return launch_gemm_jobs(p->leaf, false, jobs, s, p->sub != 0);
+    plan_jobs(p, C, jobs.job[0]);
+    return launch_gemm_jobs(p->leaf, plan_kind(p), jobs, s);
 }
 
 }  // namespace spamm

@@ -38,10 +38,11 @@ int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *o
 size_t tree_device_bytes(int64_t n, int32_t leaf, bool bf16, bool sub = false);
 size_t plan_device_bytes(int depth, bool split);
 
-// Leaf GEMM launches (gemm.hip).
-void plan_jobs(const spamm_plan *p, float *C, bool bf16, GemmJob &j);
-hipError_t launch_gemm_jobs(int leaf, bool bf16, const GemmJobs &jobs, hipStream_t s,
-                            bool sub = false);
+// Leaf GEMM launches (gemm.hip): a plan's job and kind, and one batched
+// launch of jobs of one kind and leaf size.
+void plan_jobs(const spamm_plan *p, float *C, GemmJob &j);
+GemmKind plan_kind(const spamm_plan *p);
+hipError_t launch_gemm_jobs(int leaf, GemmKind kind, const GemmJobs &jobs, hipStream_t s);
 
 // Exclusive scan of m uint32 (out[m] = total); partials: scan_partials_len(m).
 hipError_t launch_scan_u32(const uint32_t *in, uint32_t m, uint32_t *out, uint32_t *partials,

@@ -230,27 +230,23 @@ bool launch_batches(spamm_server *S)
             (S->active[i].job.rq.leaf == leaf && (int)batch.size() < kMaxJobs ? batch : rest)
                 .push_back(i);
         ready.swap(rest);
-        GemmJobs lo{}, hi{};
+        // split and FP32 jobs go to one launch each (different kernels)
+        GemmJobs sj{}, fj{};
         hipError_t e = hipSuccess;
         for (size_t i : batch) {
             Active &a = S->active[i];
             if (e == hipSuccess)
                 e = hipStreamWaitEvent(S->gemm, S->ev_cull[a.slot], 0);
-            if (a.split) {
-                GemmJob &j = lo.job[lo.njobs++];
-                plan_jobs(a.plan, a.job.rq.C, true, j);
-                j.block0 = lo.nblocks;
-                lo.nblocks += j.nblocks;
-            }
-            GemmJob &j = hi.job[hi.njobs++];
-            plan_jobs(a.plan, a.job.rq.C, false, j);
-            j.block0 = hi.nblocks;
-            hi.nblocks += j.nblocks;
+            GemmJobs &tab = a.split ? sj : fj;
+            GemmJob &j = tab.job[tab.njobs++];
+            plan_jobs(a.plan, a.job.rq.C, j);
+            j.block0 = tab.nblocks;
+            tab.nblocks += j.nblocks;
         }
-        if (e == hipSuccess && lo.njobs > 0)
-            e = launch_gemm_jobs(leaf, true, lo, S->gemm);
-        if (e == hipSuccess)
-            e = launch_gemm_jobs(leaf, false, hi, S->gemm);
+        if (e == hipSuccess && sj.njobs > 0)
+            e = launch_gemm_jobs(leaf, GemmKind::Split, sj, S->gemm);
+        if (e == hipSuccess && fj.njobs > 0)
+            e = launch_gemm_jobs(leaf, GemmKind::Fp32, fj, S->gemm);
         hipEvent_t bev = S->spare.back();
         if (e == hipSuccess)
             e = hipEventRecord(bev, S->gemm);
