@@ -205,7 +205,9 @@ int spamm_symbolic_ex(const spamm_tree *A, const spamm_tree *B, const spamm_opts
 /*
  * Numeric multiply: C = sum over kept k (ascending) of A_ik B_kj for every
  * output leaf, FP32 MFMA with FP32 accumulation (Eq. product, Alg. 1 steps
- * 7-9).  C: device pointer, n x n FP32 row-major, fully overwritten (zeros
+ * 7-9).  Split precision: the LOW products (BF16 operands) and the HIGH ones
+ * (FP32) are summed separately, each over k ascending, and a leaf is their
+ * sum.  C: device pointer, n x n FP32 row-major, fully overwritten (zeros
  * where no product lands; alpha = 1, beta = 0).  C must not overlap the
  * trees' storage; it may alias the matrix a tree was built from.  Enqueue on
  * the plan's stream or order streams yourself.
@@ -263,11 +265,13 @@ int spamm_multiply_opts(const spamm_tree *A, const spamm_tree *B, const spamm_op
  * (spamm_request_footprint bytes; C is the caller's), reused across requests
  * and grown when needed.  Requests wait in a FIFO queue; the scheduler admits
  * the head when a slot is free and its arena fits: idle arenas are released
- * to make room, and the arenas together never exceed the budget.  An admitted request's
- * trees and cull run on its slot's stream, overlapping other requests' work;
+ * to make room, and the arenas together never exceed the budget.  An
+ * admitted request's trees and cull run on its slot's stream, overlapping
+ * other requests' work;
  * the leaf products of every request whose cull has been enqueued are
- * gathered into one batched leaf-GEMM launch (up to 16 requests of one leaf
- * size per launch, uneven n, tau and precision allowed) on the server's
+ * gathered into one batched leaf-GEMM launch group (up to 16 requests of one
+ * leaf size, uneven n and tau; split and FP32 requests of a group share one
+ * launch per kind) on the server's
  * GEMM stream, so small products share the chip.  A squaring chain (the
  * matrix square is the central step of density-matrix purification,
  * Sec. IV.B) stays on the device: each step's product is rebuilt into a tree
@@ -308,7 +312,8 @@ typedef struct spamm_server_stats {
     int64_t  admitted;           /* requests admitted                                */
     int64_t  completed;          /* requests finished (any status)                   */
     int64_t  queued;             /* requests waiting for admission now               */
-    int64_t  launches;           /* batched leaf-GEMM launch groups (BF16 + FP32)     */
+    int64_t  launches;           /* batched leaf-GEMM launch groups (a split and an  */
+                                 /* FP32 launch when a batch mixes precisions)        */
     int64_t  launched_products;  /* products over all launch groups                  */
     int64_t  max_batch;          /* most products in one launch group                */
     int64_t  peak_active;        /* most requests admitted at once                   */
