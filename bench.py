@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MFMA_FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E peak
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "leaf_gemm_cluster1310-n32750_traffic.json")
 
 
@@ -57,6 +58,19 @@ def measured_traffic(workload: str):
     if rec.get("workload") != workload or rec.get("gemm_sources_sha256") != kernel_source_digest():
         return None
     return rec.get("bytes_per_launch")
+
+
+def measured_split_traffic(workload: str, tau: float, low_tol: float):
+    """HBM bytes per launch of the split kernel at (tau, low_tol) from the
+    committed counter runs, or None when the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"leaf_gemm_split_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if (t.get("gemm_sources_sha256") != kernel_source_digest() or
+            t.get("tau") != tau or abs(t.get("low_tol", -1.0) - low_tol) > 1e-12 * low_tol):
+        return None
+    return t["bytes_per_launch"]
 
 
 def sample_tiles(N: int, count: int, seed: int = 0):
@@ -99,6 +113,7 @@ def matched_error(sp, wl, A, dA, C, tau, leaf, n, N, reps=2):
                 best = ms if best is None else min(best, ms)
             points.append({"precision": "split-bf16" if lmul else "fp32", "tau": t_,
                            "low_tol": lmul * t_, "ms": round(best, 3), "err": max_err(),
+                           "ms_leaf_gemm": round(st["numeric_ms"], 3),
                            "tasks": st["tasks"], "low_frac": round(st["tasks_low"] / max(1, st["tasks"]), 4)})
     tree.free()
     target = next(p["err"] for p in points if p["precision"] == "fp32" and p["tau"] == tau)
@@ -132,12 +147,23 @@ def matched_error(sp, wl, A, dA, C, tau, leaf, n, N, reps=2):
         return min(ok, key=lambda p: p["ms"]) if ok else None
 
     f32, spl, sub = fastest("fp32"), fastest("split-bf16"), fastest("fp32-subleaf")
+    split_roofline = None
+    if spl is not None:
+        tb = measured_split_traffic(wl.name, spl["tau"], spl["low_tol"])
+        if tb is not None:
+            gbs = tb / (spl["ms_leaf_gemm"] * 1e-3) / 1e9
+            split_roofline = {"kernel": "leaf_gemm_split", "bound": "hbm", "achieved": round(gbs, 1),
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": tb,
+                              "note": "measured HBM bytes per launch / leaf-GEMM time; the LOW "
+                                      "phase runs above this average, the HIGH tail below"}
     return {
         "target_err": target,
         "err_sample": f"{len(tiles)} seeded output leaves (incl. diagonal), dense FP64 reference",
         "fp32_at_target": f32, "split_at_target": spl, "subleaf_at_target": sub,
         "speedup_split_vs_fp32": round(f32["ms"] / spl["ms"], 3) if f32 and spl else None,
         "speedup_subleaf_vs_fp32": round(f32["ms"] / sub["ms"], 3) if f32 and sub else None,
+        "split_roofline": split_roofline,
         "subleaf_same_tau": subleaf,
         "grid": "tau x {1,10,...,1e5}, low_tol = tau x {0 (fp32), 256, 1024, 4096, 16384}; "
                 "sub-leaf culling: tau x {0.1, 0.3, ..., 1e4}",
