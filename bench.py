@@ -68,7 +68,8 @@ def measured_split_traffic(workload: str, tau: float, low_tol: float):
         return None
     t = json.load(open(path))
     if (t.get("gemm_sources_sha256") != kernel_source_digest() or
-            t.get("tau") != tau or abs(t.get("low_tol", -1.0) - low_tol) > 1e-12 * low_tol):
+            abs(t.get("tau", -1.0) - tau) > 1e-12 * tau or
+            abs(t.get("low_tol", -1.0) - low_tol) > 1e-12 * low_tol):
         return None
     return t["bytes_per_launch"]
 
