@@ -363,7 +363,8 @@ int spamm_server_info(spamm_server *server, spamm_server_stats *out);
 /*
  * Stop the server: queued requests that were not admitted are dropped
  * (their C is not written), admitted ones run to completion, then the
- * scheduler thread, streams and memory are released.  NULL is a no-op.
+ * scheduler thread, streams and memory are released.  No other call on the
+ * server may run concurrently with or after this one.  NULL is a no-op.
  */
 int spamm_server_destroy(spamm_server *server);
 
