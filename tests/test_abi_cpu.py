@@ -60,3 +60,37 @@ def test_python_binding_rejects_cpu_tensors():
     torch = pytest.importorskip("torch")
     with pytest.raises(ValueError):
         sp.build_tree(torch.zeros(8, 8), 16)
+
+
+def test_newer_entry_points_check_arguments_on_the_host():
+    lib = sp.load()
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(4096)
+    dbl = ctypes.c_double
+    # epsilon-sparsified build: flags, tolerance and the other operand's norm
+    assert lib.spamm_build_tree_sparse(fake, 64, 32, 2, dbl(1e-6), dbl(0.0), None,
+                                       ctypes.byref(h)) == sp.SPAMM_E_INVAL   # SUBNORMS
+    assert lib.spamm_build_tree_sparse(fake, 64, 16, 1, dbl(1e-6), dbl(0.0), None,
+                                       ctypes.byref(h)) == sp.SPAMM_E_INVAL   # BF16 at leaf 16
+    for tau in (-1.0, float("nan"), float("inf"), 1e-200):
+        assert lib.spamm_build_tree_sparse(fake, 64, 32, 0, dbl(tau), dbl(0.0), None,
+                                           ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    for other in (-1.0, float("nan"), float("inf")):
+        assert lib.spamm_build_tree_sparse(fake, 64, 32, 0, dbl(1e-6), dbl(other), None,
+                                           ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_build_tree_sparse(None, 64, 32, 0, dbl(1e-6), dbl(0.0), None,
+                                       ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_build_tree_sparse(fake, 64, 32, 0, dbl(1e-6), dbl(0.0), None,
+                                       None) == sp.SPAMM_E_INVAL
+    assert lib.spamm_build_tree_sparse(fake, 16 * 1024 + 1, 16, 0, dbl(1e-6), dbl(0.0), None,
+                                       ctypes.byref(h)) == sp.SPAMM_E_RANGE
+    # sub-block norms only for 64 x 64 leaves; unknown flags
+    assert lib.spamm_build_tree_ex(fake, 64, 32, 2, None, ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_build_tree_ex(fake, 64, 64, 4, None, ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    # NULL handles
+    assert lib.spamm_tree_storage(None, None, None, None) == sp.SPAMM_E_INVAL
+    cnt = ctypes.c_size_t()
+    assert lib.spamm_plan_subtasks(None, None, 0, ctypes.byref(cnt)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_plan_stats(None, None) == sp.SPAMM_E_INVAL
+    assert lib.spamm_plan_tasks(None, None, 0, ctypes.byref(cnt)) == sp.SPAMM_E_INVAL
+    assert h.value is None
