@@ -325,8 +325,21 @@ def serve_bench(sp, torch, dev, count, slots, budget_gib):
     print(f"serving inputs: {len(reqs)} matrices in {t_gen:.1f} s", file=sys.stderr, flush=True)
     srv = sp.Server(int(budget_gib * (1 << 30)), max_slots=slots)
     try:
-        warm = workloads.serving_mix(24, seed=99)
+        # warm-up outside the timed runs: every slot's arena grown to the largest
+        # footprint (no device allocation inside the timed runs), every
+        # size x precision x chain combination run once, torch's cache holding
+        # output buffers for the outstanding requests
+        big = max(workloads.SERVE_SIZES)
+        warm = [workloads.ServeRequest(i, big, 0.05, 1e-8, 0, True, 900000 + i, 1.0)
+                for i in range(slots)]
+        warm += [workloads.ServeRequest(len(warm) + j, n_, 0.1, 1e-6, chain, split, 910000 + j, 1.0)
+                 for j, (n_, chain, split) in enumerate(
+                     (n_, c, sp_) for n_ in workloads.SERVE_SIZES for c in (0, 10)
+                     for sp_ in (False, True))]
         serve_run(sp, torch, srv, warm, serve_inputs(torch, warm, dev), window=slots)
+        spare = [torch.empty((n_, n_), device=dev) for n_ in workloads.SERVE_SIZES
+                 for _ in range(2 * slots)]
+        del spare
         res, _, tm = serve_run(sp, torch, srv, reqs, inputs, window=2 * slots)
         sat = serve_summary(reqs, res, tm, None)
         print(f"saturation: {sat['throughput_rps']:.2f} req/s, p50 {sat['p50_ms']} ms, "
@@ -417,6 +430,10 @@ def main() -> int:
                     help="skip the FP32-vs-split comparison at a fixed max-norm error")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark instead: saturation, then Poisson arrivals")
+    ap.add_argument("--precision", choices=("fp32", "split"), default="fp32",
+                    help="product of the timed steps (split: BF16 for LOW products)")
+    ap.add_argument("--low-tol", type=float, default=0.4096,
+                    help="split precision: absolute LOW threshold on the norm product")
     ap.add_argument("--no-sparse", action="store_true",
                     help="skip the epsilon-sparsified tree comparison")
     ap.add_argument("--no-serve", action="store_true",
@@ -462,9 +479,13 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
+    split = args.precision == "split"
+    prec = sp.PREC_SPLIT_BF16 if split else sp.PREC_FP32
+
     def step():
-        tree = sp.build_tree(dA, leaf)          # synchronizes once (root norm)
-        st = sp.multiply_ex(tree, tree, tau, C)  # events around cull and GEMM
+        tree = sp.build_tree(dA, leaf, bf16=split)   # synchronizes once (root norm)
+        st = sp.multiply_ex(tree, tree, tau, C, precision=prec,
+                            low_tol=args.low_tol if split else 0.0)   # events around cull and GEMM
         tree.free()
         return st
 
@@ -534,6 +555,18 @@ def main() -> int:
             "traffic": measured_traffic(wl.name),
         },
     }
+    if split:
+        # the split kernel moves whole BF16 leaves: rate it against HBM
+        tb = measured_split_traffic(wl.name, tau, args.low_tol)
+        gbs = tb / (gemm_ms * 1e-3) / 1e9 if tb is not None else None
+        out["dtype"] = "f32+bf16"
+        out["config"]["precision"] = "split-bf16"
+        out["config"]["low_tol"] = args.low_tol
+        out["config"]["tasks_low"] = st["tasks_low"]
+        out["roofline"] = {
+            "bound": "hbm", "achieved": round(gbs, 1) if gbs else None, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4) if gbs else None, "traffic": tb,
+        }
 
     # ---- epsilon-sparsified tree of the same matrix ----------------------------
     # leaves below tau / ||A||_F dropped at build; the product keeps the same
