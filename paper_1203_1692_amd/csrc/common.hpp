@@ -93,11 +93,6 @@ struct Leaf16Layout {
     }
 };
 
-__host__ __device__ inline int leaf16_index(int B, int r, int c)
-{
-    return B == 32 ? Leaf16Layout<32>::index(r, c) : Leaf16Layout<64>::index(r, c);
-}
-
 // FP32 -> BF16 with round-to-nearest-even on the bit pattern (inputs are
 // finite: non-finite matrices are rejected when the tree is built).
 __host__ __device__ inline uint16_t to_bf16(float x)

@@ -16,7 +16,8 @@
 // copies operand leaf w's panel with direct-to-LDS loads (global_load_lds,
 // 1 KB per instruction, no registers), into one of two LDS buffers: the copy
 // of stage t+1 is in flight while stage t is multiplied.  One barrier per
-// stage.  Two workgroups per CU (64 KB LDS each at n_b = 64).
+// stage.  The block's entry list is copied to LDS first.  Two workgroups per
+// CU (68 KB LDS each at n_b = 64).
 //
 // Operand feed.  In a panel, lane l reads 4 consecutive k of its row with one
 // conflict-free ds_read_b128.  v_mfma_f32_32x32x2_f32: A operand of lane l is
@@ -41,8 +42,32 @@ template <int B>
 struct GemmShape {
     using L = LeafLayout<B>;
     static constexpr int kStage = 4 * L::kPanel;                     // floats per stage
-    static constexpr size_t kLds = sizeof(float) * 2 * kStage;       // double buffered
+    // double-buffered stages, then the block's entry list
+    static constexpr size_t kLds = sizeof(float) * 2 * kStage + sizeof(uint32_t) * (1 << kMaxDepth);
 };
+
+// Split kernel: the BF16 stages (four whole leaves, double buffered) and the
+// FP32 stages share one area, followed by the entry list.
+template <int B>
+struct SplitShape {
+    static constexpr size_t kBf16 = sizeof(uint16_t) * 2 * 4 * B * B;
+    static constexpr size_t kFp32 = sizeof(float) * 2 * GemmShape<B>::kStage;
+    static constexpr size_t kStages = kBf16 > kFp32 ? kBf16 : kFp32;
+    static constexpr size_t kLds = kStages + sizeof(uint32_t) * (1 << kMaxDepth);
+};
+
+// A block's schedule holds at most one entry per k (N <= 2^kMaxDepth); it is
+// copied to LDS once, so a stage reads its entry from there instead of
+// waiting on a global load.
+constexpr int kMaxEnt = 1 << kMaxDepth;
+
+__device__ inline void load_entries(const uint32_t *__restrict__ bent, uint32_t e0, uint32_t e1,
+                                    uint32_t *ents)
+{
+    for (uint32_t i = threadIdx.x; i < e1 - e0; i += blockDim.x)
+        ents[i] = bent[e0 + i];
+    __syncthreads();
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
 // contiguous range of blocks (linear-index order) so its L2 sees neighbours.
@@ -200,24 +225,25 @@ template <int B>
 __device__ inline void fp32_products(const float *__restrict__ tA, const float *__restrict__ tBT,
                                      const uint32_t *slotA, const uint32_t *slotB,
                                      const uint32_t *__restrict__ bent, uint32_t e0, uint32_t e1,
-                                     uint32_t I0, uint32_t J0, float *smem, int w, int lane,
-                                     floatx16 (&acc)[B / 32][B / 32])
+                                     uint32_t I0, uint32_t J0, float *smem, uint32_t *ents, int w,
+                                     int lane, floatx16 (&acc)[B / 32][B / 32])
 {
     using L = LeafLayout<B>;
     using S = GemmShape<B>;
     constexpr int NP = L::kPanels;
     const int qa = w >> 1, qb = w & 1;
+    load_entries(bent, e0, e1, ents);
     const uint32_t T = (e1 - e0) * NP;                  // stages of this block
     if (T > 0)
-        stage_issue<B>(bent[e0], 0, tA, tBT, slotA, slotB, I0, J0, smem, w, lane);
+        stage_issue<B>(ents[0], 0, tA, tBT, slotA, slotB, I0, J0, smem, w, lane);
     for (uint32_t t = 0; t < T; ++t) {
-        const uint32_t ent = bent[e0 + t / NP];
+        const uint32_t ent = ents[t / NP];
         // this wave's copies of stage t have landed; after the barrier every
         // wave's have, and every wave is done reading the other buffer
         __builtin_amdgcn_s_waitcnt(0x0F70);             // vmcnt(0)
         __syncthreads();
         if (t + 1 < T)
-            stage_issue<B>(bent[e0 + (t + 1) / NP], (int)((t + 1) % NP), tA, tBT, slotA, slotB,
+            stage_issue<B>(ents[(t + 1) / NP], (int)((t + 1) % NP), tA, tBT, slotA, slotB,
                            I0, J0, smem + ((t + 1) & 1) * S::kStage, w, lane);
         if ((ent >> (16 + w)) & 1u) {
             const float *buf = smem + (t & 1) * S::kStage;
@@ -247,7 +273,7 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
     using L = LeafLayout<B>;
     using S = GemmShape<B>;
     constexpr int NP = L::kPanels;
-    extern __shared__ float smem[];       // 2 stages x {A_2I, A_2I+1, B_2J, B_2J+1} panels
+    extern __shared__ float smem[];       // 2 stages x {A_2I, A_2I+1, B_2J, B_2J+1} panels, entries
     const GemmJob &job = jobs.job[job_of(jobs, blockIdx.x)];
     const float *__restrict__ tA = (const float *)job.tA;
     const float *__restrict__ tBT = (const float *)job.tBT;
@@ -280,24 +306,27 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
 
     const uint32_t e0 = browptr[blk], e1 = browptr[blk + 1];
     if constexpr (!SUB && B >= 32) {
-        fp32_products<B>(tA, tBT, job.slotA, job.slotB, bent, e0, e1, I0, J0, smem, w, lane, acc);
+        fp32_products<B>(tA, tBT, job.slotA, job.slotB, bent, e0, e1, I0, J0, smem,
+                         (uint32_t *)(smem + 2 * S::kStage), w, lane, acc);
         if (single && w != 0)
             return;
         write_leaf32<B>(acc, (int64_t)(I0 + qa) * B, (int64_t)(J0 + qb) * B, n, C, lane);
         return;
     }
+    uint32_t *ents = (uint32_t *)(smem + 2 * S::kStage);
+    load_entries(bent, e0, e1, ents);
     const uint32_t T = (e1 - e0) * NP;                  // stages of this block
     uint32_t smask = 0, sub_count = 0;                  // SUB: this entry's kept sub-products
     if (T > 0)
-        stage_issue<B>(bent[e0], 0, tA, tBT, job.slotA, job.slotB, I0, J0, smem, w, lane);
+        stage_issue<B>(ents[0], 0, tA, tBT, job.slotA, job.slotB, I0, J0, smem, w, lane);
     for (uint32_t t = 0; t < T; ++t) {
-        const uint32_t ent = bent[e0 + t / NP];
+        const uint32_t ent = ents[t / NP];
         // this wave's copies of stage t have landed; after the barrier every
         // wave's have, and every wave is done reading the other buffer
         __builtin_amdgcn_s_waitcnt(0x0F70);             // vmcnt(0)
         __syncthreads();
         if (t + 1 < T)
-            stage_issue<B>(bent[e0 + (t + 1) / NP], (int)((t + 1) % NP), tA, tBT, job.slotA,
+            stage_issue<B>(ents[(t + 1) / NP], (int)((t + 1) % NP), tA, tBT, job.slotA,
                            job.slotB, I0, J0, smem + ((t + 1) & 1) * S::kStage, w, lane);
         const bool mine = (ent >> (16 + w)) & 1u;
         if constexpr (SUB) {
@@ -362,7 +391,7 @@ __device__ inline void bf16_products(const uint16_t *__restrict__ tA16,
                                      const uint16_t *__restrict__ tBT16, const uint32_t *slotA,
                                      const uint32_t *slotB, const uint32_t *__restrict__ bent,
                                      uint32_t e0, uint32_t e1, uint32_t I0, uint32_t J0,
-                                     uint16_t *smem16, int w, int lane,
+                                     uint16_t *smem16, uint32_t *ents, int w, int lane,
                                      floatx16 (&acc)[B / 32][B / 32])
 {
     using L = Leaf16Layout<B>;
@@ -383,16 +412,17 @@ __device__ inline void bf16_products(const uint16_t *__restrict__ tA16,
             __builtin_amdgcn_global_load_lds((global_void_t *)(src + 512 * i), (lds_void_t *)(d + 512 * i),
                                              16, 0, 0);
     };
+    load_entries(bent, e0, e1, ents);
     const uint32_t T = e1 - e0;
     if (T > 0)
-        issue(bent[e0], smem16);
+        issue(ents[0], smem16);
     const int r = lane & 31, h = lane >> 5;
     for (uint32_t t = 0; t < T; ++t) {
-        const uint32_t ent = bent[e0 + t];
+        const uint32_t ent = ents[t];
         __builtin_amdgcn_s_waitcnt(0x0F70);             // vmcnt(0)
         __syncthreads();
         if (t + 1 < T)
-            issue(bent[e0 + t + 1], smem16 + ((t + 1) & 1) * (4 * LEAF));
+            issue(ents[t + 1], smem16 + ((t + 1) & 1) * (4 * LEAF));
         if ((ent >> (16 + w)) & 1u) {
             const uint16_t *buf = smem16 + (t & 1) * (4 * LEAF);
             const uint16_t *Ap = buf + qa * LEAF;
@@ -443,6 +473,8 @@ __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
         I0 = 2 * lin_row(blk);
         J0 = 2 * lin_col(blk);
     }
+    constexpr size_t kStages = SplitShape<B>::kStages;
+    uint32_t *ents = (uint32_t *)((char *)smem + kStages);
     floatx16 lo[MB][MB], hi[MB][MB];
 #pragma unroll
     for (int i = 0; i < MB; ++i)
@@ -453,11 +485,11 @@ __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
         }
     bf16_products<B>((const uint16_t *)job.tA16, (const uint16_t *)job.tBT16, job.slotA, job.slotB,
                      job.bent_lo, job.browptr_lo[blk], job.browptr_lo[blk + 1], I0, J0,
-                     (uint16_t *)smem, w, lane, lo);
+                     (uint16_t *)smem, ents, w, lane, lo);
     __syncthreads();                       // every wave is done with the BF16 stages
     const uint32_t h0 = job.browptr[blk], h1 = job.browptr[blk + 1];
     fp32_products<B>((const float *)job.tA, (const float *)job.tBT, job.slotA, job.slotB, job.bent,
-                     h0, h1, I0, J0, smem, w, lane, hi);
+                     h0, h1, I0, J0, smem, ents, w, lane, hi);
     if (single && w != 0)
         return;
     if (h0 != h1) {
@@ -487,8 +519,7 @@ static hipError_t launch_fp32(const GemmJobs &jobs, hipStream_t s)
 template <int B>
 static hipError_t launch_split(const GemmJobs &jobs, hipStream_t s)
 {
-    constexpr size_t lds_bf16 = sizeof(uint16_t) * 2 * 4 * B * B;
-    constexpr size_t lds = lds_bf16 > GemmShape<B>::kLds ? lds_bf16 : GemmShape<B>::kLds;
+    constexpr size_t lds = SplitShape<B>::kLds;
     static const hipError_t attr = hipFuncSetAttribute(
         (const void *)leaf_gemm_split<B>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (attr != hipSuccess)
