@@ -243,30 +243,27 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
     t->depth = d;
     t->sub = sub;
     t->stored = int64_t(1) << (2 * d);
+    // one block for every buffer: the caller's arena, else an allocation of
+    // the tree's own
     hipError_t e = hipSuccess;
+    char *base = (char *)arena;
     if (arena != nullptr) {
-        char *base = (char *)arena;
         t->borrowed = true;
+    } else {
+        e = hipMallocAsync(&t->block, L.total, s);
+        if (e != hipSuccess)
+            t->block = nullptr;
+        base = (char *)t->block;
+    }
+    if (e == hipSuccess) {
         t->tiles = (float *)(base + L.tiles);
         t->tilesT = (float *)(base + L.tilesT);
         t->tiles16 = bf16 ? (uint16_t *)(base + L.t16) : nullptr;
         t->tilesT16 = bf16 ? (uint16_t *)(base + L.tT16) : nullptr;
         t->norms = (double *)(base + L.norms);
-    } else {
-        const size_t tile_bytes = L.tilesT - L.tiles, half = L.tT16 - L.t16;
-        e = hipMallocAsync((void **)&t->tiles, tile_bytes, s);
-        if (e == hipSuccess)
-            e = hipMallocAsync((void **)&t->tilesT, tile_bytes, s);
-        if (e == hipSuccess && bf16)
-            e = hipMallocAsync((void **)&t->tiles16, half, s);
-        if (e == hipSuccess && bf16)
-            e = hipMallocAsync((void **)&t->tilesT16, half, s);
-        if (e == hipSuccess)
-            e = hipMallocAsync((void **)&t->norms, L.total - L.norms, s);
-    }
-    if (e == hipSuccess)
         e = launch_build(A, n, leaf, d, t->tiles, t->tilesT, t->tiles16, t->tilesT16, t->norms, sub,
                          s);
+    }
     if (e == hipSuccess && root_dst != nullptr)
         e = hipMemcpyAsync(root_dst, t->norms, sizeof(double), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) {
@@ -343,22 +340,27 @@ int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *o
     const PlanSizes z = plan_sizes(d);
     for (int t = 0; t <= d; ++t)
         p->rp_off[t] = z.rp_off[t];
+    // every buffer at its offset of one block: the caller's arena, else an
+    // allocation of the plan's own
     PlanBuf bufs[12];
     const int nb = plan_bufs(p, z, split, sub, bufs);
-    size_t off = 0;
-    for (int i = 0; i < nb; ++i) {
-        if (arena != nullptr) {
-            *bufs[i].dst = (char *)arena + off;
-            off += align256(bufs[i].bytes);
-            continue;
-        }
-        hipError_t e = hipMallocAsync(bufs[i].dst, bufs[i].bytes, s);
+    size_t total = 0;
+    for (int i = 0; i < nb; ++i)
+        total += align256(bufs[i].bytes);
+    char *base = (char *)arena;
+    if (base == nullptr) {
+        hipError_t e = hipMallocAsync((void **)&base, total, s);
         if (e != hipSuccess) {
             rc = hip_fail(e, "hipMallocAsync (plan)");
             spamm_plan_free(p);
             return rc;
         }
-        p->pool[p->npool++] = *bufs[i].dst;
+        p->block = base;
+    }
+    size_t off = 0;
+    for (int i = 0; i < nb; ++i) {
+        *bufs[i].dst = base + off;
+        off += align256(bufs[i].bytes);
     }
     hipError_t e = launch_cull(p, s);
     if (e != hipSuccess) {
@@ -551,13 +553,18 @@ int spamm_tree_free(spamm_tree *t)
     if (dev0 != t->device)
         hipSetDevice(t->device);
     hipError_t e = hipSuccess;
-    for (void *ptr : {(void *)t->tiles, (void *)t->tilesT, (void *)t->tiles16, (void *)t->tilesT16,
-                      (void *)t->norms, (void *)t->slot, (void *)t->keep}) {
-        if (ptr == nullptr || t->borrowed)
-            continue;
-        hipError_t f = hipFreeAsync(ptr, t->stream);
-        if (e == hipSuccess)
-            e = f;
+    if (t->block != nullptr) {
+        e = hipFreeAsync(t->block, t->stream);
+    } else if (!t->borrowed) {
+        // sparsified trees: one allocation per buffer
+        for (void *ptr : {(void *)t->tiles, (void *)t->tilesT, (void *)t->tiles16,
+                          (void *)t->tilesT16, (void *)t->norms, (void *)t->slot, (void *)t->keep}) {
+            if (ptr == nullptr)
+                continue;
+            hipError_t f = hipFreeAsync(ptr, t->stream);
+            if (e == hipSuccess)
+                e = f;
+        }
     }
     if (dev0 >= 0 && dev0 != t->device)
         hipSetDevice(dev0);
@@ -648,12 +655,7 @@ int spamm_plan_free(spamm_plan *p)
     hipGetDevice(&dev0);
     if (dev0 != p->device)
         hipSetDevice(p->device);
-    hipError_t e = hipSuccess;
-    for (int i = 0; i < p->npool; ++i) {
-        hipError_t f = hipFreeAsync(p->pool[i], p->stream);
-        if (e == hipSuccess)
-            e = f;
-    }
+    hipError_t e = p->block != nullptr ? hipFreeAsync(p->block, p->stream) : hipSuccess;
     if (dev0 >= 0 && dev0 != p->device)
         hipSetDevice(dev0);
     delete p;

@@ -181,6 +181,7 @@ struct spamm_tree {
     double *norms;          // tiers 0..d (0..d+1 with sub-norms), tier_offset layout
     double root;            // ||A||_F^2
     bool borrowed;          // buffers carved from a caller's arena (not freed here)
+    void *block;            // dense trees: the one allocation holding every buffer
     bool sub;               // tier d+1 holds the norms of the 32 x 32 sub-blocks (n_b = 64)
     // epsilon-sparsified tree: only the kept leaves are stored, leaf l at
     // slot[l] (dropped leaves have norm 0 and are never read); else null
@@ -216,6 +217,5 @@ struct spamm_plan {
     uint8_t *submask;       // sub-leaf culling: 4 bytes per leaf-tier entry, else null
     int32_t sub;            // sub-leaf culling in the numeric multiply
     int64_t nblocks;
-    void *pool[12];         // allocations owned by the plan
-    int npool;
+    void *block;            // the plan's one allocation (all buffers), or null in an arena
 };
