@@ -128,6 +128,10 @@ __device__ inline void panel_mfma32(const float *__restrict__ Ap, const float *_
     for (int g = 0; g < NG; ++g) {
         if (g + 1 < NG)
             load((g + 1) & 1, g + 1);
+        // scheduling fence: the reads issued above stay ahead of this group's
+        // MFMAs in registers of their own, rather than being sunk behind them
+        // into the same registers (0.3-0.6 % faster, same code otherwise)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
