@@ -63,6 +63,16 @@ def _load():
         lib.oracle_spamm_tiles_split.restype = ctypes.c_int
         lib.oracle_bf16.argtypes = [ctypes.c_float]
         lib.oracle_bf16.restype = dbl
+        lib.oracle_spamm_split_fmt.argtypes = [vp, vp, i64, i32, dbl, dbl, ctypes.c_int, vp, vp,
+                                               i64, vp, vp, vp]
+        lib.oracle_spamm_split_fmt.restype = ctypes.c_int
+        lib.oracle_spamm_tiles_split_fmt.argtypes = [vp, vp, i64, i32, dbl, dbl, ctypes.c_int, vp,
+                                                     i64, vp, vp, vp, ctypes.c_int]
+        lib.oracle_spamm_tiles_split_fmt.restype = ctypes.c_int
+        lib.oracle_fp16_exponent.argtypes = [dbl]
+        lib.oracle_fp16_exponent.restype = ctypes.c_int
+        lib.oracle_fp16_scaled.argtypes = [ctypes.c_float, ctypes.c_int]
+        lib.oracle_fp16_scaled.restype = dbl
         _lib = lib
     return _lib
 
@@ -114,6 +124,21 @@ def bf16(x: float) -> float:
     return float(_load().oracle_bf16(x))
 
 
+def fp16_exponent(S: float) -> int:
+    """Scale exponent e of a leaf with squared norm S for binary16 LOW
+    operands: every entry of the leaf has |x| 2^e < 2^14 (0 when S = 0)."""
+    return int(_load().oracle_fp16_exponent(float(S)))
+
+
+def fp16_scaled(x: float, e: int) -> float:
+    """x (a float32) times 2^e rounded to the nearest binary16 (ties to even,
+    subnormals kept), times 2^-e."""
+    return float(_load().oracle_fp16_scaled(x, int(e)))
+
+
+LOW_FMT = {"bf16": 0, "fp16": 1}
+
+
 class Result:
     def __init__(self, C, keys, Kt, Klow=0):
         self.C = C          # float64 n x n (or None)
@@ -127,9 +152,12 @@ class Result:
 
 
 def spamm(A: np.ndarray, B: np.ndarray, b: int, tau: float, want_C: bool = True,
-          want_keys: bool = True, cap: int | None = None, low_tol: float = 0.0) -> Result:
+          want_keys: bool = True, cap: int | None = None, low_tol: float = 0.0,
+          low_fmt: str = "bf16") -> Result:
     """Full recursive SpAMM product in FP64; low_tol > 0 selects split
-    precision (LOW products on bfloat16-rounded operands)."""
+    precision (LOW products on operands rounded to bfloat16, or with
+    low_fmt="fp16" to binary16 at each leaf's power-of-two scale)."""
+    fmt = LOW_FMT[low_fmt]
     A, B = _f32(A), _f32(B)
     n = A.shape[0]
     if B.shape[0] != n:
@@ -143,15 +171,15 @@ def spamm(A: np.ndarray, B: np.ndarray, b: int, tau: float, want_C: bool = True,
     if want_keys:
         if cap is None:
             # count first so the key buffer is exactly sized
-            rc = _load().oracle_spamm_split(A.ctypes.data, B.ctypes.data, n, b, float(tau),
-                                            float(low_tol), None, None, 0, nk.ctypes.data,
-                                            Kt.ctypes.data, kl.ctypes.data)
+            rc = _load().oracle_spamm_split_fmt(A.ctypes.data, B.ctypes.data, n, b, float(tau),
+                                                float(low_tol), fmt, None, None, 0,
+                                                nk.ctypes.data, Kt.ctypes.data, kl.ctypes.data)
             if rc:
                 raise RuntimeError(f"oracle_spamm -> {rc}")
             cap = int(nk[0])
         keys = np.empty(max(cap, 1), dtype=np.uint64)
-    rc = _load().oracle_spamm_split(A.ctypes.data, B.ctypes.data, n, b, float(tau), float(low_tol),
-                                    None if C is None else C.ctypes.data,
+    rc = _load().oracle_spamm_split_fmt(A.ctypes.data, B.ctypes.data, n, b, float(tau),
+                                        float(low_tol), fmt, None if C is None else C.ctypes.data,
                                     None if keys is None else keys.ctypes.data,
                                     0 if keys is None else cap, nk.ctypes.data, Kt.ctypes.data,
                                     kl.ctypes.data)
@@ -163,7 +191,8 @@ def spamm(A: np.ndarray, B: np.ndarray, b: int, tau: float, want_C: bool = True,
 
 
 def spamm_tiles(A: np.ndarray, B: np.ndarray, b: int, tau: float, tiles,
-                threads: int = 1, want_klists: bool = False, low_tol: float = 0.0):
+                threads: int = 1, want_klists: bool = False, low_tol: float = 0.0,
+                low_fmt: str = "bf16"):
     """Per-tile recursion for the output tiles ``tiles`` ((I, J) pairs).
 
     Returns (Ctiles [ntiles, b, b] float64, counts [ntiles], klists or None);
@@ -178,8 +207,9 @@ def spamm_tiles(A: np.ndarray, B: np.ndarray, b: int, tau: float, tiles,
     Ct = np.empty((m, b, b), dtype=np.float64)
     counts = np.zeros(m, dtype=np.int64)
     kl = np.empty((m, 1 << d), dtype=np.int32) if want_klists else None
-    rc = _load().oracle_spamm_tiles_split(A.ctypes.data, B.ctypes.data, n, b, float(tau),
-                                          float(low_tol), t.ctypes.data, m, Ct.ctypes.data,
+    rc = _load().oracle_spamm_tiles_split_fmt(A.ctypes.data, B.ctypes.data, n, b, float(tau),
+                                              float(low_tol), LOW_FMT[low_fmt], t.ctypes.data,
+                                              m, Ct.ctypes.data,
                                           counts.ctypes.data,
                                           None if kl is None else kl.ctypes.data, int(threads))
     if rc:

@@ -34,7 +34,10 @@
  * to): a kept leaf product is LOW iff s_A * s_B < low_tol^2; its operands
  * are rounded elementwise to bfloat16 (8 significant bits, round to nearest,
  * ties to even) before the (exact, FP64) products; other products are
- * unchanged.  The class is part of the task key (bit 63).
+ * unchanged.  The class is part of the task key (bit 63).  With binary16
+ * LOW operands each leaf is scaled by a power of two 2^e fixed by its
+ * squared norm before the rounding (11 significant bits, subnormal spacing
+ * 2^-24), and the product is scaled back by 2^-(eA + eB).
  */
 #include <math.h>
 #include <stdint.h>
@@ -161,6 +164,7 @@ typedef struct {
     int64_t cap, nkeys;
     int64_t *Kt;           /* kept count per tier, d+1 entries */
     int64_t Klow;          /* kept leaf products classed LOW */
+    int fmt;               /* LOW operands: 0 bfloat16, 1 binary16 with a leaf scale */
 } mul_ctx;
 
 static int kept(const mul_ctx *x, int t, int64_t I, int64_t K, int64_t J)
@@ -193,6 +197,37 @@ static double to_bf16(float x)
 
 double oracle_bf16(float x) { return to_bf16(x); }
 
+/* Scale exponent of a leaf whose squared norm is S, for binary16 operands:
+ * with S = m 2^p (0.5 <= m < 1) every entry has |x| <= sqrt(S) < 2^q,
+ * q = ceil(p / 2), so e = 14 - q keeps every scaled entry |x| 2^e below 2^14,
+ * well inside binary16's range (largest finite 65504).  A zero leaf is never
+ * multiplied; it gets 0. */
+int oracle_fp16_exponent(double S)
+{
+    if (!(S > 0.0))
+        return 0;
+    int p;
+    frexp(S, &p);
+    int q = p >= 0 ? (p + 1) / 2 : -((-p) / 2);
+    return 14 - q;
+}
+
+/* x 2^e rounded to the nearest binary16 value (ties to even), scaled back by
+ * 2^-e, as a double (exact).  binary16 keeps 11 significant bits for
+ * magnitudes in [2^-14, 2^16) and a fixed spacing 2^-24 below 2^-14; the
+ * caller keeps |x 2^e| below 2^15. */
+double oracle_fp16_scaled(float x, int e)
+{
+    double y = ldexp((double)x, e);
+    if (y == 0.0)
+        return 0.0;
+    int E;
+    frexp(fabs(y), &E);             /* leading bit of |y| is 2^(E-1) */
+    int lead = E - 1 < -14 ? -14 : E - 1;
+    double quantum = ldexp(1.0, lead - 10);
+    double r = nearbyint(y / quantum) * quantum;   /* default mode: nearest, ties to even */
+    return ldexp(r, -e);
+}
 static int is_low(const mul_ctx *x, int t, int64_t I, int64_t K, int64_t J)
 {
     int64_t Nt = (int64_t)1 << t;
@@ -201,20 +236,29 @@ static int is_low(const mul_ctx *x, int t, int64_t I, int64_t K, int64_t J)
     return sa * sb < x->L2;
 }
 
-/* Element (r, c) of the padded matrix, rounded to bfloat16 when low. */
-static double elem_p(const float *A, int64_t n, int64_t r, int64_t c, int low)
+/* Element (r, c) of the padded matrix; for a LOW product rounded to
+ * bfloat16, or (fmt 1) to binary16 at the leaf's scale exponent e. */
+static double elem_p(const float *A, int64_t n, int64_t r, int64_t c, int low, int fmt, int e)
 {
     if (r >= n || c >= n)
         return 0.0;
-    return low ? to_bf16(A[r * n + c]) : (double)A[r * n + c];
+    if (!low)
+        return (double)A[r * n + c];
+    return fmt ? oracle_fp16_scaled(A[r * n + c], e) : to_bf16(A[r * n + c]);
 }
 
 /* C_IJ += A_IK * B_KJ over the n x n (unpadded) part, l ascending; operands
- * rounded to bfloat16 for a LOW product. */
+ * rounded to the LOW format for a LOW product. */
 static void leaf_product(mul_ctx *x, int64_t I, int64_t K, int64_t J, double *Ct,
                          int64_t ldc, int64_t r0, int64_t c0, int low)
 {
     int64_t b = x->b, n = x->n;
+    int64_t Nd = (int64_t)1 << x->d;
+    int eA = 0, eB = 0;
+    if (low && x->fmt) {
+        eA = oracle_fp16_exponent(x->sA[tier_offset(x->d) + I * Nd + K]);
+        eB = oracle_fp16_exponent(x->sB[tier_offset(x->d) + K * Nd + J]);
+    }
     for (int64_t p = 0; p < b; ++p) {
         int64_t row = I * b + p;
         if (row >= n)
@@ -225,7 +269,8 @@ static void leaf_product(mul_ctx *x, int64_t I, int64_t K, int64_t J, double *Ct
                 break;
             double acc = 0.0;
             for (int64_t l = 0; l < b; ++l)
-                acc += elem_p(x->A, n, row, K * b + l, low) * elem_p(x->B, n, K * b + l, col, low);
+                acc += elem_p(x->A, n, row, K * b + l, low, x->fmt, eA) *
+                       elem_p(x->B, n, K * b + l, col, low, x->fmt, eB);
             Ct[(row - r0) * ldc + (col - c0)] += acc;
         }
     }
@@ -282,26 +327,36 @@ static int check_inputs(int64_t n, int32_t b, double tau)
  * (linear_index(I,J) << 32) | K; *nkeys gets the total (keys beyond cap are
  * counted, not stored; OR_ERANGE then).  Kt[t] = kept triples at tier t.
  */
-int oracle_spamm_split(const float *A, const float *B, int64_t n, int32_t b, double tau,
-                       double low_tol, double *C, uint64_t *keys, int64_t cap, int64_t *nkeys,
-                       int64_t *Kt, int64_t *Klow);
+int oracle_spamm_split_fmt(const float *A, const float *B, int64_t n, int32_t b, double tau,
+                           double low_tol, int fmt, double *C, uint64_t *keys, int64_t cap,
+                           int64_t *nkeys, int64_t *Kt, int64_t *Klow);
 
 int oracle_spamm(const float *A, const float *B, int64_t n, int32_t b, double tau,
                  double *C, uint64_t *keys, int64_t cap, int64_t *nkeys, int64_t *Kt)
 {
     int64_t Klow;
-    return oracle_spamm_split(A, B, n, b, tau, 0.0, C, keys, cap, nkeys, Kt, &Klow);
+    return oracle_spamm_split_fmt(A, B, n, b, tau, 0.0, 0, C, keys, cap, nkeys, Kt, &Klow);
 }
 
-/* As oracle_spamm with split precision: LOW iff s_A s_B < low_tol^2. */
+/* As oracle_spamm with split precision: LOW iff s_A s_B < low_tol^2, LOW
+ * operands in bfloat16. */
 int oracle_spamm_split(const float *A, const float *B, int64_t n, int32_t b, double tau,
                        double low_tol, double *C, uint64_t *keys, int64_t cap, int64_t *nkeys,
                        int64_t *Kt, int64_t *Klow)
 {
+    return oracle_spamm_split_fmt(A, B, n, b, tau, low_tol, 0, C, keys, cap, nkeys, Kt, Klow);
+}
+
+/* Split precision with the LOW operand format fmt: 0 bfloat16, 1 binary16
+ * with a per-leaf power-of-two scale. */
+int oracle_spamm_split_fmt(const float *A, const float *B, int64_t n, int32_t b, double tau,
+                           double low_tol, int fmt, double *C, uint64_t *keys, int64_t cap,
+                           int64_t *nkeys, int64_t *Kt, int64_t *Klow)
+{
     int rc = check_inputs(n, b, tau);
     if (rc)
         return rc;
-    if (!(low_tol >= 0.0) || isinf(low_tol))
+    if (!(low_tol >= 0.0) || isinf(low_tol) || (fmt != 0 && fmt != 1))
         return OR_EINVAL;
     mul_ctx x;
     memset(&x, 0, sizeof x);
@@ -323,6 +378,7 @@ int oracle_spamm_split(const float *A, const float *B, int64_t n, int32_t b, dou
     x.b = b;
     x.T2 = tau * tau;
     x.L2 = low_tol * low_tol;
+    x.fmt = fmt;
     x.sA = sA;
     x.sB = sB;
     x.C = C;
@@ -377,27 +433,37 @@ static void spamm_tile(tile_ctx *y, int t, int64_t K)
         spamm_tile(y, t + 1, 2 * K + c);
 }
 
-int oracle_spamm_tiles_split(const float *A, const float *B, int64_t n, int32_t b, double tau,
-                             double low_tol, const int64_t *tiles, int64_t ntiles, double *Ctiles,
-                             int64_t *counts, int32_t *klists, int nthreads);
+int oracle_spamm_tiles_split_fmt(const float *A, const float *B, int64_t n, int32_t b,
+                                 double tau, double low_tol, int fmt, const int64_t *tiles,
+                                 int64_t ntiles, double *Ctiles, int64_t *counts,
+                                 int32_t *klists, int nthreads);
 
 int oracle_spamm_tiles(const float *A, const float *B, int64_t n, int32_t b, double tau,
                        const int64_t *tiles, int64_t ntiles, double *Ctiles,
                        int64_t *counts, int32_t *klists, int nthreads)
 {
-    return oracle_spamm_tiles_split(A, B, n, b, tau, 0.0, tiles, ntiles, Ctiles, counts, klists,
-                                    nthreads);
+    return oracle_spamm_tiles_split_fmt(A, B, n, b, tau, 0.0, 0, tiles, ntiles, Ctiles, counts,
+                                        klists, nthreads);
 }
 
-/* klists entries: K | (1 << 30) for a LOW product. */
 int oracle_spamm_tiles_split(const float *A, const float *B, int64_t n, int32_t b, double tau,
                              double low_tol, const int64_t *tiles, int64_t ntiles, double *Ctiles,
                              int64_t *counts, int32_t *klists, int nthreads)
 {
+    return oracle_spamm_tiles_split_fmt(A, B, n, b, tau, low_tol, 0, tiles, ntiles, Ctiles,
+                                        counts, klists, nthreads);
+}
+
+/* klists entries: K | (1 << 30) for a LOW product. */
+int oracle_spamm_tiles_split_fmt(const float *A, const float *B, int64_t n, int32_t b,
+                                 double tau, double low_tol, int fmt, const int64_t *tiles,
+                                 int64_t ntiles, double *Ctiles, int64_t *counts,
+                                 int32_t *klists, int nthreads)
+{
     int rc = check_inputs(n, b, tau);
     if (rc)
         return rc;
-    if (!(low_tol >= 0.0) || isinf(low_tol))
+    if (!(low_tol >= 0.0) || isinf(low_tol) || (fmt != 0 && fmt != 1))
         return OR_EINVAL;
     mul_ctx x;
     memset(&x, 0, sizeof x);
@@ -423,6 +489,7 @@ int oracle_spamm_tiles_split(const float *A, const float *B, int64_t n, int32_t 
     x.b = b;
     x.T2 = tau * tau;
     x.L2 = low_tol * low_tol;
+    x.fmt = fmt;
     x.sA = sA;
     x.sB = sB;
     int64_t bb = (int64_t)b * b;

@@ -9,6 +9,17 @@
   among the kept products;
 * a mixed product equals the per-leaf sum of numpy products, each with the
   operands its class prescribes.
+
+binary16 LOW operands (per-leaf power-of-two scale):
+
+* the scale exponent e of a leaf with squared norm S is the one integer with
+  4^(13-e) <= S < 4^(14-e), so every entry is below 2^14 once scaled;
+* the rounding equals numpy's float64 -> float16 conversion of x 2^e, on
+  ties, subnormals and scales from 2^-100 to 2^160;
+* a mixed product equals the per-leaf sum of numpy products with each LOW
+  leaf rounded through numpy's float16 at its own scale;
+* its error against the unrounded product stays within the per-element
+  rounding bound and is well below the bfloat16 one.
 """
 import numpy as np
 import pytest
@@ -133,3 +144,104 @@ def test_tile_recursion_matches_full_split():
     Cp[:256, :256] = full.C
     for s_, (I, J) in enumerate(tiles):
         assert np.array_equal(Ct[s_], Cp[I * b:(I + 1) * b, J * b:(J + 1) * b])
+
+
+# ---- binary16 LOW operands ---------------------------------------------------
+
+@pytest.mark.parametrize("S", [1.0, 2.0, 4.0, 0.25, 3.999999, 4.000001, 1e-90, 7.3e-60,
+                               1.5e30, 2.0 ** -298, 123456.0, 0.0])
+def test_fp16_exponent_closed_form(S):
+    import math
+    e = oracle.fp16_exponent(S)
+    if S == 0.0:
+        assert e == 0
+        return
+    # the unique e with 4^(13-e) <= S < 4^(14-e), i.e. sqrt(S) 2^e in [2^13, 2^14)
+    assert math.ldexp(1.0, 2 * (13 - e)) <= S < math.ldexp(1.0, 2 * (14 - e))
+
+
+def test_fp16_rounding_matches_numpy():
+    rng = np.random.default_rng(11)
+    cases = []
+    for e in (-100, -7, 0, 3, 13, 40, 100, 160):
+        # magnitudes spanning binary16's normal and subnormal ranges after scaling
+        mags = 2.0 ** rng.uniform(-30, 14, 400) * 2.0 ** -e
+        xs = (rng.choice([-1.0, 1.0], 400) * mags).astype(np.float32)
+        cases += [(float(x), e) for x in xs if x != 0 and abs(float(x) * 2.0 ** e) < 2.0 ** 14]
+    # exact ties at several binades, normal and subnormal, even and odd kept part
+    for base in (1.0, 1.0 + 2.0 ** -10, 2.0 ** -14, 2.0 ** -20, 2.0 ** -24, 3 * 2.0 ** -24):
+        q = 2.0 ** (max(int(np.floor(np.log2(base))), -14) - 10)    # binary16 spacing at base
+        cases += [(float(np.float32(base + q / 2)), 0), (float(np.float32(-(base + q / 2))), 0)]
+    cases += [(0.0, 5), (float(np.float32(1e-45)), 149), (float(np.float32(1e-45)), 120)]
+    for x, e in cases:
+        want = float(np.float16(np.float64(np.float32(x)) * 2.0 ** e)) * 2.0 ** -e
+        got = oracle.fp16_scaled(np.float32(x), e)
+        assert got == want, (x, e, got, want)
+
+
+def fp16_leaves(P, b, S):
+    """P (padded FP32) with every leaf rounded through numpy float16 at the
+    scale exponent of its squared norm."""
+    N = P.shape[0] // b
+    R = np.zeros(P.shape)
+    for I in range(N):
+        for J in range(N):
+            e = oracle.fp16_exponent(S[I, J])
+            blk = P[I * b:(I + 1) * b, J * b:(J + 1) * b].astype(np.float64) * 2.0 ** e
+            R[I * b:(I + 1) * b, J * b:(J + 1) * b] = blk.astype(np.float16).astype(np.float64) * \
+                2.0 ** -e
+    return R
+
+
+@pytest.mark.parametrize("n,b,tau,low", [(192, 32, 1e-6, 3e-2), (150, 16, 1e-7, 1e-1),
+                                         (130, 64, 0.0, 1e30)])
+def test_fp16_mixed_product_per_leaf(n, b, tau, low):
+    A, B = decay(n, 0.04, 21), 1e-3 * decay(n, 0.3, 22, sym=False)
+    r = oracle.spamm(A, B, b, tau, low_tol=low, low_fmt="fp16")
+    assert r.Klow > 0
+    rb = oracle.spamm(A, B, b, tau, low_tol=low)
+    assert np.array_equal(r.keys, rb.keys) and r.Klow == rb.Klow     # same classes as bf16
+    d, np_ = oracle.depth(n, b)
+    N = 1 << d
+    PA = np.zeros((np_, np_), dtype=np.float32)
+    PB = np.zeros((np_, np_), dtype=np.float32)
+    PA[:n, :n] = A
+    PB[:n, :n] = B
+    RA = fp16_leaves(PA, b, oracle.norms(A, b)[-1])
+    RB = fp16_leaves(PB, b, oracle.norms(B, b)[-1])
+    inv = {oracle.linear_index(i, j): (i, j) for i in range(N) for j in range(N)}
+    C = np.zeros((np_, np_))
+    for key in r.keys:
+        key = int(key)
+        I, J = inv[(key >> 32) & 0x7FFFFFFF]
+        k = key & 0xFFFFFFFF
+        X, Y = (RA, RB) if key >> 63 else (PA.astype(np.float64), PB.astype(np.float64))
+        C[I * b:(I + 1) * b, J * b:(J + 1) * b] += X[I * b:(I + 1) * b, k * b:(k + 1) * b] @ \
+            Y[k * b:(k + 1) * b, J * b:(J + 1) * b]
+    assert np.abs(C[:n, :n] - r.C).max() <= 1e-12 * (1 + np.abs(C).max())
+
+
+def test_fp16_error_within_rounding_bound_and_below_bf16():
+    n, b = 256, 32
+    A = decay(n, 0.08, 23)
+    low = 1e30                                   # every kept product LOW
+    exact = oracle.spamm(A, A, b, 0.0)
+    f16 = oracle.spamm(A, A, b, 0.0, low_tol=low, low_fmt="fp16")
+    b16 = oracle.spamm(A, A, b, 0.0, low_tol=low)
+    assert f16.Klow == f16.K
+    # per element |fl16(x) - x| <= 2^-11 |x| + 2^-25 2^-e (half the subnormal
+    # spacing, scaled back); propagate through |dA||A| + |A||dA| + |dA||dA|
+    S = oracle.norms(A, b)[-1]
+    N = n // b
+    D = np.zeros((n, n))
+    for I in range(N):
+        for J in range(N):
+            e = oracle.fp16_exponent(S[I, J])
+            blk = np.abs(A[I * b:(I + 1) * b, J * b:(J + 1) * b].astype(np.float64))
+            D[I * b:(I + 1) * b, J * b:(J + 1) * b] = 2.0 ** -11 * blk + 2.0 ** (-25 - e)
+    Aa = np.abs(A.astype(np.float64))
+    bound = D @ Aa + Aa @ D + D @ D
+    err16 = np.abs(f16.C - exact.C)
+    assert np.all(err16 <= bound * (1 + 1e-9) + 1e-300)
+    errb = np.abs(b16.C - exact.C).max()
+    assert 0 < err16.max() < errb / 4
