@@ -117,6 +117,22 @@ def matched_error(sp, wl, A, dA, C, tau, leaf, n, N, reps=2):
                            "ms_leaf_gemm": round(st["numeric_ms"], 3),
                            "tasks": st["tasks"], "low_frac": round(st["tasks_low"] / max(1, st["tasks"]), 4)})
     tree.free()
+    # FP16 LOW operands (8 times finer than BF16): the same tau grid, low_tol up to 64x higher
+    tree = sp.build_tree(dA, leaf, fp16=True)
+    for tmul in (1.0, 10.0, 100.0, 1e3, 1e4, 1e5):
+        t_ = tau * tmul
+        for lmul in (1024, 4096, 16384, 65536, 262144, 1048576):
+            best = None
+            for _ in range(reps):
+                st = sp.multiply_ex(tree, tree, t_, C, precision=sp.PREC_SPLIT_FP16,
+                                    low_tol=lmul * t_)
+                ms = st["symbolic_ms"] + st["numeric_ms"]
+                best = ms if best is None else min(best, ms)
+            points.append({"precision": "split-fp16", "tau": t_, "low_tol": lmul * t_,
+                           "ms": round(best, 3), "err": max_err(),
+                           "ms_leaf_gemm": round(st["numeric_ms"], 3), "tasks": st["tasks"],
+                           "low_frac": round(st["tasks_low"] / max(1, st["tasks"]), 4)})
+    tree.free()
     target = next(p["err"] for p in points if p["precision"] == "fp32" and p["tau"] == tau)
     subleaf = None
     if leaf == 64:
@@ -148,6 +164,7 @@ def matched_error(sp, wl, A, dA, C, tau, leaf, n, N, reps=2):
         return min(ok, key=lambda p: p["ms"]) if ok else None
 
     f32, spl, sub = fastest("fp32"), fastest("split-bf16"), fastest("fp32-subleaf")
+    s16 = fastest("split-fp16")
     split_roofline = None
     if spl is not None:
         tb = measured_split_traffic(wl.name, spl["tau"], spl["low_tol"])
@@ -161,12 +178,15 @@ def matched_error(sp, wl, A, dA, C, tau, leaf, n, N, reps=2):
     return {
         "target_err": target,
         "err_sample": f"{len(tiles)} seeded output leaves (incl. diagonal), dense FP64 reference",
-        "fp32_at_target": f32, "split_at_target": spl, "subleaf_at_target": sub,
+        "fp32_at_target": f32, "split_at_target": spl, "split_fp16_at_target": s16,
+        "subleaf_at_target": sub,
         "speedup_split_vs_fp32": round(f32["ms"] / spl["ms"], 3) if f32 and spl else None,
+        "speedup_split_fp16_vs_fp32": round(f32["ms"] / s16["ms"], 3) if f32 and s16 else None,
         "speedup_subleaf_vs_fp32": round(f32["ms"] / sub["ms"], 3) if f32 and sub else None,
         "split_roofline": split_roofline,
         "subleaf_same_tau": subleaf,
-        "grid": "tau x {1,10,...,1e5}, low_tol = tau x {0 (fp32), 256, 1024, 4096, 16384}; "
+        "grid": "tau x {1,10,...,1e5}, low_tol = tau x {0 (fp32), 256, 1024, 4096, 16384} "
+                "(bf16), tau x {1024, 4096, ..., 1048576} (fp16); "
                 "sub-leaf culling: tau x {0.1, 0.3, ..., 1e4}",
     }
 
@@ -430,8 +450,9 @@ def main() -> int:
                     help="skip the FP32-vs-split comparison at a fixed max-norm error")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark instead: saturation, then Poisson arrivals")
-    ap.add_argument("--precision", choices=("fp32", "split"), default="fp32",
-                    help="product of the timed steps (split: BF16 for LOW products)")
+    ap.add_argument("--precision", choices=("fp32", "split", "split-fp16"), default="fp32",
+                    help="product of the timed steps (split: BF16 for LOW products, "
+                         "split-fp16: FP16 at a per-leaf scale)")
     ap.add_argument("--low-tol", type=float, default=0.4096,
                     help="split precision: absolute LOW threshold on the norm product")
     ap.add_argument("--no-sparse", action="store_true",
@@ -479,11 +500,12 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
-    split = args.precision == "split"
-    prec = sp.PREC_SPLIT_BF16 if split else sp.PREC_FP32
+    split = args.precision != "fp32"
+    f16 = args.precision == "split-fp16"
+    prec = sp.PREC_SPLIT_FP16 if f16 else sp.PREC_SPLIT_BF16 if split else sp.PREC_FP32
 
     def step():
-        tree = sp.build_tree(dA, leaf, bf16=split)   # synchronizes once (root norm)
+        tree = sp.build_tree(dA, leaf, bf16=split and not f16, fp16=f16)   # syncs once (root norm)
         st = sp.multiply_ex(tree, tree, tau, C, precision=prec,
                             low_tol=args.low_tol if split else 0.0)   # events around cull and GEMM
         tree.free()
@@ -556,11 +578,11 @@ def main() -> int:
         },
     }
     if split:
-        # the split kernel moves whole BF16 leaves: rate it against HBM
-        tb = measured_split_traffic(wl.name, tau, args.low_tol)
+        # the split kernel moves whole 16-bit leaves: rate it against HBM
+        tb = None if f16 else measured_split_traffic(wl.name, tau, args.low_tol)
         gbs = tb / (gemm_ms * 1e-3) / 1e9 if tb is not None else None
-        out["dtype"] = "f32+bf16"
-        out["config"]["precision"] = "split-bf16"
+        out["dtype"] = "f32+f16" if f16 else "f32+bf16"
+        out["config"]["precision"] = "split-fp16" if f16 else "split-bf16"
         out["config"]["low_tol"] = args.low_tol
         out["config"]["tasks_low"] = st["tasks_low"]
         out["roofline"] = {

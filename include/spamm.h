@@ -45,12 +45,16 @@ extern "C" {
 /* ---- precision of the leaf products (split precision) -------------------- */
 #define SPAMM_PREC_FP32        0   /* every kept product in FP32 (MFMA, FP32 accumulation) */
 #define SPAMM_PREC_SPLIT_BF16  1   /* LOW products on BF16 operands, HIGH ones in FP32      */
+#define SPAMM_PREC_SPLIT_FP16  2   /* LOW products on scaled FP16 operands, HIGH ones FP32  */
 
 /* Tree build flags. */
 #define SPAMM_TREE_BF16        1u  /* also keep BF16 copies of the leaves (split precision) */
 #define SPAMM_TREE_SUBNORMS    2u  /* n_b = 64: also keep the norms of the 32 x 32 sub-blocks */
                                    /* (sub-leaf culling); the whole pyramid is then that of  */
                                    /* a tree with 32 x 32 leaves                            */
+#define SPAMM_TREE_FP16        4u  /* also keep FP16 copies of the leaves, each leaf scaled  */
+                                   /* by a power of two fixed by its squared norm (split    */
+                                   /* precision SPAMM_PREC_SPLIT_FP16); not with BF16       */
 
 typedef struct spamm_tree spamm_tree;   /* one operand: packed leaves + norms  */
 typedef struct spamm_plan spamm_plan;   /* one product's kept task list        */
@@ -97,11 +101,15 @@ int spamm_build_tree(const float *A, int64_t n, int32_t leaf, void *stream,
 /*
  * Options of a product.
  *   tau        SpAMM tolerance (absolute), as for spamm_symbolic.
- *   precision  SPAMM_PREC_FP32 or SPAMM_PREC_SPLIT_BF16.
+ *   precision  SPAMM_PREC_FP32, SPAMM_PREC_SPLIT_BF16 or SPAMM_PREC_SPLIT_FP16.
  *   low_tol    split only: a kept product A_ik B_kj is LOW iff
  *              fl64(s_A s_B) < fl64(low_tol^2) on the stored squared norms,
  *              i.e. ||A_ik||_F ||B_kj||_F < low_tol; LOW products use BF16
- *              operands (each FP32 entry rounded to nearest even) with FP32
+ *              operands (each FP32 entry rounded to nearest even) or FP16
+ *              ones (each leaf times 2^e, e = 14 - ceil(p / 2) where its
+ *              squared norm is S = m 2^p with 0.5 <= m < 1, so every scaled
+ *              entry is below 2^14; rounded to nearest even, subnormals kept;
+ *              the product is scaled back by 2^-(eA + eB)) with FP32
  *              accumulation, HIGH products stay FP32.  0 = nothing is LOW.
  *              A relative threshold theta ||A||_F ||B||_F is low_tol =
  *              theta * sqrt(norm2_A) * sqrt(norm2_B) (spamm_tree_info).
@@ -120,7 +128,9 @@ typedef struct spamm_opts {
 } spamm_opts;
 
 /* As spamm_build_tree, with flags (SPAMM_TREE_BF16: also store BF16 copies of
- * every leaf, needed by split-precision products; leaf must be 32 or 64.
+ * every leaf, needed by SPAMM_PREC_SPLIT_BF16 products; leaf must be 32 or 64.
+ * SPAMM_TREE_FP16: FP16 copies at the per-leaf scale of spamm_opts, for
+ * SPAMM_PREC_SPLIT_FP16; leaf 32 or 64, not together with SPAMM_TREE_BF16.
  * SPAMM_TREE_SUBNORMS: leaf must be 64; tiers 0..d+1 of norms, tier d+1 being
  * the 32 x 32 sub-blocks, each a pairwise sum over its own row-major index,
  * and every coarser tier the (s11 + s12) + (s21 + s22) of its children). */
@@ -145,13 +155,14 @@ int spamm_build_tree_ex(const float *A, int64_t n, int32_t leaf, uint32_t flags,
  * Synchronizes `stream` once (kept-leaf count and roots).  spamm_tree_info's
  * norm2 is ||A_sparsified||_F^2.  NaN/Inf anywhere in A -> SPAMM_E_NONFINITE.
  * Errors as spamm_build_tree_ex, plus SPAMM_E_INVAL for a bad tau or
- * norm2_other (negative, NaN/Inf) or SPAMM_TREE_SUBNORMS.
+ * norm2_other (negative, NaN/Inf), SPAMM_TREE_SUBNORMS or SPAMM_TREE_FP16.
  */
 int spamm_build_tree_sparse(const float *A, int64_t n, int32_t leaf, uint32_t flags, double tau,
                             double norm2_other, void *stream, spamm_tree **out);
 
 /* Storage of a tree: leaves stored (N^2 for a dense tree), N^2, and the device
- * bytes it holds (leaf copies, norm pyramid, slot map).  Outputs may be NULL. */
+ * bytes it holds (leaf copies, norm pyramid, slot map, FP16 scale exponents).
+ * Outputs may be NULL. */
 int spamm_tree_storage(const spamm_tree *tree, int64_t *leaves_stored, int64_t *leaves_total,
                        size_t *device_bytes);
 
@@ -193,10 +204,11 @@ int spamm_symbolic(const spamm_tree *A, const spamm_tree *B, double tau,
 
 /*
  * Symbolic multiply with options (split precision).  With
- * SPAMM_PREC_SPLIT_BF16 each kept leaf product is also classed LOW or HIGH
- * (see spamm_opts); both trees must have been built with SPAMM_TREE_BF16.
+ * SPAMM_PREC_SPLIT_BF16 (SPAMM_PREC_SPLIT_FP16) each kept leaf product is
+ * also classed LOW or HIGH (see spamm_opts); both trees must have been built
+ * with SPAMM_TREE_BF16 (SPAMM_TREE_FP16).
  * Errors as spamm_symbolic, plus SPAMM_E_INVAL for an unknown precision, a
- * bad low_tol (negative, NaN/Inf, 0 < low_tol < 1e-150), missing BF16 copies,
+ * bad low_tol (negative, NaN/Inf, 0 < low_tol < 1e-150), missing 16-bit copies,
  * or sub_cull with split precision, n_b != 64 or trees without sub-norms.
  */
 int spamm_symbolic_ex(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
@@ -205,9 +217,10 @@ int spamm_symbolic_ex(const spamm_tree *A, const spamm_tree *B, const spamm_opts
 /*
  * Numeric multiply: C = sum over kept k (ascending) of A_ik B_kj for every
  * output leaf, FP32 MFMA with FP32 accumulation (Eq. product, Alg. 1 steps
- * 7-9).  Split precision: the LOW products (BF16 operands) and the HIGH ones
- * (FP32) are summed separately, each over k ascending, and a leaf is their
- * sum.  C: device pointer, n x n FP32 row-major, fully overwritten (zeros
+ * 7-9).  Split precision: the LOW products (BF16 or scaled FP16 operands;
+ * with FP16 each product is accumulated on its own, scaled back and added)
+ * and the HIGH ones (FP32) are summed separately, each over k ascending, and
+ * a leaf is their sum.  C: device pointer, n x n FP32 row-major, fully overwritten (zeros
  * where no product lands; alpha = 1, beta = 0).  C must not overlap the
  * trees' storage; it may alias the matrix a tree was built from.  Enqueue on
  * the plan's stream or order streams yourself.
@@ -270,8 +283,8 @@ int spamm_multiply_opts(const spamm_tree *A, const spamm_tree *B, const spamm_op
  * other requests' work;
  * the leaf products of every request whose cull has been enqueued are
  * gathered into one batched leaf-GEMM launch group (up to 16 requests of one
- * leaf size, uneven n and tau; split and FP32 requests of a group share one
- * launch per kind) on the server's
+ * leaf size, uneven n and tau; the FP32, BF16-split and FP16-split requests
+ * of a group get one launch per kind) on the server's
  * GEMM stream, so small products share the chip.  A squaring chain (the
  * matrix square is the central step of density-matrix purification,
  * Sec. IV.B) stays on the device: each step's product is rebuilt into a tree
@@ -289,7 +302,7 @@ typedef struct spamm_request {
     float *C;            /* device, n x n FP32 row-major output; may alias A          */
     int64_t n;           /* order, >= 1                                                */
     int32_t leaf;        /* n_b in {16, 32, 64} (32 or 64 for split precision)         */
-    int32_t precision;   /* SPAMM_PREC_FP32 or SPAMM_PREC_SPLIT_BF16                   */
+    int32_t precision;   /* SPAMM_PREC_FP32, SPAMM_PREC_SPLIT_BF16 or _SPLIT_FP16      */
     double tau;          /* SpAMM tolerance of every product (as spamm_symbolic)      */
     double low_tol;      /* split precision: LOW threshold (as spamm_opts)            */
     int32_t chain_len;   /* 0: C = A B.  L in 1..64: X_0 = A, X_{s+1} = X_s X_s under  */
@@ -312,8 +325,8 @@ typedef struct spamm_server_stats {
     int64_t  admitted;           /* requests admitted                                */
     int64_t  completed;          /* requests finished (any status)                   */
     int64_t  queued;             /* requests waiting for admission now               */
-    int64_t  launches;           /* batched leaf-GEMM launch groups (a split and an  */
-                                 /* FP32 launch when a batch mixes precisions)        */
+    int64_t  launches;           /* batched leaf-GEMM launch groups (one launch per  */
+                                 /* precision present in the group)                   */
     int64_t  launched_products;  /* products over all launch groups                  */
     int64_t  max_batch;          /* most products in one launch group                */
     int64_t  peak_active;        /* most requests admitted at once                   */

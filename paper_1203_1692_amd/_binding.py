@@ -29,8 +29,10 @@ SPAMM_PENDING = 1
 
 PREC_FP32 = 0
 PREC_SPLIT_BF16 = 1
+PREC_SPLIT_FP16 = 2
 TREE_BF16 = 1
 TREE_SUBNORMS = 2
+TREE_FP16 = 4
 
 _lib = None
 
@@ -298,18 +300,22 @@ class Plan:
             pass
 
 
-def build_tree(A, leaf: int, stream=None, bf16: bool = False, subnorms: bool = False) -> Tree:
-    """Quadtree of A; bf16=True also keeps BF16 leaf copies (split precision);
+def build_tree(A, leaf: int, stream=None, bf16: bool = False, subnorms: bool = False,
+               fp16: bool = False) -> Tree:
+    """Quadtree of A; bf16=True also keeps BF16 leaf copies (PREC_SPLIT_BF16),
+    fp16=True FP16 copies at a per-leaf power-of-two scale (PREC_SPLIT_FP16);
     subnorms=True (leaf 64) also keeps 32 x 32 sub-block norms (sub-leaf
     culling)."""
     A = _device_matrix(A, "A")
     h = ctypes.c_void_p()
-    flags = (TREE_BF16 if bf16 else 0) | (TREE_SUBNORMS if subnorms else 0)
+    flags = ((TREE_BF16 if bf16 else 0) | (TREE_SUBNORMS if subnorms else 0) |
+             (TREE_FP16 if fp16 else 0))
     _check(load().spamm_build_tree_ex(ctypes.c_void_p(A.data_ptr()), A.shape[0], leaf, flags,
                                       _stream(stream), ctypes.byref(h)),
            "spamm_build_tree")
     t = Tree(h)
     t.bf16 = bool(bf16)
+    t.fp16 = bool(fp16)
     t.subnorms = bool(subnorms)
     return t
 

@@ -19,6 +19,9 @@ namespace spamm {
 hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *tiles,
                         float *tilesT, uint16_t *t16, uint16_t *tT16, double *norms, bool sub,
                         hipStream_t s);
+hipError_t launch_pack_fp16(const float *tiles, const float *tilesT, const double *leafn,
+                            uint16_t *t16, uint16_t *tT16, int32_t *scale, int leaf,
+                            uint32_t ntiles, hipStream_t s);
 hipError_t launch_cull(spamm_plan *p, hipStream_t s);
 hipError_t launch_gemm(const spamm_plan *p, float *C, hipStream_t s);
 }  // namespace spamm
@@ -165,14 +168,18 @@ size_t plan_device_bytes(int depth, bool split)
     return total;
 }
 
-// Tree buffers: left and right FP32 leaf copies, optional BF16 copies, the
-// norm pyramid; 256-byte aligned offsets of one block.
+// Tree buffers: left and right FP32 leaf copies, optional 16-bit copies
+// (BF16, or FP16 with a scale exponent per leaf), the norm pyramid; 256-byte
+// aligned offsets of one block.
 struct TreeLayout {
-    size_t tiles, tilesT, t16, tT16, norms, total;
+    size_t tiles, tilesT, t16, tT16, scale16, norms, total;
 };
 
-static TreeLayout tree_layout(int64_t np, int32_t d, bool bf16, bool sub)
+static TreeLayout tree_layout(int64_t np, int32_t d, uint32_t flags)
 {
+    const bool copies16 = (flags & (SPAMM_TREE_BF16 | SPAMM_TREE_FP16)) != 0;
+    const bool fp16 = (flags & SPAMM_TREE_FP16) != 0;
+    const bool sub = (flags & SPAMM_TREE_SUBNORMS) != 0;
     TreeLayout L{};
     const size_t tile = sizeof(float) * (size_t)np * (size_t)np;
     const size_t norm = sizeof(double) * (size_t)tier_offset(d + (sub ? 2 : 1));
@@ -182,16 +189,18 @@ static TreeLayout tree_layout(int64_t np, int32_t d, bool bf16, bool sub)
     L.tilesT = o;
     o += align256(tile);
     L.t16 = o;
-    o += bf16 ? align256(tile / 2) : 0;
+    o += copies16 ? align256(tile / 2) : 0;
     L.tT16 = o;
-    o += bf16 ? align256(tile / 2) : 0;
+    o += copies16 ? align256(tile / 2) : 0;
+    L.scale16 = o;
+    o += fp16 ? align256(sizeof(int32_t) * ((size_t)1 << (2 * d))) : 0;
     L.norms = o;
     o += align256(norm);
     L.total = o;
     return L;
 }
 
-size_t tree_device_bytes(int64_t n, int32_t leaf, bool bf16, bool sub)
+size_t tree_device_bytes(int64_t n, int32_t leaf, uint32_t flags)
 {
     int32_t d = 0;
     int64_t p = leaf;
@@ -199,7 +208,7 @@ size_t tree_device_bytes(int64_t n, int32_t leaf, bool bf16, bool sub)
         p *= 2;
         d += 1;
     }
-    return tree_layout(p, d, bf16, sub).total;
+    return tree_layout(p, d, flags).total;
 }
 
 int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hipStream_t s,
@@ -214,12 +223,15 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
         return fail(SPAMM_E_INVAL, "n = %lld < 1", (long long)n);
     if (leaf != 16 && leaf != 32 && leaf != 64)
         return fail(SPAMM_E_INVAL, "leaf = %d not in {16, 32, 64}", leaf);
-    if ((flags & ~(SPAMM_TREE_BF16 | SPAMM_TREE_SUBNORMS)) != 0)
+    if ((flags & ~(SPAMM_TREE_BF16 | SPAMM_TREE_SUBNORMS | SPAMM_TREE_FP16)) != 0)
         return fail(SPAMM_E_INVAL, "unknown tree flags 0x%x", flags);
     const bool bf16 = (flags & SPAMM_TREE_BF16) != 0;
+    const bool fp16 = (flags & SPAMM_TREE_FP16) != 0;
     const bool sub = (flags & SPAMM_TREE_SUBNORMS) != 0;
-    if (bf16 && leaf == 16)
-        return fail(SPAMM_E_INVAL, "BF16 leaf copies need leaf 32 or 64");
+    if (bf16 && fp16)
+        return fail(SPAMM_E_INVAL, "a tree keeps BF16 or FP16 leaf copies, not both");
+    if ((bf16 || fp16) && leaf == 16)
+        return fail(SPAMM_E_INVAL, "16-bit leaf copies need leaf 32 or 64");
     if (sub && leaf != 64)
         return fail(SPAMM_E_INVAL, "sub-block norms need leaf 64");
     int32_t d;
@@ -230,7 +242,7 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
     int dev;
     if ((rc = prepare_device(&dev)))
         return rc;
-    const TreeLayout L = tree_layout(np, d, bf16, sub);
+    const TreeLayout L = tree_layout(np, d, flags);
 
     spamm_tree *t = new (std::nothrow) spamm_tree();
     if (!t)
@@ -258,11 +270,17 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
     if (e == hipSuccess) {
         t->tiles = (float *)(base + L.tiles);
         t->tilesT = (float *)(base + L.tilesT);
-        t->tiles16 = bf16 ? (uint16_t *)(base + L.t16) : nullptr;
-        t->tilesT16 = bf16 ? (uint16_t *)(base + L.tT16) : nullptr;
+        t->tiles16 = bf16 || fp16 ? (uint16_t *)(base + L.t16) : nullptr;
+        t->tilesT16 = bf16 || fp16 ? (uint16_t *)(base + L.tT16) : nullptr;
+        t->fp16 = fp16;
+        t->scale16 = fp16 ? (int32_t *)(base + L.scale16) : nullptr;
         t->norms = (double *)(base + L.norms);
-        e = launch_build(A, n, leaf, d, t->tiles, t->tilesT, t->tiles16, t->tilesT16, t->norms, sub,
-                         s);
+        // BF16 copies come with the norm pass; FP16 ones need each leaf's norm first
+        e = launch_build(A, n, leaf, d, t->tiles, t->tilesT, bf16 ? t->tiles16 : nullptr,
+                         bf16 ? t->tilesT16 : nullptr, t->norms, sub, s);
+        if (e == hipSuccess && fp16)
+            e = launch_pack_fp16(t->tiles, t->tilesT, t->norms + tier_offset(d), t->tiles16,
+                                 t->tilesT16, t->scale16, leaf, 1u << (2 * d), s);
     }
     if (e == hipSuccess && root_dst != nullptr)
         e = hipMemcpyAsync(root_dst, t->norms, sizeof(double), hipMemcpyDeviceToHost, s);
@@ -295,16 +313,21 @@ int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *o
     int rc;
     if ((rc = check_tol(opts->tau, "tau")))
         return rc;
-    if (opts->precision != SPAMM_PREC_FP32 && opts->precision != SPAMM_PREC_SPLIT_BF16)
+    if (opts->precision != SPAMM_PREC_FP32 && opts->precision != SPAMM_PREC_SPLIT_BF16 &&
+        opts->precision != SPAMM_PREC_SPLIT_FP16)
         return fail(SPAMM_E_INVAL, "unknown precision %d", opts->precision);
-    const bool split = opts->precision == SPAMM_PREC_SPLIT_BF16;
+    const bool split = opts->precision != SPAMM_PREC_FP32;
+    const bool want16 = opts->precision == SPAMM_PREC_SPLIT_FP16;
     if (split && (rc = check_tol(opts->low_tol, "low_tol")))
         return rc;
     if (A->n != B->n || A->leaf != B->leaf)
         return fail(SPAMM_E_MISMATCH, "A is %lld/%d, B is %lld/%d (n/leaf)", (long long)A->n,
                     A->leaf, (long long)B->n, B->leaf);
-    if (split && (A->tiles16 == nullptr || B->tilesT16 == nullptr))
-        return fail(SPAMM_E_INVAL, "split precision needs trees built with SPAMM_TREE_BF16");
+    if (split && (A->tiles16 == nullptr || B->tilesT16 == nullptr || A->fp16 != want16 ||
+                  B->fp16 != want16))
+        return fail(SPAMM_E_INVAL, "split precision %s needs trees built with %s",
+                    want16 ? "SPLIT_FP16" : "SPLIT_BF16",
+                    want16 ? "SPAMM_TREE_FP16" : "SPAMM_TREE_BF16");
     if (opts->sub_cull != 0 && opts->sub_cull != 1)
         return fail(SPAMM_E_INVAL, "sub_cull = %d not in {0, 1}", opts->sub_cull);
     const bool sub = opts->sub_cull == 1;
@@ -533,11 +556,13 @@ int spamm_tree_storage(const spamm_tree *t, int64_t *stored, int64_t *total, siz
         return fail(SPAMM_E_INVAL, "tree is NULL");
     const int64_t N2 = int64_t(1) << (2 * t->depth);
     const size_t leaf_bytes = sizeof(float) * (size_t)t->leaf * (size_t)t->leaf;
-    const size_t copies = (t->tiles16 != nullptr) ? 3 : 2;   // two FP32 + two half-size BF16
+    const size_t copies = (t->tiles16 != nullptr) ? 3 : 2;   // two FP32 + two half-size 16-bit
     size_t b = copies * leaf_bytes * (size_t)std::max<int64_t>(t->stored, t->slot ? 1 : 0) +
                sizeof(double) * (size_t)tier_offset(t->depth + (t->sub ? 2 : 1));
     if (t->slot != nullptr)
         b += sizeof(uint32_t) * (2 * (size_t)N2 + 1);
+    if (t->scale16 != nullptr)
+        b += sizeof(int32_t) * (size_t)N2;
     if (stored) *stored = t->stored;
     if (total) *total = N2;
     if (device_bytes) *device_bytes = b;

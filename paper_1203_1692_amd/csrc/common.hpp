@@ -120,7 +120,8 @@ __device__ inline uint64_t lanes_below() { return (uint64_t(1) << lane_id()) - 1
 
 // One product in a (possibly batched) leaf-GEMM launch: grid blocks
 // [block0, block0 + nblocks) work on this job.  tA / tBT point to the FP32
-// leaves (LeafLayout), tA16 / tBT16 to the BF16 ones (Leaf16Layout).
+// leaves (LeafLayout), tA16 / tBT16 to the 16-bit ones (Leaf16Layout: BF16,
+// or FP16 at the per-leaf scale exponents escA / escB).
 struct GemmJob {
     const void *tA;
     const void *tBT;
@@ -145,6 +146,9 @@ struct GemmJob {
     // sparsified trees: storage slot of each leaf (linear index), else null
     const uint32_t *slotA;
     const uint32_t *slotB;
+    // FP16 split: scale exponent of every leaf (linear index), else null
+    const int32_t *escA;
+    const int32_t *escB;
 };
 
 // Storage position of leaf `l` of a tree: its slot when the tree is
@@ -157,8 +161,9 @@ __device__ inline int64_t leaf_slot(const uint32_t *slot, uint32_t l)
 constexpr int kMaxJobs = 16;
 
 // Leaf-GEMM kernels of a launch: whole FP32 leaf products, split precision
-// (LOW on BF16, HIGH on FP32, one kernel), FP32 with sub-leaf culling.
-enum class GemmKind { Fp32, Split, Sub };
+// (LOW on BF16 or scaled FP16, HIGH on FP32, one kernel), FP32 with sub-leaf
+// culling.
+enum class GemmKind { Fp32, Split, SplitF16, Sub };
 
 struct GemmJobs {          // passed by value as a kernel argument
     int32_t njobs;
@@ -176,8 +181,10 @@ struct spamm_tree {
     int32_t leaf, depth;
     float *tiles;           // N^2 leaves (left-operand copy), linear-index order, LeafLayout
     float *tilesT;          // the same leaves transposed (right-operand copy), LeafLayout
-    uint16_t *tiles16;      // BF16 left-operand copy (Leaf16Layout), or null
-    uint16_t *tilesT16;     // BF16 right-operand (transposed) copy, or null
+    uint16_t *tiles16;      // 16-bit left-operand copy (Leaf16Layout), or null
+    uint16_t *tilesT16;     // 16-bit right-operand (transposed) copy, or null
+    bool fp16;              // the 16-bit copies are FP16 at scale16, else BF16
+    int32_t *scale16;       // FP16 copies: scale exponent e of every leaf, else null
     double *norms;          // tiers 0..d (0..d+1 with sub-norms), tier_offset layout
     double root;            // ||A||_F^2
     bool borrowed;          // buffers carved from a caller's arena (not freed here)

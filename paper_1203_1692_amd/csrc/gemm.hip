@@ -35,6 +35,7 @@ namespace spamm {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void global_void_t;
 
@@ -385,21 +386,25 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
 }
 
 // ---------------------------------------------------------------------------
-// LOW products (split precision): BF16 operands, FP32 accumulation, on
-// v_mfma_f32_32x32x16_bf16 (A operand of lane l: A[l%32][k0 + 8(l/32) + i],
+// LOW products (split precision): 16-bit operands, FP32 accumulation, on
+// v_mfma_f32_32x32x16_bf16 / _f16 (A operand of lane l: A[l%32][k0 + 8(l/32) + i],
 // i < 8; B operand B[k0 + 8(l/32) + i][l%32]).  Same ownership and
 // double-buffered direct-to-LDS staging as the FP32 loop; a stage is the four
-// whole BF16 leaves of one entry (Leaf16Layout, 8 KB each at n_b = 64).
-template <int B>
+// whole 16-bit leaves of one entry (Leaf16Layout, 8 KB each at n_b = 64).
+// F16: the leaves hold x 2^e (e per leaf, escA / escB), so each product is
+// accumulated on its own from zero and added as tmp 2^-(eA + eB) (an exact
+// scaling unless it underflows).
+template <int B, bool F16>
 __device__ inline void bf16_products(const uint16_t *__restrict__ tA16,
                                      const uint16_t *__restrict__ tBT16, const uint32_t *slotA,
                                      const uint32_t *slotB, const uint32_t *__restrict__ bent,
                                      uint32_t e0, uint32_t e1, uint32_t I0, uint32_t J0,
                                      uint16_t *smem16, uint32_t *ents, int w, int lane,
+                                     const int32_t *escA, const int32_t *escB,
                                      floatx16 (&acc)[B / 32][B / 32])
 {
     using L = Leaf16Layout<B>;
-    constexpr int LEAF = B * B;            // bf16 per leaf
+    constexpr int LEAF = B * B;            // 16-bit values per leaf
     constexpr int MB = B / 32;
     const int qa = w >> 1, qb = w & 1;
     auto issue = [&](uint32_t ent, uint16_t *dst) {
@@ -442,27 +447,56 @@ __device__ inline void bf16_products(const uint16_t *__restrict__ tA16,
                 for (int j = 0; j < MB; ++j)
                     bv[st][j] = *reinterpret_cast<const bf16x8 *>(Bp + L::index(j * 32 + r, c));
             }
-#pragma unroll
-            for (int st = 0; st < B / 16; ++st)
+            if constexpr (F16) {
+                const uint32_t k = ent & 0xFFFFu;
+                const int esum =
+                    escA[__builtin_amdgcn_readfirstlane(lin_index(I0 + qa, k))] +
+                    escB[__builtin_amdgcn_readfirstlane(lin_index(k, J0 + qb))];
+                floatx16 tmp[MB][MB];
 #pragma unroll
                 for (int i = 0; i < MB; ++i)
 #pragma unroll
                     for (int j = 0; j < MB; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[st][i], bv[st][j],
-                                                                            acc[i][j], 0, 0, 0);
+                        tmp[i][j] = floatx16{0};
+#pragma unroll
+                for (int st = 0; st < B / 16; ++st)
+#pragma unroll
+                    for (int i = 0; i < MB; ++i)
+#pragma unroll
+                        for (int j = 0; j < MB; ++j)
+                            tmp[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                                __builtin_bit_cast(f16x8, av[st][i]),
+                                __builtin_bit_cast(f16x8, bv[st][j]), tmp[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < MB; ++j)
+#pragma unroll
+                        for (int v = 0; v < 16; ++v)
+                            acc[i][j][v] += ldexpf(tmp[i][j][v], -esum);
+            } else {
+#pragma unroll
+                for (int st = 0; st < B / 16; ++st)
+#pragma unroll
+                    for (int i = 0; i < MB; ++i)
+#pragma unroll
+                        for (int j = 0; j < MB; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                av[st][i], bv[st][j], acc[i][j], 0, 0, 0);
+            }
         }
     }
 }
 
-// Split precision in one launch: every block runs its LOW list (BF16) and
-// then its HIGH list (FP32), so the few blocks with many HIGH products (the
+// Split precision in one launch: every block runs its LOW list (BF16 or
+// scaled FP16) and then its HIGH list (FP32), so the few blocks with many HIGH products (the
 // large leaves near the diagonal) overlap the LOW work of the others instead
 // of forming a second launch of their own.  The classes keep separate
 // accumulators (the MFMA result layouts are the same): a leaf is written as
 // its LOW sum, plus its HIGH sum in one FP32 addition when the block has HIGH
 // entries -- the sums of the paper's product split by class, each over k
 // ascending.
-template <int B>
+template <int B, bool F16>
 __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
 {
     constexpr int MB = B / 32;
@@ -487,9 +521,10 @@ __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
             lo[i][j] = floatx16{0};
             hi[i][j] = floatx16{0};
         }
-    bf16_products<B>((const uint16_t *)job.tA16, (const uint16_t *)job.tBT16, job.slotA, job.slotB,
+    bf16_products<B, F16>((const uint16_t *)job.tA16, (const uint16_t *)job.tBT16, job.slotA,
+                          job.slotB,
                      job.bent_lo, job.browptr_lo[blk], job.browptr_lo[blk + 1], I0, J0,
-                     (uint16_t *)smem, ents, w, lane, lo);
+                     (uint16_t *)smem, ents, w, lane, job.escA, job.escB, lo);
     __syncthreads();                       // every wave is done with the BF16 stages
     const uint32_t h0 = job.browptr[blk], h1 = job.browptr[blk + 1];
     fp32_products<B>((const float *)job.tA, (const float *)job.tBT, job.slotA, job.slotB, job.bent,
@@ -520,15 +555,16 @@ static hipError_t launch_fp32(const GemmJobs &jobs, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int B>
+template <int B, bool F16>
 static hipError_t launch_split(const GemmJobs &jobs, hipStream_t s)
 {
     constexpr size_t lds = SplitShape<B>::kLds;
-    static const hipError_t attr = hipFuncSetAttribute(
-        (const void *)leaf_gemm_split<B>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void *)leaf_gemm_split<B, F16>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (attr != hipSuccess)
         return attr;
-    hipLaunchKernelGGL(leaf_gemm_split<B>, dim3(jobs.nblocks), dim3(256), lds, s, jobs);
+    hipLaunchKernelGGL((leaf_gemm_split<B, F16>), dim3(jobs.nblocks), dim3(256), lds, s, jobs);
     return hipGetLastError();
 }
 
@@ -543,8 +579,14 @@ hipError_t launch_gemm_jobs(int leaf, GemmKind kind, const GemmJobs &jobs, hipSt
         return leaf == 64 ? launch_fp32<64, true>(jobs, s) : hipErrorInvalidValue;
     case GemmKind::Split:
         switch (leaf) {
-        case 32: return launch_split<32>(jobs, s);
-        case 64: return launch_split<64>(jobs, s);
+        case 32: return launch_split<32, false>(jobs, s);
+        case 64: return launch_split<64, false>(jobs, s);
+        default: return hipErrorInvalidValue;
+        }
+    case GemmKind::SplitF16:
+        switch (leaf) {
+        case 32: return launch_split<32, true>(jobs, s);
+        case 64: return launch_split<64, true>(jobs, s);
         default: return hipErrorInvalidValue;
         }
     case GemmKind::Fp32:
@@ -560,8 +602,11 @@ hipError_t launch_gemm_jobs(int leaf, GemmKind kind, const GemmJobs &jobs, hipSt
 
 GemmKind plan_kind(const spamm_plan *p)
 {
-    return p->sub ? GemmKind::Sub : p->precision != SPAMM_PREC_FP32 ? GemmKind::Split
-                                                                    : GemmKind::Fp32;
+    if (p->sub)
+        return GemmKind::Sub;
+    return p->precision == SPAMM_PREC_SPLIT_FP16   ? GemmKind::SplitF16
+           : p->precision == SPAMM_PREC_SPLIT_BF16 ? GemmKind::Split
+                                                   : GemmKind::Fp32;
 }
 
 // The plan's job: FP32 copies and HIGH (or only) schedule; with split
@@ -588,6 +633,8 @@ void plan_jobs(const spamm_plan *p, float *C, GemmJob &j)
     j.T2 = p->T2;
     j.slotA = p->A->slot;
     j.slotB = p->B->slot;
+    j.escA = p->precision == SPAMM_PREC_SPLIT_FP16 ? p->A->scale16 : nullptr;
+    j.escB = p->precision == SPAMM_PREC_SPLIT_FP16 ? p->B->scale16 : nullptr;
     if (p->sub) {
         j.subA = p->A->norms + tier_offset(p->depth + 1);
         j.subB = p->B->norms + tier_offset(p->depth + 1);

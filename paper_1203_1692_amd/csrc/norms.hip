@@ -272,6 +272,98 @@ hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *t
     return hipGetLastError();
 }
 
+// ---- FP16 leaf copies (split precision with FP16 LOW operands) ---------------
+// Leaf l is multiplied by 2^e before rounding, e fixed by its squared norm S
+// alone: with S = f 2^E (1 <= f < 2), 4^(13-e) <= S < 4^(14-e) for
+// e = 14 - floor((E + 2) / 2), so every entry (|x| <= sqrt(S)) is below 2^14
+// once scaled.  A zero leaf (never multiplied) gets e = 0.
+__device__ inline int fp16_scale_exponent(double S)
+{
+    if (!(S > 0.0))
+        return 0;
+    const int E = (int)((__double_as_longlong(S) >> 52) & 0x7FF) - 1023;   // S >= 2^-298: normal
+    return 14 - ((E + 2) >> 1);
+}
+
+// x 2^e (|x 2^e| < 2^14) rounded to binary16, nearest with ties to even,
+// subnormals (spacing 2^-24 below 2^-14) kept; bit pattern.  Integer
+// rounding on the FP32 bits, so it does not depend on the FP16 denormal mode.
+__device__ inline uint16_t to_fp16_scaled(float x, int e)
+{
+    const uint32_t u = __float_as_uint(ldexpf(x, e));    // exact: a power-of-two scaling up
+    const uint32_t sign = (u >> 16) & 0x8000u, mag = u & 0x7FFFFFFFu;
+    const int ef = (int)(mag >> 23);                      // biased FP32 exponent
+    if (ef >= 113) {                                      // >= 2^-14: normal binary16
+        const uint32_t frac = mag & 0x7FFFFFu, keep = frac >> 13, rest = frac & 0x1FFFu;
+        uint32_t h = ((uint32_t)(ef - 112) << 10) | keep;
+        if (rest > 0x1000u || (rest == 0x1000u && (keep & 1u)))
+            h += 1u;                                      // a carry moves to the next binade
+        return (uint16_t)(sign | h);
+    }
+    if (ef < 102)                                         // below 2^-25: rounds to zero
+        return (uint16_t)sign;
+    // subnormal binary16: value / 2^-24 = sig 2^(ef - 126), sig the 24-bit significand
+    const uint32_t sig = (mag & 0x7FFFFFu) | 0x800000u;
+    const int sh = 126 - ef;                              // 14 .. 24
+    uint32_t q = sig >> sh;
+    const uint32_t rest = sig & ((1u << sh) - 1u), half = 1u << (sh - 1);
+    if (rest > half || (rest == half && (q & 1u)))
+        q += 1u;                                          // 1024 encodes 2^-14 exactly
+    return (uint16_t)(sign | q);
+}
+
+// One wave per leaf: both packed FP32 copies (LeafLayout) to FP16
+// (Leaf16Layout) at the leaf's scale, and the scale exponent itself.
+template <int B>
+__global__ __launch_bounds__(256) void pack_fp16(const float *__restrict__ tiles,
+                                                 const float *__restrict__ tilesT,
+                                                 const double *__restrict__ leafn,
+                                                 uint16_t *__restrict__ t16,
+                                                 uint16_t *__restrict__ tT16,
+                                                 int32_t *__restrict__ scale, uint32_t ntiles)
+{
+    const uint32_t l = blockIdx.x * 4u + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (l >= ntiles)
+        return;
+    const int e = fp16_scale_exponent(leafn[l]);
+    if (lane == 0)
+        scale[l] = e;
+    const int64_t base = (int64_t)l * (B * B);
+    for (int idx = lane; idx < B * B / 4; idx += 64) {
+        const int r = idx / (B / 4), c = 4 * (idx % (B / 4));
+        const int src = LeafLayout<B>::index(r, c), dst = Leaf16Layout<B>::index(r, c);
+#pragma unroll
+        for (int copy = 0; copy < 2; ++copy) {
+            const float4 v = *reinterpret_cast<const float4 *>((copy ? tilesT : tiles) + base + src);
+            const uint32_t lo = (uint32_t)to_fp16_scaled(v.x, e) |
+                                ((uint32_t)to_fp16_scaled(v.y, e) << 16);
+            const uint32_t hi = (uint32_t)to_fp16_scaled(v.z, e) |
+                                ((uint32_t)to_fp16_scaled(v.w, e) << 16);
+            *reinterpret_cast<uint2 *>((copy ? tT16 : t16) + base + dst) = make_uint2(lo, hi);
+        }
+    }
+}
+
+hipError_t launch_pack_fp16(const float *tiles, const float *tilesT, const double *leafn,
+                            uint16_t *t16, uint16_t *tT16, int32_t *scale, int leaf,
+                            uint32_t ntiles, hipStream_t s)
+{
+    const dim3 grid((ntiles + 3) / 4);
+    switch (leaf) {
+    case 32:
+        hipLaunchKernelGGL(pack_fp16<32>, grid, dim3(256), 0, s, tiles, tilesT, leafn, t16, tT16,
+                           scale, ntiles);
+        break;
+    case 64:
+        hipLaunchKernelGGL(pack_fp16<64>, grid, dim3(256), 0, s, tiles, tilesT, leafn, t16, tT16,
+                           scale, ntiles);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // ---- epsilon-sparsified trees (Sec. II.C) ------------------------------------
 // Leaf l is kept iff s_l > 0 and fl64(s_l * m) >= fl64(tau^2), with
 // m = max(||A||_F^2, other2) read from the dense root; a dropped leaf's norm

@@ -35,7 +35,14 @@ int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *o
 
 // Device bytes of one tree / one plan of depth d, buffers at 256-byte
 // aligned offsets (the arena sizes; also admission control).
-size_t tree_device_bytes(int64_t n, int32_t leaf, bool bf16, bool sub = false);
+size_t tree_device_bytes(int64_t n, int32_t leaf, uint32_t flags);
+
+// Tree flags a request of this precision needs (16-bit copies for split).
+inline uint32_t tree_flags_for(int32_t precision)
+{
+    return precision == SPAMM_PREC_SPLIT_BF16 ? SPAMM_TREE_BF16
+           : precision == SPAMM_PREC_SPLIT_FP16 ? SPAMM_TREE_FP16 : 0u;
+}
 size_t plan_device_bytes(int depth, bool split);
 
 // Leaf GEMM launches (gemm.hip): a plan's job and kind, and one batched

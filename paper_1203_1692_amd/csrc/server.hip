@@ -80,9 +80,10 @@ int check_request(const spamm_request *r, size_t *bytes)
         return fail(SPAMM_E_INVAL, "n = %lld < 1", (long long)r->n);
     if (r->leaf != 16 && r->leaf != 32 && r->leaf != 64)
         return fail(SPAMM_E_INVAL, "leaf = %d not in {16, 32, 64}", r->leaf);
-    if (r->precision != SPAMM_PREC_FP32 && r->precision != SPAMM_PREC_SPLIT_BF16)
+    if (r->precision != SPAMM_PREC_FP32 && r->precision != SPAMM_PREC_SPLIT_BF16 &&
+        r->precision != SPAMM_PREC_SPLIT_FP16)
         return fail(SPAMM_E_INVAL, "unknown precision %d", r->precision);
-    const bool split = r->precision == SPAMM_PREC_SPLIT_BF16;
+    const bool split = r->precision != SPAMM_PREC_FP32;
     if (split && r->leaf == 16)
         return fail(SPAMM_E_INVAL, "split precision needs leaf 32 or 64");
     if (bad_tol(r->tau))
@@ -99,7 +100,7 @@ int check_request(const spamm_request *r, size_t *bytes)
     if (rc)
         return rc;
     const bool distinctB = r->B != nullptr && r->B != r->A;
-    *bytes = tree_device_bytes(r->n, r->leaf, split) * (distinctB ? 2 : 1) +
+    *bytes = tree_device_bytes(r->n, r->leaf, tree_flags_for(r->precision)) * (distinctB ? 2 : 1) +
              plan_device_bytes(d, split);
     return SPAMM_OK;
 }
@@ -145,12 +146,12 @@ int start_step(spamm_server *S, Active &a)
     hipStream_t ss = S->ss[a.slot];
     Pinned &P = S->pin[a.slot];
     const spamm_request &r = a.job.rq;
-    const uint32_t flags = a.split ? SPAMM_TREE_BF16 : 0u;
+    const uint32_t flags = tree_flags_for(r.precision);
     P.root[a.step][1] = 0.0;
     P.K[a.step][1] = 0;
     // arena: [tree of A or X_s][tree of B, step 0 only][plan]
     char *base = (char *)S->arena[a.slot];
-    const size_t tb = tree_device_bytes(r.n, r.leaf, a.split);
+    const size_t tb = tree_device_bytes(r.n, r.leaf, flags);
     int rc = tree_build_async(a.step == 0 ? r.A : r.C, r.n, r.leaf, flags, ss,
                               &P.root[a.step][0], &a.tA, base);
     if (rc)
@@ -230,23 +231,24 @@ bool launch_batches(spamm_server *S)
             (S->active[i].job.rq.leaf == leaf && (int)batch.size() < kMaxJobs ? batch : rest)
                 .push_back(i);
         ready.swap(rest);
-        // split and FP32 jobs go to one launch each (different kernels)
-        GemmJobs sj{}, fj{};
+        // jobs of each kernel kind (FP32, BF16 split, FP16 split) go to one launch
+        constexpr GemmKind kinds[3] = {GemmKind::Fp32, GemmKind::Split, GemmKind::SplitF16};
+        GemmJobs tabs[3] = {};
         hipError_t e = hipSuccess;
         for (size_t i : batch) {
             Active &a = S->active[i];
             if (e == hipSuccess)
                 e = hipStreamWaitEvent(S->gemm, S->ev_cull[a.slot], 0);
-            GemmJobs &tab = a.split ? sj : fj;
+            const GemmKind kind = plan_kind(a.plan);
+            GemmJobs &tab = tabs[kind == GemmKind::Split ? 1 : kind == GemmKind::SplitF16 ? 2 : 0];
             GemmJob &j = tab.job[tab.njobs++];
             plan_jobs(a.plan, a.job.rq.C, j);
             j.block0 = tab.nblocks;
             tab.nblocks += j.nblocks;
         }
-        if (e == hipSuccess && sj.njobs > 0)
-            e = launch_gemm_jobs(leaf, GemmKind::Split, sj, S->gemm);
-        if (e == hipSuccess && fj.njobs > 0)
-            e = launch_gemm_jobs(leaf, GemmKind::Fp32, fj, S->gemm);
+        for (int k = 0; k < 3 && e == hipSuccess; ++k)
+            if (tabs[k].njobs > 0)
+                e = launch_gemm_jobs(leaf, kinds[k], tabs[k], S->gemm);
         hipEvent_t bev = S->spare.back();
         if (e == hipSuccess)
             e = hipEventRecord(bev, S->gemm);
@@ -408,7 +410,7 @@ void scheduler(spamm_server *S)
             a.job = admitted[i];
             a.slot = slots[i];
             a.steps = std::max(1, a.job.rq.chain_len);
-            a.split = a.job.rq.precision == SPAMM_PREC_SPLIT_BF16;
+            a.split = a.job.rq.precision != SPAMM_PREC_FP32;
             a.distinctB = a.job.rq.B != nullptr && a.job.rq.B != a.job.rq.A;
             a.t_admit = now_us();
             int rc = start_step(S, a);

@@ -84,9 +84,16 @@ def test_newer_entry_points_check_arguments_on_the_host():
                                        None) == sp.SPAMM_E_INVAL
     assert lib.spamm_build_tree_sparse(fake, 16 * 1024 + 1, 16, 0, dbl(1e-6), dbl(0.0), None,
                                        ctypes.byref(h)) == sp.SPAMM_E_RANGE
-    # sub-block norms only for 64 x 64 leaves; unknown flags
+    # sub-block norms only for 64 x 64 leaves; unknown flags; FP16 copies not
+    # with BF16 ones, not for 16 x 16 leaves, not in a sparsified tree
     assert lib.spamm_build_tree_ex(fake, 64, 32, 2, None, ctypes.byref(h)) == sp.SPAMM_E_INVAL
-    assert lib.spamm_build_tree_ex(fake, 64, 64, 4, None, ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_build_tree_ex(fake, 64, 64, 8, None, ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_build_tree_ex(fake, 64, 64, sp.TREE_FP16 | sp.TREE_BF16, None,
+                                   ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_build_tree_ex(fake, 64, 16, sp.TREE_FP16, None,
+                                   ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_build_tree_sparse(fake, 64, 32, sp.TREE_FP16, dbl(1e-6), dbl(0.0), None,
+                                       ctypes.byref(h)) == sp.SPAMM_E_INVAL
     # NULL handles
     assert lib.spamm_tree_storage(None, None, None, None) == sp.SPAMM_E_INVAL
     cnt = ctypes.c_size_t()

@@ -1,8 +1,9 @@
 """The serving loop on the GPU.
 
 * every request's C is bit-identical whether it runs alone or in a mix of
-  uneven n, tau, leaf, precision and chain length (fixed owner and k order
-  per output leaf), and equal to the one-call API's result;
+  uneven n, tau, leaf, precision (FP32, BF16 and FP16 split) and chain
+  length (fixed owner and k order per output leaf), and equal to the
+  one-call API's result;
 * plain requests agree with the oracle (task counts exact, C within
   1e-5 ||A||_F ||B||_F); a chain's last step agrees with the oracle run on
   the previous step's matrix;
@@ -54,6 +55,9 @@ MIX = [
     (512, 32, 1e-6, 0, 0.0, 0, False, 0.5, 12),
     (1, 32, 0.0, 0, 0.0, 0, False, 0.1, 13),
     (1200, 32, 1e-6, 1, 1e-3, 0, True, 0.08, 14),
+    (600, 32, 1e-6, 2, 1e-3, 0, False, 0.1, 15),
+    (1024, 64, 1e-8, 2, 1e-4, 2, False, 0.15, 16),
+    (300, 32, 1e-6, 2, 1e-2, 0, True, 0.1, 17),
 ]
 
 
@@ -83,13 +87,13 @@ def reference(gpu, spec, dA, dB, low):
     """The same request through the one-call API, step by step."""
     import torch
     n, leaf, tau, prec, theta, chain, *_ = spec
-    bf = prec == gpu.PREC_SPLIT_BF16
+    bf, f16 = prec == gpu.PREC_SPLIT_BF16, prec == gpu.PREC_SPLIT_FP16
     X = dA
     prev = None
     tasks = 0
     for _ in range(max(1, chain)):
-        tA = gpu.build_tree(X, leaf, bf16=bf)
-        tB = tA if (dB is None or chain) else gpu.build_tree(dB, leaf, bf16=bf)
+        tA = gpu.build_tree(X, leaf, bf16=bf, fp16=f16)
+        tB = tA if (dB is None or chain) else gpu.build_tree(dB, leaf, bf16=bf, fp16=f16)
         C = torch.empty_like(dA)
         st = gpu.multiply_ex(tA, tB, tau, C, precision=prec, low_tol=low)
         tasks += st["tasks"]
@@ -161,15 +165,16 @@ def test_matches_oracle(mix, i):
     n, leaf, tau, prec, theta, chain, *_ = MIX[i]
     A, B = mix["inputs"][i][0], mix["inputs"][i][1]
     low = mix["lows"][i]
+    fmt = "fp16" if prec == 2 else "bf16"
     if chain:
         # the last squaring, on the previous step's matrix as the GPU holds it
         prev = mix["refs"][i][1].cpu().numpy()
-        ref = oracle.spamm(prev, prev, leaf, tau, low_tol=low)
+        ref = oracle.spamm(prev, prev, leaf, tau, low_tol=low, low_fmt=fmt)
         nrm = float(np.sqrt(oracle.norms(prev, leaf)[0][0, 0]))
         bound = 1e-5 * nrm * nrm
     else:
         Bm = A if B is None else B
-        ref = oracle.spamm(A, Bm, leaf, tau, low_tol=low)
+        ref = oracle.spamm(A, Bm, leaf, tau, low_tol=low, low_fmt=fmt)
         nA = math.sqrt(oracle.norms(A, leaf)[0][0, 0])
         nB = math.sqrt(oracle.norms(Bm, leaf)[0][0, 0])
         bound = 1e-5 * nA * nB

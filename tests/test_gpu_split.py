@@ -190,3 +190,169 @@ def test_split_argument_errors(gpu):
         assert ei.value.code == gpu.SPAMM_E_INVAL
     with pytest.raises(gpu.SpammError):
         gpu.symbolic(t, t, 1e-6, precision=7)
+
+
+# ---- FP16 LOW operands (per-leaf power-of-two scale) ---------------------------
+
+def fp16_leaves(P, leaf, S):
+    """P (padded FP32) with every leaf rounded through numpy float16 at the
+    scale exponent of its squared norm S[I, J] (oracle.fp16_exponent)."""
+    N = P.shape[0] // leaf
+    R = np.zeros(P.shape)
+    for I in range(N):
+        for J in range(N):
+            e = oracle.fp16_exponent(S[I, J])
+            blk = P[I * leaf:(I + 1) * leaf, J * leaf:(J + 1) * leaf].astype(np.float64) * 2.0 ** e
+            R[I * leaf:(I + 1) * leaf, J * leaf:(J + 1) * leaf] = \
+                blk.astype(np.float16).astype(np.float64) * 2.0 ** -e
+    return R
+
+
+def split16_bound(A, B, leaf, keys):
+    """As split_bound with FP16 LOW operands; each LOW product is summed on its
+    own and added (one more FP32 rounding per product): m = (n_b + 1) K + 1."""
+    PA, d = padded(A, leaf)
+    PB, _ = padded(B, leaf)
+    N = 1 << d
+    inv = {oracle.linear_index(i, j): (i, j) for i in range(N) for j in range(N)}
+    ops = {0: (np.abs(PA.astype(np.float64)), np.abs(PB.astype(np.float64))),
+           1: (np.abs(fp16_leaves(PA, leaf, oracle.norms(A, leaf)[-1])),
+               np.abs(fp16_leaves(PB, leaf, oracle.norms(B, leaf)[-1])))}
+    M = np.zeros(PA.shape)
+    cnt = np.zeros((N, N), dtype=np.int64)
+    for key in keys:
+        key = int(key)
+        I, J = inv[(key >> 32) & 0x7FFFFFFF]
+        k = key & 0xFFFFFFFF
+        X, Y = ops[key >> 63]
+        M[I * leaf:(I + 1) * leaf, J * leaf:(J + 1) * leaf] += (
+            X[I * leaf:(I + 1) * leaf, k * leaf:(k + 1) * leaf] @ Y[k * leaf:(k + 1) * leaf,
+                                                                  J * leaf:(J + 1) * leaf])
+        cnt[I, J] += 1
+    m = (leaf + 1) * np.kron(cnt, np.ones((leaf, leaf))) + 1
+    gamma = m * U32 / (1 - m * U32)
+    n = A.shape[0]
+    return (gamma * M + m * 2.0 ** -126)[:n, :n]
+
+
+@pytest.fixture(scope="module")
+def runs16(gpu):
+    import torch
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            A, B, leaf, tau, low = CASES[name]()
+            Bm = A if B is None else B
+            ref = oracle.spamm(A, Bm, leaf, tau, low_tol=low, low_fmt="fp16")
+            dA = torch.from_numpy(A).cuda()
+            tA = gpu.build_tree(dA, leaf, fp16=True)
+            tB = tA if B is None else gpu.build_tree(torch.from_numpy(B).cuda(), leaf, fp16=True)
+            plan = gpu.symbolic(tA, tB, tau, precision=gpu.PREC_SPLIT_FP16, low_tol=low)
+            C = torch.full_like(dA, float("nan"))
+            plan.numeric(C)
+            torch.cuda.synchronize()
+            cache[name] = dict(A=A, B=Bm, leaf=leaf, tau=tau, low=low, ref=ref, plan=plan,
+                               C=C.cpu().numpy())
+        return cache[name]
+    return get
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp16_task_list_with_classes(runs16, name):
+    r = runs16(name)
+    assert np.array_equal(r["plan"].tasks(), r["ref"].keys)
+    st = r["plan"].stats()
+    assert st["tasks"] == r["ref"].K and st["tasks_low"] == r["ref"].Klow
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp16_product_within_bound(runs16, name):
+    r = runs16(name)
+    assert np.all(np.isfinite(r["C"]))
+    err = np.abs(r["C"].astype(np.float64) - r["ref"].C)
+    worst = float(np.max(err - split16_bound(r["A"], r["B"], r["leaf"], r["ref"].keys)))
+    assert worst <= 0.0, f"bound exceeded by {worst}"
+
+
+def test_fp16_tiny_entries_keep_their_digits(gpu):
+    """Entries far below binary16's range (1e-30 .. 1e-40) survive because each
+    leaf is scaled by its own power of two: the all-LOW FP16 product of such a
+    matrix matches the oracle's as closely as one of order-one entries."""
+    import torch
+    A = decay(200, 0.05, 31) * np.float32(1e-33)
+    B = decay(200, 0.07, 32, sym=False)
+    ref = oracle.spamm(A, B, 32, 0.0, low_tol=1e30, low_fmt="fp16")
+    assert ref.Klow == ref.K
+    tA = gpu.build_tree(torch.from_numpy(A).cuda(), 32, fp16=True)
+    tB = gpu.build_tree(torch.from_numpy(B).cuda(), 32, fp16=True)
+    C = torch.empty((200, 200), device="cuda")
+    gpu.multiply_ex(tA, tB, 0.0, C, precision=gpu.PREC_SPLIT_FP16, low_tol=1e30)
+    got = C.cpu().numpy().astype(np.float64)
+    scale = np.abs(ref.C).max()
+    assert scale > 0 and np.abs(got - ref.C).max() <= 1e-5 * scale
+    exact = A.astype(np.float64) @ B.astype(np.float64)
+    # unscaled binary16 would flush every entry to zero (a 100 % error)
+    assert np.abs(got - exact).max() <= 1e-2 * np.abs(exact).max()
+
+
+def test_fp16_zero_low_tol_equals_fp32(gpu):
+    import torch
+    A = decay(512, 0.05, 9)
+    dA = torch.from_numpy(A).cuda()
+    t = gpu.build_tree(dA, 64, fp16=True)
+    C1, C2 = torch.empty_like(dA), torch.empty_like(dA)
+    gpu.multiply_ex(t, t, 1e-6, C1)
+    st = gpu.multiply_ex(t, t, 1e-6, C2, precision=gpu.PREC_SPLIT_FP16, low_tol=0.0)
+    assert st["tasks_low"] == 0
+    assert torch.equal(C1, C2)
+
+
+def test_fp16_error_below_bf16_at_same_classes(gpu):
+    """Same tau and low_tol, so the same LOW set: the FP16 product's max-norm
+    error against the dense FP64 product is well below the BF16 one's, and
+    within the truncation error plus sum_LOW (2 2^-11 + 2^-22) ||A_ik|| ||B_kj||
+    plus the FP32 rounding."""
+    import torch
+    A = workloads.exp_decay(1024, 0.1, 0)
+    dA = torch.from_numpy(A).cuda()
+    t16 = gpu.build_tree(dA, 32, fp16=True)
+    tb = gpu.build_tree(dA, 32, bf16=True)
+    low = gpu.relative_low_tol(t16, t16, 1e-2)
+    C16, Cb = torch.empty_like(dA), torch.empty_like(dA)
+    s16 = gpu.multiply_ex(t16, t16, 1e-6, C16, precision=gpu.PREC_SPLIT_FP16, low_tol=low)
+    sb = gpu.multiply_ex(tb, tb, 1e-6, Cb, precision=gpu.PREC_SPLIT_BF16, low_tol=low)
+    assert s16["tasks_low"] == sb["tasks_low"] > 0
+    exact = A.astype(np.float64) @ A.astype(np.float64)
+    e16 = float(np.abs(C16.cpu().numpy() - exact).max())
+    eb = float(np.abs(Cb.cpu().numpy() - exact).max())
+    assert e16 < eb / 4
+    nrm = np.sqrt(oracle.norms(A, 32)[-1])
+    ref = oracle.spamm(A, A, 32, 1e-6, want_C=False, low_tol=low)
+    inv = {oracle.linear_index(i, j): (i, j) for i in range(32) for j in range(32)}
+    lowsum = {}
+    for key in ref.keys:
+        key = int(key)
+        if key >> 63:
+            I, J = inv[(key >> 32) & 0x7FFFFFFF]
+            k = key & 0xFFFFFFFF
+            lowsum[(I, J)] = lowsum.get((I, J), 0.0) + nrm[I, k] * nrm[k, J]
+    trunc = oracle.spamm(A, A, 32, 1e-6).C
+    bound = float(np.abs(trunc - exact).max()) + (2 * 2.0 ** -11 + 2.0 ** -22) * \
+        max(lowsum.values()) + 1e-5 * t16.norm2
+    assert e16 <= bound
+
+
+def test_fp16_argument_errors(gpu):
+    import torch
+    A = torch.from_numpy(decay(200, 0.05, 1)).cuda()
+    tb = gpu.build_tree(A, 32, bf16=True)
+    t16 = gpu.build_tree(A, 32, fp16=True)
+    for t, prec in ((tb, gpu.PREC_SPLIT_FP16), (t16, gpu.PREC_SPLIT_BF16)):
+        with pytest.raises(gpu.SpammError) as ei:
+            gpu.symbolic(t, t, 1e-6, precision=prec, low_tol=1e-3)
+        assert ei.value.code == gpu.SPAMM_E_INVAL
+    with pytest.raises(gpu.SpammError):
+        gpu.build_tree(A, 16, fp16=True)
+    with pytest.raises(gpu.SpammError):
+        gpu.build_tree(A, 32, fp16=True, bf16=True)

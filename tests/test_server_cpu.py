@@ -13,27 +13,33 @@ def fp(**kw):
     return sp.request_footprint(**args)
 
 
-def tree_bytes(n, leaf, bf16):
-    """Packed leaves (two FP32 copies, two BF16 copies when bf16) plus the
-    FP64 norm pyramid of tiers 0..d, each buffer rounded up to 256 bytes
-    (leaf copies are multiples of 256 already)."""
+def tree_bytes(n, leaf, prec):
+    """Packed leaves (two FP32 copies, two 16-bit copies for split precision,
+    plus an int32 scale exponent per leaf for FP16) and the FP64 norm pyramid
+    of tiers 0..d, each buffer rounded up to 256 bytes (leaf copies are
+    multiples of 256 already)."""
     d = 0
     while leaf << d < n:
         d += 1
     np_ = leaf << d
+    up = lambda b: -(-b // 256) * 256                                     # noqa: E731
     norms = 8 * (4 ** (d + 1) - 1) // 3
-    return 8 * np_ * np_ + (4 * np_ * np_ if bf16 else 0) + -(-norms // 256) * 256
+    split = prec != sp.PREC_FP32
+    scales = up(4 * 4 ** d) if prec == sp.PREC_SPLIT_FP16 else 0
+    return 8 * np_ * np_ + (4 * np_ * np_ if split else 0) + scales + up(norms)
 
 
 @pytest.mark.parametrize("n,leaf,prec", [(1, 16, sp.PREC_FP32), (1000, 32, sp.PREC_FP32),
                                          (4096, 32, sp.PREC_SPLIT_BF16),
-                                         (8192, 64, sp.PREC_SPLIT_BF16)])
+                                         (8192, 64, sp.PREC_SPLIT_BF16),
+                                         (100, 32, sp.PREC_SPLIT_FP16),
+                                         (8192, 64, sp.PREC_SPLIT_FP16)])
 def test_footprint_tree_part(n, leaf, prec):
     one = fp(n=n, leaf=leaf, precision=prec, low_tol=1e-3)
     two = fp(n=n, leaf=leaf, precision=prec, low_tol=1e-3, distinct_b=True)
-    assert two - one == tree_bytes(n, leaf, prec == sp.PREC_SPLIT_BF16)
+    assert two - one == tree_bytes(n, leaf, prec)
     # the task arena is a modest share of the operand at these sizes
-    assert 0 < one - tree_bytes(n, leaf, prec == sp.PREC_SPLIT_BF16) <= tree_bytes(n, leaf, False)
+    assert 0 < one - tree_bytes(n, leaf, prec) <= tree_bytes(n, leaf, sp.PREC_FP32)
 
 
 def test_footprint_grows_with_n_and_chain_does_not_change_it():
@@ -47,6 +53,7 @@ def test_footprint_grows_with_n_and_chain_does_not_change_it():
     (dict(n=0), sp.SPAMM_E_INVAL),
     (dict(leaf=48), sp.SPAMM_E_INVAL),
     (dict(leaf=16, precision=sp.PREC_SPLIT_BF16), sp.SPAMM_E_INVAL),
+    (dict(leaf=16, precision=sp.PREC_SPLIT_FP16), sp.SPAMM_E_INVAL),
     (dict(precision=5), sp.SPAMM_E_INVAL),
     (dict(tau=-1.0), sp.SPAMM_E_INVAL),
     (dict(tau=float("nan")), sp.SPAMM_E_INVAL),
