@@ -47,14 +47,17 @@ struct GemmShape {
     static constexpr size_t kLds = sizeof(float) * 2 * kStage + sizeof(uint32_t) * (1 << kMaxDepth);
 };
 
-// Split kernel: the BF16 stages (four whole leaves, double buffered) and the
-// FP32 stages share one area, followed by the entry list.
-template <int B>
+// Split kernel: the 16-bit stages (four whole leaves, double buffered) and
+// the FP32 stages share one area, followed by the entry list and, with FP16
+// LOW operands, each entry's four scale exponents (rows 2I, 2I+1, columns
+// 2J, 2J+1).
+template <int B, bool F16>
 struct SplitShape {
     static constexpr size_t kBf16 = sizeof(uint16_t) * 2 * 4 * B * B;
     static constexpr size_t kFp32 = sizeof(float) * 2 * GemmShape<B>::kStage;
     static constexpr size_t kStages = kBf16 > kFp32 ? kBf16 : kFp32;
-    static constexpr size_t kLds = kStages + sizeof(uint32_t) * (1 << kMaxDepth);
+    static constexpr size_t kEnts = sizeof(uint32_t) * (1 << kMaxDepth);
+    static constexpr size_t kLds = kStages + kEnts + (F16 ? 4 * sizeof(int16_t) * (1 << kMaxDepth) : 0);
 };
 
 // A block's schedule holds at most one entry per k (N <= 2^kMaxDepth); it is
@@ -392,15 +395,17 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
 // double-buffered direct-to-LDS staging as the FP32 loop; a stage is the four
 // whole 16-bit leaves of one entry (Leaf16Layout, 8 KB each at n_b = 64).
 // F16: the leaves hold x 2^e (e per leaf, escA / escB), so each product is
-// accumulated on its own from zero and added as tmp 2^-(eA + eB) (an exact
-// scaling unless it underflows).
+// accumulated on its own from zero and added as tmp 2^-(eA + eB): one FMA
+// with the exact power of two when that is a normal float, else an exact
+// ldexp and an add.  The block's exponents are copied to LDS (`eexp`, four
+// per entry) before its first stage.
 template <int B, bool F16>
 __device__ inline void bf16_products(const uint16_t *__restrict__ tA16,
                                      const uint16_t *__restrict__ tBT16, const uint32_t *slotA,
                                      const uint32_t *slotB, const uint32_t *__restrict__ bent,
                                      uint32_t e0, uint32_t e1, uint32_t I0, uint32_t J0,
-                                     uint16_t *smem16, uint32_t *ents, int w, int lane,
-                                     const int32_t *escA, const int32_t *escB,
+                                     uint16_t *smem16, uint32_t *ents, int16_t *eexp, int w,
+                                     int lane, const int32_t *escA, const int32_t *escB,
                                      floatx16 (&acc)[B / 32][B / 32])
 {
     using L = Leaf16Layout<B>;
@@ -425,6 +430,20 @@ __device__ inline void bf16_products(const uint16_t *__restrict__ tA16,
     const uint32_t T = e1 - e0;
     if (T > 0)
         issue(ents[0], smem16);
+    if constexpr (F16) {
+        // operand o of entry i: rows I0, I0+1 of A (o = 0, 1), columns J0, J0+1
+        // of B (o = 2, 3); only the operands the entry's mask uses exist (a
+        // single-leaf product has no row I0+1).  Visible after the first
+        // stage's barrier.
+        for (uint32_t x = threadIdx.x; x < 4 * T; x += blockDim.x) {
+            const uint32_t ent = ents[x >> 2], o = x & 3u, k = ent & 0xFFFFu, mask = ent >> 16;
+            const uint32_t users = o < 2 ? (0x3u << (2 * o)) : (0x5u << (o - 2));
+            int e = 0;
+            if (mask & users)
+                e = o < 2 ? escA[lin_index(I0 + o, k)] : escB[lin_index(k, J0 + (o - 2))];
+            eexp[x] = (int16_t)e;
+        }
+    }
     const int r = lane & 31, h = lane >> 5;
     for (uint32_t t = 0; t < T; ++t) {
         const uint32_t ent = ents[t];
@@ -448,10 +467,7 @@ __device__ inline void bf16_products(const uint16_t *__restrict__ tA16,
                     bv[st][j] = *reinterpret_cast<const bf16x8 *>(Bp + L::index(j * 32 + r, c));
             }
             if constexpr (F16) {
-                const uint32_t k = ent & 0xFFFFu;
-                const int esum =
-                    escA[__builtin_amdgcn_readfirstlane(lin_index(I0 + qa, k))] +
-                    escB[__builtin_amdgcn_readfirstlane(lin_index(k, J0 + qb))];
+                const int esum = (int)eexp[4 * t + qa] + (int)eexp[4 * t + 2 + qb];
                 floatx16 tmp[MB][MB];
 #pragma unroll
                 for (int i = 0; i < MB; ++i)
@@ -467,13 +483,24 @@ __device__ inline void bf16_products(const uint16_t *__restrict__ tA16,
                             tmp[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
                                 __builtin_bit_cast(f16x8, av[st][i]),
                                 __builtin_bit_cast(f16x8, bv[st][j]), tmp[i][j], 0, 0, 0);
+                if (esum >= -126 && esum <= 126) {
+                    const float sc = __uint_as_float((uint32_t)(127 - esum) << 23);   // 2^-esum
 #pragma unroll
-                for (int i = 0; i < MB; ++i)
+                    for (int i = 0; i < MB; ++i)
 #pragma unroll
-                    for (int j = 0; j < MB; ++j)
+                        for (int j = 0; j < MB; ++j)
 #pragma unroll
-                        for (int v = 0; v < 16; ++v)
-                            acc[i][j][v] += ldexpf(tmp[i][j][v], -esum);
+                            for (int v = 0; v < 16; ++v)
+                                acc[i][j][v] = fmaf(tmp[i][j][v], sc, acc[i][j][v]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < MB; ++i)
+#pragma unroll
+                        for (int j = 0; j < MB; ++j)
+#pragma unroll
+                            for (int v = 0; v < 16; ++v)
+                                acc[i][j][v] += ldexpf(tmp[i][j][v], -esum);
+                }
             } else {
 #pragma unroll
                 for (int st = 0; st < B / 16; ++st)
@@ -511,8 +538,9 @@ __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
         I0 = 2 * lin_row(blk);
         J0 = 2 * lin_col(blk);
     }
-    constexpr size_t kStages = SplitShape<B>::kStages;
-    uint32_t *ents = (uint32_t *)((char *)smem + kStages);
+    using SS = SplitShape<B, F16>;
+    uint32_t *ents = (uint32_t *)((char *)smem + SS::kStages);
+    int16_t *eexp = (int16_t *)((char *)smem + SS::kStages + SS::kEnts);
     floatx16 lo[MB][MB], hi[MB][MB];
 #pragma unroll
     for (int i = 0; i < MB; ++i)
@@ -524,7 +552,7 @@ __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
     bf16_products<B, F16>((const uint16_t *)job.tA16, (const uint16_t *)job.tBT16, job.slotA,
                           job.slotB,
                      job.bent_lo, job.browptr_lo[blk], job.browptr_lo[blk + 1], I0, J0,
-                     (uint16_t *)smem, ents, w, lane, job.escA, job.escB, lo);
+                     (uint16_t *)smem, ents, eexp, w, lane, job.escA, job.escB, lo);
     __syncthreads();                       // every wave is done with the BF16 stages
     const uint32_t h0 = job.browptr[blk], h1 = job.browptr[blk + 1];
     fp32_products<B>((const float *)job.tA, (const float *)job.tBT, job.slotA, job.slotB, job.bent,
@@ -558,7 +586,7 @@ static hipError_t launch_fp32(const GemmJobs &jobs, hipStream_t s)
 template <int B, bool F16>
 static hipError_t launch_split(const GemmJobs &jobs, hipStream_t s)
 {
-    constexpr size_t lds = SplitShape<B>::kLds;
+    constexpr size_t lds = SplitShape<B, F16>::kLds;
     static const hipError_t attr =
         hipFuncSetAttribute((const void *)leaf_gemm_split<B, F16>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
