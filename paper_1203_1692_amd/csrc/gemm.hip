@@ -1,6 +1,6 @@
 // Numeric multiply: C_ij = sum over kept k (ascending) of A_ik B_kj
 // (Eq. product, Alg. 1 steps 7-9) on FP32 MFMA with FP32 accumulation; with
-// split precision the LOW products run on BF16 MFMA in the same kernel.
+// split precision the LOW products run on BF16 or FP16 MFMA in the same kernel.
 //
 // Ownership.  A workgroup of 4 waves owns one block of 2 x 2 output leaves
 // (the children of one tier-(d-1) tile); wave q = 2a + b owns leaf
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
 // ldexp and an add.  The block's exponents are copied to LDS (`eexp`, four
 // per entry) before its first stage.
 template <int B, bool F16>
-__device__ inline void bf16_products(const uint16_t *__restrict__ tA16,
+__device__ inline void low_products(const uint16_t *__restrict__ tA16,
                                      const uint16_t *__restrict__ tBT16, const uint32_t *slotA,
                                      const uint32_t *slotB, const uint32_t *__restrict__ bent,
                                      uint32_t e0, uint32_t e1, uint32_t I0, uint32_t J0,
@@ -527,7 +527,7 @@ template <int B, bool F16>
 __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
 {
     constexpr int MB = B / 32;
-    extern __shared__ float smem[];        // the BF16 stages, then the FP32 stages
+    extern __shared__ float smem[];        // the 16-bit stages, then the FP32 stages
     const GemmJob &job = jobs.job[job_of(jobs, blockIdx.x)];
     const int single = job.single;
     const uint32_t blk = xcd_block(blockIdx.x - job.block0, job.nblocks);
@@ -549,11 +549,11 @@ __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
             lo[i][j] = floatx16{0};
             hi[i][j] = floatx16{0};
         }
-    bf16_products<B, F16>((const uint16_t *)job.tA16, (const uint16_t *)job.tBT16, job.slotA,
+    low_products<B, F16>((const uint16_t *)job.tA16, (const uint16_t *)job.tBT16, job.slotA,
                           job.slotB,
                      job.bent_lo, job.browptr_lo[blk], job.browptr_lo[blk + 1], I0, J0,
                      (uint16_t *)smem, ents, eexp, w, lane, job.escA, job.escB, lo);
-    __syncthreads();                       // every wave is done with the BF16 stages
+    __syncthreads();                       // every wave is done with the 16-bit stages
     const uint32_t h0 = job.browptr[blk], h1 = job.browptr[blk + 1];
     fp32_products<B>((const float *)job.tA, (const float *)job.tBT, job.slotA, job.slotB, job.bent,
                      h0, h1, I0, J0, smem, ents, w, lane, hi);
@@ -638,7 +638,7 @@ GemmKind plan_kind(const spamm_plan *p)
 }
 
 // The plan's job: FP32 copies and HIGH (or only) schedule; with split
-// precision also the BF16 copies and the LOW schedule.
+// precision also the 16-bit copies and the LOW schedule.
 void plan_jobs(const spamm_plan *p, float *C, GemmJob &j)
 {
     const bool split = p->precision != SPAMM_PREC_FP32;
