@@ -60,10 +60,12 @@ def measured_traffic(workload: str):
     return rec.get("bytes_per_launch")
 
 
-def measured_split_traffic(workload: str, tau: float, low_tol: float):
-    """HBM bytes per launch of the split kernel at (tau, low_tol) from the
-    committed counter runs, or None when the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", f"leaf_gemm_split_{workload}_traffic.json")
+def measured_split_traffic(workload: str, tau: float, low_tol: float, fmt: str = "bf16"):
+    """HBM bytes per launch of the split kernel (LOW operands in `fmt`) at
+    (tau, low_tol) from the committed counter runs, or None when the kernel
+    sources changed since."""
+    kind = "leaf_gemm_split" if fmt == "bf16" else "leaf_gemm_split_fp16"
+    path = os.path.join(ROOT, "profiles", f"{kind}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
@@ -165,16 +167,22 @@ def matched_error(sp, wl, A, dA, C, tau, leaf, n, N, reps=2):
 
     f32, spl, sub = fastest("fp32"), fastest("split-bf16"), fastest("fp32-subleaf")
     s16 = fastest("split-fp16")
-    split_roofline = None
-    if spl is not None:
-        tb = measured_split_traffic(wl.name, spl["tau"], spl["low_tol"])
-        if tb is not None:
-            gbs = tb / (spl["ms_leaf_gemm"] * 1e-3) / 1e9
-            split_roofline = {"kernel": "leaf_gemm_split", "bound": "hbm", "achieved": round(gbs, 1),
-                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": tb,
-                              "note": "measured HBM bytes per launch / leaf-GEMM time; the LOW "
-                                      "phase runs above this average, the HIGH tail below"}
+
+    def split_roof(point, fmt, kernel):
+        if point is None:
+            return None
+        tb = measured_split_traffic(wl.name, point["tau"], point["low_tol"], fmt)
+        if tb is None:
+            return None
+        gbs = tb / (point["ms_leaf_gemm"] * 1e-3) / 1e9
+        return {"kernel": kernel, "bound": "hbm", "achieved": round(gbs, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                "traffic": tb,
+                "note": "measured HBM bytes per launch / leaf-GEMM time; the LOW phase runs "
+                        "above this average, the HIGH tail below"}
+
+    split_roofline = split_roof(spl, "bf16", "leaf_gemm_split<64, false>")
+    split_fp16_roofline = split_roof(s16, "fp16", "leaf_gemm_split<64, true>")
     return {
         "target_err": target,
         "err_sample": f"{len(tiles)} seeded output leaves (incl. diagonal), dense FP64 reference",
@@ -184,6 +192,7 @@ def matched_error(sp, wl, A, dA, C, tau, leaf, n, N, reps=2):
         "speedup_split_fp16_vs_fp32": round(f32["ms"] / s16["ms"], 3) if f32 and s16 else None,
         "speedup_subleaf_vs_fp32": round(f32["ms"] / sub["ms"], 3) if f32 and sub else None,
         "split_roofline": split_roofline,
+        "split_fp16_roofline": split_fp16_roofline,
         "subleaf_same_tau": subleaf,
         "grid": "tau x {1,10,...,1e5}, low_tol = tau x {0 (fp32), 256, 1024, 4096, 16384} "
                 "(bf16), tau x {1024, 4096, ..., 1048576} (fp16); "
@@ -579,7 +588,7 @@ def main() -> int:
     }
     if split:
         # the split kernel moves whole 16-bit leaves: rate it against HBM
-        tb = None if f16 else measured_split_traffic(wl.name, tau, args.low_tol)
+        tb = measured_split_traffic(wl.name, tau, args.low_tol, "fp16" if f16 else "bf16")
         gbs = tb / (gemm_ms * 1e-3) / 1e9 if tb is not None else None
         out["dtype"] = "f32+f16" if f16 else "f32+bf16"
         out["config"]["precision"] = "split-fp16" if f16 else "split-bf16"
