@@ -198,3 +198,89 @@ def test_largest_grid_n16384_leaf16(gpu):
     with pytest.raises(gpu.SpammError) as ei:
         gpu.build_tree(big, 16)
     assert ei.value.code == gpu.SPAMM_E_RANGE
+
+
+# ---- split precision at full size -------------------------------------------
+
+def round_leaf(X, S, fmt):
+    """A leaf block rounded as a LOW operand: bfloat16, or binary16 at the
+    scale exponent of its squared norm S."""
+    import torch
+    if fmt == "bf16":
+        return torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(torch.bfloat16).to(
+            torch.float64).numpy()
+    e = oracle.fp16_exponent(S)
+    return (X * 2.0 ** e).astype(np.float16).astype(np.float64) * 2.0 ** -e
+
+
+class SplitRun:
+    def __init__(self, sp, A, leaf, tau, low, fmt, label):
+        import torch
+        self.A, self.leaf, self.tau, self.low, self.fmt, self.n = A, leaf, tau, low, fmt, A.shape[0]
+        print(f"\n[fullsize] {label} split-{fmt} tau={tau:g} low_tol={low:g}", flush=True)
+        dA = torch.from_numpy(A).cuda()
+        self.tree = sp.build_tree(dA, leaf, bf16=(fmt == "bf16"), fp16=(fmt == "fp16"))
+        prec = sp.PREC_SPLIT_FP16 if fmt == "fp16" else sp.PREC_SPLIT_BF16
+        self.plan = sp.symbolic(self.tree, self.tree, tau, precision=prec, low_tol=low)
+        C = torch.full_like(dA, float("nan"))
+        self.plan.numeric(C)
+        torch.cuda.synchronize()
+        del dA
+        self.C = C.cpu().numpy()
+        del C
+        self.keys = self.plan.tasks()
+        self.stats = self.plan.stats()
+        print(f"[fullsize] K={self.stats['tasks']} LOW={self.stats['tasks_low']}", flush=True)
+
+
+def check_split(run, seed):
+    """Every task key (class bit included) against the oracle's split mode;
+    sampled output leaves against the oracle's per-leaf recursion within
+    Higham's bound over each class's operands (m = n_b K + 1, one more
+    rounding per LOW product with FP16)."""
+    ref = oracle.spamm(run.A, run.A, run.leaf, run.tau, want_C=False, low_tol=run.low,
+                       low_fmt=run.fmt)
+    assert run.stats["tasks"] == ref.K and run.stats["tasks_low"] == ref.Klow
+    assert np.array_equal(run.keys, ref.keys)
+    N = 1 << run.tree.depth
+    S = oracle.norms(run.A, run.leaf)[-1]
+    tiles = choose_tiles(N, seed, count=24)
+    Ct, counts, kl = oracle.spamm_tiles(run.A, run.A, run.leaf, run.tau, tiles, threads=16,
+                                        want_klists=True, low_tol=run.low, low_fmt=run.fmt)
+    extra = 1 if run.fmt == "fp16" else 0
+    worst = -np.inf
+    for s, (I, J) in enumerate(tiles):
+        M = np.zeros((run.leaf, run.leaf))
+        for v in kl[s, :counts[s]]:
+            k, low = int(v) & 0x3FFFFFFF, int(v) >> 30
+            X = leaf_block(run.A, I, k, run.leaf, run.n)
+            Y = leaf_block(run.A, k, J, run.leaf, run.n)
+            if low:
+                X, Y = round_leaf(X, S[I, k], run.fmt), round_leaf(Y, S[k, J], run.fmt)
+            M += np.abs(X) @ np.abs(Y)
+        m = (run.leaf + extra) * int(counts[s]) + 1
+        bound = m * U32 / (1 - m * U32) * M + m * 2.0 ** -126
+        got = leaf_block(run.C, I, J, run.leaf, run.n)
+        assert np.all(np.isfinite(got))
+        worst = max(worst, float(np.max(np.abs(got - Ct[s]) - bound)))
+    assert worst <= 0.0, f"rounding bound exceeded by {worst}"
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_algdecay_split_theta_1e4(gpu, fmt):
+    """algdecay-n16384 at tau = 1e-8 with LOW iff ||A_ik|| ||A_kj|| < 1e-4 ||A||_F^2."""
+    wl = workloads.WORKLOADS["algdecay-n16384"]
+    A = wl.matrix()
+    low = 1e-4 * float(oracle.norms(A, wl.leaf)[0][0, 0])
+    r = SplitRun(gpu, A, wl.leaf, 1e-8, low, fmt, wl.name)
+    assert 0 < r.stats["tasks_low"] < r.stats["tasks"]
+    check_split(r, seed=21)
+
+
+@pytest.mark.parametrize("fmt,low", [("bf16", 0.4096), ("fp16", 1.6384)])
+def test_cluster1310_split_matched_error_point(cluster1310, gpu, fmt, low):
+    """cluster1310-n32750 at the split products' matched-error points of the
+    benchmark (tau = 1e-4)."""
+    r = SplitRun(gpu, cluster1310.A, cluster1310.leaf, 1e-4, low, fmt, "cluster1310-n32750")
+    assert r.stats["tasks_low"] > 0.9 * r.stats["tasks"]
+    check_split(r, seed=31)
