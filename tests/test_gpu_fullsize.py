@@ -277,7 +277,7 @@ def test_algdecay_split_theta_1e4(gpu, fmt):
     check_split(r, seed=21)
 
 
-@pytest.mark.parametrize("fmt,low", [("bf16", 0.4096), ("fp16", 1.6384)])
+@pytest.mark.parametrize("fmt,low", [("bf16", 0.8192), ("fp16", 3.2768)])
 def test_cluster1310_split_matched_error_point(cluster1310, gpu, fmt, low):
     """cluster1310-n32750 at the split products' matched-error points of the
     benchmark (tau = 1e-4)."""
