@@ -465,6 +465,8 @@ def main() -> int:
                          "split-fp16: FP16 at a per-leaf scale)")
     ap.add_argument("--low-tol", type=float, default=0.8192,
                     help="split precision: absolute LOW threshold on the norm product")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the dense FP32 GEMM context of the same matrix")
     ap.add_argument("--no-sparse", action="store_true",
                     help="skip the epsilon-sparsified tree comparison")
     ap.add_argument("--no-serve", action="store_true",
@@ -598,6 +600,28 @@ def main() -> int:
         out["roofline"] = {
             "bound": "hbm", "achieved": round(gbs, 1) if gbs else None, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4) if gbs else None, "traffic": tb,
+        }
+
+    # ---- context: the dense FP32 product of the same matrix (torch.matmul) ------
+    # the paper's cross-over against SGEMM; not part of the timed step
+    if not args.no_dense and not split:
+        D = torch.empty_like(C)
+        torch.matmul(dA, dA, out=D)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(2):
+            torch.matmul(dA, dA, out=D)
+        ev[1].record()
+        torch.cuda.synchronize()
+        dense_ms = ev[0].elapsed_time(ev[1]) / 2
+        del D
+        spamm_ms = cull_ms + gemm_ms
+        out["dense_fp32_context"] = {
+            "op": "torch.matmul (FP32, rocBLAS/hipBLASLt) of the same n x n matrix",
+            "ms": round(dense_ms, 3), "tflops": round(2.0 * n ** 3 / (dense_ms * 1e-3) / 1e12, 3),
+            "spamm_ms_multiply": round(spamm_ms, 3),
+            "spamm_speedup": round(dense_ms / spamm_ms, 3),
         }
 
     # ---- epsilon-sparsified tree of the same matrix ----------------------------
