@@ -451,7 +451,7 @@ def main() -> int:
     ap.add_argument("--tau", type=float, default=None)
     ap.add_argument("--sample-tiles", type=int, default=96,
                     help="output leaves checked against the dense FP64 product")
-    ap.add_argument("--oracle-tiles", type=int, default=2048,
+    ap.add_argument("--oracle-tiles", type=int, default=3072,
                     help="output leaves computed by the FP64 oracle (CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
