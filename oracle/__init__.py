@@ -131,8 +131,8 @@ def fp16_exponent(S: float) -> int:
 
 
 def fp16_scaled(x: float, e: int) -> float:
-    """x (a float32) times 2^e rounded to the nearest binary16 (ties to even,
-    subnormals kept), times 2^-e."""
+    """x (a float32) times 2^e rounded to the nearest binary16 (ties to even),
+    zero when that falls below binary16's normal range (2^-14), times 2^-e."""
     return float(_load().oracle_fp16_scaled(x, int(e)))
 
 

@@ -36,8 +36,9 @@
  * ties to even) before the (exact, FP64) products; other products are
  * unchanged.  The class is part of the task key (bit 63).  With binary16
  * LOW operands each leaf is scaled by a power of two 2^e fixed by its
- * squared norm before the rounding (11 significant bits, subnormal spacing
- * 2^-24), and the product is scaled back by 2^-(eA + eB).
+ * squared norm before the rounding (11 significant bits; a value that rounds
+ * below binary16's normal range, 2^-14, becomes zero), and the product is
+ * scaled back by 2^-(eA + eB).
  */
 #include <math.h>
 #include <stdint.h>
@@ -214,8 +215,10 @@ int oracle_fp16_exponent(double S)
 
 /* x 2^e rounded to the nearest binary16 value (ties to even), scaled back by
  * 2^-e, as a double (exact).  binary16 keeps 11 significant bits for
- * magnitudes in [2^-14, 2^16) and a fixed spacing 2^-24 below 2^-14; the
- * caller keeps |x 2^e| below 2^15. */
+ * magnitudes in [2^-14, 2^16) and a fixed spacing 2^-24 below 2^-14; a
+ * result below 2^-14 (a subnormal) is flushed to zero, since the matrix
+ * units' products of binary16 subnormals are not exact.  The caller keeps
+ * |x 2^e| below 2^15. */
 double oracle_fp16_scaled(float x, int e)
 {
     double y = ldexp((double)x, e);
@@ -226,6 +229,8 @@ double oracle_fp16_scaled(float x, int e)
     int lead = E - 1 < -14 ? -14 : E - 1;
     double quantum = ldexp(1.0, lead - 10);
     double r = nearbyint(y / quantum) * quantum;   /* default mode: nearest, ties to even */
+    if (fabs(r) < ldexp(1.0, -14))
+        return 0.0;
     return ldexp(r, -e);
 }
 static int is_low(const mul_ctx *x, int t, int64_t I, int64_t K, int64_t J)

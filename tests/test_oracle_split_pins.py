@@ -15,7 +15,8 @@ binary16 LOW operands (per-leaf power-of-two scale):
 * the scale exponent e of a leaf with squared norm S is the one integer with
   4^(13-e) <= S < 4^(14-e), so every entry is below 2^14 once scaled;
 * the rounding equals numpy's float64 -> float16 conversion of x 2^e, on
-  ties, subnormals and scales from 2^-100 to 2^160;
+  ties and scales from 2^-100 to 2^160, with a result below binary16's
+  normal range (2^-14) flushed to zero;
 * a mixed product equals the per-leaf sum of numpy products with each LOW
   leaf rounded through numpy's float16 at its own scale;
 * its error against the unrounded product stays within the per-element
@@ -173,22 +174,29 @@ def test_fp16_rounding_matches_numpy():
         q = 2.0 ** (max(int(np.floor(np.log2(base))), -14) - 10)    # binary16 spacing at base
         cases += [(float(np.float32(base + q / 2)), 0), (float(np.float32(-(base + q / 2))), 0)]
     cases += [(0.0, 5), (float(np.float32(1e-45)), 149), (float(np.float32(1e-45)), 120)]
+    # the boundary: within half a subnormal spacing below 2^-14 rounds up and
+    # stays; one spacing below is a subnormal and becomes zero
+    assert oracle.fp16_scaled(np.float32(2.0 ** -14 - 2.0 ** -26), 0) == 2.0 ** -14
+    assert oracle.fp16_scaled(np.float32(2.0 ** -14 - 2.0 ** -24), 0) == 0.0
+    assert oracle.fp16_scaled(np.float32(-(2.0 ** -14)), 0) == -(2.0 ** -14)
     for x, e in cases:
-        want = float(np.float16(np.float64(np.float32(x)) * 2.0 ** e)) * 2.0 ** -e
+        h = float(np.float16(np.float64(np.float32(x)) * 2.0 ** e))
+        want = (h if abs(h) >= 2.0 ** -14 else 0.0) * 2.0 ** -e
         got = oracle.fp16_scaled(np.float32(x), e)
         assert got == want, (x, e, got, want)
 
 
 def fp16_leaves(P, b, S):
     """P (padded FP32) with every leaf rounded through numpy float16 at the
-    scale exponent of its squared norm."""
+    scale exponent of its squared norm, binary16 subnormals flushed."""
     N = P.shape[0] // b
     R = np.zeros(P.shape)
     for I in range(N):
         for J in range(N):
             e = oracle.fp16_exponent(S[I, J])
             blk = P[I * b:(I + 1) * b, J * b:(J + 1) * b].astype(np.float64) * 2.0 ** e
-            R[I * b:(I + 1) * b, J * b:(J + 1) * b] = blk.astype(np.float16).astype(np.float64) * \
+            h = blk.astype(np.float16).astype(np.float64)
+            R[I * b:(I + 1) * b, J * b:(J + 1) * b] = np.where(np.abs(h) < 2.0 ** -14, 0.0, h) * \
                 2.0 ** -e
     return R
 
@@ -229,8 +237,8 @@ def test_fp16_error_within_rounding_bound_and_below_bf16():
     f16 = oracle.spamm(A, A, b, 0.0, low_tol=low, low_fmt="fp16")
     b16 = oracle.spamm(A, A, b, 0.0, low_tol=low)
     assert f16.Klow == f16.K
-    # per element |fl16(x) - x| <= 2^-11 |x| + 2^-25 2^-e (half the subnormal
-    # spacing, scaled back); propagate through |dA||A| + |A||dA| + |dA||dA|
+    # per element |fl16(x) - x| <= 2^-11 |x| + 2^-14 2^-e (a flushed value is
+    # below 2^-14, scaled back); propagate through |dA||A| + |A||dA| + |dA||dA|
     S = oracle.norms(A, b)[-1]
     N = n // b
     D = np.zeros((n, n))
@@ -238,7 +246,7 @@ def test_fp16_error_within_rounding_bound_and_below_bf16():
         for J in range(N):
             e = oracle.fp16_exponent(S[I, J])
             blk = np.abs(A[I * b:(I + 1) * b, J * b:(J + 1) * b].astype(np.float64))
-            D[I * b:(I + 1) * b, J * b:(J + 1) * b] = 2.0 ** -11 * blk + 2.0 ** (-25 - e)
+            D[I * b:(I + 1) * b, J * b:(J + 1) * b] = 2.0 ** -11 * blk + 2.0 ** (-14 - e)
     Aa = np.abs(A.astype(np.float64))
     bound = D @ Aa + Aa @ D + D @ D
     err16 = np.abs(f16.C - exact.C)
