@@ -108,8 +108,9 @@ int spamm_build_tree(const float *A, int64_t n, int32_t leaf, void *stream,
  *              operands (each FP32 entry rounded to nearest even) or FP16
  *              ones (each leaf times 2^e, e = 14 - ceil(p / 2) where its
  *              squared norm is S = m 2^p with 0.5 <= m < 1, so every scaled
- *              entry is below 2^14; rounded to nearest even, subnormals kept;
- *              the product is scaled back by 2^-(eA + eB)) with FP32
+ *              entry is below 2^14; rounded to nearest even, a result below
+ *              2^-14 (a binary16 subnormal) flushed to zero; the product is
+ *              scaled back by 2^-(eA + eB)) with FP32
  *              accumulation, HIGH products stay FP32.  0 = nothing is LOW.
  *              A relative threshold theta ||A||_F ||B||_F is low_tol =
  *              theta * sqrt(norm2_A) * sqrt(norm2_B) (spamm_tree_info).

@@ -285,9 +285,10 @@ __device__ inline int fp16_scale_exponent(double S)
     return 14 - ((E + 2) >> 1);
 }
 
-// x 2^e (|x 2^e| < 2^14) rounded to binary16, nearest with ties to even,
-// subnormals (spacing 2^-24 below 2^-14) kept; bit pattern.  Integer
-// rounding on the FP32 bits, so it does not depend on the FP16 denormal mode.
+// x 2^e (|x 2^e| < 2^14) rounded to binary16, nearest with ties to even; a
+// result below the normal range (2^-14) is flushed to zero, because the
+// matrix units' products of binary16 subnormals are not exact.  Bit pattern,
+// from integer rounding on the FP32 bits.
 __device__ inline uint16_t to_fp16_scaled(float x, int e)
 {
     const uint32_t u = __float_as_uint(ldexpf(x, e));    // exact: a power-of-two scaling up
@@ -300,16 +301,16 @@ __device__ inline uint16_t to_fp16_scaled(float x, int e)
             h += 1u;                                      // a carry moves to the next binade
         return (uint16_t)(sign | h);
     }
-    if (ef < 102)                                         // below 2^-25: rounds to zero
-        return (uint16_t)sign;
-    // subnormal binary16: value / 2^-24 = sig 2^(ef - 126), sig the 24-bit significand
+    if (ef < 112)                                         // below 2^-15: never reaches 2^-14
+        return 0;
+    // [2^-15, 2^-14): in units of 2^-24, sig 2^(ef - 126) with sig the 24-bit
+    // significand; it stays only if it rounds up to 1024 (= 2^-14, normal)
     const uint32_t sig = (mag & 0x7FFFFFu) | 0x800000u;
-    const int sh = 126 - ef;                              // 14 .. 24
-    uint32_t q = sig >> sh;
-    const uint32_t rest = sig & ((1u << sh) - 1u), half = 1u << (sh - 1);
-    if (rest > half || (rest == half && (q & 1u)))
-        q += 1u;                                          // 1024 encodes 2^-14 exactly
-    return (uint16_t)(sign | q);
+    uint32_t q = sig >> 14;
+    const uint32_t rest = sig & 0x3FFFu;
+    if (rest > 0x2000u || (rest == 0x2000u && (q & 1u)))
+        q += 1u;
+    return q == 1024u ? (uint16_t)(sign | 0x400u) : (uint16_t)0;
 }
 
 // One wave per leaf: both packed FP32 copies (LeafLayout) to FP16

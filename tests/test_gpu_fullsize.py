@@ -204,13 +204,14 @@ def test_largest_grid_n16384_leaf16(gpu):
 
 def round_leaf(X, S, fmt):
     """A leaf block rounded as a LOW operand: bfloat16, or binary16 at the
-    scale exponent of its squared norm S."""
+    scale exponent of its squared norm S (subnormals flushed)."""
     import torch
     if fmt == "bf16":
         return torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(torch.bfloat16).to(
             torch.float64).numpy()
     e = oracle.fp16_exponent(S)
-    return (X * 2.0 ** e).astype(np.float16).astype(np.float64) * 2.0 ** -e
+    h = (X * 2.0 ** e).astype(np.float16).astype(np.float64)
+    return np.where(np.abs(h) < 2.0 ** -14, 0.0, h) * 2.0 ** -e
 
 
 class SplitRun:

@@ -1,0 +1,99 @@
+"""A seeded random sweep of the GPU path against the oracle: odd n (1 .. 700),
+all leaf sizes, tau from 0 to 1e-2, decay rates from dense to nearly
+diagonal, A = B or distinct B, FP32 and both split precisions.
+
+For every case: the sorted task keys (class bit included) bit-exact, kept and
+LOW counts equal, and C within Higham's elementwise bound around the oracle's
+product, built from each class's operands (m = n_b K + 1, one more rounding
+per LOW product with FP16 operands)."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def make_cases(count=36, seed=2024):
+    rng = np.random.default_rng(seed)
+    cases = []
+    for c in range(count):
+        leaf = int(rng.choice([16, 32, 64], p=[0.2, 0.4, 0.4]))
+        n = int(rng.integers(1, 701))
+        prec = "fp32" if leaf == 16 else str(rng.choice(["fp32", "bf16", "fp16"]))
+        cases.append(dict(id=c, n=n, leaf=leaf, prec=prec,
+                          tau=float(rng.choice([0.0, 1e-8, 1e-6, 1e-4, 1e-2])),
+                          rate=float(rng.uniform(0.0, 0.5)), distinct=bool(rng.random() < 0.4),
+                          theta=float(rng.choice([1e-3, 1e-1])), seed=int(rng.integers(1 << 30))))
+    return cases
+
+
+CASES = make_cases()
+
+
+def matrix(n, rate, seed, transpose=False):
+    rng = np.random.default_rng(seed)
+    i = np.arange(n)
+    env = np.exp(-rate * np.abs(i[:, None] - i[None, :]))
+    A = rng.uniform(-1, 1, (n, n)) * env
+    return np.ascontiguousarray((A.T if transpose else A).astype(np.float32))
+
+
+def low_operand(X, S, fmt):
+    if fmt == "bf16":
+        import torch
+        return torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(torch.bfloat16).to(
+            torch.float64).numpy()
+    e = oracle.fp16_exponent(S)
+    h = (X * 2.0 ** e).astype(np.float16).astype(np.float64)
+    return np.where(np.abs(h) < 2.0 ** -14, 0.0, h) * 2.0 ** -e
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"c{c['id']}-n{c['n']}-b{c['leaf']}-{c['prec']}")
+def test_random_case(gpu, case):
+    import torch
+    n, leaf, prec, tau = case["n"], case["leaf"], case["prec"], case["tau"]
+    A = matrix(n, case["rate"], case["seed"])
+    B = matrix(n, case["rate"] * 1.5, case["seed"] + 1, transpose=True) if case["distinct"] else A
+    split = prec != "fp32"
+    sA, sB = oracle.norms(A, leaf), oracle.norms(B, leaf)
+    low = case["theta"] * float(np.sqrt(sA[0][0, 0]) * np.sqrt(sB[0][0, 0])) if split else 0.0
+    ref = oracle.spamm(A, B, leaf, tau, low_tol=low, low_fmt=prec if split else "bf16")
+    dA = torch.from_numpy(A).cuda()
+    kw = dict(bf16=(prec == "bf16"), fp16=(prec == "fp16"))
+    tA = gpu.build_tree(dA, leaf, **kw)
+    tB = tA if B is A else gpu.build_tree(torch.from_numpy(B).cuda(), leaf, **kw)
+    p = {"fp32": gpu.PREC_FP32, "bf16": gpu.PREC_SPLIT_BF16, "fp16": gpu.PREC_SPLIT_FP16}[prec]
+    plan = gpu.symbolic(tA, tB, tau, precision=p, low_tol=low)
+    C = torch.full_like(dA, float("nan"))
+    plan.numeric(C)
+    torch.cuda.synchronize()
+    st = plan.stats()
+    assert np.array_equal(plan.tasks(), ref.keys)
+    assert st["tasks"] == ref.K and st["tasks_low"] == ref.Klow
+    # Higham's bound around the oracle's product
+    d, np_ = oracle.depth(n, leaf)
+    N = 1 << d
+    PA = np.zeros((np_, np_))
+    PB = np.zeros((np_, np_))
+    PA[:n, :n], PB[:n, :n] = A, B
+    inv = {oracle.linear_index(i, j): (i, j) for i in range(N) for j in range(N)}
+    M = np.zeros((np_, np_))
+    cnt = np.zeros((N, N), dtype=np.int64)
+    for key in ref.keys:
+        key = int(key)
+        I, J = inv[(key >> 32) & 0x7FFFFFFF]
+        k = key & 0xFFFFFFFF
+        X = PA[I * leaf:(I + 1) * leaf, k * leaf:(k + 1) * leaf]
+        Y = PB[k * leaf:(k + 1) * leaf, J * leaf:(J + 1) * leaf]
+        if key >> 63:
+            X, Y = low_operand(X, sA[-1][I, k], prec), low_operand(Y, sB[-1][k, J], prec)
+        M[I * leaf:(I + 1) * leaf, J * leaf:(J + 1) * leaf] += np.abs(X) @ np.abs(Y)
+        cnt[I, J] += 1
+    m = (leaf + (1 if prec == "fp16" else 0)) * np.kron(cnt, np.ones((leaf, leaf))) + 1
+    bound = (m * U32 / (1 - m * U32) * M + m * 2.0 ** -126)[:n, :n]
+    got = C.cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(got))
+    assert np.all(np.abs(got - ref.C) <= bound)

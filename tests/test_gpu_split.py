@@ -196,15 +196,17 @@ def test_split_argument_errors(gpu):
 
 def fp16_leaves(P, leaf, S):
     """P (padded FP32) with every leaf rounded through numpy float16 at the
-    scale exponent of its squared norm S[I, J] (oracle.fp16_exponent)."""
+    scale exponent of its squared norm S[I, J] (oracle.fp16_exponent),
+    binary16 subnormals flushed to zero."""
     N = P.shape[0] // leaf
     R = np.zeros(P.shape)
     for I in range(N):
         for J in range(N):
             e = oracle.fp16_exponent(S[I, J])
             blk = P[I * leaf:(I + 1) * leaf, J * leaf:(J + 1) * leaf].astype(np.float64) * 2.0 ** e
+            h = blk.astype(np.float16).astype(np.float64)
             R[I * leaf:(I + 1) * leaf, J * leaf:(J + 1) * leaf] = \
-                blk.astype(np.float16).astype(np.float64) * 2.0 ** -e
+                np.where(np.abs(h) < 2.0 ** -14, 0.0, h) * 2.0 ** -e
     return R
 
 
