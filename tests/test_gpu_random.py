@@ -1,4 +1,4 @@
-"""A seeded random sweep of the GPU path against the oracle: odd n (1 .. 700),
+"""A seeded random sweep of the GPU path against the oracle: odd n (1 .. 1500),
 all leaf sizes, tau from 0 to 1e-2, decay rates from dense to nearly
 diagonal, A = B or distinct B, FP32 and both split precisions.
 
@@ -16,12 +16,12 @@ pytestmark = pytest.mark.gpu
 U32 = 2.0 ** -24
 
 
-def make_cases(count=36, seed=2024):
+def make_cases(count=36, seed=2024, nmax=700, first=0):
     rng = np.random.default_rng(seed)
     cases = []
-    for c in range(count):
+    for c in range(first, first + count):
         leaf = int(rng.choice([16, 32, 64], p=[0.2, 0.4, 0.4]))
-        n = int(rng.integers(1, 701))
+        n = int(rng.integers(1, nmax + 1))
         prec = "fp32" if leaf == 16 else str(rng.choice(["fp32", "bf16", "fp16"]))
         cases.append(dict(id=c, n=n, leaf=leaf, prec=prec,
                           tau=float(rng.choice([0.0, 1e-8, 1e-6, 1e-4, 1e-2])),
@@ -30,7 +30,7 @@ def make_cases(count=36, seed=2024):
     return cases
 
 
-CASES = make_cases()
+CASES = make_cases() + make_cases(count=24, seed=2025, nmax=1500, first=36)
 
 
 def matrix(n, rate, seed, transpose=False):
