@@ -5,7 +5,9 @@ diagonal, A = B or distinct B, FP32 and both split precisions.
 For every case: the sorted task keys (class bit included) bit-exact, kept and
 LOW counts equal, and C within Higham's elementwise bound around the oracle's
 product, built from each class's operands (m = n_b K + 1, one more rounding
-per LOW product with FP16 operands)."""
+per LOW product with FP16 operands).  Also seeded cases of sub-leaf culling
+(performed sub-products against the leaf-32 oracle) and of sparsified trees
+(stored leaves, keys, C bit-identical to the dense product)."""
 import numpy as np
 import pytest
 
@@ -97,3 +99,85 @@ def test_random_case(gpu, case):
     got = C.cpu().numpy().astype(np.float64)
     assert np.all(np.isfinite(got))
     assert np.all(np.abs(got - ref.C) <= bound)
+
+
+# ---- sub-leaf culling and sparsified trees, seeded -------------------------------
+
+def tree_cases(count, seed, first):
+    rng = np.random.default_rng(seed)
+    return [dict(id=c, n=int(rng.integers(1, 1201)), tau=float(rng.choice([0.0, 1e-8, 1e-6, 1e-4, 1e-2])),
+                 rate=float(rng.uniform(0.0, 0.5)), distinct=bool(rng.random() < 0.4),
+                 seed=int(rng.integers(1 << 30)), leaf=int(rng.choice([16, 32, 64])))
+            for c in range(first, first + count)]
+
+
+SUB_CASES = tree_cases(16, 2026, 100)
+SPARSE_CASES = tree_cases(16, 2027, 200)
+
+
+def higham(A, B, leaf, keys, n):
+    d, np_ = oracle.depth(n, leaf)
+    N = 1 << d
+    PA = np.zeros((np_, np_))
+    PB = np.zeros((np_, np_))
+    PA[:n, :n], PB[:n, :n] = np.abs(A), np.abs(B)
+    inv = {oracle.linear_index(i, j): (i, j) for i in range(N) for j in range(N)}
+    M = np.zeros((np_, np_))
+    cnt = np.zeros((N, N), dtype=np.int64)
+    for key in keys:
+        I, J = inv[int(key) >> 32]
+        k = int(key) & 0xFFFFFFFF
+        M[I * leaf:(I + 1) * leaf, J * leaf:(J + 1) * leaf] += \
+            PA[I * leaf:(I + 1) * leaf, k * leaf:(k + 1) * leaf] @ PB[k * leaf:(k + 1) * leaf, J * leaf:(J + 1) * leaf]
+        cnt[I, J] += 1
+    m = leaf * np.kron(cnt, np.ones((leaf, leaf))) + 1
+    return (m * U32 / (1 - m * U32) * M + m * 2.0 ** -126)[:n, :n]
+
+
+@pytest.mark.parametrize("case", SUB_CASES, ids=lambda c: f"sub{c['id']}-n{c['n']}")
+def test_random_subleaf_case(gpu, case):
+    """Leaf 64 with sub-leaf culling: the performed 32 x 32 sub-products equal
+    the leaf-32 oracle's task set, C within the leaf-32 rounding bound."""
+    import torch
+    n, tau = case["n"], case["tau"]
+    A = matrix(n, case["rate"], case["seed"])
+    B = matrix(n, case["rate"] * 1.5, case["seed"] + 1, transpose=True) if case["distinct"] else A
+    ref = oracle.spamm(A, B, 32, tau)
+    dA = torch.from_numpy(A).cuda()
+    tA = gpu.build_tree(dA, 64, subnorms=True)
+    tB = tA if B is A else gpu.build_tree(torch.from_numpy(B).cuda(), 64, subnorms=True)
+    plan = gpu.symbolic(tA, tB, tau, sub_cull=True)
+    C = torch.full_like(dA, float("nan"))
+    plan.numeric(C)
+    torch.cuda.synchronize()
+    assert np.array_equal(plan.subtasks(), ref.keys)
+    assert plan.stats()["subtasks"] == ref.K
+    got = C.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref.C) <= higham(A, B, 32, ref.keys, n))
+
+
+@pytest.mark.parametrize("case", SPARSE_CASES, ids=lambda c: f"sp{c['id']}-n{c['n']}-b{c['leaf']}")
+def test_random_sparse_case(gpu, case):
+    """Epsilon-sparsified operands: stored leaves as the oracle's, task keys
+    equal to the dense oracle product's, C bit-identical to the dense trees'."""
+    import torch
+    n, tau, leaf = case["n"], case["tau"], case["leaf"]
+    A = matrix(n, case["rate"], case["seed"])
+    B = matrix(n, case["rate"] * 1.5, case["seed"] + 1, transpose=True) if case["distinct"] else A
+    nA2 = float(oracle.norms(A, leaf)[0][0, 0])
+    nB2 = float(oracle.norms(B, leaf)[0][0, 0])
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    sA = gpu.build_tree_sparse(dA, leaf, tau, norm2_other=nB2)
+    sB = sA if B is A else gpu.build_tree_sparse(dB, leaf, tau, norm2_other=nA2)
+    _, kA = oracle.sparsify(A, leaf, tau, norm2_other=nB2)
+    assert sA.storage()["stored"] == int(kA.sum())
+    ref = oracle.spamm(A, B, leaf, tau, want_C=False)
+    p = gpu.symbolic(sA, sB, tau)
+    assert np.array_equal(p.tasks(), ref.keys)
+    C1, C2 = torch.empty_like(dA), torch.empty_like(dA)
+    p.numeric(C1)
+    tA = gpu.build_tree(dA, leaf)
+    tB = tA if B is A else gpu.build_tree(dB, leaf)
+    gpu.multiply(tA, tB, tau, C2)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
