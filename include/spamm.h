@@ -211,6 +211,7 @@ int spamm_symbolic(const spamm_tree *A, const spamm_tree *B, double tau,
  * Errors as spamm_symbolic, plus SPAMM_E_INVAL for an unknown precision, a
  * bad low_tol (negative, NaN/Inf, 0 < low_tol < 1e-150), missing 16-bit copies,
  * or sub_cull with split precision, n_b != 64 or trees without sub-norms.
+ * A plan refers to both trees: they must not be freed before the plan.
  */
 int spamm_symbolic_ex(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
                       void *stream, spamm_plan **out);

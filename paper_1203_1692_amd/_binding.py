@@ -196,6 +196,7 @@ class Tree:
 
     def __init__(self, handle: ctypes.c_void_p):
         self._h = handle
+        self._plans = 0       # live plans that read this tree
         n, leaf, depth, nrm = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         _check(load().spamm_tree_info(handle, ctypes.byref(n), ctypes.byref(leaf),
                                       ctypes.byref(depth), ctypes.byref(nrm)), "spamm_tree_info")
@@ -235,6 +236,8 @@ class Tree:
 
     def free(self):
         if self._h is not None:
+            if self._plans:
+                raise ValueError(f"tree is read by {self._plans} live plan(s); free them first")
             _check(load().spamm_tree_free(self._h), "spamm_tree_free")
             self._h = None
 
@@ -251,6 +254,8 @@ class Plan:
     def __init__(self, handle, A: Tree, B: Tree):
         self._h = handle
         self._keep = (A, B)   # the plan reads both trees
+        for t in {id(A): A, id(B): B}.values():
+            t._plans += 1
 
     @property
     def handle(self):
@@ -292,6 +297,8 @@ class Plan:
         if self._h is not None:
             _check(load().spamm_plan_free(self._h), "spamm_plan_free")
             self._h = None
+            for t in {id(t): t for t in self._keep}.values():
+                t._plans -= 1
 
     def __del__(self):
         try:

@@ -255,3 +255,22 @@ def test_bad_arguments_rejected(gpu):
     with pytest.raises(gpu.SpammError) as ei:
         t32.norms(t32.depth + 1)
     assert ei.value.code == gpu.SPAMM_E_INVAL
+
+
+def test_binding_keeps_trees_alive_for_their_plans(gpu):
+    """A tree that a live plan reads cannot be freed through the binding; once
+    the plan is freed it can, and a freed handle is refused."""
+    import torch
+    A = torch.from_numpy(np.eye(100, dtype=np.float32)).cuda()
+    t = gpu.build_tree(A, 32)
+    p = gpu.symbolic(t, t, 0.0)
+    with pytest.raises(ValueError):
+        t.free()
+    C = torch.empty_like(A)
+    p.numeric(C)
+    torch.cuda.synchronize()
+    assert torch.equal(C, A)
+    p.free()
+    t.free()
+    with pytest.raises(ValueError):
+        gpu.symbolic(t, t, 0.0)
