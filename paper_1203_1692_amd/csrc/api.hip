@@ -1,5 +1,5 @@
-// C ABI of libspamm: argument checks, device memory (stream-ordered HIP
-// memory pool), launches and host-side exports.  No computation of the
+// C ABI of libspamm: argument checks, device memory (a stream-ordered pool
+// of the library's own per device), launches and host-side exports.  No computation of the
 // multiply happens here; every step runs in the kernels of norms.hip,
 // cull.hip and gemm.hip.
 #include <math.h>
@@ -57,25 +57,52 @@ int hip_fail(hipError_t e, const char *what)
             return hip_fail(e_, what);            \
     } while (0)
 
-// Keep freed pool memory cached on every device we touch (the default pool
-// would otherwise hand it back to the driver at each synchronization).
+// One stream-ordered memory pool per device, created on first use and owned
+// by the library for the life of the process.  Its release threshold is
+// unbounded so that freed blocks stay cached for the next tree or plan; the
+// device's default pool, which other code in the process may use, is left as
+// it is.
+namespace {
+hipMemPool_t g_pool[64] = {};
+std::mutex g_pool_mu;
+}  // namespace
+
 int prepare_device(int *dev)
 {
-    static std::mutex mu;
-    static bool done[64] = {};
     HIP_TRY(hipGetDevice(dev), "hipGetDevice");
     if (*dev < 0 || *dev >= 64)
         return fail(SPAMM_E_HIP, "device ordinal %d out of range", *dev);
-    std::lock_guard<std::mutex> lock(mu);
-    if (!done[*dev]) {
-        hipMemPool_t pool;
-        HIP_TRY(hipDeviceGetDefaultMemPool(&pool, *dev), "hipDeviceGetDefaultMemPool");
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if (g_pool[*dev] == nullptr) {
+        hipMemPoolProps props;
+        memset(&props, 0, sizeof props);
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = *dev;
+        hipMemPool_t pool = nullptr;
+        HIP_TRY(hipMemPoolCreate(&pool, &props), "hipMemPoolCreate");
         uint64_t thr = UINT64_MAX;
-        HIP_TRY(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr),
-                "hipMemPoolSetAttribute");
-        done[*dev] = true;
+        hipError_t e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        if (e != hipSuccess) {
+            hipMemPoolDestroy(pool);
+            return hip_fail(e, "hipMemPoolSetAttribute");
+        }
+        g_pool[*dev] = pool;
     }
     return SPAMM_OK;
+}
+
+hipError_t dev_alloc_async(int dev, void **ptr, size_t bytes, hipStream_t s)
+{
+    hipMemPool_t pool;
+    {
+        std::lock_guard<std::mutex> lock(g_pool_mu);
+        pool = (dev >= 0 && dev < 64) ? g_pool[dev] : nullptr;
+    }
+    if (pool == nullptr)
+        return hipErrorInvalidDevice;
+    return hipMallocFromPoolAsync(ptr, bytes, pool, s);
 }
 
 double now_us()
@@ -262,7 +289,7 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
     if (arena != nullptr) {
         t->borrowed = true;
     } else {
-        e = hipMallocAsync(&t->block, L.total, s);
+        e = dev_alloc_async(dev, &t->block, L.total, s);
         if (e != hipSuccess)
             t->block = nullptr;
         base = (char *)t->block;
@@ -372,9 +399,9 @@ int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *o
         total += align256(bufs[i].bytes);
     char *base = (char *)arena;
     if (base == nullptr) {
-        hipError_t e = hipMallocAsync((void **)&base, total, s);
+        hipError_t e = dev_alloc_async(dev, (void **)&base, total, s);
         if (e != hipSuccess) {
-            rc = hip_fail(e, "hipMallocAsync (plan)");
+            rc = hip_fail(e, "plan allocation");
             spamm_plan_free(p);
             return rc;
         }
@@ -494,13 +521,13 @@ int spamm_build_tree_sparse(const float *A, int64_t n, int32_t leaf, uint32_t fl
     // scratch: scan partials, then the dense root (8-byte aligned)
     const size_t np_bytes = align256(sizeof(uint32_t) * scan_partials_len(N2));
     void *scratch = nullptr;
-    hipError_t e = hipMallocAsync((void **)&t->norms, sizeof(double) * (size_t)tier_offset(d + 1), s);
+    hipError_t e = dev_alloc_async(dev, (void **)&t->norms, sizeof(double) * (size_t)tier_offset(d + 1), s);
     if (e == hipSuccess)
-        e = hipMallocAsync((void **)&t->keep, sizeof(uint32_t) * N2, s);
+        e = dev_alloc_async(dev, (void **)&t->keep, sizeof(uint32_t) * N2, s);
     if (e == hipSuccess)
-        e = hipMallocAsync((void **)&t->slot, sizeof(uint32_t) * ((size_t)N2 + 1), s);
+        e = dev_alloc_async(dev, (void **)&t->slot, sizeof(uint32_t) * ((size_t)N2 + 1), s);
     if (e == hipSuccess)
-        e = hipMallocAsync(&scratch, np_bytes + sizeof(double), s);
+        e = dev_alloc_async(dev, &scratch, np_bytes + sizeof(double), s);
     double *root_dense_dev = (double *)((char *)scratch + np_bytes);
     if (e == hipSuccess)
         e = launch_sparse_norms(A, n, leaf, d, t->norms, tau, norm2_other, t->keep, t->slot,
@@ -528,13 +555,13 @@ int spamm_build_tree_sparse(const float *A, int64_t n, int32_t leaf, uint32_t fl
     }
     const size_t leaf_bytes = sizeof(float) * (size_t)leaf * (size_t)leaf;
     const size_t cnt = std::max<size_t>(kept, 1);     // keep the pointers valid when empty
-    e = hipMallocAsync((void **)&t->tiles, cnt * leaf_bytes, s);
+    e = dev_alloc_async(dev, (void **)&t->tiles, cnt * leaf_bytes, s);
     if (e == hipSuccess)
-        e = hipMallocAsync((void **)&t->tilesT, cnt * leaf_bytes, s);
+        e = dev_alloc_async(dev, (void **)&t->tilesT, cnt * leaf_bytes, s);
     if (e == hipSuccess && bf16)
-        e = hipMallocAsync((void **)&t->tiles16, cnt * leaf_bytes / 2, s);
+        e = dev_alloc_async(dev, (void **)&t->tiles16, cnt * leaf_bytes / 2, s);
     if (e == hipSuccess && bf16)
-        e = hipMallocAsync((void **)&t->tilesT16, cnt * leaf_bytes / 2, s);
+        e = dev_alloc_async(dev, (void **)&t->tilesT16, cnt * leaf_bytes / 2, s);
     if (e == hipSuccess && kept > 0)
         e = launch_sparse_pack(A, n, leaf, d, t->tiles, t->tilesT, t->tiles16, t->tilesT16, t->keep,
                                t->slot, s);

@@ -16,8 +16,14 @@ int hip_fail(hipError_t e, const char *what);
 // past kMaxDepth tiers).
 int tree_depth(int64_t n, int32_t leaf, int32_t *d, int64_t *np);
 
-// Current device, with the stream-ordered memory pool prepared.
+// Current device, with the library's stream-ordered memory pool for it
+// created (once per device).
 int prepare_device(int *dev);
+
+// Stream-ordered allocation on `s` from the pool of device `dev`, which
+// prepare_device has created (hipErrorInvalidDevice otherwise).  Freed with
+// hipFreeAsync.
+hipError_t dev_alloc_async(int dev, void **ptr, size_t bytes, hipStream_t s);
 
 // Validates and enqueues a tree build on `s` without synchronizing; the
 // root squared norm is copied to *root_dst (pinned host memory, may be null)

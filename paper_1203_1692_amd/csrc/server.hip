@@ -348,7 +348,7 @@ int claim_slot(spamm_server *S, size_t need, hipError_t *err)
         S->arena[big] = nullptr;
         S->cap[big] = 0;
     }
-    hipError_t e = hipMallocAsync(&S->arena[big], need, S->ss[big]);
+    hipError_t e = dev_alloc_async(S->device, &S->arena[big], need, S->ss[big]);
     if (e != hipSuccess) {
         S->arena[big] = nullptr;
         *err = e;
