@@ -17,11 +17,8 @@
 
 namespace spamm {
 hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *tiles,
-                        float *tilesT, uint16_t *t16, uint16_t *tT16, double *norms, bool sub,
-                        hipStream_t s);
-hipError_t launch_pack_fp16(const float *tiles, const float *tilesT, const double *leafn,
-                            uint16_t *t16, uint16_t *tT16, int32_t *scale, int leaf,
-                            uint32_t ntiles, hipStream_t s);
+                        float *tilesT, uint16_t *t16, uint16_t *tT16, int32_t *scale16,
+                        double *norms, bool sub, hipStream_t s);
 hipError_t launch_cull(spamm_plan *p, hipStream_t s);
 hipError_t launch_gemm(const spamm_plan *p, float *C, hipStream_t s);
 }  // namespace spamm
@@ -302,12 +299,9 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
         t->fp16 = fp16;
         t->scale16 = fp16 ? (int32_t *)(base + L.scale16) : nullptr;
         t->norms = (double *)(base + L.norms);
-        // BF16 copies come with the norm pass; FP16 ones need each leaf's norm first
-        e = launch_build(A, n, leaf, d, t->tiles, t->tilesT, bf16 ? t->tiles16 : nullptr,
-                         bf16 ? t->tilesT16 : nullptr, t->norms, sub, s);
-        if (e == hipSuccess && fp16)
-            e = launch_pack_fp16(t->tiles, t->tilesT, t->norms + tier_offset(d), t->tiles16,
-                                 t->tilesT16, t->scale16, leaf, 1u << (2 * d), s);
+        // the 16-bit copies (and FP16 scale exponents) come with the norm pass
+        e = launch_build(A, n, leaf, d, t->tiles, t->tilesT, t->tiles16, t->tilesT16, t->scale16,
+                         t->norms, sub, s);
     }
     if (e == hipSuccess && root_dst != nullptr)
         e = hipMemcpyAsync(root_dst, t->norms, sizeof(double), hipMemcpyDeviceToHost, s);

@@ -48,11 +48,63 @@ __device__ inline void store_bf16x4(uint16_t *dst, float4 v)
     *reinterpret_cast<uint2 *>(dst) = make_uint2(lo, hi);
 }
 
+// ---- FP16 leaf copies (split precision with FP16 LOW operands) ---------------
+// Leaf l is multiplied by 2^e before rounding, e fixed by its squared norm S
+// alone: with S = f 2^E (1 <= f < 2), 4^(13-e) <= S < 4^(14-e) for
+// e = 14 - floor((E + 2) / 2), so every entry (|x| <= sqrt(S)) is below 2^14
+// once scaled.  A zero leaf (never multiplied) gets e = 0.
+__device__ inline int fp16_scale_exponent(double S)
+{
+    if (!(S > 0.0))
+        return 0;
+    const int E = (int)((__double_as_longlong(S) >> 52) & 0x7FF) - 1023;   // S >= 2^-298: normal
+    return 14 - ((E + 2) >> 1);
+}
+
+// x 2^e (|x 2^e| < 2^14) rounded to binary16, nearest with ties to even; a
+// result below the normal range (2^-14) is flushed to zero, because the
+// matrix units' products of binary16 subnormals are not exact.  Bit pattern,
+// from integer rounding on the FP32 bits.
+__device__ inline uint16_t to_fp16_scaled(float x, int e)
+{
+    const uint32_t u = __float_as_uint(ldexpf(x, e));    // exact: a power-of-two scaling up
+    const uint32_t sign = (u >> 16) & 0x8000u, mag = u & 0x7FFFFFFFu;
+    const int ef = (int)(mag >> 23);                      // biased FP32 exponent
+    if (ef >= 113) {                                      // >= 2^-14: normal binary16
+        const uint32_t frac = mag & 0x7FFFFFu, keep = frac >> 13, rest = frac & 0x1FFFu;
+        uint32_t h = ((uint32_t)(ef - 112) << 10) | keep;
+        if (rest > 0x1000u || (rest == 0x1000u && (keep & 1u)))
+            h += 1u;                                      // a carry moves to the next binade
+        return (uint16_t)(sign | h);
+    }
+    if (ef < 112)                                         // below 2^-15: never reaches 2^-14
+        return 0;
+    // [2^-15, 2^-14): in units of 2^-24, sig 2^(ef - 126) with sig the 24-bit
+    // significand; it stays only if it rounds up to 1024 (= 2^-14, normal)
+    const uint32_t sig = (mag & 0x7FFFFFu) | 0x800000u;
+    uint32_t q = sig >> 14;
+    const uint32_t rest = sig & 0x3FFFu;
+    if (rest > 0x2000u || (rest == 0x2000u && (q & 1u)))
+        q += 1u;
+    return q == 1024u ? (uint16_t)(sign | 0x400u) : (uint16_t)0;
+}
+
+// Four consecutive elements x 2^e, rounded to binary16 (8 bytes, aligned).
+__device__ inline void store_fp16x4(uint16_t *dst, float4 v, int e)
+{
+    const uint32_t lo = (uint32_t)to_fp16_scaled(v.x, e) | ((uint32_t)to_fp16_scaled(v.y, e) << 16);
+    const uint32_t hi = (uint32_t)to_fp16_scaled(v.z, e) | ((uint32_t)to_fp16_scaled(v.w, e) << 16);
+    *reinterpret_cast<uint2 *>(dst) = make_uint2(lo, hi);
+}
+
 // Block of 4 waves = the 4 children of one tier-(d-1) node (linear indices
 // 4p .. 4p+3); the block also writes that parent's norm when `parent` != null.
 // Each leaf is stored twice in LeafLayout: as is (left-operand copy) and
 // transposed through LDS (right-operand copy), so that the GEMM reads both of
-// its operands along k with contiguous 16-byte loads.
+// its operands along k with contiguous 16-byte loads.  With tiles16 the two
+// 16-bit copies follow in Leaf16Layout: BF16 from the loads, or, with
+// scale16, FP16 at the leaf's scale, which needs the leaf's norm and so is
+// written from the LDS copy after the norm is known (with its exponent).
 //
 // SUB (n_b = 64, sub-leaf culling): the norms are those of a tree with 32 x 32
 // leaves one tier deeper.  Sub-block (a, b) (rows 32a.., columns 32b..) is
@@ -73,6 +125,7 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
                                                       double *__restrict__ sub_norm,
                                                       const uint32_t *__restrict__ keep,
                                                       const uint32_t *__restrict__ slot,
+                                                      int32_t *__restrict__ scale16,
                                                       uint32_t ntiles)
 {
     static_assert(!SUB || B == 64, "sub-block norms are built for 64 x 64 leaves");
@@ -108,7 +161,7 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
             if (pack) {
                 *reinterpret_cast<float4 *>(tiles + dl * (B * B) + L::index(r, c)) = v[m];
                 if constexpr (B >= 32) {
-                    if (tiles16 != nullptr)
+                    if (tiles16 != nullptr && scale16 == nullptr)
                         store_bf16x4(tiles16 + dl * (B * B) + Leaf16Layout<B>::index(r, c), v[m]);
                 }
             }
@@ -159,6 +212,11 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
     __syncthreads();
     if (pack) {
         float *dstT = tilesT + dl * (B * B);
+        // FP16: the leaf's scale exponent from its norm (s is the same in
+        // every lane of the wave)
+        const int e16 = scale16 != nullptr ? fp16_scale_exponent(s) : 0;
+        if (scale16 != nullptr && lane == 0)
+            scale16[dl] = e16;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int e = 256 * m + 4 * lane;
@@ -167,8 +225,25 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
                                          tr[(ct + 2) * P + rt], tr[(ct + 3) * P + rt]);
             *reinterpret_cast<float4 *>(dstT + L::index(rt, ct)) = t;
             if constexpr (B >= 32) {
-                if (tilesT16 != nullptr)
-                    store_bf16x4(tilesT16 + dl * (B * B) + Leaf16Layout<B>::index(rt, ct), t);
+                if (tilesT16 != nullptr) {
+                    uint16_t *d16 = tilesT16 + dl * (B * B) + Leaf16Layout<B>::index(rt, ct);
+                    if (scale16 != nullptr)
+                        store_fp16x4(d16, t, e16);
+                    else
+                        store_bf16x4(d16, t);
+                }
+            }
+        }
+        if constexpr (B >= 32) {
+            if (scale16 != nullptr && tiles16 != nullptr) {
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const int e = 256 * m + 4 * lane;
+                    const int r = e / B, c = e % B;
+                    const float *row = tr + r * P + c;
+                    store_fp16x4(tiles16 + dl * (B * B) + Leaf16Layout<B>::index(r, c),
+                                 make_float4(row[0], row[1], row[2], row[3]), e16);
+                }
             }
         }
     }
@@ -198,7 +273,7 @@ template <int B, int VEC, bool SUB>
 static hipError_t launch_leaf_v(const float *A, int64_t n, float *tiles, float *tilesT,
                                 uint16_t *t16, uint16_t *tT16, double *leaf, double *parent,
                                 double *sub, const uint32_t *keep, const uint32_t *slot,
-                                uint32_t ntiles, hipStream_t s)
+                                int32_t *scale16, uint32_t ntiles, hipStream_t s)
 {
     constexpr size_t lds = sizeof(float) * 4 * B * (B + 1);
     // once per process (thread-safe static initialization)
@@ -208,7 +283,7 @@ static hipError_t launch_leaf_v(const float *A, int64_t n, float *tiles, float *
     if (attr != hipSuccess)
         return attr;
     hipLaunchKernelGGL((leaf_norm_pack<B, VEC, SUB>), dim3((ntiles + 3) / 4), dim3(256), lds, s, A,
-                       n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep, slot, ntiles);
+                       n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep, slot, scale16, ntiles);
     return hipGetLastError();
 }
 
@@ -216,38 +291,41 @@ template <int B, bool SUB>
 static hipError_t launch_leaf(const float *A, int64_t n, int vec, float *tiles, float *tilesT,
                               uint16_t *t16, uint16_t *tT16, double *leaf, double *parent,
                               double *sub, const uint32_t *keep, const uint32_t *slot,
-                              uint32_t ntiles, hipStream_t s)
+                              int32_t *scale16, uint32_t ntiles, hipStream_t s)
 {
     if (vec == 4)
         return launch_leaf_v<B, 4, SUB>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep,
-                                        slot, ntiles, s);
+                                        slot, scale16, ntiles, s);
     if (vec == 2)
         return launch_leaf_v<B, 2, SUB>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep,
-                                        slot, ntiles, s);
+                                        slot, scale16, ntiles, s);
     return launch_leaf_v<B, 1, SUB>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep, slot,
-                                    ntiles, s);
+                                    scale16, ntiles, s);
 }
 
 static hipError_t launch_leaf_any(const float *A, int64_t n, int leaf, float *tiles,
                                   float *tilesT, uint16_t *t16, uint16_t *tT16, double *leafn,
                                   double *parent, double *subn, const uint32_t *keep,
-                                  const uint32_t *slot, uint32_t ntiles, hipStream_t s)
+                                  const uint32_t *slot, int32_t *scale16, uint32_t ntiles,
+                                  hipStream_t s)
 {
     const uintptr_t addr = reinterpret_cast<uintptr_t>(A);
     const int vec = (n % 4 == 0 && addr % 16 == 0) ? 4 : (n % 2 == 0 && addr % 8 == 0) ? 2 : 1;
+    if (scale16 != nullptr && (t16 == nullptr || tT16 == nullptr || leaf == 16))
+        return hipErrorInvalidValue;
     switch (leaf) {
     case 16:
         return launch_leaf<16, false>(A, n, vec, tiles, tilesT, nullptr, nullptr, leafn, parent,
-                                      nullptr, keep, slot, ntiles, s);
+                                      nullptr, keep, slot, nullptr, ntiles, s);
     case 32:
         return launch_leaf<32, false>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent, nullptr,
-                                      keep, slot, ntiles, s);
+                                      keep, slot, scale16, ntiles, s);
     case 64:
         return subn != nullptr
                    ? launch_leaf<64, true>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent,
-                                           subn, keep, slot, ntiles, s)
+                                           subn, keep, slot, scale16, ntiles, s)
                    : launch_leaf<64, false>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent,
-                                            nullptr, keep, slot, ntiles, s);
+                                            nullptr, keep, slot, scale16, ntiles, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -255,8 +333,8 @@ static hipError_t launch_leaf_any(const float *A, int64_t n, int leaf, float *ti
 // sub (n_b = 64 only): norms hold tiers 0..depth+1, tier depth+1 being the
 // 32 x 32 sub-blocks; otherwise tiers 0..depth.  tiles == null: norms only.
 hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *tiles,
-                        float *tilesT, uint16_t *t16, uint16_t *tT16, double *norms, bool sub,
-                        hipStream_t s)
+                        float *tilesT, uint16_t *t16, uint16_t *tT16, int32_t *scale16,
+                        double *norms, bool sub, hipStream_t s)
 {
     const uint32_t ntiles = 1u << (2 * depth);
     double *leafn = norms + tier_offset(depth);
@@ -265,103 +343,10 @@ hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *t
     if (sub && leaf != 64)
         return hipErrorInvalidValue;
     hipError_t e = launch_leaf_any(A, n, leaf, tiles, tilesT, t16, tT16, leafn, parent, subn,
-                                   nullptr, nullptr, ntiles, s);
+                                   nullptr, nullptr, scale16, ntiles, s);
     if (e != hipSuccess || depth < 2)
         return e;
     hipLaunchKernelGGL(norm_pyramid, dim3(1), dim3(1024), 0, s, norms, depth - 1);
-    return hipGetLastError();
-}
-
-// ---- FP16 leaf copies (split precision with FP16 LOW operands) ---------------
-// Leaf l is multiplied by 2^e before rounding, e fixed by its squared norm S
-// alone: with S = f 2^E (1 <= f < 2), 4^(13-e) <= S < 4^(14-e) for
-// e = 14 - floor((E + 2) / 2), so every entry (|x| <= sqrt(S)) is below 2^14
-// once scaled.  A zero leaf (never multiplied) gets e = 0.
-__device__ inline int fp16_scale_exponent(double S)
-{
-    if (!(S > 0.0))
-        return 0;
-    const int E = (int)((__double_as_longlong(S) >> 52) & 0x7FF) - 1023;   // S >= 2^-298: normal
-    return 14 - ((E + 2) >> 1);
-}
-
-// x 2^e (|x 2^e| < 2^14) rounded to binary16, nearest with ties to even; a
-// result below the normal range (2^-14) is flushed to zero, because the
-// matrix units' products of binary16 subnormals are not exact.  Bit pattern,
-// from integer rounding on the FP32 bits.
-__device__ inline uint16_t to_fp16_scaled(float x, int e)
-{
-    const uint32_t u = __float_as_uint(ldexpf(x, e));    // exact: a power-of-two scaling up
-    const uint32_t sign = (u >> 16) & 0x8000u, mag = u & 0x7FFFFFFFu;
-    const int ef = (int)(mag >> 23);                      // biased FP32 exponent
-    if (ef >= 113) {                                      // >= 2^-14: normal binary16
-        const uint32_t frac = mag & 0x7FFFFFu, keep = frac >> 13, rest = frac & 0x1FFFu;
-        uint32_t h = ((uint32_t)(ef - 112) << 10) | keep;
-        if (rest > 0x1000u || (rest == 0x1000u && (keep & 1u)))
-            h += 1u;                                      // a carry moves to the next binade
-        return (uint16_t)(sign | h);
-    }
-    if (ef < 112)                                         // below 2^-15: never reaches 2^-14
-        return 0;
-    // [2^-15, 2^-14): in units of 2^-24, sig 2^(ef - 126) with sig the 24-bit
-    // significand; it stays only if it rounds up to 1024 (= 2^-14, normal)
-    const uint32_t sig = (mag & 0x7FFFFFu) | 0x800000u;
-    uint32_t q = sig >> 14;
-    const uint32_t rest = sig & 0x3FFFu;
-    if (rest > 0x2000u || (rest == 0x2000u && (q & 1u)))
-        q += 1u;
-    return q == 1024u ? (uint16_t)(sign | 0x400u) : (uint16_t)0;
-}
-
-// One wave per leaf: both packed FP32 copies (LeafLayout) to FP16
-// (Leaf16Layout) at the leaf's scale, and the scale exponent itself.
-template <int B>
-__global__ __launch_bounds__(256) void pack_fp16(const float *__restrict__ tiles,
-                                                 const float *__restrict__ tilesT,
-                                                 const double *__restrict__ leafn,
-                                                 uint16_t *__restrict__ t16,
-                                                 uint16_t *__restrict__ tT16,
-                                                 int32_t *__restrict__ scale, uint32_t ntiles)
-{
-    const uint32_t l = blockIdx.x * 4u + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (l >= ntiles)
-        return;
-    const int e = fp16_scale_exponent(leafn[l]);
-    if (lane == 0)
-        scale[l] = e;
-    const int64_t base = (int64_t)l * (B * B);
-    for (int idx = lane; idx < B * B / 4; idx += 64) {
-        const int r = idx / (B / 4), c = 4 * (idx % (B / 4));
-        const int src = LeafLayout<B>::index(r, c), dst = Leaf16Layout<B>::index(r, c);
-#pragma unroll
-        for (int copy = 0; copy < 2; ++copy) {
-            const float4 v = *reinterpret_cast<const float4 *>((copy ? tilesT : tiles) + base + src);
-            const uint32_t lo = (uint32_t)to_fp16_scaled(v.x, e) |
-                                ((uint32_t)to_fp16_scaled(v.y, e) << 16);
-            const uint32_t hi = (uint32_t)to_fp16_scaled(v.z, e) |
-                                ((uint32_t)to_fp16_scaled(v.w, e) << 16);
-            *reinterpret_cast<uint2 *>((copy ? tT16 : t16) + base + dst) = make_uint2(lo, hi);
-        }
-    }
-}
-
-hipError_t launch_pack_fp16(const float *tiles, const float *tilesT, const double *leafn,
-                            uint16_t *t16, uint16_t *tT16, int32_t *scale, int leaf,
-                            uint32_t ntiles, hipStream_t s)
-{
-    const dim3 grid((ntiles + 3) / 4);
-    switch (leaf) {
-    case 32:
-        hipLaunchKernelGGL(pack_fp16<32>, grid, dim3(256), 0, s, tiles, tilesT, leafn, t16, tT16,
-                           scale, ntiles);
-        break;
-    case 64:
-        hipLaunchKernelGGL(pack_fp16<64>, grid, dim3(256), 0, s, tiles, tilesT, leafn, t16, tT16,
-                           scale, ntiles);
-        break;
-    default: return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 
@@ -396,8 +381,8 @@ hipError_t launch_sparse_norms(const float *A, int64_t n, int leaf, int depth, d
                                uint32_t *partials, double *root_dense, hipStream_t s)
 {
     const uint32_t ntiles = 1u << (2 * depth);
-    hipError_t e = launch_build(A, n, leaf, depth, nullptr, nullptr, nullptr, nullptr, norms,
-                                false, s);
+    hipError_t e = launch_build(A, n, leaf, depth, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                norms, false, s);
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(drop_leaves, dim3((ntiles + 255) / 256), dim3(256), 0, s,
@@ -420,7 +405,7 @@ hipError_t launch_sparse_pack(const float *A, int64_t n, int leaf, int depth, fl
                               const uint32_t *slot, hipStream_t s)
 {
     return launch_leaf_any(A, n, leaf, tiles, tilesT, t16, tT16, nullptr, nullptr, nullptr, keep,
-                           slot, 1u << (2 * depth), s);
+                           slot, nullptr, 1u << (2 * depth), s);
 }
 
 }  // namespace spamm
