@@ -188,6 +188,19 @@ int spamm_tree_norms(const spamm_tree *tree, int32_t tier, double *host, size_t 
  * same matrix.  Synchronizes. */
 int spamm_tree_matrix(const spamm_tree *tree, int32_t copy, float *host, size_t len);
 
+/* Copy the 16-bit leaf copies of a tree built with SPAMM_TREE_BF16 or
+ * SPAMM_TREE_FP16 (the LOW operands of split precision, Sec. VI outlook) to
+ * host memory as an n_p x n_p row-major array of raw bit patterns (len >=
+ * n_p^2), copy 0 or 1 as in spamm_tree_matrix.  BF16: element (i, j) is
+ * x_ij rounded to bfloat16.  FP16: element (i, j) is x_ij 2^e rounded to
+ * binary16 (nearest even, a result below 2^-14 flushed to zero), e the
+ * exponent of its leaf; `scale` (may be NULL, else scale_len >= N^2 for N
+ * leaves per dimension) receives the exponents, leaf (I, J) at I N + J.
+ * SPAMM_E_INVAL when the tree has no 16-bit copies, SPAMM_E_RANGE for short
+ * buffers.  Synchronizes the tree's stream. */
+int spamm_tree_matrix16(const spamm_tree *tree, int32_t copy, uint16_t *host, size_t len,
+                        int32_t *scale, size_t scale_len);
+
 /* ---- symbolic / numeric multiply (Alg. 1: collect products, then multiply) -- */
 
 /*

@@ -135,6 +135,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
                             ctypes.POINTER(dbl)],
         "spamm_tree_norms": [vp, i32, vp, sz],
         "spamm_tree_matrix": [vp, i32, vp, sz],
+        "spamm_tree_matrix16": [vp, i32, vp, sz, vp, sz],
         "spamm_symbolic": [vp, vp, dbl, vp, pp],
         "spamm_numeric": [vp, vp, vp],
         "spamm_plan_tasks": [vp, vp, sz, ctypes.POINTER(sz)],
@@ -226,6 +227,19 @@ class Tree:
         _check(load().spamm_tree_matrix(self.handle, copy, out.ctypes.data, out.size),
                "spamm_tree_matrix")
         return out
+
+    def matrix16(self, copy: int = 0):
+        """The 16-bit leaf copies as raw bit patterns (uint16, n_p x n_p) and,
+        for FP16 copies, the leaves' scale exponents (int32, N x N; else
+        None)."""
+        out = np.empty((self.np, self.np), dtype=np.uint16)
+        N = self.np // self.leaf
+        scale = np.empty((N, N), dtype=np.int32) if getattr(self, "fp16", False) else None
+        _check(load().spamm_tree_matrix16(self.handle, copy, out.ctypes.data, out.size,
+                                          None if scale is None else scale.ctypes.data,
+                                          0 if scale is None else scale.size),
+               "spamm_tree_matrix16")
+        return out, scale
 
     def storage(self) -> dict:
         """Leaves stored, leaves in the grid, device bytes held."""

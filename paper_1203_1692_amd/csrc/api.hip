@@ -693,6 +693,62 @@ int spamm_tree_matrix(const spamm_tree *t, int32_t copy, float *host, size_t len
     return SPAMM_OK;
 }
 
+int spamm_tree_matrix16(const spamm_tree *t, int32_t copy, uint16_t *host, size_t len,
+                        int32_t *scale, size_t scale_len)
+{
+    if (t == nullptr || host == nullptr)
+        return fail(SPAMM_E_INVAL, "NULL argument");
+    if (copy != 0 && copy != 1)
+        return fail(SPAMM_E_INVAL, "copy = %d not in {0, 1}", copy);
+    if (t->tiles16 == nullptr)
+        return fail(SPAMM_E_INVAL, "the tree holds no 16-bit leaf copies");
+    const int64_t np = t->np, b = t->leaf, N = int64_t(1) << t->depth;
+    if (len < (size_t)(np * np))
+        return fail(SPAMM_E_RANGE, "host buffer holds %zu < %lld values", len, (long long)(np * np));
+    if (scale != nullptr && t->scale16 != nullptr && scale_len < (size_t)(N * N))
+        return fail(SPAMM_E_RANGE, "scale buffer holds %zu < %lld values", scale_len,
+                    (long long)(N * N));
+    const bool sparse = t->slot != nullptr;
+    std::vector<uint16_t> tiles((size_t)(t->stored * b * b));
+    std::vector<int32_t> sc(t->scale16 != nullptr ? (size_t)(N * N) : 0);
+    std::vector<uint32_t> slot(sparse ? (size_t)(N * N) : 0), keep(sparse ? (size_t)(N * N) : 0);
+    if (!tiles.empty())
+        HIP_TRY(hipMemcpyAsync(tiles.data(), copy == 0 ? t->tiles16 : t->tilesT16,
+                               sizeof(uint16_t) * tiles.size(), hipMemcpyDeviceToHost, t->stream),
+                "hipMemcpyAsync");
+    if (!sc.empty())
+        HIP_TRY(hipMemcpyAsync(sc.data(), t->scale16, sizeof(int32_t) * sc.size(),
+                               hipMemcpyDeviceToHost, t->stream),
+                "hipMemcpyAsync");
+    if (sparse) {
+        HIP_TRY(hipMemcpyAsync(slot.data(), t->slot, sizeof(uint32_t) * slot.size(),
+                               hipMemcpyDeviceToHost, t->stream),
+                "hipMemcpyAsync");
+        HIP_TRY(hipMemcpyAsync(keep.data(), t->keep, sizeof(uint32_t) * keep.size(),
+                               hipMemcpyDeviceToHost, t->stream),
+                "hipMemcpyAsync");
+    }
+    HIP_TRY(hipStreamSynchronize(t->stream), "hipStreamSynchronize");
+    const std::vector<uint16_t> zero((size_t)(b * b), 0);
+    for (int64_t l = 0; l < N * N; ++l) {
+        const int64_t I = lin_row((uint32_t)l), J = lin_col((uint32_t)l);
+        const uint16_t *src = !sparse ? tiles.data() + l * b * b
+                              : keep[(size_t)l] ? tiles.data() + (int64_t)slot[(size_t)l] * b * b
+                                                : zero.data();
+        for (int r = 0; r < (int)b; ++r)
+            for (int c = 0; c < (int)b; ++c) {
+                const int idx = b == 32 ? Leaf16Layout<32>::index(r, c) : Leaf16Layout<64>::index(r, c);
+                if (copy == 0)
+                    host[(I * b + r) * np + J * b + c] = src[idx];
+                else
+                    host[(I * b + c) * np + J * b + r] = src[idx];
+            }
+        if (scale != nullptr && !sc.empty())
+            scale[I * N + J] = sc[(size_t)l];
+    }
+    return SPAMM_OK;
+}
+
 int spamm_plan_free(spamm_plan *p)
 {
     if (p == nullptr)

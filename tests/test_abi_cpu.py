@@ -96,6 +96,7 @@ def test_newer_entry_points_check_arguments_on_the_host():
                                        ctypes.byref(h)) == sp.SPAMM_E_INVAL
     # NULL handles
     assert lib.spamm_tree_storage(None, None, None, None) == sp.SPAMM_E_INVAL
+    assert lib.spamm_tree_matrix16(None, 0, None, 0, None, 0) == sp.SPAMM_E_INVAL
     cnt = ctypes.c_size_t()
     assert lib.spamm_plan_subtasks(None, None, 0, ctypes.byref(cnt)) == sp.SPAMM_E_INVAL
     assert lib.spamm_plan_stats(None, None) == sp.SPAMM_E_INVAL
