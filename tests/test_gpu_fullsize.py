@@ -200,6 +200,28 @@ def test_largest_grid_n16384_leaf16(gpu):
     assert ei.value.code == gpu.SPAMM_E_RANGE
 
 
+def test_largest_order_n65536_leaf64(gpu):
+    """The largest order the library takes at n_b = 64: n = 65536 (N = 1024,
+    n^2 = 2^32 elements, so every element offset needs 64-bit arithmetic);
+    every norm tier and the whole task set bit-exact, C on sampled leaves
+    (zero leaves where nothing is kept included)."""
+    import torch
+    A = workloads.exp_decay(65536, 0.5, 4)
+    r = MatrixRun(gpu, A, 64, 1e-6, "expdecay0.5-n65536-leaf64")
+    assert r.tree.depth == 10
+    check_norms(r)
+    ref = oracle.spamm(r.A, r.A, 64, r.tau, want_C=False)
+    assert r.stats["kept"] == [int(v) for v in ref.Kt]
+    assert np.array_equal(r.keys, ref.keys)
+    check_sampled_product(r, seed=4)
+    # the last element, written once, equals the oracle's
+    Ct, _, _ = oracle.spamm_tiles(r.A, r.A, 64, r.tau, [(1023, 1023)], threads=16,
+                                  want_klists=True)
+    assert abs(float(r.C[-1, -1]) - Ct[0][-1, -1]) <= 1e-5 * r.tree.norm2
+    del r
+    torch.cuda.empty_cache()
+
+
 # ---- split precision at full size -------------------------------------------
 
 def round_leaf(X, S, fmt):
