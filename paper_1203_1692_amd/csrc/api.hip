@@ -171,7 +171,8 @@ static int plan_bufs(spamm_plan *p, const PlanSizes &z, bool split, bool sub, Pl
     out[k++] = {(void **)&p->partials, z.partials};
     out[k++] = {(void **)&p->browptr, z.browptr};
     out[k++] = {(void **)&p->bent, z.bent};
-    out[k++] = {(void **)&p->leafK, 4 * sizeof(uint64_t)};
+    // [0] HIGH, [1] LOW leaf products, [2] sub-products, [3]/[4] the roots
+    out[k++] = {(void **)&p->leafK, 5 * sizeof(uint64_t)};
     if (split) {
         out[k++] = {(void **)&p->browptr_lo, z.browptr};
         out[k++] = {(void **)&p->bent_lo, z.bent};

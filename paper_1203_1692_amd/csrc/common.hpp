@@ -220,7 +220,8 @@ struct spamm_plan {
     uint32_t *bent;
     uint32_t *browptr_lo;   // LOW (BF16) products, split precision only
     uint32_t *bent_lo;
-    uint64_t *leafK;        // [0] kept leaf triples, [1] of which LOW, [2] sub-products done
+    uint64_t *leafK;        // [0] HIGH, [1] LOW kept leaf products, [2] sub-products done,
+                            // [3], [4] ||A||_F^2, ||B||_F^2 (FP64 bits, written by the cull)
     uint8_t *submask;       // sub-leaf culling: 4 bytes per leaf-tier entry, else null
     int32_t sub;            // sub-leaf culling in the numeric multiply
     int64_t nblocks;

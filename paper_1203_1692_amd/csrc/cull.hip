@@ -36,6 +36,8 @@ __global__ void cull_root(const double *__restrict__ nA, const double *__restric
     if (threadIdx.x != 0 || blockIdx.x != 0)
         return;
     const uint32_t kept = keep_pair(nA[0], nB[0], T2) ? 1u : 0u;
+    reinterpret_cast<double *>(leafK)[3] = nA[0];
+    reinterpret_cast<double *>(leafK)[4] = nB[0];
     if (last) {
         // d = 0: the root is the only leaf
         const uint32_t low = (kept && low_pair(nA[0], nB[0], L2)) ? 1u : 0u;
@@ -44,6 +46,7 @@ __global__ void cull_root(const double *__restrict__ nA, const double *__restric
         if (kept & ~low)
             bent[0] = 0u | (1u << 16);
         leafK[0] = kept & ~low;
+        leafK[1] = 0;
         if (browptr_lo != nullptr) {
             browptr_lo[0] = 0;
             browptr_lo[1] = low;
@@ -55,7 +58,7 @@ __global__ void cull_root(const double *__restrict__ nA, const double *__restric
         rowptr0[0] = 0;
         rowptr0[1] = kept;
         list0[0] = 0;
-        *leafK = 0;
+        leafK[0] = leafK[1] = 0;
     }
 }
 
@@ -299,27 +302,6 @@ __global__ __launch_bounds__(256) void cull_emit_leaf(const double *__restrict__
     }
 }
 
-// Sum of m uint32 values into one uint64 (single workgroup).
-__global__ __launch_bounds__(1024) void reduce_tasks(const uint32_t *__restrict__ in, uint32_t m,
-                                                     uint64_t *__restrict__ out)
-{
-    __shared__ uint64_t part[1024 / kWave];
-    uint64_t s = 0;
-    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x)
-        s += in[i];
-    for (int o = 32; o > 0; o >>= 1)
-        s += __shfl_xor(s, o);
-    if ((threadIdx.x & 63) == 0)
-        part[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t t = 0;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i)
-            t += part[i];
-        *out = t;
-    }
-}
-
 // ---- exclusive scan of uint32 counts: out[0..m) prefix, out[m] = total -------
 constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 4;
@@ -370,8 +352,8 @@ __global__ __launch_bounds__(kScanThreads) void scan_chunk_sums(const uint32_t *
 
 // Single workgroup: exclusive scan of in[0..m) (m <= kScanChunk per pass, loops
 // otherwise) into out; out[m] = total.
-__global__ __launch_bounds__(kScanThreads) void scan_single(const uint32_t *__restrict__ in, uint32_t m,
-                                                            uint32_t *__restrict__ out)
+__device__ inline void block_exclusive_scan(const uint32_t *__restrict__ in, uint32_t m,
+                                            uint32_t *__restrict__ out)
 {
     uint32_t carry = 0;
     for (int64_t c0 = 0; c0 < m; c0 += kScanChunk) {
@@ -392,6 +374,55 @@ __global__ __launch_bounds__(kScanThreads) void scan_single(const uint32_t *__re
     }
     if (threadIdx.x == 0)
         out[m] = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_single(const uint32_t *__restrict__ in, uint32_t m,
+                                                            uint32_t *__restrict__ out)
+{
+    block_exclusive_scan(in, m, out);
+}
+
+// Single workgroup: sum of in[0..m) (returned to thread 0).
+__device__ inline uint64_t block_sum(const uint32_t *__restrict__ in, uint32_t m)
+{
+    __shared__ uint64_t part[kScanThreads / kWave];
+    uint64_t s = 0;
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x)
+        s += in[i];
+    for (int o = 32; o > 0; o >>= 1)
+        s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    uint64_t t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i)
+            t += part[i];
+    __syncthreads();   // part may be reused by the caller's next call
+    return t;
+}
+
+// Leaf tier with few parent tiles (np <= 4 kScanChunk), one workgroup: the
+// block row pointers from the HIGH (and, with browptr_lo, LOW) entry counts
+// of cull_count_leaf, and the kept leaf products of each class into leafK.
+// Replaces two to four launches of the general path for small products.
+__global__ __launch_bounds__(kScanThreads) void leaf_scan_totals(const uint32_t *__restrict__ counts,
+                                                                 uint32_t np,
+                                                                 uint32_t *__restrict__ browptr,
+                                                                 uint32_t *__restrict__ browptr_lo,
+                                                                 uint64_t *__restrict__ leafK)
+{
+    block_exclusive_scan(counts, np, browptr);
+    const uint64_t hi = block_sum(counts + np, np);
+    uint64_t lo = 0;
+    if (browptr_lo != nullptr) {
+        block_exclusive_scan(counts + 2 * (size_t)np, np, browptr_lo);
+        lo = block_sum(counts + 3 * (size_t)np, np);
+    }
+    if (threadIdx.x == 0) {
+        leafK[0] = hi;
+        leafK[1] = lo;
+    }
 }
 
 __global__ __launch_bounds__(kScanThreads) void scan_chunks(const uint32_t *__restrict__ in, uint32_t m,
@@ -438,7 +469,9 @@ __global__ __launch_bounds__(kScanThreads) void cull_top(const double *__restric
         rowptr[0] = 0;
         rowptr[1] = keep_pair(nA[0], nB[0], T2) ? 1u : 0u;
         list0[0] = 0;
-        *leafK = 0;
+        leafK[0] = leafK[1] = 0;
+        reinterpret_cast<double *>(leafK)[3] = nA[0];
+        reinterpret_cast<double *>(leafK)[4] = nB[0];
     }
     __syncthreads();
     for (int t = 1; t <= top; ++t) {
@@ -497,6 +530,15 @@ hipError_t launch_scan_u32(const uint32_t *in, uint32_t m, uint32_t *out, uint32
 
 size_t scan_partials_len(uint32_t m) { return (m + kScanChunk - 1) / kScanChunk + 1; }
 
+// Sum of m uint32 values into one uint64 (single workgroup).
+__global__ __launch_bounds__(kScanThreads) void reduce_tasks(const uint32_t *__restrict__ in,
+                                                             uint32_t m, uint64_t *__restrict__ out)
+{
+    const uint64_t t = block_sum(in, m);
+    if (threadIdx.x == 0)
+        *out = t;
+}
+
 hipError_t launch_cull(spamm_plan *p, hipStream_t s)
 {
     const int d = p->depth;
@@ -530,37 +572,51 @@ hipError_t launch_cull(spamm_plan *p, hipStream_t s)
                 return e;
             hipLaunchKernelGGL(cull_emit, grid, block, 0, s, tA, tB, p->T2, prow, plist, np,
                                (const uint32_t *)crow, p->list[t & 1]);
-        } else if (!split) {
-            hipLaunchKernelGGL(cull_count_leaf<false>, grid, block, 0, s, tA, tB, p->T2, 0.0, prow,
-                               plist, np, p->counts);
-            hipLaunchKernelGGL(reduce_tasks, dim3(1), dim3(1024), 0, s, p->counts + np, np, p->leafK);
-            if ((e = hipGetLastError()) != hipSuccess)
-                return e;
-            if ((e = launch_scan_u32(p->counts, np, p->browptr, p->partials, s)) != hipSuccess)
-                return e;
-            hipLaunchKernelGGL(cull_emit_leaf<false>, grid, block, 0, s, tA, tB, p->T2, 0.0, prow,
-                               plist, np, (const uint32_t *)p->browptr, p->bent,
-                               (const uint32_t *)nullptr, (uint32_t *)nullptr);
         } else {
-            hipLaunchKernelGGL(cull_count_leaf<true>, grid, block, 0, s, tA, tB, p->T2, p->L2, prow,
-                               plist, np, p->counts);
-            hipLaunchKernelGGL(reduce_tasks, dim3(1), dim3(1024), 0, s, p->counts + np, np, p->leafK);
-            hipLaunchKernelGGL(reduce_tasks, dim3(1), dim3(1024), 0, s, p->counts + 3 * np, np,
-                               p->leafK + 1);
+            if (split)
+                hipLaunchKernelGGL(cull_count_leaf<true>, grid, block, 0, s, tA, tB, p->T2, p->L2,
+                                   prow, plist, np, p->counts);
+            else
+                hipLaunchKernelGGL(cull_count_leaf<false>, grid, block, 0, s, tA, tB, p->T2, 0.0,
+                                   prow, plist, np, p->counts);
             if ((e = hipGetLastError()) != hipSuccess)
                 return e;
-            if ((e = launch_scan_u32(p->counts, np, p->browptr, p->partials, s)) != hipSuccess)
-                return e;
-            if ((e = launch_scan_u32(p->counts + 2 * np, np, p->browptr_lo, p->partials, s)) != hipSuccess)
-                return e;
-            hipLaunchKernelGGL(cull_emit_leaf<true>, grid, block, 0, s, tA, tB, p->T2, p->L2, prow,
-                               plist, np, (const uint32_t *)p->browptr, p->bent,
-                               (const uint32_t *)p->browptr_lo, p->bent_lo);
+            if (np <= (uint32_t)kScanChunk * 4) {
+                // row pointers and totals in one workgroup
+                hipLaunchKernelGGL(leaf_scan_totals, dim3(1), dim3(kScanThreads), 0, s, p->counts,
+                                   np, p->browptr, split ? p->browptr_lo : (uint32_t *)nullptr,
+                                   p->leafK);
+                if ((e = hipGetLastError()) != hipSuccess)
+                    return e;
+            } else {
+                hipLaunchKernelGGL(reduce_tasks, dim3(1), dim3(kScanThreads), 0, s, p->counts + np,
+                                   np, p->leafK);
+                if (split)
+                    hipLaunchKernelGGL(reduce_tasks, dim3(1), dim3(kScanThreads), 0, s,
+                                       p->counts + 3 * (size_t)np, np, p->leafK + 1);
+                if ((e = hipGetLastError()) != hipSuccess)
+                    return e;
+                if ((e = launch_scan_u32(p->counts, np, p->browptr, p->partials, s)) != hipSuccess)
+                    return e;
+                if (split && (e = launch_scan_u32(p->counts + 2 * (size_t)np, np, p->browptr_lo,
+                                                  p->partials, s)) != hipSuccess)
+                    return e;
+            }
+            if (split)
+                hipLaunchKernelGGL(cull_emit_leaf<true>, grid, block, 0, s, tA, tB, p->T2, p->L2,
+                                   prow, plist, np, (const uint32_t *)p->browptr, p->bent,
+                                   (const uint32_t *)p->browptr_lo, p->bent_lo);
+            else
+                hipLaunchKernelGGL(cull_emit_leaf<false>, grid, block, 0, s, tA, tB, p->T2, 0.0,
+                                   prow, plist, np, (const uint32_t *)p->browptr, p->bent,
+                                   (const uint32_t *)nullptr, (uint32_t *)nullptr);
         }
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
-    return hipSuccess;   // leafK[0] = HIGH leaf products, leafK[1] = LOW ones (split)
+    // leafK[0] = HIGH leaf products, leafK[1] = LOW ones (0 without split),
+    // leafK[3], leafK[4] = the roots ||A||_F^2, ||B||_F^2 (FP64 bit patterns)
+    return hipSuccess;
 }
 
 }  // namespace spamm

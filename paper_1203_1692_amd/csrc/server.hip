@@ -43,9 +43,15 @@ constexpr size_t kMaxQueue = 65536;
 // the stream is full wait and join the next batch.
 constexpr int kInflightBatches = 2;
 
+struct StepOut {                   // one step's cull readback: its plan's leafK[0..5)
+    uint64_t K[2];                 // HIGH / LOW leaf products
+    uint64_t sub;                  // (sub-leaf products; not used by the server)
+    double root[2];                // ||X_s||_F^2 of the step's left and right trees
+};
+static_assert(sizeof(StepOut) == 5 * sizeof(uint64_t), "plan leafK layout");
+
 struct Pinned {                    // per-slot readbacks (host-visible)
-    double root[kMaxChain][2];     // ||X_s||_F^2 of each step's tree(s)
-    uint64_t K[kMaxChain][2];      // HIGH / LOW leaf products of each step
+    StepOut step[kMaxChain];
 };
 
 struct Job {
@@ -147,17 +153,15 @@ int start_step(spamm_server *S, Active &a)
     Pinned &P = S->pin[a.slot];
     const spamm_request &r = a.job.rq;
     const uint32_t flags = tree_flags_for(r.precision);
-    P.root[a.step][1] = 0.0;
-    P.K[a.step][1] = 0;
     // arena: [tree of A or X_s][tree of B, step 0 only][plan]
     char *base = (char *)S->arena[a.slot];
     const size_t tb = tree_device_bytes(r.n, r.leaf, flags);
-    int rc = tree_build_async(a.step == 0 ? r.A : r.C, r.n, r.leaf, flags, ss,
-                              &P.root[a.step][0], &a.tA, base);
+    int rc = tree_build_async(a.step == 0 ? r.A : r.C, r.n, r.leaf, flags, ss, nullptr, &a.tA,
+                              base);
     if (rc)
         return rc;
     if (a.step == 0 && a.distinctB) {
-        if ((rc = tree_build_async(r.B, r.n, r.leaf, flags, ss, &P.root[0][1], &a.tB, base + tb)))
+        if ((rc = tree_build_async(r.B, r.n, r.leaf, flags, ss, nullptr, &a.tB, base + tb)))
             return rc;
     } else {
         a.tB = a.tA;
@@ -168,7 +172,8 @@ int start_step(spamm_server *S, Active &a)
     o.low_tol = a.split ? r.low_tol : 0.0;
     if ((rc = symbolic_async(a.tA, a.tB, &o, ss, base + (a.distinctB ? 2 : 1) * tb, &a.plan)))
         return rc;
-    hipError_t e = hipMemcpyAsync(P.K[a.step], a.plan->leafK, (a.split ? 2 : 1) * sizeof(uint64_t),
+    // kept counts and both roots in one copy (the cull writes them all)
+    hipError_t e = hipMemcpyAsync(&P.step[a.step], a.plan->leafK, sizeof(StepOut),
                                   hipMemcpyDeviceToHost, ss);
     if (e == hipSuccess)
         e = hipEventRecord(S->ev_cull[a.slot], ss);
@@ -290,13 +295,13 @@ void finish(spamm_server *S, Active &a)
     res.steps = a.step + 1;
     if (res.status == SPAMM_OK) {
         for (int s = 0; s <= a.step; ++s) {
-            const bool finite = isfinite(P.root[s][0]) && isfinite(P.root[s][1]);
+            const bool finite = isfinite(P.step[s].root[0]) && isfinite(P.step[s].root[1]);
             if (!finite) {
                 res.status = SPAMM_E_NONFINITE;
                 break;
             }
-            res.tasks += (int64_t)(P.K[s][0] + P.K[s][1]);
-            res.tasks_low += (int64_t)P.K[s][1];
+            res.tasks += (int64_t)(P.step[s].K[0] + P.step[s].K[1]);
+            res.tasks_low += (int64_t)P.step[s].K[1];
         }
     }
     const double b = a.job.rq.leaf;
