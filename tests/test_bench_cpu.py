@@ -1,0 +1,74 @@
+"""bench.py's host-side contract, without a GPU: one GPU only (more exits
+with a message), the traffic figures are used only for the kernel sources
+they were measured on, and the sampling / summary helpers."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.parametrize("argv,env", [(["--gpus", "2"], {}), (["--gpus", "8"], {}),
+                                      ([], {"WORLD_SIZE": "4"})])
+def test_more_than_one_gpu_exits_with_a_message(argv, env):
+    e = dict(os.environ, **env)
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *argv], env=e,
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+    assert p.stdout == ""
+
+
+def test_traffic_only_for_the_sources_it_was_measured_on(tmp_path, monkeypatch):
+    rec = {"workload": "w", "gemm_sources_sha256": bench.kernel_source_digest(),
+           "bytes_per_launch": 1234.0}
+    path = tmp_path / "t.json"
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "PROFILE_TRAFFIC", str(path))
+    assert bench.measured_traffic("w") == 1234.0
+    assert bench.measured_traffic("other") is None
+    path.write_text(json.dumps(dict(rec, gemm_sources_sha256="0" * 64)))
+    assert bench.measured_traffic("w") is None
+    path.write_text("not json")
+    assert bench.measured_traffic("w") is None
+    monkeypatch.setattr(bench, "PROFILE_TRAFFIC", str(tmp_path / "missing.json"))
+    assert bench.measured_traffic("w") is None
+
+
+def test_source_digest_covers_the_kernel_and_its_build_flags():
+    assert len(bench.kernel_source_digest()) == 64
+    assert any(s.endswith("gemm.hip") for s in bench.GEMM_SOURCES)
+    assert any(s.endswith("_build.py") for s in bench.GEMM_SOURCES)
+    for rel in bench.GEMM_SOURCES:
+        assert os.path.exists(os.path.join(ROOT, rel)), rel
+
+
+def test_committed_split_traffic_records_name_their_point():
+    for kind, fmt in (("leaf_gemm_split", "bf16"), ("leaf_gemm_split_fp16", "fp16")):
+        path = os.path.join(ROOT, "profiles", f"{kind}_cluster1310-n32750_traffic.json")
+        rec = json.load(open(path))
+        assert rec["tau"] > 0 and rec["low_tol"] > 0 and rec["bytes_per_launch"] > 0
+        # another point, or other kernel sources, never reuse the record
+        assert bench.measured_split_traffic("cluster1310-n32750", rec["tau"] * 10,
+                                            rec["low_tol"], fmt) is None
+        assert bench.measured_split_traffic("cluster1310-n32750", rec["tau"],
+                                            rec["low_tol"] * 2, fmt) is None
+
+
+def test_sample_tiles_distinct_sorted_in_range():
+    t = bench.sample_tiles(64, 100, seed=3)
+    assert len(t) == 100 and len(set(t)) == 100
+    assert t == sorted(t)
+    assert all(0 <= i < 64 and 0 <= j < 64 for i, j in t)
+    assert bench.sample_tiles(4, 100) == [(i, j) for i in range(4) for j in range(4)]
+
+
+def test_percentile_and_empty():
+    assert bench.percentile([], 50) is None
+    assert bench.percentile([1.0, 2.0, 3.0], 50) == 2.0
+    assert bench.percentile(list(range(101)), 99) == 99.0
