@@ -34,6 +34,17 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E peak
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "leaf_gemm_cluster1310-n32750_traffic.json")
 
 
+# The paper's single-core CPU figures (Sec. V.B, numeric multiply against
+# SGEMM; platforms in Sec. IV.A).  Context for the GPU numbers only.
+PAPER_CONTEXT = {
+    "note": "the paper's own FP32 CPU figures, one core, context only (other hardware, other matrices)",
+    "spamm_numeric_gflops_dense_16x16_blocks": {"AMD Opteron 6168 (1.8 GHz)": 8.1,
+                                                 "Intel Xeon X5650 (2.66 GHz)": 13.7},
+    "sgemm_gflops_large_n": {"AMD Opteron 6168, ACML or MKL": 12.6,
+                             "Intel Xeon X5650, ACML": 12.7, "Intel Xeon X5650, MKL": 19.8},
+    "source": "Sec. V.B (numeric multiply vs. SGEMM), Sec. IV.A (platforms)",
+}
+
 GEMM_SOURCES = ("paper_1203_1692_amd/csrc/gemm.hip", "paper_1203_1692_amd/csrc/common.hpp",
                 "paper_1203_1692_amd/_build.py")
 
@@ -685,6 +696,9 @@ def main() -> int:
                        f"{int(counts.sum())} kept leaf products, recursive FP64 oracle incl. its "
                        f"full-matrix norm pass, {t:.1f} s wall"),
         }
+    # ---- the paper's own figures (single CPU core, FP32 SSE kernels), for
+    # context only: another machine and other matrices, never a target -------
+    out["paper_context"] = PAPER_CONTEXT
     # ---- serving: a stream of products and squaring chains --------------------
     if not args.no_serve:
         del dA, C

@@ -72,3 +72,10 @@ def test_percentile_and_empty():
     assert bench.percentile([], 50) is None
     assert bench.percentile([1.0, 2.0, 3.0], 50) == 2.0
     assert bench.percentile(list(range(101)), 99) == 99.0
+
+
+def test_paper_context_is_context_only():
+    c = bench.PAPER_CONTEXT
+    assert "context only" in c["note"]
+    assert c["spamm_numeric_gflops_dense_16x16_blocks"]["AMD Opteron 6168 (1.8 GHz)"] == 8.1
+    assert all(v > 0 for v in c["sgemm_gflops_large_n"].values())
