@@ -270,12 +270,7 @@ __device__ inline int job_of(const GemmJobs &jobs, uint32_t bid)
     return j;
 }
 
-// SUB (n_b = 64): sub-leaf culling.  For its leaf product A_(2I+a', k) B_(k, 2J+b')
-// a wave tests the 8 products of 32 x 32 sub-blocks A_(a, c) B_(c, b) against
-// tau with the stored sub-block norms (tier d+1) and runs the MFMAs of
-// accumulator (a, b) on k-panel c only for the kept ones.  The performed set
-// is written per (entry, wave) to submask and counted in subK.
-template <int B, bool SUB>
+template <int B>
 __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
 {
     using L = LeafLayout<B>;
@@ -313,7 +308,7 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
     }
 
     const uint32_t e0 = browptr[blk], e1 = browptr[blk + 1];
-    if constexpr (!SUB && B >= 32) {
+    if constexpr (B >= 32) {
         fp32_products<B>(tA, tBT, job.slotA, job.slotB, bent, e0, e1, I0, J0, smem,
                          (uint32_t *)(smem + 2 * S::kStage), w, lane, acc);
         if (single && w != 0)
@@ -324,7 +319,6 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
     uint32_t *ents = (uint32_t *)(smem + 2 * S::kStage);
     load_entries(bent, e0, e1, ents);
     const uint32_t T = (e1 - e0) * NP;                  // stages of this block
-    uint32_t smask = 0, sub_count = 0;                  // SUB: this entry's kept sub-products
     if (T > 0)
         stage_issue<B>(ents[0], 0, tA, tBT, job.slotA, job.slotB, I0, J0, smem, w, lane);
     for (uint32_t t = 0; t < T; ++t) {
@@ -336,56 +330,169 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
         if (t + 1 < T)
             stage_issue<B>(ents[(t + 1) / NP], (int)((t + 1) % NP), tA, tBT, job.slotA,
                            job.slotB, I0, J0, smem + ((t + 1) & 1) * S::kStage, w, lane);
-        const bool mine = (ent >> (16 + w)) & 1u;
-        if constexpr (SUB) {
-            if (t % NP == 0) {
-                smask = 0;
-                if (mine) {
-                    const uint32_t k = ent & 0xFFFFu;
-                    const double *sa = job.subA + 4 * (int64_t)lin_index(I0 + qa, k);
-                    const double *sb = job.subB + 4 * (int64_t)lin_index(k, J0 + qb);
-#pragma unroll
-                    for (int a = 0; a < 2; ++a)
-#pragma unroll
-                        for (int b = 0; b < 2; ++b)
-#pragma unroll
-                            for (int c = 0; c < 2; ++c)
-                                smask |= keep_pair(sa[2 * a + c], sb[2 * c + b], job.T2)
-                                             ? 1u << (2 * (2 * a + b) + c) : 0u;
-                    sub_count += __builtin_popcount(smask);
-                }
-                if (lane == 0)
-                    job.submask[4 * (int64_t)(e0 + t / NP) + w] = (uint8_t)smask;
-            }
-        }
-        if (mine) {
+        if ((ent >> (16 + w)) & 1u) {
             const float *buf = smem + (t & 1) * S::kStage;
-            const float *Ap = buf + qa * L::kPanel;
-            const float *Bp = buf + (2 + qb) * L::kPanel;
-            if constexpr (SUB) {
-                // accumulator (a, b) on panel c = t % NP
-                const uint32_t c = t % NP;
-                const uint32_t pm = ((smask >> c) & 1u) | ((smask >> (1 + c)) & 2u) |
-                                    ((smask >> (2 + c)) & 4u) | ((smask >> (3 + c)) & 8u);
-                if (pm != 0u)
-                    panel_mfma32_sub<B>(Ap, Bp, acc, lane, pm);
-            } else {
-                panel_mfma16(Ap, Bp, acc16, lane);
-            }
+            panel_mfma16(buf + qa * L::kPanel, buf + (2 + qb) * L::kPanel, acc16, lane);
         }
     }
-    if constexpr (SUB) {
-        if (lane == 0 && sub_count != 0)
-            atomicAdd(job.subK, (unsigned long long)sub_count);
-    }
-
     if (single && w != 0)
         return;
-    const int64_t row0 = (int64_t)(I0 + qa) * B, col0 = (int64_t)(J0 + qb) * B;
-    if constexpr (B >= 32)
-        write_leaf32<B>(acc, row0, col0, n, C, lane);
-    else
-        write_leaf16(acc16, row0, col0, n, C, lane);
+    write_leaf16(acc16, (int64_t)(I0 + qa) * B, (int64_t)(J0 + qb) * B, n, C, lane);
+}
+
+// Sub-leaf culling (n_b = 64, 32 x 32 sub-blocks).  For its leaf product
+// A_(2I+a', k) B_(k, 2J+b') wave q = 2a' + b' keeps sub-product (a, c, b),
+// A_(a, c) B_(c, b), unless its stored sub-block norms fail the test against
+// tau, and runs accumulator (a, b) on k-panel c only for the kept ones.
+// Before its first copy the block works out every entry's kept sub-products
+// (one byte per entry and wave, also written to submask and counted in subK)
+// and compacts its stages to the (entry, panel) pairs some wave needs: a
+// panel no wave takes is neither copied nor waited for, and an operand leaf's
+// panel is copied only if one of its two user waves takes it.  The MFMAs each
+// accumulator runs, and their order, are those of the uncompacted loop.
+template <int B>
+struct SubShape {
+    static constexpr size_t kStages = sizeof(float) * 2 * GemmShape<B>::kStage;
+    static constexpr size_t kEnts = sizeof(uint32_t) * kMaxEnt;
+    static constexpr size_t kMasks = 4 * kMaxEnt;                       // uint8 per entry, wave
+    static constexpr size_t kList = sizeof(uint16_t) * 2 * kMaxEnt;     // entry << 1 | panel
+    static constexpr size_t kLds = kStages + kEnts + kMasks + kList;
+};
+
+template <int B>
+__global__ __launch_bounds__(256) void leaf_gemm_sub(const GemmJobs jobs)
+{
+    static_assert(B == 64, "sub-blocks are the 32 x 32 quadrants of 64 x 64 leaves");
+    using L = LeafLayout<B>;
+    using S = GemmShape<B>;
+    using Z = SubShape<B>;
+    constexpr int MB = B / 32;
+    static_assert(L::kPanels == 2, "one k-panel per sub-block column");
+    static_assert(kMaxEnt == 4 * 256, "four entries per thread cover a block's list");
+    extern __shared__ float smem[];
+    __shared__ uint32_t wtot[4];
+    const GemmJob &job = jobs.job[job_of(jobs, blockIdx.x)];
+    const float *__restrict__ tA = (const float *)job.tA;
+    const float *__restrict__ tBT = (const float *)job.tBT;
+    const int single = job.single;
+    const uint32_t blk = xcd_block(blockIdx.x - job.block0, job.nblocks);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int qa = w >> 1, qb = w & 1;
+    uint32_t I0 = 0, J0 = 0;
+    if (!single) {
+        I0 = 2 * lin_row(blk);
+        J0 = 2 * lin_col(blk);
+    }
+    char *lds = (char *)smem;
+    uint32_t *ents = (uint32_t *)(lds + Z::kStages);
+    uint8_t *smk = (uint8_t *)(lds + Z::kStages + Z::kEnts);
+    uint16_t *list = (uint16_t *)(lds + Z::kStages + Z::kEnts + Z::kMasks);
+    const uint32_t e0 = job.browptr[blk], e1 = job.browptr[blk + 1];
+    const uint32_t E = e1 - e0;
+    load_entries(job.bent, e0, e1, ents);
+
+    // kept sub-products of entries 4 tid .. 4 tid + 3 for all four waves,
+    // and the panels each entry needs
+    uint32_t need = 0, cnt = 0, subs = 0;            // need: 2 bits per entry
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t i = 4 * threadIdx.x + j;
+        if (i >= E)
+            break;
+        const uint32_t ent = ents[i], k = ent & 0xFFFFu;
+        uint32_t word = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t m = 0;
+            if ((ent >> (16 + q)) & 1u) {
+                const double *sa = job.subA + 4 * (int64_t)lin_index(I0 + (q >> 1), k);
+                const double *sb = job.subB + 4 * (int64_t)lin_index(k, J0 + (q & 1));
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c)
+                            m |= keep_pair(sa[2 * a + c], sb[2 * c + b], job.T2)
+                                     ? 1u << (2 * (2 * a + b) + c) : 0u;
+            }
+            word |= m << (8 * q);
+            subs += __builtin_popcount(m);
+        }
+        *reinterpret_cast<uint32_t *>(smk + 4 * i) = word;
+        *reinterpret_cast<uint32_t *>(job.submask + 4 * (int64_t)(e0 + i)) = word;
+        const uint32_t nb = ((word & 0x55555555u) ? 1u : 0u) | ((word & 0xAAAAAAAAu) ? 2u : 0u);
+        need |= nb << (2 * j);
+        cnt += __builtin_popcount(nb);
+    }
+    // exclusive scan of the per-thread stage counts: stage list in entry order
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if (lane >= o)
+            inc += y;
+    }
+    if (lane == 63)
+        wtot[w] = inc;
+    for (int o = 32; o > 0; o >>= 1)
+        subs += __shfl_xor(subs, o);
+    if (lane == 0 && subs != 0)
+        atomicAdd(job.subK, (unsigned long long)subs);
+    __syncthreads();
+    uint32_t pos = inc - cnt, T = 0;
+    for (int v = 0; v < 4; ++v) {
+        pos += v < w ? wtot[v] : 0u;
+        T += wtot[v];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            if ((need >> (2 * j + c)) & 1u)
+                list[pos++] = (uint16_t)(((4 * threadIdx.x + j) << 1) | c);
+    __syncthreads();
+
+    // waves that take panel c of entry i: bit q set
+    auto takers = [&](uint32_t st) {
+        const uint32_t word = *reinterpret_cast<const uint32_t *>(smk + 4 * (st >> 1));
+        const uint32_t m = (word >> (st & 1u)) & 0x55555555u;
+        return ((m & 0xFFu) ? 1u : 0u) | ((m & 0xFF00u) ? 2u : 0u) |
+               ((m & 0xFF0000u) ? 4u : 0u) | ((m & 0xFF000000u) ? 8u : 0u);
+    };
+    floatx16 acc[MB][MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < MB; ++j)
+            acc[i][j] = floatx16{0};
+    if (T > 0) {
+        const uint32_t st = list[0];
+        stage_issue<B>((ents[st >> 1] & 0xFFFFu) | (takers(st) << 16), (int)(st & 1u), tA, tBT,
+                       job.slotA, job.slotB, I0, J0, smem, w, lane);
+    }
+    for (uint32_t t = 0; t < T; ++t) {
+        const uint32_t st = list[t];
+        __builtin_amdgcn_s_waitcnt(0x0F70);             // vmcnt(0)
+        __syncthreads();
+        if (t + 1 < T) {
+            const uint32_t nx = list[t + 1];
+            stage_issue<B>((ents[nx >> 1] & 0xFFFFu) | (takers(nx) << 16), (int)(nx & 1u), tA, tBT,
+                           job.slotA, job.slotB, I0, J0, smem + ((t + 1) & 1) * S::kStage, w, lane);
+        }
+        // accumulator (a, b) of this wave on panel c
+        const uint32_t c = st & 1u;
+        const uint32_t sm = smk[4 * (st >> 1) + w];
+        const uint32_t pm = ((sm >> c) & 1u) | ((sm >> (1 + c)) & 2u) | ((sm >> (2 + c)) & 4u) |
+                            ((sm >> (3 + c)) & 8u);
+        if (pm != 0u) {
+            const float *buf = smem + (t & 1) * S::kStage;
+            panel_mfma32_sub<B>(buf + qa * L::kPanel, buf + (2 + qb) * L::kPanel, acc, lane, pm);
+        }
+    }
+    if (single && w != 0)
+        return;
+    write_leaf32<B>(acc, (int64_t)(I0 + qa) * B, (int64_t)(J0 + qb) * B, job.n, job.C, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -569,17 +676,29 @@ __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
     write_leaf32<B>(lo, (int64_t)(I0 + qa) * B, (int64_t)(J0 + qb) * B, job.n, job.C, lane);
 }
 
-template <int B, bool SUB>
+template <int B>
 static hipError_t launch_fp32(const GemmJobs &jobs, hipStream_t s)
 {
     using S = GemmShape<B>;
     // once per process (thread-safe static initialization)
     static const hipError_t attr =
-        hipFuncSetAttribute((const void *)leaf_gemm<B, SUB>,
+        hipFuncSetAttribute((const void *)leaf_gemm<B>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::kLds);
     if (attr != hipSuccess)
         return attr;
-    hipLaunchKernelGGL((leaf_gemm<B, SUB>), dim3(jobs.nblocks), dim3(256), S::kLds, s, jobs);
+    hipLaunchKernelGGL((leaf_gemm<B>), dim3(jobs.nblocks), dim3(256), S::kLds, s, jobs);
+    return hipGetLastError();
+}
+
+static hipError_t launch_sub(const GemmJobs &jobs, hipStream_t s)
+{
+    constexpr size_t lds = SubShape<64>::kLds;
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void *)leaf_gemm_sub<64>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess)
+        return attr;
+    hipLaunchKernelGGL((leaf_gemm_sub<64>), dim3(jobs.nblocks), dim3(256), lds, s, jobs);
     return hipGetLastError();
 }
 
@@ -604,7 +723,7 @@ hipError_t launch_gemm_jobs(int leaf, GemmKind kind, const GemmJobs &jobs, hipSt
         return hipSuccess;
     switch (kind) {
     case GemmKind::Sub:
-        return leaf == 64 ? launch_fp32<64, true>(jobs, s) : hipErrorInvalidValue;
+        return leaf == 64 ? launch_sub(jobs, s) : hipErrorInvalidValue;
     case GemmKind::Split:
         switch (leaf) {
         case 32: return launch_split<32, false>(jobs, s);
@@ -619,9 +738,9 @@ hipError_t launch_gemm_jobs(int leaf, GemmKind kind, const GemmJobs &jobs, hipSt
         }
     case GemmKind::Fp32:
         switch (leaf) {
-        case 16: return launch_fp32<16, false>(jobs, s);
-        case 32: return launch_fp32<32, false>(jobs, s);
-        case 64: return launch_fp32<64, false>(jobs, s);
+        case 16: return launch_fp32<16>(jobs, s);
+        case 32: return launch_fp32<32>(jobs, s);
+        case 64: return launch_fp32<64>(jobs, s);
         default: return hipErrorInvalidValue;
         }
     }
