@@ -87,6 +87,19 @@ def measured_split_traffic(workload: str, tau: float, low_tol: float, fmt: str =
     return t["bytes_per_launch"]
 
 
+def measured_sub_traffic(workload: str, tau: float):
+    """HBM bytes per launch of the sub-leaf culling kernel at tau from the
+    committed counter runs, or None when the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"leaf_gemm_sub_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if (t.get("gemm_sources_sha256") != kernel_source_digest() or
+            abs(t.get("tau", -1.0) - tau) > 1e-12 * tau):
+        return None
+    return t["bytes_per_launch"]
+
+
 def sample_tiles(N: int, count: int, seed: int = 0):
     import numpy as np
     rng = np.random.default_rng(seed)
@@ -474,6 +487,9 @@ def main() -> int:
     ap.add_argument("--precision", choices=("fp32", "split", "split-fp16"), default="fp32",
                     help="product of the timed steps (split: BF16 for LOW products, "
                          "split-fp16: FP16 at a per-leaf scale)")
+    ap.add_argument("--sub-cull", action="store_true",
+                    help="sub-leaf culling (32 x 32 sub-products inside 64 x 64 leaves); "
+                         "value and roofline then count the performed sub-products")
     ap.add_argument("--low-tol", type=float, default=0.8192,
                     help="split precision: absolute LOW threshold on the norm product")
     ap.add_argument("--no-dense", action="store_true",
@@ -526,11 +542,20 @@ def main() -> int:
     split = args.precision != "fp32"
     f16 = args.precision == "split-fp16"
     prec = sp.PREC_SPLIT_FP16 if f16 else sp.PREC_SPLIT_BF16 if split else sp.PREC_FP32
+    sub = args.sub_cull
+    if sub and (split or leaf != 64):
+        print("--sub-cull needs FP32 precision and a 64 x 64 leaf workload", file=sys.stderr)
+        return 2
+    if sub:
+        # the other legs compare against the whole-leaf product: not run here
+        args.no_sparse = args.no_matched_error = args.no_cpu_baseline = True
 
     def step():
-        tree = sp.build_tree(dA, leaf, bf16=split and not f16, fp16=f16)   # syncs once (root norm)
+        tree = sp.build_tree(dA, leaf, bf16=split and not f16, fp16=f16,
+                             subnorms=sub)                            # syncs once (root norm)
         st = sp.multiply_ex(tree, tree, tau, C, precision=prec,
-                            low_tol=args.low_tol if split else 0.0)   # events around cull and GEMM
+                            low_tol=args.low_tol if split else 0.0,
+                            sub_cull=sub)                             # events around cull and GEMM
         tree.free()
         return st
 
@@ -546,7 +571,7 @@ def main() -> int:
 
     ms_step = (t1 - t0) * 1e3 / args.steps
     st = stats[-1]
-    flops = st["flops"]
+    flops = st["flops"]    # with sub-leaf culling: 2 * 32^3 per performed sub-product
     K = st["tasks"]
     gemm_ms = sum(s["numeric_ms"] for s in stats) / len(stats)
     cull_ms = sum(s["symbolic_ms"] for s in stats) / len(stats)
@@ -600,6 +625,11 @@ def main() -> int:
             "traffic": measured_traffic(wl.name),
         },
     }
+    if sub:
+        out["config"]["sub_cull"] = True
+        out["config"]["sub_products"] = st["subtasks"]
+        out["config"]["flops_counted"] = "2 * 32^3 per performed 32 x 32 sub-product"
+        out["roofline"]["traffic"] = measured_sub_traffic(wl.name, tau)
     if split:
         # the split kernel moves whole 16-bit leaves: rate it against HBM
         tb = measured_split_traffic(wl.name, tau, args.low_tol, "fp16" if f16 else "bf16")
@@ -615,7 +645,7 @@ def main() -> int:
 
     # ---- context: the dense FP32 product of the same matrix (torch.matmul) ------
     # the paper's cross-over against SGEMM; not part of the timed step
-    if not args.no_dense and not split:
+    if not args.no_dense and not split and not sub:
         D = torch.empty_like(C)
         torch.matmul(dA, dA, out=D)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]

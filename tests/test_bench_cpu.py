@@ -79,3 +79,11 @@ def test_paper_context_is_context_only():
     assert "context only" in c["note"]
     assert c["spamm_numeric_gflops_dense_16x16_blocks"]["AMD Opteron 6168 (1.8 GHz)"] == 8.1
     assert all(v > 0 for v in c["sgemm_gflops_large_n"].values())
+
+
+def test_committed_sub_traffic_record_names_its_point():
+    path = os.path.join(ROOT, "profiles", "leaf_gemm_sub_cluster1310-n32750_traffic.json")
+    rec = json.load(open(path))
+    assert rec["tau"] > 0 and rec["bytes_per_launch"] > 0
+    assert bench.measured_sub_traffic("cluster1310-n32750", rec["tau"] * 10) is None
+    assert bench.measured_sub_traffic("other-workload", rec["tau"]) is None
