@@ -194,3 +194,65 @@ def test_subleaf_argument_errors(gpu):
     gpu.multiply_ex(s, s, 0.0, C1)
     gpu.multiply_ex(plain, plain, 0.0, C2)
     assert torch.equal(C1, C2)
+
+
+def arrow(n, w, seed):
+    """Symmetric matrix whose first w rows and columns are non-zero (values
+    decaying along the strip, every other group of 32 strip rows scaled by
+    1e-4 so that sub-products inside kept leaf products fail the test),
+    zero elsewhere."""
+    rng = np.random.default_rng(seed)
+    A = np.empty((n, n), dtype=np.float32)
+    A.fill(0.0)                     # touched in row order (faster than zero pages)
+    rows = np.where((np.arange(w) // 32) % 2 == 0, 1.0, 1e-4)[:, None]
+    strip = (rng.uniform(-1, 1, (w, n)) * np.exp(-np.arange(n) / 3000.0) * rows).astype(np.float32)
+    A[:w, :] = strip
+    A[:, :w] = strip.T
+    corner = strip[:, :w]
+    A[:w, :w] = np.triu(corner) + np.triu(corner, 1).T
+    return A
+
+
+def test_subleaf_block_with_the_longest_entry_list(gpu):
+    """n = 32768: the output block of leaves (0, 0)-(1, 1) takes all 512
+    values of k, the longest entry list a block holds at this order (every
+    other block takes two), so the masks and stage list of every thread of
+    the workgroup are used.  Performed sub-products bit-exact against the
+    leaf-32 oracle; C on the long block and on sampled blocks against the
+    oracle's per-leaf products within Higham's bound."""
+    import torch
+    n, tau = 32768, 1e-7
+    A = arrow(n, 128, 21)
+    print("\n[subleaf] arrow-n32768", flush=True)
+    dA = torch.from_numpy(A).cuda()
+    t = gpu.build_tree(dA, 64, subnorms=True)
+    plan = gpu.symbolic(t, t, tau, sub_cull=True)
+    C = torch.full_like(dA, float("nan"))
+    plan.numeric(C)
+    torch.cuda.synchronize()
+    del dA
+    sub = plan.subtasks()
+    st = plan.stats()
+    ref = oracle.spamm(A, A, 32, tau, want_C=False)
+    assert sub.size == ref.K
+    assert np.array_equal(sub, ref.keys)
+    # the long block really is long, and sub-culling acts inside it
+    hi = ref.keys >> np.uint64(32)
+    lc = np.uint64(oracle.linear_index(0, 0))
+    k00 = (ref.keys[hi == lc] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    assert len(np.unique(k00 // 2)) == 512           # every leaf-64 k for output leaf (0, 0)
+    assert st["subtasks"] < 0.6 * 8 * st["tasks"]     # and about half the sub-products culled
+    tiles = [(0, 0), (0, 1), (1, 0), (1, 1), (3, 3), (0, 1023), (1023, 0), (500, 700), (1023, 1023)]
+    Ct, counts, kl = oracle.spamm_tiles(A, A, 32, tau, tiles, threads=16, want_klists=True)
+    Cg = C.cpu().numpy()
+    for s, (I, J) in enumerate(tiles):
+        got = Cg[I * 32:(I + 1) * 32, J * 32:(J + 1) * 32].astype(np.float64)
+        want = Ct[s]
+        ks = kl[s, :counts[s]]
+        M = np.zeros((32, 32))
+        for k in ks:
+            M += np.abs(A[I * 32:(I + 1) * 32, k * 32:(k + 1) * 32]).astype(np.float64) @ \
+                np.abs(A[k * 32:(k + 1) * 32, J * 32:(J + 1) * 32]).astype(np.float64)
+        m = 32 * len(ks) + 1
+        bound = m * U32 / (1 - m * U32) * M + m * 2.0 ** -126
+        assert np.all(np.abs(got - want) <= bound), (I, J)
