@@ -294,6 +294,7 @@ def serve_run(sp, torch, srv, reqs, inputs, qps=None, window=16, keep=()):
         return got
 
     t_first = t_last = None
+    info0 = srv.info()
     for k, req in enumerate(reqs):
         if arrivals is None:
             while len(pending) >= window:
@@ -316,7 +317,10 @@ def serve_run(sp, torch, srv, reqs, inputs, qps=None, window=16, keep=()):
         if not sweep():
             time.sleep(50e-6)
     t_end = time.perf_counter()
-    return out, kept, dict(t0=t0, t_first=t_first, t_last=t_last, t_end=t_end)
+    info1 = srv.info()
+    busy = ((info1["sched_cpu_ms"] - info0["sched_cpu_ms"]) /
+            max(info1["sched_wall_ms"] - info0["sched_wall_ms"], 1e-9))
+    return out, kept, dict(t0=t0, t_first=t_first, t_last=t_last, t_end=t_end, sched_busy=busy)
 
 
 def serve_summary(reqs, res, tm, qps):
@@ -339,6 +343,7 @@ def serve_summary(reqs, res, tm, qps):
         "queue_p50_ms": percentile([res[r.index]["queue_ms"] for r in reqs], 50),
         "queue_p99_ms": percentile([res[r.index]["queue_ms"] for r in reqs], 99),
         "failed": bad,
+        "scheduler_cpu_fraction": tm.get("sched_busy"),
         "plain": pq(lambda r: r.chain_len == 0),
         "chains": pq(lambda r: r.chain_len > 0),
         "fp32": pq(lambda r: not r.split),

@@ -348,6 +348,8 @@ typedef struct spamm_server_stats {
     uint64_t used;               /* bytes held by the slot arenas now                */
     uint64_t peak_used;          /* most bytes held by the slot arenas at once       */
     uint64_t budget;             /* hbm_budget                                       */
+    double   sched_cpu_ms;       /* CPU time used by the scheduler thread so far     */
+    double   sched_wall_ms;      /* wall time since the scheduler thread started     */
 } spamm_server_stats;
 
 /*

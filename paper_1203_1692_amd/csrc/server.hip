@@ -17,7 +17,9 @@
 // larger request lands on the slot, so the steady state allocates nothing.
 // The arenas together never exceed the server's budget.
 #include <math.h>
+#include <pthread.h>
 #include <string.h>
+#include <time.h>
 
 #include <algorithm>
 #include <chrono>
@@ -137,6 +139,7 @@ struct spamm_server {
     bool busy[kMaxSlots] = {};
     uint64_t next_ticket = 1;
     bool stopping = false;
+    double t_start = 0.0;          // host clock (us) when the scheduler started
 
     // scheduler thread only
     std::vector<Active> active;
@@ -538,6 +541,7 @@ int spamm_server_create(size_t hbm_budget, int32_t max_slots, spamm_server **out
     }
     memset(S->pin, 0, sizeof(Pinned) * (size_t)max_slots);
     try {
+        S->t_start = now_us();
         S->worker = std::thread(scheduler, S);
     } catch (...) {
         release_server(S);
@@ -603,6 +607,15 @@ int spamm_server_info(spamm_server *S, spamm_server_stats *out)
     out->queued = (int64_t)S->queue.size();
     out->used = S->used;
     out->budget = S->budget;
+    // the scheduler thread's own CPU clock: how busy the host side is
+    out->sched_cpu_ms = 0.0;
+    out->sched_wall_ms = (now_us() - S->t_start) * 1e-3;
+    clockid_t cid;
+    timespec ts;
+    if (S->worker.joinable() &&
+        pthread_getcpuclockid(S->worker.native_handle(), &cid) == 0 &&
+        clock_gettime(cid, &ts) == 0)
+        out->sched_cpu_ms = ts.tv_sec * 1e3 + ts.tv_nsec * 1e-6;
     return SPAMM_OK;
 }
 
