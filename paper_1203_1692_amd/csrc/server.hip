@@ -5,8 +5,9 @@
 // Stream protocol of one admitted request (slot stream ss, GEMM stream gs):
 //   ss: build tree(s) -> root norm to pinned host -> cull -> task counts to
 //       pinned host -> record ev_cull
-//   gs: wait ev_cull (of every request in the batch) -> [BF16 pass] -> FP32
-//       pass -> record ev_done
+//   gs: a batch of requests whose ev_cull has completed (the host polls it,
+//       so a long build or cull never holds up the GEMM stream) -> one launch
+//       per kernel kind -> record ev_done
 //   chain step s -> s+1, enqueued at once after the GEMM:
 //   ss: wait ev_done -> build the tree of X_{s+1} from C over the arena
 //       space of X_s's tree -> cull -> ... (no host round trip)
@@ -229,7 +230,7 @@ bool launch_batches(spamm_server *S)
     bool any = false;
     std::vector<size_t> ready;
     for (size_t i = 0; i < S->active.size(); ++i)
-        if (S->active[i].culled)
+        if (S->active[i].culled && hipEventQuery(S->ev_cull[S->active[i].slot]) == hipSuccess)
             ready.push_back(i);
     while (!ready.empty() && (int)S->inflight.size() < kInflightBatches) {
         // one batch: up to kMaxJobs requests of the first ready request's leaf size
@@ -245,8 +246,6 @@ bool launch_batches(spamm_server *S)
         hipError_t e = hipSuccess;
         for (size_t i : batch) {
             Active &a = S->active[i];
-            if (e == hipSuccess)
-                e = hipStreamWaitEvent(S->gemm, S->ev_cull[a.slot], 0);
             const GemmKind kind = plan_kind(a.plan);
             GemmJobs &tab = tabs[kind == GemmKind::Split ? 1 : kind == GemmKind::SplitF16 ? 2 : 0];
             GemmJob &j = tab.job[tab.njobs++];
