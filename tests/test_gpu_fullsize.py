@@ -307,3 +307,33 @@ def test_cluster1310_split_matched_error_point(cluster1310, gpu, fmt, low):
     r = SplitRun(gpu, cluster1310.A, cluster1310.leaf, 1e-4, low, fmt, "cluster1310-n32750")
     assert r.stats["tasks_low"] > 0.9 * r.stats["tasks"]
     check_split(r, seed=31)
+
+
+# ---- the longest entry list a block can hold ------------------------------------
+
+def test_longest_entry_list_leaf32_fp32(gpu):
+    """n = 32768 at 32 x 32 leaves (N = 1024): with only the first 128 rows
+    and columns non-zero, output leaf (0, 0) takes all 1024 values of k, as
+    many entries as a block's list holds; the whole task set bit-exact, C on
+    sampled leaves (the long one included) within the bound."""
+    from inputs import arrow
+    A = arrow(32768, 128, 21)
+    r = MatrixRun(gpu, A, 32, 1e-7, "arrow-n32768-leaf32")
+    ref = oracle.spamm(A, A, 32, 1e-7, want_C=False)
+    assert r.stats["kept"] == [int(v) for v in ref.Kt]
+    assert np.array_equal(r.keys, ref.keys)
+    hi = r.keys >> np.uint64(32)
+    assert int(np.count_nonzero(hi == np.uint64(oracle.linear_index(0, 0)))) == 1024
+    check_sampled_product(r, seed=6)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_longest_entry_list_leaf32_split(gpu, fmt):
+    """The same matrix with split precision (57 % of the products LOW): both
+    schedules of the long block, every key with its class bit, sampled C
+    within the class-aware bound."""
+    from inputs import arrow
+    A = arrow(32768, 128, 21)
+    r = SplitRun(gpu, A, 32, 1e-7, 1e-2, fmt, "arrow-n32768-leaf32")
+    assert 0.5 * r.stats["tasks"] < r.stats["tasks_low"] < 0.7 * r.stats["tasks"]
+    check_split(r, seed=8)

@@ -18,6 +18,7 @@ import pytest
 
 import oracle
 import workloads
+from inputs import arrow
 
 pytestmark = pytest.mark.gpu
 
@@ -194,23 +195,6 @@ def test_subleaf_argument_errors(gpu):
     gpu.multiply_ex(s, s, 0.0, C1)
     gpu.multiply_ex(plain, plain, 0.0, C2)
     assert torch.equal(C1, C2)
-
-
-def arrow(n, w, seed):
-    """Symmetric matrix whose first w rows and columns are non-zero (values
-    decaying along the strip, every other group of 32 strip rows scaled by
-    1e-4 so that sub-products inside kept leaf products fail the test),
-    zero elsewhere."""
-    rng = np.random.default_rng(seed)
-    A = np.empty((n, n), dtype=np.float32)
-    A.fill(0.0)                     # touched in row order (faster than zero pages)
-    rows = np.where((np.arange(w) // 32) % 2 == 0, 1.0, 1e-4)[:, None]
-    strip = (rng.uniform(-1, 1, (w, n)) * np.exp(-np.arange(n) / 3000.0) * rows).astype(np.float32)
-    A[:w, :] = strip
-    A[:, :w] = strip.T
-    corner = strip[:, :w]
-    A[:w, :w] = np.triu(corner) + np.triu(corner, 1).T
-    return A
 
 
 def test_subleaf_block_with_the_longest_entry_list(gpu):
