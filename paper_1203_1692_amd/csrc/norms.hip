@@ -114,7 +114,7 @@ __device__ inline void store_fp16x4(uint16_t *dst, float4 v, int e)
 // is a.  So the butterfly skips lane bit 3, the register tree stops below m
 // bit 3, and the leaf norm is the parent of its four sub-blocks:
 // (s_00 + s_01) + (s_10 + s_11), written to sub_norm[4 l + 2a + b].
-template <int B, int VEC, bool SUB>
+template <int B, int VEC, bool SUB, bool TWO>
 __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ A, int64_t n,
                                                       float *__restrict__ tiles,
                                                       float *__restrict__ tilesT,
@@ -133,21 +133,29 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
     constexpr int M = (B * B) / 256;   // float4 loads per lane
     constexpr int P = B + 1;           // LDS pitch of the transpose buffer
     static_assert(M >= 1 && (M & (M - 1)) == 0, "leaf must be 16, 32 or 64");
+    // TWO (64 x 64 leaves): the transpose runs in two halves of 32 source
+    // rows (one k-panel of the transposed copy each), which halves the LDS
+    // and lets more workgroups share a CU.  A 16-bit transposed row (128
+    // bytes) is then written in two halves; with BF16 copies that costs more
+    // than the extra workgroups gain, so they are transposed in one pass.
+    static_assert(!TWO || B == 64, "two-pass transpose for 64 x 64 leaves");
+    constexpr int NPASS = TWO ? 2 : 1;
+    constexpr int RH = B / NPASS, MH = M / NPASS;
     extern __shared__ float tr_smem[];
     __shared__ double part[4];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const uint32_t l = blockIdx.x * 4u + (uint32_t)w;
     const bool valid = l < ntiles;
-    float *tr = tr_smem + w * (B * P);
+    float *tr = tr_smem + w * (RH * P);
     double s = 0.0;
     // pack this leaf?  (tiles null: norms only; keep/slot: a sparsified tree
     // stores only its kept leaves, leaf l at slot[l])
     const bool pack = valid && tiles != nullptr && (keep == nullptr || keep[l] != 0u);
     const int64_t dl = pack && slot != nullptr ? (int64_t)slot[l] : (int64_t)l;
+    float4 v[M];
     if (valid) {
         const int64_t I = lin_row(l), J = lin_col(l);
-        float4 v[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int e = 256 * m + 4 * lane;
@@ -165,11 +173,6 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
                         store_bf16x4(tiles16 + dl * (B * B) + Leaf16Layout<B>::index(r, c), v[m]);
                 }
             }
-            float *o = tr + r * P + c;
-            o[0] = v[m].x;
-            o[1] = v[m].y;
-            o[2] = v[m].z;
-            o[3] = v[m].w;
             const double x0 = v[m].x, x1 = v[m].y, x2 = v[m].z, x3 = v[m].w;
             double t = (x0 * x0 + x1 * x1) + (x2 * x2 + x3 * x3);
 #pragma unroll
@@ -209,43 +212,71 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
                 leaf_norm[l] = s;
         }
     }
-    __syncthreads();
-    if (pack) {
-        float *dstT = tilesT + dl * (B * B);
-        // FP16: the leaf's scale exponent from its norm (s is the same in
-        // every lane of the wave)
-        const int e16 = scale16 != nullptr ? fp16_scale_exponent(s) : 0;
-        if (scale16 != nullptr && lane == 0)
-            scale16[dl] = e16;
+    // FP16: the leaf's scale exponent from its norm (s is the same in every
+    // lane of the wave); the as-is copy straight from the loaded values
+    const int e16 = pack && scale16 != nullptr ? fp16_scale_exponent(s) : 0;
+    if (pack && scale16 != nullptr && lane == 0)
+        scale16[dl] = e16;
+    if constexpr (B >= 32) {
+        if (pack && scale16 != nullptr && tiles16 != nullptr) {
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const int e = 256 * m + 4 * lane;
-            const int rt = e / B, ct = e % B;   // element (rt, ct..ct+3) of the transpose
-            const float4 t = make_float4(tr[(ct + 0) * P + rt], tr[(ct + 1) * P + rt],
-                                         tr[(ct + 2) * P + rt], tr[(ct + 3) * P + rt]);
-            *reinterpret_cast<float4 *>(dstT + L::index(rt, ct)) = t;
-            if constexpr (B >= 32) {
-                if (tilesT16 != nullptr) {
-                    uint16_t *d16 = tilesT16 + dl * (B * B) + Leaf16Layout<B>::index(rt, ct);
-                    if (scale16 != nullptr)
-                        store_fp16x4(d16, t, e16);
-                    else
-                        store_bf16x4(d16, t);
+            for (int m = 0; m < M; ++m) {
+                const int e = 256 * m + 4 * lane;
+                store_fp16x4(tiles16 + dl * (B * B) + Leaf16Layout<B>::index(e / B, e % B), v[m],
+                             e16);
+            }
+        }
+    }
+    // transposed copies through LDS, RH source rows at a time
+#pragma unroll
+    for (int h = 0; h < NPASS; ++h) {
+        if (pack) {
+#pragma unroll
+            for (int mm = 0; mm < MH; ++mm) {
+                const int m = h * MH + mm;
+                const int e = 256 * m + 4 * lane;
+                float *o = tr + (e / B - h * RH) * P + e % B;
+                o[0] = v[m].x;
+                o[1] = v[m].y;
+                o[2] = v[m].z;
+                o[3] = v[m].w;
+            }
+        }
+        __syncthreads();
+        if (pack) {
+            float *dstT = tilesT + dl * (B * B);
+#pragma unroll
+            for (int i = 0; i < MH; ++i) {
+                // element (rt, ct..ct+3) of the transpose, ct in this half;
+                // source row cr of the half.  With two halves, lane groups of
+                // 8 take rows rt = 4i + g and 4i + g + 32 so that the 64 lanes
+                // hit 64 distinct banks (pitch B + 1).
+                int rt, cr;
+                if constexpr (NPASS == 2) {
+                    cr = 4 * (lane & 7);
+                    rt = 4 * i + ((lane >> 3) & 3) + 32 * (lane >> 5);
+                } else {
+                    const int e = 256 * i + 4 * lane;
+                    rt = e / B;
+                    cr = e % B;
+                }
+                const int ct = h * RH + cr;
+                const float4 t = make_float4(tr[(cr + 0) * P + rt], tr[(cr + 1) * P + rt],
+                                             tr[(cr + 2) * P + rt], tr[(cr + 3) * P + rt]);
+                *reinterpret_cast<float4 *>(dstT + L::index(rt, ct)) = t;
+                if constexpr (B >= 32) {
+                    if (tilesT16 != nullptr) {
+                        uint16_t *d16 = tilesT16 + dl * (B * B) + Leaf16Layout<B>::index(rt, ct);
+                        if (scale16 != nullptr)
+                            store_fp16x4(d16, t, e16);
+                        else
+                            store_bf16x4(d16, t);
+                    }
                 }
             }
         }
-        if constexpr (B >= 32) {
-            if (scale16 != nullptr && tiles16 != nullptr) {
-#pragma unroll
-                for (int m = 0; m < M; ++m) {
-                    const int e = 256 * m + 4 * lane;
-                    const int r = e / B, c = e % B;
-                    const float *row = tr + r * P + c;
-                    store_fp16x4(tiles16 + dl * (B * B) + Leaf16Layout<B>::index(r, c),
-                                 make_float4(row[0], row[1], row[2], row[3]), e16);
-                }
-            }
-        }
+        if (h + 1 < NPASS)
+            __syncthreads();        // the next half overwrites the buffer
     }
     if (parent != nullptr) {
         if (lane == 0)
@@ -269,22 +300,40 @@ __global__ __launch_bounds__(1024) void norm_pyramid(double *__restrict__ norms,
     }
 }
 
+template <int B, int VEC, bool SUB, bool TWO>
+static hipError_t launch_leaf_t(const float *A, int64_t n, float *tiles, float *tilesT,
+                                uint16_t *t16, uint16_t *tT16, double *leaf, double *parent,
+                                double *sub, const uint32_t *keep, const uint32_t *slot,
+                                int32_t *scale16, uint32_t ntiles, hipStream_t s)
+{
+    constexpr size_t lds = sizeof(float) * 4 * (TWO ? B / 2 : B) * (B + 1);
+    // once per process (thread-safe static initialization)
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void *)leaf_norm_pack<B, VEC, SUB, TWO>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess)
+        return attr;
+    hipLaunchKernelGGL((leaf_norm_pack<B, VEC, SUB, TWO>), dim3((ntiles + 3) / 4), dim3(256), lds,
+                       s, A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep, slot, scale16,
+                       ntiles);
+    return hipGetLastError();
+}
+
 template <int B, int VEC, bool SUB>
 static hipError_t launch_leaf_v(const float *A, int64_t n, float *tiles, float *tilesT,
                                 uint16_t *t16, uint16_t *tT16, double *leaf, double *parent,
                                 double *sub, const uint32_t *keep, const uint32_t *slot,
                                 int32_t *scale16, uint32_t ntiles, hipStream_t s)
 {
-    constexpr size_t lds = sizeof(float) * 4 * B * (B + 1);
-    // once per process (thread-safe static initialization)
-    static const hipError_t attr =
-        hipFuncSetAttribute((const void *)leaf_norm_pack<B, VEC, SUB>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (attr != hipSuccess)
-        return attr;
-    hipLaunchKernelGGL((leaf_norm_pack<B, VEC, SUB>), dim3((ntiles + 3) / 4), dim3(256), lds, s, A,
-                       n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep, slot, scale16, ntiles);
-    return hipGetLastError();
+    // two passes except with BF16 copies (FP16 copies gain from the extra
+    // workgroups: their conversion is the longer part)
+    if constexpr (B == 64) {
+        if (t16 == nullptr || scale16 != nullptr)
+            return launch_leaf_t<B, VEC, SUB, true>(A, n, tiles, tilesT, t16, tT16, leaf, parent,
+                                                    sub, keep, slot, scale16, ntiles, s);
+    }
+    return launch_leaf_t<B, VEC, SUB, false>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub,
+                                             keep, slot, scale16, ntiles, s);
 }
 
 template <int B, bool SUB>
