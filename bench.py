@@ -373,6 +373,30 @@ def serve_verify(sp, torch, reqs, kept, inputs):
     return ok
 
 
+def serve_one_call(sp, torch, reqs, inputs):
+    """The same requests through the one-call API, one after another (tree
+    build + multiply per step, each synchronizing): the plain GPU form the
+    server is compared with.  Results are those of the server bit for bit
+    (serve_verify), so the errors match."""
+    from workloads import SERVE_LEAF
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for req in reqs:
+        X, low = inputs[req.index]
+        prec = sp.PREC_SPLIT_BF16 if req.split else sp.PREC_FP32
+        for _ in range(max(1, req.chain_len)):
+            t = sp.build_tree(X, SERVE_LEAF, bf16=req.split)
+            C = torch.empty_like(X)
+            sp.multiply_ex(t, t, req.tau, C, precision=prec, low_tol=low)
+            t.free()
+            X = C
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"requests_per_s": round(len(reqs) / wall, 2), "wall_s": round(wall, 3),
+            "note": "each request alone through spamm_build_tree + spamm_multiply_opts per "
+                    "step, synchronizing; same results as served"}
+
+
 def serve_bench(sp, torch, dev, count, slots, budget_gib):
     """Saturation (closed loop, 2 x slots outstanding), then Poisson arrivals
     at 0.5x and 0.8x of it; returns the summary dict."""
@@ -427,6 +451,9 @@ def serve_bench(sp, torch, dev, count, slots, budget_gib):
         info = srv.info()
     finally:
         srv.destroy()
+    one = serve_one_call(sp, torch, reqs, inputs)
+    print(f"one-call API, one request at a time: {one['requests_per_s']} req/s",
+          file=sys.stderr, flush=True)
     del inputs
     torch.cuda.empty_cache()
     return {
@@ -440,6 +467,8 @@ def serve_bench(sp, torch, dev, count, slots, budget_gib):
         "saturation": sat,
         "loads": loads,
         "verified_bitwise_vs_alone": f"{verified}/{len(keep_idx)}",
+        "one_call_sequential": one,
+        "served_speedup_vs_one_call": round(sat["throughput_rps"] / one["requests_per_s"], 3),
         "server": {k: info[k] for k in ("max_batch", "peak_active", "peak_used", "budget")},
     }
 
