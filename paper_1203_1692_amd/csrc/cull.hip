@@ -454,6 +454,11 @@ __device__ inline int64_t rowptr_offset(int t) { return tier_offset(t) + t; }
 // emit per tier as the per-tier kernels (same per-wave code), so the lists
 // are identical; barriers separate the phases.
 constexpr int kTopTiers = 5;
+// offset of tier t (1 <= t <= kTopTiers) in cull_top's LDS copy: tiers 1..t-1
+// back to back (4^u values each, a multiple of 4, so every tier starts 32-byte
+// aligned)
+__host__ __device__ constexpr int top_offset(int t) { return int(((int64_t(1) << (2 * t)) - 4) / 3); }
+constexpr int kTopNorms = top_offset(kTopTiers + 1);
 
 __global__ __launch_bounds__(kScanThreads) void cull_top(const double *__restrict__ nA,
                                                          const double *__restrict__ nB, double T2,
@@ -465,6 +470,16 @@ __global__ __launch_bounds__(kScanThreads) void cull_top(const double *__restric
 {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     constexpr int NW = kScanThreads / kWave;
+    // tiers 1..top of both pyramids in LDS, each tier at a 16-byte aligned
+    // offset (the children of a node are read as two 16-byte pairs)
+    __shared__ __align__(16) double sA[kTopNorms], sB[kTopNorms];
+    for (int t = 1; t <= top; ++t) {
+        const int64_t cnt = int64_t(1) << (2 * t);
+        for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+            sA[top_offset(t) + i] = nA[tier_offset(t) + i];
+            sB[top_offset(t) + i] = nB[tier_offset(t) + i];
+        }
+    }
     if (threadIdx.x == 0) {
         rowptr[0] = 0;
         rowptr[1] = keep_pair(nA[0], nB[0], T2) ? 1u : 0u;
@@ -476,7 +491,7 @@ __global__ __launch_bounds__(kScanThreads) void cull_top(const double *__restric
     __syncthreads();
     for (int t = 1; t <= top; ++t) {
         const uint32_t np = 1u << (2 * (t - 1));
-        const double *tA = nA + tier_offset(t), *tB = nB + tier_offset(t);
+        const double *tA = sA + top_offset(t), *tB = sB + top_offset(t);
         const uint32_t *prow = rowptr + rowptr_offset(t - 1);
         uint32_t *crow = rowptr + rowptr_offset(t);
         const uint32_t *plist = (t - 1) & 1 ? list1 : list0;
