@@ -41,11 +41,15 @@ __device__ inline float4 load_row4(const float *__restrict__ A, int64_t n, int64
 }
 
 // Four consecutive elements of a row, rounded to BF16 (8 bytes, aligned).
+__device__ inline uint2 pack_bf16x4(float4 v)
+{
+    return make_uint2((uint32_t)to_bf16(v.x) | ((uint32_t)to_bf16(v.y) << 16),
+                      (uint32_t)to_bf16(v.z) | ((uint32_t)to_bf16(v.w) << 16));
+}
+
 __device__ inline void store_bf16x4(uint16_t *dst, float4 v)
 {
-    const uint32_t lo = (uint32_t)to_bf16(v.x) | ((uint32_t)to_bf16(v.y) << 16);
-    const uint32_t hi = (uint32_t)to_bf16(v.z) | ((uint32_t)to_bf16(v.w) << 16);
-    *reinterpret_cast<uint2 *>(dst) = make_uint2(lo, hi);
+    *reinterpret_cast<uint2 *>(dst) = pack_bf16x4(v);
 }
 
 // ---- FP16 leaf copies (split precision with FP16 LOW operands) ---------------
@@ -90,11 +94,15 @@ __device__ inline uint16_t to_fp16_scaled(float x, int e)
 }
 
 // Four consecutive elements x 2^e, rounded to binary16 (8 bytes, aligned).
+__device__ inline uint2 pack_fp16x4(float4 v, int e)
+{
+    return make_uint2((uint32_t)to_fp16_scaled(v.x, e) | ((uint32_t)to_fp16_scaled(v.y, e) << 16),
+                      (uint32_t)to_fp16_scaled(v.z, e) | ((uint32_t)to_fp16_scaled(v.w, e) << 16));
+}
+
 __device__ inline void store_fp16x4(uint16_t *dst, float4 v, int e)
 {
-    const uint32_t lo = (uint32_t)to_fp16_scaled(v.x, e) | ((uint32_t)to_fp16_scaled(v.y, e) << 16);
-    const uint32_t hi = (uint32_t)to_fp16_scaled(v.z, e) | ((uint32_t)to_fp16_scaled(v.w, e) << 16);
-    *reinterpret_cast<uint2 *>(dst) = make_uint2(lo, hi);
+    *reinterpret_cast<uint2 *>(dst) = pack_fp16x4(v, e);
 }
 
 // Block of 4 waves = the 4 children of one tier-(d-1) node (linear indices
@@ -136,8 +144,9 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
     // TWO (64 x 64 leaves): the transpose runs in two halves of 32 source
     // rows (one k-panel of the transposed copy each), which halves the LDS
     // and lets more workgroups share a CU.  A 16-bit transposed row (128
-    // bytes) is then written in two halves; with BF16 copies that costs more
-    // than the extra workgroups gain, so they are transposed in one pass.
+    // bytes) spans both halves: each lane keeps its first-half values packed
+    // in registers and writes them with the second half, so every row is
+    // written whole.
     static_assert(!TWO || B == 64, "two-pass transpose for 64 x 64 leaves");
     constexpr int NPASS = TWO ? 2 : 1;
     constexpr int RH = B / NPASS, MH = M / NPASS;
@@ -228,6 +237,7 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
         }
     }
     // transposed copies through LDS, RH source rows at a time
+    uint2 stash[MH];                  // 16-bit copies, two passes: pass 0's half rows
 #pragma unroll
     for (int h = 0; h < NPASS; ++h) {
         if (pack) {
@@ -267,10 +277,21 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
                 if constexpr (B >= 32) {
                     if (tilesT16 != nullptr) {
                         uint16_t *d16 = tilesT16 + dl * (B * B) + Leaf16Layout<B>::index(rt, ct);
-                        if (scale16 != nullptr)
+                        if constexpr (NPASS == 2) {
+                            const uint2 b = scale16 != nullptr ? pack_fp16x4(t, e16) : pack_bf16x4(t);
+                            if (h == 0) {
+                                stash[i] = b;
+                            } else {
+                                // both halves of the 128-byte row together
+                                *reinterpret_cast<uint2 *>(tilesT16 + dl * (B * B) +
+                                                           Leaf16Layout<B>::index(rt, cr)) = stash[i];
+                                *reinterpret_cast<uint2 *>(d16) = b;
+                            }
+                        } else if (scale16 != nullptr) {
                             store_fp16x4(d16, t, e16);
-                        else
+                        } else {
                             store_bf16x4(d16, t);
+                        }
                     }
                 }
             }
@@ -325,15 +346,12 @@ static hipError_t launch_leaf_v(const float *A, int64_t n, float *tiles, float *
                                 double *sub, const uint32_t *keep, const uint32_t *slot,
                                 int32_t *scale16, uint32_t ntiles, hipStream_t s)
 {
-    // two passes except with BF16 copies (FP16 copies gain from the extra
-    // workgroups: their conversion is the longer part)
-    if constexpr (B == 64) {
-        if (t16 == nullptr || scale16 != nullptr)
-            return launch_leaf_t<B, VEC, SUB, true>(A, n, tiles, tilesT, t16, tT16, leaf, parent,
-                                                    sub, keep, slot, scale16, ntiles, s);
-    }
-    return launch_leaf_t<B, VEC, SUB, false>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub,
-                                             keep, slot, scale16, ntiles, s);
+    if constexpr (B == 64)
+        return launch_leaf_t<B, VEC, SUB, true>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub,
+                                                keep, slot, scale16, ntiles, s);
+    else
+        return launch_leaf_t<B, VEC, SUB, false>(A, n, tiles, tilesT, t16, tT16, leaf, parent,
+                                                 sub, keep, slot, scale16, ntiles, s);
 }
 
 template <int B, bool SUB>
