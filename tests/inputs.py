@@ -19,3 +19,18 @@ def arrow(n, w, seed):
     corner = strip[:, :w]
     A[:w, :w] = np.triu(corner) + np.triu(corner, 1).T
     return A
+
+
+def sum_order(b):
+    """2b x 2b matrix whose squared leaf norms depend on the summation order:
+    leaf (0, 0) holds 1 at (0, 0) and 2^-27 at (1, 0..3) (row-major pairwise
+    gives 1 + 2^-52, column-major or sequential orders give 1); leaves (1, 0)
+    and (1, 1) hold two entries 2^-27 each (squared norm 2^-53), leaf (0, 1)
+    is zero."""
+    A = np.zeros((2 * b, 2 * b), dtype=np.float32)
+    e = np.float32(2.0 ** -27)
+    A[0, 0] = 1.0
+    A[1, 0:4] = e
+    A[b, 0:2] = e
+    A[b + 5, b + 4:b + 6] = e
+    return A

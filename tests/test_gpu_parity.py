@@ -14,6 +14,7 @@ import math
 import numpy as np
 import pytest
 
+import inputs
 import oracle
 import workloads
 
@@ -64,12 +65,17 @@ def make(name):
         return workloads.exp_decay(512, 0.6, 0), None, 16, 1e-40
     if name == "algdecay-b64":
         return workloads.alg_decay(1000, 3.0, 0), None, 64, 1e-6
+    if name.startswith("sumorder-b"):
+        # leaf norms whose bits depend on the summation order (inputs.sum_order)
+        b = int(name[len("sumorder-b"):])
+        return inputs.sum_order(b), None, b, 0.0
     raise KeyError(name)
 
 
 CASES = ["expdecay-n1024", "expdecay-n1024-tau0", "ragged-b16", "odd-n-b32", "n2mod4-b64",
          "single-tile", "exact-tile-b64", "depth1-b64", "nonsym-b32", "zero-tiles-b16",
-         "denormals-b16", "denormals-tau-b16", "algdecay-b64"]
+         "denormals-b16", "denormals-tau-b16", "algdecay-b64", "sumorder-b16", "sumorder-b32",
+         "sumorder-b64"]
 
 
 class GpuRun:

@@ -368,3 +368,132 @@ def test_invalid_inputs_rejected():
         oracle.spamm(A, A, 16, -1.0)
     with pytest.raises(RuntimeError):
         oracle.spamm(A, A, 16, float("nan"))
+
+
+# --------------------------------------------------------------------------
+# Eq. norm: the summation ORDER of the FP64 squared norms (the reading that
+# fixes it: leaf = pairwise sum over the leaf's row-major flattened index,
+# parent = (s11 + s12) + (s21 + s22)).  The bound checks above hold for any
+# order; these cases are built so that only that order gives the stated bits.
+# --------------------------------------------------------------------------
+E27 = np.float32(2.0 ** -27)   # its square 2^-54 is a quarter of ulp(1) = 2^-52
+
+
+def order_leaf():
+    """A 16 x 16 leaf: x = 1 at (0, 0) and x = 2^-27 at (1, 0..3).
+
+    Squares: 1 and four times 2^-54.  Row-major flattened index e = 16 r + c:
+    the 1 sits at e = 0, the small squares at e = 16..19.
+
+    * pairwise over the row-major index: the block [0, 16) sums to 1, the
+      block [16, 32) to exactly 4 * 2^-54 = 2^-52, and 1 + 2^-52 is exact,
+      so s = 1 + 2^-52;
+    * pairwise over the column-major index (e' = 16 c + r): the small
+      squares sit at e' = 1, 17, 33, 49.  [0, 2) gives 1 + 2^-54 -> 1 (below
+      half an ulp), [16, 32) gives 2^-54 and 1 + 2^-54 -> 1, [32, 64) gives
+      2^-53 and 1 + 2^-53 is a tie that rounds to the even 1: s = 1;
+    * sequential from e = 0: each 1 + 2^-54 rounds back to 1: s = 1;
+    * numpy's sum of the same 256 values (eight strided partial sums per
+      block of 128): the partial holding the 1 absorbs e = 16, the partials
+      of e = 17, 18, 19 meet it as 2^-54 + 2^-53 pieces: s = 1.
+    """
+    A = np.zeros((16, 16), dtype=np.float32)
+    A[0, 0] = 1.0
+    A[1, 0:4] = E27
+    return A
+
+
+def test_leaf_norm_order_is_rowmajor_pairwise():
+    A = order_leaf()
+    want = 1.0 + 2.0 ** -52
+    assert oracle.norms(A, 16)[0][0, 0] == want
+    sq = (A.astype(np.float64) ** 2)
+
+    def pairwise(v):
+        if len(v) == 1:
+            return v[0]
+        h = len(v) // 2
+        return pairwise(v[:h]) + pairwise(v[h:])
+
+    def sequential(v):
+        s = 0.0
+        for x in v:
+            s += x
+        return s
+
+    # the hand-derived value is the row-major pairwise sum, and every other
+    # plausible order gives different bits on this leaf
+    assert pairwise(list(sq.ravel())) == want
+    assert pairwise(list(sq.T.ravel())) == 1.0             # column-major pairwise
+    assert sequential(sq.ravel()) == 1.0                    # row-major sequential
+    assert sequential(sq.T.ravel()) == 1.0
+    assert float(np.sum(sq.ravel())) == 1.0                 # numpy's blocked pairwise
+    assert math.fsum(sq.ravel()) == want                    # correctly rounded total
+
+
+def order_parents():
+    """A 32 x 32 matrix of four 16 x 16 leaves (tier 1):
+
+        s(0,0) = 1              (one entry 1.0)
+        s(0,1) = 0              (zero leaf)
+        s(1,0) = 2^-53          (two entries 2^-27: 2^-54 + 2^-54, exact)
+        s(1,1) = 2^-53          (two entries 2^-27)
+
+    Root by (s11 + s12) + (s21 + s22) = (1 + 0) + (2^-53 + 2^-53)
+    = 1 + 2^-52 (exact).  Column-first (s11 + s21) + (s12 + s22) =
+    (1 + 2^-53) + 2^-53 = 1 + 2^-53, a tie, -> 1.  Sequential
+    ((s11 + s12) + s21) + s22 = 1.  So the three orders give two values and
+    only the row-pair order gives 1 + 2^-52."""
+    A = np.zeros((32, 32), dtype=np.float32)
+    A[0, 0] = 1.0
+    A[16, 0:2] = E27
+    A[17 + 4, 20:22] = E27
+    return A
+
+
+def test_parent_norm_order_is_row_pairs():
+    tiers = oracle.norms(order_parents(), 16)
+    leaf = tiers[1]
+    assert leaf[0, 0] == 1.0 and leaf[0, 1] == 0.0
+    assert leaf[1, 0] == 2.0 ** -53 and leaf[1, 1] == 2.0 ** -53
+    assert tiers[0][0, 0] == 1.0 + 2.0 ** -52
+    # the alternatives this pin rejects
+    assert (leaf[0, 0] + leaf[1, 0]) + (leaf[0, 1] + leaf[1, 1]) == 1.0
+    assert ((leaf[0, 0] + leaf[0, 1]) + leaf[1, 0]) + leaf[1, 1] == 1.0
+
+
+def test_reordered_oracle_fails_the_order_pins(tmp_path):
+    """Mutation check on the CPU: the oracle recompiled with its leaf sum made
+    sequential, or its parent sum taken column-first, must fail the order
+    pins above (so those pins see the order, not only the bound)."""
+    import ctypes
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    src = open(oracle._SRC).read()
+    seq = src.replace(
+        "    int64_t h = len / 2;\n    return pairwise_sum(v, h) + pairwise_sum(v + h, len - h);",
+        "    double s = 0.0;\n    for (int64_t i = 0; i < len; ++i)\n        s += v[i];\n"
+        "    return s;")
+    col = src.replace("pa[I * Nt + J] = (s11 + s12) + (s21 + s22);",
+                      "pa[I * Nt + J] = (s11 + s21) + (s12 + s22);")
+    assert seq != src and col != src
+    for name, text, case, ok_value in (
+            ("seq", seq, order_leaf(), 1.0 + 2.0 ** -52),
+            ("col", col, order_parents(), 1.0 + 2.0 ** -52)):
+        c = tmp_path / f"oracle_{name}.c"
+        so = tmp_path / f"oracle_{name}.so"
+        c.write_text(text)
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-o", str(so), str(c), "-lm"])
+        lib = ctypes.CDLL(str(so))
+        lib.oracle_norms.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                     ctypes.c_void_p]
+        n = case.shape[0]
+        d, _ = oracle.depth(n, 16)
+        out = np.zeros(int(oracle._load().oracle_norms_len(d)), dtype=np.float64)
+        a = np.ascontiguousarray(case)
+        assert lib.oracle_norms(a.ctypes.data, n, 16, out.ctypes.data) == 0
+        assert out[0] != ok_value, name          # the mutant's root differs
+        assert oracle.norms(case, 16)[0][0, 0] == ok_value
