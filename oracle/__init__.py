@@ -69,6 +69,12 @@ def _load():
         lib.oracle_spamm_tiles_split_fmt.argtypes = [vp, vp, i64, i32, dbl, dbl, ctypes.c_int, vp,
                                                      i64, vp, vp, vp, ctypes.c_int]
         lib.oracle_spamm_tiles_split_fmt.restype = ctypes.c_int
+        lib.oracle_spamm_split_rel.argtypes = [vp, vp, i64, i32, dbl, dbl, ctypes.c_int, vp, vp,
+                                               i64, vp, vp, vp]
+        lib.oracle_spamm_split_rel.restype = ctypes.c_int
+        lib.oracle_spamm_tiles_split_rel.argtypes = [vp, vp, i64, i32, dbl, dbl, ctypes.c_int, vp,
+                                                     i64, vp, vp, vp, ctypes.c_int]
+        lib.oracle_spamm_tiles_split_rel.restype = ctypes.c_int
         lib.oracle_fp16_exponent.argtypes = [dbl]
         lib.oracle_fp16_exponent.restype = ctypes.c_int
         lib.oracle_fp16_scaled.argtypes = [ctypes.c_float, ctypes.c_int]
@@ -151,13 +157,25 @@ class Result:
         return int(self.Kt[-1])
 
 
+def _split_args(low_tol: float, low_rel: float):
+    """(entry point suffix, threshold argument) of a split product: an
+    absolute low_tol or a relative low_rel (theta), not both."""
+    if low_rel and low_tol:
+        raise ValueError("give low_tol or low_rel, not both")
+    return ("rel", float(low_rel)) if low_rel else ("fmt", float(low_tol))
+
+
 def spamm(A: np.ndarray, B: np.ndarray, b: int, tau: float, want_C: bool = True,
           want_keys: bool = True, cap: int | None = None, low_tol: float = 0.0,
-          low_fmt: str = "bf16") -> Result:
-    """Full recursive SpAMM product in FP64; low_tol > 0 selects split
-    precision (LOW products on operands rounded to bfloat16, or with
-    low_fmt="fp16" to binary16 at each leaf's power-of-two scale)."""
+          low_fmt: str = "bf16", low_rel: float = 0.0) -> Result:
+    """Full recursive SpAMM product in FP64; low_tol > 0 (absolute: LOW iff
+    the norm product is below low_tol) or low_rel > 0 (relative: below
+    low_rel ||A||_F ||B||_F) selects split precision (LOW products on
+    operands rounded to bfloat16, or with low_fmt="fp16" to binary16 at each
+    leaf's power-of-two scale)."""
     fmt = LOW_FMT[low_fmt]
+    kind, thr = _split_args(low_tol, low_rel)
+    fn = getattr(_load(), f"oracle_spamm_split_{kind}")
     A, B = _f32(A), _f32(B)
     n = A.shape[0]
     if B.shape[0] != n:
@@ -171,18 +189,15 @@ def spamm(A: np.ndarray, B: np.ndarray, b: int, tau: float, want_C: bool = True,
     if want_keys:
         if cap is None:
             # count first so the key buffer is exactly sized
-            rc = _load().oracle_spamm_split_fmt(A.ctypes.data, B.ctypes.data, n, b, float(tau),
-                                                float(low_tol), fmt, None, None, 0,
-                                                nk.ctypes.data, Kt.ctypes.data, kl.ctypes.data)
+            rc = fn(A.ctypes.data, B.ctypes.data, n, b, float(tau), thr, fmt, None, None, 0,
+                    nk.ctypes.data, Kt.ctypes.data, kl.ctypes.data)
             if rc:
                 raise RuntimeError(f"oracle_spamm -> {rc}")
             cap = int(nk[0])
         keys = np.empty(max(cap, 1), dtype=np.uint64)
-    rc = _load().oracle_spamm_split_fmt(A.ctypes.data, B.ctypes.data, n, b, float(tau),
-                                        float(low_tol), fmt, None if C is None else C.ctypes.data,
-                                    None if keys is None else keys.ctypes.data,
-                                    0 if keys is None else cap, nk.ctypes.data, Kt.ctypes.data,
-                                    kl.ctypes.data)
+    rc = fn(A.ctypes.data, B.ctypes.data, n, b, float(tau), thr, fmt,
+            None if C is None else C.ctypes.data, None if keys is None else keys.ctypes.data,
+            0 if keys is None else cap, nk.ctypes.data, Kt.ctypes.data, kl.ctypes.data)
     if rc:
         raise RuntimeError(f"oracle_spamm -> {rc}")
     if keys is not None:
@@ -192,13 +207,16 @@ def spamm(A: np.ndarray, B: np.ndarray, b: int, tau: float, want_C: bool = True,
 
 def spamm_tiles(A: np.ndarray, B: np.ndarray, b: int, tau: float, tiles,
                 threads: int = 1, want_klists: bool = False, low_tol: float = 0.0,
-                low_fmt: str = "bf16"):
+                low_fmt: str = "bf16", low_rel: float = 0.0):
     """Per-tile recursion for the output tiles ``tiles`` ((I, J) pairs).
 
     Returns (Ctiles [ntiles, b, b] float64, counts [ntiles], klists or None);
     klists[s, :counts[s]] are the kept K values of tile s in ascending order,
-    with 1 << 30 added for a LOW product (split precision, low_tol > 0).
+    with 1 << 30 added for a LOW product (split precision, low_tol > 0 or
+    low_rel > 0 as for spamm; the roots are those of the whole operands).
     """
+    kind, thr = _split_args(low_tol, low_rel)
+    fn = getattr(_load(), f"oracle_spamm_tiles_split_{kind}")
     A, B = _f32(A), _f32(B)
     n = A.shape[0]
     d, _ = depth(n, b)
@@ -207,11 +225,9 @@ def spamm_tiles(A: np.ndarray, B: np.ndarray, b: int, tau: float, tiles,
     Ct = np.empty((m, b, b), dtype=np.float64)
     counts = np.zeros(m, dtype=np.int64)
     kl = np.empty((m, 1 << d), dtype=np.int32) if want_klists else None
-    rc = _load().oracle_spamm_tiles_split_fmt(A.ctypes.data, B.ctypes.data, n, b, float(tau),
-                                              float(low_tol), LOW_FMT[low_fmt], t.ctypes.data,
-                                              m, Ct.ctypes.data,
-                                          counts.ctypes.data,
-                                          None if kl is None else kl.ctypes.data, int(threads))
+    rc = fn(A.ctypes.data, B.ctypes.data, n, b, float(tau), thr, LOW_FMT[low_fmt], t.ctypes.data,
+            m, Ct.ctypes.data, counts.ctypes.data, None if kl is None else kl.ctypes.data,
+            int(threads))
     if rc:
         raise RuntimeError(f"oracle_spamm_tiles -> {rc}")
     return Ct, counts, kl

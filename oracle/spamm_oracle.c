@@ -31,7 +31,10 @@
  * the product of two FP32 values is exact in FP64.
  *
  * Split precision (the precision extension the paper's conclusions point
- * to): a kept leaf product is LOW iff s_A * s_B < low_tol^2; its operands
+ * to): a kept leaf product is LOW iff s_A * s_B < L2, with L2 = low_tol^2
+ * for an absolute threshold, or L2 = (theta^2 * s_A0) * s_B0 for a relative
+ * one (s_A0, s_B0 the root squared norms: norm product < theta ||A|| ||B||,
+ * every step in FP64 in that order); its operands
  * are rounded elementwise to bfloat16 (8 significant bits, round to nearest,
  * ties to even) before the (exact, FP64) products; other products are
  * unchanged.  The class is part of the task key (bit 63).  With binary16
@@ -335,6 +338,9 @@ static int check_inputs(int64_t n, int32_t b, double tau)
 int oracle_spamm_split_fmt(const float *A, const float *B, int64_t n, int32_t b, double tau,
                            double low_tol, int fmt, double *C, uint64_t *keys, int64_t cap,
                            int64_t *nkeys, int64_t *Kt, int64_t *Klow);
+static int run_split(const float *A, const float *B, int64_t n, int32_t b, double tau,
+                     double low_tol, double theta, int fmt, double *C, uint64_t *keys,
+                     int64_t cap, int64_t *nkeys, int64_t *Kt, int64_t *Klow);
 
 int oracle_spamm(const float *A, const float *B, int64_t n, int32_t b, double tau,
                  double *C, uint64_t *keys, int64_t cap, int64_t *nkeys, int64_t *Kt)
@@ -358,11 +364,49 @@ int oracle_spamm_split_fmt(const float *A, const float *B, int64_t n, int32_t b,
                            double low_tol, int fmt, double *C, uint64_t *keys, int64_t cap,
                            int64_t *nkeys, int64_t *Kt, int64_t *Klow)
 {
+    return run_split(A, B, n, b, tau, low_tol, 0.0, fmt, C, keys, cap, nkeys, Kt, Klow);
+}
+
+/* Split precision with a relative threshold: LOW iff s_A s_B <
+ * (theta^2 s_A0) s_B0, i.e. ||A_ik|| ||B_kj|| < theta ||A||_F ||B||_F on the
+ * stored squared norms, the roots s_A0, s_B0 taken from this product's own
+ * norm pyramids. */
+int oracle_spamm_split_rel(const float *A, const float *B, int64_t n, int32_t b, double tau,
+                           double theta, int fmt, double *C, uint64_t *keys, int64_t cap,
+                           int64_t *nkeys, int64_t *Kt, int64_t *Klow)
+{
+    return run_split(A, B, n, b, tau, 0.0, theta, fmt, C, keys, cap, nkeys, Kt, Klow);
+}
+
+/* L2 of the LOW test: low_tol^2 (absolute) or (theta^2 s_A0) s_B0 (relative). */
+static double low_threshold(double low_tol, double theta, const double *sA, const double *sB)
+{
+    if (theta > 0.0) {
+        double t2 = theta * theta;
+        double u = t2 * sA[0];
+        return u * sB[0];
+    }
+    return low_tol * low_tol;
+}
+
+static int check_split(double low_tol, double theta, int fmt)
+{
+    if (!(low_tol >= 0.0) || isinf(low_tol) || (fmt != 0 && fmt != 1))
+        return OR_EINVAL;
+    if (!(theta >= 0.0) || isinf(theta) || (theta > 0.0 && low_tol > 0.0))
+        return OR_EINVAL;
+    return OR_OK;
+}
+
+static int run_split(const float *A, const float *B, int64_t n, int32_t b, double tau,
+                     double low_tol, double theta, int fmt, double *C, uint64_t *keys,
+                     int64_t cap, int64_t *nkeys, int64_t *Kt, int64_t *Klow)
+{
     int rc = check_inputs(n, b, tau);
     if (rc)
         return rc;
-    if (!(low_tol >= 0.0) || isinf(low_tol) || (fmt != 0 && fmt != 1))
-        return OR_EINVAL;
+    if ((rc = check_split(low_tol, theta, fmt)))
+        return rc;
     mul_ctx x;
     memset(&x, 0, sizeof x);
     int64_t np;
@@ -382,7 +426,7 @@ int oracle_spamm_split_fmt(const float *A, const float *B, int64_t n, int32_t b,
     x.n = n;
     x.b = b;
     x.T2 = tau * tau;
-    x.L2 = low_tol * low_tol;
+    x.L2 = low_threshold(low_tol, theta, sA, sB);
     x.fmt = fmt;
     x.sA = sA;
     x.sB = sB;
@@ -442,6 +486,10 @@ int oracle_spamm_tiles_split_fmt(const float *A, const float *B, int64_t n, int3
                                  double tau, double low_tol, int fmt, const int64_t *tiles,
                                  int64_t ntiles, double *Ctiles, int64_t *counts,
                                  int32_t *klists, int nthreads);
+static int run_tiles(const float *A, const float *B, int64_t n, int32_t b, double tau,
+                     double low_tol, double theta, int fmt, const int64_t *tiles,
+                     int64_t ntiles, double *Ctiles, int64_t *counts, int32_t *klists,
+                     int nthreads);
 
 int oracle_spamm_tiles(const float *A, const float *B, int64_t n, int32_t b, double tau,
                        const int64_t *tiles, int64_t ntiles, double *Ctiles,
@@ -465,11 +513,31 @@ int oracle_spamm_tiles_split_fmt(const float *A, const float *B, int64_t n, int3
                                  int64_t ntiles, double *Ctiles, int64_t *counts,
                                  int32_t *klists, int nthreads)
 {
+    return run_tiles(A, B, n, b, tau, low_tol, 0.0, fmt, tiles, ntiles, Ctiles, counts, klists,
+                     nthreads);
+}
+
+/* As oracle_spamm_tiles_split_fmt with the relative LOW threshold of
+ * oracle_spamm_split_rel (roots of the whole operands' pyramids). */
+int oracle_spamm_tiles_split_rel(const float *A, const float *B, int64_t n, int32_t b,
+                                 double tau, double theta, int fmt, const int64_t *tiles,
+                                 int64_t ntiles, double *Ctiles, int64_t *counts,
+                                 int32_t *klists, int nthreads)
+{
+    return run_tiles(A, B, n, b, tau, 0.0, theta, fmt, tiles, ntiles, Ctiles, counts, klists,
+                     nthreads);
+}
+
+static int run_tiles(const float *A, const float *B, int64_t n, int32_t b, double tau,
+                     double low_tol, double theta, int fmt, const int64_t *tiles,
+                     int64_t ntiles, double *Ctiles, int64_t *counts, int32_t *klists,
+                     int nthreads)
+{
     int rc = check_inputs(n, b, tau);
     if (rc)
         return rc;
-    if (!(low_tol >= 0.0) || isinf(low_tol) || (fmt != 0 && fmt != 1))
-        return OR_EINVAL;
+    if ((rc = check_split(low_tol, theta, fmt)))
+        return rc;
     mul_ctx x;
     memset(&x, 0, sizeof x);
     int64_t np;
@@ -493,7 +561,7 @@ int oracle_spamm_tiles_split_fmt(const float *A, const float *B, int64_t n, int3
     x.n = n;
     x.b = b;
     x.T2 = tau * tau;
-    x.L2 = low_tol * low_tol;
+    x.L2 = low_threshold(low_tol, theta, sA, sB);
     x.fmt = fmt;
     x.sA = sA;
     x.sB = sB;

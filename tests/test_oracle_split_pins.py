@@ -253,3 +253,108 @@ def test_fp16_error_within_rounding_bound_and_below_bf16():
     assert np.all(err16 <= bound * (1 + 1e-9) + 1e-300)
     errb = np.abs(b16.C - exact.C).max()
     assert 0 < err16.max() < errb / 4
+
+
+# --------------------------------------------------------------------------
+# Relative LOW threshold: LOW iff ||A_ik|| ||B_kj|| < theta ||A||_F ||B||_F
+# (norm product small relative to ||A|| ||B||, the precision outlook of
+# Sec. VI), taken as s_A s_B < (theta^2 s_A0) s_B0 on the stored squared norms.
+# --------------------------------------------------------------------------
+def exact_sq_norms(P, b):
+    """Exact (rational) squared Frobenius norm of every leaf of the padded
+    matrix and of the whole matrix: sums of squares of FP32 values, done in
+    Fractions (no rounding at all)."""
+    from fractions import Fraction
+    N = P.shape[0] // b
+    leaf = [[sum((Fraction(float(x)) ** 2 for x in P[I * b:(I + 1) * b, J * b:(J + 1) * b].ravel()
+                  if x != 0), Fraction(0)) for J in range(N)] for I in range(N)]
+    total = sum((leaf[I][J] for I in range(N) for J in range(N)), Fraction(0))
+    return leaf, total
+
+
+@pytest.mark.parametrize("theta,tau", [(1e-2, 1e-6), (1e-3, 1e-8), (3e-2, 0.0)])
+def test_relative_low_set_against_exact_norms(theta, tau):
+    """The relative LOW class equals the exact-arithmetic classification
+    ||A_ik|| ||B_kj|| < theta ||A|| ||B|| (rational squared norms; triples
+    within 1e-9 of the threshold are left out)."""
+    from fractions import Fraction
+    A, B = decay(160, 0.05, 21), decay(160, 0.08, 22, sym=False)
+    b = 32
+    r = oracle.spamm(A, B, b, tau, want_C=False, low_rel=theta)
+    d, np_ = oracle.depth(160, b)
+    PA = np.zeros((np_, np_), dtype=np.float32)
+    PB = np.zeros((np_, np_), dtype=np.float32)
+    PA[:160, :160], PB[:160, :160] = A, B
+    sA, SA = exact_sq_norms(PA, b)
+    sB, SB = exact_sq_norms(PB, b)
+    th2 = Fraction(theta) ** 2
+    kept = {int(k) & ~(1 << 63): int(k) >> 63 for k in r.keys}
+    N = 1 << d
+    checked = 0
+    for I in range(N):
+        for K in range(N):
+            for J in range(N):
+                key = (oracle.linear_index(I, J) << 32) | K
+                if key not in kept:
+                    continue
+                lhs, rhs = sA[I][K] * sB[K][J], th2 * SA * SB
+                if abs(lhs - rhs) <= Fraction(1, 10 ** 9) * rhs:
+                    continue
+                assert kept[key] == int(lhs < rhs), (I, K, J)
+                checked += 1
+    assert checked > 0 and 0 < r.Klow < r.K
+
+
+def test_relative_low_is_scale_invariant():
+    """Scaling A by 2^7 and B by 2^-5 (exact) leaves the relative classes
+    unchanged; the same absolute threshold changes them (so a threshold
+    that ignored the roots would fail here)."""
+    A, B = decay(200, 0.05, 23), decay(200, 0.07, 24, sym=False)
+    b, theta = 32, 2e-3
+    base = oracle.spamm(A, B, b, 0.0, want_C=False, low_rel=theta)
+    As, Bs = (A * np.float32(2.0 ** 7)), (B * np.float32(2.0 ** -5))
+    scaled = oracle.spamm(As, Bs, b, 0.0, want_C=False, low_rel=theta)
+    assert 0 < base.Klow < base.K
+    assert np.array_equal(base.keys, scaled.keys) and base.Klow == scaled.Klow
+    # an absolute threshold equal to theta ||A|| ||B|| of the unscaled pair
+    sA0 = oracle.norms(A, b)[0][0, 0]
+    sB0 = oracle.norms(B, b)[0][0, 0]
+    low = theta * np.sqrt(sA0) * np.sqrt(sB0)
+    a1 = oracle.spamm(A, B, b, 0.0, want_C=False, low_tol=low)
+    a2 = oracle.spamm(As, Bs, b, 0.0, want_C=False, low_tol=low)
+    assert a1.Klow != a2.Klow
+
+
+def test_relative_low_product_and_tiles():
+    """C of a relative split product equals the absolute split product at the
+    matching threshold when no norm product sits near it, and the per-leaf
+    recursion gives the same classes and values."""
+    A = decay(192, 0.05, 25)
+    b, tau, theta = 32, 1e-7, 1e-3
+    r = oracle.spamm(A, A, b, tau, low_rel=theta)
+    s = oracle.norms(A, b)
+    low = theta * s[0][0, 0]                          # theta ||A||^2
+    leaf = s[-1]
+    prod = leaf[:, :, None] * leaf[None, :, :]
+    assert np.all(np.abs(prod - low * low) > 1e-9 * low * low)
+    a = oracle.spamm(A, A, b, tau, low_tol=low)
+    assert np.array_equal(r.keys, a.keys) and np.array_equal(r.C, a.C) and 0 < r.Klow < r.K
+    N = leaf.shape[0]
+    tiles = [(I, J) for I in range(N) for J in range(N)]
+    Ct, counts, kl = oracle.spamm_tiles(A, A, b, tau, tiles, threads=2, want_klists=True,
+                                        low_rel=theta)
+    assert counts.sum() == r.K
+    assert int(sum(int((kl[s_, :counts[s_]] >> 30).sum()) for s_ in range(len(tiles)))) == r.Klow
+    for s_, (I, J) in enumerate(tiles):
+        r0, c0 = I * b, J * b
+        blk = r.C[r0:r0 + b, c0:c0 + b]
+        assert np.array_equal(Ct[s_][:blk.shape[0], :blk.shape[1]], blk)
+
+
+def test_relative_low_rejects_bad_arguments():
+    A = decay(64, 0.1, 26)
+    with pytest.raises(ValueError):
+        oracle.spamm(A, A, 32, 0.0, low_tol=1e-3, low_rel=1e-3)
+    for bad in (-1e-3, float("inf"), float("nan")):
+        with pytest.raises(RuntimeError):
+            oracle.spamm(A, A, 32, 0.0, low_rel=bad)
