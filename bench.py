@@ -228,41 +228,16 @@ def matched_error(sp, wl, A, dA, C, tau, leaf, n, N, reps=2):
 # ---------------------------------------------------------------------------
 # Serving: continuous batching of a stream of products and squaring chains
 # ---------------------------------------------------------------------------
-def serve_matrix(torch, req, dev):
-    """Request r's input on the device: symmetric u ~ U(-1, 1) from a torch
-    generator seeded 1000 + r, times exp(-rate |i - j|); a chain starts from
-    X_0 = A / max_i sum_j |a_ij| (Gershgorin), so no power overflows."""
-    g = torch.Generator(device=dev)
-    g.manual_seed(req.seed)
-    n = req.n
-    u = torch.rand((n, n), generator=g, device=dev, dtype=torch.float32).mul_(2.0).sub_(1.0)
-    A = torch.triu(u)
-    A += torch.triu(u, 1).T
-    del u
-    i = torch.arange(n, device=dev, dtype=torch.float32)
-    A *= torch.exp((i[:, None] - i[None, :]).abs_().mul_(-req.rate))
-    if req.chain_len:
-        A /= A.abs().sum(dim=1).max()
-    return A
-
-
 def percentile(v, q):
     import numpy as np
     return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
 
 
 def serve_inputs(torch, reqs, dev):
-    """Every request's input and absolute LOW threshold, generated on the
-    device before any timed run (so the runs measure the server, not the
-    generator).  low_tol = theta ||A||_F^2 for split requests (A = B)."""
-    from workloads import SERVE_THETA
-    inputs = {}
-    for req in reqs:
-        A = serve_matrix(torch, req, dev)
-        low = 0.0
-        if req.split:
-            low = SERVE_THETA * float(torch.linalg.vector_norm(A, dtype=torch.float64)) ** 2
-        inputs[req.index] = (A, low)
+    """Every request's input, generated on the device before any timed run
+    (so the runs measure the server, not the generator)."""
+    from workloads import serve_matrix
+    inputs = {req.index: serve_matrix(torch, req, dev) for req in reqs}
     torch.cuda.synchronize()
     return inputs
 
@@ -272,7 +247,7 @@ def serve_run(sp, torch, srv, reqs, inputs, qps=None, window=16, keep=()):
     `qps`, or closed loop with `window` requests outstanding (qps None).
     Returns per-request results, timing and the C of the requests in `keep`."""
     import numpy as np
-    from workloads import SERVE_LEAF
+    from workloads import SERVE_LEAF, SERVE_THETA
     out, kept = {}, {}
     pending = {}
     arrivals = None
@@ -304,14 +279,15 @@ def serve_run(sp, torch, srv, reqs, inputs, qps=None, window=16, keep=()):
             while time.perf_counter() < arrivals[k]:
                 if not sweep():
                     time.sleep(50e-6)
-        A, low = inputs[req.index]
+        A = inputs[req.index]
         C = torch.empty_like(A)
         t_sub = time.perf_counter()
         t_first = t_first or t_sub
         t_last = t_sub
         tk = srv.submit(A, C, req.tau, SERVE_LEAF,
                         precision=sp.PREC_SPLIT_BF16 if req.split else sp.PREC_FP32,
-                        low_tol=low, chain_len=req.chain_len, sync=False)
+                        low_rel=SERVE_THETA if req.split else 0.0, chain_len=req.chain_len,
+                        sync=False)
         pending[tk] = (req, C)
     while pending:
         if not sweep():
@@ -355,22 +331,31 @@ def serve_summary(reqs, res, tm, qps):
 
 def serve_verify(sp, torch, reqs, kept, inputs):
     """Requests kept from the mix, recomputed alone through the one-call API
-    (tree build + multiply per step): the bits must agree."""
-    from workloads import SERVE_LEAF
+    (tree build + multiply per step): the bits must agree.  Returns the
+    number that agree and, per kept chain, its kept (and LOW) products per
+    step."""
+    from workloads import SERVE_LEAF, SERVE_THETA
     ok = 0
+    per_step = {}
     for req in reqs:
         if req.index not in kept:
             continue
-        X, low = inputs[req.index]
+        X = inputs[req.index]
         prec = sp.PREC_SPLIT_BF16 if req.split else sp.PREC_FP32
+        ks = []
         for _ in range(max(1, req.chain_len)):
             t = sp.build_tree(X, SERVE_LEAF, bf16=req.split)
             C = torch.empty_like(X)
-            sp.multiply_ex(t, t, req.tau, C, precision=prec, low_tol=low)
+            st = sp.multiply_ex(t, t, req.tau, C, precision=prec,
+                                low_rel=SERVE_THETA if req.split else 0.0)
+            ks.append([st["tasks"], st["tasks_low"]])
             t.free()
             X = C
         ok += int(torch.equal(X, kept[req.index]))
-    return ok
+        if req.chain_len:
+            per_step[f"request {req.index} (n={req.n}, rate={req.rate:.3f}, tau={req.tau:g}, "
+                     f"{'split' if req.split else 'fp32'})"] = ks
+    return ok, per_step
 
 
 def serve_one_call(sp, torch, reqs, inputs):
@@ -378,16 +363,17 @@ def serve_one_call(sp, torch, reqs, inputs):
     build + multiply per step, each synchronizing): the plain GPU form the
     server is compared with.  Results are those of the server bit for bit
     (serve_verify), so the errors match."""
-    from workloads import SERVE_LEAF
+    from workloads import SERVE_LEAF, SERVE_THETA
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for req in reqs:
-        X, low = inputs[req.index]
+        X = inputs[req.index]
         prec = sp.PREC_SPLIT_BF16 if req.split else sp.PREC_FP32
         for _ in range(max(1, req.chain_len)):
             t = sp.build_tree(X, SERVE_LEAF, bf16=req.split)
             C = torch.empty_like(X)
-            sp.multiply_ex(t, t, req.tau, C, precision=prec, low_tol=low)
+            sp.multiply_ex(t, t, req.tau, C, precision=prec,
+                           low_rel=SERVE_THETA if req.split else 0.0)
             t.free()
             X = C
     torch.cuda.synchronize()
@@ -447,7 +433,7 @@ def serve_bench(sp, torch, dev, count, slots, budget_gib):
             print(f"{frac}x load: {s['arrival_qps']} req/s offered, p50 {s['p50_ms']} ms, "
                   f"p99 {s['p99_ms']} ms", file=sys.stderr, flush=True)
             if frac == 0.8:
-                verified = serve_verify(sp, torch, reqs, kept, inputs)
+                verified, chain_steps = serve_verify(sp, torch, reqs, kept, inputs)
         info = srv.info()
     finally:
         srv.destroy()
@@ -467,6 +453,7 @@ def serve_bench(sp, torch, dev, count, slots, budget_gib):
         "saturation": sat,
         "loads": loads,
         "verified_bitwise_vs_alone": f"{verified}/{len(keep_idx)}",
+        "chain_kept_products_per_step": chain_steps,
         "one_call_sequential": one,
         "served_speedup_vs_one_call": round(sat["throughput_rps"] / one["requests_per_s"], 3),
         "server": {k: info[k] for k in ("max_batch", "peak_active", "peak_used", "budget")},

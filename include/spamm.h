@@ -111,9 +111,17 @@ int spamm_build_tree(const float *A, int64_t n, int32_t leaf, void *stream,
  *              entry is below 2^14; rounded to nearest even, a result below
  *              2^-14 (a binary16 subnormal) flushed to zero; the product is
  *              scaled back by 2^-(eA + eB)) with FP32
- *              accumulation, HIGH products stay FP32.  0 = nothing is LOW.
- *              A relative threshold theta ||A||_F ||B||_F is low_tol =
- *              theta * sqrt(norm2_A) * sqrt(norm2_B) (spamm_tree_info).
+ *              accumulation, HIGH products stay FP32.  0 = nothing is LOW
+ *              (unless low_rel is set).
+ *   low_rel    split only, instead of low_tol: the relative threshold theta
+ *              of the precision split, LOW iff ||A_ik||_F ||B_kj||_F <
+ *              theta ||A||_F ||B||_F, evaluated on the device as
+ *              fl64(s_A s_B) < fl64(fl64(fl64(theta^2) s_A0) s_B0), where
+ *              s_A0 and s_B0 are the FP64 roots of the two trees' own norm
+ *              pyramids (so every product, every step of a squaring chain
+ *              included, is split against its own operands' norms).
+ *              Finite, 0 or >= 1e-150; at most one of low_tol and low_rel
+ *              may be non-zero.
  */
 typedef struct spamm_opts {
     double  tau;
@@ -126,6 +134,7 @@ typedef struct spamm_opts {
                         /* (the paper's conditional products inside a leaf, Alg. 2);   */
                         /* the performed set equals the cull of a tree with 32 x 32    */
                         /* leaves.  0: whole leaf products.                             */
+    double  low_rel;    /* split only: relative LOW threshold theta (see above)        */
 } spamm_opts;
 
 /* As spamm_build_tree, with flags (SPAMM_TREE_BF16: also store BF16 copies of
@@ -222,7 +231,8 @@ int spamm_symbolic(const spamm_tree *A, const spamm_tree *B, double tau,
  * also classed LOW or HIGH (see spamm_opts); both trees must have been built
  * with SPAMM_TREE_BF16 (SPAMM_TREE_FP16).
  * Errors as spamm_symbolic, plus SPAMM_E_INVAL for an unknown precision, a
- * bad low_tol (negative, NaN/Inf, 0 < low_tol < 1e-150), missing 16-bit copies,
+ * bad low_tol or low_rel (negative, NaN/Inf, 0 < x < 1e-150, both non-zero),
+ * missing 16-bit copies,
  * or sub_cull with split precision, n_b != 64 or trees without sub-norms.
  * A plan refers to both trees: they must not be freed before the plan.
  */
@@ -319,9 +329,11 @@ typedef struct spamm_request {
     int32_t leaf;        /* n_b in {16, 32, 64} (32 or 64 for split precision)         */
     int32_t precision;   /* SPAMM_PREC_FP32, SPAMM_PREC_SPLIT_BF16 or _SPLIT_FP16      */
     double tau;          /* SpAMM tolerance of every product (as spamm_symbolic)      */
-    double low_tol;      /* split precision: LOW threshold (as spamm_opts)            */
+    double low_tol;      /* split precision: absolute LOW threshold (as spamm_opts)   */
     int32_t chain_len;   /* 0: C = A B.  L in 1..64: X_0 = A, X_{s+1} = X_s X_s under  */
                          /* tau (each X_s rebuilt into a tree), C = X_L               */
+    double low_rel;      /* split precision: relative LOW threshold theta (as         */
+                         /* spamm_opts), taken against each step's own roots         */
 } spamm_request;
 
 typedef struct spamm_result {
@@ -362,7 +374,8 @@ int spamm_server_create(size_t hbm_budget, int32_t max_slots, spamm_server **out
 /*
  * Device bytes of a request's slot arena (its trees and task arena, buffers
  * at 256-byte aligned offsets); also validates the request (host only, no device call).  Errors: SPAMM_E_INVAL (null
- * pointers, n < 1, bad leaf, precision, tau, low_tol, chain_len outside 0..64,
+ * pointers, n < 1, bad leaf, precision, tau, low_tol, low_rel (as
+ * spamm_symbolic_ex), chain_len outside 0..64,
  * a chain with B not NULL and not A, split precision with leaf 16),
  * SPAMM_E_RANGE (more than 1024 leaves per dimension).
  */

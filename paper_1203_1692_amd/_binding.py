@@ -45,7 +45,8 @@ class SpammError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("low_tol", ctypes.c_double), ("sub_cull", ctypes.c_int32)]
+                ("low_tol", ctypes.c_double), ("sub_cull", ctypes.c_int32),
+                ("low_rel", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -80,7 +81,7 @@ class Request(ctypes.Structure):
     _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
                 ("n", ctypes.c_int64), ("leaf", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("low_tol", ctypes.c_double),
-                ("chain_len", ctypes.c_int32)]
+                ("chain_len", ctypes.c_int32), ("low_rel", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
@@ -359,20 +360,17 @@ def build_tree_sparse(A, leaf: int, tau: float, norm2_other: float = 0.0, stream
     return t
 
 
-def _opts(tau, precision, low_tol, sub_cull=False) -> Opts:
-    return Opts(float(tau), int(precision), float(low_tol), 1 if sub_cull else 0)
-
-
-def relative_low_tol(A: Tree, B: Tree, theta: float) -> float:
-    """low_tol for the split class 'norm product < theta ||A||_F ||B||_F'."""
-    import math
-    return float(theta) * math.sqrt(A.norm2) * math.sqrt(B.norm2)
+def _opts(tau, precision, low_tol, sub_cull=False, low_rel=0.0) -> Opts:
+    return Opts(float(tau), int(precision), float(low_tol), 1 if sub_cull else 0, float(low_rel))
 
 
 def symbolic(A: Tree, B: Tree, tau: float, stream=None, precision: int = PREC_FP32,
-             low_tol: float = 0.0, sub_cull: bool = False) -> Plan:
+             low_tol: float = 0.0, sub_cull: bool = False, low_rel: float = 0.0) -> Plan:
+    """Symbolic multiply; split precision classes a product LOW below the
+    absolute low_tol, or below low_rel ||A||_F ||B||_F (relative theta,
+    evaluated by the library from the trees' roots)."""
     h = ctypes.c_void_p()
-    o = _opts(tau, precision, low_tol, sub_cull)
+    o = _opts(tau, precision, low_tol, sub_cull, low_rel)
     _check(load().spamm_symbolic_ex(A.handle, B.handle, ctypes.byref(o), _stream(stream),
                                     ctypes.byref(h)), "spamm_symbolic")
     return Plan(h, A, B)
@@ -388,13 +386,13 @@ def multiply(A: Tree, B: Tree, tau: float, C, stream=None):
 
 
 def multiply_ex(A: Tree, B: Tree, tau: float, C, stream=None, precision: int = PREC_FP32,
-                low_tol: float = 0.0, sub_cull: bool = False) -> dict:
+                low_tol: float = 0.0, sub_cull: bool = False, low_rel: float = 0.0) -> dict:
     """C = A B under the SpAMM condition, timed (synchronizes); returns stats."""
     _device_matrix(C, "C")
     if C.shape[0] != A.n:
         raise ValueError("C has the wrong shape")
     st = Stats()
-    o = _opts(tau, precision, low_tol, sub_cull)
+    o = _opts(tau, precision, low_tol, sub_cull, low_rel)
     _check(load().spamm_multiply_opts(A.handle, B.handle, ctypes.byref(o),
                                       ctypes.c_void_p(C.data_ptr()), _stream(stream),
                                       ctypes.byref(st)), "spamm_multiply_opts")
@@ -403,16 +401,19 @@ def multiply_ex(A: Tree, B: Tree, tau: float, C, stream=None, precision: int = P
 
 # ---- serving -----------------------------------------------------------------
 
-def _request(A_ptr, B_ptr, C_ptr, n, leaf, tau, precision, low_tol, chain_len) -> Request:
+def _request(A_ptr, B_ptr, C_ptr, n, leaf, tau, precision, low_tol, chain_len,
+             low_rel=0.0) -> Request:
     return Request(A_ptr, B_ptr, C_ptr, int(n), int(leaf), int(precision), float(tau),
-                   float(low_tol), int(chain_len))
+                   float(low_tol), int(chain_len), float(low_rel))
 
 
 def request_footprint(n: int, leaf: int, tau: float = 0.0, precision: int = PREC_FP32,
-                      low_tol: float = 0.0, chain_len: int = 0, distinct_b: bool = False) -> int:
+                      low_tol: float = 0.0, chain_len: int = 0, distinct_b: bool = False,
+                      low_rel: float = 0.0) -> int:
     """Device bytes a server reserves for such a request (host-only check;
     the placeholder pointers are never dereferenced)."""
-    r = _request(1, 2 if distinct_b else None, 3, n, leaf, tau, precision, low_tol, chain_len)
+    r = _request(1, 2 if distinct_b else None, 3, n, leaf, tau, precision, low_tol, chain_len,
+                 low_rel)
     out = ctypes.c_size_t()
     _check(load().spamm_request_footprint(ctypes.byref(r), ctypes.byref(out)),
            "spamm_request_footprint")
@@ -442,9 +443,12 @@ class Server:
         return self._h
 
     def submit(self, A, C, tau: float, leaf: int, B=None, precision: int = PREC_FP32,
-               low_tol: float = 0.0, chain_len: int = 0, sync: bool = True) -> int:
+               low_tol: float = 0.0, chain_len: int = 0, sync: bool = True,
+               low_rel: float = 0.0) -> int:
         """Queue a request; `sync` first waits for the current stream so that
-        A and B hold their values when the server's streams read them."""
+        A and B hold their values when the server's streams read them.
+        low_rel is the relative split threshold theta, taken by the library
+        against the roots of each product's (each chain step's) operands."""
         import torch
         _device_matrix(A, "A")
         _device_matrix(C, "C")
@@ -456,7 +460,7 @@ class Server:
         if sync:
             torch.cuda.current_stream().synchronize()
         r = _request(A.data_ptr(), None if B is None else B.data_ptr(), C.data_ptr(), A.shape[0],
-                     leaf, tau, precision, low_tol, chain_len)
+                     leaf, tau, precision, low_tol, chain_len, low_rel)
         t = ctypes.c_uint64()
         _check(load().spamm_submit(self.handle, ctypes.byref(r), ctypes.byref(t)), "spamm_submit")
         self._keep[t.value] = (A, B, C)

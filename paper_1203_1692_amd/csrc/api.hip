@@ -324,12 +324,13 @@ static int check_tol(double v, const char *name)
     return SPAMM_OK;
 }
 
-int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
-                   hipStream_t s, void *arena, spamm_plan **out)
+// Validates a product's operands and options against device `dev` and fills
+// *p (host fields only, no allocation, no device call); *bytes receives the
+// size of the plan's one device block (its buffers at 256-byte aligned
+// offsets).
+static int plan_setup(spamm_plan *p, const spamm_tree *A, const spamm_tree *B,
+                      const spamm_opts *opts, int dev, hipStream_t s, size_t *bytes)
 {
-    if (out == nullptr)
-        return fail(SPAMM_E_INVAL, "out is NULL");
-    *out = nullptr;
     if (A == nullptr || B == nullptr || opts == nullptr)
         return fail(SPAMM_E_INVAL, "tree or options NULL");
     int rc;
@@ -342,6 +343,11 @@ int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *o
     const bool want16 = opts->precision == SPAMM_PREC_SPLIT_FP16;
     if (split && (rc = check_tol(opts->low_tol, "low_tol")))
         return rc;
+    if (split && (rc = check_tol(opts->low_rel, "low_rel")))
+        return rc;
+    if (split && opts->low_tol > 0.0 && opts->low_rel > 0.0)
+        return fail(SPAMM_E_INVAL, "low_tol = %g and low_rel = %g: give one threshold",
+                    opts->low_tol, opts->low_rel);
     if (A->n != B->n || A->leaf != B->leaf)
         return fail(SPAMM_E_MISMATCH, "A is %lld/%d, B is %lld/%d (n/leaf)", (long long)A->n,
                     A->leaf, (long long)B->n, B->leaf);
@@ -357,15 +363,9 @@ int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *o
         return fail(SPAMM_E_INVAL,
                     "sub-leaf culling needs FP32 precision and leaf-64 trees built with "
                     "SPAMM_TREE_SUBNORMS");
-    int dev;
-    if ((rc = prepare_device(&dev)))
-        return rc;
     if (A->device != dev || B->device != dev)
         return fail(SPAMM_E_INVAL, "trees live on device %d/%d, current device is %d", A->device,
                     B->device, dev);
-    spamm_plan *p = new (std::nothrow) spamm_plan();
-    if (!p)
-        return fail(SPAMM_E_NOMEM, "host allocation failed");
     p->device = dev;
     p->stream = s;
     p->A = A;
@@ -378,20 +378,59 @@ int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *o
     p->precision = opts->precision;
     p->low_tol = split ? opts->low_tol : 0.0;
     p->L2 = p->low_tol * p->low_tol;
+    p->low_rel = split ? opts->low_rel : 0.0;
+    p->theta2 = p->low_rel * p->low_rel;
     p->sub = sub ? 1 : 0;
     const int d = p->depth;
     p->nblocks = d == 0 ? 1 : (int64_t(1) << (2 * (d - 1)));
-
     const PlanSizes z = plan_sizes(d);
     for (int t = 0; t <= d; ++t)
         p->rp_off[t] = z.rp_off[t];
-    // every buffer at its offset of one block: the caller's arena, else an
-    // allocation of the plan's own
     PlanBuf bufs[12];
     const int nb = plan_bufs(p, z, split, sub, bufs);
     size_t total = 0;
     for (int i = 0; i < nb; ++i)
         total += align256(bufs[i].bytes);
+    *bytes = total;
+    return SPAMM_OK;
+}
+
+// Points the buffers of a set-up plan into `base` (its block) and enqueues
+// the cull on the plan's stream.
+static hipError_t plan_carve_and_cull(spamm_plan *p, char *base)
+{
+    PlanBuf bufs[12];
+    const int nb = plan_bufs(p, plan_sizes(p->depth), p->precision != SPAMM_PREC_FP32,
+                             p->sub != 0, bufs);
+    size_t off = 0;
+    for (int i = 0; i < nb; ++i) {
+        *bufs[i].dst = base + off;
+        off += align256(bufs[i].bytes);
+    }
+    return launch_cull(p, p->stream);
+}
+
+int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
+                   hipStream_t s, void *arena, spamm_plan **out)
+{
+    if (out == nullptr)
+        return fail(SPAMM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (A == nullptr || B == nullptr || opts == nullptr)
+        return fail(SPAMM_E_INVAL, "tree or options NULL");
+    int dev, rc;
+    if ((rc = prepare_device(&dev)))
+        return rc;
+    spamm_plan *p = new (std::nothrow) spamm_plan();
+    if (!p)
+        return fail(SPAMM_E_NOMEM, "host allocation failed");
+    size_t total = 0;
+    if ((rc = plan_setup(p, A, B, opts, dev, s, &total))) {
+        delete p;
+        return rc;
+    }
+    // every buffer at its offset of one block: the caller's arena, else an
+    // allocation of the plan's own
     char *base = (char *)arena;
     if (base == nullptr) {
         hipError_t e = dev_alloc_async(dev, (void **)&base, total, s);
@@ -402,12 +441,7 @@ int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *o
         }
         p->block = base;
     }
-    size_t off = 0;
-    for (int i = 0; i < nb; ++i) {
-        *bufs[i].dst = base + off;
-        off += align256(bufs[i].bytes);
-    }
-    hipError_t e = launch_cull(p, s);
+    hipError_t e = plan_carve_and_cull(p, base);
     if (e != hipSuccess) {
         rc = hip_fail(e, "cull launch");
         spamm_plan_free(p);
@@ -971,10 +1005,20 @@ int spamm_multiply_opts(const spamm_tree *A, const spamm_tree *B, const spamm_op
     if (C == nullptr)
         return fail(SPAMM_E_INVAL, "C is NULL");
     hipStream_t s = (hipStream_t)stream;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    // the timing events are destroyed on every exit path
+    struct Events {
+        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        ~Events()
+        {
+            for (hipEvent_t x : ev)
+                if (x)
+                    hipEventDestroy(x);
+        }
+    } events;
+    hipEvent_t *ev = events.ev;
     if (stats) {
-        for (auto &x : ev)
-            HIP_TRY(hipEventCreate(&x), "hipEventCreate");
+        for (int i = 0; i < 3; ++i)
+            HIP_TRY(hipEventCreate(&ev[i]), "hipEventCreate");
         HIP_TRY(hipEventRecord(ev[0], s), "hipEventRecord");
     }
     spamm_plan *p = nullptr;
@@ -999,9 +1043,6 @@ int spamm_multiply_opts(const spamm_tree *A, const spamm_tree *B, const spamm_op
             stats->numeric_ms = ms;
     }
     int rc2 = spamm_plan_free(p);
-    for (auto &x : ev)
-        if (x)
-            hipEventDestroy(x);
     return rc != SPAMM_OK ? rc : rc2;
 }
 
@@ -1019,5 +1060,4 @@ int spamm_multiply(const spamm_tree *A, const spamm_tree *B, double tau, float *
 {
     return spamm_multiply_ex(A, B, tau, C, stream, nullptr);
 }
-
 }  // extern "C"

@@ -110,9 +110,19 @@ __device__ inline bool keep_pair(double sa, double sb, double T2)
     return (sa > 0.0) & (sb > 0.0) & !(sa * sb < T2);
 }
 
-// Split precision: a kept product is LOW (BF16 operands) iff s_A s_B < L2,
+// Split precision: a kept product is LOW (16-bit operands) iff s_A s_B < L2,
 // L2 = fl64(low_tol^2); L2 = 0 makes every product HIGH (FP32).
 __device__ inline bool low_pair(double sa, double sb, double L2) { return sa * sb < L2; }
+
+// The LOW bound of a product: with a relative threshold (theta2 =
+// fl64(theta^2) > 0) it is (theta2 s_A0) s_B0 from the roots of the two
+// trees' own pyramids, i.e. norm product < theta ||A||_F ||B||_F; else the
+// absolute L2.
+__device__ inline double low_bound(double L2, double theta2, const double *__restrict__ rootA,
+                                   const double *__restrict__ rootB)
+{
+    return theta2 > 0.0 ? (theta2 * rootA[0]) * rootB[0] : L2;
+}
 
 __device__ inline int lane_id() { return __lane_id(); }
 
@@ -206,7 +216,9 @@ struct spamm_plan {
     int64_t n;
     double tau, T2;
     int32_t precision;      // SPAMM_PREC_*
-    double low_tol, L2;     // split: LOW iff s_A s_B < L2 = low_tol^2
+    double low_tol, L2;     // split: LOW iff s_A s_B < L2 = low_tol^2 (absolute)
+    double low_rel, theta2; // split, relative: L2 = (theta2 s_A0) s_B0 on the device,
+                            // theta2 = low_rel^2 (0 when the threshold is absolute)
     // tier lists for t < d: CSR over the 4^t tier-t output tiles (linear
     // index), entries = kept k at that tier, ascending
     uint32_t *rowptr;       // all tiers t = 0..d-1, offset rp_off[t], 4^t + 1 each

@@ -21,14 +21,16 @@
 // one tier-(d-1) tile), so the last tier emits per block the union of kept k
 // with a 4-bit mask of the leaves (q) that take the product.  With split
 // precision each kept leaf product is also classed LOW (s_A s_B < low_tol^2,
-// BF16 operands) or HIGH (FP32), and the two classes get separate lists.
+// or < (theta^2 s_A0) s_B0 for a relative threshold; 16-bit operands) or
+// HIGH (FP32), and the two classes get separate lists.
 #include "common.hpp"
 
 namespace spamm {
 
 // Root triple (0,0,0) at tier 0.
 __global__ void cull_root(const double *__restrict__ nA, const double *__restrict__ nB, double T2,
-                          double L2, uint32_t *__restrict__ rowptr0, uint32_t *__restrict__ list0,
+                          double L2, double theta2, uint32_t *__restrict__ rowptr0,
+                          uint32_t *__restrict__ list0,
                           uint32_t *__restrict__ browptr, uint32_t *__restrict__ bent,
                           uint32_t *__restrict__ browptr_lo, uint32_t *__restrict__ bent_lo,
                           uint64_t *__restrict__ leafK, int last)
@@ -40,7 +42,8 @@ __global__ void cull_root(const double *__restrict__ nA, const double *__restric
     reinterpret_cast<double *>(leafK)[4] = nB[0];
     if (last) {
         // d = 0: the root is the only leaf
-        const uint32_t low = (kept && low_pair(nA[0], nB[0], L2)) ? 1u : 0u;
+        const uint32_t low =
+            (kept && low_pair(nA[0], nB[0], low_bound(L2, theta2, nA, nB))) ? 1u : 0u;
         browptr[0] = 0;
         browptr[1] = kept & ~low;
         if (kept & ~low)
@@ -159,7 +162,10 @@ __global__ __launch_bounds__(256) void cull_count(const double *__restrict__ nA,
 template <bool SPLIT>
 __global__ __launch_bounds__(256) void cull_count_leaf(const double *__restrict__ nA,
                                                        const double *__restrict__ nB, double T2,
-                                                       double L2, const uint32_t *__restrict__ prow,
+                                                       double L2a, double theta2,
+                                                       const double *__restrict__ rootA,
+                                                       const double *__restrict__ rootB,
+                                                       const uint32_t *__restrict__ prow,
                                                        const uint32_t *__restrict__ plist,
                                                        uint32_t nparents,
                                                        uint32_t *__restrict__ counts)
@@ -167,6 +173,7 @@ __global__ __launch_bounds__(256) void cull_count_leaf(const double *__restrict_
     const uint32_t P = blockIdx.x * 4u + (threadIdx.x >> 6);
     if (P >= nparents)
         return;
+    const double L2 = SPLIT ? low_bound(L2a, theta2, rootA, rootB) : 0.0;
     const int lane = threadIdx.x & 63;
     const uint32_t I = lin_row(P), J = lin_col(P);
     const uint32_t beg = prow[P], end = prow[P + 1];
@@ -269,7 +276,10 @@ __device__ inline void emit_entries(uint32_t fl, uint32_t kp, uint64_t below, ui
 template <bool SPLIT>
 __global__ __launch_bounds__(256) void cull_emit_leaf(const double *__restrict__ nA,
                                                       const double *__restrict__ nB, double T2,
-                                                      double L2, const uint32_t *__restrict__ prow,
+                                                      double L2a, double theta2,
+                                                      const double *__restrict__ rootA,
+                                                      const double *__restrict__ rootB,
+                                                      const uint32_t *__restrict__ prow,
                                                       const uint32_t *__restrict__ plist,
                                                       uint32_t nparents,
                                                       const uint32_t *__restrict__ rp_hi,
@@ -280,6 +290,7 @@ __global__ __launch_bounds__(256) void cull_emit_leaf(const double *__restrict__
     const uint32_t P = blockIdx.x * 4u + (threadIdx.x >> 6);
     if (P >= nparents)
         return;
+    const double L2 = SPLIT ? low_bound(L2a, theta2, rootA, rootB) : 0.0;
     const int lane = threadIdx.x & 63;
     const uint64_t below = lanes_below();
     const uint32_t I = lin_row(P), J = lin_col(P);
@@ -562,7 +573,7 @@ hipError_t launch_cull(spamm_plan *p, hipStream_t s)
     hipError_t e;
     if (d == 0) {
         hipLaunchKernelGGL(cull_root, dim3(1), dim3(64), 0, s, nA, nB, p->T2, split ? p->L2 : 0.0,
-                           p->rowptr + p->rp_off[0], p->list[0], p->browptr, p->bent,
+                           split ? p->theta2 : 0.0, p->rowptr + p->rp_off[0], p->list[0], p->browptr, p->bent,
                            p->browptr_lo, p->bent_lo, p->leafK, 1);
         return hipGetLastError();
     }
@@ -590,10 +601,10 @@ hipError_t launch_cull(spamm_plan *p, hipStream_t s)
         } else {
             if (split)
                 hipLaunchKernelGGL(cull_count_leaf<true>, grid, block, 0, s, tA, tB, p->T2, p->L2,
-                                   prow, plist, np, p->counts);
+                                   p->theta2, nA, nB, prow, plist, np, p->counts);
             else
                 hipLaunchKernelGGL(cull_count_leaf<false>, grid, block, 0, s, tA, tB, p->T2, 0.0,
-                                   prow, plist, np, p->counts);
+                                   0.0, nA, nB, prow, plist, np, p->counts);
             if ((e = hipGetLastError()) != hipSuccess)
                 return e;
             if (np <= (uint32_t)kScanChunk * 4) {
@@ -619,11 +630,12 @@ hipError_t launch_cull(spamm_plan *p, hipStream_t s)
             }
             if (split)
                 hipLaunchKernelGGL(cull_emit_leaf<true>, grid, block, 0, s, tA, tB, p->T2, p->L2,
-                                   prow, plist, np, (const uint32_t *)p->browptr, p->bent,
+                                   p->theta2, nA, nB, prow, plist, np,
+                                   (const uint32_t *)p->browptr, p->bent,
                                    (const uint32_t *)p->browptr_lo, p->bent_lo);
             else
                 hipLaunchKernelGGL(cull_emit_leaf<false>, grid, block, 0, s, tA, tB, p->T2, 0.0,
-                                   prow, plist, np, (const uint32_t *)p->browptr, p->bent,
+                                   0.0, nA, nB, prow, plist, np, (const uint32_t *)p->browptr, p->bent,
                                    (const uint32_t *)nullptr, (uint32_t *)nullptr);
         }
         if ((e = hipGetLastError()) != hipSuccess)

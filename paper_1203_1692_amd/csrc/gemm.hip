@@ -790,14 +790,22 @@ void plan_jobs(const spamm_plan *p, float *C, GemmJob &j)
     }
 }
 
+// Clears one counter (a kernel rather than a memset node, so the launch
+// sequence stays valid under stream capture).
+__global__ void zero_counter(unsigned long long *c) { *c = 0ull; }
+
 hipError_t launch_gemm(const spamm_plan *p, float *C, hipStream_t s)
 {
     GemmJobs jobs{};
     jobs.njobs = 1;
     jobs.nblocks = (uint32_t)p->nblocks;
-    hipError_t e;
-    if (p->sub && (e = hipMemsetAsync(p->leafK + 2, 0, sizeof(uint64_t), s)) != hipSuccess)
-        return e;
+    if (p->sub) {
+        hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s,
+                           (unsigned long long *)(p->leafK + 2));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
     plan_jobs(p, C, jobs.job[0]);
     return launch_gemm_jobs(p->leaf, plan_kind(p), jobs, s);
 }

@@ -99,6 +99,11 @@ int check_request(const spamm_request *r, size_t *bytes)
         return fail(SPAMM_E_INVAL, "tau = %g must be 0 or in [1e-150, inf)", r->tau);
     if (split && bad_tol(r->low_tol))
         return fail(SPAMM_E_INVAL, "low_tol = %g must be 0 or in [1e-150, inf)", r->low_tol);
+    if (split && bad_tol(r->low_rel))
+        return fail(SPAMM_E_INVAL, "low_rel = %g must be 0 or in [1e-150, inf)", r->low_rel);
+    if (split && r->low_tol > 0.0 && r->low_rel > 0.0)
+        return fail(SPAMM_E_INVAL, "low_tol = %g and low_rel = %g: give one threshold",
+                    r->low_tol, r->low_rel);
     if (r->chain_len < 0 || r->chain_len > kMaxChain)
         return fail(SPAMM_E_INVAL, "chain_len = %d outside 0..%d", r->chain_len, kMaxChain);
     if (r->chain_len > 0 && r->B != nullptr && r->B != r->A)
@@ -174,6 +179,8 @@ int start_step(spamm_server *S, Active &a)
     o.tau = r.tau;
     o.precision = r.precision;
     o.low_tol = a.split ? r.low_tol : 0.0;
+    // a relative threshold is taken against this step's own roots on the device
+    o.low_rel = a.split ? r.low_rel : 0.0;
     if ((rc = symbolic_async(a.tA, a.tB, &o, ss, base + (a.distinctB ? 2 : 1) * tb, &a.plan)))
         return rc;
     // kept counts and both roots in one copy (the cull writes them all)
@@ -229,9 +236,24 @@ bool launch_batches(spamm_server *S)
     }
     bool any = false;
     std::vector<size_t> ready;
-    for (size_t i = 0; i < S->active.size(); ++i)
-        if (S->active[i].culled && hipEventQuery(S->ev_cull[S->active[i].slot]) == hipSuccess)
+    for (size_t i = 0; i < S->active.size(); ++i) {
+        Active &a = S->active[i];
+        if (!a.culled)
+            continue;
+        const hipError_t q = hipEventQuery(S->ev_cull[a.slot]);
+        if (q == hipSuccess) {
             ready.push_back(i);
+        } else if (q != hipErrorNotReady) {
+            // the build or cull on the slot stream failed: nothing more is
+            // enqueued for this request, and it finishes with the error once
+            // its slot stream has drained
+            a.status = hip_fail(q, "request build / cull");
+            a.culled = false;
+            a.final = true;
+            hipStreamSynchronize(S->ss[a.slot]);
+            any = true;
+        }
+    }
     while (!ready.empty() && (int)S->inflight.size() < kInflightBatches) {
         // one batch: up to kMaxJobs requests of the first ready request's leaf size
         const int leaf = S->active[ready[0]].job.rq.leaf;

@@ -237,14 +237,20 @@ def round_leaf(X, S, fmt):
 
 
 class SplitRun:
-    def __init__(self, sp, A, leaf, tau, low, fmt, label):
+    """A split product with an absolute threshold `low` or a relative one
+    `rel` (theta, formed by the library from the tree's root)."""
+
+    def __init__(self, sp, A, leaf, tau, low, fmt, label, rel=0.0):
         import torch
         self.A, self.leaf, self.tau, self.low, self.fmt, self.n = A, leaf, tau, low, fmt, A.shape[0]
-        print(f"\n[fullsize] {label} split-{fmt} tau={tau:g} low_tol={low:g}", flush=True)
+        self.rel = rel
+        print(f"\n[fullsize] {label} split-{fmt} tau={tau:g} low_tol={low:g} theta={rel:g}",
+              flush=True)
         dA = torch.from_numpy(A).cuda()
         self.tree = sp.build_tree(dA, leaf, bf16=(fmt == "bf16"), fp16=(fmt == "fp16"))
         prec = sp.PREC_SPLIT_FP16 if fmt == "fp16" else sp.PREC_SPLIT_BF16
-        self.plan = sp.symbolic(self.tree, self.tree, tau, precision=prec, low_tol=low)
+        self.plan = sp.symbolic(self.tree, self.tree, tau, precision=prec, low_tol=low,
+                                low_rel=rel)
         C = torch.full_like(dA, float("nan"))
         self.plan.numeric(C)
         torch.cuda.synchronize()
@@ -262,14 +268,15 @@ def check_split(run, seed):
     Higham's bound over each class's operands (m = n_b K + 1, one more
     rounding per LOW product with FP16)."""
     ref = oracle.spamm(run.A, run.A, run.leaf, run.tau, want_C=False, low_tol=run.low,
-                       low_fmt=run.fmt)
+                       low_fmt=run.fmt, low_rel=run.rel)
     assert run.stats["tasks"] == ref.K and run.stats["tasks_low"] == ref.Klow
     assert np.array_equal(run.keys, ref.keys)
     N = 1 << run.tree.depth
     S = oracle.norms(run.A, run.leaf)[-1]
     tiles = choose_tiles(N, seed, count=24)
     Ct, counts, kl = oracle.spamm_tiles(run.A, run.A, run.leaf, run.tau, tiles, threads=16,
-                                        want_klists=True, low_tol=run.low, low_fmt=run.fmt)
+                                        want_klists=True, low_tol=run.low, low_fmt=run.fmt,
+                                        low_rel=run.rel)
     extra = 1 if run.fmt == "fp16" else 0
     worst = -np.inf
     for s, (I, J) in enumerate(tiles):
@@ -291,13 +298,32 @@ def check_split(run, seed):
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp16"])
 def test_algdecay_split_theta_1e4(gpu, fmt):
-    """algdecay-n16384 at tau = 1e-8 with LOW iff ||A_ik|| ||A_kj|| < 1e-4 ||A||_F^2."""
+    """algdecay-n16384 at tau = 1e-8 with LOW iff ||A_ik|| ||A_kj|| < 1e-4 ||A||_F^2
+    (theta = 1e-4, the bound formed by the library)."""
     wl = workloads.WORKLOADS["algdecay-n16384"]
     A = wl.matrix()
-    low = 1e-4 * float(oracle.norms(A, wl.leaf)[0][0, 0])
-    r = SplitRun(gpu, A, wl.leaf, 1e-8, low, fmt, wl.name)
+    r = SplitRun(gpu, A, wl.leaf, 1e-8, 0.0, fmt, wl.name, rel=1e-4)
     assert 0 < r.stats["tasks_low"] < r.stats["tasks"]
     check_split(r, seed=21)
+
+
+@pytest.mark.parametrize("tau", [1e-4, 1e-6, 1e-10])
+def test_algdecay_split_tau_sweep_theta_1e4(gpu, tau):
+    """The rest of the algdecay-n16384 tau sweep with BF16 LOW operands at
+    theta = 1e-4: every key with its class bit, sampled C within the bound."""
+    wl = workloads.WORKLOADS["algdecay-n16384"]
+    r = SplitRun(gpu, wl.matrix(), wl.leaf, tau, 0.0, "bf16", wl.name, rel=1e-4)
+    assert 0 < r.stats["tasks_low"] < r.stats["tasks"]
+    check_split(r, seed=22)
+
+
+def test_cluster1310_split_theta_1e4(cluster1310, gpu):
+    """cluster1310-n32750 at tau = 1e-8 with LOW iff the norm product is below
+    1e-4 ||A||_F^2 (nearly every product LOW): all keys with class bits."""
+    r = SplitRun(gpu, cluster1310.A, cluster1310.leaf, 1e-8, 0.0, "bf16", "cluster1310-n32750",
+                 rel=1e-4)
+    assert r.stats["tasks_low"] > 0.9 * r.stats["tasks"]
+    check_split(r, seed=33)
 
 
 @pytest.mark.parametrize("fmt,low", [("bf16", 0.8192), ("fp16", 3.2768)])

@@ -4,9 +4,12 @@
   uneven n, tau, leaf, precision (FP32, BF16 and FP16 split) and chain
   length (fixed owner and k order per output leaf), and equal to the
   one-call API's result;
-* plain requests agree with the oracle (task counts exact, C within
-  1e-5 ||A||_F ||B||_F); a chain's last step agrees with the oracle run on
-  the previous step's matrix;
+* teacher-forced parity with the oracle at every step: step s of a request
+  (its input X_s as the GPU holds it) has the oracle's task keys bit for bit,
+  class bits included (a split request's relative threshold theta is taken
+  by the library against each step's own roots), the served task counts are
+  the sums over the steps, and every step's C, the served C included, is
+  within Higham's elementwise bound around the oracle's product;
 * admission under a budget that holds one request at a time, rejection of a
   request larger than the budget, destroy with requests pending, NaN input
   and an overflowing chain reported as non-finite, poll semantics, several
@@ -19,6 +22,7 @@ import numpy as np
 import pytest
 
 import oracle
+from bounds import class_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -73,46 +77,45 @@ def make_inputs(spec):
     return A, B, dA, dB
 
 
-def low_tol_of(gpu, spec, dA, dB):
-    """Absolute LOW threshold theta ||A||_F ||B||_F from the trees' roots."""
-    n, leaf, tau, prec, theta, *_ = spec
-    if prec == 0:
-        return 0.0
-    tA = gpu.build_tree(dA, leaf)
-    tB = tA if dB is None else gpu.build_tree(dB, leaf)
-    return gpu.relative_low_tol(tA, tB, theta)
-
-
-def reference(gpu, spec, dA, dB, low):
-    """The same request through the one-call API, step by step."""
+def reference(gpu, spec, dA, dB, low_tol=0.0, keep_steps=False):
+    """The same request through the one-call API, step by step: symbolic +
+    numeric per step, with the spec's relative split threshold theta (or an
+    absolute low_tol).  Returns (C, steps): with keep_steps, per step its input
+    X_s as the GPU holds it, the plan's task keys and counts and its C."""
     import torch
     n, leaf, tau, prec, theta, chain, *_ = spec
     bf, f16 = prec == gpu.PREC_SPLIT_BF16, prec == gpu.PREC_SPLIT_FP16
+    rel = theta if (prec and not low_tol) else 0.0
     X = dA
-    prev = None
-    tasks = 0
+    steps = []
     for _ in range(max(1, chain)):
         tA = gpu.build_tree(X, leaf, bf16=bf, fp16=f16)
         tB = tA if (dB is None or chain) else gpu.build_tree(dB, leaf, bf16=bf, fp16=f16)
         C = torch.empty_like(dA)
-        st = gpu.multiply_ex(tA, tB, tau, C, precision=prec, low_tol=low)
-        tasks += st["tasks"]
-        prev, X = X, C
-    return X, prev, tasks
+        plan = gpu.symbolic(tA, tB, tau, precision=prec, low_tol=low_tol, low_rel=rel)
+        plan.numeric(C)
+        st = plan.stats()
+        if keep_steps:
+            steps.append(dict(X=X.cpu().numpy(), keys=plan.tasks(), K=st["tasks"],
+                              Klow=st["tasks_low"], C=C.cpu().numpy()))
+        else:
+            steps.append(dict(K=st["tasks"], Klow=st["tasks_low"]))
+        plan.free()
+        X = C
+    return X, steps
 
 
 @pytest.fixture(scope="module")
 def mix(gpu):
     import torch
     inputs = [make_inputs(s) for s in MIX]
-    lows = [low_tol_of(gpu, s, a[2], a[3]) for s, a in zip(MIX, inputs)]
-    refs = [reference(gpu, s, a[2], a[3], lo) for s, a, lo in zip(MIX, inputs, lows)]
+    refs = [reference(gpu, s, a[2], a[3], keep_steps=s[0] <= 1200) for s, a in zip(MIX, inputs)]
     torch.cuda.synchronize()
 
     def submit(srv, i, C):
         n, leaf, tau, prec, theta, chain, *_ = MIX[i]
         return srv.submit(inputs[i][2], C, tau, leaf, B=inputs[i][3], precision=prec,
-                          low_tol=lows[i], chain_len=chain)
+                          low_rel=theta if prec else 0.0, chain_len=chain)
 
     alone = []
     srv = gpu.Server(8 * GiB, max_slots=8)
@@ -128,8 +131,7 @@ def mix(gpu):
     results = [srv.wait(t) for t in tickets]
     info = srv.info()
     srv.destroy()
-    return dict(inputs=inputs, lows=lows, refs=refs, alone=alone, outs=outs, results=results,
-                info=info)
+    return dict(inputs=inputs, refs=refs, alone=alone, outs=outs, results=results, info=info)
 
 
 @pytest.mark.parametrize("i", range(len(MIX)))
@@ -141,10 +143,11 @@ def test_same_alone_and_in_mix(mix, i):
     assert torch.equal(C_alone, C_mix)
     assert r_alone["tasks"] == r_mix["tasks"] and r_alone["tasks_low"] == r_mix["tasks_low"]
     assert r_mix["steps"] == max(1, MIX[i][5])
-    # and the one-call API gives the same bits
-    X, _, tasks = mix["refs"][i]
+    # and the one-call API gives the same bits and counts, step by step
+    X, steps = mix["refs"][i]
     assert torch.equal(C_mix, X)
-    assert r_mix["tasks"] == tasks
+    assert r_mix["tasks"] == sum(st["K"] for st in steps)
+    assert r_mix["tasks_low"] == sum(st["Klow"] for st in steps)
     assert r_mix["flops"] == 2.0 * MIX[i][1] ** 3 * r_mix["tasks"]
     assert 0.0 <= r_mix["queue_ms"] <= r_mix["latency_ms"]
 
@@ -160,28 +163,40 @@ def test_mix_was_batched(mix):
     assert 0 < info["used"] <= info["peak_used"] <= info["budget"]
 
 
-@pytest.mark.parametrize("i", [i for i, s in enumerate(MIX) if s[0] <= 1200])
-def test_matches_oracle(mix, i):
+ORACLE_CASES = [i for i, s in enumerate(MIX) if s[0] <= 1200]
+
+
+@pytest.mark.parametrize("i", ORACLE_CASES)
+def test_matches_oracle_every_step(mix, i):
+    """Teacher-forced: the oracle takes each step's input as the GPU holds it
+    (a chain's X_s is the GPU's FP32 result of step s-1) and must give the
+    same task keys (class bits included) and a product within Higham's bound
+    of that step's C; the served counts are the sums over the steps."""
     n, leaf, tau, prec, theta, chain, *_ = MIX[i]
     A, B = mix["inputs"][i][0], mix["inputs"][i][1]
-    low = mix["lows"][i]
     fmt = "fp16" if prec == 2 else "bf16"
-    if chain:
-        # the last squaring, on the previous step's matrix as the GPU holds it
-        prev = mix["refs"][i][1].cpu().numpy()
-        ref = oracle.spamm(prev, prev, leaf, tau, low_tol=low, low_fmt=fmt)
-        nrm = float(np.sqrt(oracle.norms(prev, leaf)[0][0, 0]))
-        bound = 1e-5 * nrm * nrm
-    else:
-        Bm = A if B is None else B
-        ref = oracle.spamm(A, Bm, leaf, tau, low_tol=low, low_fmt=fmt)
-        nA = math.sqrt(oracle.norms(A, leaf)[0][0, 0])
-        nB = math.sqrt(oracle.norms(Bm, leaf)[0][0, 0])
-        bound = 1e-5 * nA * nB
-        assert mix["results"][i]["tasks"] == ref.K
-        assert mix["results"][i]["tasks_low"] == ref.Klow
-    C = mix["outs"][i].cpu().numpy().astype(np.float64)
-    assert float(np.abs(C - ref.C).max()) <= bound
+    _, steps = mix["refs"][i]
+    assert len(steps) == max(1, chain)
+    K = Klow = 0
+    for s, st in enumerate(steps):
+        X = st["X"]
+        if s == 0:
+            assert np.array_equal(X.view(np.uint32), A.view(np.uint32))
+        Y = X if (chain or B is None) else B
+        ref = oracle.spamm(X, Y, leaf, tau, low_rel=theta if prec else 0.0, low_fmt=fmt)
+        assert np.array_equal(st["keys"], ref.keys), f"step {s}: task keys differ"
+        assert st["K"] == ref.K and st["Klow"] == ref.Klow, f"step {s}"
+        C = mix["outs"][i].cpu().numpy() if s == len(steps) - 1 else st["C"]
+        assert np.array_equal(C.view(np.uint32), st["C"].view(np.uint32))
+        err = np.abs(C.astype(np.float64) - ref.C)
+        worst = float(np.max(err - class_bound(X, Y, leaf, ref.keys, fmt)))
+        assert worst <= 0.0, f"step {s}: rounding bound exceeded by {worst}"
+        K += ref.K
+        Klow += ref.Klow
+    assert mix["results"][i]["tasks"] == K
+    assert mix["results"][i]["tasks_low"] == Klow
+    if prec and theta and n > leaf:
+        assert Klow > 0     # (a one-leaf product is its own norm product: never LOW)
 
 
 def test_tiny_budget_one_at_a_time(gpu):
@@ -191,7 +206,8 @@ def test_tiny_budget_one_at_a_time(gpu):
     srv = gpu.Server(max(need), max_slots=4)
     try:
         ins = [make_inputs(s) for s in specs]
-        refs = [reference(gpu, s, a[2], a[3], 1e-3 if s[3] else 0.0) for s, a in zip(specs, ins)]
+        refs = [reference(gpu, s, a[2], a[3], low_tol=1e-3 if s[3] else 0.0)
+                for s, a in zip(specs, ins)]
         outs = [torch.empty_like(a[2]) for a in ins]
         tickets = [srv.submit(a[2], C, s[2], s[1], B=a[3], precision=s[3],
                               low_tol=1e-3 if s[3] else 0.0, chain_len=s[5])
@@ -248,7 +264,7 @@ def test_nonfinite_input_and_overflowing_chain(gpu):
         assert r1["status"] == gpu.SPAMM_E_NONFINITE
         assert r2["status"] == gpu.SPAMM_E_NONFINITE     # X_1 = A^2 overflows FP32
         assert r3["status"] == 0
-        ref = reference(gpu, (300, 32, 1e-6, 0, 0.0, 3, False, 0, 0), dgood, None, 0.0)[0]
+        ref = reference(gpu, (300, 32, 1e-6, 0, 0.0, 3, False, 0, 0), dgood, None)[0]
         assert torch.equal(outs[2], ref)
     finally:
         srv.destroy()
@@ -281,7 +297,7 @@ def test_submitters_on_several_threads(gpu):
     specs = [(n, 32, 1e-6, 0, 0.0, c, False, 0.1, 50 + k)
              for k, (n, c) in enumerate([(256, 0), (512, 2), (384, 0), (640, 1)] * 2)]
     ins = [make_inputs(s) for s in specs]
-    refs = [reference(gpu, s, a[2], None, 0.0)[0] for s, a in zip(specs, ins)]
+    refs = [reference(gpu, s, a[2], None)[0] for s, a in zip(specs, ins)]
     torch.cuda.synchronize()
     outs = [torch.empty_like(a[2]) for a in ins]
     srv = gpu.Server(4 * GiB, max_slots=8)
@@ -311,7 +327,8 @@ def test_chain_in_place(gpu):
     import torch
     A = gershgorin_scaled(decay(700, 0.1, 21))
     X = torch.from_numpy(A).cuda()
-    ref = reference(gpu, (700, 32, 1e-7, 1, 0.0, 4, False, 0, 0), X.clone(), None, 1e-4)[0]
+    ref = reference(gpu, (700, 32, 1e-7, 1, 0.0, 4, False, 0, 0), X.clone(), None,
+                    low_tol=1e-4)[0]
     srv = gpu.Server(2 * GiB, max_slots=2)
     try:
         r = srv.wait(srv.submit(X, X, 1e-7, 32, precision=gpu.PREC_SPLIT_BF16, low_tol=1e-4,

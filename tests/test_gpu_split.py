@@ -151,13 +151,13 @@ def test_split_error_vs_dense_fp64_is_stated(gpu):
     A = workloads.exp_decay(1024, 0.1, 0)
     dA = torch.from_numpy(A).cuda()
     t = gpu.build_tree(dA, 32, bf16=True)
-    low = gpu.relative_low_tol(t, t, 1e-4)
     C = torch.empty_like(dA)
-    st = gpu.multiply_ex(t, t, 1e-6, C, precision=gpu.PREC_SPLIT_BF16, low_tol=low)
+    st = gpu.multiply_ex(t, t, 1e-6, C, precision=gpu.PREC_SPLIT_BF16, low_rel=1e-4)
     exact = A.astype(np.float64) @ A.astype(np.float64)
     err = float(np.abs(C.cpu().numpy() - exact).max())
     nrm = np.sqrt(oracle.norms(A, 32)[-1])
-    ref = oracle.spamm(A, A, 32, 1e-6, want_C=False, low_tol=low)
+    ref = oracle.spamm(A, A, 32, 1e-6, want_C=False, low_rel=1e-4)
+    assert st["tasks_low"] == ref.Klow
     inv = {oracle.linear_index(i, j): (i, j) for i in range(32) for j in range(32)}
     lowsum = {}   # per output leaf: sum over its LOW products of ||A_ik|| ||A_kj||
     for key in ref.keys:
@@ -188,8 +188,63 @@ def test_split_argument_errors(gpu):
         with pytest.raises(gpu.SpammError) as ei:
             gpu.symbolic(t, t, 1e-6, precision=gpu.PREC_SPLIT_BF16, low_tol=bad)
         assert ei.value.code == gpu.SPAMM_E_INVAL
+    for bad in (-1.0, float("nan"), float("inf"), 1e-200):
+        with pytest.raises(gpu.SpammError) as ei:
+            gpu.symbolic(t, t, 1e-6, precision=gpu.PREC_SPLIT_BF16, low_rel=bad)
+        assert ei.value.code == gpu.SPAMM_E_INVAL
+    with pytest.raises(gpu.SpammError) as ei:     # one threshold, not both
+        gpu.symbolic(t, t, 1e-6, precision=gpu.PREC_SPLIT_BF16, low_tol=1e-3, low_rel=1e-4)
+    assert ei.value.code == gpu.SPAMM_E_INVAL
     with pytest.raises(gpu.SpammError):
         gpu.symbolic(t, t, 1e-6, precision=7)
+
+
+# ---- relative threshold theta, evaluated by the library ------------------------
+
+REL_CASES = {
+    # name: (A, B or None, leaf, tau, theta, format)
+    "rel-b32-1e-4": lambda: (workloads.exp_decay(1024, 0.1, 0), None, 32, 1e-6, 1e-4, "bf16"),
+    "rel-b32-1e-2": lambda: (workloads.exp_decay(1024, 0.1, 0), None, 32, 1e-6, 1e-2, "bf16"),
+    "rel-b64-fp16": lambda: (decay(700, 0.02, 1), None, 64, 1e-6, 1e-3, "fp16"),
+    "rel-nonsym-b32": lambda: (decay(256, 0.05, 4, sym=False), decay(256, 0.08, 5, sym=False),
+                               32, 1e-5, 3e-3, "bf16"),
+    "rel-nonsym-fp16": lambda: (decay(256, 0.05, 4, sym=False),
+                                50.0 * decay(256, 0.08, 5, sym=False), 32, 1e-5, 3e-3, "fp16"),
+    "rel-single-leaf": lambda: (decay(50, 0.1, 6), None, 64, 0.0, 2.0, "bf16"),
+    "rel-algdecay-b64": lambda: (workloads.alg_decay(1000, 3.0, 0), None, 64, 1e-8, 1e-4,
+                                 "bf16"),
+}
+
+
+@pytest.mark.parametrize("name", list(REL_CASES))
+def test_relative_threshold_task_list_and_product(gpu, name):
+    """LOW iff norm product < theta ||A||_F ||B||_F, the bound formed by the
+    library from the two trees' roots: task keys with class bits bit-exact
+    against the oracle's relative mode, C within Higham's bound over each
+    class's operands."""
+    import torch
+    from bounds import class_bound
+    A, B, leaf, tau, theta, fmt = REL_CASES[name]()
+    Bm = A if B is None else B
+    prec = gpu.PREC_SPLIT_FP16 if fmt == "fp16" else gpu.PREC_SPLIT_BF16
+    ref = oracle.spamm(A, Bm, leaf, tau, low_rel=theta, low_fmt=fmt)
+    dA = torch.from_numpy(A).cuda()
+    kw = {fmt: True}
+    tA = gpu.build_tree(dA, leaf, **kw)
+    tB = tA if B is None else gpu.build_tree(torch.from_numpy(B).cuda(), leaf, **kw)
+    plan = gpu.symbolic(tA, tB, tau, precision=prec, low_rel=theta)
+    C = torch.full_like(dA, float("nan"))
+    plan.numeric(C)
+    torch.cuda.synchronize()
+    assert np.array_equal(plan.tasks(), ref.keys)
+    st = plan.stats()
+    assert st["tasks"] == ref.K and st["tasks_low"] == ref.Klow
+    assert 0 < ref.Klow, name
+    if name != "rel-single-leaf":
+        assert ref.Klow < ref.K, name
+    err = np.abs(C.cpu().numpy().astype(np.float64) - ref.C)
+    worst = float(np.max(err - class_bound(A, Bm, leaf, ref.keys, fmt)))
+    assert worst <= 0.0, f"bound exceeded by {worst}"
 
 
 # ---- FP16 LOW operands (per-leaf power-of-two scale) ---------------------------
@@ -320,17 +375,17 @@ def test_fp16_error_below_bf16_at_same_classes(gpu):
     dA = torch.from_numpy(A).cuda()
     t16 = gpu.build_tree(dA, 32, fp16=True)
     tb = gpu.build_tree(dA, 32, bf16=True)
-    low = gpu.relative_low_tol(t16, t16, 1e-2)
     C16, Cb = torch.empty_like(dA), torch.empty_like(dA)
-    s16 = gpu.multiply_ex(t16, t16, 1e-6, C16, precision=gpu.PREC_SPLIT_FP16, low_tol=low)
-    sb = gpu.multiply_ex(tb, tb, 1e-6, Cb, precision=gpu.PREC_SPLIT_BF16, low_tol=low)
+    s16 = gpu.multiply_ex(t16, t16, 1e-6, C16, precision=gpu.PREC_SPLIT_FP16, low_rel=1e-2)
+    sb = gpu.multiply_ex(tb, tb, 1e-6, Cb, precision=gpu.PREC_SPLIT_BF16, low_rel=1e-2)
     assert s16["tasks_low"] == sb["tasks_low"] > 0
     exact = A.astype(np.float64) @ A.astype(np.float64)
     e16 = float(np.abs(C16.cpu().numpy() - exact).max())
     eb = float(np.abs(Cb.cpu().numpy() - exact).max())
     assert e16 < eb / 4
     nrm = np.sqrt(oracle.norms(A, 32)[-1])
-    ref = oracle.spamm(A, A, 32, 1e-6, want_C=False, low_tol=low)
+    ref = oracle.spamm(A, A, 32, 1e-6, want_C=False, low_rel=1e-2, low_fmt="fp16")
+    assert s16["tasks_low"] == ref.Klow
     inv = {oracle.linear_index(i, j): (i, j) for i in range(32) for j in range(32)}
     lowsum = {}
     for key in ref.keys:

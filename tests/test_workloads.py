@@ -85,3 +85,38 @@ def test_cluster_matrix_structure():
     for (i, j) in [(0, 1), (0, 7), (13, 99), (50, 51)]:
         r = np.linalg.norm(p[i // 5] - p[j // 5])
         assert A[i, j] == np.float32(workloads.sym_u(3, i, j) * np.exp(-0.6 * r))
+
+
+def test_spectral_radius_against_eigvalsh():
+    """Lanczos estimate of the serving chains' normalisation against LAPACK's
+    symmetric eigenvalues (slow and fast decay, and a matrix whose largest
+    |eigenvalue| is negative)."""
+    import torch
+    for n, rate, seed in ((300, 0.05, 1), (700, 0.5, 2), (512, 0.2, 3)):
+        req = workloads.ServeRequest(0, n, rate, 1e-6, 0, False, seed, 1.0)
+        A = workloads.serve_matrix(torch, req, "cpu")
+        rho = float(np.abs(np.linalg.eigvalsh(A.double().numpy())).max())
+        assert abs(workloads.spectral_radius(torch, A, seed=seed) - rho) <= 1e-6 * rho
+    D = torch.diag(torch.tensor([-3.0, 1.0, 2.0, -0.5]))
+    assert abs(workloads.spectral_radius(torch, D) - 3.0) <= 3e-6     # FP32 products
+
+
+@pytest.mark.parametrize("n,rate,tau", [(512, 0.05, 1e-6), (512, 0.5, 1e-8), (512, 0.5, 1e-6),
+                                        (1024, 0.3, 1e-6)])
+def test_serving_chains_keep_products_every_step(n, rate, tau):
+    """A 10-step squaring chain of the serving mix, run through the oracle,
+    keeps leaf products at every step and stays bounded: X_0 = A / rho(A)
+    leaves the top eigenvalues at +-1, so the squarings neither vanish nor
+    overflow."""
+    import torch
+    import oracle
+    req = workloads.ServeRequest(0, n, rate, tau, 10, False, 1000 + n, 1.0)
+    X = workloads.serve_matrix(torch, req, "cpu").numpy()
+    kept = []
+    for _ in range(req.chain_len):
+        ref = oracle.spamm(X, X, workloads.SERVE_LEAF, tau, want_keys=False)
+        kept.append(ref.K)
+        X = ref.C.astype(np.float32)
+    assert min(kept) > 0, kept
+    # the top of the spectrum is still near 1 after 2^10-th powers
+    assert 0.5 < float(np.abs(np.linalg.eigvalsh(X.astype(np.float64))).max()) < 2.0

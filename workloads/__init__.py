@@ -241,3 +241,58 @@ def serving_mix(count: int = 2000, seed: int = 0, chain_share: float = 0.3,
     gap = rng.exponential(1.0, size=count)
     return [ServeRequest(r, int(n[r]), float(rate[r]), float(tau[r]), 10 if chain[r] else 0,
                          bool(split[r]), 1000 + r, float(gap[r])) for r in range(count)]
+
+
+def spectral_radius(torch, A, iters: int = 64, seed: int = 0) -> float:
+    """Largest |eigenvalue| of a symmetric matrix A (a torch tensor on any
+    device) by Lanczos with full reorthogonalization: `iters` FP32
+    matrix-vector products, the Krylov basis in FP64, the extreme Ritz values
+    from the small tridiagonal matrix.  Ritz values lie inside the spectrum,
+    so the estimate is a lower bound that converges quickly even when the top
+    eigenvalues are clustered (where power iteration stalls)."""
+    n = A.shape[0]
+    k = min(iters, n)
+    g = torch.Generator(device=A.device)
+    g.manual_seed(seed)
+    Q = torch.zeros((k + 1, n), dtype=torch.float64, device=A.device)
+    q = torch.rand(n, generator=g, device=A.device, dtype=torch.float64) - 0.5
+    Q[0] = q / q.norm()
+    alpha = torch.zeros(k, dtype=torch.float64, device=A.device)
+    beta = torch.zeros(k, dtype=torch.float64, device=A.device)
+    for j in range(k):
+        w = (A @ Q[j].to(A.dtype)).to(torch.float64)
+        alpha[j] = Q[j] @ w
+        # full reorthogonalization against the basis so far (twice is enough)
+        for _ in range(2):
+            w = w - Q[:j + 1].T @ (Q[:j + 1] @ w)
+        beta[j] = w.norm()
+        Q[j + 1] = w / beta[j].clamp_min(1e-300)
+    a = alpha.cpu().numpy()
+    b = beta.cpu().numpy()
+    m = k
+    small = np.nonzero(b[:k - 1] <= 1e-12 * max(1.0, float(np.abs(a).max())))[0]
+    if len(small):
+        m = int(small[0]) + 1             # an invariant subspace was found
+    T = np.diag(a[:m]) + np.diag(b[:m - 1], 1) + np.diag(b[:m - 1], -1)
+    return float(np.abs(np.linalg.eigvalsh(T)).max())
+
+
+def serve_matrix(torch, req: ServeRequest, device):
+    """Request r's input on `device`: symmetric u ~ U(-1, 1) from a torch
+    generator seeded req.seed, times exp(-rate |i - j|).  A squaring chain
+    starts from X_0 = A / rho(A) (spectral radius by Lanczos), so its
+    eigenvalues lie in [-1, 1] and the ones near +-1 survive every squaring:
+    the powers neither vanish nor overflow, as in density-matrix purification,
+    where the spectrum is mapped into [0, 1] before squaring."""
+    g = torch.Generator(device=device)
+    g.manual_seed(req.seed)
+    n = req.n
+    u = torch.rand((n, n), generator=g, device=device, dtype=torch.float32).mul_(2.0).sub_(1.0)
+    A = torch.triu(u)
+    A += torch.triu(u, 1).T
+    del u
+    i = torch.arange(n, device=device, dtype=torch.float32)
+    A *= torch.exp((i[:, None] - i[None, :]).abs_().mul_(-req.rate))
+    if req.chain_len:
+        A /= spectral_radius(torch, A, seed=req.seed)
+    return A
