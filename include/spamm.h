@@ -294,6 +294,27 @@ int spamm_multiply_ex(const spamm_tree *A, const spamm_tree *B, double tau, floa
 int spamm_multiply_opts(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
                         float *C, void *stream, spamm_stats *stats);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * product of spamm_multiply_opts (symbolic + numeric on `stream`, no stats)
+ * with the task arena in a fixed device block of the library instead of an
+ * allocation.  The block (SPAMM_NOALLOC_SCRATCH_BYTES on every device the
+ * library runs on, held until the process ends) is found once per device;
+ * the call itself allocates nothing (no hipMalloc, no pool, no host heap)
+ * and never synchronizes.  Trees, A, B and C are the caller's, as for
+ * spamm_multiply_opts.
+ * Every call on one device shares that device's block, and it keeps the
+ * last call's contents: calls that overlap on one device (on different
+ * streams or threads) race and must be ordered by the caller.
+ * A product whose task arena exceeds the block is refused with SPAMM_E_RANGE:
+ * depth d <= 8 (at most 256 leaves per dimension) fits in every precision
+ * and with sub-leaf culling.  Other errors as spamm_symbolic_ex.
+ */
+#define SPAMM_NOALLOC_SCRATCH_BYTES (64u << 20)
+int spamm_multiply_noalloc(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
+                           float *C, void *stream);
+
 /* ---- serving: continuous batching of products and squaring chains -------- */
 
 /*

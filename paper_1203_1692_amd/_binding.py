@@ -147,6 +147,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "spamm_plan_free": [vp],
         "spamm_multiply": [vp, vp, dbl, vp, vp],
         "spamm_multiply_ex": [vp, vp, dbl, vp, vp, ctypes.POINTER(Stats)],
+        "spamm_multiply_noalloc": [vp, vp, ctypes.POINTER(Opts), vp, vp],
         "spamm_server_create": [sz, i32, pp],
         "spamm_request_footprint": [ctypes.POINTER(Request), ctypes.POINTER(sz)],
         "spamm_submit": [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)],
@@ -397,6 +398,21 @@ def multiply_ex(A: Tree, B: Tree, tau: float, C, stream=None, precision: int = P
                                       ctypes.c_void_p(C.data_ptr()), _stream(stream),
                                       ctypes.byref(st)), "spamm_multiply_opts")
     return st.as_dict()
+
+
+def multiply_noalloc(A: Tree, B: Tree, tau: float, C, stream=None, precision: int = PREC_FP32,
+                     low_tol: float = 0.0, sub_cull: bool = False, low_rel: float = 0.0):
+    """C = A B through spamm_multiply_noalloc: the task arena lives in the
+    library's fixed per-device block, nothing is allocated (products of depth
+    <= 8; calls on one device must not overlap)."""
+    _device_matrix(C, "C")
+    if C.shape[0] != A.n:
+        raise ValueError("C has the wrong shape")
+    o = _opts(tau, precision, low_tol, sub_cull, low_rel)
+    _check(load().spamm_multiply_noalloc(A.handle, B.handle, ctypes.byref(o),
+                                         ctypes.c_void_p(C.data_ptr()), _stream(stream)),
+           "spamm_multiply_noalloc")
+    return C
 
 
 # ---- serving -----------------------------------------------------------------

@@ -451,6 +451,34 @@ int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *o
     return SPAMM_OK;
 }
 
+// ---- the product with no allocation ----------------------------------------
+// The task arena of spamm_multiply_noalloc: one fixed block per device, held
+// by the loaded code object until the process ends.  In host code `scratch`
+// only names the symbol; its device address on each device comes from
+// hipGetSymbolAddress (taken once per device, with that device current).
+static __device__ __align__(256) unsigned char scratch[SPAMM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+void *g_scratch[64] = {};
+std::mutex g_scratch_mu;
+}  // namespace
+
+static int scratch_address(int dev, void **out)
+{
+    if (dev < 0 || dev >= 64)
+        return fail(SPAMM_E_HIP, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev] == nullptr) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (ptr == nullptr)
+            return fail(SPAMM_E_HIP, "no device address for the scratch block on device %d", dev);
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return SPAMM_OK;
+}
+
 }  // namespace spamm
 
 extern "C" {
@@ -1060,4 +1088,36 @@ int spamm_multiply(const spamm_tree *A, const spamm_tree *B, double tau, float *
 {
     return spamm_multiply_ex(A, B, tau, C, stream, nullptr);
 }
+
+int spamm_multiply_noalloc(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
+                           float *C, void *stream)
+{
+    if (C == nullptr)
+        return fail(SPAMM_E_INVAL, "C is NULL");
+    if (A == nullptr || B == nullptr || opts == nullptr)
+        return fail(SPAMM_E_INVAL, "tree or options NULL");
+    int dev;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    void *base = nullptr;
+    int rc = scratch_address(dev, &base);
+    if (rc)
+        return rc;
+    // the plan lives on this stack frame; its buffers in the scratch block
+    spamm_plan p{};
+    size_t bytes = 0;
+    if ((rc = plan_setup(&p, A, B, opts, dev, (hipStream_t)stream, &bytes)))
+        return rc;
+    if (bytes > (size_t)SPAMM_NOALLOC_SCRATCH_BYTES)
+        return fail(SPAMM_E_RANGE,
+                    "the task arena of this product needs %zu bytes, the no-allocation "
+                    "scratch block holds %zu (depth %d; at most 8 fits)",
+                    bytes, (size_t)SPAMM_NOALLOC_SCRATCH_BYTES, p.depth);
+    hipError_t e = plan_carve_and_cull(&p, (char *)base);
+    if (e == hipSuccess)
+        e = launch_gemm(&p, C, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "spamm_multiply_noalloc");
+    return SPAMM_OK;
+}
+
 }  // extern "C"

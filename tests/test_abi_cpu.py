@@ -54,6 +54,12 @@ def test_argument_checks_before_any_device_call():
     assert lib.spamm_tree_info(None, None, None, None, None) == sp.SPAMM_E_INVAL
     assert lib.spamm_tree_free(None) == sp.SPAMM_OK
     assert lib.spamm_plan_free(None) == sp.SPAMM_OK
+    opts = sp.Opts(1e-6, sp.PREC_FP32, 0.0, 0, 0.0)
+    assert lib.spamm_multiply_noalloc(None, None, ctypes.byref(opts), fake,
+                                      None) == sp.SPAMM_E_INVAL
+    assert lib.spamm_multiply_noalloc(fake, fake, None, fake, None) == sp.SPAMM_E_INVAL
+    assert lib.spamm_multiply_noalloc(fake, fake, ctypes.byref(opts), None,
+                                      None) == sp.SPAMM_E_INVAL
 
 
 def test_python_binding_rejects_cpu_tensors():
