@@ -71,10 +71,10 @@ def measured_traffic(workload: str):
     return rec.get("bytes_per_launch")
 
 
-def measured_split_traffic(workload: str, tau: float, low_tol: float, fmt: str = "bf16"):
+def measured_split_traffic(workload: str, tau: float, theta: float, fmt: str = "bf16"):
     """HBM bytes per launch of the split kernel (LOW operands in `fmt`) at
-    (tau, low_tol) from the committed counter runs, or None when the kernel
-    sources changed since."""
+    (tau, theta) from the committed counter runs, or None when absent or the
+    kernel sources changed since."""
     kind = "leaf_gemm_split" if fmt == "bf16" else "leaf_gemm_split_fp16"
     path = os.path.join(ROOT, "profiles", f"{kind}_{workload}_traffic.json")
     if not os.path.exists(path):
@@ -82,7 +82,7 @@ def measured_split_traffic(workload: str, tau: float, low_tol: float, fmt: str =
     t = json.load(open(path))
     if (t.get("gemm_sources_sha256") != kernel_source_digest() or
             abs(t.get("tau", -1.0) - tau) > 1e-12 * tau or
-            abs(t.get("low_tol", -1.0) - low_tol) > 1e-12 * low_tol):
+            abs(t.get("theta", -1.0) - theta) > 1e-12 * theta):
         return None
     return t["bytes_per_launch"]
 
@@ -107,122 +107,256 @@ def sample_tiles(N: int, count: int, seed: int = 0):
     return [(int(f) // N, int(f) % N) for f in np.sort(flat)]
 
 
-def matched_error(sp, wl, A, dA, C, tau, leaf, n, N, reps=2):
-    import numpy as np
-    rng = np.random.default_rng(7)
-    tiles = [(int(i), int(j)) for i, j in rng.integers(0, N, size=(24, 2))]
-    tiles += [(int(i), int(i)) for i in rng.integers(0, N, size=12)]
-    tiles = sorted({(I, J) for I, J in tiles if I * leaf < n and J * leaf < n})
-    exact = {}
-    for (I, J) in tiles:
-        r0, r1 = I * leaf, min((I + 1) * leaf, n)
-        c0, c1 = J * leaf, min((J + 1) * leaf, n)
-        exact[(I, J)] = A[r0:r1].astype(np.float64) @ A[:, c0:c1].astype(np.float64)
+def dense_fp64(torch, dA, dB=None):
+    """The exact reference of Eq. matrix error: the dense product in FP64 on
+    the device (each FP32 entry widened exactly; rounding error ~n 2^-53)."""
+    A64 = dA.double()
+    B64 = A64 if dB is None else dB.double()
+    out = A64 @ B64
+    del A64, B64
+    return out
 
-    def max_err():
-        # only the sampled leaves come back to the host
-        e = 0.0
-        for (I, J), ex in exact.items():
-            r0, c0 = I * leaf, J * leaf
-            blk = C[r0:r0 + ex.shape[0], c0:c0 + ex.shape[1]].cpu().numpy()
-            e = max(e, float(np.abs(blk - ex).max()))
-        return e
 
+def max_err_full(C, exact, chunk: int = 4096) -> float:
+    """max |C - exact| over every element of the n x n product."""
+    e = 0.0
+    for r in range(0, C.shape[0], chunk):
+        e = max(e, float((C[r:r + chunk].double() - exact[r:r + chunk]).abs().max()))
+    return e
+
+
+def timed_product(sp, tree, tau, C, reps, precision=0, low_rel=0.0, sub_cull=False):
+    """Best-of-reps cull + leaf GEMM time (HIP events) and the last stats."""
+    best = None
+    for _ in range(reps):
+        st = sp.multiply_ex(tree, tree, tau, C, precision=precision, low_rel=low_rel,
+                            sub_cull=sub_cull)
+        ms = st["symbolic_ms"] + st["numeric_ms"]
+        if best is None or ms < best[0]:
+            best = (ms, st["numeric_ms"], st["symbolic_ms"])
+    return best, st
+
+
+THETAS = (1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7)     # relative split thresholds
+TARGETS = (1e-5, 1e-6)                                   # fixed max-norm errors
+
+
+def fastest_within(points, kind, target):
+    ok = [p for p in points if p["precision"] == kind and p["err"] <= target]
+    return min(ok, key=lambda p: p["ms"]) if ok else None
+
+
+def matched_error(sp, torch, wl, dA, C, exact, tau, leaf, reps=2):
+    """FP32 against split precision (and sub-leaf culling) at the same
+    max-norm error (Sec. IV.B, Sec. V.C: tolerances adjusted per variant until
+    the errors of Eq. matrix error match).  Every grid point's error is taken
+    over the whole matrix against the dense FP64 product.  Targets: the FP32
+    product's own error at the configured tau, and 1e-5 and 1e-6."""
     taus = [tau * 10.0 ** (h / 2) for h in range(11)]       # tau x 10^{0, 0.5, ..., 5}
-
-    tree = sp.build_tree(dA, leaf, bf16=True)
     points = []
+    tree = sp.build_tree(dA, leaf, bf16=True)
     for t_ in taus:
-        for lmul in (0, 256, 512, 1024, 2048, 4096, 8192, 16384):
-            prec = sp.PREC_SPLIT_BF16 if lmul else sp.PREC_FP32
-            best = None
-            for _ in range(reps):
-                st = sp.multiply_ex(tree, tree, t_, C, precision=prec, low_tol=lmul * t_)
-                ms = st["symbolic_ms"] + st["numeric_ms"]
-                best = ms if best is None else min(best, ms)
-            points.append({"precision": "split-bf16" if lmul else "fp32", "tau": t_,
-                           "low_tol": lmul * t_, "ms": round(best, 3), "err": max_err(),
-                           "ms_leaf_gemm": round(st["numeric_ms"], 3),
-                           "tasks": st["tasks"], "low_frac": round(st["tasks_low"] / max(1, st["tasks"]), 4)})
-    tree.free()
-    # FP16 LOW operands (8 times finer than BF16): the same tau grid, low_tol up to 64x higher
-    tree = sp.build_tree(dA, leaf, fp16=True)
-    for t_ in taus:
-        for lmul in [1024 * 2 ** h for h in range(11)]:           # 1024 .. 1048576
-            best = None
-            for _ in range(reps):
-                st = sp.multiply_ex(tree, tree, t_, C, precision=sp.PREC_SPLIT_FP16,
-                                    low_tol=lmul * t_)
-                ms = st["symbolic_ms"] + st["numeric_ms"]
-                best = ms if best is None else min(best, ms)
-            points.append({"precision": "split-fp16", "tau": t_, "low_tol": lmul * t_,
-                           "ms": round(best, 3), "err": max_err(),
-                           "ms_leaf_gemm": round(st["numeric_ms"], 3), "tasks": st["tasks"],
+        (ms, g_ms, _), st = timed_product(sp, tree, t_, C, reps)
+        points.append({"precision": "fp32", "tau": t_, "theta": 0.0, "ms": round(ms, 3),
+                       "ms_leaf_gemm": round(g_ms, 3), "err": max_err_full(C, exact),
+                       "tasks": st["tasks"], "low_frac": 0.0})
+        for th in THETAS:
+            (ms, g_ms, _), st = timed_product(sp, tree, t_, C, reps, sp.PREC_SPLIT_BF16, th)
+            points.append({"precision": "split-bf16", "tau": t_, "theta": th, "ms": round(ms, 3),
+                           "ms_leaf_gemm": round(g_ms, 3), "err": max_err_full(C, exact),
+                           "tasks": st["tasks"],
                            "low_frac": round(st["tasks_low"] / max(1, st["tasks"]), 4)})
     tree.free()
-    target = next(p["err"] for p in points if p["precision"] == "fp32" and p["tau"] == tau)
-    subleaf = None
+    tree = sp.build_tree(dA, leaf, fp16=True)
+    for t_ in taus:
+        for th in THETAS:
+            (ms, g_ms, _), st = timed_product(sp, tree, t_, C, reps, sp.PREC_SPLIT_FP16, th)
+            points.append({"precision": "split-fp16", "tau": t_, "theta": th, "ms": round(ms, 3),
+                           "ms_leaf_gemm": round(g_ms, 3), "err": max_err_full(C, exact),
+                           "tasks": st["tasks"],
+                           "low_frac": round(st["tasks_low"] / max(1, st["tasks"]), 4)})
+    tree.free()
     if leaf == 64:
         # sub-leaf culling: 32 x 32 sub-products tested inside each 64 x 64 one
         sub_tree = sp.build_tree(dA, leaf, subnorms=True)
         for h in range(-2, 10):                                # tau x 10^{-1, ..., 4.5}
             t_ = tau * 10.0 ** (h / 2)
-            best = None
-            for _ in range(reps):
-                st = sp.multiply_ex(sub_tree, sub_tree, t_, C, sub_cull=True)
-                ms = st["symbolic_ms"] + st["numeric_ms"]
-                if best is None or ms < best[0]:
-                    best = (ms, st["numeric_ms"])
-            points.append({"precision": "fp32-subleaf", "tau": t_, "low_tol": 0.0,
-                           "ms": round(best[0], 3), "ms_leaf_gemm": round(best[1], 3),
-                           "err": max_err(), "tasks": st["tasks"],
+            (ms, g_ms, _), st = timed_product(sp, sub_tree, t_, C, reps, sub_cull=True)
+            points.append({"precision": "fp32-subleaf", "tau": t_, "theta": 0.0,
+                           "ms": round(ms, 3), "ms_leaf_gemm": round(g_ms, 3),
+                           "err": max_err_full(C, exact), "tasks": st["tasks"],
                            "sub_products": st["subtasks"],
                            "sub_fraction": round(st["subtasks"] / max(1, 8 * st["tasks"]), 4)})
         sub_tree.free()
-        at_tau = next(p for p in points if p["precision"] == "fp32-subleaf" and p["tau"] == tau)
-        plain = next(p for p in points if p["precision"] == "fp32" and p["tau"] == tau)
-        subleaf = {"tau": tau, "leaf_products": plain["tasks"],
-                   "sub_products": at_tau["sub_products"], "sub_fraction": at_tau["sub_fraction"],
-                   "ms_plain": plain["ms"], "ms_subleaf": at_tau["ms"],
-                   "err_plain": plain["err"], "err_subleaf": at_tau["err"]}
+    floor = next(p["err"] for p in points if p["precision"] == "fp32" and p["tau"] == tau)
+    kinds = ("fp32", "split-bf16", "split-fp16", "fp32-subleaf")
 
-    def fastest(kind):
-        ok = [p for p in points if p["precision"] == kind and p["err"] <= target]
-        return min(ok, key=lambda p: p["ms"]) if ok else None
+    def at(target):
+        best = {k: fastest_within(points, k, target) for k in kinds}
+        f32 = best["fp32"]
+        out = {"target_err": target, "fastest": best,
+               "speedup_vs_fp32": {k: (round(f32["ms"] / best[k]["ms"], 3)
+                                       if f32 and best[k] else None) for k in kinds[1:]}}
+        if f32 is None:
+            out["note"] = ("no FP32 point reaches this error: at tau = %g the FP32 product's own "
+                           "rounding leaves %.3g" % (tau, floor))
+        return out
 
-    f32, spl, sub = fastest("fp32"), fastest("split-bf16"), fastest("fp32-subleaf")
-    s16 = fastest("split-fp16")
-
-    def split_roof(point, fmt, kernel):
-        if point is None:
-            return None
-        tb = measured_split_traffic(wl.name, point["tau"], point["low_tol"], fmt)
-        if tb is None:
-            return None
-        gbs = tb / (point["ms_leaf_gemm"] * 1e-3) / 1e9
-        return {"kernel": kernel, "bound": "hbm", "achieved": round(gbs, 1),
+    res = {"err_reference": "whole matrix, max-norm, against the dense FP64 product (Eq. matrix "
+                            "error)",
+           "fp32_error_at_tau": floor,
+           "at_fp32_error": at(floor),
+           "at_targets": {f"{t:g}": at(t) for t in TARGETS},
+           "grid": "tau x 10^{0, 0.5, ..., 5}; theta in %s for both split formats; sub-leaf "
+                   "culling tau x 10^{-1, -0.5, ..., 4.5}" % (list(THETAS),)}
+    plain = next(p for p in points if p["precision"] == "fp32" and p["tau"] == tau)
+    sub = [p for p in points if p["precision"] == "fp32-subleaf" and p["tau"] == tau]
+    if sub:
+        res["subleaf_same_tau"] = {"tau": tau, "leaf_products": plain["tasks"],
+                                   "sub_products": sub[0]["sub_products"],
+                                   "sub_fraction": sub[0]["sub_fraction"],
+                                   "ms_plain": plain["ms"], "ms_subleaf": sub[0]["ms"],
+                                   "err_plain": plain["err"], "err_subleaf": sub[0]["err"]}
+    m = res["at_fp32_error"]["fastest"]
+    for kind, fmt, kernel in (("split-bf16", "bf16", "leaf_gemm_split<64, false>"),
+                              ("split-fp16", "fp16", "leaf_gemm_split<64, true>")):
+        pt = m.get(kind)
+        if pt is None:
+            continue
+        tb = measured_split_traffic(wl.name, pt["tau"], pt["theta"], fmt)
+        if tb is not None:
+            gbs = tb / (pt["ms_leaf_gemm"] * 1e-3) / 1e9
+            res[f"{kind}_roofline"] = {
+                "kernel": kernel, "bound": "hbm", "achieved": round(gbs, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                "traffic": tb,
-                "note": "measured HBM bytes per launch / leaf-GEMM time; the LOW phase runs "
-                        "above this average, the HIGH tail below"}
+                "traffic": tb}
+    return res
 
-    split_roofline = split_roof(spl, "bf16", "leaf_gemm_split<64, false>")
-    split_fp16_roofline = split_roof(s16, "fp16", "leaf_gemm_split<64, true>")
-    return {
-        "target_err": target,
-        "err_sample": f"{len(tiles)} seeded output leaves (incl. diagonal), dense FP64 reference",
-        "fp32_at_target": f32, "split_at_target": spl, "split_fp16_at_target": s16,
-        "subleaf_at_target": sub,
-        "speedup_split_vs_fp32": round(f32["ms"] / spl["ms"], 3) if f32 and spl else None,
-        "speedup_split_fp16_vs_fp32": round(f32["ms"] / s16["ms"], 3) if f32 and s16 else None,
-        "speedup_subleaf_vs_fp32": round(f32["ms"] / sub["ms"], 3) if f32 and sub else None,
-        "split_roofline": split_roofline,
-        "split_fp16_roofline": split_fp16_roofline,
-        "subleaf_same_tau": subleaf,
-        "grid": "tau x 10^{0, 0.5, ..., 5}; low_tol = 0 (fp32), tau x {256, 512, ..., 16384} "
-                "(bf16), tau x {1024, 2048, ..., 1048576} (fp16); "
-                "sub-leaf culling: tau x 10^{-1, -0.5, ..., 4.5}",
-    }
+
+def run_config(sp, torch, dev, name, reps, tau=None, precisions=((0, 0.0),), with_exact=True):
+    """One of the other configurations of the benchmark: build + product timed
+    with HIP events per stage (best of `reps`), kept-leaf TFLOP/s on the
+    multiply and the whole step, the cull's share, and the whole-matrix
+    max-norm error against the dense FP64 product."""
+    import workloads
+    wl = workloads.WORKLOADS[name]
+    A = wl.matrix()
+    dA = torch.from_numpy(A).to(dev)
+    C = torch.empty_like(dA)
+    exact = dense_fp64(torch, dA) if with_exact else None
+    out = {"workload": wl.name, "n": wl.n, "leaf": wl.leaf, "points": []}
+    for t_ in ([tau] if tau is not None else list(wl.taus)):
+        for prec, th in precisions:
+            kw = dict(bf16=prec == sp.PREC_SPLIT_BF16, fp16=prec == sp.PREC_SPLIT_FP16)
+            tb = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                tree = sp.build_tree(dA, wl.leaf, **kw)
+                tb.append((time.perf_counter() - t0) * 1e3)
+                if _ < reps - 1:
+                    tree.free()
+            (ms, g_ms, c_ms), st = timed_product(sp, tree, t_, C, reps, prec, th)
+            tree.free()
+            flops = st["flops"]
+            pt = {"precision": {0: "fp32", 1: "split-bf16", 2: "split-fp16"}[prec], "tau": t_,
+                  "theta": th, "tasks": st["tasks"], "tasks_low": st["tasks_low"],
+                  "ms_build": round(min(tb), 4), "ms_cull": round(c_ms, 4),
+                  "ms_leaf_gemm": round(g_ms, 4), "ms_multiply": round(ms, 4),
+                  "cull_share": round(c_ms / ms, 4) if ms > 0 else None,
+                  "kept_tile_tflops_multiply": round(flops / (ms * 1e-3) / 1e12, 3),
+                  "kept_tile_tflops_step": round(flops / ((ms + min(tb)) * 1e-3) / 1e12, 3)}
+            if exact is not None:
+                pt["max_norm_err_vs_fp64_dense"] = max_err_full(C, exact)
+            out["points"].append(pt)
+    del dA, C, exact
+    torch.cuda.empty_cache()
+    return out
+
+
+def algdecay_sweep(sp, torch, dev, reps):
+    """The tau sweep of algdecay-n16384: plain FP32 against split BF16 at
+    theta = 1e-4 at each configured tau, and FP32 against both split formats
+    at the fixed errors 1e-5 and 1e-6 (tau on a 10^{1/2} grid from 1e-10 to
+    1e-4, theta from 1e-4 to 1e-9)."""
+    import workloads
+    wl = workloads.WORKLOADS["algdecay-n16384"]
+    dA = torch.from_numpy(wl.matrix()).to(dev)
+    C = torch.empty_like(dA)
+    exact = dense_fp64(torch, dA)
+    tree = sp.build_tree(dA, wl.leaf, bf16=True)
+    sweep = []
+    for t_ in wl.taus:
+        row = {"tau": t_}
+        for kind, prec, th in (("fp32", 0, 0.0), ("split-bf16", sp.PREC_SPLIT_BF16, 1e-4)):
+            (ms, g_ms, c_ms), st = timed_product(sp, tree, t_, C, reps, prec, th)
+            row[kind] = {"ms": round(ms, 4), "ms_cull": round(c_ms, 4),
+                         "ms_leaf_gemm": round(g_ms, 4), "tasks": st["tasks"],
+                         "tasks_low": st["tasks_low"], "err": max_err_full(C, exact)}
+        row["speedup_split"] = round(row["fp32"]["ms"] / row["split-bf16"]["ms"], 3)
+        sweep.append(row)
+    points = []
+    thetas = [10.0 ** -e for e in range(4, 10)]                # 1e-4 ... 1e-9
+    t16 = sp.build_tree(dA, wl.leaf, fp16=True)
+    for h in range(13):                                       # tau = 1e-10 ... 1e-4
+        t_ = 1e-10 * 10.0 ** (h / 2)
+        runs = [("fp32", tree, 0, 0.0)]
+        runs += [("split-bf16", tree, sp.PREC_SPLIT_BF16, th) for th in thetas]
+        runs += [("split-fp16", t16, sp.PREC_SPLIT_FP16, th) for th in thetas]
+        for kind, tr, prec, th in runs:
+            (ms, g_ms, _), st = timed_product(sp, tr, t_, C, reps, prec, th)
+            points.append({"precision": kind, "tau": t_, "theta": th, "ms": round(ms, 4),
+                           "err": max_err_full(C, exact), "tasks": st["tasks"],
+                           "tasks_low": st["tasks_low"]})
+    tree.free()
+    t16.free()
+    matched = {}
+    for target in TARGETS:
+        best = {k: fastest_within(points, k, target) for k in ("fp32", "split-bf16", "split-fp16")}
+        f32 = best["fp32"]
+        best["speedup_vs_fp32"] = {k: (round(f32["ms"] / best[k]["ms"], 3)
+                                       if f32 and best[k] else None)
+                                   for k in ("split-bf16", "split-fp16")}
+        matched[f"{target:g}"] = best
+    del dA, C, exact
+    torch.cuda.empty_cache()
+    return {"workload": wl.name, "n": wl.n, "leaf": wl.leaf, "tau_sweep": sweep,
+            "matched_error": matched,
+            "error": "whole matrix, max-norm, against the dense FP64 product"}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def oracle_single_core_c1() -> dict:
+    """The full FP64 oracle at expdecay-n1024 on one core (the paper times one
+    pinned core): a child process with one OpenMP thread and one CPU."""
+    import subprocess
+    code = ("import os, sys, time, json; sys.path.insert(0, %r); os.sched_setaffinity(0, "
+            "{sorted(os.sched_getaffinity(0))[0]}); import workloads, oracle; "
+            "wl = workloads.WORKLOADS['expdecay-n1024']; A = wl.matrix(); ts = []\n"
+            "for _ in range(3):\n t = time.perf_counter(); r = oracle.spamm(A, A, wl.leaf, wl.tau, "
+            "want_keys=False); ts.append(time.perf_counter() - t)\n"
+            "print(json.dumps({'K': r.K, 's': sorted(ts)[1]}))" % ROOT)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                       timeout=300)
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    flops = 2.0 * 32 ** 3 * d["K"]
+    return {"workload": "expdecay-n1024", "tau": 1e-6, "threads": 1, "kind": "oracle",
+            "ms": round(d["s"] * 1e3, 2), "gflops": round(flops / d["s"] / 1e9, 4),
+            "note": "full recursive FP64 oracle (norms + product), median of 3, one pinned core"}
 
 
 # ---------------------------------------------------------------------------
@@ -383,6 +517,50 @@ def serve_one_call(sp, torch, reqs, inputs):
                     "step, synchronizing; same results as served"}
 
 
+def serve_one_call_concurrent(sp, torch, reqs, inputs, threads=16):
+    """The same requests through the one-call API from `threads` host
+    threads, each on a stream of its own (tree build, which reads back the
+    root norm, then an asynchronous product per step; one synchronization
+    per request): the plain GPU form used concurrently."""
+    import threading
+    from workloads import SERVE_LEAF, SERVE_THETA
+    dev = torch.cuda.current_device()
+    errors = []
+
+    def worker(k):
+        try:
+            torch.cuda.set_device(dev)
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                for req in reqs[k::threads]:
+                    X = inputs[req.index]
+                    prec = sp.PREC_SPLIT_BF16 if req.split else sp.PREC_FP32
+                    for _ in range(max(1, req.chain_len)):
+                        t = sp.build_tree(X, SERVE_LEAF, stream=st, bf16=req.split)
+                        C = torch.empty_like(X)
+                        sp.multiply_ex(t, t, req.tau, C, stream=st, precision=prec,
+                                       low_rel=SERVE_THETA if req.split else 0.0, stats=False)
+                        t.free()
+                        X = C
+                    st.synchronize()
+        except Exception as e:        # reported below
+            errors.append(repr(e))
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ths = [threading.Thread(target=worker, args=(k,)) for k in range(threads)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"requests_per_s": round(len(reqs) / wall, 2), "wall_s": round(wall, 3),
+            "threads": threads, "errors": errors[:3],
+            "note": f"{threads} host threads on {threads} streams, each request through "
+                    "spamm_build_tree + asynchronous spamm_multiply_opts per step"}
+
+
 def serve_bench(sp, torch, dev, count, slots, budget_gib):
     """Saturation (closed loop, 2 x slots outstanding), then Poisson arrivals
     at 0.5x and 0.8x of it; returns the summary dict."""
@@ -440,6 +618,9 @@ def serve_bench(sp, torch, dev, count, slots, budget_gib):
     one = serve_one_call(sp, torch, reqs, inputs)
     print(f"one-call API, one request at a time: {one['requests_per_s']} req/s",
           file=sys.stderr, flush=True)
+    conc = serve_one_call_concurrent(sp, torch, reqs, inputs)
+    print(f"one-call API, 16 threads: {conc['requests_per_s']} req/s",
+          file=sys.stderr, flush=True)
     del inputs
     torch.cuda.empty_cache()
     return {
@@ -456,6 +637,9 @@ def serve_bench(sp, torch, dev, count, slots, budget_gib):
         "chain_kept_products_per_step": chain_steps,
         "one_call_sequential": one,
         "served_speedup_vs_one_call": round(sat["throughput_rps"] / one["requests_per_s"], 3),
+        "one_call_concurrent": conc,
+        "served_speedup_vs_one_call_concurrent":
+            round(sat["throughput_rps"] / conc["requests_per_s"], 3),
         "server": {k: info[k] for k in ("max_batch", "peak_active", "peak_used", "budget")},
     }
 
@@ -494,8 +678,6 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cluster1310-n32750")
     ap.add_argument("--tau", type=float, default=None)
-    ap.add_argument("--sample-tiles", type=int, default=96,
-                    help="output leaves checked against the dense FP64 product")
     ap.add_argument("--oracle-tiles", type=int, default=3072,
                     help="output leaves computed by the FP64 oracle (CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -511,8 +693,11 @@ def main() -> int:
     ap.add_argument("--sub-cull", action="store_true",
                     help="sub-leaf culling (32 x 32 sub-products inside 64 x 64 leaves); "
                          "value and roofline then count the performed sub-products")
-    ap.add_argument("--low-tol", type=float, default=0.8192,
-                    help="split precision: absolute LOW threshold on the norm product")
+    ap.add_argument("--theta", type=float, default=1e-4,
+                    help="split precision: LOW iff the norm product < theta ||A||_F ||B||_F")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other configurations (expdecay-n1024, cluster300-n7500, "
+                         "the algdecay-n16384 tau sweep)")
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense FP32 GEMM context of the same matrix")
     ap.add_argument("--no-sparse", action="store_true",
@@ -575,7 +760,7 @@ def main() -> int:
         tree = sp.build_tree(dA, leaf, bf16=split and not f16, fp16=f16,
                              subnorms=sub)                            # syncs once (root norm)
         st = sp.multiply_ex(tree, tree, tau, C, precision=prec,
-                            low_tol=args.low_tol if split else 0.0,
+                            low_rel=args.theta if split else 0.0,
                             sub_cull=sub)                             # events around cull and GEMM
         tree.free()
         return st
@@ -599,19 +784,12 @@ def main() -> int:
     value = flops / (ms_step * 1e-3) / 1e12
     gemm_tflops = flops / (gemm_ms * 1e-3) / 1e12
 
-    # ---- error on sampled output leaves -------------------------------------
+    # ---- error over the whole matrix against the dense FP64 product ----------
     d = st["depth"]
     N = 1 << d
-    tiles = sample_tiles(N, args.sample_tiles)
     Ch = C.cpu().numpy()
-    err_exact = 0.0
-    for (I, J) in tiles:
-        r0, r1 = I * leaf, min((I + 1) * leaf, n)
-        c0, c1 = J * leaf, min((J + 1) * leaf, n)
-        if r0 >= n or c0 >= n:
-            continue
-        exact = A[r0:r1].astype(np.float64) @ A[:, c0:c1].astype(np.float64)
-        err_exact = max(err_exact, float(np.abs(Ch[r0:r1, c0:c1] - exact).max()))
+    exact = dense_fp64(torch, dA)
+    err_exact = max_err_full(C, exact)
 
     out = {
         "metric": "kept-tile TFLOP/s (2 n_b^3 K per step / step time)",
@@ -633,8 +811,8 @@ def main() -> int:
             "ms_multiply": round(cull_ms + gemm_ms, 3), "ms_cull": round(cull_ms, 3),
             "ms_leaf_gemm": round(gemm_ms, 3),
             "ms_build": round(ms_step - cull_ms - gemm_ms, 3),
-            "max_norm_err_vs_fp64_dense_sampled": err_exact,
-            "error_sample_tiles": len(tiles),
+            "max_norm_err_vs_fp64_dense": err_exact,
+            "error_reference": "every element of C against the dense FP64 product on the GPU",
             "effective_tflops_2n3": round(2.0 * n ** 3 / (ms_step * 1e-3) / 1e12, 3),
         },
         "roofline": {
@@ -653,11 +831,11 @@ def main() -> int:
         out["roofline"]["traffic"] = measured_sub_traffic(wl.name, tau)
     if split:
         # the split kernel moves whole 16-bit leaves: rate it against HBM
-        tb = measured_split_traffic(wl.name, tau, args.low_tol, "fp16" if f16 else "bf16")
+        tb = measured_split_traffic(wl.name, tau, args.theta, "fp16" if f16 else "bf16")
         gbs = tb / (gemm_ms * 1e-3) / 1e9 if tb is not None else None
         out["dtype"] = "f32+f16" if f16 else "f32+bf16"
         out["config"]["precision"] = "split-fp16" if f16 else "split-bf16"
-        out["config"]["low_tol"] = args.low_tol
+        out["config"]["theta"] = args.theta
         out["config"]["tasks_low"] = st["tasks_low"]
         out["roofline"] = {
             "bound": "hbm", "achieved": round(gbs, 1) if gbs else None, "peak": HBM_PEAK_GBS,
@@ -717,7 +895,9 @@ def main() -> int:
     # variant, the fastest grid point whose error is <= E* (errors measured on
     # the same seeded output leaves, dense FP64 reference).
     if not args.no_matched_error:
-        out["matched_error"] = matched_error(sp, wl, A, dA, C, tau, leaf, n, N)
+        out["matched_error"] = matched_error(sp, torch, wl, dA, C, exact, tau, leaf)
+    del exact
+    torch.cuda.empty_cache()
 
     # ---- CPU baseline: the FP64 oracle on the sampled output leaves ----------
     if not args.no_cpu_baseline:
@@ -742,17 +922,31 @@ def main() -> int:
             "value": cflops / t / 1e12,
             "unit": "TFLOP/s",
             "cores": threads,
+            "threads": threads,
+            "cpu_model": cpu_model(),
             "kind": "oracle",
             "sample": (f"{len(otiles)} seeded output leaves of {wl.name} (tau={tau:g}), "
                        f"{int(counts.sum())} kept leaf products, recursive FP64 oracle incl. its "
-                       f"full-matrix norm pass, {t:.1f} s wall"),
+                       f"full-matrix norm pass, {t:.1f} s wall on {threads} OpenMP threads"),
+            "single_core_full_c1": oracle_single_core_c1(),
         }
+    # ---- the other configurations: the small case, the n = 7500 cluster and
+    # the algebraic-decay tau sweep (plain FP32 against split BF16) -----------
+    if not args.no_configs and not sub:
+        del dA, C
+        torch.cuda.empty_cache()
+        out["configs"] = {
+            "expdecay-n1024": run_config(sp, torch, dev, "expdecay-n1024", reps=20),
+            "cluster300-n7500": run_config(sp, torch, dev, "cluster300-n7500", reps=10),
+            "algdecay-n16384": algdecay_sweep(sp, torch, dev, reps=5),
+        }
+        print("configs done", file=sys.stderr, flush=True)
     # ---- the paper's own figures (single CPU core, FP32 SSE kernels), for
     # context only: another machine and other matrices, never a target -------
     out["paper_context"] = PAPER_CONTEXT
     # ---- serving: a stream of products and squaring chains --------------------
     if not args.no_serve:
-        del dA, C
+        dA = C = None
         torch.cuda.empty_cache()
         sv = serve_bench(sp, torch, dev, args.serve_requests, args.serve_slots,
                          args.serve_budget_gib)

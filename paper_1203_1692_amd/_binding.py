@@ -387,8 +387,11 @@ def multiply(A: Tree, B: Tree, tau: float, C, stream=None):
 
 
 def multiply_ex(A: Tree, B: Tree, tau: float, C, stream=None, precision: int = PREC_FP32,
-                low_tol: float = 0.0, sub_cull: bool = False, low_rel: float = 0.0) -> dict:
-    """C = A B under the SpAMM condition, timed (synchronizes); returns stats."""
+                low_tol: float = 0.0, sub_cull: bool = False, low_rel: float = 0.0,
+                stats: bool = True):
+    """C = A B under the SpAMM condition.  With stats (default) the cull and
+    the leaf GEMM are timed and the call synchronizes, returning the stats;
+    stats=False enqueues the product asynchronously and returns None."""
     _device_matrix(C, "C")
     if C.shape[0] != A.n:
         raise ValueError("C has the wrong shape")
@@ -396,8 +399,9 @@ def multiply_ex(A: Tree, B: Tree, tau: float, C, stream=None, precision: int = P
     o = _opts(tau, precision, low_tol, sub_cull, low_rel)
     _check(load().spamm_multiply_opts(A.handle, B.handle, ctypes.byref(o),
                                       ctypes.c_void_p(C.data_ptr()), _stream(stream),
-                                      ctypes.byref(st)), "spamm_multiply_opts")
-    return st.as_dict()
+                                      ctypes.byref(st) if stats else None),
+           "spamm_multiply_opts")
+    return st.as_dict() if stats else None
 
 
 def multiply_noalloc(A: Tree, B: Tree, tau: float, C, stream=None, precision: int = PREC_FP32,
