@@ -80,16 +80,20 @@ __host__ __device__ inline int leaf_index(int B, int r, int c)
     }
 }
 
-// BF16 copy of a leaf (split precision): rows of n_b bf16 (n_b in {32, 64}),
-// the 16-byte granules (8 bf16) of each row XOR-permuted so that 16 rows read
-// at one logical column by a ds_read_b128 hit 16 distinct groups of banks.
+// 16-bit copy of a leaf (split precision, n_b in {32, 64}): the columns (the k
+// of a left operand) cut into panels of 32 stored one after the other (one
+// panel at n_b = 32, two at 64), each panel row-major with rows of 32 values
+// (64 bytes: four 16-byte granules of 8 values); the granules of a row are
+// XOR-permuted by (r >> 2) & 3, so that 16 rows read at one logical column by
+// a ds_read_b128 hit 16 distinct groups of banks.  A panel (4 KB at n_b = 64)
+// is the unit the wide LOW kernel stages.
 template <int B>
 struct Leaf16Layout {
-    static constexpr int kGran = B / 8;                          // granules per row
-    static constexpr int kShift = kGran == 8 ? 1 : 2;
+    static constexpr int kKS = 32;                               // panel width
+    static constexpr int kPanel = B * kKS;                       // values per panel
     __host__ __device__ static constexpr int index(int r, int c)
     {
-        return r * B + 8 * ((c >> 3) ^ ((r >> kShift) & (kGran - 1))) + (c & 7);
+        return (c >> 5) * kPanel + r * kKS + 8 * (((c & 31) >> 3) ^ ((r >> 2) & 3)) + (c & 7);
     }
 };
 
@@ -129,7 +133,8 @@ __device__ inline int lane_id() { return __lane_id(); }
 __device__ inline uint64_t lanes_below() { return (uint64_t(1) << lane_id()) - 1; }
 
 // One product in a (possibly batched) leaf-GEMM launch: grid blocks
-// [block0, block0 + nblocks) work on this job.  tA / tBT point to the FP32
+// [block0, block0 + nblocks) work on this job (blocks of 2 x 2 output leaves,
+// or of 4 x 4 for the wide split kernel).  tA / tBT point to the FP32
 // leaves (LeafLayout), tA16 / tBT16 to the 16-bit ones (Leaf16Layout: BF16,
 // or FP16 at the per-leaf scale exponents escA / escB).
 struct GemmJob {
@@ -140,6 +145,7 @@ struct GemmJob {
     float *C;
     int64_t n;
     uint32_t nblocks, block0;
+    uint32_t nleaf;        // leaves per dimension, N = 2^d
     int32_t single;        // depth 0: one leaf
     // split precision: BF16 leaf copies and the LOW schedule (tA/tBT,
     // browptr/bent then hold the FP32 copies and the HIGH schedule), else null
@@ -173,7 +179,7 @@ constexpr int kMaxJobs = 16;
 // Leaf-GEMM kernels of a launch: whole FP32 leaf products, split precision
 // (LOW on BF16 or scaled FP16, HIGH on FP32, one kernel), FP32 with sub-leaf
 // culling.
-enum class GemmKind { Fp32, Split, SplitF16, Sub };
+enum class GemmKind { Fp32, Split, SplitF16, Sub, SplitWide };
 
 struct GemmJobs {          // passed by value as a kernel argument
     int32_t njobs;

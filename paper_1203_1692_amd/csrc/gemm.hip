@@ -73,13 +73,21 @@ __device__ inline void load_entries(const uint32_t *__restrict__ bent, uint32_t 
     __syncthreads();
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of blocks (linear-index order) so its L2 sees neighbours.
+// Workgroups are dispatched round-robin over the 8 XCDs (bid mod 8).  Deal
+// the blocks out in chunks of 16 consecutive ones (linear-index order: a
+// 4 x 4 patch of blocks), chunk c to XCD c mod 8, each XCD taking its chunks
+// in order: neighbours share an XCD's L2, and every XCD samples the whole
+// matrix.  (Contiguous eighths of the linear index put the two off-diagonal
+// quadrants, where decaying products are few, on half of the XCDs: with
+// split precision the busiest XCD then held 1.2x its share of the LOW
+// products and 1.8x of the HIGH ones.)
 __device__ inline uint32_t xcd_block(uint32_t bid, uint32_t nblocks)
 {
-    if (nblocks % 8u != 0u)
+    constexpr uint32_t kChunk = 16;
+    if (nblocks % (8u * kChunk) != 0u)
         return bid;
-    return (bid % 8u) * (nblocks / 8u) + bid / 8u;
+    const uint32_t x = bid % 8u, s = bid / 8u;
+    return ((s / kChunk) * 8u + x) * kChunk + s % kChunk;
 }
 
 // Wave w copies panel p of operand leaf w (0: A_2I, 1: A_2I+1, 2: B_2J,
@@ -676,6 +684,268 @@ __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
     write_leaf32<B>(lo, (int64_t)(I0 + qa) * B, (int64_t)(J0 + qb) * B, job.n, job.C, lane);
 }
 
+// ---------------------------------------------------------------------------
+// Wide split kernel (BF16 LOW operands, n_b = 64, depth >= 2).  A LOW product
+// is cheap on the matrix units and its 8 KB operands dominate: with blocks of
+// 2 x 2 output leaves every staged leaf feeds at most 2 products (3.1 per
+// entry of 4 leaves at the benchmark's matched-error point), and the kernel
+// is bound by HBM.  Here a workgroup of 16 waves owns a block of 4 x 4 output
+// leaves (a tier-(d-2) node; wave w = 4r + c owns leaf (4I + r, 4J + c) and is
+// its only writer), so a staged A leaf feeds up to 4 products and the bytes
+// per product fall by about 1.7x.  The schedules come from the cull as the
+// four 2 x 2 children's lists; the block merges them in LDS into one list
+// per class of (k | 16-bit mask << 16), k ascending.
+//
+// Stages are half leaves (one 32-wide k-panel of Leaf16Layout, 4 KB) of the
+// up to 4 A leaves (rows) and 4 B leaves (columns) an entry needs: 32 KB per
+// stage in a 4-deep LDS ring, three stages in flight while one is multiplied
+// (the workgroup fills the CU, so its own prefetch must cover the copies'
+// latency).  A wave waits only for its own copies of the stage it needs
+// (vmcnt counts exactly its outstanding copies), then the barrier makes every
+// wave's copies visible.  Then the block's HIGH products (few, and
+// concentrated in the blocks along the diagonal) on FP32 MFMA: stages of the
+// FP32 k-panels (8 KB each, 64 KB per stage) in a 2-deep ring over the same
+// LDS.  One running FP32 sum per leaf: its LOW products over k ascending,
+// then its HIGH products over k ascending.  (A second launch for the HIGH
+// products alone, adding to the LOW sums in C, was 14 % slower: they could
+// no longer overlap the LOW work of other blocks.)
+constexpr int kWideWaves = 16;
+
+// Workgroup barrier without the memory fence of __syncthreads (whose release
+// half would wait for every outstanding copy, the prefetched stages
+// included): the caller has already waited, by vmcnt, for its own
+// direct-to-LDS copies that must be visible, and its LDS reads of the
+// buffer about to be refilled were consumed before it got here.  The empty
+// asm statements keep the compiler from moving memory accesses across.
+__device__ inline void barrier_no_fence()
+{
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+}
+
+constexpr int kWideRing = 4;                          // LOW stages in the ring
+constexpr int kWideStage16 = 8 * Leaf16Layout<64>::kPanel;   // 16-bit values per LOW stage
+constexpr int kWideStage32 = 8 * LeafLayout<64>::kPanel;     // floats per HIGH stage
+
+struct WideShape {
+    static constexpr size_t kRing = sizeof(uint16_t) * kWideRing * kWideStage16;   // 128 KB
+    static_assert(kRing == sizeof(float) * 2 * kWideStage32, "the HIGH ring reuses the LOW one");
+    static constexpr size_t kMask = sizeof(uint32_t) * kMaxEnt;
+    static constexpr size_t kList = sizeof(uint32_t) * kMaxEnt;
+    static constexpr size_t kLds = kRing + kMask + kList + sizeof(uint32_t) * kWideWaves;
+};
+
+// Merges the schedules of the four 2 x 2 children of 4 x 4 block P4 into
+// list[0..count): k ascending, entry k | mask << 16, mask bit 4 r + c for leaf
+// (r, c) of the block.  kmask: kMaxEnt words of scratch; wsum: one word per
+// wave.  Returns the count (every thread).
+__device__ inline uint32_t merge_children(const uint32_t *__restrict__ rp,
+                                          const uint32_t *__restrict__ ent, uint32_t P4,
+                                          uint32_t N, uint32_t *kmask, uint32_t *list,
+                                          uint32_t *wsum)
+{
+    for (uint32_t i = threadIdx.x; i < N; i += blockDim.x)
+        kmask[i] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (uint32_t ch = 0; ch < 4; ++ch) {
+        // child ch = 2a + b holds leaves (2a + a', 2b + b'), its bit q = 2a' + b'
+        const uint32_t P2 = 4u * P4 + ch, a = ch >> 1, b = ch & 1u;
+        const uint32_t e0 = rp[P2], e1 = rp[P2 + 1];
+        for (uint32_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+            const uint32_t x = ent[e], k = x & 0xFFFFu, m = x >> 16;
+            uint32_t bits = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q)
+                if ((m >> q) & 1u)
+                    bits |= 1u << (4 * (2 * a + (q >> 1)) + 2 * b + (q & 1u));
+            atomicOr(&kmask[k], bits);
+        }
+    }
+    __syncthreads();
+    // compaction in k order: one slot per thread per round
+    uint32_t base = 0;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (uint32_t r0 = 0; r0 < N; r0 += blockDim.x) {
+        const uint32_t k = r0 + threadIdx.x;
+        const uint32_t m = k < N ? kmask[k] : 0u;
+        const uint64_t bal = __ballot(m != 0u);
+        if (lane == 0)
+            wsum[w] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (int i = 0; i < kWideWaves; ++i) {
+            const uint32_t c = wsum[i];
+            before += i < w ? c : 0u;
+            total += c;
+        }
+        if (m != 0u)
+            list[base + before + (uint32_t)__popcll(bal & lanes_below())] = k | (m << 16);
+        base += total;
+        __syncthreads();                     // wsum is rewritten next round
+    }
+    return base;
+}
+
+__global__ __launch_bounds__(1024) void leaf_gemm_split_wide(const GemmJobs jobs)
+{
+    constexpr int B = 64, MB = 2;
+    constexpr int P16 = Leaf16Layout<B>::kPanel;       // 2048 values: one 16-bit k-panel
+    extern __shared__ float smem[];
+    uint16_t *ring16 = (uint16_t *)smem;
+    uint32_t *kmask = (uint32_t *)((char *)smem + WideShape::kRing);
+    uint32_t *list = kmask + kMaxEnt;
+    uint32_t *wsum = list + kMaxEnt;
+    const GemmJob &job = jobs.job[job_of(jobs, blockIdx.x)];
+    const uint32_t P4 = xcd_block(blockIdx.x - job.block0, job.nblocks);
+    const uint32_t I0 = 4 * lin_row(P4), J0 = 4 * lin_col(P4);
+    // the wave index in a scalar register: every per-wave decision below
+    // (copies, waits, the mask test) is then a scalar branch.  The waves of
+    // one SIMD (w mod 4 = s) own the leaves (i, (i + s) mod 4): an entry's
+    // mask is close to the outer product of a set of rows and a set of
+    // columns, and this Latin square spreads such a product set over the four
+    // SIMDs rather than piling a whole column onto one.
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int r = w >> 2, c = (r + (w & 3)) & 3;
+    const int bit = 4 * r + c;
+    const uint32_t NK = job.nleaf;                     // k ranges over [0, N)
+    const uint16_t *__restrict__ tA16 = (const uint16_t *)job.tA16;
+    const uint16_t *__restrict__ tBT16 = (const uint16_t *)job.tBT16;
+
+    floatx16 acc[MB][MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < MB; ++j)
+            acc[i][j] = floatx16{0};
+
+    // ---- LOW products: 16-bit half-leaf panels, 4-deep ring ----------------
+    const uint32_t nlo = merge_children(job.browptr_lo, job.bent_lo, P4, NK, kmask, list, wsum);
+    // wave w copies half (w & 1) of panel w >> 1 (0..3: A rows, 4..7: B
+    // columns): two 1 KB direct-to-LDS copies, or none if no leaf needs it
+    const int pan = w >> 1, part = w & 1;
+    auto issue_lo = [&](uint32_t st) -> int {
+        const uint32_t ent = list[st >> 1], k = ent & 0xFFFFu, m = ent >> 16;
+        const uint32_t need = pan < 4 ? (m >> (4 * pan)) & 0xFu : (m >> (pan - 4)) & 0x1111u;
+        if (need == 0u)
+            return 0;
+        const uint16_t *leaf = pan < 4 ? tA16 + (int64_t)lin_index(I0 + pan, k) * (B * B)
+                                       : tBT16 + (int64_t)lin_index(k, J0 + (pan - 4)) * (B * B);
+        const uint16_t *src = leaf + (st & 1u) * P16 + part * (P16 / 2) + 8 * lane;
+        uint16_t *dst = ring16 + (st % kWideRing) * kWideStage16 + pan * P16 + part * (P16 / 2);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            __builtin_amdgcn_global_load_lds((global_void_t *)(src + 512 * i),
+                                             (lds_void_t *)(dst + 512 * i), 16, 0, 0);
+        return 2;
+    };
+    const uint32_t S = 2 * nlo;
+    int c1 = 0, c2 = 0, c3 = 0;          // copies this wave issued for stages t+1, t+2 (t+3)
+    if (S > 0)
+        issue_lo(0);
+    if (S > 1)
+        c1 = issue_lo(1);
+    if (S > 2)
+        c2 = issue_lo(2);
+    const int row = lane & 31, h = lane >> 5;
+    for (uint32_t t = 0; t < S; ++t) {
+        // this wave's copies of stage t have landed once at most those of
+        // stages t+1 and t+2 are outstanding
+        const int later = c1 + c2;
+        if (later == 0)
+            __builtin_amdgcn_s_waitcnt(0x0F70);         // vmcnt(0)
+        else if (later == 2)
+            __builtin_amdgcn_s_waitcnt(0x0F72);         // vmcnt(2)
+        else
+            __builtin_amdgcn_s_waitcnt(0x0F74);         // vmcnt(4)
+        barrier_no_fence();
+        // stage t+3 goes to the buffer every wave finished reading at t-1
+        c3 = t + 3 < S ? issue_lo(t + 3) : 0;
+        const uint32_t ent = list[t >> 1];
+        if ((ent >> (16 + bit)) & 1u) {
+            const uint16_t *buf = ring16 + (t % kWideRing) * kWideStage16;
+            const uint16_t *Ap = buf + r * P16;
+            const uint16_t *Bp = buf + (4 + c) * P16;
+            bf16x8 av[2][MB], bv[2][MB];
+#pragma unroll
+            for (int st = 0; st < 2; ++st) {
+                const int col = 16 * st + 8 * h;
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+                    av[st][i] = *reinterpret_cast<const bf16x8 *>(
+                        Ap + Leaf16Layout<B>::index(i * 32 + row, col));
+#pragma unroll
+                for (int j = 0; j < MB; ++j)
+                    bv[st][j] = *reinterpret_cast<const bf16x8 *>(
+                        Bp + Leaf16Layout<B>::index(j * 32 + row, col));
+            }
+#pragma unroll
+            for (int st = 0; st < 2; ++st)
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < MB; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[st][i], bv[st][j],
+                                                                            acc[i][j], 0, 0, 0);
+        }
+        c1 = c2;
+        c2 = c3;
+    }
+    __syncthreads();                      // every wave is done with the LOW ring and list
+
+    // ---- HIGH products: FP32 k-panels (8 KB), 64 KB stages, 2-deep ring --------
+    constexpr int P32 = LeafLayout<B>::kPanel;
+    float *ring32 = smem;
+    const float *__restrict__ tA = (const float *)job.tA;
+    const float *__restrict__ tBT = (const float *)job.tBT;
+    const uint32_t nhi = merge_children(job.browptr, job.bent, P4, NK, kmask, list, wsum);
+    // wave w copies half (w & 1) of FP32 panel w >> 1: four 1 KB copies
+    auto issue_hi = [&](uint32_t st) {
+        const uint32_t ent = list[st >> 1], k = ent & 0xFFFFu, m = ent >> 16;
+        const uint32_t need = pan < 4 ? (m >> (4 * pan)) & 0xFu : (m >> (pan - 4)) & 0x1111u;
+        if (need == 0u)
+            return;
+        const float *leaf = pan < 4 ? tA + (int64_t)lin_index(I0 + pan, k) * (B * B)
+                                    : tBT + (int64_t)lin_index(k, J0 + (pan - 4)) * (B * B);
+        const float *src = leaf + (st & 1u) * P32 + part * (P32 / 2) + 4 * lane;
+        float *dst = ring32 + (st & 1u) * kWideStage32 + pan * P32 + part * (P32 / 2);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            __builtin_amdgcn_global_load_lds((global_void_t *)(src + 256 * i),
+                                             (lds_void_t *)(dst + 256 * i), 16, 0, 0);
+    };
+    const uint32_t T = 2 * nhi;
+    if (T > 0)
+        issue_hi(0);
+    for (uint32_t t = 0; t < T; ++t) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);             // vmcnt(0)
+        __syncthreads();
+        if (t + 1 < T)
+            issue_hi(t + 1);
+        const uint32_t ent = list[t >> 1];
+        if ((ent >> (16 + bit)) & 1u) {
+            const float *buf = ring32 + (t & 1u) * kWideStage32;
+            panel_mfma32<B>(buf + r * P32, buf + (4 + c) * P32, acc, lane);
+        }
+    }
+    write_leaf32<B>(acc, (int64_t)(I0 + r) * B, (int64_t)(J0 + c) * B, job.n, job.C, lane);
+}
+
+// jobs.block0 / nblocks count 4 x 4 blocks here
+static hipError_t launch_split_wide(const GemmJobs &jobs, hipStream_t s)
+{
+    constexpr size_t lds = WideShape::kLds;
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void *)leaf_gemm_split_wide,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess)
+        return attr;
+    hipLaunchKernelGGL(leaf_gemm_split_wide, dim3(jobs.nblocks), dim3(64 * kWideWaves), lds, s,
+                       jobs);
+    return hipGetLastError();
+}
+
 template <int B>
 static hipError_t launch_fp32(const GemmJobs &jobs, hipStream_t s)
 {
@@ -724,6 +994,8 @@ hipError_t launch_gemm_jobs(int leaf, GemmKind kind, const GemmJobs &jobs, hipSt
     switch (kind) {
     case GemmKind::Sub:
         return leaf == 64 ? launch_sub(jobs, s) : hipErrorInvalidValue;
+    case GemmKind::SplitWide:
+        return leaf == 64 ? launch_split_wide(jobs, s) : hipErrorInvalidValue;
     case GemmKind::Split:
         switch (leaf) {
         case 32: return launch_split<32, false>(jobs, s);
@@ -751,6 +1023,8 @@ GemmKind plan_kind(const spamm_plan *p)
 {
     if (p->sub)
         return GemmKind::Sub;
+    if (p->precision == SPAMM_PREC_SPLIT_BF16 && p->leaf == 64 && p->depth >= 2)
+        return GemmKind::SplitWide;
     return p->precision == SPAMM_PREC_SPLIT_FP16   ? GemmKind::SplitF16
            : p->precision == SPAMM_PREC_SPLIT_BF16 ? GemmKind::Split
                                                    : GemmKind::Fp32;
@@ -767,7 +1041,9 @@ void plan_jobs(const spamm_plan *p, float *C, GemmJob &j)
     j.bent = p->bent;
     j.C = C;
     j.n = p->n;
-    j.nblocks = (uint32_t)p->nblocks;
+    j.nleaf = 1u << p->depth;
+    // the wide split kernel's workgroups own 4 x 4 output leaves
+    j.nblocks = (uint32_t)p->nblocks / (plan_kind(p) == GemmKind::SplitWide ? 4u : 1u);
     j.block0 = 0;
     j.single = p->depth == 0 ? 1 : 0;
     j.tA16 = split ? (const void *)p->A->tiles16 : nullptr;
@@ -798,7 +1074,6 @@ hipError_t launch_gemm(const spamm_plan *p, float *C, hipStream_t s)
 {
     GemmJobs jobs{};
     jobs.njobs = 1;
-    jobs.nblocks = (uint32_t)p->nblocks;
     if (p->sub) {
         hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s,
                            (unsigned long long *)(p->leafK + 2));
@@ -807,6 +1082,7 @@ hipError_t launch_gemm(const spamm_plan *p, float *C, hipStream_t s)
             return e;
     }
     plan_jobs(p, C, jobs.job[0]);
+    jobs.nblocks = jobs.job[0].nblocks;
     return launch_gemm_jobs(p->leaf, plan_kind(p), jobs, s);
 }
 

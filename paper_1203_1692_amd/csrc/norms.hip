@@ -142,11 +142,8 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
     constexpr int P = B + 1;           // LDS pitch of the transpose buffer
     static_assert(M >= 1 && (M & (M - 1)) == 0, "leaf must be 16, 32 or 64");
     // TWO (64 x 64 leaves): the transpose runs in two halves of 32 source
-    // rows (one k-panel of the transposed copy each), which halves the LDS
-    // and lets more workgroups share a CU.  A 16-bit transposed row (128
-    // bytes) spans both halves: each lane keeps its first-half values packed
-    // in registers and writes them with the second half, so every row is
-    // written whole.
+    // rows (one k-panel of the transposed copy each, FP32 and 16-bit alike),
+    // which halves the LDS and lets more workgroups share a CU.
     static_assert(!TWO || B == 64, "two-pass transpose for 64 x 64 leaves");
     constexpr int NPASS = TWO ? 2 : 1;
     constexpr int RH = B / NPASS, MH = M / NPASS;
@@ -237,7 +234,6 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
         }
     }
     // transposed copies through LDS, RH source rows at a time
-    uint2 stash[MH];                  // 16-bit copies, two passes: pass 0's half rows
 #pragma unroll
     for (int h = 0; h < NPASS; ++h) {
         if (pack) {
@@ -277,17 +273,7 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
                 if constexpr (B >= 32) {
                     if (tilesT16 != nullptr) {
                         uint16_t *d16 = tilesT16 + dl * (B * B) + Leaf16Layout<B>::index(rt, ct);
-                        if constexpr (NPASS == 2) {
-                            const uint2 b = scale16 != nullptr ? pack_fp16x4(t, e16) : pack_bf16x4(t);
-                            if (h == 0) {
-                                stash[i] = b;
-                            } else {
-                                // both halves of the 128-byte row together
-                                *reinterpret_cast<uint2 *>(tilesT16 + dl * (B * B) +
-                                                           Leaf16Layout<B>::index(rt, cr)) = stash[i];
-                                *reinterpret_cast<uint2 *>(d16) = b;
-                            }
-                        } else if (scale16 != nullptr) {
+                        if (scale16 != nullptr) {
                             store_fp16x4(d16, t, e16);
                         } else {
                             store_bf16x4(d16, t);

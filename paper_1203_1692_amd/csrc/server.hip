@@ -262,20 +262,26 @@ bool launch_batches(spamm_server *S)
             (S->active[i].job.rq.leaf == leaf && (int)batch.size() < kMaxJobs ? batch : rest)
                 .push_back(i);
         ready.swap(rest);
-        // jobs of each kernel kind (FP32, BF16 split, FP16 split) go to one launch
-        constexpr GemmKind kinds[3] = {GemmKind::Fp32, GemmKind::Split, GemmKind::SplitF16};
-        GemmJobs tabs[3] = {};
+        // jobs of each kernel kind (FP32, BF16 split on 2 x 2 or 4 x 4 blocks,
+        // FP16 split) go to one launch
+        constexpr int kKinds = 4;
+        constexpr GemmKind kinds[kKinds] = {GemmKind::Fp32, GemmKind::Split, GemmKind::SplitF16,
+                                            GemmKind::SplitWide};
+        GemmJobs tabs[kKinds] = {};
         hipError_t e = hipSuccess;
         for (size_t i : batch) {
             Active &a = S->active[i];
             const GemmKind kind = plan_kind(a.plan);
-            GemmJobs &tab = tabs[kind == GemmKind::Split ? 1 : kind == GemmKind::SplitF16 ? 2 : 0];
+            int slot = 0;
+            while (slot + 1 < kKinds && kinds[slot] != kind)
+                ++slot;
+            GemmJobs &tab = tabs[slot];
             GemmJob &j = tab.job[tab.njobs++];
             plan_jobs(a.plan, a.job.rq.C, j);
             j.block0 = tab.nblocks;
             tab.nblocks += j.nblocks;
         }
-        for (int k = 0; k < 3 && e == hipSuccess; ++k)
+        for (int k = 0; k < kKinds && e == hipSuccess; ++k)
             if (tabs[k].njobs > 0)
                 e = launch_gemm_jobs(leaf, kinds[k], tabs[k], S->gemm);
         hipEvent_t bev = S->spare.back();
