@@ -325,6 +325,55 @@ def algdecay_sweep(sp, torch, dev, reps):
             "error": "whole matrix, max-norm, against the dense FP64 product"}
 
 
+def write_traffic_record(args) -> int:
+    """HBM bytes per launch of one kernel from two rocprofv3 --pmc runs of the
+    same bench command with --copy-calibration: the FETCH_SIZE and
+    WRITE_SIZE counters (KiB per dispatch) of the kernel, each scaled by
+    true / counted bytes of the three 1 GiB device copies of that run."""
+    import csv
+    kernel, fcsv, wcsv = args.traffic_record
+
+    def rows(path, counter):
+        out = []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r.get("Counter_Name") == counter:
+                    out.append((r["Kernel_Name"], float(r["Counter_Value"]),
+                                int(r.get("Grid_Size", 0) or 0)))
+        return out
+
+    rec = {"kernel": kernel, "gemm_sources_sha256": kernel_source_digest(),
+           "copy_calibration_KiB": {"true": 1 << 20}, "scale": {},
+           "kernel_KiB_per_dispatch": {}}
+    for counter, path in (("FETCH_SIZE", fcsv), ("WRITE_SIZE", wcsv)):
+        rs = rows(path, counter)
+        # the three 1 GiB device copies: a grid of 131072 work items each
+        copies = [v for k, v, g in rs if "copyBuffer" in k and g == 131072]
+        if len(copies) != 3:
+            copies = [v for k, v, g in rs
+                      if "copyBuffer" in k and 0.4 * (1 << 20) <= v <= 2.5 * (1 << 20)]
+        ker = [v for k, v, g in rs if k.startswith(kernel) or ("::" + kernel) in k]
+        if not copies or not ker:
+            print(f"{counter}: copies {len(copies)}, {kernel} dispatches {len(ker)}",
+                  file=sys.stderr)
+            return 1
+        cal = sum(copies) / len(copies)
+        rec["copy_calibration_KiB"][counter] = cal
+        rec["scale"][counter] = (1 << 20) / cal
+        rec["kernel_KiB_per_dispatch"][counter] = sum(ker) / len(ker)
+    rd = rec["kernel_KiB_per_dispatch"]["FETCH_SIZE"] * rec["scale"]["FETCH_SIZE"] * 1024
+    wr = rec["kernel_KiB_per_dispatch"]["WRITE_SIZE"] * rec["scale"]["WRITE_SIZE"] * 1024
+    rec.update(read_bytes_per_launch=rd, write_bytes_per_launch=wr, bytes_per_launch=rd + wr)
+    for k in ("workload", "tau") + (("theta",) if "split" in kernel else ()):
+        if getattr(args, k, None) is not None:
+            rec[k] = getattr(args, k)
+    out = args.record_out or os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+    return 0
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -695,6 +744,14 @@ def main() -> int:
                          "value and roofline then count the performed sub-products")
     ap.add_argument("--theta", type=float, default=1e-4,
                     help="split precision: LOW iff the norm product < theta ||A||_F ||B||_F")
+    ap.add_argument("--no-error", action="store_true",
+                    help="skip the whole-matrix error against the dense FP64 product (and the "
+                         "matched-error comparison that needs it): short profiler runs")
+    ap.add_argument("--traffic-record", nargs=3, metavar=("KERNEL", "FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic record of KERNEL from two rocprofv3 --pmc "
+                         "counter CSVs (FETCH_SIZE, WRITE_SIZE) of one bench run with "
+                         "--copy-calibration, then exit (no GPU)")
+    ap.add_argument("--record-out", default=None, help="path of the traffic record")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other configurations (expdecay-n1024, cluster300-n7500, "
                          "the algdecay-n16384 tau sweep)")
@@ -708,6 +765,9 @@ def main() -> int:
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-budget-gib", type=float, default=96.0)
     args = ap.parse_args()
+
+    if args.traffic_record:
+        return write_traffic_record(args)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the SpAMM path here is single-device "
@@ -788,8 +848,8 @@ def main() -> int:
     d = st["depth"]
     N = 1 << d
     Ch = C.cpu().numpy()
-    exact = dense_fp64(torch, dA)
-    err_exact = max_err_full(C, exact)
+    exact = None if args.no_error else dense_fp64(torch, dA)
+    err_exact = None if exact is None else max_err_full(C, exact)
 
     out = {
         "metric": "kept-tile TFLOP/s (2 n_b^3 K per step / step time)",
@@ -894,7 +954,7 @@ def main() -> int:
     # E* = the error of the FP32 product at the configured tau; for each
     # variant, the fastest grid point whose error is <= E* (errors measured on
     # the same seeded output leaves, dense FP64 reference).
-    if not args.no_matched_error:
+    if not args.no_matched_error and exact is not None:
         out["matched_error"] = matched_error(sp, torch, wl, dA, C, exact, tau, leaf)
     del exact
     torch.cuda.empty_cache()

@@ -326,11 +326,14 @@ def test_cluster1310_split_theta_1e4(cluster1310, gpu):
     check_split(r, seed=33)
 
 
-@pytest.mark.parametrize("fmt,low", [("bf16", 0.8192), ("fp16", 3.2768)])
-def test_cluster1310_split_matched_error_point(cluster1310, gpu, fmt, low):
+@pytest.mark.parametrize("fmt,tau,theta", [("bf16", 3.1622776601683795e-05, 1e-6),
+                                           ("fp16", 1e-4, 1e-5)])
+def test_cluster1310_split_matched_error_point(cluster1310, gpu, fmt, tau, theta):
     """cluster1310-n32750 at the split products' matched-error points of the
-    benchmark (tau = 1e-4)."""
-    r = SplitRun(gpu, cluster1310.A, cluster1310.leaf, 1e-4, low, fmt, "cluster1310-n32750")
+    benchmark (the fastest split product within the FP32 product's
+    whole-matrix error)."""
+    r = SplitRun(gpu, cluster1310.A, cluster1310.leaf, tau, 0.0, fmt, "cluster1310-n32750",
+                 rel=theta)
     assert r.stats["tasks_low"] > 0.9 * r.stats["tasks"]
     check_split(r, seed=31)
 
