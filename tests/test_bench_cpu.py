@@ -52,12 +52,13 @@ def test_committed_split_traffic_records_name_their_point():
     for kind, fmt in (("leaf_gemm_split", "bf16"), ("leaf_gemm_split_fp16", "fp16")):
         path = os.path.join(ROOT, "profiles", f"{kind}_cluster1310-n32750_traffic.json")
         rec = json.load(open(path))
-        assert rec["tau"] > 0 and rec["low_tol"] > 0 and rec["bytes_per_launch"] > 0
+        assert rec["tau"] > 0 and rec["theta"] > 0 and rec["bytes_per_launch"] > 0
+        assert rec["workload"] == "cluster1310-n32750"
         # another point, or other kernel sources, never reuse the record
         assert bench.measured_split_traffic("cluster1310-n32750", rec["tau"] * 10,
-                                            rec["low_tol"], fmt) is None
+                                            rec["theta"], fmt) is None
         assert bench.measured_split_traffic("cluster1310-n32750", rec["tau"],
-                                            rec["low_tol"] * 2, fmt) is None
+                                            rec["theta"] * 2, fmt) is None
 
 
 def test_sample_tiles_distinct_sorted_in_range():
