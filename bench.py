@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MFMA_FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+MFMA_16BIT_PEAK_TFLOPS = 2516.6 # MI355X dense BF16 / FP16 matrix peak
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E peak
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "leaf_gemm_cluster1310-n32750_traffic.json")
 
@@ -218,7 +219,7 @@ def matched_error(sp, torch, wl, dA, C, exact, tau, leaf, reps=2):
                                    "ms_plain": plain["ms"], "ms_subleaf": sub[0]["ms"],
                                    "err_plain": plain["err"], "err_subleaf": sub[0]["err"]}
     m = res["at_fp32_error"]["fastest"]
-    for kind, fmt, kernel in (("split-bf16", "bf16", "leaf_gemm_split<64, false>"),
+    for kind, fmt, kernel in (("split-bf16", "bf16", "leaf_gemm_split_wide"),
                               ("split-fp16", "fp16", "leaf_gemm_split<64, true>")):
         pt = m.get(kind)
         if pt is None:
@@ -226,10 +227,18 @@ def matched_error(sp, torch, wl, dA, C, exact, tau, leaf, reps=2):
         tb = measured_split_traffic(wl.name, pt["tau"], pt["theta"], fmt)
         if tb is not None:
             gbs = tb / (pt["ms_leaf_gemm"] * 1e-3) / 1e9
+            # and against the matrix units: LOW products at the dense 16-bit
+            # peak, HIGH ones at the FP32 one
+            low = pt["tasks"] * pt["low_frac"]
+            mfma_ms = (2.0 * leaf ** 3 * (low / (MFMA_16BIT_PEAK_TFLOPS * 1e12) +
+                                          (pt["tasks"] - low) / (MFMA_FP32_PEAK_TFLOPS * 1e12))
+                       * 1e3)
             res[f"{kind}_roofline"] = {
                 "kernel": kernel, "bound": "hbm", "achieved": round(gbs, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                "traffic": tb}
+                "traffic": tb,
+                "mfma_ideal_ms": round(mfma_ms, 3),
+                "mfma_frac": round(mfma_ms / pt["ms_leaf_gemm"], 4)}
     return res
 
 
