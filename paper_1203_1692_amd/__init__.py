@@ -1,5 +1,6 @@
-"""MI355X-native SpAMM: quadtree norm build, tier-by-tier cull and a
-persistent FP32-MFMA leaf GEMM behind the C ABI of include/spamm.h, plus a
+"""MI355X-native SpAMM: quadtree norm build, tier-by-tier cull and an
+FP32-MFMA leaf GEMM (one workgroup per block of output leaves; split BF16 /
+FP16 and sub-leaf variants) behind the C ABI of include/spamm.h, plus a
 continuous-batching server for products and squaring chains."""
 from ._binding import (  # noqa: F401
     HEADER, LIB_PATH, PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16, SPAMM_E_BUSY, SPAMM_E_HIP, SPAMM_E_INVAL,
