@@ -319,6 +319,32 @@ def algdecay_sweep(sp, torch, dev, reps):
                            "tasks_low": st["tasks_low"]})
     tree.free()
     t16.free()
+    # epsilon-sparsified trees (leaves below tau / ||A||_F not stored) at each
+    # configured tau: storage and product time against the dense tree, C
+    # bitwise equal
+    sparse = []
+    dense_tree = sp.build_tree(dA, wl.leaf)
+    dense_bytes = dense_tree.storage()["bytes"]
+    C2 = torch.empty_like(C)
+    for t_ in wl.taus:
+        sp.multiply_ex(dense_tree, dense_tree, t_, C)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st_tree = sp.build_tree_sparse(dA, wl.leaf, t_)
+        torch.cuda.synchronize()
+        t_build = (time.perf_counter() - t0) * 1e3
+        (ms, g_ms, _), st = timed_product(sp, st_tree, t_, C2, reps)
+        (ms_d, _, _), _ = timed_product(sp, dense_tree, t_, C, reps)
+        sto = st_tree.storage()
+        sparse.append({"tau": t_, "leaves_stored": sto["stored"], "leaves_total": sto["total"],
+                       "stored_fraction": round(sto["stored"] / sto["total"], 4),
+                       "device_bytes": sto["bytes"], "dense_device_bytes": dense_bytes,
+                       "ms_build_host_timed": round(t_build, 3), "ms_multiply": round(ms, 4),
+                       "ms_multiply_dense_tree": round(ms_d, 4),
+                       "C_bitwise_equal_dense": bool(torch.equal(C, C2))})
+        st_tree.free()
+    dense_tree.free()
+    del C2
     matched = {}
     for target in TARGETS:
         best = {k: fastest_within(points, k, target) for k in ("fp32", "split-bf16", "split-fp16")}
@@ -330,7 +356,7 @@ def algdecay_sweep(sp, torch, dev, reps):
     del dA, C, exact
     torch.cuda.empty_cache()
     return {"workload": wl.name, "n": wl.n, "leaf": wl.leaf, "tau_sweep": sweep,
-            "matched_error": matched,
+            "matched_error": matched, "sparse_tree": sparse,
             "error": "whole matrix, max-norm, against the dense FP64 product"}
 
 
