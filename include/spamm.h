@@ -170,6 +170,32 @@ int spamm_build_tree_ex(const float *A, int64_t n, int32_t leaf, uint32_t flags,
 int spamm_build_tree_sparse(const float *A, int64_t n, int32_t leaf, uint32_t flags, double tau,
                             double norm2_other, void *stream, spamm_tree **out);
 
+/*
+ * Build the quadtree of the product C = A B that `plan` computed, from C and
+ * the plan's schedule (Sec. II.C: truncating the product space truncates
+ * the result).  A leaf of C that no kept leaf product reaches is zero by
+ * construction: it is not read, its norm is +0 and it is not stored.  The
+ * reached leaves are read from C and packed as in spamm_build_tree_ex
+ * (addressed through a per-leaf slot map, like a sparsified tree), so the
+ * norms equal those of spamm_build_tree_ex on C bit for bit, and a product
+ * taking this tree gives the same C as one taking the dense tree.  This is
+ * the next operand of a squaring chain (X_{s+1} = X_s X_s) without a dense
+ * rebuild.
+ *   C      device pointer, n x n FP32 row-major, holding the plan's product
+ *          on every reached leaf (spamm_numeric of this plan, ordered before
+ *          on `stream`); its other leaves are never read.
+ *   plan   the plan of the product; it and C stay alive until this returns.
+ *   flags  0, SPAMM_TREE_BF16 or SPAMM_TREE_FP16 (16-bit copies for a split
+ *          product taking the tree; leaf 32 or 64).
+ * Synchronizes `stream` twice (reached-leaf count, then the root).
+ * spamm_tree_storage reports the reached leaves as stored.
+ * Errors: SPAMM_E_INVAL (NULL C/plan/out, bad flags, plan on another device),
+ *         SPAMM_E_NONFINITE (NaN/Inf on a reached leaf), SPAMM_E_NOMEM,
+ *         SPAMM_E_HIP.
+ */
+int spamm_build_tree_output(const float *C, const spamm_plan *plan, uint32_t flags,
+                            void *stream, spamm_tree **out);
+
 /* Storage of a tree: leaves stored (N^2 for a dense tree), N^2, and the device
  * bytes it holds (leaf copies, norm pyramid, slot map, FP16 scale exponents).
  * Outputs may be NULL. */
@@ -334,7 +360,11 @@ int spamm_multiply_noalloc(const spamm_tree *A, const spamm_tree *B, const spamm
  * GEMM stream, so small products share the chip.  A squaring chain (the
  * matrix square is the central step of density-matrix purification,
  * Sec. IV.B) stays on the device: each step's product is rebuilt into a tree
- * and squared again without a host round trip.
+ * and squared again without a host round trip.  The rebuild reads only the
+ * leaves that the step's kept products reach (the others are zero, as in
+ * spamm_build_tree_output), and the leaf GEMM of every step before the last
+ * writes only the blocks of C that have products; the last step writes all
+ * of C.
  *
  * Determinism: every output leaf is computed by one workgroup with a fixed k
  * order, so a request's C is bit-identical whether it runs alone or in a mix.
@@ -393,7 +423,8 @@ typedef struct spamm_server_stats {
 int spamm_server_create(size_t hbm_budget, int32_t max_slots, spamm_server **out);
 
 /*
- * Device bytes of a request's slot arena (its trees and task arena, buffers
+ * Device bytes of a request's slot arena (its trees and task arena, and for
+ * a chain the keep flags, slots and scan partials of its step trees; buffers
  * at 256-byte aligned offsets); also validates the request (host only, no device call).  Errors: SPAMM_E_INVAL (null
  * pointers, n < 1, bad leaf, precision, tau, low_tol, low_rel (as
  * spamm_symbolic_ex), chain_len outside 0..64,

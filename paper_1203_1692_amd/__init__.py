@@ -5,7 +5,7 @@ continuous-batching server for products and squaring chains."""
 from ._binding import (  # noqa: F401
     HEADER, LIB_PATH, PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16, SPAMM_E_BUSY, SPAMM_E_HIP, SPAMM_E_INVAL,
     SPAMM_E_MISMATCH, SPAMM_E_NOMEM, SPAMM_E_NONFINITE, SPAMM_E_RANGE, SPAMM_OK, SPAMM_PENDING,
-    Opts, Plan, Request, TREE_BF16, TREE_FP16, TREE_SUBNORMS, Result, Server, ServerStats, SpammError, Stats, Tree, build_tree, build_tree_sparse,
+    Opts, Plan, Request, TREE_BF16, TREE_FP16, TREE_SUBNORMS, Result, Server, ServerStats, SpammError, Stats, Tree, build_tree, build_tree_output, build_tree_sparse,
     header_functions, load, multiply, multiply_ex, multiply_noalloc, request_footprint, strerror,
     symbolic,
 )

@@ -133,6 +133,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "spamm_multiply_opts": [vp, vp, ctypes.POINTER(Opts), vp, vp, ctypes.POINTER(Stats)],
         "spamm_tree_free": [vp],
         "spamm_build_tree_sparse": [vp, i64, i32, ctypes.c_uint32, dbl, dbl, vp, pp],
+        "spamm_build_tree_output": [vp, vp, ctypes.c_uint32, vp, pp],
         "spamm_tree_storage": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(sz)],
         "spamm_tree_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
                             ctypes.POINTER(dbl)],
@@ -357,6 +358,23 @@ def build_tree_sparse(A, leaf: int, tau: float, norm2_other: float = 0.0, stream
            "spamm_build_tree_sparse")
     t = Tree(h)
     t.bf16 = bool(bf16)
+    t.subnorms = False
+    return t
+
+
+def build_tree_output(C, plan: "Plan", stream=None, bf16: bool = False,
+                      fp16: bool = False) -> Tree:
+    """Quadtree of the product C that `plan` computed: only the leaves of C a
+    kept product reaches are read and stored (the others are zero)."""
+    C = _device_matrix(C, "C")
+    h = ctypes.c_void_p()
+    flags = (TREE_BF16 if bf16 else 0) | (TREE_FP16 if fp16 else 0)
+    _check(load().spamm_build_tree_output(ctypes.c_void_p(C.data_ptr()), plan.handle, flags,
+                                          _stream(stream), ctypes.byref(h)),
+           "spamm_build_tree_output")
+    t = Tree(h)
+    t.bf16 = bool(bf16)
+    t.fp16 = bool(fp16)
     t.subnorms = False
     return t
 

@@ -21,6 +21,14 @@ hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *t
                         double *norms, bool sub, hipStream_t s);
 hipError_t launch_cull(spamm_plan *p, hipStream_t s);
 hipError_t launch_gemm(const spamm_plan *p, float *C, hipStream_t s);
+hipError_t launch_output_map(const uint32_t *browptr, const uint32_t *bent,
+                             const uint32_t *browptr_lo, const uint32_t *bent_lo,
+                             uint32_t nblocks, int depth, uint32_t *keep, uint32_t *slot,
+                             uint32_t *partials, hipStream_t s);
+hipError_t launch_output_pack(const float *C, int64_t n, int leaf, int depth, float *tiles,
+                              float *tilesT, uint16_t *t16, uint16_t *tT16, int32_t *scale16,
+                              double *norms, const uint32_t *keep, const uint32_t *slot,
+                              hipStream_t s);
 }  // namespace spamm
 
 using namespace spamm;
@@ -315,6 +323,121 @@ int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hi
     return SPAMM_OK;
 }
 
+// keep flags, slots and scan partials of an output tree of depth d
+struct OutputMap {
+    size_t keep, slot, partials, total;
+};
+
+static OutputMap output_map(int32_t d)
+{
+    const uint32_t N2 = 1u << (2 * d);
+    OutputMap M{};
+    M.keep = 0;
+    M.slot = align256(sizeof(uint32_t) * N2);
+    M.partials = M.slot + align256(sizeof(uint32_t) * ((size_t)N2 + 1));
+    M.total = M.partials + align256(sizeof(uint32_t) * scan_partials_len(N2));
+    return M;
+}
+
+size_t output_map_bytes(int32_t depth) { return output_map(depth).total; }
+
+static int check_output_args(const float *C, const spamm_plan *p, uint32_t flags, int *dev)
+{
+    if (C == nullptr || p == nullptr)
+        return fail(SPAMM_E_INVAL, "C or plan is NULL");
+    if ((flags & ~(SPAMM_TREE_BF16 | SPAMM_TREE_FP16)) != 0)
+        return fail(SPAMM_E_INVAL, "flags 0x%x: an output tree takes SPAMM_TREE_BF16 or "
+                    "SPAMM_TREE_FP16 only", flags);
+    if ((flags & SPAMM_TREE_BF16) && (flags & SPAMM_TREE_FP16))
+        return fail(SPAMM_E_INVAL, "a tree keeps BF16 or FP16 leaf copies, not both");
+    if (flags != 0 && p->leaf == 16)
+        return fail(SPAMM_E_INVAL, "16-bit leaf copies need leaf 32 or 64");
+    int rc = prepare_device(dev);
+    if (rc)
+        return rc;
+    if (*dev != p->device)
+        return fail(SPAMM_E_INVAL, "the plan lives on device %d, current device is %d",
+                    p->device, *dev);
+    return SPAMM_OK;
+}
+
+static spamm_tree *output_tree_shell(const spamm_plan *p, int dev, hipStream_t s)
+{
+    spamm_tree *t = new (std::nothrow) spamm_tree();
+    if (!t)
+        return nullptr;
+    t->device = dev;
+    t->stream = s;
+    t->n = p->n;
+    t->np = p->A->np;
+    t->leaf = p->leaf;
+    t->depth = p->depth;
+    return t;
+}
+
+static void output_tree_carve(spamm_tree *t, char *base, const TreeLayout &L, uint32_t flags)
+{
+    const bool fp16 = (flags & SPAMM_TREE_FP16) != 0, c16 = flags != 0;
+    t->tiles = (float *)(base + L.tiles);
+    t->tilesT = (float *)(base + L.tilesT);
+    t->tiles16 = c16 ? (uint16_t *)(base + L.t16) : nullptr;
+    t->tilesT16 = c16 ? (uint16_t *)(base + L.tT16) : nullptr;
+    t->fp16 = fp16;
+    t->scale16 = fp16 ? (int32_t *)(base + L.scale16) : nullptr;
+    t->norms = (double *)(base + L.norms);
+}
+
+int tree_build_output_async(const float *C, const spamm_plan *p, uint32_t flags, hipStream_t s,
+                            spamm_tree **out, void *arena, void *map)
+{
+    if (out == nullptr)
+        return fail(SPAMM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int dev;
+    int rc = check_output_args(C, p, flags, &dev);
+    if (rc)
+        return rc;
+    if ((arena == nullptr) != (map == nullptr))
+        return fail(SPAMM_E_INVAL, "give both the tree arena and the output map, or neither");
+    const int32_t d = p->depth;
+    const TreeLayout L = tree_layout(p->A->np, d, flags);
+    const OutputMap M = output_map(d);
+    spamm_tree *t = output_tree_shell(p, dev, s);
+    if (!t)
+        return fail(SPAMM_E_NOMEM, "host allocation failed");
+    t->stored = int64_t(1) << (2 * d);      // capacity: the reached leaves fill a prefix
+    hipError_t e = hipSuccess;
+    char *base = (char *)arena, *mbase = (char *)map;
+    if (arena != nullptr) {
+        t->borrowed = true;
+    } else {
+        e = dev_alloc_async(dev, &t->block, L.total + M.total, s);
+        if (e != hipSuccess)
+            t->block = nullptr;
+        base = (char *)t->block;
+        mbase = base + L.total;
+    }
+    if (e == hipSuccess) {
+        output_tree_carve(t, base, L, flags);
+        t->keep = (uint32_t *)(mbase + M.keep);
+        t->slot = (uint32_t *)(mbase + M.slot);
+        const bool split = p->precision != SPAMM_PREC_FP32;
+        e = launch_output_map(p->browptr, p->bent, split ? p->browptr_lo : nullptr,
+                              split ? p->bent_lo : nullptr, (uint32_t)p->nblocks, d, t->keep,
+                              t->slot, (uint32_t *)(mbase + M.partials), s);
+        if (e == hipSuccess)
+            e = launch_output_pack(C, p->n, p->leaf, d, t->tiles, t->tilesT, t->tiles16,
+                                   t->tilesT16, t->scale16, t->norms, t->keep, t->slot, s);
+    }
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "output tree build");
+        spamm_tree_free(t);
+        return rc;
+    }
+    *out = t;
+    return SPAMM_OK;
+}
+
 static int check_tol(double v, const char *name)
 {
     if (!(v >= 0.0) || isinf(v))
@@ -534,6 +657,87 @@ int spamm_build_tree_ex(const float *A, int64_t n, int32_t leaf, uint32_t flags,
     return SPAMM_OK;
 }
 
+int spamm_build_tree_output(const float *C, const spamm_plan *plan, uint32_t flags,
+                            void *stream, spamm_tree **out)
+{
+    if (out == nullptr)
+        return fail(SPAMM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int dev;
+    int rc = check_output_args(C, plan, flags, &dev);
+    if (rc)
+        return rc;
+    const spamm_plan *p = plan;
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t d = p->depth;
+    const uint32_t N2 = 1u << (2 * d);
+    spamm_tree *t = output_tree_shell(p, dev, s);
+    if (!t)
+        return fail(SPAMM_E_NOMEM, "host allocation failed");
+    // pass 1: keep flags and slots (storage then follows the reached leaves)
+    const size_t np_bytes = align256(sizeof(uint32_t) * scan_partials_len(N2));
+    void *scratch = nullptr;
+    uint32_t reached = 0;
+    hipError_t e = dev_alloc_async(dev, (void **)&t->keep, sizeof(uint32_t) * N2, s);
+    if (e == hipSuccess)
+        e = dev_alloc_async(dev, (void **)&t->slot, sizeof(uint32_t) * ((size_t)N2 + 1), s);
+    if (e == hipSuccess)
+        e = dev_alloc_async(dev, &scratch, np_bytes, s);
+    if (e == hipSuccess) {
+        const bool split = p->precision != SPAMM_PREC_FP32;
+        e = launch_output_map(p->browptr, p->bent, split ? p->browptr_lo : nullptr,
+                              split ? p->bent_lo : nullptr, (uint32_t)p->nblocks, d, t->keep,
+                              t->slot, (uint32_t *)scratch, s);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&reached, t->slot + N2, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (scratch != nullptr)
+        hipFreeAsync(scratch, s);
+    // pass 2: the reached leaves (one buffer each, as a sparsified tree)
+    const bool c16 = flags != 0, fp16 = (flags & SPAMM_TREE_FP16) != 0;
+    const size_t leaf_bytes = sizeof(float) * (size_t)p->leaf * (size_t)p->leaf;
+    const size_t cnt = std::max<size_t>(reached, 1);   // keep the pointers valid when empty
+    t->stored = reached;
+    t->fp16 = fp16;
+    if (e == hipSuccess)
+        e = dev_alloc_async(dev, (void **)&t->tiles, leaf_bytes * cnt, s);
+    if (e == hipSuccess)
+        e = dev_alloc_async(dev, (void **)&t->tilesT, leaf_bytes * cnt, s);
+    if (e == hipSuccess && c16)
+        e = dev_alloc_async(dev, (void **)&t->tiles16, leaf_bytes / 2 * cnt, s);
+    if (e == hipSuccess && c16)
+        e = dev_alloc_async(dev, (void **)&t->tilesT16, leaf_bytes / 2 * cnt, s);
+    if (e == hipSuccess && fp16)
+        e = dev_alloc_async(dev, (void **)&t->scale16, sizeof(int32_t) * N2, s);
+    if (e == hipSuccess)
+        e = dev_alloc_async(dev, (void **)&t->norms,
+                            sizeof(double) * (size_t)tier_offset(d + 1), s);
+    if (e == hipSuccess)
+        e = launch_output_pack(C, p->n, p->leaf, d, t->tiles, t->tilesT, t->tiles16, t->tilesT16,
+                               t->scale16, t->norms, t->keep, t->slot, s);
+    double root = 0.0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&root, t->norms, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "spamm_build_tree_output");
+        spamm_tree_free(t);
+        return rc;
+    }
+    if (!isfinite(root)) {
+        spamm_tree_free(t);
+        return fail(SPAMM_E_NONFINITE, "C holds NaN or Inf on a reached leaf (||C||_F^2 = %g)",
+                    root);
+    }
+    t->root = root;
+    t->root_dense = root;
+    *out = t;
+    return SPAMM_OK;
+}
+
 int spamm_build_tree_sparse(const float *A, int64_t n, int32_t leaf, uint32_t flags, double tau,
                             double norm2_other, void *stream, spamm_tree **out)
 {
@@ -665,9 +869,10 @@ int spamm_tree_free(spamm_tree *t)
     if (t->block != nullptr) {
         e = hipFreeAsync(t->block, t->stream);
     } else if (!t->borrowed) {
-        // sparsified trees: one allocation per buffer
+        // sparsified and output trees: one allocation per buffer
         for (void *ptr : {(void *)t->tiles, (void *)t->tilesT, (void *)t->tiles16,
-                          (void *)t->tilesT16, (void *)t->norms, (void *)t->slot, (void *)t->keep}) {
+                          (void *)t->tilesT16, (void *)t->norms, (void *)t->slot, (void *)t->keep,
+                          (void *)t->scale16}) {
             if (ptr == nullptr)
                 continue;
             hipError_t f = hipFreeAsync(ptr, t->stream);

@@ -147,6 +147,8 @@ struct GemmJob {
     uint32_t nblocks, block0;
     uint32_t nleaf;        // leaves per dimension, N = 2^d
     int32_t single;        // depth 0: one leaf
+    int32_t skip_empty;    // blocks without products write nothing (their C
+                           // leaves keep what they held), else they write zeros
     // split precision: BF16 leaf copies and the LOW schedule (tA/tBT,
     // browptr/bent then hold the FP32 copies and the HIGH schedule), else null
     const void *tA16;

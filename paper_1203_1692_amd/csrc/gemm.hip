@@ -316,6 +316,8 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
     }
 
     const uint32_t e0 = browptr[blk], e1 = browptr[blk + 1];
+    if (job.skip_empty && e0 == e1)
+        return;                                          // the same for every wave
     if constexpr (B >= 32) {
         fp32_products<B>(tA, tBT, job.slotA, job.slotB, bent, e0, e1, I0, J0, smem,
                          (uint32_t *)(smem + 2 * S::kStage), w, lane, acc);
@@ -656,6 +658,9 @@ __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
     using SS = SplitShape<B, F16>;
     uint32_t *ents = (uint32_t *)((char *)smem + SS::kStages);
     int16_t *eexp = (int16_t *)((char *)smem + SS::kStages + SS::kEnts);
+    if (job.skip_empty && job.browptr_lo[blk] == job.browptr_lo[blk + 1] &&
+        job.browptr[blk] == job.browptr[blk + 1])
+        return;                                          // the same for every wave
     floatx16 lo[MB][MB], hi[MB][MB];
 #pragma unroll
     for (int i = 0; i < MB; ++i)
@@ -810,6 +815,9 @@ __global__ __launch_bounds__(1024) void leaf_gemm_split_wide(const GemmJobs jobs
     const int r = w >> 2, c = (r + (w & 3)) & 3;
     const int bit = 4 * r + c;
     const uint32_t NK = job.nleaf;                     // k ranges over [0, N)
+    if (job.skip_empty && job.browptr_lo[4 * P4] == job.browptr_lo[4 * P4 + 4] &&
+        job.browptr[4 * P4] == job.browptr[4 * P4 + 4])
+        return;                                          // none of the 4 children has products
     const uint16_t *__restrict__ tA16 = (const uint16_t *)job.tA16;
     const uint16_t *__restrict__ tBT16 = (const uint16_t *)job.tBT16;
 
@@ -830,8 +838,9 @@ __global__ __launch_bounds__(1024) void leaf_gemm_split_wide(const GemmJobs jobs
         const uint32_t need = pan < 4 ? (m >> (4 * pan)) & 0xFu : (m >> (pan - 4)) & 0x1111u;
         if (need == 0u)
             return 0;
-        const uint16_t *leaf = pan < 4 ? tA16 + (int64_t)lin_index(I0 + pan, k) * (B * B)
-                                       : tBT16 + (int64_t)lin_index(k, J0 + (pan - 4)) * (B * B);
+        const uint16_t *leaf =
+            pan < 4 ? tA16 + leaf_slot(job.slotA, lin_index(I0 + pan, k)) * (B * B)
+                    : tBT16 + leaf_slot(job.slotB, lin_index(k, J0 + (pan - 4))) * (B * B);
         const uint16_t *src = leaf + (st & 1u) * P16 + part * (P16 / 2) + 8 * lane;
         uint16_t *dst = ring16 + (st % kWideRing) * kWideStage16 + pan * P16 + part * (P16 / 2);
 #pragma unroll
@@ -906,8 +915,9 @@ __global__ __launch_bounds__(1024) void leaf_gemm_split_wide(const GemmJobs jobs
         const uint32_t need = pan < 4 ? (m >> (4 * pan)) & 0xFu : (m >> (pan - 4)) & 0x1111u;
         if (need == 0u)
             return;
-        const float *leaf = pan < 4 ? tA + (int64_t)lin_index(I0 + pan, k) * (B * B)
-                                    : tBT + (int64_t)lin_index(k, J0 + (pan - 4)) * (B * B);
+        const float *leaf = pan < 4
+                                ? tA + leaf_slot(job.slotA, lin_index(I0 + pan, k)) * (B * B)
+                                : tBT + leaf_slot(job.slotB, lin_index(k, J0 + (pan - 4))) * (B * B);
         const float *src = leaf + (st & 1u) * P32 + part * (P32 / 2) + 4 * lane;
         float *dst = ring32 + (st & 1u) * kWideStage32 + pan * P32 + part * (P32 / 2);
 #pragma unroll
@@ -1046,6 +1056,7 @@ void plan_jobs(const spamm_plan *p, float *C, GemmJob &j)
     j.nblocks = (uint32_t)p->nblocks / (plan_kind(p) == GemmKind::SplitWide ? 4u : 1u);
     j.block0 = 0;
     j.single = p->depth == 0 ? 1 : 0;
+    j.skip_empty = 0;
     j.tA16 = split ? (const void *)p->A->tiles16 : nullptr;
     j.tBT16 = split ? (const void *)p->B->tilesT16 : nullptr;
     j.browptr_lo = split ? p->browptr_lo : nullptr;

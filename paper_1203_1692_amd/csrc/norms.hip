@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
                                                       const uint32_t *__restrict__ keep,
                                                       const uint32_t *__restrict__ slot,
                                                       int32_t *__restrict__ scale16,
-                                                      uint32_t ntiles)
+                                                      uint32_t ntiles, int known_zero)
 {
     static_assert(!SUB || B == 64, "sub-block norms are built for 64 x 64 leaves");
     using L = LeafLayout<B>;
@@ -156,11 +156,24 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
     float *tr = tr_smem + w * (RH * P);
     double s = 0.0;
     // pack this leaf?  (tiles null: norms only; keep/slot: a sparsified tree
-    // stores only its kept leaves, leaf l at slot[l])
+    // stores only its kept leaves, leaf l at slot[l].  known_zero: a leaf
+    // that is not kept is known to be all zeros, so it is not read and its
+    // norm is +0, the value the pairwise sum of its squares gives.)
+    const bool zero = valid && known_zero && keep[l] == 0u;
     const bool pack = valid && tiles != nullptr && (keep == nullptr || keep[l] != 0u);
     const int64_t dl = pack && slot != nullptr ? (int64_t)slot[l] : (int64_t)l;
     float4 v[M];
-    if (valid) {
+    if (zero && lane == 0 && scale16 != nullptr)
+        scale16[l] = 0;                   // the exponent of a zero leaf
+    if (zero && lane == 0 && leaf_norm != nullptr) {
+        leaf_norm[l] = 0.0;
+        if constexpr (SUB) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                sub_norm[4 * (int64_t)l + i] = 0.0;
+        }
+    }
+    if (valid && !zero) {
         const int64_t I = lin_row(l), J = lin_col(l);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -222,7 +235,7 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
     // lane of the wave); the as-is copy straight from the loaded values
     const int e16 = pack && scale16 != nullptr ? fp16_scale_exponent(s) : 0;
     if (pack && scale16 != nullptr && lane == 0)
-        scale16[dl] = e16;
+        scale16[l] = e16;                 // by linear index, also in a sparse tree
     if constexpr (B >= 32) {
         if (pack && scale16 != nullptr && tiles16 != nullptr) {
 #pragma unroll
@@ -311,7 +324,7 @@ template <int B, int VEC, bool SUB, bool TWO>
 static hipError_t launch_leaf_t(const float *A, int64_t n, float *tiles, float *tilesT,
                                 uint16_t *t16, uint16_t *tT16, double *leaf, double *parent,
                                 double *sub, const uint32_t *keep, const uint32_t *slot,
-                                int32_t *scale16, uint32_t ntiles, hipStream_t s)
+                                int32_t *scale16, uint32_t ntiles, int known_zero, hipStream_t s)
 {
     constexpr size_t lds = sizeof(float) * 4 * (TWO ? B / 2 : B) * (B + 1);
     // once per process (thread-safe static initialization)
@@ -322,7 +335,7 @@ static hipError_t launch_leaf_t(const float *A, int64_t n, float *tiles, float *
         return attr;
     hipLaunchKernelGGL((leaf_norm_pack<B, VEC, SUB, TWO>), dim3((ntiles + 3) / 4), dim3(256), lds,
                        s, A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep, slot, scale16,
-                       ntiles);
+                       ntiles, known_zero);
     return hipGetLastError();
 }
 
@@ -330,37 +343,37 @@ template <int B, int VEC, bool SUB>
 static hipError_t launch_leaf_v(const float *A, int64_t n, float *tiles, float *tilesT,
                                 uint16_t *t16, uint16_t *tT16, double *leaf, double *parent,
                                 double *sub, const uint32_t *keep, const uint32_t *slot,
-                                int32_t *scale16, uint32_t ntiles, hipStream_t s)
+                                int32_t *scale16, uint32_t ntiles, int known_zero, hipStream_t s)
 {
     if constexpr (B == 64)
         return launch_leaf_t<B, VEC, SUB, true>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub,
-                                                keep, slot, scale16, ntiles, s);
+                                                keep, slot, scale16, ntiles, known_zero, s);
     else
         return launch_leaf_t<B, VEC, SUB, false>(A, n, tiles, tilesT, t16, tT16, leaf, parent,
-                                                 sub, keep, slot, scale16, ntiles, s);
+                                                 sub, keep, slot, scale16, ntiles, known_zero, s);
 }
 
 template <int B, bool SUB>
 static hipError_t launch_leaf(const float *A, int64_t n, int vec, float *tiles, float *tilesT,
                               uint16_t *t16, uint16_t *tT16, double *leaf, double *parent,
                               double *sub, const uint32_t *keep, const uint32_t *slot,
-                              int32_t *scale16, uint32_t ntiles, hipStream_t s)
+                              int32_t *scale16, uint32_t ntiles, int known_zero, hipStream_t s)
 {
     if (vec == 4)
         return launch_leaf_v<B, 4, SUB>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep,
-                                        slot, scale16, ntiles, s);
+                                        slot, scale16, ntiles, known_zero, s);
     if (vec == 2)
         return launch_leaf_v<B, 2, SUB>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep,
-                                        slot, scale16, ntiles, s);
+                                        slot, scale16, ntiles, known_zero, s);
     return launch_leaf_v<B, 1, SUB>(A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep, slot,
-                                    scale16, ntiles, s);
+                                    scale16, ntiles, known_zero, s);
 }
 
 static hipError_t launch_leaf_any(const float *A, int64_t n, int leaf, float *tiles,
                                   float *tilesT, uint16_t *t16, uint16_t *tT16, double *leafn,
                                   double *parent, double *subn, const uint32_t *keep,
                                   const uint32_t *slot, int32_t *scale16, uint32_t ntiles,
-                                  hipStream_t s)
+                                  int known_zero, hipStream_t s)
 {
     const uintptr_t addr = reinterpret_cast<uintptr_t>(A);
     const int vec = (n % 4 == 0 && addr % 16 == 0) ? 4 : (n % 2 == 0 && addr % 8 == 0) ? 2 : 1;
@@ -369,16 +382,16 @@ static hipError_t launch_leaf_any(const float *A, int64_t n, int leaf, float *ti
     switch (leaf) {
     case 16:
         return launch_leaf<16, false>(A, n, vec, tiles, tilesT, nullptr, nullptr, leafn, parent,
-                                      nullptr, keep, slot, nullptr, ntiles, s);
+                                      nullptr, keep, slot, nullptr, ntiles, known_zero, s);
     case 32:
         return launch_leaf<32, false>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent, nullptr,
-                                      keep, slot, scale16, ntiles, s);
+                                      keep, slot, scale16, ntiles, known_zero, s);
     case 64:
         return subn != nullptr
                    ? launch_leaf<64, true>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent,
-                                           subn, keep, slot, scale16, ntiles, s)
+                                           subn, keep, slot, scale16, ntiles, known_zero, s)
                    : launch_leaf<64, false>(A, n, vec, tiles, tilesT, t16, tT16, leafn, parent,
-                                            nullptr, keep, slot, scale16, ntiles, s);
+                                            nullptr, keep, slot, scale16, ntiles, known_zero, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -396,7 +409,7 @@ hipError_t launch_build(const float *A, int64_t n, int leaf, int depth, float *t
     if (sub && leaf != 64)
         return hipErrorInvalidValue;
     hipError_t e = launch_leaf_any(A, n, leaf, tiles, tilesT, t16, tT16, leafn, parent, subn,
-                                   nullptr, nullptr, scale16, ntiles, s);
+                                   nullptr, nullptr, scale16, ntiles, 0, s);
     if (e != hipSuccess || depth < 2)
         return e;
     hipLaunchKernelGGL(norm_pyramid, dim3(1), dim3(1024), 0, s, norms, depth - 1);
@@ -458,7 +471,70 @@ hipError_t launch_sparse_pack(const float *A, int64_t n, int leaf, int depth, fl
                               const uint32_t *slot, hipStream_t s)
 {
     return launch_leaf_any(A, n, leaf, tiles, tilesT, t16, tT16, nullptr, nullptr, nullptr, keep,
-                           slot, nullptr, 1u << (2 * depth), s);
+                           slot, nullptr, 1u << (2 * depth), 0, s);
+}
+
+// ---- the tree of a product's output (Sec. II.C) ------------------------------
+// Truncating the product space leaves every leaf of C = A B that no kept
+// product reaches at zero.  The plan's leaf-tier schedule says which are
+// reached: leaf 4b + q of GEMM block b (the children of a tier-(d-1) node; b
+// = 0, q = 0 for the single leaf at depth 0) iff an entry of the block's
+// HIGH or LOW list has bit q in its quadrant mask.  One thread per block.
+__global__ __launch_bounds__(256) void output_keep(const uint32_t *__restrict__ browptr,
+                                                   const uint32_t *__restrict__ bent,
+                                                   const uint32_t *__restrict__ browptr_lo,
+                                                   const uint32_t *__restrict__ bent_lo,
+                                                   uint32_t nblocks, uint32_t nleaves,
+                                                   uint32_t *__restrict__ keep)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblocks)
+        return;
+    uint32_t m = 0;
+    for (uint32_t e = browptr[b], e1 = browptr[b + 1]; e < e1 && m != 0xFu; ++e)
+        m |= bent[e] >> 16;
+    if (browptr_lo != nullptr)
+        for (uint32_t e = browptr_lo[b], e1 = browptr_lo[b + 1]; e < e1 && m != 0xFu; ++e)
+            m |= bent_lo[e] >> 16;
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q)
+        if (4 * b + q < nleaves)
+            keep[4 * b + q] = (m >> q) & 1u;
+}
+
+// Tree of C from the plan that produced it, in two parts: the keep flags
+// and their exclusive scan into slots (slot[N^2] = leaves stored); then the
+// pack and norms of the reached leaves only (the others are not read: norm
+// +0) and the pyramid.  The norms are those of the dense tree of C bit for
+// bit, as long as C holds the product on every reached leaf.
+hipError_t launch_output_map(const uint32_t *browptr, const uint32_t *bent,
+                             const uint32_t *browptr_lo, const uint32_t *bent_lo,
+                             uint32_t nblocks, int depth, uint32_t *keep, uint32_t *slot,
+                             uint32_t *partials, hipStream_t s)
+{
+    const uint32_t ntiles = 1u << (2 * depth);
+    hipLaunchKernelGGL(output_keep, dim3((nblocks + 255) / 256), dim3(256), 0, s, browptr, bent,
+                       browptr_lo, bent_lo, nblocks, ntiles, keep);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    return launch_scan_u32(keep, ntiles, slot, partials, s);
+}
+
+hipError_t launch_output_pack(const float *C, int64_t n, int leaf, int depth, float *tiles,
+                              float *tilesT, uint16_t *t16, uint16_t *tT16, int32_t *scale16,
+                              double *norms, const uint32_t *keep, const uint32_t *slot,
+                              hipStream_t s)
+{
+    const uint32_t ntiles = 1u << (2 * depth);
+    double *leafn = norms + tier_offset(depth);
+    double *parent = depth >= 1 ? norms + tier_offset(depth - 1) : nullptr;
+    hipError_t e = launch_leaf_any(C, n, leaf, tiles, tilesT, t16, tT16, leafn, parent, nullptr,
+                                   keep, slot, scale16, ntiles, 1, s);
+    if (e != hipSuccess || depth < 2)
+        return e;
+    hipLaunchKernelGGL(norm_pyramid, dim3(1), dim3(1024), 0, s, norms, depth - 1);
+    return hipGetLastError();
 }
 
 }  // namespace spamm

@@ -34,6 +34,16 @@ hipError_t dev_alloc_async(int dev, void **ptr, size_t bytes, hipStream_t s);
 int tree_build_async(const float *A, int64_t n, int32_t leaf, uint32_t flags, hipStream_t s,
                      double *root_dst, spamm_tree **out, void *arena = nullptr);
 
+// Tree of the product C that plan `p` computed (only the leaves a kept
+// product reaches are read and stored, leaf l at slot[l]; the others are
+// zero), enqueued on `s` without synchronizing.  With `arena` (tree_device_bytes
+// bytes) and `map` (output_map_bytes(depth) bytes: keep flags, slots, scan
+// partials) the buffers are carved from them; otherwise one allocation of the
+// tree's own.  The plan's schedule is read by the enqueued work.
+int tree_build_output_async(const float *C, const spamm_plan *p, uint32_t flags, hipStream_t s,
+                            spamm_tree **out, void *arena = nullptr, void *map = nullptr);
+size_t output_map_bytes(int32_t depth);
+
 // spamm_symbolic_ex on stream `s`, optionally with the plan's buffers carved
 // from `arena` (plan_device_bytes bytes, 256-byte aligned).
 int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,

@@ -9,8 +9,11 @@
 //       so a long build or cull never holds up the GEMM stream) -> one launch
 //       per kernel kind -> record ev_done
 //   chain step s -> s+1, enqueued at once after the GEMM:
-//   ss: wait ev_done -> build the tree of X_{s+1} from C over the arena
-//       space of X_s's tree -> cull -> ... (no host round trip)
+//   ss: wait ev_done -> build the tree of X_{s+1} from C and step s's
+//       schedule over the arena space of X_s's tree -> cull -> ... (no host
+//       round trip).  Only the leaves of C that step s's kept products reach
+//       are read (the others are zero), and the GEMM of every step before
+//       the last writes only the blocks that have products.
 // The host only watches ev_done of a request's last product.
 //
 // Memory: each slot owns one device arena (trees + task arena of its current
@@ -115,7 +118,7 @@ int check_request(const spamm_request *r, size_t *bytes)
         return rc;
     const bool distinctB = r->B != nullptr && r->B != r->A;
     *bytes = tree_device_bytes(r->n, r->leaf, tree_flags_for(r->precision)) * (distinctB ? 2 : 1) +
-             plan_device_bytes(d, split);
+             plan_device_bytes(d, split) + (r->chain_len > 0 ? output_map_bytes(d) : 0);
     return SPAMM_OK;
 }
 
@@ -155,18 +158,25 @@ struct spamm_server {
 namespace {
 
 // Enqueue the trees and the cull of the request's current step on its slot
-// stream.  Step 0 reads A (and B); step s > 0 reads X_s from C.
-int start_step(spamm_server *S, Active &a)
+// stream.  Step 0 reads A (and B); step s > 0 builds the tree of X_s from C
+// and the plan `prev` of step s-1 that wrote it: only the leaves that step's
+// kept products reached are read (the others are zero).
+int start_step(spamm_server *S, Active &a, const spamm_plan *prev)
 {
     hipStream_t ss = S->ss[a.slot];
     Pinned &P = S->pin[a.slot];
     const spamm_request &r = a.job.rq;
     const uint32_t flags = tree_flags_for(r.precision);
-    // arena: [tree of A or X_s][tree of B, step 0 only][plan]
+    // arena: [tree of A or X_s][tree of B, step 0 only][plan][output map, chains]
     char *base = (char *)S->arena[a.slot];
     const size_t tb = tree_device_bytes(r.n, r.leaf, flags);
-    int rc = tree_build_async(a.step == 0 ? r.A : r.C, r.n, r.leaf, flags, ss, nullptr, &a.tA,
-                              base);
+    int rc;
+    if (a.step == 0) {
+        rc = tree_build_async(r.A, r.n, r.leaf, flags, ss, nullptr, &a.tA, base);
+    } else {
+        char *map = base + tb + plan_device_bytes(prev->depth, a.split);
+        rc = tree_build_output_async(r.C, prev, flags, ss, &a.tA, base, map);
+    }
     if (rc)
         return rc;
     if (a.step == 0 && a.distinctB) {
@@ -217,9 +227,20 @@ void advance(spamm_server *S, Active &a)
         a.final = true;
         return;
     }
-    release_step(S, a);
+    // step s+1 reads C and step s's schedule, and overwrites step s's trees:
+    // the slot stream waits for the GEMM; the handles of step s go once step
+    // s+1 is enqueued (their buffers live in the slot arena)
+    hipStreamWaitEvent(S->ss[a.slot], S->ev_done[a.slot], 0);
+    spamm_plan *prev = a.plan;
+    spamm_tree *pA = a.tA, *pB = a.tB;
+    a.plan = nullptr;
+    a.tA = a.tB = nullptr;
     a.step += 1;
-    int rc = start_step(S, a);
+    int rc = start_step(S, a, prev);
+    spamm_plan_free(prev);
+    if (pB != nullptr && pB != pA)
+        spamm_tree_free(pB);
+    spamm_tree_free(pA);
     if (rc) {
         a.status = rc;
         a.final = true;
@@ -278,6 +299,10 @@ bool launch_batches(spamm_server *S)
             GemmJobs &tab = tabs[slot];
             GemmJob &j = tab.job[tab.njobs++];
             plan_jobs(a.plan, a.job.rq.C, j);
+            // a chain step before the last: the next tree reads only the
+            // leaves this product reaches, so blocks without products need
+            // not write their zeros
+            j.skip_empty = a.step + 1 < a.steps ? 1 : 0;
             j.block0 = tab.nblocks;
             tab.nblocks += j.nblocks;
         }
@@ -448,7 +473,7 @@ void scheduler(spamm_server *S)
             a.split = a.job.rq.precision != SPAMM_PREC_FP32;
             a.distinctB = a.job.rq.B != nullptr && a.job.rq.B != a.job.rq.A;
             a.t_admit = now_us();
-            int rc = start_step(S, a);
+            int rc = start_step(S, a, nullptr);
             if (rc) {
                 a.status = rc;
                 a.culled = false;

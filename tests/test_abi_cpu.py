@@ -100,6 +100,10 @@ def test_newer_entry_points_check_arguments_on_the_host():
                                    ctypes.byref(h)) == sp.SPAMM_E_INVAL
     assert lib.spamm_build_tree_sparse(fake, 64, 32, sp.TREE_FP16, dbl(1e-6), dbl(0.0), None,
                                        ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    # tree of a product's output: NULL C, plan or out
+    assert lib.spamm_build_tree_output(None, fake, 0, None, ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_build_tree_output(fake, None, 0, None, ctypes.byref(h)) == sp.SPAMM_E_INVAL
+    assert lib.spamm_build_tree_output(fake, fake, 0, None, None) == sp.SPAMM_E_INVAL
     # NULL handles
     assert lib.spamm_tree_storage(None, None, None, None) == sp.SPAMM_E_INVAL
     assert lib.spamm_tree_matrix16(None, 0, None, 0, None, 0) == sp.SPAMM_E_INVAL

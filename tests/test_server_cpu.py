@@ -42,11 +42,26 @@ def test_footprint_tree_part(n, leaf, prec):
     assert 0 < one - tree_bytes(n, leaf, prec) <= tree_bytes(n, leaf, sp.PREC_FP32)
 
 
-def test_footprint_grows_with_n_and_chain_does_not_change_it():
+def align256(b):
+    return (b + 255) // 256 * 256
+
+
+def test_footprint_grows_with_n_and_chain_adds_its_output_map():
     sizes = [fp(n=n) for n in (512, 1024, 2048, 4096, 8192)]
     assert sizes == sorted(sizes) and len(set(sizes)) == 5
-    assert fp(n=2048, chain_len=10) == fp(n=2048)
     assert all(s % 256 == 0 for s in sizes)
+    # a chain step's tree is built from the previous product's schedule:
+    # keep flags (N^2 words), slots (N^2 + 1) and the scan's chunk sums
+    # (ceil(N^2 / 4096) + 1), whatever the chain's length
+    for n, leaf in ((2048, 32), (8192, 32), (1000, 64), (20, 16)):
+        d = 0
+        while leaf << d < n:
+            d += 1
+        N2 = 4 ** d
+        extra = (align256(4 * N2) + align256(4 * (N2 + 1)) +
+                 align256(4 * ((N2 + 4095) // 4096 + 1)))
+        assert fp(n=n, leaf=leaf, chain_len=10) == fp(n=n, leaf=leaf) + extra
+        assert fp(n=n, leaf=leaf, chain_len=2) == fp(n=n, leaf=leaf, chain_len=64)
 
 
 @pytest.mark.parametrize("kw,code", [
