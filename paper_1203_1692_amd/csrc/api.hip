@@ -387,6 +387,40 @@ static void output_tree_carve(spamm_tree *t, char *base, const TreeLayout &L, ui
     t->norms = (double *)(base + L.norms);
 }
 
+int tree_prepare(int64_t n, int32_t leaf, uint32_t flags, void *arena, uint32_t *keep,
+                 hipStream_t s, spamm_tree **out)
+{
+    if (out == nullptr || arena == nullptr)
+        return fail(SPAMM_E_INVAL, "out or arena is NULL");
+    *out = nullptr;
+    if ((flags & ~(SPAMM_TREE_BF16 | SPAMM_TREE_FP16)) != 0 ||
+        ((flags & SPAMM_TREE_BF16) && (flags & SPAMM_TREE_FP16)) || (flags != 0 && leaf == 16))
+        return fail(SPAMM_E_INVAL, "tree flags 0x%x at leaf %d", flags, leaf);
+    int32_t d;
+    int64_t np;
+    int rc = tree_depth(n, leaf, &d, &np);
+    if (rc)
+        return rc;
+    int dev;
+    if ((rc = prepare_device(&dev)))
+        return rc;
+    spamm_tree *t = new (std::nothrow) spamm_tree();
+    if (!t)
+        return fail(SPAMM_E_NOMEM, "host allocation failed");
+    t->device = dev;
+    t->stream = s;
+    t->n = n;
+    t->np = np;
+    t->leaf = leaf;
+    t->depth = d;
+    t->stored = int64_t(1) << (2 * d);
+    t->borrowed = true;
+    output_tree_carve(t, (char *)arena, tree_layout(np, d, flags), flags);
+    t->keep = keep;
+    *out = t;
+    return SPAMM_OK;
+}
+
 int tree_build_output_async(const float *C, const spamm_plan *p, uint32_t flags, hipStream_t s,
                             spamm_tree **out, void *arena, void *map)
 {
@@ -518,9 +552,8 @@ static int plan_setup(spamm_plan *p, const spamm_tree *A, const spamm_tree *B,
     return SPAMM_OK;
 }
 
-// Points the buffers of a set-up plan into `base` (its block) and enqueues
-// the cull on the plan's stream.
-static hipError_t plan_carve_and_cull(spamm_plan *p, char *base)
+// Points the buffers of a set-up plan into `base` (its block).
+static void plan_carve(spamm_plan *p, char *base)
 {
     PlanBuf bufs[12];
     const int nb = plan_bufs(p, plan_sizes(p->depth), p->precision != SPAMM_PREC_FP32,
@@ -530,7 +563,35 @@ static hipError_t plan_carve_and_cull(spamm_plan *p, char *base)
         *bufs[i].dst = base + off;
         off += align256(bufs[i].bytes);
     }
+}
+
+// ... and enqueues the cull on the plan's stream.
+static hipError_t plan_carve_and_cull(spamm_plan *p, char *base)
+{
+    plan_carve(p, base);
     return launch_cull(p, p->stream);
+}
+
+int plan_prepare(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
+                 hipStream_t s, void *arena, spamm_plan **out)
+{
+    if (out == nullptr || arena == nullptr)
+        return fail(SPAMM_E_INVAL, "out or arena is NULL");
+    *out = nullptr;
+    int dev, rc;
+    if ((rc = prepare_device(&dev)))
+        return rc;
+    spamm_plan *p = new (std::nothrow) spamm_plan();
+    if (!p)
+        return fail(SPAMM_E_NOMEM, "host allocation failed");
+    size_t total = 0;
+    if ((rc = plan_setup(p, A, B, opts, dev, s, &total))) {
+        delete p;
+        return rc;
+    }
+    plan_carve(p, (char *)arena);
+    *out = p;
+    return SPAMM_OK;
 }
 
 int symbolic_async(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,

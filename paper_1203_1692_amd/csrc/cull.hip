@@ -23,7 +23,10 @@
 // precision each kept leaf product is also classed LOW (s_A s_B < low_tol^2,
 // or < (theta^2 s_A0) s_B0 for a relative threshold; 16-bit operands) or
 // HIGH (FP32), and the two classes get separate lists.
-#include "common.hpp"
+#include <algorithm>
+#include <vector>
+
+#include "runtime.hpp"
 
 namespace spamm {
 
@@ -160,21 +163,12 @@ __global__ __launch_bounds__(256) void cull_count(const double *__restrict__ nA,
 // [0,np) HIGH entries, [np,2np) HIGH products, [2np,3np) LOW entries,
 // [3np,4np) LOW products.
 template <bool SPLIT>
-__global__ __launch_bounds__(256) void cull_count_leaf(const double *__restrict__ nA,
-                                                       const double *__restrict__ nB, double T2,
-                                                       double L2a, double theta2,
-                                                       const double *__restrict__ rootA,
-                                                       const double *__restrict__ rootB,
-                                                       const uint32_t *__restrict__ prow,
-                                                       const uint32_t *__restrict__ plist,
-                                                       uint32_t nparents,
-                                                       uint32_t *__restrict__ counts)
+__device__ inline void count_leaf_tile(const double *__restrict__ nA,
+                                       const double *__restrict__ nB, double T2, double L2,
+                                       const uint32_t *__restrict__ prow,
+                                       const uint32_t *__restrict__ plist, uint32_t nparents,
+                                       uint32_t *__restrict__ counts, uint32_t P, int lane)
 {
-    const uint32_t P = blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (P >= nparents)
-        return;
-    const double L2 = SPLIT ? low_bound(L2a, theta2, rootA, rootB) : 0.0;
-    const int lane = threadIdx.x & 63;
     const uint32_t I = lin_row(P), J = lin_col(P);
     const uint32_t beg = prow[P], end = prow[P + 1];
     uint32_t ent_hi = 0, ent_lo = 0, tasks_hi = 0, tasks_lo = 0;
@@ -208,6 +202,24 @@ __global__ __launch_bounds__(256) void cull_count_leaf(const double *__restrict_
             counts[3 * nparents + P] = tasks_lo;
         }
     }
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void cull_count_leaf(const double *__restrict__ nA,
+                                                       const double *__restrict__ nB, double T2,
+                                                       double L2a, double theta2,
+                                                       const double *__restrict__ rootA,
+                                                       const double *__restrict__ rootB,
+                                                       const uint32_t *__restrict__ prow,
+                                                       const uint32_t *__restrict__ plist,
+                                                       uint32_t nparents,
+                                                       uint32_t *__restrict__ counts)
+{
+    const uint32_t P = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (P >= nparents)
+        return;
+    const double L2 = SPLIT ? low_bound(L2a, theta2, rootA, rootB) : 0.0;
+    count_leaf_tile<SPLIT>(nA, nB, T2, L2, prow, plist, nparents, counts, P, threadIdx.x & 63);
 }
 
 // Writes the kept children of parent output tile P (one wave) into the
@@ -274,24 +286,15 @@ __device__ inline void emit_entries(uint32_t fl, uint32_t kp, uint64_t below, ui
 }
 
 template <bool SPLIT>
-__global__ __launch_bounds__(256) void cull_emit_leaf(const double *__restrict__ nA,
-                                                      const double *__restrict__ nB, double T2,
-                                                      double L2a, double theta2,
-                                                      const double *__restrict__ rootA,
-                                                      const double *__restrict__ rootB,
-                                                      const uint32_t *__restrict__ prow,
-                                                      const uint32_t *__restrict__ plist,
-                                                      uint32_t nparents,
-                                                      const uint32_t *__restrict__ rp_hi,
-                                                      uint32_t *__restrict__ ent_hi,
-                                                      const uint32_t *__restrict__ rp_lo,
-                                                      uint32_t *__restrict__ ent_lo)
+__device__ inline void emit_leaf_tile(const double *__restrict__ nA,
+                                      const double *__restrict__ nB, double T2, double L2,
+                                      const uint32_t *__restrict__ prow,
+                                      const uint32_t *__restrict__ plist,
+                                      const uint32_t *__restrict__ rp_hi,
+                                      uint32_t *__restrict__ ent_hi,
+                                      const uint32_t *__restrict__ rp_lo,
+                                      uint32_t *__restrict__ ent_lo, uint32_t P, int lane)
 {
-    const uint32_t P = blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (P >= nparents)
-        return;
-    const double L2 = SPLIT ? low_bound(L2a, theta2, rootA, rootB) : 0.0;
-    const int lane = threadIdx.x & 63;
     const uint64_t below = lanes_below();
     const uint32_t I = lin_row(P), J = lin_col(P);
     const uint32_t beg = prow[P], end = prow[P + 1];
@@ -311,6 +314,28 @@ __global__ __launch_bounds__(256) void cull_emit_leaf(const double *__restrict__
         if constexpr (SPLIT)
             emit_entries(lo, kp, below, run_lo, ent_lo);
     }
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void cull_emit_leaf(const double *__restrict__ nA,
+                                                      const double *__restrict__ nB, double T2,
+                                                      double L2a, double theta2,
+                                                      const double *__restrict__ rootA,
+                                                      const double *__restrict__ rootB,
+                                                      const uint32_t *__restrict__ prow,
+                                                      const uint32_t *__restrict__ plist,
+                                                      uint32_t nparents,
+                                                      const uint32_t *__restrict__ rp_hi,
+                                                      uint32_t *__restrict__ ent_hi,
+                                                      const uint32_t *__restrict__ rp_lo,
+                                                      uint32_t *__restrict__ ent_lo)
+{
+    const uint32_t P = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (P >= nparents)
+        return;
+    const double L2 = SPLIT ? low_bound(L2a, theta2, rootA, rootB) : 0.0;
+    emit_leaf_tile<SPLIT>(nA, nB, T2, L2, prow, plist, rp_hi, ent_hi, rp_lo, ent_lo, P,
+                          threadIdx.x & 63);
 }
 
 // ---- exclusive scan of uint32 counts: out[0..m) prefix, out[m] = total -------
@@ -463,27 +488,40 @@ __device__ inline int64_t rowptr_offset(int t) { return tier_offset(t) + t; }
 // The root and tiers 1..top in one workgroup (top <= kTopTiers): the small
 // upper tiers cost one launch instead of three each.  Same count -> scan ->
 // emit per tier as the per-tier kernels (same per-wave code), so the lists
-// are identical; barriers separate the phases.
+// are identical; barriers separate the phases.  Everything the tiers read
+// stays in LDS: both pyramids' tiers 1..top, the row pointers, the lists of
+// tiers below `top` and the counts, so a tier costs LDS round trips rather
+// than dependent global loads.  The row pointers of every tier (the plan's
+// kept counts) and the list of tier `top` (read by the next tier's kernels)
+// are also written to global memory.
 constexpr int kTopTiers = 5;
 // offset of tier t (1 <= t <= kTopTiers) in cull_top's LDS copy: tiers 1..t-1
 // back to back (4^u values each, a multiple of 4, so every tier starts 32-byte
 // aligned)
 __host__ __device__ constexpr int top_offset(int t) { return int(((int64_t(1) << (2 * t)) - 4) / 3); }
 constexpr int kTopNorms = top_offset(kTopTiers + 1);
+// row pointers of tiers 0..kTopTiers back to back (4^t + 1 each)
+__host__ __device__ constexpr int top_row_offset(int t) { return int(((int64_t(1) << (2 * t)) - 1) / 3) + t; }
+constexpr int kTopRows = top_row_offset(kTopTiers + 1);
+// lists of the tiers below the top one: even tiers <= 8^(kTopTiers - 1)
+// entries, odd tiers <= 8^(kTopTiers - 2)
+constexpr int kTopListEven = 1 << (3 * (kTopTiers - 1));
+constexpr int kTopListOdd = 1 << (3 * (kTopTiers - 2));
+static_assert(kTopTiers % 2 == 1, "tier kTopTiers - 1 is even");
 
-__global__ __launch_bounds__(kScanThreads) void cull_top(const double *__restrict__ nA,
-                                                         const double *__restrict__ nB, double T2,
-                                                         uint32_t *__restrict__ rowptr,
-                                                         uint32_t *__restrict__ list0,
-                                                         uint32_t *__restrict__ list1,
-                                                         uint32_t *__restrict__ counts,
-                                                         uint64_t *__restrict__ leafK, int top)
+__device__ inline void top_tiers(const double *__restrict__ nA, const double *__restrict__ nB,
+                                 double T2, uint32_t *__restrict__ rowptr,
+                                 uint32_t *__restrict__ list0, uint32_t *__restrict__ list1,
+                                 uint64_t *__restrict__ leafK, int top)
 {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     constexpr int NW = kScanThreads / kWave;
-    // tiers 1..top of both pyramids in LDS, each tier at a 16-byte aligned
-    // offset (the children of a node are read as two 16-byte pairs)
+    // tiers 1..top of both pyramids, each tier at a 16-byte aligned offset
+    // (the children of a node are read as two 16-byte pairs)
     __shared__ __align__(16) double sA[kTopNorms], sB[kTopNorms];
+    __shared__ uint32_t sRow[kTopRows];
+    __shared__ uint32_t sList0[kTopListEven], sList1[kTopListOdd];
+    __shared__ uint32_t sCnt[4 << (2 * (kTopTiers - 1))];
     for (int t = 1; t <= top; ++t) {
         const int64_t cnt = int64_t(1) << (2 * t);
         for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
@@ -492,9 +530,14 @@ __global__ __launch_bounds__(kScanThreads) void cull_top(const double *__restric
         }
     }
     if (threadIdx.x == 0) {
+        const uint32_t kept = keep_pair(nA[0], nB[0], T2) ? 1u : 0u;
+        sRow[0] = 0;
+        sRow[1] = kept;
+        sList0[0] = 0;
         rowptr[0] = 0;
-        rowptr[1] = keep_pair(nA[0], nB[0], T2) ? 1u : 0u;
-        list0[0] = 0;
+        rowptr[1] = kept;
+        if (top == 0)
+            list0[0] = 0;
         leafK[0] = leafK[1] = 0;
         reinterpret_cast<double *>(leafK)[3] = nA[0];
         reinterpret_cast<double *>(leafK)[4] = nB[0];
@@ -503,39 +546,54 @@ __global__ __launch_bounds__(kScanThreads) void cull_top(const double *__restric
     for (int t = 1; t <= top; ++t) {
         const uint32_t np = 1u << (2 * (t - 1));
         const double *tA = sA + top_offset(t), *tB = sB + top_offset(t);
-        const uint32_t *prow = rowptr + rowptr_offset(t - 1);
-        uint32_t *crow = rowptr + rowptr_offset(t);
-        const uint32_t *plist = (t - 1) & 1 ? list1 : list0;
-        uint32_t *clist = t & 1 ? list1 : list0;
+        const uint32_t *prow = sRow + top_row_offset(t - 1);
+        uint32_t *crow = sRow + top_row_offset(t);
+        const uint32_t *plist = (t - 1) & 1 ? sList1 : sList0;
         for (uint32_t P = w; P < np; P += NW)
-            count_tile(tA, tB, T2, prow, plist, P, counts, lane);
+            count_tile(tA, tB, T2, prow, plist, P, sCnt, lane);
         __syncthreads();
-        // exclusive scan of counts[0 .. 4 np) into crow, crow[4 np] = total
+        // exclusive scan of the counts (4 np <= kScanChunk: one pass) into
+        // crow, crow[4 np] = total, in LDS and in the plan's row pointers
         const uint32_t m = 4 * np;
-        uint32_t carry = 0;
-        for (uint32_t c0 = 0; c0 < m; c0 += kScanChunk) {
-            const uint32_t base = c0 + threadIdx.x * kScanItems;
+        uint32_t *grow = rowptr + rowptr_offset(t);
+        {
+            const uint32_t base = threadIdx.x * kScanItems;
             uint32_t v[kScanItems];
 #pragma unroll
             for (int i = 0; i < kScanItems; ++i)
-                v[i] = (base + i < m) ? counts[base + i] : 0u;
+                v[i] = (base + i < m) ? sCnt[base + i] : 0u;
             uint32_t total;
-            uint32_t pfx = block_scan4(v, &total) + carry;
+            uint32_t pfx = block_scan4(v, &total);
 #pragma unroll
             for (int i = 0; i < kScanItems; ++i) {
-                if (base + i < m)
+                if (base + i < m) {
                     crow[base + i] = pfx;
+                    grow[base + i] = pfx;
+                }
                 pfx += v[i];
             }
-            carry += total;
+            if (threadIdx.x == 0) {
+                crow[m] = total;
+                grow[m] = total;
+            }
         }
-        if (threadIdx.x == 0)
-            crow[m] = carry;
         __syncthreads();
+        // the top tier's list goes to the plan (the next tier reads it)
+        uint32_t *clist = t == top ? (t & 1 ? list1 : list0) : (t & 1 ? sList1 : sList0);
         for (uint32_t P = w; P < np; P += NW)
             emit_tile(tA, tB, T2, prow, plist, P, crow, clist, lane);
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(kScanThreads) void cull_top(const double *__restrict__ nA,
+                                                         const double *__restrict__ nB, double T2,
+                                                         uint32_t *__restrict__ rowptr,
+                                                         uint32_t *__restrict__ list0,
+                                                         uint32_t *__restrict__ list1,
+                                                         uint64_t *__restrict__ leafK, int top)
+{
+    top_tiers(nA, nB, T2, rowptr, list0, list1, leafK, top);
 }
 
 // partials needs ceil(m / kScanChunk) + 1 entries.
@@ -580,7 +638,7 @@ hipError_t launch_cull(spamm_plan *p, hipStream_t s)
     // root and the upper tiers in one workgroup, the rest tier by tier
     const int top = d - 1 < kTopTiers ? d - 1 : kTopTiers;
     hipLaunchKernelGGL(cull_top, dim3(1), dim3(kScanThreads), 0, s, nA, nB, p->T2, p->rowptr,
-                       p->list[0], p->list[1], p->counts, p->leafK, top);
+                       p->list[0], p->list[1], p->leafK, top);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     for (int t = top + 1; t <= d; ++t) {
@@ -644,6 +702,199 @@ hipError_t launch_cull(spamm_plan *p, hipStream_t s)
     // leafK[0] = HIGH leaf products, leafK[1] = LOW ones (0 without split),
     // leafK[3], leafK[4] = the roots ||A||_F^2, ||B||_F^2 (FP64 bit patterns)
     return hipSuccess;
+}
+
+// ---- rounds: the culls of several plans in shared launches -----------------
+// The same per-wave code as the per-plan kernels above, so every plan's
+// lists are the ones its own cull would give; plans of depth 1..8.
+__global__ __launch_bounds__(kScanThreads) void cull_top_jobs(const Jobs<TopJob> jobs)
+{
+    const TopJob &j = jobs.job[blockIdx.x];
+    top_tiers(j.nA, j.nB, j.T2, j.rowptr, j.list0, j.list1, j.leafK, j.top);
+}
+
+__global__ __launch_bounds__(256) void cull_count_jobs(const Jobs<TierJob> jobs)
+{
+    const TierJob &j = job_at(jobs, blockIdx.x);
+    const uint32_t P = (blockIdx.x - j.block0) * 4u + (threadIdx.x >> 6);
+    if (P < j.np)
+        count_tile(j.tA, j.tB, j.T2, j.prow, j.plist, P, j.counts, threadIdx.x & 63);
+}
+
+// exclusive scan of one plan's 4 np child counts into its row pointers
+__global__ __launch_bounds__(kScanThreads) void cull_scan_jobs(const Jobs<TierJob> jobs)
+{
+    const TierJob &j = jobs.job[blockIdx.x];
+    block_exclusive_scan(j.counts, 4 * j.np, j.crow);
+}
+
+__global__ __launch_bounds__(256) void cull_emit_jobs(const Jobs<TierJob> jobs)
+{
+    const TierJob &j = job_at(jobs, blockIdx.x);
+    const uint32_t P = (blockIdx.x - j.block0) * 4u + (threadIdx.x >> 6);
+    if (P < j.np)
+        emit_tile(j.tA, j.tB, j.T2, j.prow, j.plist, P, j.crow, j.clist, threadIdx.x & 63);
+}
+
+__global__ __launch_bounds__(256) void cull_count_leaf_jobs(const Jobs<LeafJob> jobs)
+{
+    const LeafJob &j = job_at(jobs, blockIdx.x);
+    const uint32_t P = (blockIdx.x - j.block0) * 4u + (threadIdx.x >> 6);
+    if (P >= j.np)
+        return;
+    if (j.split)
+        count_leaf_tile<true>(j.tA, j.tB, j.T2, low_bound(j.L2, j.theta2, j.nA, j.nB), j.prow,
+                              j.plist, j.np, j.counts, P, threadIdx.x & 63);
+    else
+        count_leaf_tile<false>(j.tA, j.tB, j.T2, 0.0, j.prow, j.plist, j.np, j.counts, P,
+                               threadIdx.x & 63);
+}
+
+// One workgroup per plan (np <= 4 kScanChunk): block row pointers of both
+// classes, the kept leaf products into leafK, and the plan's readback words.
+__global__ __launch_bounds__(kScanThreads) void leaf_totals_jobs(const Jobs<LeafJob> jobs)
+{
+    const LeafJob &j = jobs.job[blockIdx.x];
+    block_exclusive_scan(j.counts, j.np, j.browptr);
+    const uint64_t hi = block_sum(j.counts + j.np, j.np);
+    uint64_t lo = 0;
+    if (j.split) {
+        block_exclusive_scan(j.counts + 2 * (size_t)j.np, j.np, j.browptr_lo);
+        lo = block_sum(j.counts + 3 * (size_t)j.np, j.np);
+    }
+    if (threadIdx.x == 0) {
+        j.leafK[0] = hi;
+        j.leafK[1] = lo;
+        j.rout[0] = hi;
+        j.rout[1] = lo;
+        j.rout[2] = 0;
+        j.rout[3] = (uint64_t)__double_as_longlong(j.nA[0]);
+        j.rout[4] = (uint64_t)__double_as_longlong(j.nB[0]);
+    }
+}
+
+__global__ __launch_bounds__(256) void cull_emit_leaf_jobs(const Jobs<LeafJob> jobs)
+{
+    const LeafJob &j = job_at(jobs, blockIdx.x);
+    const uint32_t P = (blockIdx.x - j.block0) * 4u + (threadIdx.x >> 6);
+    if (P >= j.np)
+        return;
+    if (j.split)
+        emit_leaf_tile<true>(j.tA, j.tB, j.T2, low_bound(j.L2, j.theta2, j.nA, j.nB), j.prow,
+                             j.plist, j.browptr, j.bent, j.browptr_lo, j.bent_lo, P,
+                             threadIdx.x & 63);
+    else
+        emit_leaf_tile<false>(j.tA, j.tB, j.T2, 0.0, j.prow, j.plist, j.browptr, j.bent,
+                              nullptr, nullptr, P, threadIdx.x & 63);
+}
+
+template <typename J>
+static hipError_t launch_jobs_chunked(const std::vector<J> &all, bool per_block,
+                                      void (*kernel)(const Jobs<J>), int threads,
+                                      uint32_t (*blocks_of)(const J &), hipStream_t s)
+{
+    for (size_t i0 = 0; i0 < all.size(); i0 += kMaxRound) {
+        Jobs<J> t{};
+        for (size_t i = i0; i < all.size() && t.njobs < kMaxRound; ++i) {
+            J j = all[i];
+            j.block0 = per_block ? (uint32_t)t.njobs : t.nblocks;
+            t.nblocks += per_block ? 1u : blocks_of(j);
+            t.job[t.njobs++] = j;
+        }
+        hipLaunchKernelGGL(kernel, dim3(t.nblocks), dim3(threads), 0, s, t);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+static uint32_t tier_blocks(const TierJob &j) { return (j.np + 3) / 4; }
+static uint32_t leaf_blocks(const LeafJob &j) { return (j.np + 3) / 4; }
+static uint32_t one_block(const TopJob &) { return 1; }
+
+// The culls of `nplans` plans (depth 1..8, buffers carved): the upper tiers
+// of all in one launch, then each deeper tier's count -> scan -> emit over
+// the plans that have it, then the leaf tier of all.
+hipError_t launch_cull_round(const spamm_plan *const *plans, int nplans, uint64_t *rout,
+                             hipStream_t s)
+{
+    std::vector<TopJob> tops;
+    int dmax = 0;
+    for (int i = 0; i < nplans; ++i) {
+        const spamm_plan *p = plans[i];
+        if (p->depth < 1 || p->depth > 8)
+            return hipErrorInvalidValue;
+        TopJob t{};
+        t.nA = p->A->norms;
+        t.nB = p->B->norms;
+        t.rowptr = p->rowptr;
+        t.list0 = p->list[0];
+        t.list1 = p->list[1];
+        t.leafK = p->leafK;
+        t.T2 = p->T2;
+        t.top = p->depth - 1 < kTopTiers ? p->depth - 1 : kTopTiers;
+        tops.push_back(t);
+        dmax = std::max(dmax, (int)p->depth);
+    }
+    hipError_t e = launch_jobs_chunked(tops, true, cull_top_jobs, kScanThreads, one_block, s);
+    for (int t = kTopTiers + 1; t < dmax && e == hipSuccess; ++t) {
+        std::vector<TierJob> tiers;
+        for (int i = 0; i < nplans; ++i) {
+            const spamm_plan *p = plans[i];
+            if (t >= p->depth)
+                continue;
+            TierJob j{};
+            j.tA = p->A->norms + tier_offset(t);
+            j.tB = p->B->norms + tier_offset(t);
+            j.prow = p->rowptr + p->rp_off[t - 1];
+            j.plist = p->list[(t - 1) & 1];
+            j.counts = p->counts;
+            j.crow = p->rowptr + p->rp_off[t];
+            j.clist = p->list[t & 1];
+            j.T2 = p->T2;
+            j.np = 1u << (2 * (t - 1));
+            tiers.push_back(j);
+        }
+        e = launch_jobs_chunked(tiers, false, cull_count_jobs, 256, tier_blocks, s);
+        if (e == hipSuccess)
+            e = launch_jobs_chunked(tiers, true, cull_scan_jobs, kScanThreads, tier_blocks, s);
+        if (e == hipSuccess)
+            e = launch_jobs_chunked(tiers, false, cull_emit_jobs, 256, tier_blocks, s);
+    }
+    std::vector<LeafJob> leaves;
+    for (int i = 0; i < nplans; ++i) {
+        const spamm_plan *p = plans[i];
+        const int d = p->depth;
+        const bool split = p->precision != SPAMM_PREC_FP32;
+        LeafJob j{};
+        j.tA = p->A->norms + tier_offset(d);
+        j.tB = p->B->norms + tier_offset(d);
+        j.nA = p->A->norms;
+        j.nB = p->B->norms;
+        j.prow = p->rowptr + p->rp_off[d - 1];
+        j.plist = p->list[(d - 1) & 1];
+        j.counts = p->counts;
+        j.browptr = p->browptr;
+        j.bent = p->bent;
+        j.browptr_lo = split ? p->browptr_lo : nullptr;
+        j.bent_lo = split ? p->bent_lo : nullptr;
+        j.leafK = p->leafK;
+        j.rout = rout + 5 * (size_t)i;
+        j.T2 = p->T2;
+        j.L2 = split ? p->L2 : 0.0;
+        j.theta2 = split ? p->theta2 : 0.0;
+        j.np = 1u << (2 * (d - 1));
+        j.split = split ? 1 : 0;
+        leaves.push_back(j);
+    }
+    if (e == hipSuccess)
+        e = launch_jobs_chunked(leaves, false, cull_count_leaf_jobs, 256, leaf_blocks, s);
+    if (e == hipSuccess)
+        e = launch_jobs_chunked(leaves, true, leaf_totals_jobs, kScanThreads, leaf_blocks, s);
+    if (e == hipSuccess)
+        e = launch_jobs_chunked(leaves, false, cull_emit_leaf_jobs, 256, leaf_blocks, s);
+    return e;
 }
 
 }  // namespace spamm

@@ -10,6 +10,8 @@
 // (bits 0-1 of e), a six-step xor butterfly over lanes (bits 2-7) and an
 // in-register tree over m (bits 8 and up).  Squares of FP32 values are exact
 // in FP64, so only the additions round and their order is fixed.
+#include <vector>
+
 #include "runtime.hpp"
 
 namespace spamm {
@@ -122,19 +124,19 @@ __device__ inline void store_fp16x4(uint16_t *dst, float4 v, int e)
 // is a.  So the butterfly skips lane bit 3, the register tree stops below m
 // bit 3, and the leaf norm is the parent of its four sub-blocks:
 // (s_00 + s_01) + (s_10 + s_11), written to sub_norm[4 l + 2a + b].
+// The body of one workgroup (block `bid` of the leaves' grid).
 template <int B, int VEC, bool SUB, bool TWO>
-__global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ A, int64_t n,
-                                                      float *__restrict__ tiles,
-                                                      float *__restrict__ tilesT,
-                                                      uint16_t *__restrict__ tiles16,
-                                                      uint16_t *__restrict__ tilesT16,
-                                                      double *__restrict__ leaf_norm,
-                                                      double *__restrict__ parent,
-                                                      double *__restrict__ sub_norm,
-                                                      const uint32_t *__restrict__ keep,
-                                                      const uint32_t *__restrict__ slot,
-                                                      int32_t *__restrict__ scale16,
-                                                      uint32_t ntiles, int known_zero)
+__device__ inline void norm_pack_block(const float *__restrict__ A, int64_t n,
+                                       float *__restrict__ tiles, float *__restrict__ tilesT,
+                                       uint16_t *__restrict__ tiles16,
+                                       uint16_t *__restrict__ tilesT16,
+                                       double *__restrict__ leaf_norm,
+                                       double *__restrict__ parent,
+                                       double *__restrict__ sub_norm,
+                                       const uint32_t *__restrict__ keep,
+                                       const uint32_t *__restrict__ slot,
+                                       int32_t *__restrict__ scale16, uint32_t ntiles,
+                                       int known_zero, uint32_t bid)
 {
     static_assert(!SUB || B == 64, "sub-block norms are built for 64 x 64 leaves");
     using L = LeafLayout<B>;
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
     __shared__ double part[4];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const uint32_t l = blockIdx.x * 4u + (uint32_t)w;
+    const uint32_t l = bid * 4u + (uint32_t)w;
     const bool valid = l < ntiles;
     float *tr = tr_smem + w * (RH * P);
     double s = 0.0;
@@ -303,12 +305,31 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
             part[w] = s;
         __syncthreads();
         if (threadIdx.x == 0)
-            parent[blockIdx.x] = (part[0] + part[1]) + (part[2] + part[3]);
+            parent[bid] = (part[0] + part[1]) + (part[2] + part[3]);
     }
 }
 
+template <int B, int VEC, bool SUB, bool TWO>
+__global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ A, int64_t n,
+                                                      float *__restrict__ tiles,
+                                                      float *__restrict__ tilesT,
+                                                      uint16_t *__restrict__ tiles16,
+                                                      uint16_t *__restrict__ tilesT16,
+                                                      double *__restrict__ leaf_norm,
+                                                      double *__restrict__ parent,
+                                                      double *__restrict__ sub_norm,
+                                                      const uint32_t *__restrict__ keep,
+                                                      const uint32_t *__restrict__ slot,
+                                                      int32_t *__restrict__ scale16,
+                                                      uint32_t ntiles, int known_zero)
+{
+    norm_pack_block<B, VEC, SUB, TWO>(A, n, tiles, tilesT, tiles16, tilesT16, leaf_norm, parent,
+                                      sub_norm, keep, slot, scale16, ntiles, known_zero,
+                                      blockIdx.x);
+}
+
 // Tiers top-1 .. 0 from tier `top` (already built), one workgroup.
-__global__ __launch_bounds__(1024) void norm_pyramid(double *__restrict__ norms, int top)
+__device__ inline void pyramid_tiers(double *__restrict__ norms, int top)
 {
     for (int t = top - 1; t >= 0; --t) {
         const double *ch = norms + tier_offset(t + 1);
@@ -318,6 +339,11 @@ __global__ __launch_bounds__(1024) void norm_pyramid(double *__restrict__ norms,
             pa[i] = (ch[4 * i] + ch[4 * i + 1]) + (ch[4 * i + 2] + ch[4 * i + 3]);
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(1024) void norm_pyramid(double *__restrict__ norms, int top)
+{
+    pyramid_tiers(norms, top);
 }
 
 template <int B, int VEC, bool SUB, bool TWO>
@@ -480,14 +506,12 @@ hipError_t launch_sparse_pack(const float *A, int64_t n, int leaf, int depth, fl
 // reached: leaf 4b + q of GEMM block b (the children of a tier-(d-1) node; b
 // = 0, q = 0 for the single leaf at depth 0) iff an entry of the block's
 // HIGH or LOW list has bit q in its quadrant mask.  One thread per block.
-__global__ __launch_bounds__(256) void output_keep(const uint32_t *__restrict__ browptr,
-                                                   const uint32_t *__restrict__ bent,
-                                                   const uint32_t *__restrict__ browptr_lo,
-                                                   const uint32_t *__restrict__ bent_lo,
-                                                   uint32_t nblocks, uint32_t nleaves,
-                                                   uint32_t *__restrict__ keep)
+__device__ inline void keep_of_block(const uint32_t *__restrict__ browptr,
+                                     const uint32_t *__restrict__ bent,
+                                     const uint32_t *__restrict__ browptr_lo,
+                                     const uint32_t *__restrict__ bent_lo, uint32_t nblocks,
+                                     uint32_t nleaves, uint32_t *__restrict__ keep, uint32_t b)
 {
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nblocks)
         return;
     uint32_t m = 0;
@@ -500,6 +524,17 @@ __global__ __launch_bounds__(256) void output_keep(const uint32_t *__restrict__ 
     for (uint32_t q = 0; q < 4; ++q)
         if (4 * b + q < nleaves)
             keep[4 * b + q] = (m >> q) & 1u;
+}
+
+__global__ __launch_bounds__(256) void output_keep(const uint32_t *__restrict__ browptr,
+                                                   const uint32_t *__restrict__ bent,
+                                                   const uint32_t *__restrict__ browptr_lo,
+                                                   const uint32_t *__restrict__ bent_lo,
+                                                   uint32_t nblocks, uint32_t nleaves,
+                                                   uint32_t *__restrict__ keep)
+{
+    keep_of_block(browptr, bent, browptr_lo, bent_lo, nblocks, nleaves, keep,
+                  blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Tree of C from the plan that produced it, in two parts: the keep flags
@@ -535,6 +570,147 @@ hipError_t launch_output_pack(const float *C, int64_t n, int leaf, int depth, fl
         return e;
     hipLaunchKernelGGL(norm_pyramid, dim3(1), dim3(1024), 0, s, norms, depth - 1);
     return hipGetLastError();
+}
+
+// ---- rounds: the builds of several trees in shared launches ---------------
+template <int B, int VEC, bool TWO>
+__global__ __launch_bounds__(256) void leaf_norm_pack_jobs(const Jobs<PackJob> jobs)
+{
+    const PackJob &p = job_at(jobs, blockIdx.x);
+    norm_pack_block<B, VEC, false, TWO>(p.A, p.n, p.tiles, p.tilesT, p.t16, p.tT16, p.leafn,
+                                        p.parent, nullptr, p.keep, nullptr, p.scale16, p.ntiles,
+                                        p.known_zero, blockIdx.x - p.block0);
+}
+
+__global__ __launch_bounds__(1024) void norm_pyramid_jobs(const Jobs<PyrJob> jobs)
+{
+    const PyrJob &p = jobs.job[blockIdx.x];
+    pyramid_tiers(p.norms, p.top);
+}
+
+__global__ __launch_bounds__(256) void output_keep_jobs(const Jobs<KeepJob> jobs)
+{
+    const KeepJob &k = job_at(jobs, blockIdx.x);
+    keep_of_block(k.browptr, k.bent, k.browptr_lo, k.bent_lo, k.nblocks, k.nleaves, k.keep,
+                  (blockIdx.x - k.block0) * blockDim.x + threadIdx.x);
+}
+
+template <int B, int VEC>
+static hipError_t launch_pack_jobs(const Jobs<PackJob> &jobs, hipStream_t s)
+{
+    constexpr bool TWO = B == 64;
+    constexpr size_t lds = sizeof(float) * 4 * (TWO ? B / 2 : B) * (B + 1);
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void *)leaf_norm_pack_jobs<B, VEC, TWO>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess)
+        return attr;
+    hipLaunchKernelGGL((leaf_norm_pack_jobs<B, VEC, TWO>), dim3(jobs.nblocks), dim3(256), lds, s,
+                       jobs);
+    return hipGetLastError();
+}
+
+static hipError_t launch_pack_any(int leaf, int vec, const Jobs<PackJob> &jobs, hipStream_t s)
+{
+#define SPAMM_PACK_VEC(B)                                                                     \
+    return vec == 4 ? launch_pack_jobs<B, 4>(jobs, s)                                          \
+           : vec == 2 ? launch_pack_jobs<B, 2>(jobs, s) : launch_pack_jobs<B, 1>(jobs, s)
+    switch (leaf) {
+    case 16: SPAMM_PACK_VEC(16);
+    case 32: SPAMM_PACK_VEC(32);
+    case 64: SPAMM_PACK_VEC(64);
+    default: return hipErrorInvalidValue;
+    }
+#undef SPAMM_PACK_VEC
+}
+
+static int load_width(const float *A, int64_t n)
+{
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(A);
+    return (n % 4 == 0 && addr % 16 == 0) ? 4 : (n % 2 == 0 && addr % 8 == 0) ? 2 : 1;
+}
+
+// The keep flags of the output trees, then every tree's leaves (one launch
+// per leaf size and load width, at most kMaxRound trees each), then the
+// pyramids.  Each tree is built exactly as by launch_build (dense) or as an
+// output tree with its leaves at their linear index.
+hipError_t launch_build_round(const RoundTree *trees, int ntrees, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    {
+        Jobs<KeepJob> kj{};
+        for (int i = 0; i <= ntrees && e == hipSuccess; ++i) {
+            if (i < ntrees && trees[i].from != nullptr) {
+                const spamm_plan *p = trees[i].from;
+                const bool split = p->precision != SPAMM_PREC_FP32;
+                KeepJob &k = kj.job[kj.njobs++];
+                k.browptr = p->browptr;
+                k.bent = p->bent;
+                k.browptr_lo = split ? p->browptr_lo : nullptr;
+                k.bent_lo = split ? p->bent_lo : nullptr;
+                k.keep = trees[i].tree->keep;
+                k.nblocks = (uint32_t)p->nblocks;
+                k.nleaves = 1u << (2 * p->depth);
+                k.block0 = kj.nblocks;
+                kj.nblocks += (k.nblocks + 255) / 256;
+            }
+            if (kj.njobs > 0 && (i == ntrees || kj.njobs == kMaxRound)) {
+                hipLaunchKernelGGL(output_keep_jobs, dim3(kj.nblocks), dim3(256), 0, s, kj);
+                e = hipGetLastError();
+                kj = Jobs<KeepJob>{};
+            }
+        }
+    }
+    std::vector<bool> done(ntrees, false);
+    for (int i = 0; i < ntrees && e == hipSuccess; ++i) {
+        if (done[i])
+            continue;
+        const int leaf = trees[i].tree->leaf, vec = load_width(trees[i].src, trees[i].tree->n);
+        Jobs<PackJob> pj{};
+        for (int k = i; k < ntrees && e == hipSuccess; ++k) {
+            const spamm_tree *t = trees[k].tree;
+            if (done[k] || t->leaf != leaf || load_width(trees[k].src, t->n) != vec)
+                continue;
+            done[k] = true;
+            const int d = t->depth;
+            PackJob &p = pj.job[pj.njobs++];
+            p.A = trees[k].src;
+            p.n = t->n;
+            p.tiles = t->tiles;
+            p.tilesT = t->tilesT;
+            p.t16 = t->tiles16;
+            p.tT16 = t->tilesT16;
+            p.scale16 = t->scale16;
+            p.leafn = t->norms + tier_offset(d);
+            p.parent = d >= 1 ? t->norms + tier_offset(d - 1) : nullptr;
+            p.keep = trees[k].from != nullptr ? t->keep : nullptr;
+            p.known_zero = trees[k].from != nullptr ? 1 : 0;
+            p.ntiles = 1u << (2 * d);
+            p.block0 = pj.nblocks;
+            pj.nblocks += (p.ntiles + 3) / 4;
+            if (pj.njobs == kMaxRound) {
+                e = launch_pack_any(leaf, vec, pj, s);
+                pj = Jobs<PackJob>{};
+            }
+        }
+        if (e == hipSuccess && pj.njobs > 0)
+            e = launch_pack_any(leaf, vec, pj, s);
+    }
+    Jobs<PyrJob> yj{};
+    for (int i = 0; i <= ntrees && e == hipSuccess; ++i) {
+        if (i < ntrees && trees[i].tree->depth >= 2) {
+            PyrJob &y = yj.job[yj.njobs++];
+            y.norms = trees[i].tree->norms;
+            y.top = trees[i].tree->depth - 1;
+            y.block0 = (uint32_t)yj.njobs - 1;
+        }
+        if (yj.njobs > 0 && (i == ntrees || yj.njobs == kMaxRound)) {
+            hipLaunchKernelGGL(norm_pyramid_jobs, dim3(yj.njobs), dim3(1024), 0, s, yj);
+            e = hipGetLastError();
+            yj = Jobs<PyrJob>{};
+        }
+    }
+    return e;
 }
 
 }  // namespace spamm

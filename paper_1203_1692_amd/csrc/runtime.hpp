@@ -81,6 +81,31 @@ hipError_t launch_sparse_pack(const float *A, int64_t n, int leaf, int depth, fl
                               float *tilesT, uint16_t *t16, uint16_t *tT16, const uint32_t *keep,
                               const uint32_t *slot, hipStream_t s);
 
+// ---- rounds: the tree builds and culls of several products in shared
+// launches (serving loop).  Trees and plans are set up on the host with
+// their buffers carved (tree_prepare, plan_prepare), then built and culled
+// together; depths 1..kRoundMaxDepth.
+constexpr int kRoundMaxDepth = 8;
+
+struct RoundTree {
+    const spamm_tree *tree;     // carved, not yet built
+    const float *src;           // the matrix (A, B, or the product of `from`)
+    const spamm_plan *from;     // output tree: the plan that computed src, else null
+};
+
+// Carves a tree (tree_device_bytes bytes of `arena`) without building it.
+// `keep`: for an output tree, N^2 words of keep flags (leaves stay at their
+// linear index, so the tree needs no slot map), else null.
+int tree_prepare(int64_t n, int32_t leaf, uint32_t flags, void *arena, uint32_t *keep,
+                 hipStream_t s, spamm_tree **out);
+// Sets up a plan with its buffers carved from `arena`, without culling.
+int plan_prepare(const spamm_tree *A, const spamm_tree *B, const spamm_opts *opts,
+                 hipStream_t s, void *arena, spamm_plan **out);
+hipError_t launch_build_round(const RoundTree *trees, int ntrees, hipStream_t s);
+// rout: 5 words per plan (HIGH and LOW leaf products, 0, the roots' bits).
+hipError_t launch_cull_round(const spamm_plan *const *plans, int nplans, uint64_t *rout,
+                             hipStream_t s);
+
 // Steady clock in microseconds (request timestamps).
 double now_us();
 

@@ -1,8 +1,20 @@
 // Serving loop: FIFO admission by device-memory footprint and free slots,
-// one stream per slot for tree builds and culls, batched leaf-GEMM launches
-// across requests on one GEMM stream, squaring chains kept on the device.
+// tree builds and culls of many requests in shared launches (rounds),
+// batched leaf-GEMM launches across requests on one GEMM stream, squaring
+// chains kept on the device.
 //
-// Stream protocol of one admitted request (slot stream ss, GEMM stream gs):
+// Rounds (requests of depth 1..8, every serving size): the steps waiting
+// for their build and cull are gathered into one round on the prep stream
+// ps: [wait for the GEMMs enqueued so far, when a chain step is in it] ->
+// keep flags of the output trees -> every tree's leaves and norms -> the
+// pyramids -> the culls of all plans, tier by tier -> one readback of every
+// plan's counts and roots -> record the round's event.  About 15 launches
+// for up to 16 requests, where one request alone took 10 to 18.  Once the
+// host sees the event, the round's requests join the next GEMM batch; a
+// chain request's next step joins the next round.
+//
+// Other depths run each step on their slot's stream (slot stream ss, GEMM
+// stream gs):
 //   ss: build tree(s) -> root norm to pinned host -> cull -> task counts to
 //       pinned host -> record ev_cull
 //   gs: a batch of requests whose ev_cull has completed (the host polls it,
@@ -48,6 +60,8 @@ constexpr size_t kMaxQueue = 65536;
 // GEMM batches allowed on the GEMM stream at once; requests culled while
 // the stream is full wait and join the next batch.
 constexpr int kInflightBatches = 2;
+// rounds in flight on the prep stream
+constexpr int kRounds = 4;
 
 struct StepOut {                   // one step's cull readback: its plan's leafK[0..5)
     uint64_t K[2];                 // HIGH / LOW leaf products
@@ -65,6 +79,18 @@ struct Job {
     spamm_request rq;
     size_t bytes;
     double t_submit;
+    bool batched;                  // its steps go through rounds
+};
+
+// a batched request's step: waiting for a round, in one, culled
+enum Phase : int { kIdle = 0, kPrep, kCulling, kReady };
+
+struct Round {
+    hipEvent_t ev = nullptr;
+    uint64_t *dout = nullptr;      // device: 5 words per plan (launch_cull_round)
+    uint64_t *hout = nullptr;      // pinned copy of dout
+    std::vector<uint64_t> tickets; // the requests of the round, in plan order
+    bool busy = false;
 };
 
 struct Active {
@@ -75,6 +101,8 @@ struct Active {
     spamm_tree *tA = nullptr, *tB = nullptr;
     spamm_plan *plan = nullptr;
     bool culled = false;           // this step's cull enqueued, its GEMM not yet
+    bool batched = false;
+    int phase = kIdle;             // batched requests
     bool final = false;            // nothing more to enqueue; done once ev_done passes
     int status = SPAMM_OK;
     double t_admit = 0.0;
@@ -82,7 +110,7 @@ struct Active {
 
 bool bad_tol(double v) { return !(v >= 0.0) || isinf(v) || (v > 0.0 && v < 1e-150); }
 
-int check_request(const spamm_request *r, size_t *bytes)
+int check_request(const spamm_request *r, size_t *bytes, bool *batched = nullptr)
 {
     if (r == nullptr)
         return fail(SPAMM_E_INVAL, "request is NULL");
@@ -119,6 +147,8 @@ int check_request(const spamm_request *r, size_t *bytes)
     const bool distinctB = r->B != nullptr && r->B != r->A;
     *bytes = tree_device_bytes(r->n, r->leaf, tree_flags_for(r->precision)) * (distinctB ? 2 : 1) +
              plan_device_bytes(d, split) + (r->chain_len > 0 ? output_map_bytes(d) : 0);
+    if (batched != nullptr)
+        *batched = d >= 1 && d <= kRoundMaxDepth;
     return SPAMM_OK;
 }
 
@@ -129,6 +159,8 @@ struct spamm_server {
     size_t budget = 0;
     int nslots = 0;
     hipStream_t gemm = nullptr;
+    hipStream_t prep = nullptr;          // rounds
+    Round rounds[kRounds];
     hipStream_t ss[kMaxSlots] = {};
     hipEvent_t ev_cull[kMaxSlots] = {}, ev_done[kMaxSlots] = {};
     Pinned *pin = nullptr;
@@ -223,8 +255,16 @@ void release_step(spamm_server *S, Active &a)
 void advance(spamm_server *S, Active &a)
 {
     a.culled = false;
+    a.phase = kIdle;
     if (a.step + 1 >= a.steps) {
         a.final = true;
+        return;
+    }
+    if (a.batched) {
+        // the next round builds step s+1 from C and this step's plan (kept
+        // until then, with the step's trees)
+        a.step += 1;
+        a.phase = kPrep;
         return;
     }
     // step s+1 reads C and step s's schedule, and overwrites step s's trees:
@@ -259,6 +299,11 @@ bool launch_batches(spamm_server *S)
     std::vector<size_t> ready;
     for (size_t i = 0; i < S->active.size(); ++i) {
         Active &a = S->active[i];
+        if (a.batched) {
+            if (a.phase == kReady)
+                ready.push_back(i);
+            continue;
+        }
         if (!a.culled)
             continue;
         const hipError_t q = hipEventQuery(S->ev_cull[a.slot]);
@@ -328,12 +373,174 @@ bool launch_batches(spamm_server *S)
                 // are released once the GEMM stream has drained
                 a.status = hip_fail(f, "batched leaf GEMM");
                 a.culled = false;
+                a.phase = kIdle;
                 a.final = true;
                 hipStreamSynchronize(S->gemm);
                 continue;
             }
             advance(S, a);
         }
+        any = true;
+    }
+    return any;
+}
+
+Active *find_active(spamm_server *S, uint64_t ticket)
+{
+    for (Active &a : S->active)
+        if (a.job.ticket == ticket)
+            return &a;
+    return nullptr;
+}
+
+// One round on the prep stream for the requests S->active[pick[..]] (at most
+// kMaxRound, all in phase kPrep).
+void launch_round(spamm_server *S, Round &R, const std::vector<size_t> &pick)
+{
+    hipStream_t ps = S->prep;
+    bool chain = false;
+    for (size_t i : pick)
+        chain |= S->active[i].step > 0;
+    // a chain step reads C and overwrites its previous trees: after every
+    // GEMM enqueued so far (the GEMM stream runs in order)
+    if (chain && !S->inflight.empty())
+        hipStreamWaitEvent(ps, S->inflight.back(), 0);
+    std::vector<RoundTree> trees;
+    std::vector<const spamm_plan *> plans;
+    std::vector<size_t> in;
+    std::vector<spamm_plan *> old_plans;
+    std::vector<spamm_tree *> old_trees;
+    for (size_t i : pick) {
+        Active &a = S->active[i];
+        const spamm_request &r = a.job.rq;
+        const uint32_t flags = tree_flags_for(r.precision);
+        // arena: [tree of A or X_s][tree of B, step 0 only][plan][keep flags, chains]
+        char *base = (char *)S->arena[a.slot];
+        const size_t tb = tree_device_bytes(r.n, r.leaf, flags);
+        spamm_plan *prev = a.step > 0 ? a.plan : nullptr;
+        old_plans.push_back(a.plan);
+        old_trees.push_back(a.tA);
+        if (a.tB != a.tA)
+            old_trees.push_back(a.tB);
+        a.plan = nullptr;
+        a.tA = a.tB = nullptr;
+        int rc;
+        if (a.step > 0) {
+            uint32_t *keep = (uint32_t *)(base + tb + plan_device_bytes(prev->depth, a.split));
+            rc = tree_prepare(r.n, r.leaf, flags, base, keep, ps, &a.tA);
+            a.tB = a.tA;
+        } else {
+            rc = tree_prepare(r.n, r.leaf, flags, base, nullptr, ps, &a.tA);
+            if (rc == SPAMM_OK && a.distinctB)
+                rc = tree_prepare(r.n, r.leaf, flags, base + tb, nullptr, ps, &a.tB);
+            else
+                a.tB = a.tA;
+        }
+        spamm_opts o{};
+        o.tau = r.tau;
+        o.precision = r.precision;
+        o.low_tol = a.split ? r.low_tol : 0.0;
+        o.low_rel = a.split ? r.low_rel : 0.0;
+        if (rc == SPAMM_OK)
+            rc = plan_prepare(a.tA, a.tB, &o, ps, base + (a.distinctB ? 2 : 1) * tb, &a.plan);
+        if (rc != SPAMM_OK) {
+            a.status = rc;
+            a.phase = kIdle;
+            a.final = true;
+            continue;
+        }
+        trees.push_back({a.tA, a.step == 0 ? r.A : r.C, prev});
+        if (a.tB != a.tA)
+            trees.push_back({a.tB, r.B, nullptr});
+        plans.push_back(a.plan);
+        in.push_back(i);
+    }
+    hipError_t e = hipSuccess;
+    if (!in.empty()) {
+        e = launch_build_round(trees.data(), (int)trees.size(), ps);
+        if (e == hipSuccess)
+            e = launch_cull_round(plans.data(), (int)plans.size(), R.dout, ps);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(R.hout, R.dout, sizeof(StepOut) * in.size(), hipMemcpyDeviceToHost,
+                               ps);
+        if (e == hipSuccess)
+            e = hipEventRecord(R.ev, ps);
+    }
+    // the previous steps' handles (their buffers live in the slot arenas and
+    // were read by the work just enqueued)
+    for (spamm_plan *p : old_plans)
+        spamm_plan_free(p);
+    for (spamm_tree *t : old_trees)
+        spamm_tree_free(t);
+    if (e != hipSuccess) {
+        const int rc = hip_fail(e, "round build / cull");
+        hipStreamSynchronize(ps);
+        for (size_t i : in) {
+            S->active[i].status = rc;
+            S->active[i].phase = kIdle;
+            S->active[i].final = true;
+        }
+        return;
+    }
+    if (in.empty())
+        return;
+    R.busy = true;
+    R.tickets.clear();
+    for (size_t i : in) {
+        R.tickets.push_back(S->active[i].job.ticket);
+        S->active[i].phase = kCulling;
+    }
+}
+
+// Rounds for every request waiting in phase kPrep, while round records are
+// free.  Returns true if anything was launched.
+bool form_rounds(spamm_server *S)
+{
+    bool any = false;
+    for (Round &R : S->rounds) {
+        if (R.busy)
+            continue;
+        std::vector<size_t> pick;
+        for (size_t i = 0; i < S->active.size() && (int)pick.size() < kMaxRound; ++i)
+            if (S->active[i].batched && S->active[i].phase == kPrep)
+                pick.push_back(i);
+        if (pick.empty())
+            break;
+        launch_round(S, R, pick);
+        any = true;
+    }
+    return any;
+}
+
+// Completed rounds: their requests' counts and roots to the slots' step
+// records, and on to the GEMM batches.
+bool poll_rounds(spamm_server *S)
+{
+    bool any = false;
+    for (Round &R : S->rounds) {
+        if (!R.busy)
+            continue;
+        const hipError_t q = hipEventQuery(R.ev);
+        if (q == hipErrorNotReady)
+            continue;
+        const int rc = q == hipSuccess ? SPAMM_OK : hip_fail(q, "round build / cull");
+        if (q != hipSuccess)
+            hipStreamSynchronize(S->prep);
+        for (size_t j = 0; j < R.tickets.size(); ++j) {
+            Active *a = find_active(S, R.tickets[j]);
+            if (a == nullptr)
+                continue;
+            if (rc == SPAMM_OK) {
+                memcpy(&S->pin[a->slot].step[a->step], R.hout + 5 * j, sizeof(StepOut));
+                a->phase = kReady;
+            } else {
+                a->status = rc;
+                a->phase = kIdle;
+                a->final = true;
+            }
+        }
+        R.busy = false;
+        R.tickets.clear();
         any = true;
     }
     return any;
@@ -373,8 +580,10 @@ void finish(spamm_server *S, Active &a)
 
 // Pick a free slot whose arena can hold `need` bytes, growing one (and
 // releasing idle arenas) within the budget.  Called with S->mu held; -1 when
-// the request has to wait.  Returns a HIP error through *err.
-int claim_slot(spamm_server *S, size_t need, hipError_t *err)
+// the request has to wait.  Returns a HIP error through *err.  A new arena
+// is allocated in the order of the stream that will first use it (the prep
+// stream for a batched request, else the slot's stream).
+int claim_slot(spamm_server *S, size_t need, bool batched, hipError_t *err)
 {
     int fit = -1, big = -1;
     for (int i = 0; i < S->nslots; ++i) {
@@ -408,7 +617,8 @@ int claim_slot(spamm_server *S, size_t need, hipError_t *err)
         S->arena[big] = nullptr;
         S->cap[big] = 0;
     }
-    hipError_t e = dev_alloc_async(S->device, &S->arena[big], need, S->ss[big]);
+    hipError_t e = dev_alloc_async(S->device, &S->arena[big], need,
+                                   batched ? S->prep : S->ss[big]);
     if (e != hipSuccess) {
         S->arena[big] = nullptr;
         *err = e;
@@ -436,7 +646,8 @@ void scheduler(spamm_server *S)
             }
             while (!S->queue.empty()) {
                 hipError_t err = hipSuccess;
-                const int slot = claim_slot(S, S->queue.front().bytes, &err);
+                const int slot = claim_slot(S, S->queue.front().bytes, S->queue.front().batched,
+                                            &err);
                 if (slot < 0) {
                     if (err == hipSuccess)
                         break;
@@ -472,16 +683,23 @@ void scheduler(spamm_server *S)
             a.steps = std::max(1, a.job.rq.chain_len);
             a.split = a.job.rq.precision != SPAMM_PREC_FP32;
             a.distinctB = a.job.rq.B != nullptr && a.job.rq.B != a.job.rq.A;
+            a.batched = a.job.batched;
             a.t_admit = now_us();
-            int rc = start_step(S, a, nullptr);
-            if (rc) {
-                a.status = rc;
-                a.culled = false;
-                a.final = true;
+            if (a.batched) {
+                a.phase = kPrep;          // the next round builds and culls it
+            } else {
+                int rc = start_step(S, a, nullptr);
+                if (rc) {
+                    a.status = rc;
+                    a.culled = false;
+                    a.final = true;
+                }
             }
             S->active.push_back(a);
         }
+        progress |= poll_rounds(S);
         progress |= launch_batches(S);
+        progress |= form_rounds(S);
         for (size_t i = 0; i < S->active.size();) {
             Active &a = S->active[i];
             bool over = false;
@@ -517,6 +735,8 @@ void release_server(spamm_server *S)
 {
     if (S->gemm)
         hipStreamSynchronize(S->gemm);
+    if (S->prep)
+        hipStreamSynchronize(S->prep);
     for (int i = 0; i < S->nslots; ++i)
         if (S->ss[i])
             hipStreamSynchronize(S->ss[i]);
@@ -536,6 +756,15 @@ void release_server(spamm_server *S)
     }
     if (S->gemm)
         hipStreamDestroy(S->gemm);
+    for (Round &R : S->rounds)
+        if (R.ev)
+            hipEventDestroy(R.ev);
+    if (S->rounds[0].dout)
+        hipFree(S->rounds[0].dout);
+    if (S->rounds[0].hout)
+        hipHostFree(S->rounds[0].hout);
+    if (S->prep)
+        hipStreamDestroy(S->prep);
     if (S->pin)
         hipHostFree(S->pin);
     delete S;
@@ -571,6 +800,25 @@ int spamm_server_create(size_t hbm_budget, int32_t max_slots, spamm_server **out
     S->budget = hbm_budget;
     S->nslots = max_slots;
     hipError_t e = hipStreamCreateWithFlags(&S->gemm, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&S->prep, hipStreamNonBlocking);
+    // round readbacks: 5 words per plan, kMaxRound plans per round
+    const size_t rwords = 5 * (size_t)kMaxRound;
+    uint64_t *dout = nullptr, *hout = nullptr;
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&dout, sizeof(uint64_t) * rwords * kRounds);
+    if (e == hipSuccess)
+        S->rounds[0].dout = dout;
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&hout, sizeof(uint64_t) * rwords * kRounds,
+                          hipHostMallocDefault);
+    if (e == hipSuccess)
+        S->rounds[0].hout = hout;
+    for (int r = 0; r < kRounds && e == hipSuccess; ++r) {
+        S->rounds[r].dout = dout + rwords * r;
+        S->rounds[r].hout = hout + rwords * r;
+        e = hipEventCreateWithFlags(&S->rounds[r].ev, hipEventDisableTiming);
+    }
     for (int i = 0; i < max_slots && e == hipSuccess; ++i) {
         e = hipStreamCreateWithFlags(&S->ss[i], hipStreamNonBlocking);
         if (e == hipSuccess)
@@ -608,7 +856,8 @@ int spamm_submit(spamm_server *S, const spamm_request *req, uint64_t *ticket)
     if (S == nullptr || ticket == nullptr)
         return fail(SPAMM_E_INVAL, "NULL argument");
     size_t bytes = 0;
-    int rc = check_request(req, &bytes);
+    bool batched = false;
+    int rc = check_request(req, &bytes, &batched);
     if (rc)
         return rc;
     if (bytes > S->budget)
@@ -618,6 +867,7 @@ int spamm_submit(spamm_server *S, const spamm_request *req, uint64_t *ticket)
     j.rq = *req;
     j.bytes = bytes;
     j.t_submit = now_us();
+    j.batched = batched;
     {
         std::lock_guard<std::mutex> lock(S->mu);
         if (S->stopping)
