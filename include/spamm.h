@@ -413,6 +413,9 @@ typedef struct spamm_server_stats {
     uint64_t budget;             /* hbm_budget                                       */
     double   sched_cpu_ms;       /* CPU time used by the scheduler thread so far     */
     double   sched_wall_ms;      /* wall time since the scheduler thread started     */
+    int64_t  rounds;             /* rounds: shared launches of the tree builds and   */
+                                 /* culls of several requests' steps                 */
+    int64_t  round_steps;        /* request steps built and culled in rounds         */
 } spamm_server_stats;
 
 /*

@@ -98,7 +98,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("admitted", "completed", "queued", "launches",
                                               "launched_products", "max_batch", "peak_active")] + \
                [(k, ctypes.c_uint64) for k in ("used", "peak_used", "budget")] + \
-               [(k, ctypes.c_double) for k in ("sched_cpu_ms", "sched_wall_ms")]
+               [(k, ctypes.c_double) for k in ("sched_cpu_ms", "sched_wall_ms")] + \
+               [(k, ctypes.c_int64) for k in ("rounds", "round_steps")]
 
     def as_dict(self) -> dict:
         return {k: (float(getattr(self, k)) if k.endswith("_ms") else int(getattr(self, k)))

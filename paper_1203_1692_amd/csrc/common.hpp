@@ -205,9 +205,11 @@ struct Jobs {
 template <typename J>
 __device__ inline const J &job_at(const Jobs<J> &jobs, uint32_t bid)
 {
+    // independent tests (no chain of dependent loads)
     int j = 0;
-    while (j + 1 < jobs.njobs && bid >= jobs.job[j + 1].block0)
-        ++j;
+#pragma unroll
+    for (int i = 1; i < kMaxRound; ++i)
+        j += (i < jobs.njobs && bid >= jobs.job[i].block0) ? 1 : 0;
     return jobs.job[j];
 }
 
@@ -221,6 +223,10 @@ struct PackJob {           // leaf norms and packed copies of one tree
     const uint32_t *keep;  // with known_zero: the leaves not kept are zero
     uint32_t ntiles, block0;
     int32_t known_zero;
+    // a pack after the norms: leaf norms, the two roots and tau^2 of the
+    // product the tree takes part in (leaves no product can keep are skipped)
+    const double *drop_s, *rootA, *rootB;
+    double T2;
 };
 
 struct KeepJob {           // output-leaf keep flags from a product's schedule

@@ -136,7 +136,11 @@ __device__ inline void norm_pack_block(const float *__restrict__ A, int64_t n,
                                        const uint32_t *__restrict__ keep,
                                        const uint32_t *__restrict__ slot,
                                        int32_t *__restrict__ scale16, uint32_t ntiles,
-                                       int known_zero, uint32_t bid)
+                                       int known_zero, uint32_t bid,
+                                       const double *__restrict__ drop_s = nullptr,
+                                       const double *__restrict__ rootA = nullptr,
+                                       const double *__restrict__ rootB = nullptr,
+                                       double T2 = 0.0)
 {
     static_assert(!SUB || B == 64, "sub-block norms are built for 64 x 64 leaves");
     using L = LeafLayout<B>;
@@ -161,7 +165,13 @@ __device__ inline void norm_pack_block(const float *__restrict__ A, int64_t n,
     // stores only its kept leaves, leaf l at slot[l].  known_zero: a leaf
     // that is not kept is known to be all zeros, so it is not read and its
     // norm is +0, the value the pairwise sum of its squares gives.)
-    const bool zero = valid && known_zero && keep[l] == 0u;
+    // drop_s (a pack after the norms are built): a leaf whose squared norm s
+    // passes no product test against a leaf of norm at most the larger root
+    // (s = 0, or fl64(s m) < T2 with m = max(rootA, rootB)) can never be read,
+    // so it is not packed (Sec. II.C)
+    const bool dropped = valid && drop_s != nullptr &&
+                         !(drop_s[l] > 0.0 && !(drop_s[l] * fmax(rootA[0], rootB[0]) < T2));
+    const bool zero = valid && ((known_zero && keep[l] == 0u) || dropped);
     const bool pack = valid && tiles != nullptr && (keep == nullptr || keep[l] != 0u);
     const int64_t dl = pack && slot != nullptr ? (int64_t)slot[l] : (int64_t)l;
     float4 v[M];
@@ -573,13 +583,49 @@ hipError_t launch_output_pack(const float *C, int64_t n, int leaf, int depth, fl
 }
 
 // ---- rounds: the builds of several trees in shared launches ---------------
-template <int B, int VEC, bool TWO>
+// A workgroup takes CB consecutive blocks (4 leaves each) of one tree.  The
+// first wave finds which of them hold a leaf to read (neither known zero nor
+// dropped); the workgroup then runs the blocks that do, and a block that
+// does not only gets its zero norms (norm pass).  Far fewer workgroups than
+// one per block, and the ones of a mostly-zero or mostly-dropped tree finish
+// at once.
+template <int B, int VEC, bool TWO, int CB>
 __global__ __launch_bounds__(256) void leaf_norm_pack_jobs(const Jobs<PackJob> jobs)
 {
+    static_assert(4 * CB <= kWave, "one wave tests the chunk's leaves");
     const PackJob &p = job_at(jobs, blockIdx.x);
-    norm_pack_block<B, VEC, false, TWO>(p.A, p.n, p.tiles, p.tilesT, p.t16, p.tT16, p.leafn,
-                                        p.parent, nullptr, p.keep, nullptr, p.scale16, p.ntiles,
-                                        p.known_zero, blockIdx.x - p.block0);
+    const uint32_t b0 = (blockIdx.x - p.block0) * CB;
+    __shared__ uint64_t live;
+    if (threadIdx.x < kWave) {
+        const uint32_t l = 4 * b0 + threadIdx.x;
+        bool act = threadIdx.x < 4 * CB && l < p.ntiles;
+        if (act && p.known_zero && p.keep[l] == 0u)
+            act = false;
+        if (act && p.drop_s != nullptr)
+            act = p.drop_s[l] > 0.0 && !(p.drop_s[l] * fmax(p.rootA[0], p.rootB[0]) < p.T2);
+        const uint64_t m = __ballot(act);
+        if (threadIdx.x == 0)
+            live = m;
+    }
+    __syncthreads();
+    const uint64_t m = live;
+    const uint32_t nblk = (p.ntiles + 3) / 4;
+    for (int i = 0; i < CB && b0 + i < nblk; ++i) {
+        const uint32_t b = b0 + i;
+        if ((m >> (4 * i)) & 0xFu) {
+            norm_pack_block<B, VEC, false, TWO>(p.A, p.n, p.tiles, p.tilesT, p.t16, p.tT16,
+                                                p.leafn, p.parent, nullptr, p.keep, nullptr,
+                                                p.scale16, p.ntiles, p.known_zero, b, p.drop_s,
+                                                p.rootA, p.rootB, p.T2);
+            __syncthreads();              // the block's LDS (parent partials) is reused
+        } else if (p.leafn != nullptr && threadIdx.x < 4) {
+            // every leaf of the block is zero: norms +0, and so is the parent
+            if (4 * b + threadIdx.x < p.ntiles)
+                p.leafn[4 * b + threadIdx.x] = 0.0;
+            if (threadIdx.x == 0 && p.parent != nullptr)
+                p.parent[b] = 0.0;
+        }
+    }
 }
 
 __global__ __launch_bounds__(1024) void norm_pyramid_jobs(const Jobs<PyrJob> jobs)
@@ -595,18 +641,21 @@ __global__ __launch_bounds__(256) void output_keep_jobs(const Jobs<KeepJob> jobs
                   (blockIdx.x - k.block0) * blockDim.x + threadIdx.x);
 }
 
+// blocks per workgroup of the round pack kernel
+constexpr int kPackChunk = 8;
+
 template <int B, int VEC>
 static hipError_t launch_pack_jobs(const Jobs<PackJob> &jobs, hipStream_t s)
 {
     constexpr bool TWO = B == 64;
     constexpr size_t lds = sizeof(float) * 4 * (TWO ? B / 2 : B) * (B + 1);
     static const hipError_t attr =
-        hipFuncSetAttribute((const void *)leaf_norm_pack_jobs<B, VEC, TWO>,
+        hipFuncSetAttribute((const void *)leaf_norm_pack_jobs<B, VEC, TWO, kPackChunk>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (attr != hipSuccess)
         return attr;
-    hipLaunchKernelGGL((leaf_norm_pack_jobs<B, VEC, TWO>), dim3(jobs.nblocks), dim3(256), lds, s,
-                       jobs);
+    hipLaunchKernelGGL((leaf_norm_pack_jobs<B, VEC, TWO, kPackChunk>), dim3(jobs.nblocks),
+                       dim3(256), lds, s, jobs);
     return hipGetLastError();
 }
 
@@ -661,41 +710,61 @@ hipError_t launch_build_round(const RoundTree *trees, int ntrees, hipStream_t s)
             }
         }
     }
-    std::vector<bool> done(ntrees, false);
-    for (int i = 0; i < ntrees && e == hipSuccess; ++i) {
-        if (done[i])
-            continue;
-        const int leaf = trees[i].tree->leaf, vec = load_width(trees[i].src, trees[i].tree->n);
-        Jobs<PackJob> pj{};
-        for (int k = i; k < ntrees && e == hipSuccess; ++k) {
-            const spamm_tree *t = trees[k].tree;
-            if (done[k] || t->leaf != leaf || load_width(trees[k].src, t->n) != vec)
+    // pass 1 (tau > 0): norms only; pass 2 after the pyramids: the pack of
+    // the leaves that can take part in a kept product.  tau = 0: one pass.
+    auto pack_pass = [&](int pass) {
+        std::vector<bool> done(ntrees, false);
+        for (int i = 0; i < ntrees && e == hipSuccess; ++i) {
+            if (done[i])
                 continue;
-            done[k] = true;
-            const int d = t->depth;
-            PackJob &p = pj.job[pj.njobs++];
-            p.A = trees[k].src;
-            p.n = t->n;
-            p.tiles = t->tiles;
-            p.tilesT = t->tilesT;
-            p.t16 = t->tiles16;
-            p.tT16 = t->tilesT16;
-            p.scale16 = t->scale16;
-            p.leafn = t->norms + tier_offset(d);
-            p.parent = d >= 1 ? t->norms + tier_offset(d - 1) : nullptr;
-            p.keep = trees[k].from != nullptr ? t->keep : nullptr;
-            p.known_zero = trees[k].from != nullptr ? 1 : 0;
-            p.ntiles = 1u << (2 * d);
-            p.block0 = pj.nblocks;
-            pj.nblocks += (p.ntiles + 3) / 4;
-            if (pj.njobs == kMaxRound) {
-                e = launch_pack_any(leaf, vec, pj, s);
-                pj = Jobs<PackJob>{};
+            const int leaf = trees[i].tree->leaf;
+            const int vec = load_width(trees[i].src, trees[i].tree->n);
+            Jobs<PackJob> pj{};
+            for (int k = i; k < ntrees && e == hipSuccess; ++k) {
+                const spamm_tree *t = trees[k].tree;
+                if (done[k] || t->leaf != leaf || load_width(trees[k].src, t->n) != vec)
+                    continue;
+                done[k] = true;
+                const bool two = trees[k].T2 > 0.0;
+                if (pass == 2 && !two)
+                    continue;
+                const int d = t->depth;
+                PackJob &p = pj.job[pj.njobs++];
+                p = PackJob{};
+                p.A = trees[k].src;
+                p.n = t->n;
+                p.ntiles = 1u << (2 * d);
+                p.block0 = pj.nblocks;
+                pj.nblocks += ((p.ntiles + 3) / 4 + kPackChunk - 1) / kPackChunk;
+                if (pass == 1) {
+                    p.leafn = t->norms + tier_offset(d);
+                    p.parent = d >= 1 ? t->norms + tier_offset(d - 1) : nullptr;
+                    p.keep = trees[k].from != nullptr ? t->keep : nullptr;
+                    p.known_zero = trees[k].from != nullptr ? 1 : 0;
+                }
+                if (pass == 2 || !two) {
+                    p.tiles = t->tiles;
+                    p.tilesT = t->tilesT;
+                    p.t16 = t->tiles16;
+                    p.tT16 = t->tilesT16;
+                    p.scale16 = t->scale16;
+                }
+                if (pass == 2) {
+                    p.drop_s = t->norms + tier_offset(d);
+                    p.rootA = t->norms;
+                    p.rootB = trees[k].other->norms;
+                    p.T2 = trees[k].T2;
+                }
+                if (pj.njobs == kMaxRound) {
+                    e = launch_pack_any(leaf, vec, pj, s);
+                    pj = Jobs<PackJob>{};
+                }
             }
+            if (e == hipSuccess && pj.njobs > 0)
+                e = launch_pack_any(leaf, vec, pj, s);
         }
-        if (e == hipSuccess && pj.njobs > 0)
-            e = launch_pack_any(leaf, vec, pj, s);
-    }
+    };
+    pack_pass(1);
     Jobs<PyrJob> yj{};
     for (int i = 0; i <= ntrees && e == hipSuccess; ++i) {
         if (i < ntrees && trees[i].tree->depth >= 2) {
@@ -710,6 +779,7 @@ hipError_t launch_build_round(const RoundTree *trees, int ntrees, hipStream_t s)
             yj = Jobs<PyrJob>{};
         }
     }
+    pack_pass(2);
     return e;
 }
 

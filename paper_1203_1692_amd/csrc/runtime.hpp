@@ -91,6 +91,11 @@ struct RoundTree {
     const spamm_tree *tree;     // carved, not yet built
     const float *src;           // the matrix (A, B, or the product of `from`)
     const spamm_plan *from;     // output tree: the plan that computed src, else null
+    // tau^2 of the product the tree takes part in, and its other operand
+    // (the tree itself for a square).  T2 > 0: the norms are built first and
+    // only the leaves some kept product can read are packed
+    double T2;
+    const spamm_tree *other;
 };
 
 // Carves a tree (tree_device_bytes bytes of `arena`) without building it.

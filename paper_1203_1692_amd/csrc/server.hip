@@ -4,11 +4,15 @@
 // chains kept on the device.
 //
 // Rounds (requests of depth 1..8, every serving size): the steps waiting
-// for their build and cull are gathered into one round on the prep stream
-// ps: [wait for the GEMMs enqueued so far, when a chain step is in it] ->
-// keep flags of the output trees -> every tree's leaves and norms -> the
-// pyramids -> the culls of all plans, tier by tier -> one readback of every
-// plan's counts and roots -> record the round's event.  About 15 launches
+// for their build and cull are gathered into one round on a prep stream ps
+// (two rounds in flight, one per prep stream):
+//   ps: [wait for the GEMMs enqueued so far, when a chain step is in it] ->
+// keep flags of the output trees -> every tree's leaf norms -> the pyramids
+// -> the pack of the leaves that some kept product can read (tau > 0: a leaf
+// with fl64(s max(||A||^2, ||B||^2)) < tau^2 never passes the product test,
+// Sec. II.C; its norm stays, so task sets, roots and C are those of the
+// dense trees) -> the culls of all plans, tier by tier -> one readback of
+// every plan's counts and roots -> record the round's event.  About 15 launches
 // for up to 16 requests, where one request alone took 10 to 18.  Once the
 // host sees the event, the round's requests join the next GEMM batch; a
 // chain request's next step joins the next round.
@@ -34,6 +38,7 @@
 // The arenas together never exceed the server's budget.
 #include <math.h>
 #include <pthread.h>
+#include <sys/prctl.h>
 #include <string.h>
 #include <time.h>
 
@@ -60,8 +65,12 @@ constexpr size_t kMaxQueue = 65536;
 // GEMM batches allowed on the GEMM stream at once; requests culled while
 // the stream is full wait and join the next batch.
 constexpr int kInflightBatches = 2;
-// rounds in flight on the prep stream
-constexpr int kRounds = 4;
+// rounds in flight, each on a prep stream of its own: a round is a chain of
+// short launches, so two overlap on the chip; a new round takes every step
+// waiting at the time (up to kMaxRound)
+constexpr int kRounds = 2;
+// idle scheduler passes that yield before it sleeps between polls
+constexpr int kSpinPasses = 16;
 
 struct StepOut {                   // one step's cull readback: its plan's leafK[0..5)
     uint64_t K[2];                 // HIGH / LOW leaf products
@@ -86,6 +95,7 @@ struct Job {
 enum Phase : int { kIdle = 0, kPrep, kCulling, kReady };
 
 struct Round {
+    hipStream_t s = nullptr;       // the round's prep stream
     hipEvent_t ev = nullptr;
     uint64_t *dout = nullptr;      // device: 5 words per plan (launch_cull_round)
     uint64_t *hout = nullptr;      // pinned copy of dout
@@ -159,8 +169,7 @@ struct spamm_server {
     size_t budget = 0;
     int nslots = 0;
     hipStream_t gemm = nullptr;
-    hipStream_t prep = nullptr;          // rounds
-    Round rounds[kRounds];
+    Round rounds[kRounds];               // each with its prep stream
     hipStream_t ss[kMaxSlots] = {};
     hipEvent_t ev_cull[kMaxSlots] = {}, ev_done[kMaxSlots] = {};
     Pinned *pin = nullptr;
@@ -393,11 +402,11 @@ Active *find_active(spamm_server *S, uint64_t ticket)
     return nullptr;
 }
 
-// One round on the prep stream for the requests S->active[pick[..]] (at most
+// One round on R's prep stream for the requests S->active[pick[..]] (at most
 // kMaxRound, all in phase kPrep).
 void launch_round(spamm_server *S, Round &R, const std::vector<size_t> &pick)
 {
-    hipStream_t ps = S->prep;
+    hipStream_t ps = R.s;
     bool chain = false;
     for (size_t i : pick)
         chain |= S->active[i].step > 0;
@@ -449,9 +458,10 @@ void launch_round(spamm_server *S, Round &R, const std::vector<size_t> &pick)
             a.final = true;
             continue;
         }
-        trees.push_back({a.tA, a.step == 0 ? r.A : r.C, prev});
+        const double T2 = r.tau * r.tau;
+        trees.push_back({a.tA, a.step == 0 ? r.A : r.C, prev, T2, a.tB});
         if (a.tB != a.tA)
-            trees.push_back({a.tB, r.B, nullptr});
+            trees.push_back({a.tB, r.B, nullptr, T2, a.tA});
         plans.push_back(a.plan);
         in.push_back(i);
     }
@@ -486,6 +496,11 @@ void launch_round(spamm_server *S, Round &R, const std::vector<size_t> &pick)
         return;
     R.busy = true;
     R.tickets.clear();
+    {
+        std::lock_guard<std::mutex> lock(S->mu);
+        S->st.rounds += 1;
+        S->st.round_steps += (int64_t)in.size();
+    }
     for (size_t i : in) {
         R.tickets.push_back(S->active[i].job.ticket);
         S->active[i].phase = kCulling;
@@ -525,7 +540,7 @@ bool poll_rounds(spamm_server *S)
             continue;
         const int rc = q == hipSuccess ? SPAMM_OK : hip_fail(q, "round build / cull");
         if (q != hipSuccess)
-            hipStreamSynchronize(S->prep);
+            hipStreamSynchronize(R.s);
         for (size_t j = 0; j < R.tickets.size(); ++j) {
             Active *a = find_active(S, R.tickets[j]);
             if (a == nullptr)
@@ -581,8 +596,9 @@ void finish(spamm_server *S, Active &a)
 // Pick a free slot whose arena can hold `need` bytes, growing one (and
 // releasing idle arenas) within the budget.  Called with S->mu held; -1 when
 // the request has to wait.  Returns a HIP error through *err.  A new arena
-// is allocated in the order of the stream that will first use it (the prep
-// stream for a batched request, else the slot's stream).
+// is allocated in the slot stream's order; for a batched request, whose
+// rounds run on the prep streams, that stream is then synchronized (arenas
+// grow rarely: the steady state reuses them).
 int claim_slot(spamm_server *S, size_t need, bool batched, hipError_t *err)
 {
     int fit = -1, big = -1;
@@ -617,8 +633,9 @@ int claim_slot(spamm_server *S, size_t need, bool batched, hipError_t *err)
         S->arena[big] = nullptr;
         S->cap[big] = 0;
     }
-    hipError_t e = dev_alloc_async(S->device, &S->arena[big], need,
-                                   batched ? S->prep : S->ss[big]);
+    hipError_t e = dev_alloc_async(S->device, &S->arena[big], need, S->ss[big]);
+    if (e == hipSuccess && batched)
+        e = hipStreamSynchronize(S->ss[big]);
     if (e != hipSuccess) {
         S->arena[big] = nullptr;
         *err = e;
@@ -632,6 +649,8 @@ int claim_slot(spamm_server *S, size_t need, bool batched, hipError_t *err)
 void scheduler(spamm_server *S)
 {
     hipSetDevice(S->device);
+    // short sleeps between polls stay short (the default slack is 50 us)
+    prctl(PR_SET_TIMERSLACK, 2000UL, 0UL, 0UL, 0UL);
     int idle = 0;
     for (;;) {
         std::vector<Job> admitted;
@@ -721,12 +740,14 @@ void scheduler(spamm_server *S)
                 ++i;
             }
         }
+        // nothing moved: yield a few passes, then poll every ~10 us (the
+        // GPU work being waited for takes tens of microseconds or more)
         if (progress) {
             idle = 0;
-        } else if (++idle < 256) {
+        } else if (++idle < kSpinPasses) {
             std::this_thread::yield();
         } else {
-            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            std::this_thread::sleep_for(std::chrono::microseconds(8));
         }
     }
 }
@@ -735,8 +756,9 @@ void release_server(spamm_server *S)
 {
     if (S->gemm)
         hipStreamSynchronize(S->gemm);
-    if (S->prep)
-        hipStreamSynchronize(S->prep);
+    for (Round &R : S->rounds)
+        if (R.s)
+            hipStreamSynchronize(R.s);
     for (int i = 0; i < S->nslots; ++i)
         if (S->ss[i])
             hipStreamSynchronize(S->ss[i]);
@@ -756,15 +778,16 @@ void release_server(spamm_server *S)
     }
     if (S->gemm)
         hipStreamDestroy(S->gemm);
-    for (Round &R : S->rounds)
+    for (Round &R : S->rounds) {
         if (R.ev)
             hipEventDestroy(R.ev);
+        if (R.s)
+            hipStreamDestroy(R.s);
+    }
     if (S->rounds[0].dout)
         hipFree(S->rounds[0].dout);
     if (S->rounds[0].hout)
         hipHostFree(S->rounds[0].hout);
-    if (S->prep)
-        hipStreamDestroy(S->prep);
     if (S->pin)
         hipHostFree(S->pin);
     delete S;
@@ -800,8 +823,6 @@ int spamm_server_create(size_t hbm_budget, int32_t max_slots, spamm_server **out
     S->budget = hbm_budget;
     S->nslots = max_slots;
     hipError_t e = hipStreamCreateWithFlags(&S->gemm, hipStreamNonBlocking);
-    if (e == hipSuccess)
-        e = hipStreamCreateWithFlags(&S->prep, hipStreamNonBlocking);
     // round readbacks: 5 words per plan, kMaxRound plans per round
     const size_t rwords = 5 * (size_t)kMaxRound;
     uint64_t *dout = nullptr, *hout = nullptr;
@@ -818,6 +839,8 @@ int spamm_server_create(size_t hbm_budget, int32_t max_slots, spamm_server **out
         S->rounds[r].dout = dout + rwords * r;
         S->rounds[r].hout = hout + rwords * r;
         e = hipEventCreateWithFlags(&S->rounds[r].ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipStreamCreateWithFlags(&S->rounds[r].s, hipStreamNonBlocking);
     }
     for (int i = 0; i < max_slots && e == hipSuccess; ++i) {
         e = hipStreamCreateWithFlags(&S->ss[i], hipStreamNonBlocking);
