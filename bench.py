@@ -514,7 +514,10 @@ def serve_run(sp, torch, srv, reqs, inputs, qps=None, window=16, keep=()):
     info1 = srv.info()
     busy = ((info1["sched_cpu_ms"] - info0["sched_cpu_ms"]) /
             max(info1["sched_wall_ms"] - info0["sched_wall_ms"], 1e-9))
-    return out, kept, dict(t0=t0, t_first=t_first, t_last=t_last, t_end=t_end, sched_busy=busy)
+    grew = {k: info1[k] - info0[k] for k in ("launches", "launched_products", "rounds",
+                                              "round_steps")}
+    return out, kept, dict(t0=t0, t_first=t_first, t_last=t_last, t_end=t_end, sched_busy=busy,
+                           **grew)
 
 
 def serve_summary(reqs, res, tm, qps):
@@ -538,6 +541,13 @@ def serve_summary(reqs, res, tm, qps):
         "queue_p99_ms": percentile([res[r.index]["queue_ms"] for r in reqs], 99),
         "failed": bad,
         "scheduler_cpu_fraction": tm.get("sched_busy"),
+        # shared launches: GEMM launch groups, and rounds of tree builds + culls
+        "gemm_launch_groups": tm.get("launches"),
+        "products_per_gemm_group": (round(tm["launched_products"] / tm["launches"], 3)
+                                    if tm.get("launches") else None),
+        "rounds": tm.get("rounds"),
+        "steps_per_round": (round(tm["round_steps"] / tm["rounds"], 3)
+                            if tm.get("rounds") else None),
         "plain": pq(lambda r: r.chain_len == 0),
         "chains": pq(lambda r: r.chain_len > 0),
         "fp32": pq(lambda r: not r.split),
