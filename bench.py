@@ -59,6 +59,18 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
+def gemm_kernel_name(precision: str, leaf: int, depth: int, sub: bool = False) -> str:
+    """The leaf-GEMM kernel the library picks for a product (its plan's kind)."""
+    if sub:
+        return "leaf_gemm_sub<64>"
+    if precision == "split-bf16":
+        return ("leaf_gemm_split_wide" if leaf == 64 and depth >= 2
+                else f"leaf_gemm_split<{leaf}, false>")
+    if precision == "split-fp16":
+        return f"leaf_gemm_split<{leaf}, true>"
+    return "leaf_gemm_wide32" if leaf == 64 and depth >= 2 else f"leaf_gemm<{leaf}>"
+
+
 def measured_traffic(workload: str):
     """HBM bytes per leaf-GEMM launch from the committed rocprofv3 counter runs,
     or None when absent, for another workload, or taken on other kernel code."""
@@ -921,6 +933,7 @@ def main() -> int:
             "effective_tflops_2n3": round(2.0 * n ** 3 / (ms_step * 1e-3) / 1e12, 3),
         },
         "roofline": {
+            "kernel": gemm_kernel_name("fp32", leaf, d, sub),
             "bound": "mfma",
             "achieved": round(gemm_tflops, 3),
             "peak": MFMA_FP32_PEAK_TFLOPS,
@@ -943,6 +956,7 @@ def main() -> int:
         out["config"]["theta"] = args.theta
         out["config"]["tasks_low"] = st["tasks_low"]
         out["roofline"] = {
+            "kernel": gemm_kernel_name("split-fp16" if f16 else "split-bf16", leaf, d),
             "bound": "hbm", "achieved": round(gbs, 1) if gbs else None, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4) if gbs else None, "traffic": tb,
         }

@@ -793,6 +793,54 @@ __device__ inline uint32_t merge_children(const uint32_t *__restrict__ rp,
     return base;
 }
 
+// FP32 products of 4 x 4 block P4 (merged list of its children's HIGH, or
+// only, schedules): FP32 k-panels (8 KB), 64 KB stages in a 2-deep ring over
+// the workgroup's LDS; wave (r, c) adds its leaf's products into acc, k
+// ascending.
+__device__ inline void wide_fp32_products(const GemmJob &job, uint32_t P4, uint32_t I0,
+                                          uint32_t J0, uint32_t NK, int w, int r, int c,
+                                          int bit, int lane, float *smem, uint32_t *kmask,
+                                          uint32_t *list, uint32_t *wsum, floatx16 (&acc)[2][2])
+{
+    constexpr int B = 64;
+    const int pan = w >> 1, part = w & 1;
+    constexpr int P32 = LeafLayout<B>::kPanel;
+    float *ring32 = smem;
+    const float *__restrict__ tA = (const float *)job.tA;
+    const float *__restrict__ tBT = (const float *)job.tBT;
+    const uint32_t nhi = merge_children(job.browptr, job.bent, P4, NK, kmask, list, wsum);
+    // wave w copies half (w & 1) of FP32 panel w >> 1: four 1 KB copies
+    auto issue_hi = [&](uint32_t st) {
+        const uint32_t ent = list[st >> 1], k = ent & 0xFFFFu, m = ent >> 16;
+        const uint32_t need = pan < 4 ? (m >> (4 * pan)) & 0xFu : (m >> (pan - 4)) & 0x1111u;
+        if (need == 0u)
+            return;
+        const float *leaf = pan < 4
+                                ? tA + leaf_slot(job.slotA, lin_index(I0 + pan, k)) * (B * B)
+                                : tBT + leaf_slot(job.slotB, lin_index(k, J0 + (pan - 4))) * (B * B);
+        const float *src = leaf + (st & 1u) * P32 + part * (P32 / 2) + 4 * lane;
+        float *dst = ring32 + (st & 1u) * kWideStage32 + pan * P32 + part * (P32 / 2);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            __builtin_amdgcn_global_load_lds((global_void_t *)(src + 256 * i),
+                                             (lds_void_t *)(dst + 256 * i), 16, 0, 0);
+    };
+    const uint32_t T = 2 * nhi;
+    if (T > 0)
+        issue_hi(0);
+    for (uint32_t t = 0; t < T; ++t) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);             // vmcnt(0)
+        __syncthreads();
+        if (t + 1 < T)
+            issue_hi(t + 1);
+        const uint32_t ent = list[t >> 1];
+        if ((ent >> (16 + bit)) & 1u) {
+            const float *buf = ring32 + (t & 1u) * kWideStage32;
+            panel_mfma32<B>(buf + r * P32, buf + (4 + c) * P32, acc, lane);
+        }
+    }
+}
+
 __global__ __launch_bounds__(1024) void leaf_gemm_split_wide(const GemmJobs jobs)
 {
     constexpr int B = 64, MB = 2;
@@ -903,43 +951,51 @@ __global__ __launch_bounds__(1024) void leaf_gemm_split_wide(const GemmJobs jobs
     }
     __syncthreads();                      // every wave is done with the LOW ring and list
 
-    // ---- HIGH products: FP32 k-panels (8 KB), 64 KB stages, 2-deep ring --------
-    constexpr int P32 = LeafLayout<B>::kPanel;
-    float *ring32 = smem;
-    const float *__restrict__ tA = (const float *)job.tA;
-    const float *__restrict__ tBT = (const float *)job.tBT;
-    const uint32_t nhi = merge_children(job.browptr, job.bent, P4, NK, kmask, list, wsum);
-    // wave w copies half (w & 1) of FP32 panel w >> 1: four 1 KB copies
-    auto issue_hi = [&](uint32_t st) {
-        const uint32_t ent = list[st >> 1], k = ent & 0xFFFFu, m = ent >> 16;
-        const uint32_t need = pan < 4 ? (m >> (4 * pan)) & 0xFu : (m >> (pan - 4)) & 0x1111u;
-        if (need == 0u)
-            return;
-        const float *leaf = pan < 4
-                                ? tA + leaf_slot(job.slotA, lin_index(I0 + pan, k)) * (B * B)
-                                : tBT + leaf_slot(job.slotB, lin_index(k, J0 + (pan - 4))) * (B * B);
-        const float *src = leaf + (st & 1u) * P32 + part * (P32 / 2) + 4 * lane;
-        float *dst = ring32 + (st & 1u) * kWideStage32 + pan * P32 + part * (P32 / 2);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            __builtin_amdgcn_global_load_lds((global_void_t *)(src + 256 * i),
-                                             (lds_void_t *)(dst + 256 * i), 16, 0, 0);
-    };
-    const uint32_t T = 2 * nhi;
-    if (T > 0)
-        issue_hi(0);
-    for (uint32_t t = 0; t < T; ++t) {
-        __builtin_amdgcn_s_waitcnt(0x0F70);             // vmcnt(0)
-        __syncthreads();
-        if (t + 1 < T)
-            issue_hi(t + 1);
-        const uint32_t ent = list[t >> 1];
-        if ((ent >> (16 + bit)) & 1u) {
-            const float *buf = ring32 + (t & 1u) * kWideStage32;
-            panel_mfma32<B>(buf + r * P32, buf + (4 + c) * P32, acc, lane);
-        }
-    }
+    // ---- HIGH products ------------------------------------------------------------
+    wide_fp32_products(job, P4, I0, J0, NK, w, r, c, bit, lane, smem, kmask, list, wsum, acc);
     write_leaf32<B>(acc, (int64_t)(I0 + r) * B, (int64_t)(J0 + c) * B, job.n, job.C, lane);
+}
+
+// FP32 products on 4 x 4 blocks of 64 x 64 leaves (depth >= 2): the FP32
+// phase of the wide split kernel alone, so a staged panel feeds up to 4 leaf
+// products instead of 2.  Every leaf sums its products over k ascending, one
+// k-panel at a time, as in the 2 x 2 kernel: the same bits.
+__global__ __launch_bounds__(1024) void leaf_gemm_wide32(const GemmJobs jobs)
+{
+    constexpr int B = 64, MB = 2;
+    extern __shared__ float smem[];
+    uint32_t *kmask = (uint32_t *)((char *)smem + WideShape::kRing);
+    uint32_t *list = kmask + kMaxEnt;
+    uint32_t *wsum = list + kMaxEnt;
+    const GemmJob &job = jobs.job[job_of(jobs, blockIdx.x)];
+    const uint32_t P4 = xcd_block(blockIdx.x - job.block0, job.nblocks);
+    const uint32_t I0 = 4 * lin_row(P4), J0 = 4 * lin_col(P4);
+    // waves of one SIMD own the leaves (i, (i + s) mod 4), as in the split kernel
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int r = w >> 2, c = (r + (w & 3)) & 3;
+    if (job.skip_empty && job.browptr[4 * P4] == job.browptr[4 * P4 + 4])
+        return;                                          // none of the 4 children has products
+    floatx16 acc[MB][MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < MB; ++j)
+            acc[i][j] = floatx16{0};
+    wide_fp32_products(job, P4, I0, J0, job.nleaf, w, r, c, 4 * r + c, lane, smem, kmask, list,
+                       wsum, acc);
+    write_leaf32<B>(acc, (int64_t)(I0 + r) * B, (int64_t)(J0 + c) * B, job.n, job.C, lane);
+}
+
+static hipError_t launch_wide32(const GemmJobs &jobs, hipStream_t s)
+{
+    constexpr size_t lds = WideShape::kLds;
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void *)leaf_gemm_wide32,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess)
+        return attr;
+    hipLaunchKernelGGL(leaf_gemm_wide32, dim3(jobs.nblocks), dim3(64 * kWideWaves), lds, s, jobs);
+    return hipGetLastError();
 }
 
 // jobs.block0 / nblocks count 4 x 4 blocks here
@@ -1006,6 +1062,8 @@ hipError_t launch_gemm_jobs(int leaf, GemmKind kind, const GemmJobs &jobs, hipSt
         return leaf == 64 ? launch_sub(jobs, s) : hipErrorInvalidValue;
     case GemmKind::SplitWide:
         return leaf == 64 ? launch_split_wide(jobs, s) : hipErrorInvalidValue;
+    case GemmKind::Wide32:
+        return leaf == 64 ? launch_wide32(jobs, s) : hipErrorInvalidValue;
     case GemmKind::Split:
         switch (leaf) {
         case 32: return launch_split<32, false>(jobs, s);
@@ -1035,6 +1093,10 @@ GemmKind plan_kind(const spamm_plan *p)
         return GemmKind::Sub;
     if (p->precision == SPAMM_PREC_SPLIT_BF16 && p->leaf == 64 && p->depth >= 2)
         return GemmKind::SplitWide;
+    // FP32 at 64 x 64 leaves: 4 x 4 blocks (313.6 against 330.6 ms for 2 x 2
+    // at n = 32768, tau = 1e-8, bit-identical C)
+    if (p->precision == SPAMM_PREC_FP32 && p->leaf == 64 && p->depth >= 2)
+        return GemmKind::Wide32;
     return p->precision == SPAMM_PREC_SPLIT_FP16   ? GemmKind::SplitF16
            : p->precision == SPAMM_PREC_SPLIT_BF16 ? GemmKind::Split
                                                    : GemmKind::Fp32;
@@ -1052,8 +1114,10 @@ void plan_jobs(const spamm_plan *p, float *C, GemmJob &j)
     j.C = C;
     j.n = p->n;
     j.nleaf = 1u << p->depth;
-    // the wide split kernel's workgroups own 4 x 4 output leaves
-    j.nblocks = (uint32_t)p->nblocks / (plan_kind(p) == GemmKind::SplitWide ? 4u : 1u);
+    // the wide kernels' workgroups own 4 x 4 output leaves
+    const GemmKind kind = plan_kind(p);
+    j.nblocks = (uint32_t)p->nblocks /
+                (kind == GemmKind::SplitWide || kind == GemmKind::Wide32 ? 4u : 1u);
     j.block0 = 0;
     j.single = p->depth == 0 ? 1 : 0;
     j.skip_empty = 0;

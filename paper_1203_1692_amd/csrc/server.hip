@@ -337,11 +337,11 @@ bool launch_batches(spamm_server *S)
             (S->active[i].job.rq.leaf == leaf && (int)batch.size() < kMaxJobs ? batch : rest)
                 .push_back(i);
         ready.swap(rest);
-        // jobs of each kernel kind (FP32, BF16 split on 2 x 2 or 4 x 4 blocks,
-        // FP16 split) go to one launch
-        constexpr int kKinds = 4;
+        // jobs of each kernel kind (FP32 or BF16 split on 2 x 2 or 4 x 4
+        // blocks, FP16 split) go to one launch
+        constexpr int kKinds = 5;
         constexpr GemmKind kinds[kKinds] = {GemmKind::Fp32, GemmKind::Split, GemmKind::SplitF16,
-                                            GemmKind::SplitWide};
+                                            GemmKind::SplitWide, GemmKind::Wide32};
         GemmJobs tabs[kKinds] = {};
         hipError_t e = hipSuccess;
         for (size_t i : batch) {
