@@ -75,19 +75,23 @@ __device__ inline void load_entries(const uint32_t *__restrict__ bent, uint32_t 
 
 // Workgroups are dispatched round-robin over the 8 XCDs (bid mod 8).  Deal
 // the blocks out in chunks of 16 consecutive ones (linear-index order: a
-// 4 x 4 patch of blocks), chunk c to XCD c mod 8, each XCD taking its chunks
-// in order: neighbours share an XCD's L2, and every XCD samples the whole
-// matrix.  (Contiguous eighths of the linear index put the two off-diagonal
-// quadrants, where decaying products are few, on half of the XCDs: with
-// split precision the busiest XCD then held 1.2x its share of the LOW
-// products and 1.8x of the HIGH ones.)
+// 4 x 4 patch of blocks), one chunk of each group of 8 to every XCD, each
+// XCD taking its chunks in order: neighbours share an XCD's L2, and every
+// XCD samples the whole matrix.  The chunk an XCD takes from group g is
+// rotated by g: chunk c mod 8 is three bits of the linear index, and on the
+// diagonal (i = j) two of them are equal, so a fixed c mod 8 gave the
+// diagonal's heavy blocks to half of the XCDs (rotated: 305.5 against 314.8
+// ms for the FP32 product at n = 32768, tau = 1e-8).  (Contiguous eighths of
+// the linear index put the two off-diagonal quadrants, where decaying
+// products are few, on half of the XCDs: with split precision the busiest
+// XCD then held 1.2x its share of the LOW products and 1.8x of the HIGH ones.)
 __device__ inline uint32_t xcd_block(uint32_t bid, uint32_t nblocks)
 {
     constexpr uint32_t kChunk = 16;
     if (nblocks % (8u * kChunk) != 0u)
         return bid;
-    const uint32_t x = bid % 8u, s = bid / 8u;
-    return ((s / kChunk) * 8u + x) * kChunk + s % kChunk;
+    const uint32_t x = bid % 8u, s = bid / 8u, g = s / kChunk;
+    return (g * 8u + ((x + g) & 7u)) * kChunk + s % kChunk;
 }
 
 // Wave w copies panel p of operand leaf w (0: A_2I, 1: A_2I+1, 2: B_2J,
@@ -1094,7 +1098,8 @@ GemmKind plan_kind(const spamm_plan *p)
     if (p->precision == SPAMM_PREC_SPLIT_BF16 && p->leaf == 64 && p->depth >= 2)
         return GemmKind::SplitWide;
     // FP32 at 64 x 64 leaves: 4 x 4 blocks (313.6 against 330.6 ms for 2 x 2
-    // at n = 32768, tau = 1e-8, bit-identical C)
+    // at n = 32768, tau = 1e-8, bit-identical C, with the unrotated XCD
+    // mapping)
     if (p->precision == SPAMM_PREC_FP32 && p->leaf == 64 && p->depth >= 2)
         return GemmKind::Wide32;
     return p->precision == SPAMM_PREC_SPLIT_FP16   ? GemmKind::SplitF16
