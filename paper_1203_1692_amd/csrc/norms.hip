@@ -124,8 +124,10 @@ __device__ inline void store_fp16x4(uint16_t *dst, float4 v, int e)
 // is a.  So the butterfly skips lane bit 3, the register tree stops below m
 // bit 3, and the leaf norm is the parent of its four sub-blocks:
 // (s_00 + s_01) + (s_10 + s_11), written to sub_norm[4 l + 2a + b].
-// The body of one workgroup (block `bid` of the leaves' grid).
-template <int B, int VEC, bool SUB, bool TWO>
+// The body of one workgroup (block `bid` of the leaves' grid).  SKIP: leaves
+// may be known zero (keep flags) or dropped (drop_s); without it neither test
+// is compiled in (the dense build keeps its register budget).
+template <int B, int VEC, bool SUB, bool TWO, bool SKIP>
 __device__ inline void norm_pack_block(const float *__restrict__ A, int64_t n,
                                        float *__restrict__ tiles, float *__restrict__ tilesT,
                                        uint16_t *__restrict__ tiles16,
@@ -169,12 +171,22 @@ __device__ inline void norm_pack_block(const float *__restrict__ A, int64_t n,
     // passes no product test against a leaf of norm at most the larger root
     // (s = 0, or fl64(s m) < T2 with m = max(rootA, rootB)) can never be read,
     // so it is not packed (Sec. II.C)
-    const bool dropped = valid && drop_s != nullptr &&
-                         !(drop_s[l] > 0.0 && !(drop_s[l] * fmax(rootA[0], rootB[0]) < T2));
-    const bool zero = valid && ((known_zero && keep[l] == 0u) || dropped);
+    bool zero = false;
+    if constexpr (SKIP) {
+        const bool dropped =
+            valid && drop_s != nullptr &&
+            !(drop_s[l] > 0.0 && !(drop_s[l] * fmax(rootA[0], rootB[0]) < T2));
+        zero = valid && ((known_zero && keep[l] == 0u) || dropped);
+    }
     const bool pack = valid && tiles != nullptr && (keep == nullptr || keep[l] != 0u);
     const int64_t dl = pack && slot != nullptr ? (int64_t)slot[l] : (int64_t)l;
     float4 v[M];
+    if constexpr (SKIP) {
+        // defined on every path (a skipped leaf is never stored)
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            v[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     if (zero && lane == 0 && scale16 != nullptr)
         scale16[l] = 0;                   // the exponent of a zero leaf
     if (zero && lane == 0 && leaf_norm != nullptr) {
@@ -319,8 +331,10 @@ __device__ inline void norm_pack_block(const float *__restrict__ A, int64_t n,
     }
 }
 
-template <int B, int VEC, bool SUB, bool TWO>
-__global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ A, int64_t n,
+// (at least 3 waves per SIMD: the loads of a 64 x 64 leaf are 64 registers
+// a lane, and the build is an HBM stream that needs the waves in flight)
+template <int B, int VEC, bool SUB, bool TWO, bool SKIP>
+__global__ __launch_bounds__(256, 3) void leaf_norm_pack(const float *__restrict__ A, int64_t n,
                                                       float *__restrict__ tiles,
                                                       float *__restrict__ tilesT,
                                                       uint16_t *__restrict__ tiles16,
@@ -333,7 +347,8 @@ __global__ __launch_bounds__(256) void leaf_norm_pack(const float *__restrict__ 
                                                       int32_t *__restrict__ scale16,
                                                       uint32_t ntiles, int known_zero)
 {
-    norm_pack_block<B, VEC, SUB, TWO>(A, n, tiles, tilesT, tiles16, tilesT16, leaf_norm, parent,
+    norm_pack_block<B, VEC, SUB, TWO, SKIP>(A, n, tiles, tilesT, tiles16, tilesT16, leaf_norm,
+                                            parent,
                                       sub_norm, keep, slot, scale16, ntiles, known_zero,
                                       blockIdx.x);
 }
@@ -364,14 +379,22 @@ static hipError_t launch_leaf_t(const float *A, int64_t n, float *tiles, float *
 {
     constexpr size_t lds = sizeof(float) * 4 * (TWO ? B / 2 : B) * (B + 1);
     // once per process (thread-safe static initialization)
-    static const hipError_t attr =
-        hipFuncSetAttribute((const void *)leaf_norm_pack<B, VEC, SUB, TWO>,
+    static const hipError_t attr0 =
+        hipFuncSetAttribute((const void *)leaf_norm_pack<B, VEC, SUB, TWO, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (attr != hipSuccess)
-        return attr;
-    hipLaunchKernelGGL((leaf_norm_pack<B, VEC, SUB, TWO>), dim3((ntiles + 3) / 4), dim3(256), lds,
-                       s, A, n, tiles, tilesT, t16, tT16, leaf, parent, sub, keep, slot, scale16,
-                       ntiles, known_zero);
+    static const hipError_t attr1 =
+        hipFuncSetAttribute((const void *)leaf_norm_pack<B, VEC, SUB, TWO, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr0 != hipSuccess || attr1 != hipSuccess)
+        return attr0 != hipSuccess ? attr0 : attr1;
+    if (known_zero)
+        hipLaunchKernelGGL((leaf_norm_pack<B, VEC, SUB, TWO, true>), dim3((ntiles + 3) / 4),
+                           dim3(256), lds, s, A, n, tiles, tilesT, t16, tT16, leaf, parent, sub,
+                           keep, slot, scale16, ntiles, known_zero);
+    else
+        hipLaunchKernelGGL((leaf_norm_pack<B, VEC, SUB, TWO, false>), dim3((ntiles + 3) / 4),
+                           dim3(256), lds, s, A, n, tiles, tilesT, t16, tT16, leaf, parent, sub,
+                           keep, slot, scale16, ntiles, known_zero);
     return hipGetLastError();
 }
 
@@ -590,7 +613,7 @@ hipError_t launch_output_pack(const float *C, int64_t n, int leaf, int depth, fl
 // one per block, and the ones of a mostly-zero or mostly-dropped tree finish
 // at once.
 template <int B, int VEC, bool TWO, int CB>
-__global__ __launch_bounds__(256) void leaf_norm_pack_jobs(const Jobs<PackJob> jobs)
+__global__ __launch_bounds__(256, 3) void leaf_norm_pack_jobs(const Jobs<PackJob> jobs)
 {
     static_assert(4 * CB <= kWave, "one wave tests the chunk's leaves");
     const PackJob &p = job_at(jobs, blockIdx.x);
@@ -613,7 +636,7 @@ __global__ __launch_bounds__(256) void leaf_norm_pack_jobs(const Jobs<PackJob> j
     for (int i = 0; i < CB && b0 + i < nblk; ++i) {
         const uint32_t b = b0 + i;
         if ((m >> (4 * i)) & 0xFu) {
-            norm_pack_block<B, VEC, false, TWO>(p.A, p.n, p.tiles, p.tilesT, p.t16, p.tT16,
+            norm_pack_block<B, VEC, false, TWO, true>(p.A, p.n, p.tiles, p.tilesT, p.t16, p.tT16,
                                                 p.leafn, p.parent, nullptr, p.keep, nullptr,
                                                 p.scale16, p.ntiles, p.known_zero, b, p.drop_s,
                                                 p.rootA, p.rootB, p.T2);

@@ -81,6 +81,86 @@ hipError_t launch_sparse_pack(const float *A, int64_t n, int leaf, int depth, fl
                               float *tilesT, uint16_t *t16, uint16_t *tT16, const uint32_t *keep,
                               const uint32_t *slot, hipStream_t s);
 
+// ---- batched tree builds and culls of several products ----------------------
+// Tables of jobs passed by value to one launch; a workgroup finds its job by
+// block0 (ascending).  Used by the serving loop to build and cull the steps of
+// many requests in a few launches.
+constexpr int kMaxRound = 16;
+
+template <typename J>
+struct Jobs {
+    int32_t njobs;
+    uint32_t nblocks;      // total grid
+    J job[kMaxRound];
+};
+
+template <typename J>
+__device__ inline const J &job_at(const Jobs<J> &jobs, uint32_t bid)
+{
+    // independent tests (no chain of dependent loads)
+    int j = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxRound; ++i)
+        j += (i < jobs.njobs && bid >= jobs.job[i].block0) ? 1 : 0;
+    return jobs.job[j];
+}
+
+struct PackJob {           // leaf norms and packed copies of one tree
+    const float *A;
+    int64_t n;
+    float *tiles, *tilesT;
+    uint16_t *t16, *tT16;
+    int32_t *scale16;
+    double *leafn, *parent;
+    const uint32_t *keep;  // with known_zero: the leaves not kept are zero
+    uint32_t ntiles, block0;
+    int32_t known_zero;
+    // a pack after the norms: leaf norms, the two roots and tau^2 of the
+    // product the tree takes part in (leaves no product can keep are skipped)
+    const double *drop_s, *rootA, *rootB;
+    double T2;
+};
+
+struct KeepJob {           // output-leaf keep flags from a product's schedule
+    const uint32_t *browptr, *bent, *browptr_lo, *bent_lo;
+    uint32_t *keep;
+    uint32_t nblocks, nleaves, block0;
+};
+
+struct PyrJob {            // one workgroup per tree
+    double *norms;
+    int32_t top;
+    uint32_t block0;
+};
+
+struct TopJob {            // root and tiers 1..top, one workgroup per plan
+    const double *nA, *nB;
+    uint32_t *rowptr, *list0, *list1;
+    uint64_t *leafK;
+    double T2;
+    int32_t top;
+    uint32_t block0;
+};
+
+struct TierJob {           // one tier below the leaves of one plan
+    const double *tA, *tB;
+    const uint32_t *prow, *plist;
+    uint32_t *counts, *crow, *clist;
+    double T2;
+    uint32_t np, block0;
+};
+
+struct LeafJob {           // the leaf tier of one plan
+    const double *tA, *tB, *nA, *nB;
+    const uint32_t *prow, *plist;
+    uint32_t *counts, *browptr, *bent, *browptr_lo, *bent_lo;
+    uint64_t *leafK;
+    uint64_t *rout;        // 5 words: HIGH and LOW products, 0, the two roots
+    double T2, L2, theta2;
+    uint32_t np, block0;
+    int32_t split;
+};
+
 // ---- rounds: the tree builds and culls of several products in shared
 // launches (serving loop).  Trees and plans are set up on the host with
 // their buffers carved (tree_prepare, plan_prepare), then built and culled
