@@ -62,7 +62,7 @@ def kernel_source_digest() -> str:
 def gemm_kernel_name(precision: str, leaf: int, depth: int, sub: bool = False) -> str:
     """The leaf-GEMM kernel the library picks for a product (its plan's kind)."""
     if sub:
-        return "leaf_gemm_sub<64>"
+        return "leaf_gemm_sub_wide" if depth >= 2 else "leaf_gemm_sub<64>"
     if precision == "split-bf16":
         return ("leaf_gemm_split_wide" if leaf == 64 and depth >= 2
                 else f"leaf_gemm_split<{leaf}, false>")

@@ -990,6 +990,173 @@ __global__ __launch_bounds__(1024) void leaf_gemm_wide32(const GemmJobs jobs)
     write_leaf32<B>(acc, (int64_t)(I0 + r) * B, (int64_t)(J0 + c) * B, job.n, job.C, lane);
 }
 
+// Sub-leaf culling on 4 x 4 blocks of 64 x 64 leaves (depth >= 2): the
+// sub-products of the 2 x 2 kernel above, staged as in leaf_gemm_wide32.
+// First every child entry's kept sub-products are worked out (one byte per
+// leaf: bit 2 (2a + b) + c for sub-product (a, c, b)), exported to submask in
+// the 2 x 2 layout (one word per child entry) and scattered into a table by
+// (k, leaf of the block).  The stages are then the (k, k-panel) pairs some
+// leaf needs, in k and panel order; a stage copies only the operand panels
+// of the rows and columns whose leaves take it, and wave (r, c) runs, on
+// panel c', the accumulators (a, b) of its leaf with sub-product (a, c', b)
+// kept.  Each accumulator runs the same MFMAs in the same order as in the
+// 2 x 2 kernel: the same C.
+struct SubWideShape {
+    static constexpr size_t kRing = WideShape::kRing;                        // 2 x 64 KB
+    static constexpr size_t kMasks = 16 * (size_t)kMaxEnt;                   // byte per (k, leaf)
+    static constexpr size_t kList = sizeof(uint32_t) * 2 * kMaxEnt;          // k << 17 | c << 16 | takers
+    static constexpr size_t kLds = kRing + kMasks + kList + sizeof(uint32_t) * kWideWaves;
+};
+
+__global__ __launch_bounds__(1024) void leaf_gemm_sub_wide(const GemmJobs jobs)
+{
+    constexpr int B = 64, MB = 2;
+    constexpr int P32 = LeafLayout<B>::kPanel;
+    extern __shared__ float smem[];
+    float *ring32 = smem;
+    uint8_t *subm = (uint8_t *)((char *)smem + SubWideShape::kRing);
+    uint32_t *stl = (uint32_t *)((char *)subm + SubWideShape::kMasks);
+    uint32_t *wsum = stl + 2 * kMaxEnt;
+    const GemmJob &job = jobs.job[job_of(jobs, blockIdx.x)];
+    const uint32_t P4 = xcd_block(blockIdx.x - job.block0, job.nblocks);
+    const uint32_t I0 = 4 * lin_row(P4), J0 = 4 * lin_col(P4);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int r = w >> 2, c = (r + (w & 3)) & 3;
+    const int bit = 4 * r + c;
+    const uint32_t NK = job.nleaf;
+    const uint32_t *__restrict__ rp = job.browptr;
+    const uint32_t *__restrict__ bent = job.bent;
+    const uint32_t ea = rp[4 * P4], eb = rp[4 * P4 + 4];
+    if (job.skip_empty && ea == eb)
+        return;
+
+    // ---- kept sub-products of every child entry ----------------------------
+    for (uint32_t i = threadIdx.x; i < NK; i += blockDim.x)
+        reinterpret_cast<uint4 *>(subm)[i] = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
+    uint32_t subs = 0;
+    const uint32_t b1 = rp[4 * P4 + 1], b2 = rp[4 * P4 + 2], b3 = rp[4 * P4 + 3];
+    for (uint32_t e = ea + threadIdx.x; e < eb; e += blockDim.x) {
+        const uint32_t ch = (e >= b1 ? 1u : 0u) + (e >= b2 ? 1u : 0u) + (e >= b3 ? 1u : 0u);
+        const uint32_t ca = ch >> 1, cb = ch & 1u;          // child rows 2 ca.., columns 2 cb..
+        const uint32_t ent = bent[e], k = ent & 0xFFFFu;
+        uint32_t word = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            if (!((ent >> (16 + q)) & 1u))
+                continue;
+            const uint32_t lr = 2 * ca + (q >> 1), lc = 2 * cb + (q & 1u);
+            const double *sa = job.subA + 4 * (int64_t)lin_index(I0 + lr, k);
+            const double *sb = job.subB + 4 * (int64_t)lin_index(k, J0 + lc);
+            uint32_t m = 0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int cc = 0; cc < 2; ++cc)
+                        m |= keep_pair(sa[2 * a + cc], sb[2 * cc + b], job.T2)
+                                 ? 1u << (2 * (2 * a + b) + cc) : 0u;
+            subm[16 * k + 4 * lr + lc] = (uint8_t)m;
+            word |= m << (8 * q);
+            subs += __builtin_popcount(m);
+        }
+        *reinterpret_cast<uint32_t *>(job.submask + 4 * (int64_t)e) = word;
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        subs += __shfl_xor(subs, o);
+    if (lane == 0 && subs != 0)
+        atomicAdd(job.subK, (unsigned long long)subs);
+    __syncthreads();
+
+    // ---- the stages: (k, panel) pairs some leaf takes, in order ---------------
+    // takers: bit 4 r' + c' when leaf (r', c') keeps a sub-product on the panel
+    uint32_t T = 0;
+    for (uint32_t r0 = 0; r0 < 2 * NK; r0 += blockDim.x) {
+        const uint32_t idx = r0 + threadIdx.x;
+        uint32_t tk = 0;
+        if (idx < 2 * NK) {
+            const uint32_t k = idx >> 1, cp = idx & 1u;
+            const uint4 v = reinterpret_cast<const uint4 *>(subm)[k];
+            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                tk |= (((wv[j >> 2] >> (8 * (j & 3))) & (0x55u << cp)) != 0u ? 1u : 0u) << j;
+        }
+        const uint64_t bal = __ballot(tk != 0u);
+        if (lane == 0)
+            wsum[w] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (int i = 0; i < kWideWaves; ++i) {
+            const uint32_t x = wsum[i];
+            before += i < w ? x : 0u;
+            total += x;
+        }
+        if (tk != 0u)
+            stl[T + before + (uint32_t)__popcll(bal & lanes_below())] = (idx << 16) | tk;
+        T += total;
+        __syncthreads();                       // wsum is rewritten next round
+    }
+
+    // ---- staged sub-products: FP32 k-panels, 64 KB stages, 2-deep ring ---------
+    const float *__restrict__ tA = (const float *)job.tA;
+    const float *__restrict__ tBT = (const float *)job.tBT;
+    const int pan = w >> 1, part = w & 1;
+    auto issue = [&](uint32_t st) {
+        const uint32_t x = stl[st], k = x >> 17, cp = (x >> 16) & 1u, tk = x & 0xFFFFu;
+        const uint32_t need = pan < 4 ? (tk >> (4 * pan)) & 0xFu : (tk >> (pan - 4)) & 0x1111u;
+        if (need == 0u)
+            return;
+        const float *leaf = pan < 4
+                                ? tA + leaf_slot(job.slotA, lin_index(I0 + pan, k)) * (B * B)
+                                : tBT + leaf_slot(job.slotB, lin_index(k, J0 + (pan - 4))) * (B * B);
+        const float *src = leaf + cp * P32 + part * (P32 / 2) + 4 * lane;
+        float *dst = ring32 + (st & 1u) * kWideStage32 + pan * P32 + part * (P32 / 2);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            __builtin_amdgcn_global_load_lds((global_void_t *)(src + 256 * i),
+                                             (lds_void_t *)(dst + 256 * i), 16, 0, 0);
+    };
+    floatx16 acc[MB][MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < MB; ++j)
+            acc[i][j] = floatx16{0};
+    if (T > 0)
+        issue(0);
+    for (uint32_t t = 0; t < T; ++t) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);             // vmcnt(0)
+        __syncthreads();
+        if (t + 1 < T)
+            issue(t + 1);
+        const uint32_t x = stl[t], k = x >> 17, cp = (x >> 16) & 1u;
+        const uint32_t sm = subm[16 * k + bit];
+        // accumulator (a, b) on panel cp: sub-product bit 2 (2a + b) + cp
+        const uint32_t pm = ((sm >> cp) & 1u) | ((sm >> (1 + cp)) & 2u) |
+                            ((sm >> (2 + cp)) & 4u) | ((sm >> (3 + cp)) & 8u);
+        if (pm != 0u) {
+            const float *buf = ring32 + (t & 1u) * kWideStage32;
+            panel_mfma32_sub<B>(buf + r * P32, buf + (4 + c) * P32, acc, lane, pm);
+        }
+    }
+    write_leaf32<B>(acc, (int64_t)(I0 + r) * B, (int64_t)(J0 + c) * B, job.n, job.C, lane);
+}
+
+static hipError_t launch_sub_wide(const GemmJobs &jobs, hipStream_t s)
+{
+    constexpr size_t lds = SubWideShape::kLds;
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void *)leaf_gemm_sub_wide,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess)
+        return attr;
+    hipLaunchKernelGGL(leaf_gemm_sub_wide, dim3(jobs.nblocks), dim3(64 * kWideWaves), lds, s,
+                       jobs);
+    return hipGetLastError();
+}
+
 static hipError_t launch_wide32(const GemmJobs &jobs, hipStream_t s)
 {
     constexpr size_t lds = WideShape::kLds;
@@ -1068,6 +1235,8 @@ hipError_t launch_gemm_jobs(int leaf, GemmKind kind, const GemmJobs &jobs, hipSt
         return leaf == 64 ? launch_split_wide(jobs, s) : hipErrorInvalidValue;
     case GemmKind::Wide32:
         return leaf == 64 ? launch_wide32(jobs, s) : hipErrorInvalidValue;
+    case GemmKind::SubWide:
+        return leaf == 64 ? launch_sub_wide(jobs, s) : hipErrorInvalidValue;
     case GemmKind::Split:
         switch (leaf) {
         case 32: return launch_split<32, false>(jobs, s);
@@ -1093,8 +1262,10 @@ hipError_t launch_gemm_jobs(int leaf, GemmKind kind, const GemmJobs &jobs, hipSt
 
 GemmKind plan_kind(const spamm_plan *p)
 {
+    // sub-leaf culling at 64 x 64 leaves: 4 x 4 blocks from depth 2 (258.5
+    // against 279.0 ms for 2 x 2 at n = 32768, tau = 1e-8, the same C)
     if (p->sub)
-        return GemmKind::Sub;
+        return p->depth >= 2 ? GemmKind::SubWide : GemmKind::Sub;
     if (p->precision == SPAMM_PREC_SPLIT_BF16 && p->leaf == 64 && p->depth >= 2)
         return GemmKind::SplitWide;
     // FP32 at 64 x 64 leaves: 4 x 4 blocks (313.6 against 330.6 ms for 2 x 2
@@ -1121,8 +1292,10 @@ void plan_jobs(const spamm_plan *p, float *C, GemmJob &j)
     j.nleaf = 1u << p->depth;
     // the wide kernels' workgroups own 4 x 4 output leaves
     const GemmKind kind = plan_kind(p);
-    j.nblocks = (uint32_t)p->nblocks /
-                (kind == GemmKind::SplitWide || kind == GemmKind::Wide32 ? 4u : 1u);
+    j.nblocks = (uint32_t)p->nblocks / (kind == GemmKind::SplitWide || kind == GemmKind::Wide32 ||
+                                                kind == GemmKind::SubWide
+                                            ? 4u
+                                            : 1u);
     j.block0 = 0;
     j.single = p->depth == 0 ? 1 : 0;
     j.skip_empty = 0;
