@@ -487,8 +487,9 @@ __device__ inline int64_t rowptr_offset(int t) { return tier_offset(t) + t; }
 
 // The root and tiers 1..top in one workgroup (top <= kTopTiers): the small
 // upper tiers cost one launch instead of three each.  Same count -> scan ->
-// emit per tier as the per-tier kernels (same per-wave code), so the lists
-// are identical; barriers separate the phases.  Everything the tiers read
+// emit per tier as the per-tier kernels (the same tests, and the same order
+// with four parents per wave), so the lists are identical; barriers separate
+// the phases.  Everything the tiers read
 // stays in LDS: both pyramids' tiers 1..top, the row pointers, the lists of
 // tiers below `top` and the counts, so a tier costs LDS round trips rather
 // than dependent global loads.  The row pointers of every tier (the plan's
@@ -508,6 +509,68 @@ constexpr int kTopRows = top_row_offset(kTopTiers + 1);
 constexpr int kTopListEven = 1 << (3 * (kTopTiers - 1));
 constexpr int kTopListOdd = 1 << (3 * (kTopTiers - 2));
 static_assert(kTopTiers % 2 == 1, "tier kTopTiers - 1 is even");
+
+// The top tiers' parents (tiers 0..4) hold at most 16 values of k, so a wave
+// takes four parents at once, one per group of 16 lanes; counts and write
+// positions come from the group's bits of each ballot, in the same order as
+// the one-parent-per-wave code (parent k ascending, then c).
+static_assert(kTopTiers <= 5, "a top-tier parent list fits 16 lanes");
+
+__device__ inline void count_tile16(const double *__restrict__ nA, const double *__restrict__ nB,
+                                    double T2, const uint32_t *__restrict__ prow,
+                                    const uint32_t *__restrict__ plist, uint32_t P, bool active,
+                                    uint32_t *__restrict__ counts, int lane)
+{
+    const int gl = lane & 15;
+    const uint64_t gmask = 0xFFFFull << (lane & 48);
+    uint32_t f = 0;
+    if (active) {
+        const uint32_t beg = prow[P], end = prow[P + 1];
+        if (beg + gl < end)
+            f = child_flags(nA, nB, T2, lin_row(P), plist[beg + gl], lin_col(P));
+    }
+    uint32_t tot[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        tot[q] = __popcll(__ballot((f >> (2 * q)) & 1u) & gmask) +
+                 __popcll(__ballot((f >> (2 * q + 1)) & 1u) & gmask);
+    if (active && gl == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            counts[4 * P + q] = tot[q];
+    }
+}
+
+__device__ inline void emit_tile16(const double *__restrict__ nA, const double *__restrict__ nB,
+                                   double T2, const uint32_t *__restrict__ prow,
+                                   const uint32_t *__restrict__ plist, uint32_t P, bool active,
+                                   const uint32_t *__restrict__ crow, uint32_t *__restrict__ clist,
+                                   int lane)
+{
+    const int gl = lane & 15;
+    const uint64_t gmask = 0xFFFFull << (lane & 48);
+    const uint64_t below = lanes_below() & gmask;
+    uint32_t f = 0, kp = 0;
+    if (active) {
+        const uint32_t beg = prow[P], end = prow[P + 1];
+        if (beg + gl < end) {
+            kp = plist[beg + gl];
+            f = child_flags(nA, nB, T2, lin_row(P), kp, lin_col(P));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t f0 = (f >> (2 * q)) & 1u, f1 = (f >> (2 * q + 1)) & 1u;
+        const uint64_t b0 = __ballot(f0), b1 = __ballot(f1);
+        if (f0 | f1) {
+            const uint32_t pos = crow[4 * P + q] + __popcll(b0 & below) + __popcll(b1 & below);
+            if (f0)
+                clist[pos] = 2 * kp;
+            if (f1)
+                clist[pos + f0] = 2 * kp + 1;
+        }
+    }
+}
 
 __device__ inline void top_tiers(const double *__restrict__ nA, const double *__restrict__ nB,
                                  double T2, uint32_t *__restrict__ rowptr,
@@ -549,8 +612,9 @@ __device__ inline void top_tiers(const double *__restrict__ nA, const double *__
         const uint32_t *prow = sRow + top_row_offset(t - 1);
         uint32_t *crow = sRow + top_row_offset(t);
         const uint32_t *plist = (t - 1) & 1 ? sList1 : sList0;
-        for (uint32_t P = w; P < np; P += NW)
-            count_tile(tA, tB, T2, prow, plist, P, sCnt, lane);
+        for (uint32_t P0 = 4 * w; P0 < np; P0 += 4 * NW)
+            count_tile16(tA, tB, T2, prow, plist, P0 + (lane >> 4), P0 + (lane >> 4) < np, sCnt,
+                         lane);
         __syncthreads();
         // exclusive scan of the counts (4 np <= kScanChunk: one pass) into
         // crow, crow[4 np] = total, in LDS and in the plan's row pointers
@@ -580,8 +644,9 @@ __device__ inline void top_tiers(const double *__restrict__ nA, const double *__
         __syncthreads();
         // the top tier's list goes to the plan (the next tier reads it)
         uint32_t *clist = t == top ? (t & 1 ? list1 : list0) : (t & 1 ? sList1 : sList0);
-        for (uint32_t P = w; P < np; P += NW)
-            emit_tile(tA, tB, T2, prow, plist, P, crow, clist, lane);
+        for (uint32_t P0 = 4 * w; P0 < np; P0 += 4 * NW)
+            emit_tile16(tA, tB, T2, prow, plist, P0 + (lane >> 4), P0 + (lane >> 4) < np, crow,
+                        clist, lane);
         __syncthreads();
     }
 }
@@ -750,17 +815,64 @@ __global__ __launch_bounds__(256) void cull_count_leaf_jobs(const Jobs<LeafJob> 
                                threadIdx.x & 63);
 }
 
-// One workgroup per plan (np <= 4 kScanChunk): block row pointers of both
-// classes, the kept leaf products into leafK, and the plan's readback words.
+// One workgroup per plan: block row pointers of both classes, the kept leaf
+// products into leafK, and the plan's readback words, in one pass over the
+// four count arrays (every chunk's loads in flight together, where separate
+// scans and sums would each wait for their own).
 __global__ __launch_bounds__(kScanThreads) void leaf_totals_jobs(const Jobs<LeafJob> jobs)
 {
     const LeafJob &j = jobs.job[blockIdx.x];
-    block_exclusive_scan(j.counts, j.np, j.browptr);
-    const uint64_t hi = block_sum(j.counts + j.np, j.np);
-    uint64_t lo = 0;
-    if (j.split) {
-        block_exclusive_scan(j.counts + 2 * (size_t)j.np, j.np, j.browptr_lo);
-        lo = block_sum(j.counts + 3 * (size_t)j.np, j.np);
+    __shared__ uint64_t tsum[kScanThreads / kWave][2];
+    const uint32_t np = j.np;
+    const uint32_t *ch = j.counts, *cth = j.counts + np;
+    const uint32_t *cl = j.counts + 2 * (size_t)np, *ctl = j.counts + 3 * (size_t)np;
+    uint32_t carry_h = 0, carry_l = 0;
+    uint64_t task_h = 0, task_l = 0;
+    for (uint32_t c0 = 0; c0 < np; c0 += kScanChunk) {
+        const uint32_t base = c0 + threadIdx.x * kScanItems;
+        uint32_t vh[kScanItems], vl[kScanItems];
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const bool in = base + i < np;
+            vh[i] = in ? ch[base + i] : 0u;
+            vl[i] = in && j.split ? cl[base + i] : 0u;
+            task_h += in ? cth[base + i] : 0u;
+            task_l += in && j.split ? ctl[base + i] : 0u;
+        }
+        uint32_t th, tl;
+        uint32_t ph = block_scan4(vh, &th) + carry_h;
+        uint32_t pl = block_scan4(vl, &tl) + carry_l;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if (base + i < np) {
+                j.browptr[base + i] = ph;
+                if (j.split)
+                    j.browptr_lo[base + i] = pl;
+            }
+            ph += vh[i];
+            pl += vl[i];
+        }
+        carry_h += th;
+        carry_l += tl;
+    }
+    if (threadIdx.x == 0) {
+        j.browptr[np] = carry_h;
+        if (j.split)
+            j.browptr_lo[np] = carry_l;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        task_h += __shfl_xor(task_h, o);
+        task_l += __shfl_xor(task_l, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        tsum[threadIdx.x >> 6][0] = task_h;
+        tsum[threadIdx.x >> 6][1] = task_l;
+    }
+    __syncthreads();
+    uint64_t hi = 0, lo = 0;
+    for (int i = 0; i < kScanThreads / kWave; ++i) {
+        hi += tsum[i][0];
+        lo += tsum[i][1];
     }
     if (threadIdx.x == 0) {
         j.leafK[0] = hi;

@@ -10,6 +10,7 @@
 // (bits 0-1 of e), a six-step xor butterfly over lanes (bits 2-7) and an
 // in-register tree over m (bits 8 and up).  Squares of FP32 values are exact
 // in FP64, so only the additions round and their order is fixed.
+#include <algorithm>
 #include <vector>
 
 #include "runtime.hpp"
@@ -606,22 +607,24 @@ hipError_t launch_output_pack(const float *C, int64_t n, int leaf, int depth, fl
 }
 
 // ---- rounds: the builds of several trees in shared launches ---------------
-// A workgroup takes CB consecutive blocks (4 leaves each) of one tree.  The
-// first wave finds which of them hold a leaf to read (neither known zero nor
-// dropped); the workgroup then runs the blocks that do, and a block that
-// does not only gets its zero norms (norm pass).  Far fewer workgroups than
-// one per block, and the ones of a mostly-zero or mostly-dropped tree finish
-// at once.
+// A workgroup takes cb <= CB consecutive blocks (4 leaves each) of one tree
+// (cb grows with the tree, so a small tree's blocks run side by side and a
+// large one needs fewer workgroups).  The first wave finds which of them
+// hold a leaf to read (neither known zero nor dropped); the workgroup then
+// runs the blocks that do, and a block that does not only gets its zero
+// norms (norm pass), so the workgroups of a mostly-zero or mostly-dropped
+// tree finish at once.
 template <int B, int VEC, bool TWO, int CB>
 __global__ __launch_bounds__(256, 3) void leaf_norm_pack_jobs(const Jobs<PackJob> jobs)
 {
     static_assert(4 * CB <= kWave, "one wave tests the chunk's leaves");
     const PackJob &p = job_at(jobs, blockIdx.x);
-    const uint32_t b0 = (blockIdx.x - p.block0) * CB;
+    const uint32_t cb = p.cb;
+    const uint32_t b0 = (blockIdx.x - p.block0) * cb;
     __shared__ uint64_t live;
     if (threadIdx.x < kWave) {
         const uint32_t l = 4 * b0 + threadIdx.x;
-        bool act = threadIdx.x < 4 * CB && l < p.ntiles;
+        bool act = threadIdx.x < 4 * cb && l < p.ntiles;
         if (act && p.known_zero && p.keep[l] == 0u)
             act = false;
         if (act && p.drop_s != nullptr)
@@ -633,7 +636,7 @@ __global__ __launch_bounds__(256, 3) void leaf_norm_pack_jobs(const Jobs<PackJob
     __syncthreads();
     const uint64_t m = live;
     const uint32_t nblk = (p.ntiles + 3) / 4;
-    for (int i = 0; i < CB && b0 + i < nblk; ++i) {
+    for (uint32_t i = 0; i < cb && b0 + i < nblk; ++i) {
         const uint32_t b = b0 + i;
         if ((m >> (4 * i)) & 0xFu) {
             norm_pack_block<B, VEC, false, TWO, true>(p.A, p.n, p.tiles, p.tilesT, p.t16, p.tT16,
@@ -664,8 +667,10 @@ __global__ __launch_bounds__(256) void output_keep_jobs(const Jobs<KeepJob> jobs
                   (blockIdx.x - k.block0) * blockDim.x + threadIdx.x);
 }
 
-// blocks per workgroup of the round pack kernel
+// most blocks per workgroup of the round pack kernel, and the grid a tree's
+// blocks are spread over before a workgroup takes more than one
 constexpr int kPackChunk = 8;
+constexpr uint32_t kPackSpread = 2048;
 
 template <int B, int VEC>
 static hipError_t launch_pack_jobs(const Jobs<PackJob> &jobs, hipStream_t s)
@@ -757,8 +762,10 @@ hipError_t launch_build_round(const RoundTree *trees, int ntrees, hipStream_t s)
                 p.A = trees[k].src;
                 p.n = t->n;
                 p.ntiles = 1u << (2 * d);
+                const uint32_t nblk = (p.ntiles + 3) / 4;
+                p.cb = std::min<uint32_t>(kPackChunk, (nblk + kPackSpread - 1) / kPackSpread);
                 p.block0 = pj.nblocks;
-                pj.nblocks += ((p.ntiles + 3) / 4 + kPackChunk - 1) / kPackChunk;
+                pj.nblocks += (nblk + p.cb - 1) / p.cb;
                 if (pass == 1) {
                     p.leafn = t->norms + tier_offset(d);
                     p.parent = d >= 1 ? t->norms + tier_offset(d - 1) : nullptr;

@@ -114,6 +114,7 @@ struct PackJob {           // leaf norms and packed copies of one tree
     double *leafn, *parent;
     const uint32_t *keep;  // with known_zero: the leaves not kept are zero
     uint32_t ntiles, block0;
+    uint32_t cb;           // blocks of 4 leaves per workgroup (1 .. kPackChunk)
     int32_t known_zero;
     // a pack after the norms: leaf norms, the two roots and tau^2 of the
     // product the tree takes part in (leaves no product can keep are skipped)
