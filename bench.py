@@ -88,16 +88,18 @@ def measured_split_traffic(workload: str, tau: float, theta: float, fmt: str = "
     """HBM bytes per launch of the split kernel (LOW operands in `fmt`) at
     (tau, theta) from the committed counter runs, or None when absent or the
     kernel sources changed since."""
+    import glob
     kind = "leaf_gemm_split" if fmt == "bf16" else "leaf_gemm_split_fp16"
-    path = os.path.join(ROOT, "profiles", f"{kind}_{workload}_traffic.json")
-    if not os.path.exists(path):
-        return None
-    t = json.load(open(path))
-    if (t.get("gemm_sources_sha256") != kernel_source_digest() or
-            abs(t.get("tau", -1.0) - tau) > 1e-12 * tau or
-            abs(t.get("theta", -1.0) - theta) > 1e-12 * theta):
-        return None
-    return t["bytes_per_launch"]
+    # one record per measured (tau, theta): <kind>_<workload>[_<point>]_traffic.json
+    digest = kernel_source_digest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles",
+                                              f"{kind}_{workload}*_traffic.json"))):
+        t = json.load(open(path))
+        if (t.get("gemm_sources_sha256") == digest and
+                abs(t.get("tau", -1.0) - tau) <= 1e-12 * tau and
+                abs(t.get("theta", -1.0) - theta) <= 1e-12 * theta):
+            return t["bytes_per_launch"]
+    return None
 
 
 def measured_sub_traffic(workload: str, tau: float):

@@ -49,16 +49,25 @@ def test_source_digest_covers_the_kernel_and_its_build_flags():
 
 
 def test_committed_split_traffic_records_name_their_point():
+    import glob
     for kind, fmt in (("leaf_gemm_split", "bf16"), ("leaf_gemm_split_fp16", "fp16")):
-        path = os.path.join(ROOT, "profiles", f"{kind}_cluster1310-n32750_traffic.json")
-        rec = json.load(open(path))
-        assert rec["tau"] > 0 and rec["theta"] > 0 and rec["bytes_per_launch"] > 0
-        assert rec["workload"] == "cluster1310-n32750"
-        # another point, or other kernel sources, never reuse the record
-        assert bench.measured_split_traffic("cluster1310-n32750", rec["tau"] * 10,
-                                            rec["theta"], fmt) is None
-        assert bench.measured_split_traffic("cluster1310-n32750", rec["tau"],
-                                            rec["theta"] * 2, fmt) is None
+        paths = sorted(glob.glob(os.path.join(
+            ROOT, "profiles", f"{kind}_cluster1310-n32750*_traffic.json")))
+        assert paths
+        points = set()
+        for path in paths:
+            rec = json.load(open(path))
+            assert rec["tau"] > 0 and rec["theta"] > 0 and rec["bytes_per_launch"] > 0
+            assert rec["workload"] == "cluster1310-n32750"
+            assert (rec["tau"], rec["theta"]) not in points
+            points.add((rec["tau"], rec["theta"]))
+        for tau, theta in points:
+            # another point, or other kernel sources, never reuse a record
+            if (tau * 10, theta) not in points:
+                assert bench.measured_split_traffic("cluster1310-n32750", tau * 10,
+                                                    theta, fmt) is None
+            assert bench.measured_split_traffic("cluster1310-n32750", tau,
+                                                theta * 2, fmt) is None
 
 
 def test_sample_tiles_distinct_sorted_in_range():
