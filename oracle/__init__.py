@@ -75,6 +75,9 @@ def _load():
         lib.oracle_spamm_tiles_split_rel.argtypes = [vp, vp, i64, i32, dbl, dbl, ctypes.c_int, vp,
                                                      i64, vp, vp, vp, ctypes.c_int]
         lib.oracle_spamm_tiles_split_rel.restype = ctypes.c_int
+        lib.oracle_bf16_parts.argtypes = [ctypes.c_float, ctypes.POINTER(dbl),
+                                          ctypes.POINTER(dbl)]
+        lib.oracle_bf16_parts.restype = None
         lib.oracle_fp16_exponent.argtypes = [dbl]
         lib.oracle_fp16_exponent.restype = ctypes.c_int
         lib.oracle_fp16_scaled.argtypes = [ctypes.c_float, ctypes.c_int]
@@ -130,6 +133,13 @@ def bf16(x: float) -> float:
     return float(_load().oracle_bf16(x))
 
 
+def bf16_parts(x: float):
+    """(hi, lo) of x (a float32): hi = bf16(x), lo = bf16(x - hi)."""
+    hi, lo = ctypes.c_double(), ctypes.c_double()
+    _load().oracle_bf16_parts(ctypes.c_float(x), ctypes.byref(hi), ctypes.byref(lo))
+    return hi.value, lo.value
+
+
 def fp16_exponent(S: float) -> int:
     """Scale exponent e of a leaf with squared norm S for binary16 LOW
     operands: every entry of the leaf has |x| 2^e < 2^14 (0 when S = 0)."""
@@ -142,7 +152,9 @@ def fp16_scaled(x: float, e: int) -> float:
     return float(_load().oracle_fp16_scaled(x, int(e)))
 
 
-LOW_FMT = {"bf16": 0, "fp16": 1}
+# LOW operand format; "bf16x3": bfloat16 LOW operands and compensated HIGH
+# products (hi_a hi_b + hi_a lo_b + lo_a hi_b of the two bfloat16 parts)
+LOW_FMT = {"bf16": 0, "fp16": 1, "bf16x3": 2}
 
 
 class Result:
@@ -172,7 +184,8 @@ def spamm(A: np.ndarray, B: np.ndarray, b: int, tau: float, want_C: bool = True,
     the norm product is below low_tol) or low_rel > 0 (relative: below
     low_rel ||A||_F ||B||_F) selects split precision (LOW products on
     operands rounded to bfloat16, or with low_fmt="fp16" to binary16 at each
-    leaf's power-of-two scale)."""
+    leaf's power-of-two scale; low_fmt="bf16x3" also takes every HIGH
+    product from the two bfloat16 parts of its operands, dropping lo lo)."""
     fmt = LOW_FMT[low_fmt]
     kind, thr = _split_args(low_tol, low_rel)
     fn = getattr(_load(), f"oracle_spamm_split_{kind}")

@@ -42,6 +42,14 @@
  * squared norm before the rounding (11 significant bits; a value that rounds
  * below binary16's normal range, 2^-14, becomes zero), and the product is
  * scaled back by 2^-(eA + eB).
+ *
+ * Compensated HIGH products (format 2): LOW operands rounded to bfloat16 as
+ * above, and each entry x of a HIGH product split into two bfloat16 parts,
+ * hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact in single precision),
+ * with the product a b taken as hi_a hi_b + hi_a lo_b + lo_a hi_b: the
+ * three-product bfloat16 method of Henry, Tang and Heinecke ("Leveraging the
+ * bfloat16 artificial intelligence datatype for higher-precision
+ * computations", ARITH 2019), which drops lo_a lo_b and the parts below lo.
  */
 #include <math.h>
 #include <stdint.h>
@@ -168,7 +176,8 @@ typedef struct {
     int64_t cap, nkeys;
     int64_t *Kt;           /* kept count per tier, d+1 entries */
     int64_t Klow;          /* kept leaf products classed LOW */
-    int fmt;               /* LOW operands: 0 bfloat16, 1 binary16 with a leaf scale */
+    int fmt;               /* LOW operands: 0 bfloat16, 1 binary16 with a leaf scale,
+                              2 bfloat16 with compensated HIGH products */
 } mul_ctx;
 
 static int kept(const mul_ctx *x, int t, int64_t I, int64_t K, int64_t J)
@@ -200,6 +209,18 @@ static double to_bf16(float x)
 }
 
 double oracle_bf16(float x) { return to_bf16(x); }
+
+/* The two bfloat16 parts of x: hi = bf16(x), lo = bf16(x - hi).  hi keeps
+ * the top 8 significant bits of x (rounded), so x - hi is a multiple of x's
+ * single-precision spacing below 2^-8 |x| and is exact as a float. */
+static void bf16_parts(float x, double *hi, double *lo)
+{
+    *hi = to_bf16(x);
+    float r = x - (float)*hi;
+    *lo = to_bf16(r);
+}
+
+void oracle_bf16_parts(float x, double *hi, double *lo) { bf16_parts(x, hi, lo); }
 
 /* Scale exponent of a leaf whose squared norm is S, for binary16 operands:
  * with S = m 2^p (0.5 <= m < 1) every entry has |x| <= sqrt(S) < 2^q,
@@ -252,7 +273,19 @@ static double elem_p(const float *A, int64_t n, int64_t r, int64_t c, int low, i
         return 0.0;
     if (!low)
         return (double)A[r * n + c];
-    return fmt ? oracle_fp16_scaled(A[r * n + c], e) : to_bf16(A[r * n + c]);
+    return fmt == 1 ? oracle_fp16_scaled(A[r * n + c], e) : to_bf16(A[r * n + c]);
+}
+
+/* a b of a HIGH product in format 2: hi_a hi_b + hi_a lo_b + lo_a hi_b. */
+static double comp_product(const float *A, const float *B, int64_t n, int64_t r, int64_t l,
+                           int64_t c)
+{
+    if (r >= n || l >= n || c >= n)
+        return 0.0;
+    double ha, la, hb, lb;
+    bf16_parts(A[r * n + l], &ha, &la);
+    bf16_parts(B[l * n + c], &hb, &lb);
+    return ha * hb + ha * lb + la * hb;
 }
 
 /* C_IJ += A_IK * B_KJ over the n x n (unpadded) part, l ascending; operands
@@ -263,7 +296,7 @@ static void leaf_product(mul_ctx *x, int64_t I, int64_t K, int64_t J, double *Ct
     int64_t b = x->b, n = x->n;
     int64_t Nd = (int64_t)1 << x->d;
     int eA = 0, eB = 0;
-    if (low && x->fmt) {
+    if (low && x->fmt == 1) {
         eA = oracle_fp16_exponent(x->sA[tier_offset(x->d) + I * Nd + K]);
         eB = oracle_fp16_exponent(x->sB[tier_offset(x->d) + K * Nd + J]);
     }
@@ -276,9 +309,14 @@ static void leaf_product(mul_ctx *x, int64_t I, int64_t K, int64_t J, double *Ct
             if (col >= n)
                 break;
             double acc = 0.0;
-            for (int64_t l = 0; l < b; ++l)
-                acc += elem_p(x->A, n, row, K * b + l, low, x->fmt, eA) *
-                       elem_p(x->B, n, K * b + l, col, low, x->fmt, eB);
+            if (!low && x->fmt == 2) {
+                for (int64_t l = 0; l < b; ++l)
+                    acc += comp_product(x->A, x->B, n, row, K * b + l, col);
+            } else {
+                for (int64_t l = 0; l < b; ++l)
+                    acc += elem_p(x->A, n, row, K * b + l, low, x->fmt, eA) *
+                           elem_p(x->B, n, K * b + l, col, low, x->fmt, eB);
+            }
             Ct[(row - r0) * ldc + (col - c0)] += acc;
         }
     }
@@ -391,7 +429,7 @@ static double low_threshold(double low_tol, double theta, const double *sA, cons
 
 static int check_split(double low_tol, double theta, int fmt)
 {
-    if (!(low_tol >= 0.0) || isinf(low_tol) || (fmt != 0 && fmt != 1))
+    if (!(low_tol >= 0.0) || isinf(low_tol) || fmt < 0 || fmt > 2)
         return OR_EINVAL;
     if (!(theta >= 0.0) || isinf(theta) || (theta > 0.0 && low_tol > 0.0))
         return OR_EINVAL;
