@@ -46,6 +46,8 @@ extern "C" {
 #define SPAMM_PREC_FP32        0   /* every kept product in FP32 (MFMA, FP32 accumulation) */
 #define SPAMM_PREC_SPLIT_BF16  1   /* LOW products on BF16 operands, HIGH ones in FP32      */
 #define SPAMM_PREC_SPLIT_FP16  2   /* LOW products on scaled FP16 operands, HIGH ones FP32  */
+#define SPAMM_PREC_SPLIT_BF16X3 3  /* LOW products on BF16 operands, HIGH ones compensated: */
+                                   /* three BF16 products of the entries' two BF16 parts   */
 
 /* Tree build flags. */
 #define SPAMM_TREE_BF16        1u  /* also keep BF16 copies of the leaves (split precision) */
@@ -101,7 +103,19 @@ int spamm_build_tree(const float *A, int64_t n, int32_t leaf, void *stream,
 /*
  * Options of a product.
  *   tau        SpAMM tolerance (absolute), as for spamm_symbolic.
- *   precision  SPAMM_PREC_FP32, SPAMM_PREC_SPLIT_BF16 or SPAMM_PREC_SPLIT_FP16.
+ *   precision  SPAMM_PREC_FP32, SPAMM_PREC_SPLIT_BF16, SPAMM_PREC_SPLIT_FP16 or
+ *              SPAMM_PREC_SPLIT_BF16X3.  SPLIT_BF16X3 classes and rounds the
+ *              LOW products as SPLIT_BF16 does and takes every HIGH product
+ *              a b from the two bfloat16 parts of its entries, hi = bf16(x)
+ *              and lo = bf16(x - hi) (x - hi exact in FP32), as
+ *              hi_a hi_b + hi_a lo_b + lo_a hi_b on BF16 matrix units with
+ *              FP32 accumulation (the three-product bfloat16 method of
+ *              Henry, Tang and Heinecke, ARITH 2019): within 2^-14 |a||b|
+ *              of the exact product per term, against FP32's exact products,
+ *              at about a fifth of the matrix-unit time.  Entries must be
+ *              below 2^128 (1 - 2^-9) in magnitude (larger ones overflow
+ *              their bfloat16 part and the result is not finite); it needs
+ *              trees built with SPAMM_TREE_BF16, like SPLIT_BF16.
  *   low_tol    split only: a kept product A_ik B_kj is LOW iff
  *              fl64(s_A s_B) < fl64(low_tol^2) on the stored squared norms,
  *              i.e. ||A_ik||_F ||B_kj||_F < low_tol; LOW products use BF16
@@ -253,7 +267,7 @@ int spamm_symbolic(const spamm_tree *A, const spamm_tree *B, double tau,
 
 /*
  * Symbolic multiply with options (split precision).  With
- * SPAMM_PREC_SPLIT_BF16 (SPAMM_PREC_SPLIT_FP16) each kept leaf product is
+ * SPAMM_PREC_SPLIT_BF16 or SPAMM_PREC_SPLIT_BF16X3 (SPAMM_PREC_SPLIT_FP16) each kept leaf product is
  * also classed LOW or HIGH (see spamm_opts); both trees must have been built
  * with SPAMM_TREE_BF16 (SPAMM_TREE_FP16).
  * Errors as spamm_symbolic, plus SPAMM_E_INVAL for an unknown precision, a
@@ -270,8 +284,9 @@ int spamm_symbolic_ex(const spamm_tree *A, const spamm_tree *B, const spamm_opts
  * output leaf, FP32 MFMA with FP32 accumulation (Eq. product, Alg. 1 steps
  * 7-9).  Split precision: the LOW products (BF16 or scaled FP16 operands;
  * with FP16 each product is accumulated on its own, scaled back and added)
- * and the HIGH ones (FP32) are summed separately, each over k ascending, and
- * a leaf is their sum.  C: device pointer, n x n FP32 row-major, fully overwritten (zeros
+ * and the HIGH ones (FP32, or compensated BF16 with SPAMM_PREC_SPLIT_BF16X3)
+ * are each summed over k ascending, the LOW ones first, and a leaf is their
+ * sum.  C: device pointer, n x n FP32 row-major, fully overwritten (zeros
  * where no product lands; alpha = 1, beta = 0).  C must not overlap the
  * trees' storage; it may alias the matrix a tree was built from.  Enqueue on
  * the plan's stream or order streams yourself.
@@ -378,7 +393,8 @@ typedef struct spamm_request {
     float *C;            /* device, n x n FP32 row-major output; may alias A          */
     int64_t n;           /* order, >= 1                                                */
     int32_t leaf;        /* n_b in {16, 32, 64} (32 or 64 for split precision)         */
-    int32_t precision;   /* SPAMM_PREC_FP32, SPAMM_PREC_SPLIT_BF16 or _SPLIT_FP16      */
+    int32_t precision;   /* SPAMM_PREC_FP32, SPAMM_PREC_SPLIT_BF16, _SPLIT_FP16 or     */
+                         /* _SPLIT_BF16X3                                              */
     double tau;          /* SpAMM tolerance of every product (as spamm_symbolic)      */
     double low_tol;      /* split precision: absolute LOW threshold (as spamm_opts)   */
     int32_t chain_len;   /* 0: C = A B.  L in 1..64: X_0 = A, X_{s+1} = X_s X_s under  */

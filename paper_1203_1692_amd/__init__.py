@@ -3,7 +3,7 @@ FP32-MFMA leaf GEMM (one workgroup per block of output leaves; split BF16 /
 FP16 and sub-leaf variants) behind the C ABI of include/spamm.h, plus a
 continuous-batching server for products and squaring chains."""
 from ._binding import (  # noqa: F401
-    HEADER, LIB_PATH, PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16, SPAMM_E_BUSY, SPAMM_E_HIP, SPAMM_E_INVAL,
+    HEADER, LIB_PATH, PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_BF16X3, PREC_SPLIT_FP16, SPAMM_E_BUSY, SPAMM_E_HIP, SPAMM_E_INVAL,
     SPAMM_E_MISMATCH, SPAMM_E_NOMEM, SPAMM_E_NONFINITE, SPAMM_E_RANGE, SPAMM_OK, SPAMM_PENDING,
     Opts, Plan, Request, TREE_BF16, TREE_FP16, TREE_SUBNORMS, Result, Server, ServerStats, SpammError, Stats, Tree, build_tree, build_tree_output, build_tree_sparse,
     header_functions, load, multiply, multiply_ex, multiply_noalloc, request_footprint, strerror,

@@ -30,6 +30,7 @@ SPAMM_PENDING = 1
 PREC_FP32 = 0
 PREC_SPLIT_BF16 = 1
 PREC_SPLIT_FP16 = 2
+PREC_SPLIT_BF16X3 = 3     # BF16 LOW products, compensated (three BF16 products) HIGH ones
 TREE_BF16 = 1
 TREE_SUBNORMS = 2
 TREE_FP16 = 4
@@ -329,7 +330,8 @@ class Plan:
 
 def build_tree(A, leaf: int, stream=None, bf16: bool = False, subnorms: bool = False,
                fp16: bool = False) -> Tree:
-    """Quadtree of A; bf16=True also keeps BF16 leaf copies (PREC_SPLIT_BF16),
+    """Quadtree of A; bf16=True also keeps BF16 leaf copies (PREC_SPLIT_BF16
+    and PREC_SPLIT_BF16X3),
     fp16=True FP16 copies at a per-leaf power-of-two scale (PREC_SPLIT_FP16);
     subnorms=True (leaf 64) also keeps 32 x 32 sub-block norms (sub-leaf
     culling)."""

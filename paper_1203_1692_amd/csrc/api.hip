@@ -494,7 +494,7 @@ static int plan_setup(spamm_plan *p, const spamm_tree *A, const spamm_tree *B,
     if ((rc = check_tol(opts->tau, "tau")))
         return rc;
     if (opts->precision != SPAMM_PREC_FP32 && opts->precision != SPAMM_PREC_SPLIT_BF16 &&
-        opts->precision != SPAMM_PREC_SPLIT_FP16)
+        opts->precision != SPAMM_PREC_SPLIT_FP16 && opts->precision != SPAMM_PREC_SPLIT_BF16X3)
         return fail(SPAMM_E_INVAL, "unknown precision %d", opts->precision);
     const bool split = opts->precision != SPAMM_PREC_FP32;
     const bool want16 = opts->precision == SPAMM_PREC_SPLIT_FP16;
@@ -511,7 +511,9 @@ static int plan_setup(spamm_plan *p, const spamm_tree *A, const spamm_tree *B,
     if (split && (A->tiles16 == nullptr || B->tilesT16 == nullptr || A->fp16 != want16 ||
                   B->fp16 != want16))
         return fail(SPAMM_E_INVAL, "split precision %s needs trees built with %s",
-                    want16 ? "SPLIT_FP16" : "SPLIT_BF16",
+                    want16 ? "SPLIT_FP16"
+                    : opts->precision == SPAMM_PREC_SPLIT_BF16X3 ? "SPLIT_BF16X3"
+                                                                 : "SPLIT_BF16",
                     want16 ? "SPAMM_TREE_FP16" : "SPAMM_TREE_BF16");
     if (opts->sub_cull != 0 && opts->sub_cull != 1)
         return fail(SPAMM_E_INVAL, "sub_cull = %d not in {0, 1}", opts->sub_cull);

@@ -181,7 +181,8 @@ constexpr int kMaxJobs = 16;
 // Leaf-GEMM kernels of a launch: whole FP32 leaf products, split precision
 // (LOW on BF16 or scaled FP16, HIGH on FP32, one kernel), FP32 with sub-leaf
 // culling.
-enum class GemmKind { Fp32, Split, SplitF16, Sub, SplitWide, Wide32, SubWide };
+enum class GemmKind { Fp32, Split, SplitF16, Sub, SplitWide, Wide32, SubWide, SplitX3,
+                      SplitWideX3 };
 
 struct GemmJobs {          // passed by value as a kernel argument
     int32_t njobs;

@@ -35,6 +35,8 @@ namespace spamm {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void global_void_t;
@@ -74,10 +76,12 @@ __device__ inline void load_entries(const uint32_t *__restrict__ bent, uint32_t 
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (bid mod 8).  Deal
-// the blocks out in chunks of 16 consecutive ones (linear-index order: a
-// 4 x 4 patch of blocks), one chunk of each group of 8 to every XCD, each
+// the blocks out in chunks of 4 consecutive ones (linear-index order: a
+// 2 x 2 patch of blocks), one chunk of each group of 8 to every XCD, each
 // XCD taking its chunks in order: neighbours share an XCD's L2, and every
-// XCD samples the whole matrix.  The chunk an XCD takes from group g is
+// XCD samples the whole matrix.  (Chunks of 4 against 16: 301.5 against
+// 305.1 ms for the FP32 product and 20.9 against 21.6 ms for the BF16 split
+// one at n = 32768; 32 and 64 were slower still.)  The chunk an XCD takes from group g is
 // rotated by g: chunk c mod 8 is three bits of the linear index, and on the
 // diagonal (i = j) two of them are equal, so a fixed c mod 8 gave the
 // diagonal's heavy blocks to half of the XCDs (rotated: 305.5 against 314.8
@@ -87,7 +91,7 @@ __device__ inline void load_entries(const uint32_t *__restrict__ bent, uint32_t 
 // XCD then held 1.2x its share of the LOW products and 1.8x of the HIGH ones.)
 __device__ inline uint32_t xcd_block(uint32_t bid, uint32_t nblocks)
 {
-    constexpr uint32_t kChunk = 16;
+    constexpr uint32_t kChunk = 4;
     if (nblocks % (8u * kChunk) != 0u)
         return bid;
     const uint32_t x = bid % 8u, s = bid / 8u, g = s / kChunk;
@@ -239,9 +243,86 @@ __device__ inline void write_leaf16(const floatx4 &acc, int64_t row0, int64_t co
     }
 }
 
-// FP32 products of one block, n_b >= 32: its entries [e0, e1) of `bent`,
-// staged by k-panels (see the pipeline note above), into acc.
+// Compensated HIGH products (split precision SPAMM_PREC_SPLIT_BF16X3): the
+// FP32 k-panels of panel_mfma32, each entry x taken as its two bfloat16
+// parts hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact in FP32), and a
+// product a b as hi_a hi_b + hi_a lo_b + lo_a hi_b on the BF16 matrix units
+// with FP32 accumulation -- the three-product bfloat16 method of Henry, Tang
+// and Heinecke (ARITH 2019), about 2^-16 |a b| from the exact product per
+// term where FP32 MFMA is exact; three 32x32x16 BF16 MFMAs replace eight
+// 32x32x2 FP32 ones.  A lane takes 8 consecutive k of its row (two 16-byte
+// reads): lane half h of slice g covers k in [16 h + 8 g, 16 h + 8 g + 8), the
+// same for both operands, so each MFMA sums 16 distinct k of the panel.
+__device__ inline void bf16_parts4(floatx4 x, uint32_t *hi, uint32_t *lo)
+{
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const floatx2 v = {x[2 * p], x[2 * p + 1]};
+        const bf16x2 h = __builtin_convertvector(v, bf16x2);        // round to nearest even
+        const floatx2 hf = __builtin_convertvector(h, floatx2);      // exact
+        const floatx2 r = {v[0] - hf[0], v[1] - hf[1]};               // exact
+        hi[p] = __builtin_bit_cast(uint32_t, h);
+        lo[p] = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
+    }
+}
+
 template <int B>
+__device__ inline void panel_mfma_x3(const float *__restrict__ Ap, const float *__restrict__ Bp,
+                                     floatx16 (&acc)[B / 32][B / 32], int lane)
+{
+    using L = LeafLayout<B>;
+    static_assert(L::kKS == 32, "two slices of 16 per k-panel");
+    constexpr int MB = B / 32;
+    const int r = lane & 31, h = lane >> 5;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        const int c = 16 * h + 8 * g;
+        uint32_t ah[MB][4], al[MB][4], bh[MB][4], bl[MB][4];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            bf16_parts4(*reinterpret_cast<const floatx4 *>(Ap + L::pindex(i * 32 + r, c)), ah[i],
+                        al[i]);
+            bf16_parts4(*reinterpret_cast<const floatx4 *>(Ap + L::pindex(i * 32 + r, c + 4)),
+                        ah[i] + 2, al[i] + 2);
+        }
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+            bf16_parts4(*reinterpret_cast<const floatx4 *>(Bp + L::pindex(j * 32 + r, c)), bh[j],
+                        bl[j]);
+            bf16_parts4(*reinterpret_cast<const floatx4 *>(Bp + L::pindex(j * 32 + r, c + 4)),
+                        bh[j] + 2, bl[j] + 2);
+        }
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < MB; ++j) {
+                const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah[i]);
+                const bf16x8 Al = __builtin_bit_cast(bf16x8, al[i]);
+                const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh[j]);
+                const bf16x8 Bl = __builtin_bit_cast(bf16x8, bl[j]);
+                // the two small terms first
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, Bh, acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bl, acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bh, acc[i][j], 0, 0, 0);
+            }
+    }
+}
+
+// The HIGH panel routine of a kernel: FP32 MFMA, or compensated BF16.
+template <int B, bool X3>
+__device__ inline void panel_high(const float *__restrict__ Ap, const float *__restrict__ Bp,
+                                  floatx16 (&acc)[B / 32][B / 32], int lane)
+{
+    if constexpr (X3)
+        panel_mfma_x3<B>(Ap, Bp, acc, lane);
+    else
+        panel_mfma32<B>(Ap, Bp, acc, lane);
+}
+
+// FP32 products of one block, n_b >= 32: its entries [e0, e1) of `bent`,
+// staged by k-panels (see the pipeline note above), into acc (X3: as
+// compensated BF16 products).
+template <int B, bool X3 = false>
 __device__ inline void fp32_products(const float *__restrict__ tA, const float *__restrict__ tBT,
                                      const uint32_t *slotA, const uint32_t *slotB,
                                      const uint32_t *__restrict__ bent, uint32_t e0, uint32_t e1,
@@ -267,7 +348,7 @@ __device__ inline void fp32_products(const float *__restrict__ tA, const float *
                            I0, J0, smem + ((t + 1) & 1) * S::kStage, w, lane);
         if ((ent >> (16 + w)) & 1u) {
             const float *buf = smem + (t & 1) * S::kStage;
-            panel_mfma32<B>(buf + qa * L::kPanel, buf + (2 + qb) * L::kPanel, acc, lane);
+            panel_high<B, X3>(buf + qa * L::kPanel, buf + (2 + qb) * L::kPanel, acc, lane);
         }
     }
 }
@@ -643,10 +724,12 @@ __device__ inline void low_products(const uint16_t *__restrict__ tA16,
 // accumulators (the MFMA result layouts are the same): a leaf is written as
 // its LOW sum, plus its HIGH sum in one FP32 addition when the block has HIGH
 // entries -- the sums of the paper's product split by class, each over k
-// ascending.
-template <int B, bool F16>
+// ascending.  X3: the HIGH products as compensated BF16 products of the
+// same FP32 stages (panel_mfma_x3).
+template <int B, bool F16, bool X3 = false>
 __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
 {
+    static_assert(!(F16 && X3), "compensated HIGH products go with BF16 LOW operands");
     constexpr int MB = B / 32;
     extern __shared__ float smem[];        // the 16-bit stages, then the FP32 stages
     const GemmJob &job = jobs.job[job_of(jobs, blockIdx.x)];
@@ -679,7 +762,7 @@ __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
                      (uint16_t *)smem, ents, eexp, w, lane, job.escA, job.escB, lo);
     __syncthreads();                       // every wave is done with the 16-bit stages
     const uint32_t h0 = job.browptr[blk], h1 = job.browptr[blk + 1];
-    fp32_products<B>((const float *)job.tA, (const float *)job.tBT, job.slotA, job.slotB, job.bent,
+    fp32_products<B, X3>((const float *)job.tA, (const float *)job.tBT, job.slotA, job.slotB, job.bent,
                      h0, h1, I0, J0, smem, ents, w, lane, hi);
     if (single && w != 0)
         return;
@@ -717,7 +800,9 @@ __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
 // LDS.  One running FP32 sum per leaf: its LOW products over k ascending,
 // then its HIGH products over k ascending.  (A second launch for the HIGH
 // products alone, adding to the LOW sums in C, was 14 % slower: they could
-// no longer overlap the LOW work of other blocks.)
+// no longer overlap the LOW work of other blocks.)  X3: the HIGH products as
+// compensated BF16 products of the same FP32 stages (at n = 32768 the HIGH
+// phase alone 4.4 against 9.6 ms for 1.34 M products).
 constexpr int kWideWaves = 16;
 
 // Workgroup barrier without the memory fence of __syncthreads (whose release
@@ -800,7 +885,8 @@ __device__ inline uint32_t merge_children(const uint32_t *__restrict__ rp,
 // FP32 products of 4 x 4 block P4 (merged list of its children's HIGH, or
 // only, schedules): FP32 k-panels (8 KB), 64 KB stages in a 2-deep ring over
 // the workgroup's LDS; wave (r, c) adds its leaf's products into acc, k
-// ascending.
+// ascending (X3: as compensated BF16 products).
+template <bool X3 = false>
 __device__ inline void wide_fp32_products(const GemmJob &job, uint32_t P4, uint32_t I0,
                                           uint32_t J0, uint32_t NK, int w, int r, int c,
                                           int bit, int lane, float *smem, uint32_t *kmask,
@@ -840,11 +926,12 @@ __device__ inline void wide_fp32_products(const GemmJob &job, uint32_t P4, uint3
         const uint32_t ent = list[t >> 1];
         if ((ent >> (16 + bit)) & 1u) {
             const float *buf = ring32 + (t & 1u) * kWideStage32;
-            panel_mfma32<B>(buf + r * P32, buf + (4 + c) * P32, acc, lane);
+            panel_high<B, X3>(buf + r * P32, buf + (4 + c) * P32, acc, lane);
         }
     }
 }
 
+template <bool X3>
 __global__ __launch_bounds__(1024) void leaf_gemm_split_wide(const GemmJobs jobs)
 {
     constexpr int B = 64, MB = 2;
@@ -956,7 +1043,7 @@ __global__ __launch_bounds__(1024) void leaf_gemm_split_wide(const GemmJobs jobs
     __syncthreads();                      // every wave is done with the LOW ring and list
 
     // ---- HIGH products ------------------------------------------------------------
-    wide_fp32_products(job, P4, I0, J0, NK, w, r, c, bit, lane, smem, kmask, list, wsum, acc);
+    wide_fp32_products<X3>(job, P4, I0, J0, NK, w, r, c, bit, lane, smem, kmask, list, wsum, acc);
     write_leaf32<B>(acc, (int64_t)(I0 + r) * B, (int64_t)(J0 + c) * B, job.n, job.C, lane);
 }
 
@@ -1170,16 +1257,17 @@ static hipError_t launch_wide32(const GemmJobs &jobs, hipStream_t s)
 }
 
 // jobs.block0 / nblocks count 4 x 4 blocks here
+template <bool X3>
 static hipError_t launch_split_wide(const GemmJobs &jobs, hipStream_t s)
 {
     constexpr size_t lds = WideShape::kLds;
     static const hipError_t attr =
-        hipFuncSetAttribute((const void *)leaf_gemm_split_wide,
+        hipFuncSetAttribute((const void *)leaf_gemm_split_wide<X3>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (attr != hipSuccess)
         return attr;
-    hipLaunchKernelGGL(leaf_gemm_split_wide, dim3(jobs.nblocks), dim3(64 * kWideWaves), lds, s,
-                       jobs);
+    hipLaunchKernelGGL(leaf_gemm_split_wide<X3>, dim3(jobs.nblocks), dim3(64 * kWideWaves), lds,
+                       s, jobs);
     return hipGetLastError();
 }
 
@@ -1209,16 +1297,17 @@ static hipError_t launch_sub(const GemmJobs &jobs, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int B, bool F16>
+template <int B, bool F16, bool X3 = false>
 static hipError_t launch_split(const GemmJobs &jobs, hipStream_t s)
 {
     constexpr size_t lds = SplitShape<B, F16>::kLds;
     static const hipError_t attr =
-        hipFuncSetAttribute((const void *)leaf_gemm_split<B, F16>,
+        hipFuncSetAttribute((const void *)leaf_gemm_split<B, F16, X3>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (attr != hipSuccess)
         return attr;
-    hipLaunchKernelGGL((leaf_gemm_split<B, F16>), dim3(jobs.nblocks), dim3(256), lds, s, jobs);
+    hipLaunchKernelGGL((leaf_gemm_split<B, F16, X3>), dim3(jobs.nblocks), dim3(256), lds, s,
+                       jobs);
     return hipGetLastError();
 }
 
@@ -1232,7 +1321,15 @@ hipError_t launch_gemm_jobs(int leaf, GemmKind kind, const GemmJobs &jobs, hipSt
     case GemmKind::Sub:
         return leaf == 64 ? launch_sub(jobs, s) : hipErrorInvalidValue;
     case GemmKind::SplitWide:
-        return leaf == 64 ? launch_split_wide(jobs, s) : hipErrorInvalidValue;
+        return leaf == 64 ? launch_split_wide<false>(jobs, s) : hipErrorInvalidValue;
+    case GemmKind::SplitWideX3:
+        return leaf == 64 ? launch_split_wide<true>(jobs, s) : hipErrorInvalidValue;
+    case GemmKind::SplitX3:
+        switch (leaf) {
+        case 32: return launch_split<32, false, true>(jobs, s);
+        case 64: return launch_split<64, false, true>(jobs, s);
+        default: return hipErrorInvalidValue;
+        }
     case GemmKind::Wide32:
         return leaf == 64 ? launch_wide32(jobs, s) : hipErrorInvalidValue;
     case GemmKind::SubWide:
@@ -1268,6 +1365,8 @@ GemmKind plan_kind(const spamm_plan *p)
         return p->depth >= 2 ? GemmKind::SubWide : GemmKind::Sub;
     if (p->precision == SPAMM_PREC_SPLIT_BF16 && p->leaf == 64 && p->depth >= 2)
         return GemmKind::SplitWide;
+    if (p->precision == SPAMM_PREC_SPLIT_BF16X3)
+        return p->leaf == 64 && p->depth >= 2 ? GemmKind::SplitWideX3 : GemmKind::SplitX3;
     // FP32 at 64 x 64 leaves: 4 x 4 blocks (313.6 against 330.6 ms for 2 x 2
     // at n = 32768, tau = 1e-8, bit-identical C, with the unrotated XCD
     // mapping)
@@ -1293,7 +1392,8 @@ void plan_jobs(const spamm_plan *p, float *C, GemmJob &j)
     // the wide kernels' workgroups own 4 x 4 output leaves
     const GemmKind kind = plan_kind(p);
     j.nblocks = (uint32_t)p->nblocks / (kind == GemmKind::SplitWide || kind == GemmKind::Wide32 ||
-                                                kind == GemmKind::SubWide
+                                                kind == GemmKind::SubWide ||
+                                                kind == GemmKind::SplitWideX3
                                             ? 4u
                                             : 1u);
     j.block0 = 0;

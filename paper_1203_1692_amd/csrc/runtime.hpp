@@ -56,7 +56,8 @@ size_t tree_device_bytes(int64_t n, int32_t leaf, uint32_t flags);
 // Tree flags a request of this precision needs (16-bit copies for split).
 inline uint32_t tree_flags_for(int32_t precision)
 {
-    return precision == SPAMM_PREC_SPLIT_BF16 ? SPAMM_TREE_BF16
+    return precision == SPAMM_PREC_SPLIT_BF16 || precision == SPAMM_PREC_SPLIT_BF16X3
+               ? SPAMM_TREE_BF16
            : precision == SPAMM_PREC_SPLIT_FP16 ? SPAMM_TREE_FP16 : 0u;
 }
 size_t plan_device_bytes(int depth, bool split);

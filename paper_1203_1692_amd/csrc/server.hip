@@ -131,7 +131,7 @@ int check_request(const spamm_request *r, size_t *bytes, bool *batched = nullptr
     if (r->leaf != 16 && r->leaf != 32 && r->leaf != 64)
         return fail(SPAMM_E_INVAL, "leaf = %d not in {16, 32, 64}", r->leaf);
     if (r->precision != SPAMM_PREC_FP32 && r->precision != SPAMM_PREC_SPLIT_BF16 &&
-        r->precision != SPAMM_PREC_SPLIT_FP16)
+        r->precision != SPAMM_PREC_SPLIT_FP16 && r->precision != SPAMM_PREC_SPLIT_BF16X3)
         return fail(SPAMM_E_INVAL, "unknown precision %d", r->precision);
     const bool split = r->precision != SPAMM_PREC_FP32;
     if (split && r->leaf == 16)
@@ -338,10 +338,13 @@ bool launch_batches(spamm_server *S)
                 .push_back(i);
         ready.swap(rest);
         // jobs of each kernel kind (FP32 or BF16 split on 2 x 2 or 4 x 4
-        // blocks, FP16 split) go to one launch
-        constexpr int kKinds = 5;
-        constexpr GemmKind kinds[kKinds] = {GemmKind::Fp32, GemmKind::Split, GemmKind::SplitF16,
-                                            GemmKind::SplitWide, GemmKind::Wide32};
+        // blocks, with FP32 or compensated HIGH products; FP16 split) go to
+        // one launch
+        constexpr int kKinds = 7;
+        constexpr GemmKind kinds[kKinds] = {GemmKind::Fp32,      GemmKind::Split,
+                                            GemmKind::SplitF16,  GemmKind::SplitWide,
+                                            GemmKind::Wide32,    GemmKind::SplitX3,
+                                            GemmKind::SplitWideX3};
         GemmJobs tabs[kKinds] = {};
         hipError_t e = hipSuccess;
         for (size_t i : batch) {

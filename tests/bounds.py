@@ -7,7 +7,10 @@ gamma_m = m u / (1 - m u), u = 2^-24 (FP32 accumulation), where X, Y are the
 operands each product was taken on (FP32 for HIGH products, the rounded
 16-bit values for LOW ones) and m = n_b K_IJ + 1 (FP32 and BF16 products) or
 (n_b + 1) K_IJ + 1 (FP16 LOW products are summed on their own and added, one
-more rounding each).  s = max(1, max|X|, max|Y|)^2 covers flushed denormal
+more rounding each).  With compensated HIGH products (low_fmt "bf16x3") a
+HIGH product adds three exact terms per k, hi_a hi_b, hi_a lo_b and
+lo_a hi_b, bounded together by (|hi_a| + |lo_a|)(|hi_b| + |lo_b|), and
+m = 3 n_b K_IJ + 1.  s = max(1, max|X|, max|Y|)^2 covers flushed denormal
 products.
 """
 import numpy as np
@@ -53,7 +56,13 @@ def class_bound(A, B, leaf, keys, low_fmt="bf16"):
     PB, _ = padded(B, leaf)
     N = 1 << d
     inv = {oracle.linear_index(i, j): (i, j) for i in range(N) for j in range(N)}
-    ops = {0: (np.abs(PA.astype(np.float64)), np.abs(PB.astype(np.float64)))}
+    if low_fmt == "bf16x3":
+        def parts(P):
+            H = bf16_round(P)
+            return np.abs(H) + np.abs(bf16_round(P - H.astype(np.float32)))
+        ops = {0: (parts(PA), parts(PB))}
+    else:
+        ops = {0: (np.abs(PA.astype(np.float64)), np.abs(PB.astype(np.float64)))}
     keys = np.asarray(keys, dtype=np.uint64)
     if len(keys) and (keys >> np.uint64(63)).any():
         if low_fmt == "fp16":
@@ -72,7 +81,7 @@ def class_bound(A, B, leaf, keys, low_fmt="bf16"):
             X[I * leaf:(I + 1) * leaf, k * leaf:(k + 1) * leaf] @ Y[k * leaf:(k + 1) * leaf,
                                                                   J * leaf:(J + 1) * leaf])
         cnt[I, J] += 1
-    per = leaf + 1 if low_fmt == "fp16" else leaf
+    per = leaf + 1 if low_fmt == "fp16" else 3 * leaf if low_fmt == "bf16x3" else leaf
     m = per * np.kron(cnt, np.ones((leaf, leaf))) + 1
     gamma = m * U32 / (1 - m * U32)
     scale = max(1.0, float(ops[0][0].max()), float(ops[0][1].max())) ** 2

@@ -228,12 +228,20 @@ def round_leaf(X, S, fmt):
     """A leaf block rounded as a LOW operand: bfloat16, or binary16 at the
     scale exponent of its squared norm S (subnormals flushed)."""
     import torch
-    if fmt == "bf16":
+    if fmt in ("bf16", "bf16x3"):
         return torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(torch.bfloat16).to(
             torch.float64).numpy()
     e = oracle.fp16_exponent(S)
     h = (X * 2.0 ** e).astype(np.float16).astype(np.float64)
     return np.where(np.abs(h) < 2.0 ** -14, 0.0, h) * 2.0 ** -e
+
+
+def abs_parts(X):
+    """|hi| + |lo| of a leaf block's two bfloat16 parts (torch's rounding,
+    float32 subtraction)."""
+    H = round_leaf(X, 0.0, "bf16")
+    L = round_leaf(np.asarray(X, dtype=np.float32) - H.astype(np.float32), 0.0, "bf16")
+    return np.abs(H) + np.abs(L)
 
 
 class SplitRun:
@@ -247,8 +255,9 @@ class SplitRun:
         print(f"\n[fullsize] {label} split-{fmt} tau={tau:g} low_tol={low:g} theta={rel:g}",
               flush=True)
         dA = torch.from_numpy(A).cuda()
-        self.tree = sp.build_tree(dA, leaf, bf16=(fmt == "bf16"), fp16=(fmt == "fp16"))
-        prec = sp.PREC_SPLIT_FP16 if fmt == "fp16" else sp.PREC_SPLIT_BF16
+        self.tree = sp.build_tree(dA, leaf, bf16=(fmt != "fp16"), fp16=(fmt == "fp16"))
+        prec = {"fp16": sp.PREC_SPLIT_FP16, "bf16": sp.PREC_SPLIT_BF16,
+                "bf16x3": sp.PREC_SPLIT_BF16X3}[fmt]
         self.plan = sp.symbolic(self.tree, self.tree, tau, precision=prec, low_tol=low,
                                 low_rel=rel)
         C = torch.full_like(dA, float("nan"))
@@ -266,7 +275,8 @@ def check_split(run, seed):
     """Every task key (class bit included) against the oracle's split mode;
     sampled output leaves against the oracle's per-leaf recursion within
     Higham's bound over each class's operands (m = n_b K + 1, one more
-    rounding per LOW product with FP16)."""
+    rounding per LOW product with FP16; with compensated HIGH products three
+    terms per product, bounded by (|hi_a| + |lo_a|)(|hi_b| + |lo_b|))."""
     ref = oracle.spamm(run.A, run.A, run.leaf, run.tau, want_C=False, low_tol=run.low,
                        low_fmt=run.fmt, low_rel=run.rel)
     assert run.stats["tasks"] == ref.K and run.stats["tasks_low"] == ref.Klow
@@ -287,8 +297,10 @@ def check_split(run, seed):
             Y = leaf_block(run.A, k, J, run.leaf, run.n)
             if low:
                 X, Y = round_leaf(X, S[I, k], run.fmt), round_leaf(Y, S[k, J], run.fmt)
+            elif run.fmt == "bf16x3":
+                X, Y = abs_parts(X), abs_parts(Y)
             M += np.abs(X) @ np.abs(Y)
-        m = (run.leaf + extra) * int(counts[s]) + 1
+        m = (3 * run.leaf if run.fmt == "bf16x3" else run.leaf + extra) * int(counts[s]) + 1
         bound = m * U32 / (1 - m * U32) * M + m * 2.0 ** -126
         got = leaf_block(run.C, I, J, run.leaf, run.n)
         assert np.all(np.isfinite(got))
@@ -327,7 +339,7 @@ def test_cluster1310_split_theta_1e4(cluster1310, gpu):
 
 
 @pytest.mark.parametrize("fmt,tau,theta", [("bf16", 3.1622776601683795e-05, 1e-6),
-                                           ("fp16", 1e-4, 1e-5)])
+                                           ("fp16", 1e-4, 1e-5), ("bf16x3", 1e-4, 3e-7)])
 def test_cluster1310_split_matched_error_point(cluster1310, gpu, fmt, tau, theta):
     """cluster1310-n32750 at the split products' matched-error points of the
     benchmark (the fastest split product within the FP32 product's

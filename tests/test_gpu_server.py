@@ -1,7 +1,7 @@
 """The serving loop on the GPU.
 
 * every request's C is bit-identical whether it runs alone or in a mix of
-  uneven n, tau, leaf, precision (FP32, BF16 and FP16 split) and chain
+  uneven n, tau, leaf, precision (FP32, BF16, compensated BF16 and FP16 split) and chain
   length (fixed owner and k order per output leaf), and equal to the
   one-call API's result;
 * teacher-forced parity with the oracle at every step: step s of a request
@@ -62,6 +62,8 @@ MIX = [
     (600, 32, 1e-6, 2, 1e-3, 0, False, 0.1, 15),
     (1024, 64, 1e-8, 2, 1e-4, 2, False, 0.15, 16),
     (300, 32, 1e-6, 2, 1e-2, 0, True, 0.1, 17),
+    (800, 64, 1e-6, 3, 1e-4, 0, False, 0.02, 18),
+    (1024, 32, 1e-8, 3, 1e-4, 3, False, 0.2, 19),
 ]
 
 
@@ -84,7 +86,8 @@ def reference(gpu, spec, dA, dB, low_tol=0.0, keep_steps=False):
     X_s as the GPU holds it, the plan's task keys and counts and its C."""
     import torch
     n, leaf, tau, prec, theta, chain, *_ = spec
-    bf, f16 = prec == gpu.PREC_SPLIT_BF16, prec == gpu.PREC_SPLIT_FP16
+    bf = prec in (gpu.PREC_SPLIT_BF16, gpu.PREC_SPLIT_BF16X3)
+    f16 = prec == gpu.PREC_SPLIT_FP16
     rel = theta if (prec and not low_tol) else 0.0
     X = dA
     steps = []
@@ -174,7 +177,7 @@ def test_matches_oracle_every_step(mix, i):
     of that step's C; the served counts are the sums over the steps."""
     n, leaf, tau, prec, theta, chain, *_ = MIX[i]
     A, B = mix["inputs"][i][0], mix["inputs"][i][1]
-    fmt = "fp16" if prec == 2 else "bf16"
+    fmt = {2: "fp16", 3: "bf16x3"}.get(prec, "bf16")
     _, steps = mix["refs"][i]
     assert len(steps) == max(1, chain)
     K = Klow = 0
