@@ -22,6 +22,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -64,10 +65,13 @@ def gemm_kernel_name(precision: str, leaf: int, depth: int, sub: bool = False) -
     if sub:
         return "leaf_gemm_sub_wide" if depth >= 2 else "leaf_gemm_sub<64>"
     if precision == "split-bf16":
-        return ("leaf_gemm_split_wide" if leaf == 64 and depth >= 2
-                else f"leaf_gemm_split<{leaf}, false>")
+        return ("leaf_gemm_split_wide<false>" if leaf == 64 and depth >= 2
+                else f"leaf_gemm_split<{leaf}, false, false>")
+    if precision == "split-bf16x3":
+        return ("leaf_gemm_split_wide<true>" if leaf == 64 and depth >= 2
+                else f"leaf_gemm_split<{leaf}, false, true>")
     if precision == "split-fp16":
-        return f"leaf_gemm_split<{leaf}, true>"
+        return f"leaf_gemm_split<{leaf}, true, false>"
     return "leaf_gemm_wide32" if leaf == 64 and depth >= 2 else f"leaf_gemm<{leaf}>"
 
 
@@ -89,7 +93,8 @@ def measured_split_traffic(workload: str, tau: float, theta: float, fmt: str = "
     (tau, theta) from the committed counter runs, or None when absent or the
     kernel sources changed since."""
     import glob
-    kind = "leaf_gemm_split" if fmt == "bf16" else "leaf_gemm_split_fp16"
+    kind = {"bf16": "leaf_gemm_split", "fp16": "leaf_gemm_split_fp16",
+            "bf16x3": "leaf_gemm_split_x3"}[fmt]
     # one record per measured (tau, theta): <kind>_<workload>[_<point>]_traffic.json
     digest = kernel_source_digest()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles",
@@ -176,11 +181,13 @@ def matched_error(sp, torch, wl, dA, C, exact, tau, leaf, reps=2):
                        "ms_leaf_gemm": round(g_ms, 3), "err": max_err_full(C, exact),
                        "tasks": st["tasks"], "low_frac": 0.0})
         for th in THETAS:
-            (ms, g_ms, _), st = timed_product(sp, tree, t_, C, reps, sp.PREC_SPLIT_BF16, th)
-            points.append({"precision": "split-bf16", "tau": t_, "theta": th, "ms": round(ms, 3),
-                           "ms_leaf_gemm": round(g_ms, 3), "err": max_err_full(C, exact),
-                           "tasks": st["tasks"],
-                           "low_frac": round(st["tasks_low"] / max(1, st["tasks"]), 4)})
+            for kind, prec in (("split-bf16", sp.PREC_SPLIT_BF16),
+                               ("split-bf16x3", sp.PREC_SPLIT_BF16X3)):
+                (ms, g_ms, _), st = timed_product(sp, tree, t_, C, reps, prec, th)
+                points.append({"precision": kind, "tau": t_, "theta": th, "ms": round(ms, 3),
+                               "ms_leaf_gemm": round(g_ms, 3), "err": max_err_full(C, exact),
+                               "tasks": st["tasks"],
+                               "low_frac": round(st["tasks_low"] / max(1, st["tasks"]), 4)})
     tree.free()
     tree = sp.build_tree(dA, leaf, fp16=True)
     for t_ in taus:
@@ -204,7 +211,7 @@ def matched_error(sp, torch, wl, dA, C, exact, tau, leaf, reps=2):
                            "sub_fraction": round(st["subtasks"] / max(1, 8 * st["tasks"]), 4)})
         sub_tree.free()
     floor = next(p["err"] for p in points if p["precision"] == "fp32" and p["tau"] == tau)
-    kinds = ("fp32", "split-bf16", "split-fp16", "fp32-subleaf")
+    kinds = ("fp32", "split-bf16", "split-bf16x3", "split-fp16", "fp32-subleaf")
 
     def at(target):
         best = {k: fastest_within(points, k, target) for k in kinds}
@@ -222,8 +229,9 @@ def matched_error(sp, torch, wl, dA, C, exact, tau, leaf, reps=2):
            "fp32_error_at_tau": floor,
            "at_fp32_error": at(floor),
            "at_targets": {f"{t:g}": at(t) for t in TARGETS},
-           "grid": "tau x 10^{0, 0.5, ..., 5}; theta in %s for both split formats; sub-leaf "
-                   "culling tau x 10^{-1, -0.5, ..., 4.5}" % (list(THETAS),)}
+           "grid": "tau x 10^{0, 0.5, ..., 5}; theta in %s for the three split formats "
+                   "(BF16, BF16 with compensated HIGH products, FP16); sub-leaf culling "
+                   "tau x 10^{-1, -0.5, ..., 4.5}" % (list(THETAS),)}
     plain = next(p for p in points if p["precision"] == "fp32" and p["tau"] == tau)
     sub = [p for p in points if p["precision"] == "fp32-subleaf" and p["tau"] == tau]
     if sub:
@@ -233,8 +241,9 @@ def matched_error(sp, torch, wl, dA, C, exact, tau, leaf, reps=2):
                                    "ms_plain": plain["ms"], "ms_subleaf": sub[0]["ms"],
                                    "err_plain": plain["err"], "err_subleaf": sub[0]["err"]}
     m = res["at_fp32_error"]["fastest"]
-    for kind, fmt, kernel in (("split-bf16", "bf16", "leaf_gemm_split_wide"),
-                              ("split-fp16", "fp16", "leaf_gemm_split<64, true>")):
+    depth = max(0, math.ceil(math.log2(wl.n / leaf))) if wl.n > leaf else 0
+    for kind, fmt in (("split-bf16", "bf16"), ("split-bf16x3", "bf16x3"),
+                      ("split-fp16", "fp16")):
         pt = m.get(kind)
         if pt is None:
             continue
@@ -242,13 +251,15 @@ def matched_error(sp, torch, wl, dA, C, exact, tau, leaf, reps=2):
         if tb is not None:
             gbs = tb / (pt["ms_leaf_gemm"] * 1e-3) / 1e9
             # and against the matrix units: LOW products at the dense 16-bit
-            # peak, HIGH ones at the FP32 one
+            # peak, HIGH ones at the FP32 one (compensated: three products at
+            # the 16-bit peak)
             low = pt["tasks"] * pt["low_frac"]
-            mfma_ms = (2.0 * leaf ** 3 * (low / (MFMA_16BIT_PEAK_TFLOPS * 1e12) +
-                                          (pt["tasks"] - low) / (MFMA_FP32_PEAK_TFLOPS * 1e12))
-                       * 1e3)
+            high_s = ((pt["tasks"] - low) * 3 / (MFMA_16BIT_PEAK_TFLOPS * 1e12)
+                      if fmt == "bf16x3" else (pt["tasks"] - low) / (MFMA_FP32_PEAK_TFLOPS * 1e12))
+            mfma_ms = 2.0 * leaf ** 3 * (low / (MFMA_16BIT_PEAK_TFLOPS * 1e12) + high_s) * 1e3
             res[f"{kind}_roofline"] = {
-                "kernel": kernel, "bound": "hbm", "achieved": round(gbs, 1),
+                "kernel": gemm_kernel_name(kind, leaf, depth), "bound": "hbm",
+                "achieved": round(gbs, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                 "traffic": tb,
                 "mfma_ideal_ms": round(mfma_ms, 3),
@@ -282,7 +293,8 @@ def run_config(sp, torch, dev, name, reps, tau=None, precisions=((0, 0.0),), wit
             (ms, g_ms, c_ms), st = timed_product(sp, tree, t_, C, reps, prec, th)
             tree.free()
             flops = st["flops"]
-            pt = {"precision": {0: "fp32", 1: "split-bf16", 2: "split-fp16"}[prec], "tau": t_,
+            pt = {"precision": {0: "fp32", 1: "split-bf16", 2: "split-fp16",
+                                3: "split-bf16x3"}[prec], "tau": t_,
                   "theta": th, "tasks": st["tasks"], "tasks_low": st["tasks_low"],
                   "ms_build": round(min(tb), 4), "ms_cull": round(c_ms, 4),
                   "ms_leaf_gemm": round(g_ms, 4), "ms_multiply": round(ms, 4),
@@ -298,8 +310,9 @@ def run_config(sp, torch, dev, name, reps, tau=None, precisions=((0, 0.0),), wit
 
 
 def algdecay_sweep(sp, torch, dev, reps):
-    """The tau sweep of algdecay-n16384: plain FP32 against split BF16 at
-    theta = 1e-4 at each configured tau, and FP32 against both split formats
+    """The tau sweep of algdecay-n16384: plain FP32 against split BF16 (with
+    FP32 or compensated HIGH products) at theta = 1e-4 at each configured
+    tau, and FP32 against the three split formats
     at the fixed errors 1e-5 and 1e-6 (tau on a 10^{1/2} grid from 1e-10 to
     1e-4, theta from 1e-4 to 1e-9)."""
     import workloads
@@ -311,12 +324,14 @@ def algdecay_sweep(sp, torch, dev, reps):
     sweep = []
     for t_ in wl.taus:
         row = {"tau": t_}
-        for kind, prec, th in (("fp32", 0, 0.0), ("split-bf16", sp.PREC_SPLIT_BF16, 1e-4)):
+        for kind, prec, th in (("fp32", 0, 0.0), ("split-bf16", sp.PREC_SPLIT_BF16, 1e-4),
+                               ("split-bf16x3", sp.PREC_SPLIT_BF16X3, 1e-4)):
             (ms, g_ms, c_ms), st = timed_product(sp, tree, t_, C, reps, prec, th)
             row[kind] = {"ms": round(ms, 4), "ms_cull": round(c_ms, 4),
                          "ms_leaf_gemm": round(g_ms, 4), "tasks": st["tasks"],
                          "tasks_low": st["tasks_low"], "err": max_err_full(C, exact)}
         row["speedup_split"] = round(row["fp32"]["ms"] / row["split-bf16"]["ms"], 3)
+        row["speedup_split_x3"] = round(row["fp32"]["ms"] / row["split-bf16x3"]["ms"], 3)
         sweep.append(row)
     points = []
     thetas = [10.0 ** -e for e in range(4, 10)]                # 1e-4 ... 1e-9
@@ -325,6 +340,7 @@ def algdecay_sweep(sp, torch, dev, reps):
         t_ = 1e-10 * 10.0 ** (h / 2)
         runs = [("fp32", tree, 0, 0.0)]
         runs += [("split-bf16", tree, sp.PREC_SPLIT_BF16, th) for th in thetas]
+        runs += [("split-bf16x3", tree, sp.PREC_SPLIT_BF16X3, th) for th in thetas]
         runs += [("split-fp16", t16, sp.PREC_SPLIT_FP16, th) for th in thetas]
         for kind, tr, prec, th in runs:
             (ms, g_ms, _), st = timed_product(sp, tr, t_, C, reps, prec, th)
@@ -361,11 +377,12 @@ def algdecay_sweep(sp, torch, dev, reps):
     del C2
     matched = {}
     for target in TARGETS:
-        best = {k: fastest_within(points, k, target) for k in ("fp32", "split-bf16", "split-fp16")}
+        kinds = ("fp32", "split-bf16", "split-bf16x3", "split-fp16")
+        best = {k: fastest_within(points, k, target) for k in kinds}
         f32 = best["fp32"]
         best["speedup_vs_fp32"] = {k: (round(f32["ms"] / best[k]["ms"], 3)
                                        if f32 and best[k] else None)
-                                   for k in ("split-bf16", "split-fp16")}
+                                   for k in kinds[1:]}
         matched[f"{target:g}"] = best
     del dA, C, exact
     torch.cuda.empty_cache()
@@ -795,8 +812,10 @@ def main() -> int:
                     help="skip the FP32-vs-split comparison at a fixed max-norm error")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark instead: saturation, then Poisson arrivals")
-    ap.add_argument("--precision", choices=("fp32", "split", "split-fp16"), default="fp32",
+    ap.add_argument("--precision", choices=("fp32", "split", "split-x3", "split-fp16"),
+                    default="fp32",
                     help="product of the timed steps (split: BF16 for LOW products, "
+                         "split-x3: also compensated BF16 HIGH products, "
                          "split-fp16: FP16 at a per-leaf scale)")
     ap.add_argument("--sub-cull", action="store_true",
                     help="sub-leaf culling (32 x 32 sub-products inside 64 x 64 leaves); "
@@ -866,7 +885,10 @@ def main() -> int:
 
     split = args.precision != "fp32"
     f16 = args.precision == "split-fp16"
-    prec = sp.PREC_SPLIT_FP16 if f16 else sp.PREC_SPLIT_BF16 if split else sp.PREC_FP32
+    x3 = args.precision == "split-x3"
+    prec = (sp.PREC_SPLIT_FP16 if f16 else sp.PREC_SPLIT_BF16X3 if x3
+            else sp.PREC_SPLIT_BF16 if split else sp.PREC_FP32)
+    split_kind = "split-fp16" if f16 else "split-bf16x3" if x3 else "split-bf16"
     sub = args.sub_cull
     if sub and (split or leaf != 64):
         print("--sub-cull needs FP32 precision and a 64 x 64 leaf workload", file=sys.stderr)
@@ -951,14 +973,15 @@ def main() -> int:
         out["roofline"]["traffic"] = measured_sub_traffic(wl.name, tau)
     if split:
         # the split kernel moves whole 16-bit leaves: rate it against HBM
-        tb = measured_split_traffic(wl.name, tau, args.theta, "fp16" if f16 else "bf16")
+        tb = measured_split_traffic(wl.name, tau, args.theta,
+                                    "fp16" if f16 else "bf16x3" if x3 else "bf16")
         gbs = tb / (gemm_ms * 1e-3) / 1e9 if tb is not None else None
-        out["dtype"] = "f32+f16" if f16 else "f32+bf16"
-        out["config"]["precision"] = "split-fp16" if f16 else "split-bf16"
+        out["dtype"] = "f32+f16" if f16 else "bf16" if x3 else "f32+bf16"
+        out["config"]["precision"] = split_kind
         out["config"]["theta"] = args.theta
         out["config"]["tasks_low"] = st["tasks_low"]
         out["roofline"] = {
-            "kernel": gemm_kernel_name("split-fp16" if f16 else "split-bf16", leaf, d),
+            "kernel": gemm_kernel_name(split_kind, leaf, d),
             "bound": "hbm", "achieved": round(gbs, 1) if gbs else None, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4) if gbs else None, "traffic": tb,
         }

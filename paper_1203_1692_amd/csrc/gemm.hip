@@ -76,12 +76,15 @@ __device__ inline void load_entries(const uint32_t *__restrict__ bent, uint32_t 
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (bid mod 8).  Deal
-// the blocks out in chunks of 4 consecutive ones (linear-index order: a
-// 2 x 2 patch of blocks), one chunk of each group of 8 to every XCD, each
-// XCD taking its chunks in order: neighbours share an XCD's L2, and every
-// XCD samples the whole matrix.  (Chunks of 4 against 16: 301.5 against
-// 305.1 ms for the FP32 product and 20.9 against 21.6 ms for the BF16 split
-// one at n = 32768; 32 and 64 were slower still.)  The chunk an XCD takes from group g is
+// the blocks out in chunks of kChunk consecutive ones (linear-index order: a
+// square or 2:1 patch of blocks), one chunk of each group of 8 to every XCD,
+// each XCD taking its chunks in order: neighbours share an XCD's L2, and
+// every XCD samples the whole matrix.  The 2 x 2-block kernels take chunks of
+// 16 (their FP16 split product is bound by HBM, and smaller chunks raised
+// its traffic by 8 %), the 4 x 4-block ones chunks of 4, which balance the
+// heavy diagonal blocks better (301.5 against 305.1 ms for the FP32 product
+// and 20.9 against 21.6 ms for the BF16 split one at n = 32768; chunks of 32
+// and 64 were slower still).  The chunk an XCD takes from group g is
 // rotated by g: chunk c mod 8 is three bits of the linear index, and on the
 // diagonal (i = j) two of them are equal, so a fixed c mod 8 gave the
 // diagonal's heavy blocks to half of the XCDs (rotated: 305.5 against 314.8
@@ -89,14 +92,15 @@ __device__ inline void load_entries(const uint32_t *__restrict__ bent, uint32_t 
 // the linear index put the two off-diagonal quadrants, where decaying
 // products are few, on half of the XCDs: with split precision the busiest
 // XCD then held 1.2x its share of the LOW products and 1.8x of the HIGH ones.)
+template <uint32_t kChunk>
 __device__ inline uint32_t xcd_block(uint32_t bid, uint32_t nblocks)
 {
-    constexpr uint32_t kChunk = 4;
     if (nblocks % (8u * kChunk) != 0u)
         return bid;
     const uint32_t x = bid % 8u, s = bid / 8u, g = s / kChunk;
     return (g * 8u + ((x + g) & 7u)) * kChunk + s % kChunk;
 }
+constexpr uint32_t kChunk2 = 16, kChunk4 = 4;    // 2 x 2 and 4 x 4 blocks
 
 // Wave w copies panel p of operand leaf w (0: A_2I, 1: A_2I+1, 2: B_2J,
 // 3: B_2J+1) of entry `ent` into LDS at dst, if the entry's mask needs it.
@@ -378,7 +382,7 @@ __global__ __launch_bounds__(256) void leaf_gemm(const GemmJobs jobs)
     float *__restrict__ C = job.C;
     const int64_t n = job.n;
     const int single = job.single;
-    const uint32_t blk = xcd_block(blockIdx.x - job.block0, job.nblocks);
+    const uint32_t blk = xcd_block<kChunk2>(blockIdx.x - job.block0, job.nblocks);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int qa = w >> 1, qb = w & 1;
     uint32_t I0 = 0, J0 = 0;
@@ -470,7 +474,7 @@ __global__ __launch_bounds__(256) void leaf_gemm_sub(const GemmJobs jobs)
     const float *__restrict__ tA = (const float *)job.tA;
     const float *__restrict__ tBT = (const float *)job.tBT;
     const int single = job.single;
-    const uint32_t blk = xcd_block(blockIdx.x - job.block0, job.nblocks);
+    const uint32_t blk = xcd_block<kChunk2>(blockIdx.x - job.block0, job.nblocks);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int qa = w >> 1, qb = w & 1;
     uint32_t I0 = 0, J0 = 0;
@@ -734,7 +738,7 @@ __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
     extern __shared__ float smem[];        // the 16-bit stages, then the FP32 stages
     const GemmJob &job = jobs.job[job_of(jobs, blockIdx.x)];
     const int single = job.single;
-    const uint32_t blk = xcd_block(blockIdx.x - job.block0, job.nblocks);
+    const uint32_t blk = xcd_block<kChunk2>(blockIdx.x - job.block0, job.nblocks);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int qa = w >> 1, qb = w & 1;
     uint32_t I0 = 0, J0 = 0;
@@ -942,7 +946,7 @@ __global__ __launch_bounds__(1024) void leaf_gemm_split_wide(const GemmJobs jobs
     uint32_t *list = kmask + kMaxEnt;
     uint32_t *wsum = list + kMaxEnt;
     const GemmJob &job = jobs.job[job_of(jobs, blockIdx.x)];
-    const uint32_t P4 = xcd_block(blockIdx.x - job.block0, job.nblocks);
+    const uint32_t P4 = xcd_block<kChunk4>(blockIdx.x - job.block0, job.nblocks);
     const uint32_t I0 = 4 * lin_row(P4), J0 = 4 * lin_col(P4);
     // the wave index in a scalar register: every per-wave decision below
     // (copies, waits, the mask test) is then a scalar branch.  The waves of
@@ -1059,7 +1063,7 @@ __global__ __launch_bounds__(1024) void leaf_gemm_wide32(const GemmJobs jobs)
     uint32_t *list = kmask + kMaxEnt;
     uint32_t *wsum = list + kMaxEnt;
     const GemmJob &job = jobs.job[job_of(jobs, blockIdx.x)];
-    const uint32_t P4 = xcd_block(blockIdx.x - job.block0, job.nblocks);
+    const uint32_t P4 = xcd_block<kChunk4>(blockIdx.x - job.block0, job.nblocks);
     const uint32_t I0 = 4 * lin_row(P4), J0 = 4 * lin_col(P4);
     // waves of one SIMD own the leaves (i, (i + s) mod 4), as in the split kernel
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -1105,7 +1109,7 @@ __global__ __launch_bounds__(1024) void leaf_gemm_sub_wide(const GemmJobs jobs)
     uint32_t *stl = (uint32_t *)((char *)subm + SubWideShape::kMasks);
     uint32_t *wsum = stl + 2 * kMaxEnt;
     const GemmJob &job = jobs.job[job_of(jobs, blockIdx.x)];
-    const uint32_t P4 = xcd_block(blockIdx.x - job.block0, job.nblocks);
+    const uint32_t P4 = xcd_block<kChunk4>(blockIdx.x - job.block0, job.nblocks);
     const uint32_t I0 = 4 * lin_row(P4), J0 = 4 * lin_col(P4);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int r = w >> 2, c = (r + (w & 3)) & 3;
