@@ -792,13 +792,15 @@ __global__ __launch_bounds__(256) void leaf_gemm_split(const GemmJobs jobs)
 // four 2 x 2 children's lists; the block merges them in LDS into one list
 // per class of (k | 16-bit mask << 16), k ascending.
 //
-// Stages are half leaves (one 32-wide k-panel of Leaf16Layout, 4 KB) of the
-// up to 4 A leaves (rows) and 4 B leaves (columns) an entry needs: 32 KB per
-// stage in a 4-deep LDS ring, three stages in flight while one is multiplied
-// (the workgroup fills the CU, so its own prefetch must cover the copies'
-// latency).  A wave waits only for its own copies of the stage it needs
-// (vmcnt counts exactly its outstanding copies), then the barrier makes every
-// wave's copies visible.  Then the block's HIGH products (few, and
+// A stage is the whole 16-bit leaves (8 KB, both k-panels of Leaf16Layout) of
+// the up to 4 A leaves (rows) and 4 B leaves (columns) an entry needs: 64 KB
+// in a 2-deep LDS ring, the next entry's copies in flight while one is
+// multiplied.  A wave waits by vmcnt for its own copies, then the barrier makes
+// every wave's copies visible.  (Half leaves in a 4-deep ring, three stages in
+// flight, were 8 % slower: the LOW phase is bound by each stage's fixed cost
+// -- the barrier, the LDS latency before the first MFMA -- against the MFMA
+// work of the busiest SIMD, small when an entry holds few products, not by
+// the copies' latency.)  Then the block's HIGH products (few, and
 // concentrated in the blocks along the diagonal) on FP32 MFMA: stages of the
 // FP32 k-panels (8 KB each, 64 KB per stage) in a 2-deep ring over the same
 // LDS.  One running FP32 sum per leaf: its LOW products over k ascending,
@@ -822,12 +824,11 @@ __device__ inline void barrier_no_fence()
     __asm__ volatile("" ::: "memory");
 }
 
-constexpr int kWideRing = 4;                          // LOW stages in the ring
-constexpr int kWideStage16 = 8 * Leaf16Layout<64>::kPanel;   // 16-bit values per LOW stage
+constexpr int kWideStage16 = 8 * 64 * 64;                   // 16-bit values per LOW stage
 constexpr int kWideStage32 = 8 * LeafLayout<64>::kPanel;     // floats per HIGH stage
 
 struct WideShape {
-    static constexpr size_t kRing = sizeof(uint16_t) * kWideRing * kWideStage16;   // 128 KB
+    static constexpr size_t kRing = sizeof(uint16_t) * 2 * kWideStage16;   // 128 KB
     static_assert(kRing == sizeof(float) * 2 * kWideStage32, "the HIGH ring reuses the LOW one");
     static constexpr size_t kMask = sizeof(uint32_t) * kMaxEnt;
     static constexpr size_t kList = sizeof(uint32_t) * kMaxEnt;
@@ -971,78 +972,68 @@ __global__ __launch_bounds__(1024) void leaf_gemm_split_wide(const GemmJobs jobs
         for (int j = 0; j < MB; ++j)
             acc[i][j] = floatx16{0};
 
-    // ---- LOW products: 16-bit half-leaf panels, 4-deep ring ----------------
+    // ---- LOW products: whole 16-bit leaves, 2-deep ring ------------------------
     const uint32_t nlo = merge_children(job.browptr_lo, job.bent_lo, P4, NK, kmask, list, wsum);
-    // wave w copies half (w & 1) of panel w >> 1 (0..3: A rows, 4..7: B
-    // columns): two 1 KB direct-to-LDS copies, or none if no leaf needs it
+    // wave w copies rows 32 (w & 1) .. +31 of both k-panels of operand leaf
+    // w >> 1 (0..3: A rows, 4..7: B columns): four 1 KB direct-to-LDS copies,
+    // or none if no leaf of the entry needs it
     const int pan = w >> 1, part = w & 1;
-    auto issue_lo = [&](uint32_t st) -> int {
-        const uint32_t ent = list[st >> 1], k = ent & 0xFFFFu, m = ent >> 16;
+    auto issue_lo = [&](uint32_t st) {
+        const uint32_t ent = list[st], k = ent & 0xFFFFu, m = ent >> 16;
         const uint32_t need = pan < 4 ? (m >> (4 * pan)) & 0xFu : (m >> (pan - 4)) & 0x1111u;
         if (need == 0u)
-            return 0;
+            return;
         const uint16_t *leaf =
             pan < 4 ? tA16 + leaf_slot(job.slotA, lin_index(I0 + pan, k)) * (B * B)
                     : tBT16 + leaf_slot(job.slotB, lin_index(k, J0 + (pan - 4))) * (B * B);
-        const uint16_t *src = leaf + (st & 1u) * P16 + part * (P16 / 2) + 8 * lane;
-        uint16_t *dst = ring16 + (st % kWideRing) * kWideStage16 + pan * P16 + part * (P16 / 2);
+        uint16_t *dst = ring16 + (st & 1u) * kWideStage16 + pan * (B * B) + part * (P16 / 2);
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-            __builtin_amdgcn_global_load_lds((global_void_t *)(src + 512 * i),
-                                             (lds_void_t *)(dst + 512 * i), 16, 0, 0);
-        return 2;
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                __builtin_amdgcn_global_load_lds(
+                    (global_void_t *)(leaf + p * P16 + part * (P16 / 2) + 512 * i + 8 * lane),
+                    (lds_void_t *)(dst + p * P16 + 512 * i), 16, 0, 0);
     };
-    const uint32_t S = 2 * nlo;
-    int c1 = 0, c2 = 0, c3 = 0;          // copies this wave issued for stages t+1, t+2 (t+3)
-    if (S > 0)
+    if (nlo > 0)
         issue_lo(0);
-    if (S > 1)
-        c1 = issue_lo(1);
-    if (S > 2)
-        c2 = issue_lo(2);
     const int row = lane & 31, h = lane >> 5;
-    for (uint32_t t = 0; t < S; ++t) {
-        // this wave's copies of stage t have landed once at most those of
-        // stages t+1 and t+2 are outstanding
-        const int later = c1 + c2;
-        if (later == 0)
-            __builtin_amdgcn_s_waitcnt(0x0F70);         // vmcnt(0)
-        else if (later == 2)
-            __builtin_amdgcn_s_waitcnt(0x0F72);         // vmcnt(2)
-        else
-            __builtin_amdgcn_s_waitcnt(0x0F74);         // vmcnt(4)
+    for (uint32_t t = 0; t < nlo; ++t) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);             // vmcnt(0): this wave's copies of t
         barrier_no_fence();
-        // stage t+3 goes to the buffer every wave finished reading at t-1
-        c3 = t + 3 < S ? issue_lo(t + 3) : 0;
-        const uint32_t ent = list[t >> 1];
+        // entry t+1 goes to the buffer every wave finished reading at t-1
+        if (t + 1 < nlo)
+            issue_lo(t + 1);
+        const uint32_t ent = list[t];
         if ((ent >> (16 + bit)) & 1u) {
-            const uint16_t *buf = ring16 + (t % kWideRing) * kWideStage16;
-            const uint16_t *Ap = buf + r * P16;
-            const uint16_t *Bp = buf + (4 + c) * P16;
-            bf16x8 av[2][MB], bv[2][MB];
+            const uint16_t *buf = ring16 + (t & 1u) * kWideStage16;
 #pragma unroll
-            for (int st = 0; st < 2; ++st) {
-                const int col = 16 * st + 8 * h;
+            for (int p = 0; p < 2; ++p) {
+                const uint16_t *Ap = buf + r * (B * B) + p * P16;
+                const uint16_t *Bp = buf + (4 + c) * (B * B) + p * P16;
+                bf16x8 av[2][MB], bv[2][MB];
 #pragma unroll
-                for (int i = 0; i < MB; ++i)
-                    av[st][i] = *reinterpret_cast<const bf16x8 *>(
-                        Ap + Leaf16Layout<B>::index(i * 32 + row, col));
+                for (int st = 0; st < 2; ++st) {
+                    const int col = 16 * st + 8 * h;
 #pragma unroll
-                for (int j = 0; j < MB; ++j)
-                    bv[st][j] = *reinterpret_cast<const bf16x8 *>(
-                        Bp + Leaf16Layout<B>::index(j * 32 + row, col));
-            }
-#pragma unroll
-            for (int st = 0; st < 2; ++st)
-#pragma unroll
-                for (int i = 0; i < MB; ++i)
+                    for (int i = 0; i < MB; ++i)
+                        av[st][i] = *reinterpret_cast<const bf16x8 *>(
+                            Ap + Leaf16Layout<B>::index(i * 32 + row, col));
 #pragma unroll
                     for (int j = 0; j < MB; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[st][i], bv[st][j],
-                                                                            acc[i][j], 0, 0, 0);
+                        bv[st][j] = *reinterpret_cast<const bf16x8 *>(
+                            Bp + Leaf16Layout<B>::index(j * 32 + row, col));
+                }
+#pragma unroll
+                for (int st = 0; st < 2; ++st)
+#pragma unroll
+                    for (int i = 0; i < MB; ++i)
+#pragma unroll
+                        for (int j = 0; j < MB; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                av[st][i], bv[st][j], acc[i][j], 0, 0, 0);
+            }
         }
-        c1 = c2;
-        c2 = c3;
     }
     __syncthreads();                      // every wave is done with the LOW ring and list
 
