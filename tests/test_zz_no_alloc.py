@@ -29,7 +29,8 @@ def decay(n, rate, seed, sym=True):
 
 def trees(gpu, A, B, leaf, prec, sub):
     import torch
-    kw = dict(bf16=prec == gpu.PREC_SPLIT_BF16, fp16=prec == gpu.PREC_SPLIT_FP16, subnorms=sub)
+    kw = dict(bf16=prec in (gpu.PREC_SPLIT_BF16, gpu.PREC_SPLIT_BF16X3),
+              fp16=prec == gpu.PREC_SPLIT_FP16, subnorms=sub)
     dA = torch.from_numpy(A).cuda()
     tA = gpu.build_tree(dA, leaf, **kw)
     tB = tA if B is None else gpu.build_tree(torch.from_numpy(B).cuda(), leaf, **kw)
@@ -73,6 +74,10 @@ CASES = {
     "fp32-b32": lambda g: (workloads.exp_decay(1024, 0.1, 0), None, 32, 1e-6, 0, 0.0, False),
     "bf16-rel": lambda g: (decay(900, 0.03, 3), None, 64, 1e-6, g.PREC_SPLIT_BF16, 1e-3, False),
     "fp16-rel": lambda g: (decay(777, 0.05, 4), None, 32, 1e-7, g.PREC_SPLIT_FP16, 1e-3, False),
+    "bf16x3-rel": lambda g: (decay(900, 0.03, 10), None, 64, 1e-6, g.PREC_SPLIT_BF16X3, 1e-3,
+                             False),
+    "bf16x3-rel-b32": lambda g: (decay(600, 0.05, 11), None, 32, 1e-7, g.PREC_SPLIT_BF16X3, 1e-3,
+                                 False),
     "subleaf-b64": lambda g: (decay(1500, 0.02, 5), None, 64, 1e-5, 0, 0.0, True),
     "nonsym-b16": lambda g: (decay(400, 0.05, 6, sym=False), decay(400, 0.08, 7, sym=False), 16,
                              1e-5, 0, 0.0, False),
