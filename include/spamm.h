@@ -112,10 +112,13 @@ int spamm_build_tree(const float *A, int64_t n, int32_t leaf, void *stream,
  *              FP32 accumulation (the three-product bfloat16 method of
  *              Henry, Tang and Heinecke, ARITH 2019): within 2^-14 |a||b|
  *              of the exact product per term, against FP32's exact products,
- *              at about a fifth of the matrix-unit time.  Entries must be
- *              below 2^128 (1 - 2^-9) in magnitude (larger ones overflow
- *              their bfloat16 part and the result is not finite); it needs
- *              trees built with SPAMM_TREE_BF16, like SPLIT_BF16.
+ *              at about a fifth of the matrix-unit time.  An entry at or
+ *              above 2^128 (1 - 2^-9) in magnitude would overflow its
+ *              bfloat16 part, so SPLIT_BF16X3 refuses operands whose squared
+ *              Frobenius norm reaches (2^128 (1 - 2^-9))^2 with SPAMM_E_RANGE
+ *              (spamm_symbolic_ex; the server reports it as the request's
+ *              status, C then undefined).  It needs trees built with
+ *              SPAMM_TREE_BF16, like SPLIT_BF16.
  *   low_tol    split only: a kept product A_ik B_kj is LOW iff
  *              fl64(s_A s_B) < fl64(low_tol^2) on the stored squared norms,
  *              i.e. ||A_ik||_F ||B_kj||_F < low_tol; LOW products use BF16

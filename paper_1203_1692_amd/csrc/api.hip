@@ -515,6 +515,12 @@ static int plan_setup(spamm_plan *p, const spamm_tree *A, const spamm_tree *B,
                     : opts->precision == SPAMM_PREC_SPLIT_BF16X3 ? "SPLIT_BF16X3"
                                                                  : "SPLIT_BF16",
                     want16 ? "SPAMM_TREE_FP16" : "SPAMM_TREE_BF16");
+    if (opts->precision == SPAMM_PREC_SPLIT_BF16X3 &&
+        (A->root >= kX3MaxRoot2 || B->root >= kX3MaxRoot2))
+        return fail(SPAMM_E_RANGE,
+                    "SPLIT_BF16X3: ||A||_F^2 = %g, ||B||_F^2 = %g; an entry could overflow its "
+                    "bfloat16 part (squared norms must stay below %g)",
+                    A->root, B->root, kX3MaxRoot2);
     if (opts->sub_cull != 0 && opts->sub_cull != 1)
         return fail(SPAMM_E_INVAL, "sub_cull = %d not in {0, 1}", opts->sub_cull);
     const bool sub = opts->sub_cull == 1;

@@ -62,6 +62,11 @@ inline uint32_t tree_flags_for(int32_t precision)
 }
 size_t plan_device_bytes(int depth, bool split);
 
+// SPAMM_PREC_SPLIT_BF16X3: an entry at or above 2^128 (1 - 2^-9) rounds to
+// an infinite bfloat16 part.  No entry reaches it while the operand's squared
+// Frobenius norm stays below the square of that bound.
+constexpr double kX3MaxRoot2 = (1.0 - 1.0 / 512) * (1.0 - 1.0 / 512) * 0x1p256;
+
 // Leaf GEMM launches (gemm.hip): a plan's job and kind, and one batched
 // launch of jobs of one kind and leaf size.
 void plan_jobs(const spamm_plan *p, float *C, GemmJob &j);

@@ -580,6 +580,11 @@ void finish(spamm_server *S, Active &a)
                 res.status = SPAMM_E_NONFINITE;
                 break;
             }
+            if (a.job.rq.precision == SPAMM_PREC_SPLIT_BF16X3 &&
+                (P.step[s].root[0] >= kX3MaxRoot2 || P.step[s].root[1] >= kX3MaxRoot2)) {
+                res.status = SPAMM_E_RANGE;
+                break;
+            }
             res.tasks += (int64_t)(P.step[s].K[0] + P.step[s].K[1]);
             res.tasks_low += (int64_t)P.step[s].K[1];
         }

@@ -190,3 +190,32 @@ def test_x3_argument_errors(gpu):
     sub = gpu.build_tree(dA, 64, bf16=True, subnorms=True)
     with pytest.raises(gpu.SpammError):
         gpu.symbolic(sub, sub, 1e-6, precision=gpu.PREC_SPLIT_BF16X3, sub_cull=True)
+
+
+def test_x3_refuses_entries_that_overflow_their_bf16_part(gpu):
+    """An entry at or above 2^128 (1 - 2^-9) rounds to an infinite bfloat16
+    part: the compensated mode refuses operands whose squared norm reaches
+    the square of that bound, on the one-call path and in the server."""
+    import torch
+    A = decay(200, 0.1, 12)
+    A[3, 3] = np.float32(2.0 ** 128 * (1 - 2.0 ** -9))   # rounds to an infinite bfloat16
+    assert float(A[3, 3]) == 2.0 ** 128 * (1 - 2.0 ** -9)
+    dA = torch.from_numpy(A).cuda()
+    t = gpu.build_tree(dA, 32, bf16=True)
+    with pytest.raises(gpu.SpammError) as ei:
+        gpu.symbolic(t, t, 1e-6, precision=gpu.PREC_SPLIT_BF16X3, low_rel=1e-3)
+    assert ei.value.code == gpu.SPAMM_E_RANGE
+    # the plain BF16 split takes it (its HIGH products stay FP32)
+    gpu.symbolic(t, t, 1e-6, precision=gpu.PREC_SPLIT_BF16, low_rel=1e-3).free()
+    # just below the bound of the norm: accepted
+    B = decay(200, 0.1, 12)
+    B[3, 3] = np.float32(1e38)
+    tb = gpu.build_tree(torch.from_numpy(B).cuda(), 32, bf16=True)
+    gpu.symbolic(tb, tb, 1e-6, precision=gpu.PREC_SPLIT_BF16X3, low_rel=1e-3).free()
+    srv = gpu.Server(2 << 30, max_slots=2)
+    try:
+        C = torch.empty_like(dA)
+        r = srv.wait(srv.submit(dA, C, 1e-6, 32, precision=gpu.PREC_SPLIT_BF16X3, low_rel=1e-3))
+        assert r["status"] == gpu.SPAMM_E_RANGE
+    finally:
+        srv.destroy()
