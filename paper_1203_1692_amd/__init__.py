@@ -1,7 +1,9 @@
 """MI355X-native SpAMM: quadtree norm build, tier-by-tier cull and an
-FP32-MFMA leaf GEMM (one workgroup per block of output leaves; split BF16 /
-FP16 and sub-leaf variants) behind the C ABI of include/spamm.h, plus a
-continuous-batching server for products and squaring chains."""
+FP32-MFMA leaf GEMM (one workgroup per block of output leaves; split
+precision with BF16 LOW products and FP32 or compensated-BF16 HIGH ones, or
+scaled FP16 LOW products; sub-leaf culling) behind the C ABI of
+include/spamm.h, plus a continuous-batching server for products and squaring
+chains."""
 from ._binding import (  # noqa: F401
     HEADER, LIB_PATH, PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_BF16X3, PREC_SPLIT_FP16, SPAMM_E_BUSY, SPAMM_E_HIP, SPAMM_E_INVAL,
     SPAMM_E_MISMATCH, SPAMM_E_NOMEM, SPAMM_E_NONFINITE, SPAMM_E_RANGE, SPAMM_OK, SPAMM_PENDING,
