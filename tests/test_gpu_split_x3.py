@@ -12,7 +12,10 @@ oracle's bf16x3 mode.
   leaves below depth 2 (2 x 2 blocks) and from depth 2 (4 x 4 blocks);
 * low_tol = 0 (every product HIGH) is within 2^-14 sum |a||b| of the exact
   product, and closer to it than BF16 operands alone;
-* the HIGH products differ from the FP32 kernel's only by that error.
+* the HIGH products differ from the FP32 kernel's only by that error;
+* with every product LOW the mode is the BF16 split bit for bit; nothing
+  kept writes zeros; entries that would overflow their bfloat16 part are
+  refused (SPAMM_E_RANGE), on the one-call path and in the server.
 """
 import numpy as np
 import pytest
@@ -219,3 +222,29 @@ def test_x3_refuses_entries_that_overflow_their_bf16_part(gpu):
         assert r["status"] == gpu.SPAMM_E_RANGE
     finally:
         srv.destroy()
+
+
+@pytest.mark.parametrize("n,leaf", [(300, 32), (700, 64)])
+def test_x3_all_low_is_the_bf16_split_bit_for_bit(gpu, n, leaf):
+    """With every product LOW the compensated mode runs only BF16 products,
+    in the same order as the BF16 split (2 x 2 and 4 x 4 kernels)."""
+    import torch
+    A = decay(n, 0.05, 13)
+    dA = torch.from_numpy(A).cuda()
+    t = gpu.build_tree(dA, leaf, bf16=True)
+    C3, Cb = torch.empty_like(dA), torch.empty_like(dA)
+    s3 = gpu.multiply_ex(t, t, 1e-6, C3, precision=gpu.PREC_SPLIT_BF16X3, low_tol=1e30)
+    sb = gpu.multiply_ex(t, t, 1e-6, Cb, precision=gpu.PREC_SPLIT_BF16, low_tol=1e30)
+    assert s3["tasks_low"] == s3["tasks"] == sb["tasks"] > 0
+    assert torch.equal(C3.view(torch.int32), Cb.view(torch.int32))
+
+
+def test_x3_nothing_kept_writes_zeros(gpu):
+    import torch
+    A = decay(400, 0.1, 14)
+    dA = torch.from_numpy(A).cuda()
+    t = gpu.build_tree(dA, 64, bf16=True)
+    C = torch.full_like(dA, float("nan"))
+    st = gpu.multiply_ex(t, t, 1e3, C, precision=gpu.PREC_SPLIT_BF16X3, low_rel=1e-3)
+    assert st["tasks"] == 0
+    assert torch.count_nonzero(C).item() == 0
