@@ -1,6 +1,7 @@
 """A seeded random sweep of the GPU path against the oracle: odd n (1 .. 1500),
 all leaf sizes, tau from 0 to 1e-2, decay rates from dense to nearly
-diagonal, A = B or distinct B, FP32 and both split precisions.
+diagonal, A = B or distinct B, FP32 and the three split precisions (BF16,
+BF16 with compensated HIGH products, FP16).
 
 For every case: the sorted task keys (class bit included) bit-exact, kept and
 LOW counts equal, and C within Higham's elementwise bound around the oracle's
@@ -35,6 +36,18 @@ def make_cases(count=36, seed=2024, nmax=700, first=0):
 CASES = make_cases() + make_cases(count=24, seed=2025, nmax=1500, first=36)
 
 
+def make_x3_cases(count=24, seed=2028, nmax=1200, first=400):
+    rng = np.random.default_rng(seed)
+    return [dict(id=c, n=int(rng.integers(1, nmax + 1)), leaf=int(rng.choice([32, 64])),
+                 prec="bf16x3", tau=float(rng.choice([0.0, 1e-8, 1e-6, 1e-4, 1e-2])),
+                 rate=float(rng.uniform(0.0, 0.5)), distinct=bool(rng.random() < 0.4),
+                 theta=float(rng.choice([1e-3, 1e-1, 1e-5])), seed=int(rng.integers(1 << 30)))
+            for c in range(first, first + count)]
+
+
+X3_CASES = make_x3_cases()
+
+
 def matrix(n, rate, seed, transpose=False):
     rng = np.random.default_rng(seed)
     i = np.arange(n)
@@ -44,7 +57,7 @@ def matrix(n, rate, seed, transpose=False):
 
 
 def low_operand(X, S, fmt):
-    if fmt == "bf16":
+    if fmt in ("bf16", "bf16x3"):
         import torch
         return torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(torch.bfloat16).to(
             torch.float64).numpy()
@@ -53,9 +66,31 @@ def low_operand(X, S, fmt):
     return np.where(np.abs(h) < 2.0 ** -14, 0.0, h) * 2.0 ** -e
 
 
+def high_operand(X, fmt):
+    """|hi| + |lo| of the two bfloat16 parts (compensated HIGH products), else X."""
+    if fmt != "bf16x3":
+        return X
+    import torch
+    X32 = np.ascontiguousarray(X, dtype=np.float32)
+    H = torch.from_numpy(X32).to(torch.bfloat16).to(torch.float32).numpy()
+    L = torch.from_numpy(X32 - H).to(torch.bfloat16).to(torch.float64).numpy()
+    return np.abs(H.astype(np.float64)) + np.abs(L)
+
+
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"c{c['id']}-n{c['n']}-b{c['leaf']}-{c['prec']}")
 def test_random_case(gpu, case):
+    check_case(gpu, case)
+
+
+@pytest.mark.parametrize("case", X3_CASES,
+                         ids=lambda c: f"x{c['id']}-n{c['n']}-b{c['leaf']}-{c['prec']}")
+def test_random_case_x3(gpu, case):
+    check_case(gpu, case)
+
+
+def check_case(gpu, case):
     import torch
+    print(f"[random] {case}", flush=True)
     n, leaf, prec, tau = case["n"], case["leaf"], case["prec"], case["tau"]
     A = matrix(n, case["rate"], case["seed"])
     B = matrix(n, case["rate"] * 1.5, case["seed"] + 1, transpose=True) if case["distinct"] else A
@@ -64,10 +99,11 @@ def test_random_case(gpu, case):
     low = case["theta"] * float(np.sqrt(sA[0][0, 0]) * np.sqrt(sB[0][0, 0])) if split else 0.0
     ref = oracle.spamm(A, B, leaf, tau, low_tol=low, low_fmt=prec if split else "bf16")
     dA = torch.from_numpy(A).cuda()
-    kw = dict(bf16=(prec == "bf16"), fp16=(prec == "fp16"))
+    kw = dict(bf16=(prec in ("bf16", "bf16x3")), fp16=(prec == "fp16"))
     tA = gpu.build_tree(dA, leaf, **kw)
     tB = tA if B is A else gpu.build_tree(torch.from_numpy(B).cuda(), leaf, **kw)
-    p = {"fp32": gpu.PREC_FP32, "bf16": gpu.PREC_SPLIT_BF16, "fp16": gpu.PREC_SPLIT_FP16}[prec]
+    p = {"fp32": gpu.PREC_FP32, "bf16": gpu.PREC_SPLIT_BF16, "fp16": gpu.PREC_SPLIT_FP16,
+         "bf16x3": gpu.PREC_SPLIT_BF16X3}[prec]
     plan = gpu.symbolic(tA, tB, tau, precision=p, low_tol=low)
     C = torch.full_like(dA, float("nan"))
     plan.numeric(C)
@@ -92,9 +128,12 @@ def test_random_case(gpu, case):
         Y = PB[k * leaf:(k + 1) * leaf, J * leaf:(J + 1) * leaf]
         if key >> 63:
             X, Y = low_operand(X, sA[-1][I, k], prec), low_operand(Y, sB[-1][k, J], prec)
+        else:
+            X, Y = high_operand(X, prec), high_operand(Y, prec)
         M[I * leaf:(I + 1) * leaf, J * leaf:(J + 1) * leaf] += np.abs(X) @ np.abs(Y)
         cnt[I, J] += 1
-    m = (leaf + (1 if prec == "fp16" else 0)) * np.kron(cnt, np.ones((leaf, leaf))) + 1
+    per = leaf + 1 if prec == "fp16" else 3 * leaf if prec == "bf16x3" else leaf
+    m = per * np.kron(cnt, np.ones((leaf, leaf))) + 1
     bound = (m * U32 / (1 - m * U32) * M + m * 2.0 ** -126)[:n, :n]
     got = C.cpu().numpy().astype(np.float64)
     assert np.all(np.isfinite(got))
