@@ -11,7 +11,10 @@ Prints one JSON line.  `value` is kept-leaf TFLOP/s over the whole step
 (2 n_b^3 K / step time).  `roofline` rates the leaf GEMM kernel (the dominant
 kernel) against the FP32 MFMA peak, with its duration from HIP events recorded
 around its launch on the stream it runs on.  `cpu_baseline` times the FP64
-oracle on a seeded sample of output leaves of the same matrix.  `serving`
+oracle on a seeded sample of output leaves of the same matrix.
+`matched_error` compares FP32 with the split precisions (BF16, BF16 with
+compensated HIGH products, FP16) and sub-leaf culling at the FP32 product's
+own whole-matrix error.  `serving`
 then drives a stream of 2000 products and squaring chains of uneven size
 through the continuous-batching server: saturation throughput, and p50/p99
 latency under Poisson arrivals at 0.5x and 0.8x of it (`--serve` runs only
