@@ -85,8 +85,8 @@ __host__ __device__ inline int leaf_index(int B, int r, int c)
 // panel at n_b = 32, two at 64), each panel row-major with rows of 32 values
 // (64 bytes: four 16-byte granules of 8 values); the granules of a row are
 // XOR-permuted by (r >> 2) & 3, so that 16 rows read at one logical column by
-// a ds_read_b128 hit 16 distinct groups of banks.  A panel (4 KB at n_b = 64)
-// is the unit the wide LOW kernel stages.
+// a ds_read_b128 hit 16 distinct groups of banks.  The wide LOW kernel stages
+// whole leaves (both panels, 8 KB at n_b = 64).
 template <int B>
 struct Leaf16Layout {
     static constexpr int kKS = 32;                               // panel width

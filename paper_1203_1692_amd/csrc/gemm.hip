@@ -252,9 +252,10 @@ __device__ inline void write_leaf16(const floatx4 &acc, int64_t row0, int64_t co
 // parts hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact in FP32), and a
 // product a b as hi_a hi_b + hi_a lo_b + lo_a hi_b on the BF16 matrix units
 // with FP32 accumulation -- the three-product bfloat16 method of Henry, Tang
-// and Heinecke (ARITH 2019), about 2^-16 |a b| from the exact product per
-// term where FP32 MFMA is exact; three 32x32x16 BF16 MFMAs replace eight
-// 32x32x2 FP32 ones.  A lane takes 8 consecutive k of its row (two 16-byte
+// and Heinecke (ARITH 2019), within 2^-14 |a||b| of the exact product per
+// term (the dropped lo_a lo_b and the parts below lo: about 3 2^-16) where
+// FP32 MFMA is exact; three 32x32x16 BF16 MFMAs replace eight 32x32x2 FP32
+// ones.  A lane takes 8 consecutive k of its row (two 16-byte
 // reads): lane half h of slice g covers k in [16 h + 8 g, 16 h + 8 g + 8), the
 // same for both operands, so each MFMA sums 16 distinct k of the panel.
 __device__ inline void bf16_parts4(floatx4 x, uint32_t *hi, uint32_t *lo)
