@@ -215,6 +215,44 @@ def matched_error(sp, torch, wl, dA, C, exact, tau, leaf, reps=2):
         sub_tree.free()
     floor = next(p["err"] for p in points if p["precision"] == "fp32" and p["tau"] == tau)
     kinds = ("fp32", "split-bf16", "split-bf16x3", "split-fp16", "fp32-subleaf")
+    # refinement: the paper adjusts each variant's tolerances until the errors
+    # match; around each variant's fastest grid point within the FP32
+    # product's error, its quarter-decade neighbours in tau (and theta)
+    seen = {(p["precision"], p["tau"], p["theta"]) for p in points}
+    todo = []
+    for k in kinds:
+        b = fastest_within(points, k, floor)
+        if b is None:
+            continue
+        for dt in (-1, 0, 1):
+            for dh in ((-1, 0, 1) if b["theta"] else (0,)):
+                key = (k, b["tau"] * 10.0 ** (dt / 4),
+                       b["theta"] * 10.0 ** (dh / 4) if b["theta"] else 0.0)
+                if (dt or dh) and key not in seen:
+                    todo.append(key)
+                    seen.add(key)
+    trees = {}
+    for k, t_, th in todo:
+        kw = ({"fp16": True} if k == "split-fp16" else
+              {"subnorms": True} if k == "fp32-subleaf" else {"bf16": True})
+        name = next(iter(kw))
+        if name not in trees:
+            trees[name] = sp.build_tree(dA, leaf, **kw)
+        prec = {"fp32": 0, "split-bf16": sp.PREC_SPLIT_BF16, "split-bf16x3": sp.PREC_SPLIT_BF16X3,
+                "split-fp16": sp.PREC_SPLIT_FP16, "fp32-subleaf": 0}[k]
+        (ms, g_ms, _), st = timed_product(sp, trees[name], t_, C, reps, prec, th,
+                                          sub_cull=k == "fp32-subleaf")
+        pt = {"precision": k, "tau": t_, "theta": th, "ms": round(ms, 3),
+              "ms_leaf_gemm": round(g_ms, 3), "err": max_err_full(C, exact),
+              "tasks": st["tasks"], "refined": True}
+        if k == "fp32-subleaf":
+            pt.update(sub_products=st["subtasks"],
+                      sub_fraction=round(st["subtasks"] / max(1, 8 * st["tasks"]), 4))
+        else:
+            pt["low_frac"] = round(st["tasks_low"] / max(1, st["tasks"]), 4)
+        points.append(pt)
+    for t in trees.values():
+        t.free()
 
     def at(target):
         best = {k: fastest_within(points, k, target) for k in kinds}
@@ -234,7 +272,9 @@ def matched_error(sp, torch, wl, dA, C, exact, tau, leaf, reps=2):
            "at_targets": {f"{t:g}": at(t) for t in TARGETS},
            "grid": "tau x 10^{0, 0.5, ..., 5}; theta in %s for the three split formats "
                    "(BF16, BF16 with compensated HIGH products, FP16); sub-leaf culling "
-                   "tau x 10^{-1, -0.5, ..., 4.5}" % (list(THETAS),)}
+                   "tau x 10^{-1, -0.5, ..., 4.5}; then, around each variant's fastest point "
+                   "within the FP32 product's error, its neighbours at tau x 10^{+-1/4} "
+                   "(and theta x 10^{+-1/4}): %d more points" % (list(THETAS), len(todo))}
     plain = next(p for p in points if p["precision"] == "fp32" and p["tau"] == tau)
     sub = [p for p in points if p["precision"] == "fp32-subleaf" and p["tau"] == tau]
     if sub:
