@@ -169,6 +169,27 @@ def fastest_within(points, kind, target):
     return min(ok, key=lambda p: p["ms"]) if ok else None
 
 
+def refine_candidates(points, kinds, target):
+    """(kind, tau, theta) of the quarter-decade neighbours (tau x 10^{-1/4,
+    0, 1/4}, and theta alike when the kind has one) of each kind's fastest
+    point within `target`, without the centre and without points already
+    measured."""
+    seen = {(p["precision"], p["tau"], p["theta"]) for p in points}
+    todo = []
+    for k in kinds:
+        b = fastest_within(points, k, target)
+        if b is None:
+            continue
+        for dt in (-1, 0, 1):
+            for dh in ((-1, 0, 1) if b["theta"] else (0,)):
+                key = (k, b["tau"] * 10.0 ** (dt / 4),
+                       b["theta"] * 10.0 ** (dh / 4) if b["theta"] else 0.0)
+                if (dt or dh) and key not in seen:
+                    todo.append(key)
+                    seen.add(key)
+    return todo
+
+
 def matched_error(sp, torch, wl, dA, C, exact, tau, leaf, reps=2):
     """FP32 against split precision (and sub-leaf culling) at the same
     max-norm error (Sec. IV.B, Sec. V.C: tolerances adjusted per variant until
@@ -218,19 +239,7 @@ def matched_error(sp, torch, wl, dA, C, exact, tau, leaf, reps=2):
     # refinement: the paper adjusts each variant's tolerances until the errors
     # match; around each variant's fastest grid point within the FP32
     # product's error, its quarter-decade neighbours in tau (and theta)
-    seen = {(p["precision"], p["tau"], p["theta"]) for p in points}
-    todo = []
-    for k in kinds:
-        b = fastest_within(points, k, floor)
-        if b is None:
-            continue
-        for dt in (-1, 0, 1):
-            for dh in ((-1, 0, 1) if b["theta"] else (0,)):
-                key = (k, b["tau"] * 10.0 ** (dt / 4),
-                       b["theta"] * 10.0 ** (dh / 4) if b["theta"] else 0.0)
-                if (dt or dh) and key not in seen:
-                    todo.append(key)
-                    seen.add(key)
+    todo = refine_candidates(points, kinds, floor)
     trees = {}
     for k, t_, th in todo:
         kw = ({"fp16": True} if k == "split-fp16" else

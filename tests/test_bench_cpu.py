@@ -97,3 +97,27 @@ def test_committed_sub_traffic_record_names_its_point():
     assert rec["tau"] > 0 and rec["bytes_per_launch"] > 0
     assert bench.measured_sub_traffic("cluster1310-n32750", rec["tau"] * 10) is None
     assert bench.measured_sub_traffic("other-workload", rec["tau"]) is None
+
+
+def test_refine_candidates_are_the_quarter_decade_neighbours():
+    pts = [
+        {"precision": "fp32", "tau": 1e-5, "theta": 0.0, "ms": 9.0, "err": 1.0},
+        {"precision": "fp32", "tau": 1e-4, "theta": 0.0, "ms": 5.0, "err": 1.0},     # fastest
+        {"precision": "fp32", "tau": 1e-3, "theta": 0.0, "ms": 2.0, "err": 3.0},     # too coarse
+        {"precision": "split-bf16", "tau": 1e-4, "theta": 1e-6, "ms": 1.0, "err": 0.5},
+        {"precision": "split-bf16", "tau": 1e-4, "theta": 1e-5, "ms": 0.5, "err": 9.0},
+        {"precision": "split-fp16", "tau": 1e-4, "theta": 1e-6, "ms": 1.0, "err": 9.0},  # none within
+    ]
+    got = bench.refine_candidates(pts, ("fp32", "split-bf16", "split-fp16"), 1.0)
+    q = 10.0 ** 0.25
+    fp32 = sorted(t for k, t, h in got if k == "fp32")
+    assert len(fp32) == 2 and abs(fp32[0] * q / 1e-4 - 1) < 1e-12 and abs(fp32[1] / q / 1e-4 - 1) < 1e-12
+    assert all(h == 0.0 for k, t, h in got if k == "fp32")
+    split = [(t, h) for k, t, h in got if k == "split-bf16"]
+    assert len(split) == 8 and (1e-4, 1e-6) not in split
+    assert {round(t / 1e-4, 6) for t, h in split} == {round(1 / q, 6), 1.0, round(q, 6)}
+    assert not any(k == "split-fp16" for k, t, h in got)
+    # a neighbour already measured is not repeated
+    pts.append({"precision": "fp32", "tau": 1e-4 * q, "theta": 0.0, "ms": 6.0, "err": 2.0})
+    again = bench.refine_candidates(pts, ("fp32",), 1.0)
+    assert len(again) == 1
