@@ -50,7 +50,8 @@ def test_source_digest_covers_the_kernel_and_its_build_flags():
 
 def test_committed_split_traffic_records_name_their_point():
     import glob
-    for kind, fmt in (("leaf_gemm_split", "bf16"), ("leaf_gemm_split_fp16", "fp16")):
+    for kind, fmt in (("leaf_gemm_split", "bf16"), ("leaf_gemm_split_fp16", "fp16"),
+                      ("leaf_gemm_split_x3", "bf16x3")):
         paths = sorted(glob.glob(os.path.join(
             ROOT, "profiles", f"{kind}_cluster1310-n32750*_traffic.json")))
         assert paths
@@ -121,3 +122,18 @@ def test_refine_candidates_are_the_quarter_decade_neighbours():
     pts.append({"precision": "fp32", "tau": 1e-4 * q, "theta": 0.0, "ms": 6.0, "err": 2.0})
     again = bench.refine_candidates(pts, ("fp32",), 1.0)
     assert len(again) == 1
+
+
+@pytest.mark.parametrize("precision,sub,page", [
+    ("fp32", False, "kernels_cluster1310-n32750_trace.md"),
+    ("split-bf16", False, "kernels_split_cluster1310-n32750_trace.md"),
+    ("split-bf16x3", False, "kernels_split_x3_cluster1310-n32750_trace.md"),
+    ("split-fp16", False, "kernels_split_fp16_cluster1310-n32750_trace.md"),
+    ("fp32", True, "kernels_subleaf_cluster1310-n32750_trace.md"),
+])
+def test_reported_kernel_names_are_the_traced_ones(precision, sub, page):
+    # the bench reports each variant's roofline under the name rocprofv3
+    # printed for the kernel the library launched (leaf 64, depth 9)
+    name = bench.gemm_kernel_name(precision, 64, 9, sub)
+    text = open(os.path.join(ROOT, "profiles", page)).read()
+    assert f"spamm::{name}" in text
