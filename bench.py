@@ -54,12 +54,43 @@ GEMM_SOURCES = ("paper_1203_1692_amd/csrc/gemm.hip", "paper_1203_1692_amd/csrc/c
                 "paper_1203_1692_amd/_build.py")
 
 
+def code_only(text: str) -> str:
+    """C++ source without its comments, trailing blanks and empty lines
+    (string and character literals kept whole): what the compiler sees."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    lines = (line.rstrip() for line in "".join(out).split("\n"))
+    return "\n".join(line for line in lines if line)
+
+
 def kernel_source_digest() -> str:
-    """SHA-256 over the leaf GEMM's source, its layout header and build flags."""
+    """SHA-256 over the leaf GEMM's source and its layout header (code only:
+    a comment edit does not change the kernel the counters were taken on) and
+    the build flags file (every byte)."""
     h = hashlib.sha256()
     for rel in GEMM_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+            data = f.read()
+        if not rel.endswith(".py"):
+            data = code_only(data.decode("utf-8")).encode("utf-8")
+        h.update(data)
     return h.hexdigest()
 
 

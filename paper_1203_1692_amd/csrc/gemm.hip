@@ -1,6 +1,7 @@
 // Numeric multiply: C_ij = sum over kept k (ascending) of A_ik B_kj
-// (Eq. product, Alg. 1 steps 7-9) on FP32 MFMA with FP32 accumulation; with
-// split precision the LOW products run on BF16 or FP16 MFMA in the same kernel.
+// (Eq. product; the multiply phase of Alg. 1) on FP32 MFMA with FP32
+// accumulation; with split precision the LOW products run on BF16 or FP16
+// MFMA in the same kernel.
 //
 // Ownership.  A workgroup of 4 waves owns one block of 2 x 2 output leaves
 // (the children of one tier-(d-1) tile); wave q = 2a + b owns leaf
@@ -883,7 +884,7 @@ __device__ inline uint32_t merge_children(const uint32_t *__restrict__ rp,
         if (m != 0u)
             list[base + before + (uint32_t)__popcll(bal & lanes_below())] = k | (m << 16);
         base += total;
-        __syncthreads();                     // wsum is rewritten next round
+        __syncthreads();                     // wsum is rewritten by the next pass
     }
     return base;
 }
@@ -1179,7 +1180,7 @@ __global__ __launch_bounds__(1024) void leaf_gemm_sub_wide(const GemmJobs jobs)
         if (tk != 0u)
             stl[T + before + (uint32_t)__popcll(bal & lanes_below())] = (idx << 16) | tk;
         T += total;
-        __syncthreads();                       // wsum is rewritten next round
+        __syncthreads();                       // wsum is rewritten by the next pass
     }
 
     // ---- staged sub-products: FP32 k-panels, 64 KB stages, 2-deep ring ---------

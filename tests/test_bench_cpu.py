@@ -137,3 +137,40 @@ def test_reported_kernel_names_are_the_traced_ones(precision, sub, page):
     name = bench.gemm_kernel_name(precision, 64, 9, sub)
     text = open(os.path.join(ROOT, "profiles", page)).read()
     assert f"spamm::{name}" in text
+
+
+def test_code_only_digest_ignores_comments_and_sees_code():
+    src = ('// header\n#include "a.h"  // trailing\nint f(int x) {   /* block\n spans */ return x;'
+           '\n\n  const char *s = "// kept /* kept */"; char q = \'"\';  \n}\n')
+    got = bench.code_only(src)
+    assert got == ('#include "a.h"\nint f(int x) {     return x;\n'
+                   '  const char *s = "// kept /* kept */"; char q = \'"\';\n}')
+    assert bench.code_only(src.replace("header", "other words")) == got
+    assert bench.code_only(src.replace("return x", "return -x")) != got
+    # a block comment between two tokens keeps them apart
+    assert bench.code_only("a/**/b") == "a b"
+    # the kernel sources' comments and code are told apart as the compiler
+    # would: nothing after stripping looks like a comment opener outside a string
+    for rel in bench.GEMM_SOURCES:
+        if rel.endswith(".py"):
+            continue
+        code = bench.code_only(open(os.path.join(ROOT, rel)).read())
+        assert "//" not in code and "/*" not in code
+
+
+def test_code_only_agrees_with_the_preprocessors_comment_removal():
+    import re
+    import shutil
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no g++")
+    for rel in bench.GEMM_SOURCES:
+        if rel.endswith(".py"):
+            continue
+        path = os.path.join(ROOT, rel)
+        # -fpreprocessed: remove comments, expand nothing (it drops a main
+        # file's #pragma once, the one other difference)
+        cpp = subprocess.run([gxx, "-x", "c++", "-fpreprocessed", "-dD", "-E", "-P", path],
+                             capture_output=True, text=True, check=True).stdout
+        mine = bench.code_only(open(path).read()).replace("#pragma once", "")
+        assert re.sub(r"\s+", "", mine) == re.sub(r"\s+", "", cpp), rel
