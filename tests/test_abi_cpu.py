@@ -30,6 +30,20 @@ def test_header_status_codes_match_binding():
     assert codes["SPAMM_PENDING"] == sp.SPAMM_PENDING
 
 
+def test_header_precision_and_tree_flags_match_binding():
+    text = open(sp.HEADER).read()
+    defs = dict((m[0], int(m[1])) for m in
+                re.findall(r"#define (SPAMM_(?:PREC|TREE)_[A-Z0-9_]+)\s+(\d+)u?", text))
+    assert defs == {"SPAMM_PREC_FP32": sp.PREC_FP32, "SPAMM_PREC_SPLIT_BF16": sp.PREC_SPLIT_BF16,
+                    "SPAMM_PREC_SPLIT_FP16": sp.PREC_SPLIT_FP16,
+                    "SPAMM_PREC_SPLIT_BF16X3": sp.PREC_SPLIT_BF16X3,
+                    "SPAMM_TREE_BF16": sp.TREE_BF16, "SPAMM_TREE_SUBNORMS": sp.TREE_SUBNORMS,
+                    "SPAMM_TREE_FP16": sp.TREE_FP16}
+    # tree flags are distinct bits
+    flags = [v for k, v in defs.items() if k.startswith("SPAMM_TREE_")]
+    assert all(f & (f - 1) == 0 for f in flags) and len(set(flags)) == len(flags)
+
+
 def test_strerror_names_every_code():
     for code in (0, -1, -2, -3, -4, -5, -6, -7, 1):
         assert sp.strerror(code) != "unknown status"
