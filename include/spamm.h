@@ -285,11 +285,11 @@ int spamm_symbolic_ex(const spamm_tree *A, const spamm_tree *B, const spamm_opts
 /*
  * Numeric multiply: C = sum over kept k (ascending) of A_ik B_kj for every
  * output leaf, FP32 MFMA with FP32 accumulation (Eq. product; the multiply
- * phase of Alg. 1).  Split precision: the LOW products (BF16 or scaled FP16 operands;
- * with FP16 each product is accumulated on its own, scaled back and added)
- * and the HIGH ones (FP32, or compensated BF16 with SPAMM_PREC_SPLIT_BF16X3)
- * are each summed over k ascending, the LOW ones first, and a leaf is their
- * sum.  C: device pointer, n x n FP32 row-major, fully overwritten (zeros
+ * phase of Alg. 1).  Split precision: the LOW products (BF16 or scaled FP16
+ * operands; with FP16 each product is accumulated on its own, scaled back
+ * and added) and the HIGH ones (FP32, or compensated BF16 with
+ * SPAMM_PREC_SPLIT_BF16X3) are each summed over k ascending, the LOW ones
+ * first, and a leaf is their sum.  C: device pointer, n x n FP32 row-major, fully overwritten (zeros
  * where no product lands; alpha = 1, beta = 0).  C must not overlap the
  * trees' storage; it may alias the matrix a tree was built from.  Enqueue on
  * the plan's stream or order streams yourself.
