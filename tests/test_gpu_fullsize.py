@@ -319,6 +319,21 @@ def test_algdecay_split_theta_1e4(gpu, fmt):
     check_split(r, seed=21)
 
 
+def test_largest_grid_split_x3_n32768_leaf32(gpu):
+    """Compensated HIGH products at the largest grid of n_b = 32 (n = 32768,
+    N = 1024 leaves per dimension, 10 tiers below the root; the 2 x 2 block
+    kernel) with theta = 1e-4: every key with its class bit against the
+    oracle's, sampled C within the bound."""
+    import torch
+    A = workloads.exp_decay(32768, 0.5, 5)
+    r = SplitRun(gpu, A, 32, 1e-6, 0.0, "bf16x3", "expdecay0.5-n32768-leaf32", rel=1e-4)
+    assert r.tree.depth == 10
+    assert 0 < r.stats["tasks_low"] < r.stats["tasks"]
+    check_split(r, seed=23)
+    del r
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("tau", [1e-4, 1e-6, 1e-10])
 def test_algdecay_split_tau_sweep_theta_1e4(gpu, tau):
     """The rest of the algdecay-n16384 tau sweep with BF16 LOW operands at
