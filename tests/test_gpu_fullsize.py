@@ -334,6 +334,21 @@ def test_largest_grid_split_x3_n32768_leaf32(gpu):
     torch.cuda.empty_cache()
 
 
+def test_largest_order_split_x3_n65536_leaf64(gpu):
+    """Compensated HIGH products at the largest order of n_b = 64 (n = 65536,
+    N = 1024, 2^32 elements; the 4 x 4 block kernel) with theta = 1e-4:
+    every key with its class bit against the oracle's, sampled C within the
+    bound."""
+    import torch
+    A = workloads.exp_decay(65536, 0.5, 6)
+    r = SplitRun(gpu, A, 64, 1e-6, 0.0, "bf16x3", "expdecay0.5-n65536-leaf64", rel=1e-4)
+    assert r.tree.depth == 10
+    assert 0 < r.stats["tasks_low"] < r.stats["tasks"]
+    check_split(r, seed=24)
+    del r
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("tau", [1e-4, 1e-6, 1e-10])
 def test_algdecay_split_tau_sweep_theta_1e4(gpu, tau):
     """The rest of the algdecay-n16384 tau sweep with BF16 LOW operands at
