@@ -319,14 +319,16 @@ def test_algdecay_split_theta_1e4(gpu, fmt):
     check_split(r, seed=21)
 
 
-def test_largest_grid_split_x3_n32768_leaf32(gpu):
-    """Compensated HIGH products at the largest grid of n_b = 32 (n = 32768,
-    N = 1024 leaves per dimension, 10 tiers below the root; the 2 x 2 block
-    kernel) with theta = 1e-4: every key with its class bit against the
-    oracle's, sampled C within the bound."""
+@pytest.mark.parametrize("fmt", ["bf16", "fp16", "bf16x3"])
+def test_largest_grid_split_n32768_leaf32(gpu, fmt):
+    """Split precision (BF16 or FP16 LOW operands, FP32 or compensated HIGH
+    products) at the largest grid of n_b = 32 (n = 32768, N = 1024 leaves
+    per dimension, 10 tiers below the root; the 2 x 2 block kernels) with
+    theta = 1e-4: every key with its class bit against the oracle's, sampled
+    C within the bound."""
     import torch
     A = workloads.exp_decay(32768, 0.5, 5)
-    r = SplitRun(gpu, A, 32, 1e-6, 0.0, "bf16x3", "expdecay0.5-n32768-leaf32", rel=1e-4)
+    r = SplitRun(gpu, A, 32, 1e-6, 0.0, fmt, "expdecay0.5-n32768-leaf32", rel=1e-4)
     assert r.tree.depth == 10
     assert 0 < r.stats["tasks_low"] < r.stats["tasks"]
     check_split(r, seed=23)
@@ -334,14 +336,15 @@ def test_largest_grid_split_x3_n32768_leaf32(gpu):
     torch.cuda.empty_cache()
 
 
-def test_largest_order_split_x3_n65536_leaf64(gpu):
-    """Compensated HIGH products at the largest order of n_b = 64 (n = 65536,
-    N = 1024, 2^32 elements; the 4 x 4 block kernel) with theta = 1e-4:
-    every key with its class bit against the oracle's, sampled C within the
-    bound."""
+@pytest.mark.parametrize("fmt", ["bf16", "fp16", "bf16x3"])
+def test_largest_order_split_n65536_leaf64(gpu, fmt):
+    """Split precision at the largest order of n_b = 64 (n = 65536, N =
+    1024, 2^32 elements; the 4 x 4 block kernels with BF16 LOW operands, the
+    2 x 2 one with FP16) with theta = 1e-4: every key with its class bit
+    against the oracle's, sampled C within the bound."""
     import torch
     A = workloads.exp_decay(65536, 0.5, 6)
-    r = SplitRun(gpu, A, 64, 1e-6, 0.0, "bf16x3", "expdecay0.5-n65536-leaf64", rel=1e-4)
+    r = SplitRun(gpu, A, 64, 1e-6, 0.0, fmt, "expdecay0.5-n65536-leaf64", rel=1e-4)
     assert r.tree.depth == 10
     assert 0 < r.stats["tasks_low"] < r.stats["tasks"]
     check_split(r, seed=24)
