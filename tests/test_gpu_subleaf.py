@@ -171,6 +171,65 @@ def test_subleaf_full_size_cluster(gpu):
     assert np.array_equal(sub, ref.keys)
 
 
+def check_subleaf_large(gpu, A, tau, label, seed, count=24):
+    """A leaf-64 sub-culled square of a large A: kept counts of tiers 0..d
+    and the performed sub-products against the leaf-32 oracle's, sampled
+    32 x 32 output blocks within Higham's bound around the oracle's."""
+    import torch
+    n = A.shape[0]
+    print(f"\n[subleaf] {label} tau={tau:g}", flush=True)
+    dA = torch.from_numpy(A).cuda()
+    t = gpu.build_tree(dA, 64, subnorms=True)
+    plan = gpu.symbolic(t, t, tau, sub_cull=True)
+    C = torch.full_like(dA, float("nan"))
+    plan.numeric(C)
+    torch.cuda.synchronize()
+    del dA
+    Ch = C.cpu().numpy()
+    del C
+    st = plan.stats()
+    sub = plan.subtasks()
+    print(f"[subleaf] {label}: leaf products {st['tasks']}, sub-products {st['subtasks']}",
+          flush=True)
+    ref = oracle.spamm(A, A, 32, tau, want_C=False)
+    d = st["depth"]
+    assert st["kept"][:d + 1] == [int(v) for v in ref.Kt[:d + 1]]
+    assert sub.size == ref.K and st["subtasks"] == ref.K
+    assert np.array_equal(sub, ref.keys)
+    assert ref.K < 8 * st["tasks"]                      # sub-blocks were culled
+    N = 1 << (d + 1)
+    rng = np.random.default_rng(seed)
+    tiles = [(int(f) // N, int(f) % N) for f in np.sort(rng.choice(N * N, count, replace=False))]
+    # the band, where the products are, besides random blocks
+    band = rng.choice(N - 1, 8, replace=False)
+    tiles += [(0, 0), (N - 1, N - 1)] + [(int(i), int(i)) for i in band[:4]] + \
+        [(int(i), int(i) + 1) for i in band[4:]]
+    Ct, counts, kl = oracle.spamm_tiles(A, A, 32, tau, tiles, threads=16, want_klists=True)
+    assert (counts > 0).sum() >= 10
+    worst = -np.inf
+    for s_, (I, J) in enumerate(tiles):
+        M = np.zeros((32, 32))
+        for v in kl[s_, :counts[s_]]:
+            k = int(v) & 0x3FFFFFFF
+            M += np.abs(A[I * 32:(I + 1) * 32, k * 32:(k + 1) * 32].astype(np.float64)) @ \
+                np.abs(A[k * 32:(k + 1) * 32, J * 32:(J + 1) * 32].astype(np.float64))
+        m = 32 * int(counts[s_]) + 1
+        bound = m * U32 / (1 - m * U32) * M + m * 2.0 ** -126
+        got = Ch[I * 32:(I + 1) * 32, J * 32:(J + 1) * 32]
+        assert np.all(np.isfinite(got))
+        worst = max(worst, float(np.max(np.abs(got - Ct[s_]) - bound)))
+    assert worst <= 0.0, f"bound exceeded by {worst}"
+
+
+def test_subleaf_largest_order_n65536(gpu):
+    """The largest order of leaf-64 trees (n = 65536, N = 1024, tiers 0..10
+    plus the sub-block tier: a 2048 x 2048 grid of 32 x 32 sub-blocks)."""
+    import torch
+    check_subleaf_large(gpu, workloads.exp_decay(65536, 0.5, 7), 1e-6,
+                        "expdecay0.5-n65536", seed=31)
+    torch.cuda.empty_cache()
+
+
 def test_subleaf_argument_errors(gpu):
     import torch
     A = torch.from_numpy(decay(200, 0.05, 1)).cuda()
