@@ -187,3 +187,32 @@ def test_sparse_full_size_cluster(gpu):
     gpu.multiply(d, d, wl.tau, C2)
     torch.cuda.synchronize()
     assert torch.equal(C1, C2)
+
+
+def test_sparse_largest_order_n65536(gpu):
+    """The largest order of leaf-64 trees (n = 65536, N = 1024) sparsified at
+    tau = 1e-6: stored leaves against the oracle's, task keys against the
+    oracle's dense product, C bit-identical to the dense-tree product."""
+    import torch
+    A = workloads.exp_decay(65536, 0.5, 8)
+    tau = 1e-6
+    print(f"\n[sparse] expdecay0.5-n65536 tau={tau:g}", flush=True)
+    dA = torch.from_numpy(A).cuda()
+    s = gpu.build_tree_sparse(dA, 64, tau)
+    _, keep = oracle.sparsify(A, 64, tau)
+    st = s.storage()
+    print(f"[sparse] stored {st['stored']} of {st['total']} leaves", flush=True)
+    assert st["stored"] == int(keep.sum()) < st["total"]
+    p = gpu.symbolic(s, s, tau)
+    ref = oracle.spamm(A, A, 64, tau, want_C=False)
+    assert np.array_equal(p.tasks(), ref.keys)
+    C1 = torch.empty_like(dA)
+    p.numeric(C1)
+    del p, s
+    d = gpu.build_tree(dA, 64)
+    C2 = torch.empty_like(dA)
+    gpu.multiply(d, d, tau, C2)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
+    del d, C1, C2, dA
+    torch.cuda.empty_cache()
