@@ -22,6 +22,7 @@ import numpy as np
 import pytest
 
 import oracle
+import workloads
 from bounds import class_bound
 
 pytestmark = pytest.mark.gpu
@@ -164,6 +165,52 @@ def test_mix_was_batched(mix):
     assert info["peak_active"] > 1
     assert info["queued"] == 0
     assert 0 < info["used"] <= info["peak_used"] <= info["budget"]
+
+
+# requests deeper than the rounds take (depth 9 and 10: the per-slot path),
+# beside one that the rounds batch; same fields as MIX
+DEEP = [
+    (16384, 32, 1e-6, 0, 0.0, 2, False, 0.5, 21),     # depth 9, a chain of two squarings
+    (32768, 32, 1e-6, 3, 1e-4, 0, False, 0.5, 22),    # depth 10, compensated split
+    (512, 32, 1e-6, 1, 1e-4, 0, False, 0.1, 23),      # depth 4, batched beside them
+]
+
+
+def test_deep_requests_on_the_per_slot_path(gpu):
+    """Requests of depth 9 and 10 run on the per-slot path while a shallow one
+    goes through a round: C bit-identical to the one-call API step by step,
+    task counts summed over the steps, the first step's counts against the
+    oracle's."""
+    import torch
+    fmt = {1: "bf16", 2: "fp16", 3: "bf16x3"}
+    ins = []
+    for n, leaf, tau, prec, theta, chain, distinct, rate, seed in DEEP:
+        A = workloads.exp_decay(n, rate, seed)
+        if chain:
+            A = gershgorin_scaled(A)
+        ins.append(torch.from_numpy(A).cuda())
+    refs = [reference(gpu, s, dA, None) for s, dA in zip(DEEP, ins)]
+    torch.cuda.synchronize()
+    srv = gpu.Server(64 * GiB, max_slots=4)
+    outs = [torch.full_like(dA, float("nan")) for dA in ins]
+    tickets = [srv.submit(ins[i], outs[i], s[2], s[1], precision=s[3],
+                          low_rel=s[4] if s[3] else 0.0, chain_len=s[5])
+               for i, s in enumerate(DEEP)]
+    results = [srv.wait(t) for t in tickets]
+    srv.destroy()
+    for i, s in enumerate(DEEP):
+        X, steps = refs[i]
+        r = results[i]
+        assert r["status"] == 0, r
+        assert r["steps"] == max(1, s[5])
+        assert torch.equal(outs[i], X)
+        assert r["tasks"] == sum(st["K"] for st in steps)
+        assert r["tasks_low"] == sum(st["Klow"] for st in steps)
+        A = ins[i].cpu().numpy()
+        kw = dict(low_rel=s[4], low_fmt=fmt[s[3]]) if s[3] else {}
+        ref = oracle.spamm(A, A, s[1], s[2], want_C=False, **kw)
+        assert steps[0]["K"] == ref.K and steps[0]["Klow"] == ref.Klow
+    assert 0 < results[1]["tasks_low"] < results[1]["tasks"]
 
 
 ORACLE_CASES = [i for i, s in enumerate(MIX) if s[0] <= 1200]
